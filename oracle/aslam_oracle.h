@@ -1,0 +1,109 @@
+/*
+ * aslam_oracle.h -- CPU oracle of the batched Active-SLAM environment step.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This is a plain, slow, obviously-correct CPU
+ * statement of what the environment step computes, written from the paper
+ * (Massive Parallel Deep Reinforcement Learning for Active SLAM, arXiv
+ * 2603.25834).  Only the test-suite, the smoke check and the CPU-baseline leg
+ * of the benchmark may load it.  It shares no code, header, table or constant
+ * generator with the GPU library; each side builds its own tables.
+ *
+ * Passages followed (section / equation of the paper):
+ *   - POMDP step contract: Sec. III-B, Eqs. (1)-(2).
+ *   - action space (v, w): Sec. III-C, Eq. (4).
+ *   - LiDAR ray fan and max range: Sec. IV-A (sensor description).
+ *   - 2-D log-odds occupancy grid, integration of the aligned scan: Sec. III-D.
+ *   - pose covariance as the uncertainty source, D-optimality: Sec. III-D,
+ *     Eq. (6); Sec. II (Table I, "D-opt").
+ *   - collision penalty and episode end: Sec. III-E, Eq. (7); Sec. IV-A.
+ * Where the paper is silent the readings are listed in DESIGN.md ("Readings").
+ *
+ * Parity status: every function here is pinned by a CPU test (closed forms,
+ * brute force, invariants) -- see tests/test_oracle_*.py.
+ */
+#ifndef ASLAM_ORACLE_H
+#define ASLAM_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ORC_NANG 46080          /* heading steps per turn */
+#define ORC_Q16 65536           /* position fraction: 1/65536 cell */
+#define ORC_DIR_ONE 16384       /* unit direction in the table: Q14 */
+
+typedef struct {
+  int32_t n_rays;        /* R; must divide ORC_NANG */
+  int32_t loop_closure;  /* 0 / 1 */
+  int32_t lc_gap;        /* minimum steps between first visit / last closure and a closure */
+  int32_t episode_len;   /* steps per episode; 0 = unbounded */
+  float cell_m;          /* cell side (m) */
+  float r_max_m;         /* LiDAR max range (m) */
+  float dt;              /* control period (s) */
+  float v_max, w_max;    /* action box [0,v_max] x [-w_max,w_max] */
+  float sigma_x, sigma_y, sigma_th;  /* odometry noise std per step */
+  float var0_xy, var0_th;            /* initial covariance diagonal */
+  float lc_cell_m, lc_radius_m, lc_sigma_m; /* loop-closure visit cell, radius, fix std */
+  float l_hit, l_miss, l_clamp;      /* log-odds increments and clamp (nats) */
+  float w_entropy, w_dopt, lambda_col; /* reward weights */
+} orc_config;
+
+/* Per-robot state, caller-owned arrays (robots are independent). */
+typedef struct {
+  int32_t n;                 /* robots in this batch */
+  const int32_t* side;       /* [n] grid side (cells), multiple of 32 */
+  const int64_t* world_off;  /* [n] offset of robot i's world in 32-bit words */
+  const int64_t* cell_off;   /* [n] offset of robot i's belief in cells */
+  const int64_t* visit_off;  /* [n] offset of robot i's visit grid in entries */
+  const uint32_t* world;     /* occupancy bits: cell (i,j) -> bit (j*s+i) */
+  int16_t* belief;           /* log-odds, Q8 (1/256 nat), row-major j*s+i */
+  float* pose;               /* [n,3] true (x,y,theta) */
+  float* est;                /* [n,3] estimate */
+  float* cov;                /* [n,6] xx,xy,xt,yy,yt,tt */
+  int64_t* h_q;              /* [n] map entropy, Q32 nats */
+  int32_t* step;             /* [n] steps since reset */
+  int32_t* last_lc;          /* [n] step of the last loop closure */
+  int32_t* visit_t;          /* ragged first-visit step (-1 none) */
+  float* visit_x;            /* ragged first-visit position */
+  float* visit_y;
+} orc_state;
+
+typedef struct {
+  float* ranges;       /* [n,R] */
+  int32_t* rho_q;      /* [n,R] Q16 cells */
+  int32_t* hit_cell;   /* [n,R] j*s+i or -1 */
+  double* reward;      /* [n] */
+  uint8_t* done;       /* [n] */
+  uint8_t* collided;   /* [n] */
+  uint8_t* closed;     /* [n] loop closure fired this step */
+  double* r_entropy;   /* [n] entropy decrease (nats) */
+  double* logdet;      /* [n] ln det Sigma */
+  int64_t* counters;   /* [n,4]: march visits, update visits, distinct updated cells, distinct world cells read */
+} orc_out;
+
+/* Tables built by the oracle's own code. */
+void orc_trig_table(int32_t* cq, int32_t* sq);           /* [ORC_NANG] each, Q14 */
+int32_t orc_logodds_q(float l);                          /* RNE(l*256) */
+void orc_entropy_table(int32_t l_clamp_q, uint32_t* hq); /* [2*l_clamp_q+1], Q32 nats */
+int32_t orc_heading_index(float theta);
+
+/* Exact integer traversal (one ray or segment); writes visited cells in order.
+ * Returns the number of cells written (<= max_out); *end_reason: 0 limit,
+ * 1 left grid, 2 origin outside the grid. e_out receives the axis distance
+ * (Q16) at which each cell was entered (0 for the origin cell), axis_out 0=x,
+ * 1=y, -1 origin. */
+int32_t orc_walk(int64_t ox, int64_t oy, int64_t a, int64_t b, int64_t scale, int64_t lim,
+                 int32_t s, int32_t* cells_x, int32_t* cells_y, int64_t* e_out, int32_t* axis_out,
+                 int32_t max_out, int32_t* end_reason);
+
+void orc_reset(const orc_config* cfg, orc_state* st, const float* init_pose, const uint8_t* mask);
+void orc_step(const orc_config* cfg, orc_state* st, const float* actions, const float* noise,
+              orc_out* out, int32_t n_threads);
+void orc_observe(const orc_config* cfg, const orc_state* st, const float* ranges, int16_t* crop,
+                 int32_t crop_side, float* scan, float* state12);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

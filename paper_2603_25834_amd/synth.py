@@ -1,0 +1,178 @@
+"""Seeded synthetic inputs for the batched Active-SLAM environment step.
+
+This module holds input generation only -- worlds, start poses, actions and
+the standard-normal draws the step consumes -- and none of the method's
+arithmetic.  Both the GPU path and the CPU oracle take their inputs from here,
+by value.
+
+The worlds stand in for the paper's indoor Isaac Sim scenes (walls and turns,
+arXiv 2603.25834 Sec. IV-A): square occupancy grids with a one-cell border
+wall, axis-aligned rectangular obstacles and thin walls.  Each robot's world is
+drawn from its own generator ``default_rng([seed, 0, i])``, so any subset of a
+batch can be regenerated on its own.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+# Environment parameters shared by every workload (units: m, rad, s, nats).
+ENV_DEFAULTS = dict(
+    dt=0.1, v_max=0.5, w_max=1.0,
+    sigma_x=0.02, sigma_y=0.02, sigma_th=0.01,
+    var0_xy=1e-4, var0_th=1e-4,
+    lc_cell_m=0.5, lc_radius_m=0.5, lc_sigma_m=0.05, lc_gap=50,
+    l_hit=0.85, l_miss=-0.4, l_clamp=3.5,
+    w_entropy=1.0, w_dopt=1.0, lambda_col=10.0,
+    episode_len=0,
+)
+
+
+@dataclass
+class Workload:
+    name: str
+    n_robots: int
+    sides: tuple            # grid sides to draw from (uniformly)
+    cell_m: float
+    n_rays: int
+    r_max_m: float
+    steps: int
+    loop_closure: int
+    rects: tuple            # (min, max) rectangle count at side 256 (scaled by (s/256)^2)
+    rect_side: tuple        # (min, max) rectangle side, cells
+    thin_walls: tuple       # (min, max) thin wall count at side 256 (scaled)
+    thin_len: tuple         # (min, max) thin wall length, cells
+    scale_counts: bool = True
+    extra: dict = field(default_factory=dict)
+
+    def params(self) -> dict:
+        p = dict(ENV_DEFAULTS)
+        p.update(n_rays=self.n_rays, cell_m=self.cell_m, r_max_m=self.r_max_m,
+                 loop_closure=self.loop_closure)
+        p.update(self.extra)
+        return p
+
+
+WORKLOADS = {
+    # 16 robots in 64x64 worlds at 0.1 m, 180 rays over 360 deg, 5 m, 100 steps.
+    "small_16x64": Workload("small_16x64", 16, (64,), 0.1, 180, 5.0, 100, 0,
+                            rects=(4, 8), rect_side=(3, 15), thin_walls=(0, 0), thin_len=(0, 0),
+                            scale_counts=False),
+    # 750 robots in 256x256 worlds at 0.05 m, 360 rays, 10 m, 1000 steps, loop closure.
+    "paper_750x256": Workload("paper_750x256", 750, (256,), 0.05, 360, 10.0, 1000, 1,
+                              rects=(20, 40), rect_side=(4, 24), thin_walls=(4, 8), thin_len=(16, 64)),
+    # 4096 robots, grid side uniform in {128,...,512}, 360 rays, 10 m, 1000 steps.
+    "ragged_4096": Workload("ragged_4096", 4096, (128, 192, 256, 384, 512), 0.05, 360, 10.0, 1000, 1,
+                            rects=(20, 40), rect_side=(4, 24), thin_walls=(4, 8), thin_len=(16, 64)),
+    # 8192 robots in 512x512 worlds, 720 rays, 15 m.
+    "full_8192x512": Workload("full_8192x512", 8192, (512,), 0.05, 720, 15.0, 1000, 1,
+                              rects=(80, 160), rect_side=(4, 24), thin_walls=(16, 32), thin_len=(16, 64),
+                              scale_counts=False),
+}
+
+
+def draw_sides(w: Workload, seed: int, n: int | None = None) -> np.ndarray:
+    n = w.n_robots if n is None else n
+    rng = np.random.default_rng([seed, 7])
+    return np.asarray(w.sides, np.int32)[rng.integers(0, len(w.sides), size=n)]
+
+
+def draw_world(w: Workload, side: int, seed: int, i: int) -> np.ndarray:
+    """Occupancy (bool [s, s], indexed [j, i] = [row y, column x]) of robot i."""
+    rng = np.random.default_rng([seed, 0, i])
+    s = int(side)
+    occ = np.zeros((s, s), bool)
+    occ[0, :] = occ[-1, :] = True
+    occ[:, 0] = occ[:, -1] = True
+    f = (s / 256.0) ** 2 if w.scale_counts else 1.0
+    k = int(round(rng.integers(w.rects[0], w.rects[1] + 1) * f))
+    for _ in range(k):
+        rw = int(rng.integers(w.rect_side[0], w.rect_side[1] + 1))
+        rh = int(rng.integers(w.rect_side[0], w.rect_side[1] + 1))
+        x0 = int(rng.integers(0, max(1, s - rw + 1)))
+        y0 = int(rng.integers(0, max(1, s - rh + 1)))
+        occ[y0:y0 + rh, x0:x0 + rw] = True
+    if w.thin_walls[1] > 0:
+        m = int(round(rng.integers(w.thin_walls[0], w.thin_walls[1] + 1) * f))
+        for _ in range(m):
+            ln = int(rng.integers(w.thin_len[0], w.thin_len[1] + 1))
+            if rng.integers(0, 2):
+                x0 = int(rng.integers(0, max(1, s - ln + 1)))
+                y0 = int(rng.integers(0, s))
+                occ[y0, x0:x0 + ln] = True
+            else:
+                x0 = int(rng.integers(0, s))
+                y0 = int(rng.integers(0, max(1, s - ln + 1)))
+                occ[y0:y0 + ln, x0] = True
+    return occ
+
+
+def pack_bits(occ: np.ndarray) -> np.ndarray:
+    """Row-major bit packing: cell (i, j) -> bit j*s + i, little-endian 32-bit words."""
+    b = np.packbits(occ.reshape(-1).astype(np.uint8), bitorder="little")
+    return b.view("<u4").astype(np.uint32)
+
+
+def draw_start(occ: np.ndarray, cell_m: float, seed: int, i: int) -> np.ndarray:
+    """Uniform over free cells, uniform inside the inner 80% of the cell, heading U[-pi, pi)."""
+    rng = np.random.default_rng([seed, 1, i])
+    free = np.flatnonzero(~occ.reshape(-1))
+    c = int(free[rng.integers(0, len(free))])
+    s = occ.shape[0]
+    ci, cj = c % s, c // s
+    x = (ci + rng.uniform(0.1, 0.9)) * cell_m
+    y = (cj + rng.uniform(0.1, 0.9)) * cell_m
+    th = rng.uniform(-math.pi, math.pi)
+    return np.array([x, y, th], np.float32)
+
+
+@dataclass
+class Batch:
+    workload: Workload
+    seed: int
+    index: np.ndarray        # robot ids within the workload
+    sides: np.ndarray        # int32 [n]
+    world: np.ndarray        # uint32 ragged words
+    world_off: np.ndarray    # int64 [n] word offsets
+    start: np.ndarray        # float32 [n, 3]
+    occ: list                # bool grids (kept for tests)
+
+
+def make_batch(name: str, seed: int = 0, robots=None, keep_occ: bool = False) -> Batch:
+    w = WORKLOADS[name]
+    all_sides = draw_sides(w, seed)
+    idx = np.arange(w.n_robots) if robots is None else np.asarray(robots, np.int64)
+    sides = all_sides[idx].astype(np.int32)
+    words, offs, starts, occs = [], [], np.zeros((len(idx), 3), np.float32), []
+    off = 0
+    for k, i in enumerate(idx):
+        occ = draw_world(w, int(all_sides[i]), seed, int(i))
+        pw = pack_bits(occ)
+        words.append(pw)
+        offs.append(off)
+        off += len(pw)
+        starts[k] = draw_start(occ, w.cell_m, seed, int(i))
+        if keep_occ:
+            occs.append(occ)
+    return Batch(w, seed, idx, sides, np.concatenate(words).astype(np.uint32),
+                 np.asarray(offs, np.int64), starts, occs)
+
+
+def actions(name: str, seed: int, steps: int, robots=None) -> np.ndarray:
+    """Actions [steps, n, 2]: v ~ U[0, 0.5] m/s, w ~ U[-1, 1] rad/s."""
+    w = WORKLOADS[name]
+    rng = np.random.default_rng([seed, 2])
+    a = np.empty((steps, w.n_robots, 2), np.float32)
+    a[..., 0] = rng.uniform(0.0, 0.5, size=(steps, w.n_robots))
+    a[..., 1] = rng.uniform(-1.0, 1.0, size=(steps, w.n_robots))
+    return a if robots is None else np.ascontiguousarray(a[:, np.asarray(robots)])
+
+
+def noise(name: str, seed: int, steps: int, robots=None) -> np.ndarray:
+    """Standard-normal draws [steps, n, 5]: odometry (x, y, theta), loop-closure fix (x, y)."""
+    w = WORKLOADS[name]
+    rng = np.random.default_rng([seed, 3])
+    g = rng.standard_normal((steps, w.n_robots, 5), dtype=np.float32)
+    return g if robots is None else np.ascontiguousarray(g[:, np.asarray(robots)])
