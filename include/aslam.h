@@ -1,0 +1,166 @@
+/*
+ * aslam.h -- C-ABI of the MI355X (gfx950) batched Active-SLAM hot path.
+ *
+ * Method: "Massive Parallel Deep Reinforcement Learning for Active SLAM"
+ * (arXiv 2603.25834).  The environment step follows the POMDP statement of
+ * Sec. III-B (Eqs. 1-2): at each step the agent applies a_t = (v, w) from the
+ * continuous action space of Sec. III-C (Eq. 4), the simulator moves every
+ * robot, the SLAM backbone of Sec. III-D integrates the LiDAR scan into a
+ * 2-D log-odds occupancy grid and propagates the pose covariance, and the
+ * reward of Sec. III-E (collision penalty of Eq. 7) combined with an
+ * uncertainty term is returned with the next observation.  The policy calls
+ * implement the PPO actor-critic of Sec. III-F (Eqs. 18-20).
+ *
+ * Conventions for every call:
+ *   - Return value: ASL_OK (0) or a negative ASL_E* code; aslam_last_error()
+ *     returns a thread-local message describing the last failure.  On error
+ *     the handle's state is unchanged.
+ *   - "dev" pointers are device (HBM) pointers owned by the caller; "host"
+ *     pointers are read during the call only.  The library owns the state
+ *     behind each handle and frees it in the matching destroy call.
+ *   - Every device-side call is asynchronous on the given HIP stream (NULL =
+ *     the legacy default stream), allocates nothing and never synchronises
+ *     the host, so it can be captured into a HIP graph.
+ *   - Units: metres, radians, seconds.  A robot's world frame has its origin
+ *     at the lower-left corner of its grid; cell (i, j) covers
+ *     [i c, (i+1) c) x [j c, (j+1) c); grids are square, side s_i cells,
+ *     s_i a multiple of 32 in [32, 4096].  Row-major cell index j*s + i.
+ *   - Ragged per-robot buffers are concatenated in robot order without gaps.
+ */
+#ifndef ASLAM_H
+#define ASLAM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ASL_OK 0
+#define ASL_EINVAL (-1)   /* invalid argument (null pointer, bad size or config) */
+#define ASL_ENOMEM (-2)   /* device or host allocation failed (create calls only) */
+#define ASL_EHIP (-3)     /* a HIP runtime call failed; the HIP error text is in the message */
+#define ASL_ESTATE (-4)   /* call not valid in the current state (e.g. step before reset) */
+#define ASL_ENOTIMPL (-5) /* feature not built */
+
+typedef struct hipStream_t_opaque* aslam_stream_t; /* a hipStream_t */
+
+/* ------------------------------------------------------------------ env */
+
+typedef struct aslam_env aslam_env;
+
+/* Environment parameters.  Sec. IV-A fixes the sensor as a LiDAR ray fan with
+ * a maximum range; Sec. III-C fixes the action box; the remaining fields are
+ * the workload's choices (odometry noise, initial covariance, loop-closure
+ * and log-odds constants, reward weights). */
+typedef struct {
+  int32_t n_rays;       /* R rays over 360 deg, ray 0 along the heading, counter-clockwise; R divides 46080 */
+  int32_t loop_closure; /* 1: EKF position fix when a robot returns to its first visit of a coarse cell */
+  int32_t lc_gap;       /* steps required since that first visit and since the last fix */
+  int32_t episode_len;  /* steps per episode for `done`; 0 = unbounded */
+  float cell_m;         /* cell side c (m), > 0 */
+  float r_max_m;        /* LiDAR max range (m), > 0, <= 4096 cells */
+  float dt;             /* control period (s) */
+  float v_max, w_max;   /* action box [0, v_max] x [-w_max, w_max] (Eq. 4) */
+  float sigma_x, sigma_y, sigma_th; /* odometry noise std per step (world frame) */
+  float var0_xy, var0_th;           /* initial covariance diagonal */
+  float lc_cell_m, lc_radius_m, lc_sigma_m; /* visit cell (m), fix radius (m), fix std (m) */
+  float l_hit, l_miss, l_clamp;     /* log-odds increments and clamp (nats); stored in 1/256 nat */
+  float w_entropy, w_dopt, lambda_col; /* reward = w_entropy*dH - w_dopt*ln det(Sigma) - lambda_col*collided */
+} aslam_env_config;
+
+/* Execution form of env_step.  PLAIN issues one launch per stage (motion and
+ * EKF, LiDAR march, map update and reward); FUSED issues one persistent launch
+ * that pulls robots in largest-grid-first order and keeps the per-ray results
+ * in LDS. */
+#define ASLAM_FORM_PLAIN 0
+#define ASLAM_FORM_FUSED 1
+
+typedef struct {
+  int32_t form;          /* ASLAM_FORM_* */
+  int32_t threads;       /* threads per workgroup: 64, 128, 256, 512 or 1024 */
+  int32_t band_rows;     /* rows of the LDS code window per pass (>= 8); 0 = as many as fit */
+  int32_t grid;          /* FUSED: workgroups launched; 0 = one per robot */
+  int32_t record_rays;   /* FUSED: also write per-ray rho_q / hit_cell to the state (PLAIN always does) */
+  int32_t lds_bytes;     /* LDS budget per workgroup; 0 = device maximum */
+} aslam_exec_config;
+
+/* Create n_robots environments.  sides_host[n_robots]: grid side of each
+ * robot.  Allocates all device state (worlds, beliefs, poses, covariances,
+ * visit grids, per-ray buffers) on the current device.  Errors: ASL_EINVAL,
+ * ASL_ENOMEM, ASL_EHIP. */
+int aslam_env_create(const aslam_env_config* cfg, int32_t n_robots, const int32_t* sides_host,
+                     aslam_env** out);
+int aslam_env_destroy(aslam_env* env);
+
+/* Device-state sizes, for callers that export or import state. */
+int64_t aslam_env_world_words(const aslam_env* env); /* sum s_i^2 / 32 */
+int64_t aslam_env_cells(const aslam_env* env);       /* sum s_i^2 */
+
+int aslam_env_set_exec(aslam_env* env, const aslam_exec_config* ex);
+int aslam_env_get_exec(const aslam_env* env, aslam_exec_config* ex);
+
+/* Start (or restart) episodes.  world_dev: uint32 occupancy bits, cell (i,j)
+ * of robot r at bit (j*s+i) of its slice (little-endian words), all robots
+ * concatenated.  init_pose_dev: float [n,3] (x, y, theta), inside a free
+ * cell.  mask_dev: uint8 [n], non-zero = reset this robot; NULL = all.
+ * Reset robots get a blank belief (log-odds 0), the estimate equal to the
+ * initial pose, covariance diag(var0_xy, var0_xy, var0_th), step 0 and an
+ * empty visit grid. */
+int aslam_env_reset(aslam_env* env, const uint32_t* world_dev, const float* init_pose_dev,
+                    const uint8_t* mask_dev, aslam_stream_t stream);
+
+/* One environment step for every robot (Sec. III-B, one POMDP transition).
+ *   actions_dev float [n,2] (v, w), clamped to the box; NaN -> 0.
+ *   noise_dev   float [n,5] standard-normal draws: odometry x, y, theta and
+ *               the loop-closure measurement x, y.
+ *   ranges_dev  float [n,R] out: range (m) to the entry face of the first
+ *               occupied cell, r_max when none within range.
+ *   reward_dev  float [n]   out.
+ *   done_dev    uint8 [n]   out: collided this step, or episode length reached.
+ * Errors: ASL_EINVAL (null pointer), ASL_ESTATE (before the first reset). */
+int aslam_env_step(aslam_env* env, const float* actions_dev, const float* noise_dev, float* ranges_dev,
+                   float* reward_dev, uint8_t* done_dev, aslam_stream_t stream);
+
+/* Observation for the policy from the current state and the last ranges:
+ *   crop_dev  int16 [n,crop,crop]: belief log-odds (1/256 nat) in an
+ *             axis-aligned window centred on the estimated cell, 0 off-map.
+ *   scan_dev  float [n,R]: ranges / r_max.
+ *   state_dev float [n,12]: x/(s c), y/(s c), theta/pi, Sigma (9, row-major). */
+int aslam_env_observe(aslam_env* env, const float* ranges_dev, int16_t* crop_dev, int32_t crop,
+                      float* scan_dev, float* state_dev, aslam_stream_t stream);
+
+/* Copy a state field into caller memory (device), for checks and export. */
+#define ASLAM_FIELD_BELIEF 0     /* int16 [sum s^2] */
+#define ASLAM_FIELD_POSE 1       /* float [n,3] true pose */
+#define ASLAM_FIELD_EST 2        /* float [n,3] estimate */
+#define ASLAM_FIELD_COV 3        /* float [n,6] xx, xy, xt, yy, yt, tt */
+#define ASLAM_FIELD_RHO_Q 4      /* int32 [n,R] range in 1/65536 cell */
+#define ASLAM_FIELD_HIT_CELL 5   /* int32 [n,R] j*s+i of the hit cell, -1 none */
+#define ASLAM_FIELD_ENTROPY_Q 6  /* int64 [n] map entropy in 2^-32 nat */
+#define ASLAM_FIELD_STEP 7       /* int32 [n] steps since reset */
+#define ASLAM_FIELD_FLAGS 8      /* uint8 [n,2] collided, loop closure fired (last step) */
+#define ASLAM_FIELD_TERMS 9      /* float [n,2] entropy decrease (nats), ln det Sigma (last step) */
+int aslam_env_read(const aslam_env* env, int32_t field, void* dst_dev, aslam_stream_t stream);
+
+/* HIP graph of K consecutive env_step calls.  Step k reads
+ * actions_dev + k*a_stride, noise_dev + k*g_stride and writes
+ * ranges_dev + k*r_stride, reward_dev + k*w_stride, done_dev + k*d_stride
+ * (strides in elements; 0 = same buffer every step).  The graph is
+ * instantiated once and replayed with aslam_env_graph_launch. */
+int aslam_env_graph_build(aslam_env* env, int32_t k_steps, const float* actions_dev, int64_t a_stride,
+                          const float* noise_dev, int64_t g_stride, float* ranges_dev, int64_t r_stride,
+                          float* reward_dev, int64_t w_stride, uint8_t* done_dev, int64_t d_stride);
+int aslam_env_graph_launch(aslam_env* env, aslam_stream_t stream);
+
+/* ------------------------------------------------------------------ misc */
+
+const char* aslam_last_error(void);
+/* Device limits used by the autotuner: LDS bytes per workgroup, compute units. */
+int aslam_device_info(int32_t* lds_per_block, int32_t* cu_count);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

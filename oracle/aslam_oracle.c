@@ -72,11 +72,12 @@ static float wrap_pi(float th) {
   return th;
 }
 
-/* Position in Q16 cells: rint(v * 65536/c) evaluated in FP32, clamped. */
+/* Position in Q16 cells: rint(v * 65536/c) evaluated in FP32, clamped to
+ * +-1e9 (a NaN maps to -1e9, i.e. far off the grid). */
 static int64_t to_q16(float v, float inv_c16) {
   float t = v * inv_c16;
-  if (t > 1.0e9f) t = 1.0e9f;
-  if (t < -1.0e9f) t = -1.0e9f;
+  if (!(t >= -1.0e9f)) t = -1.0e9f;
+  if (!(t <= 1.0e9f)) t = 1.0e9f;
   return (int64_t)rintf(t);
 }
 

@@ -1,0 +1,91 @@
+"""ctypes binding of ``libaslam.so`` (the C-ABI declared in include/aslam.h).
+
+Argument marshalling only: every step of the hot path runs in the library's
+HIP kernels.  Loading fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libaslam.so")
+
+ASL_OK = 0
+ERRORS = {-1: "ASL_EINVAL", -2: "ASL_ENOMEM", -3: "ASL_EHIP", -4: "ASL_ESTATE", -5: "ASL_ENOTIMPL"}
+
+FORM_PLAIN = 0
+FORM_FUSED = 1
+
+FIELD_BELIEF, FIELD_POSE, FIELD_EST, FIELD_COV, FIELD_RHO_Q, FIELD_HIT_CELL, FIELD_ENTROPY_Q, \
+    FIELD_STEP, FIELD_FLAGS, FIELD_TERMS = range(10)
+
+
+class AslamError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class EnvConfig(ctypes.Structure):
+    _fields_ = [
+        ("n_rays", ctypes.c_int32), ("loop_closure", ctypes.c_int32),
+        ("lc_gap", ctypes.c_int32), ("episode_len", ctypes.c_int32),
+        ("cell_m", ctypes.c_float), ("r_max_m", ctypes.c_float), ("dt", ctypes.c_float),
+        ("v_max", ctypes.c_float), ("w_max", ctypes.c_float),
+        ("sigma_x", ctypes.c_float), ("sigma_y", ctypes.c_float), ("sigma_th", ctypes.c_float),
+        ("var0_xy", ctypes.c_float), ("var0_th", ctypes.c_float),
+        ("lc_cell_m", ctypes.c_float), ("lc_radius_m", ctypes.c_float), ("lc_sigma_m", ctypes.c_float),
+        ("l_hit", ctypes.c_float), ("l_miss", ctypes.c_float), ("l_clamp", ctypes.c_float),
+        ("w_entropy", ctypes.c_float), ("w_dopt", ctypes.c_float), ("lambda_col", ctypes.c_float),
+    ]
+
+
+class ExecConfig(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in ("form", "threads", "band_rows", "grid", "record_rays", "lds_bytes")]
+
+
+_P = ctypes.c_void_p
+_I32 = ctypes.c_int32
+_I64 = ctypes.c_int64
+
+# name -> (restype, argtypes); every function of include/aslam.h
+SIGNATURES = {
+    "aslam_last_error": (ctypes.c_char_p, []),
+    "aslam_device_info": (ctypes.c_int, [_P, _P]),
+    "aslam_env_create": (ctypes.c_int, [ctypes.POINTER(EnvConfig), _I32, _P, ctypes.POINTER(_P)]),
+    "aslam_env_destroy": (ctypes.c_int, [_P]),
+    "aslam_env_world_words": (_I64, [_P]),
+    "aslam_env_cells": (_I64, [_P]),
+    "aslam_env_set_exec": (ctypes.c_int, [_P, ctypes.POINTER(ExecConfig)]),
+    "aslam_env_get_exec": (ctypes.c_int, [_P, ctypes.POINTER(ExecConfig)]),
+    "aslam_env_reset": (ctypes.c_int, [_P, _P, _P, _P, _P]),
+    "aslam_env_step": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P]),
+    "aslam_env_observe": (ctypes.c_int, [_P, _P, _P, _I32, _P, _P, _P]),
+    "aslam_env_read": (ctypes.c_int, [_P, _I32, _P, _P]),
+    "aslam_env_graph_build": (ctypes.c_int, [_P, _I32, _P, _I64, _P, _I64, _P, _I64, _P, _I64, _P, _I64]),
+    "aslam_env_graph_launch": (ctypes.c_int, [_P, _P]),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libaslam.so; raises when it is missing (no fallback path exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(rc: int) -> None:
+    if rc != ASL_OK:
+        msg = lib().aslam_last_error()
+        raise AslamError(rc, msg.decode() if msg else "")

@@ -1,0 +1,98 @@
+// env_internal.h -- library-internal types of the gfx950 environment step.
+//
+// Not part of the public ABI (include/aslam.h).  Device layout of the batch:
+//   world   : uint32 bits, robot-major, row-major inside a robot (bit j*s+i)
+//   belief  : int16 log-odds in 1/256 nat, robot-major, row-major
+//   visit   : per robot a (ceil(s c / lc_cell))^2 grid of first visits
+// Robots are independent; one workgroup owns one robot at a time.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace aslam {
+
+constexpr int kNang = 46080;     // heading steps per turn
+constexpr int kQ16 = 65536;      // position unit: 1/65536 cell
+constexpr int kDirOne = 16384;   // direction unit in the heading table (Q14)
+
+struct RobotMeta {
+  int32_t side;        // s
+  int32_t visit_side;  // loop-closure grid side
+  int64_t world_off;   // first word of the robot's world bits
+  int64_t cell_off;    // first cell of the robot's belief
+  int64_t visit_off;   // first entry of the robot's visit grid
+  float inv_ext;       // 1 / (s c), observation normalisation
+  int32_t pad;
+};
+
+// Everything a step kernel needs besides the per-call buffers.
+struct EnvParams {
+  int32_t n, R, step_ang;
+  int32_t loop_closure, lc_gap, episode_len;
+  int32_t lhit, lmiss, lclamp;
+  int32_t rhat_q;        // max range in 1/65536 cell
+  int32_t rhat_cells;    // ceil of the max range in cells
+  float v_max, w_max, dt;
+  float sigma_x, sigma_y, sigma_th;
+  float qx, qy, qth;     // sigma^2 (FP32 products)
+  float var0_xy, var0_th;
+  float inv_c16;         // 65536 / c
+  float c16;             // c / 65536
+  float k_ang;           // kNang / (2 pi)
+  float inv_lc;          // 1 / lc_cell
+  float lc_r2;           // lc_radius^2
+  float lc_sigma, lc_var;
+  float w_entropy, w_dopt, lambda_col;
+  float inv_rmax, inv_pi;
+  const RobotMeta* meta;
+  const int32_t* order;  // robots, largest grid first
+  const uint32_t* world;
+  int16_t* belief;
+  float* pose;
+  float* est;
+  float* cov;
+  int64_t* hq_total;
+  int32_t* step;
+  int32_t* last_lc;
+  int32_t* visit_t;
+  float* visit_xy;
+  int32_t* rho;          // [n,R]
+  int32_t* hitc;         // [n,R]
+  uint8_t* flags;        // [n,2] collided, closed
+  float* terms;          // [n,2] entropy decrease, ln det
+  const int32_t* dirtab; // [kNang] (cos & 0xffff) | (sin << 16), Q14
+  const uint32_t* hq_lut;// [2*lclamp+1] binary entropy, 2^-32 nat
+};
+
+struct StepArgs {
+  const float* actions;  // [n,2]
+  const float* noise;    // [n,5]
+  float* ranges;         // [n,R]
+  float* reward;         // [n]
+  uint8_t* done;         // [n]
+};
+
+// LDS plan of the per-robot kernels (byte offsets into dynamic LDS).
+struct LdsPlan {
+  int32_t off_lut, off_rho, off_misc, off_union;
+  int32_t total;
+  int32_t union_bytes;
+  int32_t band_rows;      // code-window rows per pass
+  int32_t world_halo;     // rows staged around the robot: rhat_cells + 3
+  int32_t record;         // fused: write rho / hitc to the state
+};
+
+struct ExecState;
+
+// Launchers (env_kernels.hip); all asynchronous on `stream`.
+hipError_t launch_reset(const EnvParams& P, const uint32_t* world_src, const float* init_pose,
+                        const uint8_t* mask, int32_t max_side, hipStream_t stream);
+hipError_t launch_step_plain(const EnvParams& P, const StepArgs& A, const LdsPlan& L, int threads,
+                             hipStream_t stream);
+hipError_t launch_step_fused(const EnvParams& P, const StepArgs& A, const LdsPlan& L, int threads,
+                             int grid, hipStream_t stream);
+hipError_t launch_observe(const EnvParams& P, const float* ranges, int16_t* crop, int32_t cs,
+                          float* scan, float* state, hipStream_t stream);
+hipError_t set_kernel_lds_limits(int bytes);
+
+}  // namespace aslam

@@ -1,0 +1,660 @@
+// env_kernels.hip -- gfx950 kernels of the batched Active-SLAM environment step.
+//
+// Method: arXiv 2603.25834.  One POMDP transition per robot (Sec. III-B):
+// the robot moves under the continuous action of Sec. III-C (Eq. 4), the
+// LiDAR of Sec. IV-A samples the world, the scan is integrated into the 2-D
+// log-odds grid of Sec. III-D, the pose covariance is propagated (an EKF
+// stands in for the fixed-lag backend of Sec. III-D), and the reward combines
+// the collision penalty of Eq. (7) with the map-entropy decrease and the
+// D-optimality term -ln det(Sigma) (Table I, "D-opt").
+//
+// Execution model (CDNA4): one workgroup owns one robot at a time.  Rays are
+// spread over the workgroup's lanes; each lane walks its ray through the grid
+// with an exact integer DDA (32-bit decision variable, no division in the
+// loop).  The LiDAR march reads the robot's world bits from LDS.  The map
+// update marks a per-scan code window in LDS (two bitmaps: MISS and HIT;
+// OR-ing bits makes the result independent of ray and lane order), then a
+// coalesced pass applies one saturating int16 add to each coded cell and
+// accumulates the exact entropy change in int64.
+#include "env_internal.h"
+
+namespace aslam {
+
+namespace {
+
+__device__ __forceinline__ int32_t heading_index(float th, float k_ang) {
+  float t = th * k_ang;
+  if (!(t > -1.0e9f && t < 1.0e9f)) t = 0.0f;
+  int32_t i = (int32_t)rintf(t);
+  i %= kNang;
+  if (i < 0) i += kNang;
+  return i;
+}
+
+__device__ __forceinline__ float wrap_pi(float th) {
+  const float pi = 3.14159265358979f;
+  const float two_pi = 6.28318530717959f;
+  if (th >= pi) th = th - two_pi;
+  else if (th < -pi) th = th + two_pi;
+  return th;
+}
+
+// Position in 1/65536 cell: rint(v * 65536/c) in FP32, clamped to +-1e9 (NaN -> -1e9).
+__device__ __forceinline__ int32_t to_q16(float v, float inv_c16) {
+  float t = v * inv_c16;
+  if (!(t >= -1.0e9f)) t = -1.0e9f;
+  if (!(t <= 1.0e9f)) t = 1.0e9f;
+  return (int32_t)rintf(t);
+}
+
+__device__ __forceinline__ float dir_cos(int32_t d) { return (float)(int16_t)(d & 0xffff) * (1.0f / 16384.0f); }
+__device__ __forceinline__ float dir_sin(int32_t d) { return (float)(d >> 16) * (1.0f / 16384.0f); }
+
+__device__ __forceinline__ bool world_bit(const uint32_t* w, int32_t s, int32_t i, int32_t j) {
+  int32_t bit = j * s + i;
+  return (w[bit >> 5] >> (bit & 31)) & 1u;
+}
+
+// Motion segment from Q16 (ox,oy) to (nx,ny): blocked if any cell it enters
+// (entry parameter <= 1, exact corner steps x first) is occupied or off-grid.
+__device__ bool segment_blocked(const uint32_t* w, int32_t s, int32_t ox, int32_t oy, int32_t nx, int32_t ny) {
+  int32_t cx = ox >> 16, cy = oy >> 16;
+  if (cx < 0 || cx >= s || cy < 0 || cy >= s) return true;
+  if (world_bit(w, s, cx, cy)) return true;
+  int64_t a = (int64_t)nx - ox, b = (int64_t)ny - oy;
+  if (a == 0 && b == 0) return false;
+  int64_t aa = a < 0 ? -a : a, bb = b < 0 ? -b : b;
+  int64_t fx = ox & 0xffff, fy = oy & 0xffff;
+  int64_t ex = a > 0 ? kQ16 - fx : fx;
+  int64_t ey = b > 0 ? kQ16 - fy : fy;
+  for (int32_t it = 0; it < 2 * s + 4; ++it) {
+    bool stepx = (aa == 0) ? false : ((bb == 0) ? true : (ex * bb <= ey * aa));
+    if (stepx) {
+      if (ex > aa) return false;
+      cx += a > 0 ? 1 : -1;
+      if (cx < 0 || cx >= s) return true;
+      ex += kQ16;
+    } else {
+      if (ey > bb) return false;
+      cy += b > 0 ? 1 : -1;
+      if (cy < 0 || cy >= s) return true;
+      ey += kQ16;
+    }
+    if (world_bit(w, s, cx, cy)) return true;
+  }
+  return true;
+}
+
+struct MotionOut {
+  int32_t tox, toy, ib_t;   // true origin (Q16) and heading index
+  int32_t eox, eoy, ib_e;   // estimated origin and heading index
+  int32_t collided, closed;
+};
+
+// Motion, collision, EKF predict and loop closure of robot r (one thread).
+__device__ MotionOut robot_motion(const EnvParams& P, const StepArgs& A, int32_t r) {
+  const RobotMeta m = P.meta[r];
+  const int32_t s = m.side;
+  const float a0 = A.actions[2 * r], a1 = A.actions[2 * r + 1];
+  const float* g = A.noise + 5 * (int64_t)r;
+  float v = fminf(fmaxf(a0, 0.0f), P.v_max);
+  float w = fminf(fmaxf(a1, -P.w_max), P.w_max);
+  if (v != v) v = 0.0f;
+  if (w != w) w = 0.0f;
+  float d = v * P.dt;
+  float phi = w * P.dt;
+
+  float* p = P.pose + 3 * (int64_t)r;
+  float px = p[0], py = p[1], pth = p[2];
+  const int32_t dt_ = P.dirtab[heading_index(pth, P.k_ang)];
+  const float nx = (px + d * dir_cos(dt_)) + P.sigma_x * g[0];
+  const float ny = (py + d * dir_sin(dt_)) + P.sigma_y * g[1];
+  const float nth = wrap_pi((pth + phi) + P.sigma_th * g[2]);
+  const uint32_t* W = P.world + m.world_off;
+  const bool col = segment_blocked(W, s, to_q16(px, P.inv_c16), to_q16(py, P.inv_c16),
+                                   to_q16(nx, P.inv_c16), to_q16(ny, P.inv_c16));
+  if (col) {
+    d = 0.0f;
+    phi = 0.0f;
+  } else {
+    px = nx; py = ny; pth = nth;
+    p[0] = px; p[1] = py; p[2] = pth;
+  }
+
+  // EKF predict; F uses the estimated heading before the step.
+  float* e = P.est + 3 * (int64_t)r;
+  float* c = P.cov + 6 * (int64_t)r;
+  float ex = e[0], ey = e[1], eth = e[2];
+  float c0 = c[0], c1 = c[1], c2 = c[2], c3 = c[3], c4 = c[4], c5 = c[5];
+  {
+    const int32_t de = P.dirtab[heading_index(eth, P.k_ang)];
+    const float ch = dir_cos(de), sh = dir_sin(de);
+    const float fa = -(d * sh);
+    const float fb = d * ch;
+    const float n0 = ((c0 + (2.0f * fa) * c2) + (fa * fa) * c5) + P.qx;
+    const float n1 = ((c1 + fa * c4) + fb * c2) + (fa * fb) * c5;
+    const float n2 = c2 + fa * c5;
+    const float n3 = ((c3 + (2.0f * fb) * c4) + (fb * fb) * c5) + P.qy;
+    const float n4 = c4 + fb * c5;
+    const float n5 = c5 + P.qth;
+    c0 = n0; c1 = n1; c2 = n2; c3 = n3; c4 = n4; c5 = n5;
+    ex = ex + d * ch;
+    ey = ey + d * sh;
+    eth = wrap_pi(eth + phi);
+  }
+
+  const int32_t t = P.step[r];
+  int32_t closed = 0;
+  if (P.loop_closure) {
+    const int32_t nv = m.visit_side;
+    int32_t vx = (int32_t)floorf(px * P.inv_lc);
+    int32_t vy = (int32_t)floorf(py * P.inv_lc);
+    vx = min(max(vx, 0), nv - 1);
+    vy = min(max(vy, 0), nv - 1);
+    const int64_t vk = m.visit_off + (int64_t)vy * nv + vx;
+    const int32_t t0 = P.visit_t[vk];
+    if (t0 < 0) {
+      P.visit_t[vk] = t;
+      P.visit_xy[2 * vk] = px;
+      P.visit_xy[2 * vk + 1] = py;
+    } else {
+      const float dx = px - P.visit_xy[2 * vk];
+      const float dy = py - P.visit_xy[2 * vk + 1];
+      if (t - t0 >= P.lc_gap && t - P.last_lc[r] >= P.lc_gap && (dx * dx + dy * dy) <= P.lc_r2) {
+        const float zx = px + P.lc_sigma * g[3];
+        const float zy = py + P.lc_sigma * g[4];
+        const float s00 = c0 + P.lc_var, s01 = c1, s11 = c3 + P.lc_var;
+        const float det = s00 * s11 - s01 * s01;
+        const float i00 = s11 / det, i01 = (-s01) / det, i11 = s00 / det;
+        const float kx0 = c0 * i00 + c1 * i01, kx1 = c0 * i01 + c1 * i11;
+        const float ky0 = c1 * i00 + c3 * i01, ky1 = c1 * i01 + c3 * i11;
+        const float kt0 = c2 * i00 + c4 * i01, kt1 = c2 * i01 + c4 * i11;
+        const float v0 = zx - ex, v1 = zy - ey;
+        ex = ex + (kx0 * v0 + kx1 * v1);
+        ey = ey + (ky0 * v0 + ky1 * v1);
+        eth = wrap_pi(eth + (kt0 * v0 + kt1 * v1));
+        const float m0 = c0 - (kx0 * c0 + kx1 * c1);
+        const float m1 = c1 - (kx0 * c1 + kx1 * c3);
+        const float m2 = c2 - (kx0 * c2 + kx1 * c4);
+        const float m3 = c3 - (ky0 * c1 + ky1 * c3);
+        const float m4 = c4 - (ky0 * c2 + ky1 * c4);
+        const float m5 = c5 - (kt0 * c2 + kt1 * c4);
+        c0 = m0; c1 = m1; c2 = m2; c3 = m3; c4 = m4; c5 = m5;
+        P.last_lc[r] = t;
+        closed = 1;
+      }
+    }
+  }
+  e[0] = ex; e[1] = ey; e[2] = eth;
+  c[0] = c0; c[1] = c1; c[2] = c2; c[3] = c3; c[4] = c4; c[5] = c5;
+  P.step[r] = t + 1;
+  P.flags[2 * (int64_t)r] = (uint8_t)col;
+  P.flags[2 * (int64_t)r + 1] = (uint8_t)closed;
+
+  MotionOut o;
+  o.tox = to_q16(px, P.inv_c16);
+  o.toy = to_q16(py, P.inv_c16);
+  o.ib_t = heading_index(pth, P.k_ang);
+  o.eox = to_q16(ex, P.inv_c16);
+  o.eoy = to_q16(ey, P.inv_c16);
+  o.ib_e = heading_index(eth, P.k_ang);
+  o.collided = col;
+  o.closed = closed;
+  return o;
+}
+
+// Per-robot values shared by the workgroup (LDS).
+struct RobotShared {
+  int32_t r;
+  int32_t tox, toy, ib_t;
+  int32_t eox, eoy, ib_e;
+  int32_t collided;
+  int32_t rho_max;
+  int32_t pad[7];
+  long long part[16];
+};
+
+// ---------------------------------------------------------------- DDA setup
+// Ray from Q16 origin o with table direction (a,b) (Q14), limit lim (Q16 cells).
+// x crossings happen at axis distances ex0 + k*65536; the k-th is within the
+// limit iff (ex0 + k*65536) * 2^14 <= lim * |a|.
+struct RaySetup {
+  int32_t D, DX, DY;
+  int32_t nx, ny;          // x / y steps allowed (limit and grid)
+  int32_t gx, gy;          // 1: running out of x / y steps means leaving the grid
+  int32_t ex0, ey0, aa, bb;
+};
+
+__device__ __forceinline__ RaySetup ray_setup(int32_t ox, int32_t oy, int32_t a, int32_t b, int32_t lim,
+                                              int32_t s) {
+  RaySetup q;
+  const int32_t cx = ox >> 16, cy = oy >> 16;
+  const int32_t aa = abs(a), bb = abs(b);
+  const int32_t fx = ox & 0xffff, fy = oy & 0xffff;
+  const int32_t ex0 = a > 0 ? kQ16 - fx : fx;
+  const int32_t ey0 = b > 0 ? kQ16 - fy : fy;
+  const int64_t emx = ((int64_t)lim * aa) >> 14;
+  const int64_t emy = ((int64_t)lim * bb) >> 14;
+  const int32_t nxl = (aa == 0 || emx < ex0) ? 0 : (int32_t)((emx - ex0) >> 16) + 1;
+  const int32_t nyl = (bb == 0 || emy < ey0) ? 0 : (int32_t)((emy - ey0) >> 16) + 1;
+  const int32_t nxg = a > 0 ? s - 1 - cx : cx;
+  const int32_t nyg = b > 0 ? s - 1 - cy : cy;
+  q.nx = min(nxl, nxg);
+  q.ny = min(nyl, nyg);
+  q.gx = nxg < nxl;
+  q.gy = nyg < nyl;
+  if (aa == 0) { q.D = 1; q.DX = 0; q.DY = 0; }
+  else if (bb == 0) { q.D = -1; q.DX = 0; q.DY = 0; }
+  else { q.D = ex0 * bb - ey0 * aa; q.DX = bb << 16; q.DY = aa << 16; }
+  q.ex0 = ex0; q.ey0 = ey0; q.aa = aa; q.bb = bb;
+  return q;
+}
+
+// ---------------------------------------------------------------- stages
+template <int NT>
+__device__ void stage_world(const EnvParams& P, const RobotMeta& m, int32_t cy, int32_t halo, uint32_t* sw,
+                            int32_t& wy0) {
+  const int32_t s = m.side;
+  const int32_t y0 = max(0, min(s - 1, cy - halo));
+  const int32_t y1 = max(0, min(s - 1, cy + halo));
+  const int32_t wpr = s >> 5;
+  const int32_t nwords = (y1 - y0 + 1) * wpr;
+  const uint32_t* src = P.world + m.world_off + (int64_t)y0 * wpr;
+  for (int32_t k = threadIdx.x; k < nwords; k += NT) sw[k] = src[k];
+  wy0 = y0;
+}
+
+// LiDAR march of every ray of the robot from the true pose (lanes = rays).
+template <int NT>
+__device__ void march_rays(const EnvParams& P, const RobotMeta& m, const RobotShared* sh, const uint32_t* sw,
+                           int32_t wy0, int32_t* rho_lds, float* ranges_out, bool record, int32_t r) {
+  const int32_t s = m.side;
+  const int32_t tox = sh->tox, toy = sh->toy, ib = sh->ib_t;
+  const int32_t cx0 = tox >> 16, cy0 = toy >> 16;
+  const bool inside = cx0 >= 0 && cx0 < s && cy0 >= 0 && cy0 < s;
+  for (int32_t k = threadIdx.x; k < P.R; k += NT) {
+    int32_t rq = P.rhat_q;
+    int32_t cell = -1;
+    if (inside) {
+      int32_t id = ib + k * P.step_ang;
+      id -= (id >= kNang) ? kNang : 0;
+      const int32_t dv = P.dirtab[id];
+      const int32_t a = (int16_t)(dv & 0xffff), b = dv >> 16;
+      RaySetup q = ray_setup(tox, toy, a, b, P.rhat_q, s);
+      int32_t li = (cy0 - wy0) * s + cx0;
+      const int32_t sx = a > 0 ? 1 : -1;
+      const int32_t sy = b > 0 ? s : -s;
+      int32_t rx = q.nx, ry = q.ny, D = q.D;
+      bool lastx = false;
+      bool hit = (sw[li >> 5] >> (li & 31)) & 1u;
+      while (!hit) {
+        const bool stepx = D <= 0;
+        const int32_t rem = stepx ? rx : ry;
+        if (rem == 0) break;
+        rx -= stepx ? 1 : 0;
+        ry -= stepx ? 0 : 1;
+        li += stepx ? sx : sy;
+        D += stepx ? q.DX : -q.DY;
+        lastx = stepx;
+        hit = (sw[li >> 5] >> (li & 31)) & 1u;
+      }
+      if (hit) {
+        cell = li + wy0 * s;
+        const int32_t tx = q.nx - rx, ty = q.ny - ry;
+        if (tx + ty == 0) {
+          rq = 0;
+        } else if (lastx) {
+          const int64_t E = (int64_t)q.ex0 + (int64_t)(tx - 1) * kQ16;
+          rq = (int32_t)((E * kDirOne + q.aa - 1) / q.aa);
+        } else {
+          const int64_t E = (int64_t)q.ey0 + (int64_t)(ty - 1) * kQ16;
+          rq = (int32_t)((E * kDirOne + q.bb - 1) / q.bb);
+        }
+      }
+    }
+    rho_lds[k] = rq | (cell >= 0 ? (int32_t)0x80000000 : 0);
+    ranges_out[(int64_t)r * P.R + k] = (float)rq * P.c16;
+    if (record) {
+      P.rho[(int64_t)r * P.R + k] = rq;
+      P.hitc[(int64_t)r * P.R + k] = cell;
+    }
+  }
+}
+
+__device__ __forceinline__ long long wave_sum_i64(long long v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Map update from the estimated pose with the measured ranges, then the
+// reward.  rho_lds[k]: range (Q16) with bit 31 set when ray k hit.
+template <int NT>
+__device__ void update_and_reward(const EnvParams& P, const StepArgs& A, const RobotMeta& m, RobotShared* sh,
+                                  const int32_t* rho_lds, uint32_t* uni, const uint32_t* lut, const LdsPlan& L,
+                                  int32_t r) {
+  constexpr int NWAVE = NT / 64;
+  const int32_t s = m.side;
+  const int32_t eox = sh->eox, eoy = sh->eoy, ib = sh->ib_e;
+  const int32_t ecx = eox >> 16, ecy = eoy >> 16;
+  const bool inside = ecx >= 0 && ecx < s && ecy >= 0 && ecy < s;
+  long long dh = 0;
+  if (inside) {
+    const int32_t hu = (sh->rho_max >> 16) + 3;
+    const int32_t x0 = max(0, ecx - hu), x1 = min(s - 1, ecx + hu);
+    const int32_t y0 = max(0, ecy - hu), y1 = min(s - 1, ecy + hu);
+    const int32_t x0w = x0 & ~31;
+    const int32_t nw = (x1 >> 5) - (x0 >> 5) + 1;
+    const int32_t rowbits = nw << 5;
+    const int32_t band = L.band_rows;
+    uint32_t* miss = uni;
+    uint32_t* hitm = uni + band * nw;
+    const int32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t base = m.cell_off;
+    for (int32_t by0 = y0; by0 <= y1; by0 += band) {
+      const int32_t rows = min(band, y1 - by0 + 1);
+      const uint32_t band_bits = (uint32_t)(rows * rowbits);
+      for (int32_t k = threadIdx.x; k < 2 * band * nw; k += NT) uni[k] = 0u;
+      __syncthreads();
+      // mark: one lane per ray
+      for (int32_t k = threadIdx.x; k < P.R; k += NT) {
+        const int32_t pk = rho_lds[k];
+        const int32_t lim = pk & 0x7fffffff;
+        const bool hit = pk < 0;
+        int32_t id = ib + k * P.step_ang;
+        id -= (id >= kNang) ? kNang : 0;
+        const int32_t dv = P.dirtab[id];
+        const int32_t a = (int16_t)(dv & 0xffff), b = dv >> 16;
+        RaySetup q = ray_setup(eox, eoy, a, b, lim, s);
+        int32_t wi = (ecy - by0) * rowbits + (ecx - x0w);
+        const int32_t sx = a > 0 ? 1 : -1;
+        const int32_t sy = b > 0 ? rowbits : -rowbits;
+        int32_t rx = q.nx, ry = q.ny, D = q.D;
+        if ((uint32_t)wi < band_bits) atomicOr(&miss[wi >> 5], 1u << (wi & 31));
+        bool stepx;
+        while (true) {
+          stepx = D <= 0;
+          const int32_t rem = stepx ? rx : ry;
+          if (rem == 0) break;
+          rx -= stepx ? 1 : 0;
+          ry -= stepx ? 0 : 1;
+          wi += stepx ? sx : sy;
+          D += stepx ? q.DX : -q.DY;
+          if ((uint32_t)wi < band_bits) atomicOr(&miss[wi >> 5], 1u << (wi & 31));
+        }
+        const bool grid_end = stepx ? q.gx : q.gy;
+        if (hit && !grid_end && (uint32_t)wi < band_bits) atomicOr(&hitm[wi >> 5], 1u << (wi & 31));
+      }
+      __syncthreads();
+      // apply: each coded cell once, cell pairs (int16x2) per lane, rows per wave
+      for (int32_t row = wave; row < rows; row += NWAVE) {
+        const int32_t y = by0 + row;
+        const uint32_t* mrow = miss + row * nw;
+        const uint32_t* hrow = hitm + row * nw;
+        int32_t* brow = reinterpret_cast<int32_t*>(P.belief + base + (int64_t)y * s + x0w);
+        for (int32_t pr = lane; pr < nw * 16; pr += 64) {
+          const int32_t sft = (pr & 15) * 2;
+          const uint32_t mb = (mrow[pr >> 4] >> sft) & 3u;
+          const uint32_t hb = (hrow[pr >> 4] >> sft) & 3u;
+          if ((mb | hb) == 0u) continue;
+          const int32_t v = brow[pr];
+          const int32_t l0 = (int16_t)(v & 0xffff), l1 = v >> 16;
+          int32_t n0 = l0, n1 = l1;
+          if ((mb | hb) & 1u) {
+            n0 = min(max(l0 + ((hb & 1u) ? P.lhit : P.lmiss), -P.lclamp), P.lclamp);
+            dh += (long long)lut[n0 + P.lclamp] - (long long)lut[l0 + P.lclamp];
+          }
+          if ((mb | hb) & 2u) {
+            n1 = min(max(l1 + ((hb & 2u) ? P.lhit : P.lmiss), -P.lclamp), P.lclamp);
+            dh += (long long)lut[n1 + P.lclamp] - (long long)lut[l1 + P.lclamp];
+          }
+          brow[pr] = (n0 & 0xffff) | (n1 << 16);
+        }
+      }
+      __syncthreads();
+    }
+  }
+  dh = wave_sum_i64(dh);
+  if ((threadIdx.x & 63) == 0) sh->part[threadIdx.x >> 6] = dh;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    long long tot = 0;
+    for (int w = 0; w < NWAVE; ++w) tot += sh->part[w];
+    P.hq_total[r] += tot;
+    const double rH = (double)(-tot) * (1.0 / 4294967296.0);
+    const float* c = P.cov + 6 * (int64_t)r;
+    const double det = (double)c[0] * ((double)c[3] * c[5] - (double)c[4] * c[4]) -
+                       (double)c[1] * ((double)c[1] * c[5] - (double)c[4] * c[2]) +
+                       (double)c[2] * ((double)c[1] * c[4] - (double)c[3] * c[2]);
+    const double ld = det > 0.0 ? log(det) : log(1.17549435e-38);
+    const int32_t col = sh->collided;
+    const double rew = (double)P.w_entropy * rH - (double)P.w_dopt * ld - (double)P.lambda_col * (double)col;
+    A.reward[r] = (float)rew;
+    const int32_t t = P.step[r];
+    A.done[r] = (uint8_t)(col || (P.episode_len > 0 && t >= P.episode_len));
+    P.terms[2 * (int64_t)r] = (float)rH;
+    P.terms[2 * (int64_t)r + 1] = (float)ld;
+  }
+}
+
+// ---------------------------------------------------------------- kernels
+
+__global__ void k_motion(EnvParams P, StepArgs A) {
+  const int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= P.n) return;
+  robot_motion(P, A, r);
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void k_march(EnvParams P, StepArgs A, LdsPlan L) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  int32_t* rho_lds = reinterpret_cast<int32_t*>(smem + L.off_rho);
+  RobotShared* sh = reinterpret_cast<RobotShared*>(smem + L.off_misc);
+  uint32_t* uni = reinterpret_cast<uint32_t*>(smem + L.off_union);
+  const int32_t r = blockIdx.x;
+  const RobotMeta m = P.meta[r];
+  if (threadIdx.x == 0) {
+    const float* p = P.pose + 3 * (int64_t)r;
+    sh->tox = to_q16(p[0], P.inv_c16);
+    sh->toy = to_q16(p[1], P.inv_c16);
+    sh->ib_t = heading_index(p[2], P.k_ang);
+  }
+  __syncthreads();
+  int32_t wy0;
+  stage_world<NT>(P, m, sh->toy >> 16, L.world_halo, uni, wy0);
+  __syncthreads();
+  march_rays<NT>(P, m, sh, uni, wy0, rho_lds, A.ranges, true, r);
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void k_update(EnvParams P, StepArgs A, LdsPlan L) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  uint32_t* lut = reinterpret_cast<uint32_t*>(smem + L.off_lut);
+  int32_t* rho_lds = reinterpret_cast<int32_t*>(smem + L.off_rho);
+  RobotShared* sh = reinterpret_cast<RobotShared*>(smem + L.off_misc);
+  uint32_t* uni = reinterpret_cast<uint32_t*>(smem + L.off_union);
+  const int32_t r = blockIdx.x;
+  const RobotMeta m = P.meta[r];
+  for (int32_t i = threadIdx.x; i < 2 * P.lclamp + 1; i += NT) lut[i] = P.hq_lut[i];
+  if (threadIdx.x == 0) {
+    const float* e = P.est + 3 * (int64_t)r;
+    sh->eox = to_q16(e[0], P.inv_c16);
+    sh->eoy = to_q16(e[1], P.inv_c16);
+    sh->ib_e = heading_index(e[2], P.k_ang);
+    sh->collided = P.flags[2 * (int64_t)r];
+    sh->rho_max = 0;
+  }
+  __syncthreads();
+  for (int32_t k = threadIdx.x; k < P.R; k += NT) {
+    const int32_t rq = P.rho[(int64_t)r * P.R + k];
+    const int32_t hc = P.hitc[(int64_t)r * P.R + k];
+    rho_lds[k] = rq | (hc >= 0 ? (int32_t)0x80000000 : 0);
+    atomicMax(&sh->rho_max, rq);
+  }
+  __syncthreads();
+  update_and_reward<NT>(P, A, m, sh, rho_lds, uni, lut, L, r);
+}
+
+// Fused persistent step: workgroups pull robots in largest-grid-first order.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_fused(EnvParams P, StepArgs A, LdsPlan L) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  uint32_t* lut = reinterpret_cast<uint32_t*>(smem + L.off_lut);
+  int32_t* rho_lds = reinterpret_cast<int32_t*>(smem + L.off_rho);
+  RobotShared* sh = reinterpret_cast<RobotShared*>(smem + L.off_misc);
+  uint32_t* uni = reinterpret_cast<uint32_t*>(smem + L.off_union);
+  for (int32_t i = threadIdx.x; i < 2 * P.lclamp + 1; i += NT) lut[i] = P.hq_lut[i];
+  for (int32_t w = blockIdx.x; w < P.n; w += gridDim.x) {
+    const int32_t r = P.order[w];
+    const RobotMeta m = P.meta[r];
+    if (threadIdx.x == 0) {
+      const MotionOut o = robot_motion(P, A, r);
+      sh->tox = o.tox; sh->toy = o.toy; sh->ib_t = o.ib_t;
+      sh->eox = o.eox; sh->eoy = o.eoy; sh->ib_e = o.ib_e;
+      sh->collided = o.collided;
+      sh->rho_max = 0;
+    }
+    __syncthreads();
+    int32_t wy0;
+    stage_world<NT>(P, m, sh->toy >> 16, L.world_halo, uni, wy0);
+    __syncthreads();
+    march_rays<NT>(P, m, sh, uni, wy0, rho_lds, A.ranges, L.record != 0, r);
+    __syncthreads();
+    for (int32_t k = threadIdx.x; k < P.R; k += NT) atomicMax(&sh->rho_max, rho_lds[k] & 0x7fffffff);
+    __syncthreads();
+    update_and_reward<NT>(P, A, m, sh, rho_lds, uni, lut, L, r);
+    __syncthreads();
+  }
+}
+
+__global__ void k_reset(EnvParams P, const uint32_t* world_src, const float* init_pose, const uint8_t* mask) {
+  const int32_t r = blockIdx.x;
+  if (mask && !mask[r]) return;
+  const RobotMeta m = P.meta[r];
+  const int32_t s = m.side;
+  int32_t* bel = reinterpret_cast<int32_t*>(P.belief + m.cell_off);
+  const int64_t npair = (int64_t)s * s / 2;
+  for (int64_t k = threadIdx.x; k < npair; k += blockDim.x) bel[k] = 0;
+  const int64_t nw = (int64_t)s * s / 32;
+  uint32_t* wd = const_cast<uint32_t*>(P.world) + m.world_off;
+  const uint32_t* ws = world_src + m.world_off;
+  for (int64_t k = threadIdx.x; k < nw; k += blockDim.x) wd[k] = ws[k];
+  if (P.loop_closure) {
+    const int64_t nv = (int64_t)m.visit_side * m.visit_side;
+    for (int64_t k = threadIdx.x; k < nv; k += blockDim.x) {
+      P.visit_t[m.visit_off + k] = -1;
+      P.visit_xy[2 * (m.visit_off + k)] = 0.0f;
+      P.visit_xy[2 * (m.visit_off + k) + 1] = 0.0f;
+    }
+  }
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < 3; ++k) {
+      P.pose[3 * (int64_t)r + k] = init_pose[3 * (int64_t)r + k];
+      P.est[3 * (int64_t)r + k] = init_pose[3 * (int64_t)r + k];
+    }
+    float* c = P.cov + 6 * (int64_t)r;
+    c[0] = P.var0_xy; c[1] = 0.0f; c[2] = 0.0f;
+    c[3] = P.var0_xy; c[4] = 0.0f; c[5] = P.var0_th;
+    P.hq_total[r] = (int64_t)s * (int64_t)s * (int64_t)P.hq_lut[P.lclamp];
+    P.step[r] = 0;
+    P.last_lc[r] = -(1 << 30);
+    P.flags[2 * (int64_t)r] = 0;
+    P.flags[2 * (int64_t)r + 1] = 0;
+  }
+}
+
+__global__ void k_observe(EnvParams P, const float* ranges, int16_t* crop, int32_t cs, float* scan, float* state,
+                          float inv_r, float inv_pi) {
+  const int32_t r = blockIdx.x;
+  const RobotMeta m = P.meta[r];
+  const int32_t s = m.side;
+  const float* e = P.est + 3 * (int64_t)r;
+  const int32_t ecx = to_q16(e[0], P.inv_c16) >> 16;
+  const int32_t ecy = to_q16(e[1], P.inv_c16) >> 16;
+  const int16_t* bel = P.belief + m.cell_off;
+  int16_t* out = crop + (int64_t)r * cs * cs;
+  for (int32_t k = threadIdx.x; k < cs * cs; k += blockDim.x) {
+    const int32_t ii = k % cs, jj = k / cs;
+    const int32_t i = ecx - cs / 2 + ii, j = ecy - cs / 2 + jj;
+    out[k] = (i >= 0 && i < s && j >= 0 && j < s) ? bel[(int64_t)j * s + i] : (int16_t)0;
+  }
+  for (int32_t k = threadIdx.x; k < P.R; k += blockDim.x)
+    scan[(int64_t)r * P.R + k] = ranges[(int64_t)r * P.R + k] * inv_r;
+  if (threadIdx.x == 0) {
+    const float* c = P.cov + 6 * (int64_t)r;
+    float* o = state + 12 * (int64_t)r;
+    const float inv_ext = m.inv_ext;
+    o[0] = e[0] * inv_ext; o[1] = e[1] * inv_ext; o[2] = e[2] * inv_pi;
+    o[3] = c[0]; o[4] = c[1]; o[5] = c[2];
+    o[6] = c[1]; o[7] = c[3]; o[8] = c[4];
+    o[9] = c[2]; o[10] = c[4]; o[11] = c[5];
+  }
+}
+
+template <int NT>
+hipError_t plain_nt(const EnvParams& P, const StepArgs& A, const LdsPlan& L, hipStream_t st) {
+  k_motion<<<(P.n + 255) / 256, 256, 0, st>>>(P, A);
+  k_march<NT><<<P.n, NT, L.total, st>>>(P, A, L);
+  k_update<NT><<<P.n, NT, L.total, st>>>(P, A, L);
+  return hipGetLastError();
+}
+
+template <int NT>
+hipError_t fused_nt(const EnvParams& P, const StepArgs& A, const LdsPlan& L, int grid, hipStream_t st) {
+  k_fused<NT><<<grid, NT, L.total, st>>>(P, A, L);
+  return hipGetLastError();
+}
+
+template <int NT>
+hipError_t set_lds_nt(int bytes) {
+  hipError_t e;
+  if ((e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_march<NT>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes)) != hipSuccess) return e;
+  if ((e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_update<NT>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes)) != hipSuccess) return e;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fused<NT>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
+}  // namespace
+
+hipError_t launch_reset(const EnvParams& P, const uint32_t* world_src, const float* init_pose,
+                        const uint8_t* mask, int32_t, hipStream_t stream) {
+  k_reset<<<P.n, 256, 0, stream>>>(P, world_src, init_pose, mask);
+  return hipGetLastError();
+}
+
+hipError_t launch_step_plain(const EnvParams& P, const StepArgs& A, const LdsPlan& L, int threads,
+                             hipStream_t stream) {
+  switch (threads) {
+    case 128: return plain_nt<128>(P, A, L, stream);
+    case 256: return plain_nt<256>(P, A, L, stream);
+    case 512: return plain_nt<512>(P, A, L, stream);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_step_fused(const EnvParams& P, const StepArgs& A, const LdsPlan& L, int threads, int grid,
+                             hipStream_t stream) {
+  switch (threads) {
+    case 128: return fused_nt<128>(P, A, L, grid, stream);
+    case 256: return fused_nt<256>(P, A, L, grid, stream);
+    case 512: return fused_nt<512>(P, A, L, grid, stream);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_observe(const EnvParams& P, const float* ranges, int16_t* crop, int32_t cs, float* scan,
+                          float* state, hipStream_t stream) {
+  k_observe<<<P.n, 256, 0, stream>>>(P, ranges, crop, cs, scan, state, P.inv_rmax, P.inv_pi);
+  return hipGetLastError();
+}
+
+hipError_t set_kernel_lds_limits(int bytes) {
+  hipError_t e;
+  if ((e = set_lds_nt<128>(bytes)) != hipSuccess) return e;
+  if ((e = set_lds_nt<256>(bytes)) != hipSuccess) return e;
+  return set_lds_nt<512>(bytes);
+}
+
+}  // namespace aslam
