@@ -1,0 +1,282 @@
+"""Benchmark of the batched Active-SLAM hot path on one MI355X.
+
+One step = one environment step of every robot (motion and collision, EKF
+predict and loop closure, LiDAR march, log-odds map update, entropy and
+D-optimality reward) followed by the observation assembly for the policy.
+Inputs (worlds, start poses, actions, normal draws) are seeded, synthetic and
+resident in HBM before the timed region.  Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "env-steps/s and rays/s at 750 & 4096 robots; % HBM roofline; PPO fwd+bwd/s"
+
+
+def alg_bytes_per_robot_step(D: float, R: int, loop_closure: bool) -> float:
+    """Algorithmic HBM bytes of one robot-step.
+
+    Map: read + write each coded int16 cell (4 B); world bits of the cells the
+    rays cross, taken equal to the coded cells (D/8 B); ranges out (4R B);
+    per-robot state and I/O: action 8, normal draws 20, true pose r/w 24,
+    estimate r/w 24, covariance r/w 48, step r/w 8, entropy r/w 16, reward 4,
+    done 1 (153 B); loop-closure visit record read 12 B."""
+    return 4.0 * D + D / 8.0 + 4.0 * R + 153.0 + (12.0 if loop_closure else 0.0)
+
+
+def kernel_source_digest() -> str:
+    h = hashlib.sha256()
+    for f in ("env_kernels.hip", "env_internal.h"):
+        with open(os.path.join(ROOT, "paper_2603_25834_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(kernel: str, workload: str):
+    """HBM traffic per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("source_digest") != kernel_source_digest():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+class Workbench:
+    """One workload on the GPU: env + resident inputs + output buffers."""
+
+    def __init__(self, name: str, seed: int, steps: int, exec_kw: dict):
+        import torch
+
+        from paper_2603_25834_amd import synth
+        from paper_2603_25834_amd.env import Env
+        self.torch = torch
+        self.name = name
+        w = self.w = synth.WORKLOADS[name]
+        self.p = w.params()
+        t0 = time.time()
+        self.b = synth.make_batch(name, seed)
+        self.n, self.R = len(self.b.sides), w.n_rays
+        A = synth.actions(name, seed, steps)
+        G = synth.noise(name, seed, steps)
+        self.gen_s = time.time() - t0
+        self.env = Env(self.p, self.b.sides)
+        self.env.set_exec(**exec_kw)
+        self.exec_kw = exec_kw
+        dev = "cuda"
+        self.world = torch.from_numpy(self.b.world.view(np.int32).copy()).to(dev)
+        self.start = torch.from_numpy(self.b.start).to(dev)
+        self.dA = torch.from_numpy(A).to(dev)
+        self.dG = torch.from_numpy(G).to(dev)
+        self.ranges = torch.zeros((self.n, self.R), device=dev)
+        self.reward = torch.zeros(self.n, device=dev)
+        self.done = torch.zeros(self.n, dtype=torch.uint8, device=dev)
+        self.crop = torch.zeros((self.n, 64, 64), dtype=torch.int16, device=dev)
+        self.scan = torch.zeros((self.n, self.R), device=dev)
+        self.state = torch.zeros((self.n, 12), device=dev)
+        self.env.reset(self.world, self.start)
+
+    def run(self, warmup: int, steps: int, graph: bool = True):
+        """Warm up, then time `steps` env steps (one HIP graph, or eager launches)."""
+        torch = self.torch
+        from paper_2603_25834_amd import _lib
+        e = self.env
+        n = self.n
+        for t in range(warmup):
+            e.step(self.dA[t], self.dG[t], self.ranges, self.reward, self.done)
+        if graph:
+            e.graph_build(steps, self.dA[warmup:], 2 * n, self.dG[warmup:], 5 * n, self.ranges, 0, self.reward, 0,
+                          self.done, 0)
+        torch.cuda.synchronize()
+        c0 = e.read(_lib.FIELD_COUNTERS).sum(0).cpu().numpy()
+        t_start = torch.cuda.Event(enable_timing=True)
+        t_end = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t_start.record()
+        if graph:
+            e.graph_launch()
+        else:
+            for t in range(warmup, warmup + steps):
+                e.step(self.dA[t], self.dG[t], self.ranges, self.reward, self.done)
+        t_end.record()
+        torch.cuda.synchronize()
+        ms = t_start.elapsed_time(t_end)
+        c1 = e.read(_lib.FIELD_COUNTERS).sum(0).cpu().numpy()
+        D = float(c1[0] - c0[0]) / (n * steps)
+        vm = float(c1[1] - c0[1]) / (n * steps)
+        vu = float(c1[2] - c0[2]) / (n * steps)
+        bytes_step = n * alg_bytes_per_robot_step(D, self.R, bool(self.p["loop_closure"]))
+        s = ms / 1e3
+        return dict(ms=ms, ms_per_step=ms / steps, env_steps_per_s=n * steps / s, rays_per_s=n * steps * self.R / s,
+                    coded_cells_per_robot_step=D, march_visits_per_robot_step=vm, update_visits_per_robot_step=vu,
+                    alg_bytes_per_step=bytes_step, achieved_gbs=bytes_step * steps / s / 1e9)
+
+    def observe_time(self, reps: int = 20) -> float:
+        torch = self.torch
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record()
+        for _ in range(reps):
+            self.env.observe(self.ranges, self.crop, self.scan, self.state)
+        t1.record()
+        torch.cuda.synchronize()
+        return t0.elapsed_time(t1) / reps
+
+
+def cpu_baseline(name: str, seed: int, robots: int, steps: int) -> dict:
+    """The oracle as it stands, all host threads, on a bounded sample of the workload."""
+    from oracle import oracle as O
+    from paper_2603_25834_amd import synth
+    w = synth.WORKLOADS[name]
+    idx = np.arange(min(robots, w.n_robots))
+    b = synth.make_batch(name, seed, idx)
+    A = synth.actions(name, seed, steps, idx)
+    G = synth.noise(name, seed, steps, idx)
+    env = O.OracleEnv(w.params(), b.sides, b.world, b.world_off)
+    env.reset(b.start)
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
+    threads = min(threads, os.cpu_count() or threads)
+    cnt = np.zeros(4, np.int64)
+    t0 = time.time()
+    for t in range(steps):
+        o = env.step(A[t], G[t], threads=threads)
+        cnt += o.counters.sum(0)
+    dt = time.time() - t0
+    rs = len(idx) * steps
+    return {"value": rs / dt, "unit": "env-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"{name}: first {len(idx)} robots x {steps} steps ({dt:.1f} s)",
+            "rays_per_s": rs * w.n_rays / dt,
+            "coded_cells_per_robot_step": float(cnt[2]) / rs, "world_cells_read_per_robot_step": float(cnt[3]) / rs}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="paper_750x256")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--threads", type=int, default=256)
+    ap.add_argument("--band", type=int, default=0)
+    ap.add_argument("--grid", type=int, default=0)
+    ap.add_argument("--eager", action="store_true", help="eager launches instead of one HIP graph")
+    ap.add_argument("--secondary", default="ragged_4096", help="second workload ('' to skip)")
+    ap.add_argument("--secondary-steps", type=int, default=200)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-robots", type=int, default=750)
+    ap.add_argument("--cpu-steps", type=int, default=1000)
+    ap.add_argument("--calib-copy", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (counter calibration under rocprofv3)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); robots shard across GPUs "
+              "with no exchange, see DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    from paper_2603_25834_amd import _lib
+    from paper_2603_25834_amd.env import device_info
+    lds, cus = device_info()
+
+    fused = dict(form=_lib.FORM_FUSED, threads=args.threads, band_rows=args.band, grid=args.grid)
+    plain = dict(form=_lib.FORM_PLAIN, threads=args.threads, band_rows=args.band)
+    print(f"[bench] {args.workload}: setting up", file=sys.stderr, flush=True)
+    wb = Workbench(args.workload, args.seed, args.warmup + args.steps, fused)
+    res = wb.run(args.warmup, args.steps, graph=not args.eager)
+    print(f"[bench] fused: {res['ms_per_step']*1e3:.1f} us/step", file=sys.stderr, flush=True)
+    obs_ms = wb.observe_time()
+    wb.env.set_exec(**plain)
+    wb.env.reset(wb.world, wb.start)
+    res_plain = wb.run(args.warmup, args.steps, graph=not args.eager)
+    print(f"[bench] plain: {res_plain['ms_per_step']*1e3:.1f} us/step", file=sys.stderr, flush=True)
+    if args.calib_copy:
+        src = torch.ones(args.calib_copy << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    step_ms = res["ms_per_step"] + obs_ms
+    value = wb.n / (step_ms / 1e3)
+    traffic = read_traffic("k_fused", args.workload)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "env-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": step_ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic (seeded worlds, start poses, actions and normal draws)",
+        "config": {"workload": args.workload, "robots": wb.n, "grid_side": sorted(set(map(int, wb.b.sides))),
+                   "rays": wb.R, "r_max_m": wb.p["r_max_m"], "cell_m": wb.p["cell_m"],
+                   "loop_closure": int(wb.p["loop_closure"]), "form": "fused persistent, HIP graph",
+                   "threads": args.threads, "lds_bytes": wb.env.get_exec()["lds_bytes"]},
+        "rays_per_s": value * wb.R,
+        "env_step_only": {"env_steps_per_s": res["env_steps_per_s"], "ms_per_step": res["ms_per_step"],
+                          "observe_ms": obs_ms},
+        "plain_form": {"env_steps_per_s": res_plain["env_steps_per_s"], "ms_per_step": res_plain["ms_per_step"],
+                       "fused_speedup": res["env_steps_per_s"] / res_plain["env_steps_per_s"]},
+        "roofline": {"bound": "hbm", "achieved": res["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": res["achieved_gbs"] / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_fused", "alg_bytes_per_launch": res["alg_bytes_per_step"],
+                     "avg_launch_ms": res["ms_per_step"],
+                     "coded_cells_per_robot_step": res["coded_cells_per_robot_step"],
+                     "cell_visits_per_robot_step": res["march_visits_per_robot_step"] +
+                     res["update_visits_per_robot_step"]},
+        "device": {"lds_per_block": lds, "compute_units": cus},
+    }
+    if args.secondary:
+        print(f"[bench] {args.secondary}: setting up", file=sys.stderr, flush=True)
+        del wb
+        torch.cuda.empty_cache()
+        wb2 = Workbench(args.secondary, args.seed, args.warmup + args.secondary_steps, fused)
+        r2 = wb2.run(args.warmup, args.secondary_steps)
+        wb2.env.set_exec(**plain)
+        wb2.env.reset(wb2.world, wb2.start)
+        r2p = wb2.run(args.warmup, args.secondary_steps)
+        out["secondary"] = {
+            "workload": args.secondary, "robots": wb2.n, "steps": args.secondary_steps,
+            "fused_env_steps_per_s": r2["env_steps_per_s"], "fused_rays_per_s": r2["rays_per_s"],
+            "plain_env_steps_per_s": r2p["env_steps_per_s"], "fused_speedup": r2["env_steps_per_s"] / r2p["env_steps_per_s"],
+            "fused_hbm_gbs": r2["achieved_gbs"], "fused_hbm_frac": r2["achieved_gbs"] / HBM_PEAK_GBS,
+            "coded_cells_per_robot_step": r2["coded_cells_per_robot_step"]}
+        print(f"[bench] {args.secondary}: fused {r2['ms_per_step']*1e3:.1f} us/step, plain "
+              f"{r2p['ms_per_step']*1e3:.1f} us/step", file=sys.stderr, flush=True)
+        del wb2
+    if not args.no_cpu:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(args.workload, args.seed, args.cpu_robots, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -79,7 +79,7 @@ typedef struct {
 
 typedef struct {
   int32_t form;          /* ASLAM_FORM_* */
-  int32_t threads;       /* threads per workgroup: 64, 128, 256, 512 or 1024 */
+  int32_t threads;       /* threads per workgroup: 128, 192, 256, 384 or 512 */
   int32_t band_rows;     /* rows of the LDS code window per pass (>= 8); 0 = as many as fit */
   int32_t grid;          /* FUSED: workgroups launched; 0 = one per robot */
   int32_t record_rays;   /* FUSED: also write per-ray rho_q / hit_cell to the state (PLAIN always does) */
@@ -142,6 +142,8 @@ int aslam_env_observe(aslam_env* env, const float* ranges_dev, int16_t* crop_dev
 #define ASLAM_FIELD_STEP 7       /* int32 [n] steps since reset */
 #define ASLAM_FIELD_FLAGS 8      /* uint8 [n,2] collided, loop closure fired (last step) */
 #define ASLAM_FIELD_TERMS 9      /* float [n,2] entropy decrease (nats), ln det Sigma (last step) */
+#define ASLAM_FIELD_COUNTERS 10  /* int64 [n,3] since reset: coded (updated) cells, LiDAR-march cell
+                                    visits, map-update cell visits -- the work measures of the step */
 int aslam_env_read(const aslam_env* env, int32_t field, void* dst_dev, aslam_stream_t stream);
 
 /* HIP graph of K consecutive env_step calls.  Step k reads

@@ -18,7 +18,7 @@ FORM_PLAIN = 0
 FORM_FUSED = 1
 
 FIELD_BELIEF, FIELD_POSE, FIELD_EST, FIELD_COV, FIELD_RHO_Q, FIELD_HIT_CELL, FIELD_ENTROPY_Q, \
-    FIELD_STEP, FIELD_FLAGS, FIELD_TERMS = range(10)
+    FIELD_STEP, FIELD_FLAGS, FIELD_TERMS, FIELD_COUNTERS = range(11)
 
 
 class AslamError(RuntimeError):

@@ -71,6 +71,7 @@ struct aslam_env {
   void* d_hitc = nullptr;
   void* d_flags = nullptr;
   void* d_terms = nullptr;
+  void* d_counters = nullptr;
   void* d_dirtab = nullptr;
   void* d_hq_lut = nullptr;
   // captured step sequence
@@ -84,7 +85,7 @@ namespace {
 void free_env(aslam_env* e) {
   void** ptrs[] = {&e->d_meta, &e->d_order, &e->d_world, &e->d_belief, &e->d_pose, &e->d_est, &e->d_cov,
                    &e->d_hq_total, &e->d_step, &e->d_last_lc, &e->d_visit_t, &e->d_visit_xy, &e->d_rho,
-                   &e->d_hitc, &e->d_flags, &e->d_terms, &e->d_dirtab, &e->d_hq_lut};
+                   &e->d_hitc, &e->d_flags, &e->d_terms, &e->d_counters, &e->d_dirtab, &e->d_hq_lut};
   for (void** p : ptrs) {
     if (*p) (void)hipFree(*p);
     *p = nullptr;
@@ -247,6 +248,7 @@ int aslam_env_create(const aslam_env_config* cfg, int32_t n_robots, const int32_
       {&e->d_hitc, sizeof(int32_t) * (size_t)(R * n_robots)},
       {&e->d_flags, 2 * (size_t)n_robots},
       {&e->d_terms, sizeof(float) * 2 * (size_t)n_robots},
+      {&e->d_counters, sizeof(int64_t) * 3 * (size_t)n_robots},
       {&e->d_dirtab, sizeof(int32_t) * (size_t)kNang},
       {&e->d_hq_lut, sizeof(uint32_t) * (size_t)(2 * quantise_logodds(cfg->l_clamp) + 1)},
   };
@@ -326,6 +328,7 @@ int aslam_env_create(const aslam_env_config* cfg, int32_t n_robots, const int32_
   P.hitc = (int32_t*)e->d_hitc;
   P.flags = (uint8_t*)e->d_flags;
   P.terms = (float*)e->d_terms;
+  P.counters = (int64_t*)e->d_counters;
   P.dirtab = (const int32_t*)e->d_dirtab;
   P.hq_lut = (const uint32_t*)e->d_hq_lut;
 
@@ -366,8 +369,8 @@ int64_t aslam_env_cells(const aslam_env* env) { return env ? env->cells : -1; }
 int aslam_env_set_exec(aslam_env* env, const aslam_exec_config* ex) {
   if (!env || !ex) return fail(ASL_EINVAL, "env or exec config is NULL");
   if (ex->form != ASLAM_FORM_PLAIN && ex->form != ASLAM_FORM_FUSED) return fail(ASL_EINVAL, "unknown form");
-  if (ex->threads != 128 && ex->threads != 256 && ex->threads != 512)
-    return fail(ASL_EINVAL, "threads must be 128, 256 or 512");
+  if (ex->threads != 128 && ex->threads != 192 && ex->threads != 256 && ex->threads != 384 && ex->threads != 512)
+    return fail(ASL_EINVAL, "threads must be 128, 192, 256, 384 or 512");
   if (ex->grid < 0 || ex->band_rows < 0 || ex->lds_bytes < 0) return fail(ASL_EINVAL, "negative exec field");
   LdsPlan L{};
   int rc = plan_lds(env, *ex, L);
@@ -439,6 +442,7 @@ int aslam_env_read(const aslam_env* env, int32_t field, void* dst_dev, aslam_str
     case ASLAM_FIELD_STEP: src = env->d_step; bytes = 4 * n; break;
     case ASLAM_FIELD_FLAGS: src = env->d_flags; bytes = 2 * n; break;
     case ASLAM_FIELD_TERMS: src = env->d_terms; bytes = 8 * n; break;
+    case ASLAM_FIELD_COUNTERS: src = env->d_counters; bytes = 24 * n; break;
     default: return fail(ASL_EINVAL, "unknown field");
   }
   HIP_TRY(hipMemcpyAsync(dst_dev, src, bytes, hipMemcpyDeviceToDevice, (hipStream_t)stream), "read");

@@ -60,6 +60,7 @@ struct EnvParams {
   int32_t* hitc;         // [n,R]
   uint8_t* flags;        // [n,2] collided, closed
   float* terms;          // [n,2] entropy decrease, ln det
+  int64_t* counters;     // [n,3] cumulative: coded cells, march visits, update visits
   const int32_t* dirtab; // [kNang] (cos & 0xffff) | (sin << 16), Q14
   const uint32_t* hq_lut;// [2*lclamp+1] binary entropy, 2^-32 nat
 };

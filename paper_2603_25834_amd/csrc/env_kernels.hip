@@ -85,6 +85,12 @@ __device__ bool segment_blocked(const uint32_t* w, int32_t s, int32_t ox, int32_
   return true;
 }
 
+__device__ __forceinline__ int32_t wave_sum_i32(int32_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
 struct MotionOut {
   int32_t tox, toy, ib_t;   // true origin (Q16) and heading index
   int32_t eox, eoy, ib_e;   // estimated origin and heading index
@@ -210,19 +216,28 @@ struct RobotShared {
   int32_t eox, eoy, ib_e;
   int32_t collided;
   int32_t rho_max;
-  int32_t pad[7];
+  int32_t cnt_march, cnt_upd;
+  int32_t pad[5];
   long long part[16];
+  int32_t dpart[16];
 };
 
 // ---------------------------------------------------------------- DDA setup
 // Ray from Q16 origin o with table direction (a,b) (Q14), limit lim (Q16 cells).
 // x crossings happen at axis distances ex0 + k*65536; the k-th is within the
 // limit iff (ex0 + k*65536) * 2^14 <= lim * |a|.
+// The walk stops at the first crossing that is not allowed (beyond the limit
+// or off the grid); crossings are taken in parameter order, an x crossing
+// before a y crossing at the same parameter.  `n` is the exact number of
+// steps before that crossing, so the loops run a known trip count.
 struct RaySetup {
   int32_t D, DX, DY;
   int32_t nx, ny;          // x / y steps allowed (limit and grid)
   int32_t gx, gy;          // 1: running out of x / y steps means leaving the grid
   int32_t ex0, ey0, aa, bb;
+  int32_t n;               // steps taken by the walk (cells visited = n + 1)
+  int32_t kx, ky;          // x / y steps among them
+  int32_t gend;            // 1: the walk ends by leaving the grid (else by the limit)
 };
 
 __device__ __forceinline__ RaySetup ray_setup(int32_t ox, int32_t oy, int32_t a, int32_t b, int32_t lim,
@@ -247,7 +262,45 @@ __device__ __forceinline__ RaySetup ray_setup(int32_t ox, int32_t oy, int32_t a,
   else if (bb == 0) { q.D = -1; q.DX = 0; q.DY = 0; }
   else { q.D = ex0 * bb - ey0 * aa; q.DX = bb << 16; q.DY = aa << 16; }
   q.ex0 = ex0; q.ey0 = ey0; q.aa = aa; q.bb = bb;
+  // Which forbidden crossing comes first: x crossing #nx at parameter
+  // Tx/(aa bb), y crossing #ny at Ty/(aa bb) (x first on a tie).
+  if (aa == 0) {
+    q.kx = 0; q.ky = q.ny; q.gend = q.gy;
+  } else if (bb == 0) {
+    q.kx = q.nx; q.ky = 0; q.gend = q.gx;
+  } else {
+    const int64_t Tx = (int64_t)(ex0 + (int64_t)q.nx * kQ16) * bb;
+    const int64_t Ty = (int64_t)(ey0 + (int64_t)q.ny * kQ16) * aa;
+    if (Tx <= Ty) {
+      // y crossings j strictly before it: (ey0 + j*65536)*aa < Tx
+      const int64_t X = Tx - (int64_t)ey0 * aa;
+      const int64_t den = (int64_t)aa << 16;
+      const int32_t cnt = X <= 0 ? 0 : (int32_t)((X + den - 1) / den);
+      q.kx = q.nx; q.ky = min(cnt, q.ny); q.gend = q.gx;
+    } else {
+      // x crossings k at or before it: (ex0 + k*65536)*bb <= Ty
+      const int64_t Y = Ty - (int64_t)ex0 * bb;
+      const int64_t den = (int64_t)bb << 16;
+      const int32_t cnt = Y < 0 ? 0 : (int32_t)(Y / den) + 1;
+      q.kx = min(cnt, q.nx); q.ky = q.ny; q.gend = q.gy;
+    }
+  }
+  q.n = q.kx + q.ky;
   return q;
+}
+
+// Entry axis of the cell reached after at least one step: with D in
+// (-DY, DX], an x step leaves D in (DX-DY, DX] and a y step in (-DY, DX-DY].
+__device__ __forceinline__ bool last_step_x(const RaySetup& q, int32_t D) {
+  if (q.aa == 0) return false;
+  if (q.bb == 0) return true;
+  return D > q.DX - q.DY;
+}
+
+__device__ __forceinline__ int32_t wave_max_i32(int32_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  return v;
 }
 
 // ---------------------------------------------------------------- stages
@@ -260,71 +313,166 @@ __device__ void stage_world(const EnvParams& P, const RobotMeta& m, int32_t cy, 
   const int32_t wpr = s >> 5;
   const int32_t nwords = (y1 - y0 + 1) * wpr;
   const uint32_t* src = P.world + m.world_off + (int64_t)y0 * wpr;
-  for (int32_t k = threadIdx.x; k < nwords; k += NT) sw[k] = src[k];
+  // rows start on 16-byte boundaries when s is a multiple of 128 (8 when of 64)
+  if ((wpr & 3) == 0) {
+    const uint4* s4 = reinterpret_cast<const uint4*>(src);
+    uint4* d4 = reinterpret_cast<uint4*>(sw);
+#pragma unroll 4
+    for (int32_t k = threadIdx.x; k < (nwords >> 2); k += NT) d4[k] = s4[k];
+  } else if ((wpr & 1) == 0) {
+    const uint2* s2 = reinterpret_cast<const uint2*>(src);
+    uint2* d2 = reinterpret_cast<uint2*>(sw);
+#pragma unroll 4
+    for (int32_t k = threadIdx.x; k < (nwords >> 1); k += NT) d2[k] = s2[k];
+  } else {
+#pragma unroll 4
+    for (int32_t k = threadIdx.x; k < nwords; k += NT) sw[k] = src[k];
+  }
   wy0 = y0;
 }
 
 // LiDAR march of every ray of the robot from the true pose (lanes = rays).
 template <int NT>
-__device__ void march_rays(const EnvParams& P, const RobotMeta& m, const RobotShared* sh, const uint32_t* sw,
+__device__ void march_rays(const EnvParams& P, const RobotMeta& m, RobotShared* sh, const uint32_t* sw,
                            int32_t wy0, int32_t* rho_lds, float* ranges_out, bool record, int32_t r) {
   const int32_t s = m.side;
   const int32_t tox = sh->tox, toy = sh->toy, ib = sh->ib_t;
   const int32_t cx0 = tox >> 16, cy0 = toy >> 16;
   const bool inside = cx0 >= 0 && cx0 < s && cy0 >= 0 && cy0 < s;
-  for (int32_t k = threadIdx.x; k < P.R; k += NT) {
+  int32_t visits = 0;
+  for (int32_t k0 = 0; k0 < P.R; k0 += NT) {
+    const int32_t k = k0 + (int32_t)threadIdx.x;
+    const bool active = inside && k < P.R;
     int32_t rq = P.rhat_q;
     int32_t cell = -1;
-    if (inside) {
+    RaySetup q{};
+    int32_t li = 0, D = 0, i = 0, sx = 0, sy = 0;
+    bool hit = false, done = true;
+    if (active) {
       int32_t id = ib + k * P.step_ang;
       id -= (id >= kNang) ? kNang : 0;
       const int32_t dv = P.dirtab[id];
       const int32_t a = (int16_t)(dv & 0xffff), b = dv >> 16;
-      RaySetup q = ray_setup(tox, toy, a, b, P.rhat_q, s);
-      int32_t li = (cy0 - wy0) * s + cx0;
-      const int32_t sx = a > 0 ? 1 : -1;
-      const int32_t sy = b > 0 ? s : -s;
-      int32_t rx = q.nx, ry = q.ny, D = q.D;
-      bool lastx = false;
-      bool hit = (sw[li >> 5] >> (li & 31)) & 1u;
-      while (!hit) {
+      q = ray_setup(tox, toy, a, b, P.rhat_q, s);
+      li = (cy0 - wy0) * s + cx0;
+      sx = a > 0 ? 1 : -1;
+      sy = b > 0 ? s : -s;
+      D = q.D;
+      hit = (sw[li >> 5] >> (li & 31)) & 1u;
+      done = hit || q.n == 0;
+    }
+    // one cell per iteration; the loop runs while any lane of the wave walks
+    while (__builtin_amdgcn_ballot_w64(!done) != 0) {
+      if (!done) {
         const bool stepx = D <= 0;
-        const int32_t rem = stepx ? rx : ry;
-        if (rem == 0) break;
-        rx -= stepx ? 1 : 0;
-        ry -= stepx ? 0 : 1;
         li += stepx ? sx : sy;
         D += stepx ? q.DX : -q.DY;
-        lastx = stepx;
+        ++i;
         hit = (sw[li >> 5] >> (li & 31)) & 1u;
+        done = hit || i >= q.n;
       }
+    }
+    if (active) {
+      visits += i + 1;
       if (hit) {
         cell = li + wy0 * s;
-        const int32_t tx = q.nx - rx, ty = q.ny - ry;
-        if (tx + ty == 0) {
-          rq = 0;
-        } else if (lastx) {
-          const int64_t E = (int64_t)q.ex0 + (int64_t)(tx - 1) * kQ16;
-          rq = (int32_t)((E * kDirOne + q.aa - 1) / q.aa);
+        if (i > 0) {
+          const int32_t row = li / s;
+          if (last_step_x(q, D)) {
+            const int32_t kx = abs(li - row * s - cx0);
+            const int64_t E = (int64_t)q.ex0 + (int64_t)(kx - 1) * kQ16;
+            rq = (int32_t)((E * kDirOne + q.aa - 1) / q.aa);
+          } else {
+            const int32_t ky = abs(row + wy0 - cy0);
+            const int64_t E = (int64_t)q.ey0 + (int64_t)(ky - 1) * kQ16;
+            rq = (int32_t)((E * kDirOne + q.bb - 1) / q.bb);
+          }
         } else {
-          const int64_t E = (int64_t)q.ey0 + (int64_t)(ty - 1) * kQ16;
-          rq = (int32_t)((E * kDirOne + q.bb - 1) / q.bb);
+          rq = 0;
         }
       }
     }
-    rho_lds[k] = rq | (cell >= 0 ? (int32_t)0x80000000 : 0);
-    ranges_out[(int64_t)r * P.R + k] = (float)rq * P.c16;
-    if (record) {
-      P.rho[(int64_t)r * P.R + k] = rq;
-      P.hitc[(int64_t)r * P.R + k] = cell;
+    if (k < P.R) {
+      rho_lds[k] = rq | (cell >= 0 ? (int32_t)0x80000000 : 0);
+      ranges_out[(int64_t)r * P.R + k] = (float)rq * P.c16;
+      if (record) {
+        P.rho[(int64_t)r * P.R + k] = rq;
+        P.hitc[(int64_t)r * P.R + k] = cell;
+      }
     }
   }
+  visits = wave_sum_i32(visits);
+  if ((threadIdx.x & 63) == 0 && visits) atomicAdd(&sh->cnt_march, visits);
 }
 
 __device__ __forceinline__ long long wave_sum_i64(long long v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
+}
+
+// One saturating add per coded cell of a band of the code window.  The band
+// is split into octets (8 cells, one 16-byte access, 16-byte aligned because
+// the window starts on a 32-cell boundary); each thread keeps U octets in
+// flight.  An octet is owned by one thread, so the read-modify-write is
+// race-free; uncoded cells of a touched octet are written back unchanged.
+template <int NT>
+__device__ __forceinline__ void apply_band(const EnvParams& P, const uint32_t* miss, const uint32_t* hitm,
+                                           int32_t rows, int32_t nw, int16_t* band_base, int32_t s,
+                                           const uint32_t* lut, long long& dh, int32_t& ncoded) {
+  constexpr int U = 4;
+  const int32_t lpr = nw * 4;  // octets per row
+  const int32_t total = rows * lpr;
+  int32_t row = (int32_t)threadIdx.x / lpr;
+  int32_t col = (int32_t)threadIdx.x - row * lpr;
+  const int32_t qa = NT / lpr, ra = NT - qa * lpr;
+  const int32_t lc = P.lclamp;
+  for (int32_t o = threadIdx.x; o < total; o += U * NT) {
+    uint32_t cm[U], ch[U];
+    int32_t off[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      uint32_t wm = 0u, wh = 0u;
+      if (o + u * NT < total) {
+        wm = miss[row * nw + (col >> 2)];
+        wh = hitm[row * nw + (col >> 2)];
+      }
+      const int32_t sh = (col & 3) * 8;
+      cm[u] = (wm >> sh) & 0xffu;
+      ch[u] = (wh >> sh) & 0xffu;
+      off[u] = row * s + col * 8;
+      col += ra;
+      row += qa;
+      if (col >= lpr) { col -= lpr; ++row; }
+    }
+    int4 v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (cm[u] | ch[u]) v[u] = *reinterpret_cast<const int4*>(band_base + off[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t any = cm[u] | ch[u];
+      if (!any) continue;
+      ncoded += __builtin_popcount(any);
+      int32_t w[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int32_t l0 = (int16_t)(w[j] & 0xffff), l1 = w[j] >> 16;
+        int32_t n0 = l0, n1 = l1;
+        if ((any >> (2 * j)) & 1u) {
+          n0 = min(max(l0 + (((ch[u] >> (2 * j)) & 1u) ? P.lhit : P.lmiss), -lc), lc);
+          dh += (long long)lut[n0 + lc] - (long long)lut[l0 + lc];
+        }
+        if ((any >> (2 * j + 1)) & 1u) {
+          n1 = min(max(l1 + (((ch[u] >> (2 * j + 1)) & 1u) ? P.lhit : P.lmiss), -lc), lc);
+          dh += (long long)lut[n1 + lc] - (long long)lut[l1 + lc];
+        }
+        w[j] = (n0 & 0xffff) | (n1 << 16);
+      }
+      *reinterpret_cast<int4*>(band_base + off[u]) = make_int4(w[0], w[1], w[2], w[3]);
+    }
+  }
 }
 
 // Map update from the estimated pose with the measured ranges, then the
@@ -339,6 +487,7 @@ __device__ void update_and_reward(const EnvParams& P, const StepArgs& A, const R
   const int32_t ecx = eox >> 16, ecy = eoy >> 16;
   const bool inside = ecx >= 0 && ecx < s && ecy >= 0 && ecy < s;
   long long dh = 0;
+  int32_t ncoded = 0, uvisits = 0;
   if (inside) {
     const int32_t hu = (sh->rho_max >> 16) + 3;
     const int32_t x0 = max(0, ecx - hu), x1 = min(s - 1, ecx + hu);
@@ -349,7 +498,6 @@ __device__ void update_and_reward(const EnvParams& P, const StepArgs& A, const R
     const int32_t band = L.band_rows;
     uint32_t* miss = uni;
     uint32_t* hitm = uni + band * nw;
-    const int32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t base = m.cell_off;
     for (int32_t by0 = y0; by0 <= y1; by0 += band) {
       const int32_t rows = min(band, y1 - by0 + 1);
@@ -357,69 +505,68 @@ __device__ void update_and_reward(const EnvParams& P, const StepArgs& A, const R
       for (int32_t k = threadIdx.x; k < 2 * band * nw; k += NT) uni[k] = 0u;
       __syncthreads();
       // mark: one lane per ray
-      for (int32_t k = threadIdx.x; k < P.R; k += NT) {
-        const int32_t pk = rho_lds[k];
-        const int32_t lim = pk & 0x7fffffff;
-        const bool hit = pk < 0;
-        int32_t id = ib + k * P.step_ang;
-        id -= (id >= kNang) ? kNang : 0;
-        const int32_t dv = P.dirtab[id];
-        const int32_t a = (int16_t)(dv & 0xffff), b = dv >> 16;
-        RaySetup q = ray_setup(eox, eoy, a, b, lim, s);
-        int32_t wi = (ecy - by0) * rowbits + (ecx - x0w);
-        const int32_t sx = a > 0 ? 1 : -1;
-        const int32_t sy = b > 0 ? rowbits : -rowbits;
-        int32_t rx = q.nx, ry = q.ny, D = q.D;
-        if ((uint32_t)wi < band_bits) atomicOr(&miss[wi >> 5], 1u << (wi & 31));
-        bool stepx;
-        while (true) {
-          stepx = D <= 0;
-          const int32_t rem = stepx ? rx : ry;
-          if (rem == 0) break;
-          rx -= stepx ? 1 : 0;
-          ry -= stepx ? 0 : 1;
-          wi += stepx ? sx : sy;
-          D += stepx ? q.DX : -q.DY;
+      for (int32_t k0 = 0; k0 < P.R; k0 += NT) {
+        const int32_t k = k0 + (int32_t)threadIdx.x;
+        const bool valid = k < P.R;
+        RaySetup q{};
+        int32_t wi = 0, sx = 0, sy = 0, D = 0, n = -1;
+        bool hit = false;
+        if (valid) {
+          const int32_t pk = rho_lds[k];
+          hit = pk < 0;
+          int32_t id = ib + k * P.step_ang;
+          id -= (id >= kNang) ? kNang : 0;
+          const int32_t dv = P.dirtab[id];
+          const int32_t a = (int16_t)(dv & 0xffff), b = dv >> 16;
+          q = ray_setup(eox, eoy, a, b, pk & 0x7fffffff, s);
+          wi = (ecy - by0) * rowbits + (ecx - x0w);
+          sx = a > 0 ? 1 : -1;
+          sy = b > 0 ? rowbits : -rowbits;
+          D = q.D;
+          n = q.n;
           if ((uint32_t)wi < band_bits) atomicOr(&miss[wi >> 5], 1u << (wi & 31));
         }
-        const bool grid_end = stepx ? q.gx : q.gy;
-        if (hit && !grid_end && (uint32_t)wi < band_bits) atomicOr(&hitm[wi >> 5], 1u << (wi & 31));
-      }
-      __syncthreads();
-      // apply: each coded cell once, cell pairs (int16x2) per lane, rows per wave
-      for (int32_t row = wave; row < rows; row += NWAVE) {
-        const int32_t y = by0 + row;
-        const uint32_t* mrow = miss + row * nw;
-        const uint32_t* hrow = hitm + row * nw;
-        int32_t* brow = reinterpret_cast<int32_t*>(P.belief + base + (int64_t)y * s + x0w);
-        for (int32_t pr = lane; pr < nw * 16; pr += 64) {
-          const int32_t sft = (pr & 15) * 2;
-          const uint32_t mb = (mrow[pr >> 4] >> sft) & 3u;
-          const uint32_t hb = (hrow[pr >> 4] >> sft) & 3u;
-          if ((mb | hb) == 0u) continue;
-          const int32_t v = brow[pr];
-          const int32_t l0 = (int16_t)(v & 0xffff), l1 = v >> 16;
-          int32_t n0 = l0, n1 = l1;
-          if ((mb | hb) & 1u) {
-            n0 = min(max(l0 + ((hb & 1u) ? P.lhit : P.lmiss), -P.lclamp), P.lclamp);
-            dh += (long long)lut[n0 + P.lclamp] - (long long)lut[l0 + P.lclamp];
-          }
-          if ((mb | hb) & 2u) {
-            n1 = min(max(l1 + ((hb & 2u) ? P.lhit : P.lmiss), -P.lclamp), P.lclamp);
-            dh += (long long)lut[n1 + P.lclamp] - (long long)lut[l1 + P.lclamp];
-          }
-          brow[pr] = (n0 & 0xffff) | (n1 << 16);
+        const int32_t w0 = wi;
+        // uniform trip count over the wave; lanes past their own count only step
+        const int32_t nmax = wave_max_i32(n);
+        for (int32_t i = 0; i < nmax; ++i) {
+          const bool stepx = D <= 0;
+          wi += stepx ? sx : sy;
+          D += stepx ? q.DX : -q.DY;
+          if (i < n && (uint32_t)wi < band_bits) atomicOr(&miss[wi >> 5], 1u << (wi & 31));
+        }
+        if (valid) {
+          if (by0 == y0) uvisits += n + 1;
+          const int32_t we = w0 + q.kx * sx + q.ky * sy;   // last visited cell
+          if (hit && !q.gend && (uint32_t)we < band_bits) atomicOr(&hitm[we >> 5], 1u << (we & 31));
         }
       }
+      __syncthreads();
+      // apply: each coded cell once (8 cells = one 16-byte access per octet)
+      apply_band<NT>(P, miss, hitm, rows, nw, P.belief + base + (int64_t)by0 * s + x0w, s, lut, dh, ncoded);
       __syncthreads();
     }
   }
   dh = wave_sum_i64(dh);
-  if ((threadIdx.x & 63) == 0) sh->part[threadIdx.x >> 6] = dh;
+  ncoded = wave_sum_i32(ncoded);
+  uvisits = wave_sum_i32(uvisits);
+  if ((threadIdx.x & 63) == 0) {
+    sh->part[threadIdx.x >> 6] = dh;
+    sh->dpart[threadIdx.x >> 6] = ncoded;
+    if (uvisits) atomicAdd(&sh->cnt_upd, uvisits);
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
     long long tot = 0;
-    for (int w = 0; w < NWAVE; ++w) tot += sh->part[w];
+    int64_t dsum = 0;
+    for (int w = 0; w < NWAVE; ++w) {
+      tot += sh->part[w];
+      dsum += sh->dpart[w];
+    }
+    int64_t* cnt = P.counters + 3 * (int64_t)r;
+    cnt[0] += dsum;
+    cnt[1] += sh->cnt_march;
+    cnt[2] += sh->cnt_upd;
     P.hq_total[r] += tot;
     const double rH = (double)(-tot) * (1.0 / 4294967296.0);
     const float* c = P.cov + 6 * (int64_t)r;
@@ -458,12 +605,15 @@ __global__ __launch_bounds__(NT) void k_march(EnvParams P, StepArgs A, LdsPlan L
     sh->tox = to_q16(p[0], P.inv_c16);
     sh->toy = to_q16(p[1], P.inv_c16);
     sh->ib_t = heading_index(p[2], P.k_ang);
+    sh->cnt_march = 0;
   }
   __syncthreads();
   int32_t wy0;
   stage_world<NT>(P, m, sh->toy >> 16, L.world_halo, uni, wy0);
   __syncthreads();
   march_rays<NT>(P, m, sh, uni, wy0, rho_lds, A.ranges, true, r);
+  __syncthreads();
+  if (threadIdx.x == 0) P.counters[3 * (int64_t)r + 1] += sh->cnt_march;
 }
 
 template <int NT>
@@ -483,6 +633,8 @@ __global__ __launch_bounds__(NT) void k_update(EnvParams P, StepArgs A, LdsPlan 
     sh->ib_e = heading_index(e[2], P.k_ang);
     sh->collided = P.flags[2 * (int64_t)r];
     sh->rho_max = 0;
+    sh->cnt_march = 0;
+    sh->cnt_upd = 0;
   }
   __syncthreads();
   for (int32_t k = threadIdx.x; k < P.R; k += NT) {
@@ -513,6 +665,8 @@ __global__ __launch_bounds__(NT) void k_fused(EnvParams P, StepArgs A, LdsPlan L
       sh->eox = o.eox; sh->eoy = o.eoy; sh->ib_e = o.ib_e;
       sh->collided = o.collided;
       sh->rho_max = 0;
+      sh->cnt_march = 0;
+      sh->cnt_upd = 0;
     }
     __syncthreads();
     int32_t wy0;
@@ -560,6 +714,9 @@ __global__ void k_reset(EnvParams P, const uint32_t* world_src, const float* ini
     P.last_lc[r] = -(1 << 30);
     P.flags[2 * (int64_t)r] = 0;
     P.flags[2 * (int64_t)r + 1] = 0;
+    P.counters[3 * (int64_t)r] = 0;
+    P.counters[3 * (int64_t)r + 1] = 0;
+    P.counters[3 * (int64_t)r + 2] = 0;
   }
 }
 
@@ -628,7 +785,9 @@ hipError_t launch_step_plain(const EnvParams& P, const StepArgs& A, const LdsPla
                              hipStream_t stream) {
   switch (threads) {
     case 128: return plain_nt<128>(P, A, L, stream);
+    case 192: return plain_nt<192>(P, A, L, stream);
     case 256: return plain_nt<256>(P, A, L, stream);
+    case 384: return plain_nt<384>(P, A, L, stream);
     case 512: return plain_nt<512>(P, A, L, stream);
     default: return hipErrorInvalidValue;
   }
@@ -638,7 +797,9 @@ hipError_t launch_step_fused(const EnvParams& P, const StepArgs& A, const LdsPla
                              hipStream_t stream) {
   switch (threads) {
     case 128: return fused_nt<128>(P, A, L, grid, stream);
+    case 192: return fused_nt<192>(P, A, L, grid, stream);
     case 256: return fused_nt<256>(P, A, L, grid, stream);
+    case 384: return fused_nt<384>(P, A, L, grid, stream);
     case 512: return fused_nt<512>(P, A, L, grid, stream);
     default: return hipErrorInvalidValue;
   }
@@ -653,7 +814,9 @@ hipError_t launch_observe(const EnvParams& P, const float* ranges, int16_t* crop
 hipError_t set_kernel_lds_limits(int bytes) {
   hipError_t e;
   if ((e = set_lds_nt<128>(bytes)) != hipSuccess) return e;
+  if ((e = set_lds_nt<192>(bytes)) != hipSuccess) return e;
   if ((e = set_lds_nt<256>(bytes)) != hipSuccess) return e;
+  if ((e = set_lds_nt<384>(bytes)) != hipSuccess) return e;
   return set_lds_nt<512>(bytes);
 }
 

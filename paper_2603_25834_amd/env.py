@@ -109,6 +109,7 @@ class Env:
         _lib.FIELD_STEP: (torch.int32, lambda s: (s.n,)),
         _lib.FIELD_FLAGS: (torch.uint8, lambda s: (s.n, 2)),
         _lib.FIELD_TERMS: (torch.float32, lambda s: (s.n, 2)),
+        _lib.FIELD_COUNTERS: (torch.int64, lambda s: (s.n, 3)),
     }
 
     def read(self, field: int) -> torch.Tensor:

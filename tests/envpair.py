@@ -52,9 +52,24 @@ class Pair:
         self.reward = torch.zeros(self.n, dtype=torch.float32, device=dev)
         self.done = torch.zeros(self.n, dtype=torch.uint8, device=dev)
         self.t = 0
+        self.cum = np.zeros((self.n, 3), np.int64)   # oracle work counters since reset
+
+    def reset(self, start, mask=None):
+        import torch
+        m = None if mask is None else np.asarray(mask, np.uint8)
+        if self.orc is not None:
+            self.orc.reset(start, m)
+        self.env.reset(self.world, torch.from_numpy(np.ascontiguousarray(start, np.float32)).cuda(),
+                       None if m is None else torch.from_numpy(m).cuda())
+        if m is None:
+            self.cum[:] = 0
+        else:
+            self.cum[m.astype(bool)] = 0
 
     def step(self):
         o = self.orc.step(self.A[self.t], self.G[self.t]) if self.orc is not None else None
+        if o is not None:
+            self.cum += o.counters[:, [2, 0, 1]]
         self.env.step(self.dA[self.t], self.dG[self.t], self.ranges, self.reward, self.done)
         self.t += 1
         return o
@@ -69,6 +84,7 @@ class Pair:
             hq=e.read(_lib.FIELD_ENTROPY_Q).cpu().numpy(), step=e.read(_lib.FIELD_STEP).cpu().numpy(),
             flags=e.read(_lib.FIELD_FLAGS).cpu().numpy(), terms=e.read(_lib.FIELD_TERMS).cpu().numpy(),
             rho=e.read(_lib.FIELD_RHO_Q).cpu().numpy(), hitc=e.read(_lib.FIELD_HIT_CELL).cpu().numpy(),
+            counters=e.read(_lib.FIELD_COUNTERS).cpu().numpy(),
             ranges=self.ranges.cpu().numpy(), reward=self.reward.cpu().numpy(), done=self.done.cpu().numpy())
 
     def compare(self, o, rays: bool = True, belief: bool = True, tag: str = ""):
@@ -92,6 +108,7 @@ class Pair:
             bad = np.flatnonzero(g["belief"] != orc.belief)
             assert bad.size == 0, f"belief differs in {bad.size} cells {where} (first {bad[:5]})"
             assert np.array_equal(g["hq"], orc.h_q), f"entropy differs {where}"
+        assert np.array_equal(g["counters"], self.cum), f"work counters differ {where}"
         assert np.allclose(g["terms"][:, 0], o.r_entropy, rtol=1e-5, atol=1e-4), f"entropy term {where}"
         assert np.allclose(g["terms"][:, 1], o.logdet, rtol=1e-5, atol=1e-4), f"logdet term {where}"
         assert np.all(np.abs(g["reward"] - o.reward) <= 1e-4 * np.maximum(1.0, np.abs(o.reward))), \

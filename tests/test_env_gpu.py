@@ -104,8 +104,7 @@ def test_edge_cases_collision_nan_masked_reset_episode():
         if t == 30:
             mask = np.zeros(pr.n, np.uint8)
             mask[[1, 3, 7]] = 1
-            pr.orc.reset(pr.b.start, mask)
-            pr.env.reset(pr.world, pr.start, torch.from_numpy(mask).cuda())
+            pr.reset(pr.b.start, mask)
     assert pr.gpu_state()["done"].dtype == np.uint8
 
 
@@ -118,8 +117,7 @@ def test_degenerate_start_poses():
     occ = synth.draw_world(synth.WORKLOADS["small_16x64"], 64, 6, int(pr.b.index[5]))
     j, i = np.argwhere(occ)[100]
     start[5] = [(i + 0.5) * 0.1, (j + 0.5) * 0.1, 1.0]   # inside an occupied cell
-    pr.orc.reset(start)
-    pr.env.reset(pr.world, torch.from_numpy(start).cuda())
+    pr.reset(start)
     for t in range(12):
         o = pr.step()
         pr.compare(o)
