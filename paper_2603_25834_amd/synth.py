@@ -176,3 +176,58 @@ def noise(name: str, seed: int, steps: int, robots=None) -> np.ndarray:
     rng = np.random.default_rng([seed, 3])
     g = rng.standard_normal((steps, w.n_robots, 5), dtype=np.float32)
     return g if robots is None else np.ascontiguousarray(g[:, np.asarray(robots)])
+
+
+# ----------------------------------------------------------------- policy inputs
+
+def policy_param_layout(n_scan: int = 360):
+    """(name, shape) of the actor-critic's flat FP32 parameter vector, in order.
+
+    Interface description shared by the library's binding and the tests: conv1
+    [16,1,3,3]+[16], conv2 [32,16,3,3]+[32], fc1 [256, 8192+n_scan+12]+[256],
+    fc2 [256,256]+[256], mean head [2,256]+[2], value head [1,256]+[1], log std [2]."""
+    k1 = 32 * 16 * 16 + n_scan + 12
+    return [("conv1.w", (16, 1, 3, 3)), ("conv1.b", (16,)), ("conv2.w", (32, 16, 3, 3)), ("conv2.b", (32,)),
+            ("fc1.w", (256, k1)), ("fc1.b", (256,)), ("fc2.w", (256, 256)), ("fc2.b", (256,)),
+            ("mu.w", (2, 256)), ("mu.b", (2,)), ("v.w", (1, 256)), ("v.b", (1,)), ("log_std", (2,))]
+
+
+def init_policy_params(n_scan: int = 360, seed: int = 0) -> np.ndarray:
+    """Seeded fan-in-scaled uniform initialisation, float32 flat vector; log std starts at -0.5."""
+    rng = np.random.default_rng([seed, 10])
+    parts = []
+    for name, shp in policy_param_layout(n_scan):
+        n = int(np.prod(shp))
+        if name == "log_std":
+            parts.append(np.full(n, -0.5, np.float32))
+        elif name.endswith(".b"):
+            parts.append(rng.uniform(-0.05, 0.05, n).astype(np.float32))
+        else:
+            bound = 1.0 / math.sqrt(int(np.prod(shp[1:])))
+            parts.append(rng.uniform(-bound, bound, n).astype(np.float32))
+    return np.concatenate(parts)
+
+
+def policy_batch(n: int, n_scan: int = 360, seed: int = 0):
+    """Synthetic PPO minibatch shaped like rollout data: belief crops (int16 log-odds made of
+    hit/miss counts, clamped), normalised scans, pose/covariance states, actions, old log-probs,
+    advantages and returns."""
+    rng = np.random.default_rng([seed, 11])
+    hits = rng.poisson(0.3, size=(n, 64, 64))
+    misses = rng.poisson(1.5, size=(n, 64, 64)) * (rng.random((n, 64, 64)) < 0.6)
+    crop = np.clip(218 * hits - 102 * misses, -896, 896).astype(np.int16)
+    scan = rng.uniform(0.0, 1.0, size=(n, n_scan)).astype(np.float32)
+    state = np.zeros((n, 12), np.float32)
+    state[:, 0:2] = rng.uniform(0, 1, size=(n, 2))
+    state[:, 2] = rng.uniform(-1, 1, size=n)
+    var = rng.uniform(1e-4, 5e-2, size=(n, 3))
+    cov = np.zeros((n, 3, 3))
+    cov[:, [0, 1, 2], [0, 1, 2]] = var
+    cxy = rng.uniform(-0.5, 0.5, size=n) * np.sqrt(var[:, 0] * var[:, 1])
+    cov[:, 0, 1] = cov[:, 1, 0] = cxy
+    state[:, 3:] = cov.reshape(n, 9)
+    act = np.stack([rng.uniform(0, 0.5, n), rng.uniform(-1, 1, n)], 1).astype(np.float32)
+    old_logp = rng.normal(-1.0, 0.3, size=n).astype(np.float32)
+    adv = rng.normal(0.0, 1.0, size=n).astype(np.float32)
+    ret = rng.normal(0.0, 1.0, size=n).astype(np.float32)
+    return dict(crop=crop, scan=scan, state=state, act=act, old_logp=old_logp, adv=adv, ret=ret)

@@ -1,0 +1,168 @@
+"""Pins of the FP64 policy oracle (CPU only).
+
+Each check compares the oracle with something other than itself: a brute-force
+loop convolution, scipy's normal distribution, closed forms of the clipped
+surrogate, FP64 central finite differences of the loss, a brute-force double
+sum for GAE, and the closed form of Adam's first steps.  Paper passage: PPO
+with GAE, arXiv 2603.25834 Sec. III-F, Eqs. (18)-(20).
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.stats
+import torch
+
+from oracle import policy_ref as PR
+from paper_2603_25834_amd import synth
+
+SMALL = PR.PolicyShape(n_scan=8)
+
+
+def test_layout_matches_the_interface_description():
+    for n_scan in (8, 360, 720):
+        assert PR.PolicyShape(n_scan).param_layout() == synth.policy_param_layout(n_scan)
+    assert PR.PolicyShape(360).n_params() == 2264005
+
+
+def _conv_brute(x, w, b, stride=2, pad=1):
+    B, Ci, H, W = x.shape
+    Co = w.shape[0]
+    Ho, Wo = (H + 2 * pad - 3) // stride + 1, (W + 2 * pad - 3) // stride + 1
+    out = np.zeros((B, Co, Ho, Wo))
+    for bb in range(B):
+        for co in range(Co):
+            for oy in range(Ho):
+                for ox in range(Wo):
+                    acc = b[co]
+                    for ci in range(Ci):
+                        for ky in range(3):
+                            for kx in range(3):
+                                iy, ix = oy * stride + ky - pad, ox * stride + kx - pad
+                                if 0 <= iy < H and 0 <= ix < W:
+                                    acc += w[co, ci, ky, kx] * x[bb, ci, iy, ix]
+                    out[bb, co, oy, ox] = acc
+    return out
+
+
+def test_forward_against_brute_force_loops():
+    theta = torch.from_numpy(synth.init_policy_params(8, seed=1)).double()
+    d = synth.policy_batch(2, n_scan=8, seed=2)
+    mu, log_std, value = PR.forward(theta, torch.from_numpy(d["crop"]), torch.from_numpy(d["scan"]),
+                                    torch.from_numpy(d["state"]), SMALL)
+    p = {k: v.numpy() for k, v in PR.unflatten(theta, SMALL).items()}
+    x = d["crop"].astype(np.float64)[:, None] / 256.0
+    a1 = np.maximum(_conv_brute(x, p["conv1.w"], p["conv1.b"]), 0)
+    a2 = np.maximum(_conv_brute(a1, p["conv2.w"], p["conv2.b"]), 0)
+    feat = np.concatenate([a2.reshape(2, -1), d["scan"], d["state"]], 1)
+    h1 = np.maximum(np.einsum("bk,nk->bn", feat, p["fc1.w"]) + p["fc1.b"], 0)
+    h2 = np.maximum(np.einsum("bk,nk->bn", h1, p["fc2.w"]) + p["fc2.b"], 0)
+    assert np.allclose(mu.numpy(), h2 @ p["mu.w"].T + p["mu.b"], rtol=1e-12, atol=1e-12)
+    assert np.allclose(value.numpy(), (h2 @ p["v.w"].T)[:, 0] + p["v.b"], rtol=1e-12, atol=1e-12)
+    assert a2.shape[1:] == (32, 16, 16)
+
+
+def test_gaussian_logp_and_entropy_against_scipy():
+    rng = np.random.default_rng(0)
+    mu = rng.normal(size=(5, 2))
+    ls = rng.normal(size=2) * 0.3
+    a = rng.normal(size=(5, 2))
+    got = PR.gaussian_logp(torch.from_numpy(mu), torch.from_numpy(ls), torch.from_numpy(a)).numpy()
+    want = scipy.stats.norm.logpdf(a, loc=mu, scale=np.exp(ls)).sum(1)
+    assert np.allclose(got, want, rtol=1e-13)
+    assert float(PR.gaussian_entropy(torch.from_numpy(ls))) == pytest.approx(
+        scipy.stats.norm.entropy(scale=np.exp(ls)).sum(), rel=1e-13)
+
+
+def _batch(n=4, seed=0):
+    d = synth.policy_batch(n, n_scan=8, seed=seed)
+    return {k: torch.from_numpy(v) for k, v in d.items()}
+
+
+def test_clipped_surrogate_special_cases():
+    theta = torch.from_numpy(synth.init_policy_params(8, seed=3)).double()
+    b = _batch(6, 3)
+    mu, log_std, _ = PR.forward(theta, b["crop"], b["scan"], b["state"], SMALL)
+    logp = PR.gaussian_logp(mu, log_std, b["act"].double())
+    # ratio 1: the surrogate is the mean advantage
+    _, terms = PR.ppo_loss(theta, b["crop"], b["scan"], b["state"], b["act"], logp.detach(), b["adv"], b["ret"],
+                           SMALL)
+    assert float(terms[0]) == pytest.approx(-float(b["adv"].double().mean()), rel=1e-12)
+    # ratio e: positive advantages are clipped at 1 + eps, negative ones keep the ratio
+    adv = torch.tensor([1.0, 2.0, -1.0, -3.0, 0.5, -0.5])
+    _, terms = PR.ppo_loss(theta, b["crop"], b["scan"], b["state"], b["act"], logp.detach() - 1.0, adv, b["ret"],
+                           SMALL)
+    want = -np.mean([1.2 * a if a > 0 else math.e * a for a in adv.tolist()])
+    assert float(terms[0]) == pytest.approx(want, rel=1e-12)
+
+
+def test_loss_gradient_against_central_differences():
+    theta = torch.from_numpy(synth.init_policy_params(8, seed=4)).double()
+    b = _batch(3, 4)
+    mu, log_std, _ = PR.forward(theta, b["crop"], b["scan"], b["state"], SMALL)
+    old = PR.gaussian_logp(mu, log_std, b["act"].double()).detach() + torch.tensor([0.05, -0.1, 0.02])
+    th = theta.clone().requires_grad_(True)
+    loss, _ = PR.ppo_loss(th, b["crop"], b["scan"], b["state"], b["act"], old, b["adv"], b["ret"], SMALL)
+    (g,) = torch.autograd.grad(loss, th)
+    rng = np.random.default_rng(0)
+    idx = list(range(0, 16 + 144 + 32, 7)) + list(rng.integers(0, theta.numel(), 40)) + \
+        list(range(theta.numel() - 2 - 1 - 256 - 2 - 512, theta.numel()))
+    for i in idx:
+        h = 1e-6 * max(1.0, abs(float(theta[i])))
+        tp, tm = theta.clone(), theta.clone()
+        tp[i] += h
+        tm[i] -= h
+        lp, _ = PR.ppo_loss(tp, b["crop"], b["scan"], b["state"], b["act"], old, b["adv"], b["ret"], SMALL)
+        lm, _ = PR.ppo_loss(tm, b["crop"], b["scan"], b["state"], b["act"], old, b["adv"], b["ret"], SMALL)
+        fd = float(lp - lm) / (2 * h)
+        assert abs(fd - float(g[i])) <= 1e-6 * max(1.0, abs(fd)), (i, fd, float(g[i]))
+
+
+def test_gae_special_cases_and_brute_force():
+    rng = np.random.default_rng(1)
+    T, N = 7, 5
+    r = torch.from_numpy(rng.normal(size=(T, N)))
+    v = torch.from_numpy(rng.normal(size=(T, N)))
+    last = torch.from_numpy(rng.normal(size=N))
+    d = torch.from_numpy((rng.random((T, N)) < 0.2).astype(np.float64))
+    # gamma = 0: advantage = r - V
+    adv, ret = PR.gae(r, v, d, last, gamma=0.0, lam=0.95)
+    assert torch.allclose(adv, r - v)
+    # brute force: A_t = sum_{l} (g l)^l delta_{t+l}, cut after the first done at or after t
+    g, lam = 0.97, 0.9
+    adv, ret = PR.gae(r, v, d, last, gamma=g, lam=lam)
+    vn = torch.cat([v[1:], last[None]], 0)
+    delta = r + g * vn * (1 - d) - v
+    want = torch.zeros_like(r)
+    for n in range(N):
+        for t in range(T):
+            acc, w = 0.0, 1.0
+            for u in range(t, T):
+                acc += w * float(delta[u, n])
+                if d[u, n] > 0:
+                    break
+                w *= g * lam
+            want[t, n] = acc
+    assert torch.allclose(adv, want, rtol=1e-12, atol=1e-12)
+    assert torch.allclose(ret, adv + v)
+    # lambda = 1 without dones: advantage = discounted return (bootstrapped) - V
+    adv1, _ = PR.gae(r, v, torch.zeros_like(d), last, gamma=g, lam=1.0)
+    disc = torch.zeros_like(r)
+    for t in range(T):
+        acc = sum(g ** (u - t) * r[u] for u in range(t, T)) + g ** (T - t) * last
+        disc[t] = acc
+    assert torch.allclose(adv1, disc - v, rtol=1e-12, atol=1e-12)
+
+
+def test_adam_first_steps_closed_form():
+    rng = np.random.default_rng(2)
+    th = torch.from_numpy(rng.normal(size=50))
+    g = torch.from_numpy(rng.normal(size=50))
+    m = torch.zeros(50, dtype=torch.float64)
+    v = torch.zeros(50, dtype=torch.float64)
+    lr, eps = 1e-3, 1e-8
+    t1, m, v = PR.adam_step(th, g, m, v, 1, lr=lr, eps=eps)
+    assert torch.allclose(t1, th - lr * g / (g.abs() + eps), rtol=1e-14, atol=1e-15)
+    # a constant gradient keeps the bias-corrected moments at (g, g^2)
+    t2, m, v = PR.adam_step(t1, g, m, v, 2, lr=lr, eps=eps)
+    assert torch.allclose(t2, t1 - lr * g / (g.abs() + eps), rtol=1e-12, atol=1e-14)
