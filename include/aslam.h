@@ -156,6 +156,66 @@ int aslam_env_graph_build(aslam_env* env, int32_t k_steps, const float* actions_
                           float* reward_dev, int64_t w_stride, uint8_t* done_dev, int64_t d_stride);
 int aslam_env_graph_launch(aslam_env* env, aslam_stream_t stream);
 
+/* --------------------------------------------------------------- policy */
+
+/* PPO actor-critic (Sec. III-F; Eqs. 18-20) with the workload's network:
+ * conv 1->16 and 16->32 (3x3, stride 2, padding 1, ReLU) on the 64x64 belief
+ * crop (input L/256), the 8192 features (channel-major, as c*256 + y*16 + x)
+ * concatenated with scan[R] and state[12], FC 256 + ReLU, FC 256 + ReLU, mean
+ * head (2), value head (1), state-independent log std (2).
+ *
+ * Parameters and gradients are FP32 flat vectors, in this order (row-major
+ * tensors): conv1.w [16,1,3,3], conv1.b [16], conv2.w [32,16,3,3], conv2.b
+ * [32], fc1.w [256, 8192+R+12], fc1.b [256], fc2.w [256,256], fc2.b [256],
+ * mu.w [2,256], mu.b [2], v.w [1,256], v.b [1], log_std [2].
+ * GEMM operands are rounded to BF16 and accumulated in FP32 (MFMA);
+ * activations between layers are BF16; heads, loss and reductions are FP32. */
+typedef struct aslam_policy aslam_policy;
+
+typedef struct {
+  int32_t n_scan;     /* R, scan length */
+  int32_t max_batch;  /* largest batch passed to forward / backward (sizes the workspaces) */
+  float clip_eps;     /* PPO clip epsilon (Eq. 19) */
+  float c_value;      /* value-loss weight */
+  float c_entropy;    /* entropy-bonus weight */
+} aslam_policy_config;
+
+/* Number of parameters for scan length n_scan (2,264,005 for R = 360). */
+int64_t aslam_policy_num_params(int32_t n_scan);
+/* Allocates the minibatch workspaces (about 100 KB per sample of max_batch). */
+int aslam_policy_create(const aslam_policy_config* cfg, aslam_policy** out);
+int aslam_policy_destroy(aslam_policy* pol);
+
+/* Forward pass: crop_dev int16 [B,64,64], scan_dev float [B,R], state_dev
+ * float [B,12] -> mu_dev float [B,2], value_dev float [B].  The log std is
+ * params[last 2].  1 <= B <= max_batch. */
+int aslam_policy_forward(aslam_policy* pol, const float* params_dev, const int16_t* crop_dev, const float* scan_dev,
+                         const float* state_dev, int32_t batch, float* mu_dev, float* value_dev,
+                         aslam_stream_t stream);
+
+/* PPO loss and its gradient over one minibatch, recomputing the forward
+ * activations (only the inputs are stored across the rollout).
+ *   loss = L_clip + c_value * mean((V - ret)^2) - c_entropy * H[pi],
+ *   L_clip = -mean(min(r A, clip(r, 1-eps, 1+eps) A)), r = exp(logp - old_logp).
+ * act_dev [B,2], old_logp_dev/adv_dev/ret_dev [B].  grads_dev [P] is ADDED
+ * to (accumulate over minibatches; zero it first).  loss_dev float [4] out:
+ * total, L_clip, mean((V-ret)^2), entropy. */
+int aslam_policy_backward(aslam_policy* pol, const float* params_dev, const int16_t* crop_dev,
+                          const float* scan_dev, const float* state_dev, int32_t batch, const float* act_dev,
+                          const float* old_logp_dev, const float* adv_dev, const float* ret_dev, float* grads_dev,
+                          float* loss_dev, aslam_stream_t stream);
+
+/* Generalized Advantage Estimation (Sec. III-F) over a [T,N] rollout (time-major):
+ *   delta_t = r_t + gamma V_{t+1} (1 - d_t) - V_t,  A_t = delta_t + gamma lam (1 - d_t) A_{t+1},
+ * V_T = last_value_dev [N].  Writes adv_dev and ret_dev = adv + values, [T,N] float. */
+int aslam_gae(const float* rewards_dev, const float* values_dev, const uint8_t* dones_dev,
+              const float* last_value_dev, int32_t T, int32_t N, float gamma, float lam, float* adv_dev,
+              float* ret_dev, aslam_stream_t stream);
+
+/* One Adam step (bias-corrected, step >= 1) on n FP32 parameters, in place. */
+int aslam_adam(float* params_dev, const float* grads_dev, float* m_dev, float* v_dev, int64_t n, int32_t step,
+               float lr, float beta1, float beta2, float eps, aslam_stream_t stream);
+
 /* ------------------------------------------------------------------ misc */
 
 const char* aslam_last_error(void);

@@ -138,3 +138,89 @@ def adam_step(theta, grad, m, v, step, lr=3e-4, beta1=0.9, beta2=0.999, eps=1e-8
     vhat = v / (1.0 - beta2 ** step)
     th = th - lr * mhat / (torch.sqrt(vhat) + eps)
     return th, m, v
+
+
+# ------------------------------------------------------- workload precision
+# The workload runs the network with BF16 operands and FP32 accumulation.  The
+# functions below evaluate the same network in FP64 with BF16 rounding (round
+# to nearest even) applied exactly where the workload stores or feeds BF16
+# values: GEMM / convolution weights, the crop and FC1's scan/state inputs, the
+# ReLU outputs between layers, and the gradients that the backward pass feeds
+# to the next GEMM (the gradient at each hidden ReLU output).  Everything else
+# (accumulation, biases, heads, loss) stays FP64.
+
+def round_bf16(x: torch.Tensor) -> torch.Tensor:
+    return x.to(torch.bfloat16).to(torch.float64)
+
+
+class _RoundValue(torch.autograd.Function):
+    """Rounds the value; the gradient passes through unchanged."""
+
+    @staticmethod
+    def forward(ctx, x):
+        return round_bf16(x)
+
+    @staticmethod
+    def backward(ctx, g):
+        return g
+
+
+class _RoundGrad(torch.autograd.Function):
+    """Leaves the value; rounds the incoming gradient."""
+
+    @staticmethod
+    def forward(ctx, x):
+        return x.clone()
+
+    @staticmethod
+    def backward(ctx, g):
+        return round_bf16(g)
+
+
+class _RoundBoth(torch.autograd.Function):
+    """Rounds the value and the incoming gradient."""
+
+    @staticmethod
+    def forward(ctx, x):
+        return round_bf16(x)
+
+    @staticmethod
+    def backward(ctx, g):
+        return round_bf16(g)
+
+
+def forward_bf16(theta: torch.Tensor, crop: torch.Tensor, scan: torch.Tensor, state: torch.Tensor,
+                 shape: PolicyShape, rounding: bool = True):
+    """forward() at the workload's precision (see above); rounding=False gives forward() exactly."""
+    rv = _RoundValue.apply if rounding else (lambda t: t)
+    rg = _RoundGrad.apply if rounding else (lambda t: t)
+    rb = _RoundBoth.apply if rounding else (lambda t: t)
+    p = unflatten(theta, shape)
+    x = crop.to(torch.float64).unsqueeze(1) / 256.0
+    x = round_bf16(x) if rounding else x
+    a1 = rb(torch.relu(torch.nn.functional.conv2d(x, rv(p["conv1.w"]), p["conv1.b"], stride=2, padding=1)))
+    a2 = rb(torch.relu(torch.nn.functional.conv2d(a1, rv(p["conv2.w"]), p["conv2.b"], stride=2, padding=1)))
+    sc, st = scan.to(torch.float64), state.to(torch.float64)
+    if rounding:
+        sc, st = round_bf16(sc), round_bf16(st)
+    feat = torch.cat([a2.flatten(1), sc, st], dim=1)
+    h1 = rb(torch.relu(feat @ rv(p["fc1.w"]).T + p["fc1.b"]))
+    h2 = rg(torch.relu(h1 @ rv(p["fc2.w"]).T + p["fc2.b"]))
+    mu = h2 @ p["mu.w"].T + p["mu.b"]
+    value = (h2 @ p["v.w"].T + p["v.b"]).squeeze(1)
+    return mu, p["log_std"], value
+
+
+def ppo_loss_bf16(theta, crop, scan, state, act, old_logp, adv, ret, shape, eps=0.2, c_v=0.5, c_e=0.005,
+                  rounding: bool = True):
+    """ppo_loss() on forward_bf16(); its autograd gradient is the workload-precision gradient."""
+    mu, log_std, value = forward_bf16(theta, crop, scan, state, shape, rounding)
+    logp = gaussian_logp(mu, log_std, act.to(torch.float64))
+    ratio = torch.exp(logp - old_logp.to(torch.float64))
+    adv = adv.to(torch.float64)
+    surr = torch.minimum(ratio * adv, torch.clamp(ratio, 1.0 - eps, 1.0 + eps) * adv)
+    l_clip = -surr.mean()
+    l_v = ((value - ret.to(torch.float64)) ** 2).mean()
+    ent = gaussian_entropy(log_std)
+    total = l_clip + c_v * l_v - c_e * ent
+    return total, torch.stack([l_clip, l_v, ent])

@@ -65,6 +65,14 @@ SIGNATURES = {
     "aslam_env_read": (ctypes.c_int, [_P, _I32, _P, _P]),
     "aslam_env_graph_build": (ctypes.c_int, [_P, _I32, _P, _I64, _P, _I64, _P, _I64, _P, _I64, _P, _I64]),
     "aslam_env_graph_launch": (ctypes.c_int, [_P, _P]),
+    "aslam_policy_num_params": (_I64, [_I32]),
+    "aslam_policy_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_P)]),
+    "aslam_policy_destroy": (ctypes.c_int, [_P]),
+    "aslam_policy_forward": (ctypes.c_int, [_P, _P, _P, _P, _P, _I32, _P, _P, _P]),
+    "aslam_policy_backward": (ctypes.c_int, [_P, _P, _P, _P, _P, _I32, _P, _P, _P, _P, _P, _P, _P]),
+    "aslam_gae": (ctypes.c_int, [_P, _P, _P, _P, _I32, _I32, ctypes.c_float, ctypes.c_float, _P, _P, _P]),
+    "aslam_adam": (ctypes.c_int, [_P, _P, _P, _P, _I64, _I32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                  ctypes.c_float, _P]),
 }
 
 _lib = None
@@ -89,3 +97,8 @@ def check(rc: int) -> None:
     if rc != ASL_OK:
         msg = lib().aslam_last_error()
         raise AslamError(rc, msg.decode() if msg else "")
+
+
+class PolicyConfig(ctypes.Structure):
+    _fields_ = [("n_scan", ctypes.c_int32), ("max_batch", ctypes.c_int32), ("clip_eps", ctypes.c_float),
+                ("c_value", ctypes.c_float), ("c_entropy", ctypes.c_float)]

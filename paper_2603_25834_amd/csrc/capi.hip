@@ -42,6 +42,10 @@ int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 
 }  // namespace
 
+namespace aslam {
+void set_last_error(const std::string& msg) { g_err = msg; }
+}  // namespace aslam
+
 struct aslam_env {
   aslam_env_config cfg{};
   aslam_exec_config ex{};
@@ -72,6 +76,7 @@ struct aslam_env {
   void* d_flags = nullptr;
   void* d_terms = nullptr;
   void* d_counters = nullptr;
+  void* d_raylen = nullptr;
   void* d_dirtab = nullptr;
   void* d_hq_lut = nullptr;
   // captured step sequence
@@ -85,7 +90,7 @@ namespace {
 void free_env(aslam_env* e) {
   void** ptrs[] = {&e->d_meta, &e->d_order, &e->d_world, &e->d_belief, &e->d_pose, &e->d_est, &e->d_cov,
                    &e->d_hq_total, &e->d_step, &e->d_last_lc, &e->d_visit_t, &e->d_visit_xy, &e->d_rho,
-                   &e->d_hitc, &e->d_flags, &e->d_terms, &e->d_counters, &e->d_dirtab, &e->d_hq_lut};
+                   &e->d_hitc, &e->d_flags, &e->d_terms, &e->d_counters, &e->d_raylen, &e->d_dirtab, &e->d_hq_lut};
   for (void** p : ptrs) {
     if (*p) (void)hipFree(*p);
     *p = nullptr;
@@ -140,7 +145,9 @@ int plan_lds(aslam_env* e, const aslam_exec_config& ex, LdsPlan& L) {
   const int32_t rhat_cells = e->P.rhat_cells;
   L.off_lut = 0;
   L.off_rho = (int32_t)align_up((2 * lc + 1) * 4, 16);
-  L.off_misc = L.off_rho + (int32_t)align_up(e->cfg.n_rays * 4, 16);
+  L.off_perm = L.off_rho + (int32_t)align_up(e->cfg.n_rays * 4, 16);
+  L.off_hist = L.off_perm + (int32_t)align_up(e->cfg.n_rays * 4, 16);
+  L.off_misc = L.off_hist + 256;
   L.off_union = L.off_misc + 256;
   L.world_halo = rhat_cells + 3;
   int64_t world_max = 0, nw_max = 0, rows_max = 0;
@@ -158,10 +165,12 @@ int plan_lds(aslam_env* e, const aslam_exec_config& ex, LdsPlan& L) {
     return fail(ASL_ENOTIMPL, "world window of the largest grid does not fit the LDS budget");
   int64_t band = ex.band_rows > 0 ? ex.band_rows : free_bytes / (8 * nw_max);
   band = std::min<int64_t>(band, rows_max);
-  if (band < 8 || 8 * band * nw_max > free_bytes)
+  // bitmaps: 2 x band x nw words, cleared with 16-byte stores (+16 B slack)
+  if (band > 8 && 8 * band * nw_max + 16 > free_bytes) band = (free_bytes - 16) / (8 * nw_max);
+  if (band < 8 || 8 * band * nw_max + 16 > free_bytes)
     return fail(ASL_EINVAL, "band_rows does not fit the LDS budget (need >= 8 rows)");
   L.band_rows = (int32_t)band;
-  L.union_bytes = (int32_t)std::max<int64_t>(world_max, 8 * band * nw_max);
+  L.union_bytes = (int32_t)std::max<int64_t>(world_max, 8 * band * nw_max + 16);
   L.total = L.off_union + L.union_bytes;
   L.record = ex.record_rays;
   return ASL_OK;
@@ -249,6 +258,7 @@ int aslam_env_create(const aslam_env_config* cfg, int32_t n_robots, const int32_
       {&e->d_flags, 2 * (size_t)n_robots},
       {&e->d_terms, sizeof(float) * 2 * (size_t)n_robots},
       {&e->d_counters, sizeof(int64_t) * 3 * (size_t)n_robots},
+      {&e->d_raylen, sizeof(int16_t) * (size_t)(R * n_robots)},
       {&e->d_dirtab, sizeof(int32_t) * (size_t)kNang},
       {&e->d_hq_lut, sizeof(uint32_t) * (size_t)(2 * quantise_logodds(cfg->l_clamp) + 1)},
   };
@@ -329,6 +339,7 @@ int aslam_env_create(const aslam_env_config* cfg, int32_t n_robots, const int32_
   P.flags = (uint8_t*)e->d_flags;
   P.terms = (float*)e->d_terms;
   P.counters = (int64_t*)e->d_counters;
+  P.raylen = (int16_t*)e->d_raylen;
   P.dirtab = (const int32_t*)e->d_dirtab;
   P.hq_lut = (const uint32_t*)e->d_hq_lut;
 

@@ -61,6 +61,7 @@ struct EnvParams {
   uint8_t* flags;        // [n,2] collided, closed
   float* terms;          // [n,2] entropy decrease, ln det
   int64_t* counters;     // [n,3] cumulative: coded cells, march visits, update visits
+  int16_t* raylen;       // [n,R] steps of each ray's last LiDAR walk (lane-order key)
   const int32_t* dirtab; // [kNang] (cos & 0xffff) | (sin << 16), Q14
   const uint32_t* hq_lut;// [2*lclamp+1] binary entropy, 2^-32 nat
 };
@@ -75,7 +76,7 @@ struct StepArgs {
 
 // LDS plan of the per-robot kernels (byte offsets into dynamic LDS).
 struct LdsPlan {
-  int32_t off_lut, off_rho, off_misc, off_union;
+  int32_t off_lut, off_rho, off_perm, off_hist, off_misc, off_union;
   int32_t total;
   int32_t union_bytes;
   int32_t band_rows;      // code-window rows per pass

@@ -215,12 +215,33 @@ struct RobotShared {
   int32_t tox, toy, ib_t;
   int32_t eox, eoy, ib_e;
   int32_t collided;
-  int32_t rho_max;
   int32_t cnt_march, cnt_upd;
-  int32_t pad[5];
+  int32_t bx0, bx1, by0, by1;   // cell bounding box of the ray end points (estimated pose)
+  int32_t pad[2];
   long long part[16];
   int32_t dpart[16];
 };
+
+// Pointers into the dynamic LDS of a per-robot kernel.
+struct LdsView {
+  uint32_t* lut;     // binary entropy table
+  int32_t* rho;      // [R] range (Q16) | bit 31 = hit
+  int32_t* perm;     // [R] ray of each lane slot, longest walk first
+  int32_t* hist;     // [64] sort buckets
+  RobotShared* sh;
+  uint32_t* uni;     // world rows, then the code bitmaps
+};
+
+__device__ __forceinline__ LdsView lds_view(unsigned char* smem, const LdsPlan& L) {
+  LdsView v;
+  v.lut = reinterpret_cast<uint32_t*>(smem + L.off_lut);
+  v.rho = reinterpret_cast<int32_t*>(smem + L.off_rho);
+  v.perm = reinterpret_cast<int32_t*>(smem + L.off_perm);
+  v.hist = reinterpret_cast<int32_t*>(smem + L.off_hist);
+  v.sh = reinterpret_cast<RobotShared*>(smem + L.off_misc);
+  v.uni = reinterpret_cast<uint32_t*>(smem + L.off_union);
+  return v;
+}
 
 // ---------------------------------------------------------------- DDA setup
 // Ray from Q16 origin o with table direction (a,b) (Q14), limit lim (Q16 cells).
@@ -303,6 +324,86 @@ __device__ __forceinline__ int32_t wave_max_i32(int32_t v) {
   return v;
 }
 
+__device__ __forceinline__ int32_t wave_min_i32(int32_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+__device__ __forceinline__ int32_t ray_dir(const EnvParams& P, int32_t ib, int32_t k) {
+  int32_t id = ib + k * P.step_ang;
+  id -= (id >= kNang) ? kNang : 0;
+  return P.dirtab[id];
+}
+
+// Counting sort of the R rays by a bucket key in [0, 63] (larger = longer
+// walk), longest first: perm[j] is the ray walked by lane slot j.  Lanes of a
+// wave then walk rays of similar length, so a wave's trip count (its longest
+// walk) stays close to its lanes' own.  Results do not depend on the order.
+template <int NT, typename KeyFn>
+__device__ void sort_rays(int32_t R, int32_t* perm, int32_t* hist, KeyFn key_of) {
+  constexpr int kMaxPer = 8;
+  const int32_t tid = threadIdx.x;
+  if (R > kMaxPer * NT) {
+    for (int32_t k = tid; k < R; k += NT) perm[k] = k;
+    __syncthreads();
+    return;
+  }
+  for (int32_t b = tid; b < 64; b += NT) hist[b] = 0;
+  __syncthreads();
+  int32_t key[kMaxPer], pos[kMaxPer];
+#pragma unroll
+  for (int i = 0; i < kMaxPer; ++i) {
+    const int32_t k = tid + i * NT;
+    if (k < R) {
+      key[i] = 63 - min(max(key_of(k), 0), 63);
+      pos[i] = atomicAdd(&hist[key[i]], 1);
+    }
+  }
+  __syncthreads();
+  if (tid < 64) {
+    const int32_t v = hist[tid];
+    int32_t x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int32_t y = __shfl_up(x, o, 64);
+      if (tid >= o) x += y;
+    }
+    hist[tid] = x - v;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < kMaxPer; ++i) {
+    const int32_t k = tid + i * NT;
+    if (k < R) perm[hist[key[i]] + pos[i]] = k;
+  }
+  __syncthreads();
+}
+
+// Cell bounding box of the end points of all rays walked from the Q16 origin
+// (eox, eoy) with the ranges in rho (Q16).  Every cell a walk visits lies
+// within one cell of its segment, so the box grown by 2 cells holds them all.
+template <int NT>
+__device__ void endpoint_bbox(const EnvParams& P, const int32_t* rho, int32_t eox, int32_t eoy, int32_t ib,
+                              RobotShared* sh) {
+  int32_t mnx = eox >> 16, mxx = mnx, mny = eoy >> 16, mxy = mny;
+  for (int32_t k = threadIdx.x; k < P.R; k += NT) {
+    const int32_t lim = rho[k] & 0x7fffffff;
+    const int32_t dv = ray_dir(P, ib, k);
+    const int32_t a = (int16_t)(dv & 0xffff), b = dv >> 16;
+    const int32_t qx = (int32_t)(((int64_t)eox + (((int64_t)lim * a) >> 14)) >> 16);
+    const int32_t qy = (int32_t)(((int64_t)eoy + (((int64_t)lim * b) >> 14)) >> 16);
+    mnx = min(mnx, qx); mxx = max(mxx, qx);
+    mny = min(mny, qy); mxy = max(mxy, qy);
+  }
+  mnx = wave_min_i32(mnx); mxx = wave_max_i32(mxx);
+  mny = wave_min_i32(mny); mxy = wave_max_i32(mxy);
+  if ((threadIdx.x & 63) == 0) {
+    atomicMin(&sh->bx0, mnx); atomicMax(&sh->bx1, mxx);
+    atomicMin(&sh->by0, mny); atomicMax(&sh->by1, mxy);
+  }
+}
+
 // ---------------------------------------------------------------- stages
 template <int NT>
 __device__ void stage_world(const EnvParams& P, const RobotMeta& m, int32_t cy, int32_t halo, uint32_t* sw,
@@ -333,15 +434,21 @@ __device__ void stage_world(const EnvParams& P, const RobotMeta& m, int32_t cy, 
 
 // LiDAR march of every ray of the robot from the true pose (lanes = rays).
 template <int NT>
-__device__ void march_rays(const EnvParams& P, const RobotMeta& m, RobotShared* sh, const uint32_t* sw,
-                           int32_t wy0, int32_t* rho_lds, float* ranges_out, bool record, int32_t r) {
+__device__ void march_rays(const EnvParams& P, const RobotMeta& m, const LdsView& V, const uint32_t* sw,
+                           int32_t wy0, float* ranges_out, bool record, int32_t r) {
+  RobotShared* sh = V.sh;
+  int32_t* rho_lds = V.rho;
   const int32_t s = m.side;
   const int32_t tox = sh->tox, toy = sh->toy, ib = sh->ib_t;
   const int32_t cx0 = tox >> 16, cy0 = toy >> 16;
   const bool inside = cx0 >= 0 && cx0 < s && cy0 >= 0 && cy0 < s;
+  int16_t* raylen = P.raylen + (int64_t)r * P.R;
+  // lane slots ordered by the previous step's walk length of each ray
+  sort_rays<NT>(P.R, V.perm, V.hist, [&](int32_t k) { return (int32_t)raylen[k] >> 2; });
   int32_t visits = 0;
   for (int32_t k0 = 0; k0 < P.R; k0 += NT) {
-    const int32_t k = k0 + (int32_t)threadIdx.x;
+    const int32_t j = k0 + (int32_t)threadIdx.x;
+    const int32_t k = j < P.R ? V.perm[j] : P.R;
     const bool active = inside && k < P.R;
     int32_t rq = P.rhat_q;
     int32_t cell = -1;
@@ -374,6 +481,7 @@ __device__ void march_rays(const EnvParams& P, const RobotMeta& m, RobotShared* 
     }
     if (active) {
       visits += i + 1;
+      raylen[k] = (int16_t)min(i, 32767);
       if (hit) {
         cell = li + wy0 * s;
         if (i > 0) {
@@ -403,6 +511,7 @@ __device__ void march_rays(const EnvParams& P, const RobotMeta& m, RobotShared* 
   }
   visits = wave_sum_i32(visits);
   if ((threadIdx.x & 63) == 0 && visits) atomicAdd(&sh->cnt_march, visits);
+  __syncthreads();
 }
 
 __device__ __forceinline__ long long wave_sum_i64(long long v) {
@@ -478,10 +587,12 @@ __device__ __forceinline__ void apply_band(const EnvParams& P, const uint32_t* m
 // Map update from the estimated pose with the measured ranges, then the
 // reward.  rho_lds[k]: range (Q16) with bit 31 set when ray k hit.
 template <int NT>
-__device__ void update_and_reward(const EnvParams& P, const StepArgs& A, const RobotMeta& m, RobotShared* sh,
-                                  const int32_t* rho_lds, uint32_t* uni, const uint32_t* lut, const LdsPlan& L,
-                                  int32_t r) {
+__device__ void update_and_reward(const EnvParams& P, const StepArgs& A, const RobotMeta& m, const LdsView& V,
+                                  const LdsPlan& L, int32_t r) {
   constexpr int NWAVE = NT / 64;
+  RobotShared* sh = V.sh;
+  const int32_t* rho_lds = V.rho;
+  uint32_t* uni = V.uni;
   const int32_t s = m.side;
   const int32_t eox = sh->eox, eoy = sh->eoy, ib = sh->ib_e;
   const int32_t ecx = eox >> 16, ecy = eoy >> 16;
@@ -489,9 +600,9 @@ __device__ void update_and_reward(const EnvParams& P, const StepArgs& A, const R
   long long dh = 0;
   int32_t ncoded = 0, uvisits = 0;
   if (inside) {
-    const int32_t hu = (sh->rho_max >> 16) + 3;
-    const int32_t x0 = max(0, ecx - hu), x1 = min(s - 1, ecx + hu);
-    const int32_t y0 = max(0, ecy - hu), y1 = min(s - 1, ecy + hu);
+    // code window: end-point box grown by 2 cells, clipped to the grid
+    const int32_t x0 = max(0, sh->bx0 - 2), x1 = min(s - 1, sh->bx1 + 2);
+    const int32_t y0 = max(0, sh->by0 - 2), y1 = min(s - 1, sh->by1 + 2);
     const int32_t x0w = x0 & ~31;
     const int32_t nw = (x1 >> 5) - (x0 >> 5) + 1;
     const int32_t rowbits = nw << 5;
@@ -499,24 +610,33 @@ __device__ void update_and_reward(const EnvParams& P, const StepArgs& A, const R
     uint32_t* miss = uni;
     uint32_t* hitm = uni + band * nw;
     const int64_t base = m.cell_off;
+    // lane slots ordered by the walk length estimated from the range
+    sort_rays<NT>(P.R, V.perm, V.hist, [&](int32_t k) {
+      const int32_t dv = ray_dir(P, ib, k);
+      const int32_t ab = abs((int32_t)(int16_t)(dv & 0xffff)) + abs(dv >> 16);
+      return (int32_t)((((int64_t)(rho_lds[k] & 0x7fffffff) >> 16) * ab) >> 16);
+    });
     for (int32_t by0 = y0; by0 <= y1; by0 += band) {
       const int32_t rows = min(band, y1 - by0 + 1);
       const uint32_t band_bits = (uint32_t)(rows * rowbits);
-      for (int32_t k = threadIdx.x; k < 2 * band * nw; k += NT) uni[k] = 0u;
+      {
+        uint4* u4 = reinterpret_cast<uint4*>(uni);
+        const int32_t nclr = (2 * band * nw + 3) >> 2;
+        for (int32_t k = threadIdx.x; k < nclr; k += NT) u4[k] = make_uint4(0u, 0u, 0u, 0u);
+      }
       __syncthreads();
       // mark: one lane per ray
       for (int32_t k0 = 0; k0 < P.R; k0 += NT) {
-        const int32_t k = k0 + (int32_t)threadIdx.x;
-        const bool valid = k < P.R;
+        const int32_t j = k0 + (int32_t)threadIdx.x;
+        const bool valid = j < P.R;
+        const int32_t k = valid ? V.perm[j] : 0;
         RaySetup q{};
         int32_t wi = 0, sx = 0, sy = 0, D = 0, n = -1;
         bool hit = false;
         if (valid) {
           const int32_t pk = rho_lds[k];
           hit = pk < 0;
-          int32_t id = ib + k * P.step_ang;
-          id -= (id >= kNang) ? kNang : 0;
-          const int32_t dv = P.dirtab[id];
+          const int32_t dv = ray_dir(P, ib, k);
           const int32_t a = (int16_t)(dv & 0xffff), b = dv >> 16;
           q = ray_setup(eox, eoy, a, b, pk & 0x7fffffff, s);
           wi = (ecy - by0) * rowbits + (ecx - x0w);
@@ -543,7 +663,7 @@ __device__ void update_and_reward(const EnvParams& P, const StepArgs& A, const R
       }
       __syncthreads();
       // apply: each coded cell once (8 cells = one 16-byte access per octet)
-      apply_band<NT>(P, miss, hitm, rows, nw, P.belief + base + (int64_t)by0 * s + x0w, s, lut, dh, ncoded);
+      apply_band<NT>(P, miss, hitm, rows, nw, P.belief + base + (int64_t)by0 * s + x0w, s, V.lut, dh, ncoded);
       __syncthreads();
     }
   }
@@ -595,9 +715,8 @@ __global__ void k_motion(EnvParams P, StepArgs A) {
 template <int NT>
 __global__ __launch_bounds__(NT) void k_march(EnvParams P, StepArgs A, LdsPlan L) {
   extern __shared__ __align__(16) unsigned char smem[];
-  int32_t* rho_lds = reinterpret_cast<int32_t*>(smem + L.off_rho);
-  RobotShared* sh = reinterpret_cast<RobotShared*>(smem + L.off_misc);
-  uint32_t* uni = reinterpret_cast<uint32_t*>(smem + L.off_union);
+  const LdsView V = lds_view(smem, L);
+  RobotShared* sh = V.sh;
   const int32_t r = blockIdx.x;
   const RobotMeta m = P.meta[r];
   if (threadIdx.x == 0) {
@@ -609,53 +728,53 @@ __global__ __launch_bounds__(NT) void k_march(EnvParams P, StepArgs A, LdsPlan L
   }
   __syncthreads();
   int32_t wy0;
-  stage_world<NT>(P, m, sh->toy >> 16, L.world_halo, uni, wy0);
+  stage_world<NT>(P, m, sh->toy >> 16, L.world_halo, V.uni, wy0);
   __syncthreads();
-  march_rays<NT>(P, m, sh, uni, wy0, rho_lds, A.ranges, true, r);
-  __syncthreads();
+  march_rays<NT>(P, m, V, V.uni, wy0, A.ranges, true, r);
   if (threadIdx.x == 0) P.counters[3 * (int64_t)r + 1] += sh->cnt_march;
+}
+
+__device__ __forceinline__ void init_bbox(RobotShared* sh) {
+  sh->bx0 = 0x7fffffff; sh->bx1 = -0x7fffffff;
+  sh->by0 = 0x7fffffff; sh->by1 = -0x7fffffff;
 }
 
 template <int NT>
 __global__ __launch_bounds__(NT) void k_update(EnvParams P, StepArgs A, LdsPlan L) {
   extern __shared__ __align__(16) unsigned char smem[];
-  uint32_t* lut = reinterpret_cast<uint32_t*>(smem + L.off_lut);
-  int32_t* rho_lds = reinterpret_cast<int32_t*>(smem + L.off_rho);
-  RobotShared* sh = reinterpret_cast<RobotShared*>(smem + L.off_misc);
-  uint32_t* uni = reinterpret_cast<uint32_t*>(smem + L.off_union);
+  const LdsView V = lds_view(smem, L);
+  RobotShared* sh = V.sh;
   const int32_t r = blockIdx.x;
   const RobotMeta m = P.meta[r];
-  for (int32_t i = threadIdx.x; i < 2 * P.lclamp + 1; i += NT) lut[i] = P.hq_lut[i];
+  for (int32_t i = threadIdx.x; i < 2 * P.lclamp + 1; i += NT) V.lut[i] = P.hq_lut[i];
   if (threadIdx.x == 0) {
     const float* e = P.est + 3 * (int64_t)r;
     sh->eox = to_q16(e[0], P.inv_c16);
     sh->eoy = to_q16(e[1], P.inv_c16);
     sh->ib_e = heading_index(e[2], P.k_ang);
     sh->collided = P.flags[2 * (int64_t)r];
-    sh->rho_max = 0;
     sh->cnt_march = 0;
     sh->cnt_upd = 0;
+    init_bbox(sh);
   }
-  __syncthreads();
   for (int32_t k = threadIdx.x; k < P.R; k += NT) {
     const int32_t rq = P.rho[(int64_t)r * P.R + k];
     const int32_t hc = P.hitc[(int64_t)r * P.R + k];
-    rho_lds[k] = rq | (hc >= 0 ? (int32_t)0x80000000 : 0);
-    atomicMax(&sh->rho_max, rq);
+    V.rho[k] = rq | (hc >= 0 ? (int32_t)0x80000000 : 0);
   }
   __syncthreads();
-  update_and_reward<NT>(P, A, m, sh, rho_lds, uni, lut, L, r);
+  endpoint_bbox<NT>(P, V.rho, sh->eox, sh->eoy, sh->ib_e, sh);
+  __syncthreads();
+  update_and_reward<NT>(P, A, m, V, L, r);
 }
 
 // Fused persistent step: workgroups pull robots in largest-grid-first order.
 template <int NT>
 __global__ __launch_bounds__(NT) void k_fused(EnvParams P, StepArgs A, LdsPlan L) {
   extern __shared__ __align__(16) unsigned char smem[];
-  uint32_t* lut = reinterpret_cast<uint32_t*>(smem + L.off_lut);
-  int32_t* rho_lds = reinterpret_cast<int32_t*>(smem + L.off_rho);
-  RobotShared* sh = reinterpret_cast<RobotShared*>(smem + L.off_misc);
-  uint32_t* uni = reinterpret_cast<uint32_t*>(smem + L.off_union);
-  for (int32_t i = threadIdx.x; i < 2 * P.lclamp + 1; i += NT) lut[i] = P.hq_lut[i];
+  const LdsView V = lds_view(smem, L);
+  RobotShared* sh = V.sh;
+  for (int32_t i = threadIdx.x; i < 2 * P.lclamp + 1; i += NT) V.lut[i] = P.hq_lut[i];
   for (int32_t w = blockIdx.x; w < P.n; w += gridDim.x) {
     const int32_t r = P.order[w];
     const RobotMeta m = P.meta[r];
@@ -664,19 +783,18 @@ __global__ __launch_bounds__(NT) void k_fused(EnvParams P, StepArgs A, LdsPlan L
       sh->tox = o.tox; sh->toy = o.toy; sh->ib_t = o.ib_t;
       sh->eox = o.eox; sh->eoy = o.eoy; sh->ib_e = o.ib_e;
       sh->collided = o.collided;
-      sh->rho_max = 0;
       sh->cnt_march = 0;
       sh->cnt_upd = 0;
+      init_bbox(sh);
     }
     __syncthreads();
     int32_t wy0;
-    stage_world<NT>(P, m, sh->toy >> 16, L.world_halo, uni, wy0);
+    stage_world<NT>(P, m, sh->toy >> 16, L.world_halo, V.uni, wy0);
     __syncthreads();
-    march_rays<NT>(P, m, sh, uni, wy0, rho_lds, A.ranges, L.record != 0, r);
+    march_rays<NT>(P, m, V, V.uni, wy0, A.ranges, L.record != 0, r);
+    endpoint_bbox<NT>(P, V.rho, sh->eox, sh->eoy, sh->ib_e, sh);
     __syncthreads();
-    for (int32_t k = threadIdx.x; k < P.R; k += NT) atomicMax(&sh->rho_max, rho_lds[k] & 0x7fffffff);
-    __syncthreads();
-    update_and_reward<NT>(P, A, m, sh, rho_lds, uni, lut, L, r);
+    update_and_reward<NT>(P, A, m, V, L, r);
     __syncthreads();
   }
 }
@@ -718,6 +836,7 @@ __global__ void k_reset(EnvParams P, const uint32_t* world_src, const float* ini
     P.counters[3 * (int64_t)r + 1] = 0;
     P.counters[3 * (int64_t)r + 2] = 0;
   }
+  for (int32_t k = threadIdx.x; k < P.R; k += blockDim.x) P.raylen[(int64_t)r * P.R + k] = 0;
 }
 
 __global__ void k_observe(EnvParams P, const float* ranges, int16_t* crop, int32_t cs, float* scan, float* state,

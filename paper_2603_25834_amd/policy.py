@@ -1,0 +1,120 @@
+"""PPO actor-critic on the GPU (thin wrapper over the C-ABI) and autograd glue.
+
+Method: arXiv 2603.25834 Sec. III-F (PPO clipped surrogate, Eqs. 18-20, with
+GAE).  Every forward, loss, gradient, GAE and Adam computation runs in the
+library's kernels; this module only marshals torch device tensors.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from ._lib import PolicyConfig, check, lib
+
+
+def _p(t):
+    assert t.is_cuda and t.is_contiguous(), "device tensors must be contiguous CUDA tensors"
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def num_params(n_scan: int) -> int:
+    return int(lib().aslam_policy_num_params(n_scan))
+
+
+class Policy:
+    def __init__(self, n_scan: int = 360, max_batch: int = 16384, clip_eps: float = 0.2, c_value: float = 0.5,
+                 c_entropy: float = 0.005):
+        self.n_scan, self.max_batch = n_scan, max_batch
+        self.cfg = PolicyConfig(n_scan, max_batch, clip_eps, c_value, c_entropy)
+        h = ctypes.c_void_p()
+        check(lib().aslam_policy_create(ctypes.byref(self.cfg), ctypes.byref(h)))
+        self.h = h
+        self.n_params = num_params(n_scan)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().aslam_policy_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check_obs(self, params, crop, scan, state):
+        B = crop.shape[0]
+        assert params.dtype == torch.float32 and params.numel() == self.n_params
+        assert crop.dtype == torch.int16 and crop.shape[1:] == (64, 64)
+        assert scan.dtype == torch.float32 and scan.shape == (B, self.n_scan)
+        assert state.dtype == torch.float32 and state.shape == (B, 12)
+        return B
+
+    def forward(self, params, crop, scan, state, mu=None, value=None):
+        B = self._check_obs(params, crop, scan, state)
+        mu = torch.empty((B, 2), device=crop.device) if mu is None else mu
+        value = torch.empty(B, device=crop.device) if value is None else value
+        check(lib().aslam_policy_forward(self.h, _p(params), _p(crop), _p(scan), _p(state), B, _p(mu), _p(value),
+                                         _stream()))
+        return mu, value
+
+    def backward(self, params, crop, scan, state, act, old_logp, adv, ret, grads, loss=None):
+        """Adds the PPO loss gradient of this minibatch to `grads`; returns loss terms [4]."""
+        B = self._check_obs(params, crop, scan, state)
+        for t, shp in ((act, (B, 2)), (old_logp, (B,)), (adv, (B,)), (ret, (B,))):
+            assert t.dtype == torch.float32 and tuple(t.shape) == shp
+        assert grads.dtype == torch.float32 and grads.numel() == self.n_params
+        loss = torch.empty(4, device=crop.device) if loss is None else loss
+        check(lib().aslam_policy_backward(self.h, _p(params), _p(crop), _p(scan), _p(state), B, _p(act),
+                                          _p(old_logp), _p(adv), _p(ret), _p(grads), _p(loss), _stream()))
+        return loss
+
+
+def gae(rewards, values, dones, last_value, gamma=0.99, lam=0.95):
+    T, N = rewards.shape
+    adv = torch.empty_like(rewards)
+    ret = torch.empty_like(rewards)
+    check(lib().aslam_gae(_p(rewards), _p(values), _p(dones), _p(last_value), T, N, gamma, lam, _p(adv), _p(ret),
+                          _stream()))
+    return adv, ret
+
+
+def adam(params, grads, m, v, step, lr=3e-4, beta1=0.9, beta2=0.999, eps=1e-8):
+    check(lib().aslam_adam(_p(params), _p(grads), _p(m), _p(v), params.numel(), step, lr, beta1, beta2, eps,
+                           _stream()))
+
+
+class PPOLossFn(torch.autograd.Function):
+    """loss = PPOLossFn.apply(params, policy, crop, scan, state, act, old_logp, adv, ret).
+
+    The forward pass runs the fused loss-and-gradient kernels (activations are
+    recomputed, only inputs are kept); backward scales the stored gradient."""
+
+    @staticmethod
+    def forward(ctx, params, policy, crop, scan, state, act, old_logp, adv, ret):
+        grads = torch.zeros_like(params)
+        loss = policy.backward(params, crop, scan, state, act, old_logp, adv, ret, grads)
+        ctx.save_for_backward(grads)
+        return loss[0].clone()
+
+    @staticmethod
+    def backward(ctx, g):
+        (grads,) = ctx.saved_tensors
+        return (grads * g,) + (None,) * 8
+
+
+class PolicyFn(torch.autograd.Function):
+    """(mu, value) = PolicyFn.apply(params, policy, crop, scan, state) for rollouts (no gradient)."""
+
+    @staticmethod
+    def forward(ctx, params, policy, crop, scan, state):
+        return policy.forward(params, crop, scan, state)
+
+    @staticmethod
+    def backward(ctx, gm, gv):
+        raise RuntimeError("PolicyFn has no backward; train through PPOLossFn")

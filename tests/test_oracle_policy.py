@@ -166,3 +166,37 @@ def test_adam_first_steps_closed_form():
     # a constant gradient keeps the bias-corrected moments at (g, g^2)
     t2, m, v = PR.adam_step(t1, g, m, v, 2, lr=lr, eps=eps)
     assert torch.allclose(t2, t1 - lr * g / (g.abs() + eps), rtol=1e-12, atol=1e-14)
+
+
+def _rne_bits(x: np.ndarray) -> np.ndarray:
+    """BF16 round-to-nearest-even by integer arithmetic on the FP32 bit pattern (finite inputs)."""
+    u = x.astype(np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16 << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def test_bf16_rounding_is_round_to_nearest_even():
+    rng = np.random.default_rng(7)
+    x = np.concatenate([rng.normal(size=10000).astype(np.float32) * 10.0 ** rng.integers(-6, 6, 10000),
+                        np.array([1.0 + 2 ** -8, 1.0 + 3 * 2 ** -8, -1.0 - 2 ** -8, 0.0], np.float32)])
+    got = PR.round_bf16(torch.from_numpy(x.astype(np.float64))).numpy()
+    assert np.array_equal(got, _rne_bits(x))
+    assert got[-4] == 1.0 and got[-3] == 1.0 + 4 * 2 ** -8  # ties to even
+
+
+def test_workload_precision_mode_reduces_to_fp64_without_rounding():
+    theta = torch.from_numpy(synth.init_policy_params(8, seed=8)).double()
+    b = _batch(5, 8)
+    args = (b["crop"], b["scan"], b["state"], b["act"], b["old_logp"], b["adv"], b["ret"], SMALL)
+    t1 = theta.clone().requires_grad_(True)
+    t2 = theta.clone().requires_grad_(True)
+    l1, _ = PR.ppo_loss(t1, *args)
+    l2, _ = PR.ppo_loss_bf16(t2, *args, rounding=False)
+    (g1,) = torch.autograd.grad(l1, t1)
+    (g2,) = torch.autograd.grad(l2, t2)
+    assert float(l1) == float(l2) and torch.equal(g1, g2)
+    # with rounding the outputs stay close to the FP64 network (BF16 has 8 significant bits)
+    mu, _, v = PR.forward(theta, b["crop"], b["scan"], b["state"], SMALL)
+    mub, _, vb = PR.forward_bf16(theta, b["crop"], b["scan"], b["state"], SMALL)
+    assert torch.linalg.norm(mub - mu) <= 2e-2 * torch.linalg.norm(mu)
+    assert torch.linalg.norm(vb - v) <= 2e-2 * torch.linalg.norm(v)
