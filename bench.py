@@ -23,6 +23,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+BF16_PEAK_TFLOPS = 2500.0
 METRIC = "env-steps/s and rays/s at 750 & 4096 robots; % HBM roofline; PPO fwd+bwd/s"
 
 
@@ -145,6 +146,69 @@ class Workbench:
         return t0.elapsed_time(t1) / reps
 
 
+def policy_flops(n_scan: int) -> tuple:
+    """Algorithmic FLOP per sample of the actor-critic: forward, and backward with the forward recomputed.
+
+    conv1 1->16 (3x3, stride 2) onto 32x32, conv2 16->32 onto 16x16, FC1 (8192 + R + 12)->256, FC2 256->256,
+    heads 256->3.  Backward: weight gradients of every layer, input gradients of every layer but conv1, and
+    of FC1 only for its conv2 inputs."""
+    c1 = 2 * 16 * 32 * 32 * 9
+    c2 = 2 * 32 * 16 * 16 * 16 * 9
+    k1 = 8192 + n_scan + 12
+    f1 = 2 * k1 * 256
+    f2 = 2 * 256 * 256
+    hd = 2 * 256 * 3
+    fwd = c1 + c2 + f1 + f2 + hd
+    bwd = fwd + c1 + 2 * c2 + (f1 + 2 * 8192 * 256) + 2 * f2 + 2 * hd
+    return float(fwd), float(bwd)
+
+
+def ppo_time(n_scan: int, batch: int, seed: int, reps: int = 10) -> dict:
+    """Policy forward and fused loss+backward on one synthetic minibatch resident in HBM."""
+    import torch
+
+    from paper_2603_25834_amd import synth
+    from paper_2603_25834_amd.policy import Policy
+    pol = Policy(n_scan, max_batch=batch)
+    d = {k: torch.from_numpy(v).cuda() for k, v in synth.policy_batch(batch, n_scan, seed).items()}
+    params = torch.from_numpy(synth.init_policy_params(n_scan, seed)).cuda()
+    grads = torch.zeros_like(params)
+    mu = torch.empty((batch, 2), device="cuda")
+    val = torch.empty(batch, device="cuda")
+    loss = torch.empty(4, device="cuda")
+
+    def fwd():
+        pol.forward(params, d["crop"], d["scan"], d["state"], mu, val)
+
+    def bwd():
+        pol.backward(params, d["crop"], d["scan"], d["state"], d["act"], d["old_logp"], d["adv"], d["ret"], grads,
+                     loss)
+
+    out = {}
+    for name, fn in (("forward", fwd), ("backward", bwd)):
+        for _ in range(2):
+            fn()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        out[name] = e0.elapsed_time(e1) / reps
+    f_fwd, f_bwd = policy_flops(n_scan)
+    tf_f = f_fwd * batch / (out["forward"] / 1e3) / 1e12
+    tf_b = f_bwd * batch / (out["backward"] / 1e3) / 1e12
+    pol.close()
+    return {"minibatch": batch, "forward_ms": out["forward"], "backward_ms": out["backward"],
+            "forward_samples_per_s": batch / (out["forward"] / 1e3),
+            "fwd_bwd_samples_per_s": batch / ((out["forward"] + out["backward"]) / 1e3),
+            "forward_tflops": tf_f, "backward_tflops": tf_b,
+            "mfma_frac_forward": tf_f / BF16_PEAK_TFLOPS, "mfma_frac_backward": tf_b / BF16_PEAK_TFLOPS,
+            "flop_per_sample": {"forward": f_fwd, "backward_with_recompute": f_bwd}}
+
+
 def cpu_baseline(name: str, seed: int, robots: int, steps: int) -> dict:
     """The oracle as it stands, all host threads, on a bounded sample of the workload."""
     from oracle import oracle as O
@@ -185,6 +249,8 @@ def main():
     ap.add_argument("--secondary", default="ragged_4096", help="second workload ('' to skip)")
     ap.add_argument("--secondary-steps", type=int, default=200)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-ppo", action="store_true")
+    ap.add_argument("--ppo-batch", type=int, default=16384)
     ap.add_argument("--cpu-robots", type=int, default=750)
     ap.add_argument("--cpu-steps", type=int, default=1000)
     ap.add_argument("--calib-copy", type=int, default=0,
@@ -272,6 +338,12 @@ def main():
         print(f"[bench] {args.secondary}: fused {r2['ms_per_step']*1e3:.1f} us/step, plain "
               f"{r2p['ms_per_step']*1e3:.1f} us/step", file=sys.stderr, flush=True)
         del wb2
+    if not args.no_ppo:
+        print(f"[bench] PPO minibatch {args.ppo_batch}", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+        out["ppo"] = ppo_time(out["config"]["rays"], args.ppo_batch, args.seed)
+        print(f"[bench] PPO fwd {out['ppo']['forward_ms']:.3f} ms, fwd+bwd(recompute) {out['ppo']['backward_ms']:.3f} ms",
+              file=sys.stderr, flush=True)
     if not args.no_cpu:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.workload, args.seed, args.cpu_robots, args.cpu_steps)

@@ -435,7 +435,7 @@ __device__ void stage_world(const EnvParams& P, const RobotMeta& m, int32_t cy, 
 // LiDAR march of every ray of the robot from the true pose (lanes = rays).
 template <int NT>
 __device__ void march_rays(const EnvParams& P, const RobotMeta& m, const LdsView& V, const uint32_t* sw,
-                           int32_t wy0, float* ranges_out, bool record, int32_t r) {
+                           int32_t wy0, int32_t wmax, float* ranges_out, bool record, int32_t r) {
   RobotShared* sh = V.sh;
   int32_t* rho_lds = V.rho;
   const int32_t s = m.side;
@@ -468,15 +468,43 @@ __device__ void march_rays(const EnvParams& P, const RobotMeta& m, const LdsView
       hit = (sw[li >> 5] >> (li & 31)) & 1u;
       done = hit || q.n == 0;
     }
-    // one cell per iteration; the loop runs while any lane of the wave walks
+    // Four cells per iteration: the next four DDA steps are taken first and
+    // their world words read together, so one LDS round trip covers four
+    // cells.  Steps past the walk's own count n are read (word index clamped
+    // to the staged buffer) but never count as hits.
     while (__builtin_amdgcn_ballot_w64(!done) != 0) {
       if (!done) {
-        const bool stepx = D <= 0;
-        li += stepx ? sx : sy;
-        D += stepx ? q.DX : -q.DY;
-        ++i;
-        hit = (sw[li >> 5] >> (li & 31)) & 1u;
-        done = hit || i >= q.n;
+        int32_t l[4], d[4];
+        int32_t lc = li, dc = D;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const bool stepx = dc <= 0;
+          lc += stepx ? sx : sy;
+          dc += stepx ? q.DX : -q.DY;
+          l[u] = lc;
+          d[u] = dc;
+        }
+        uint32_t wd[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) wd[u] = sw[min(max(l[u] >> 5, 0), wmax)];
+        uint32_t bits = 0u;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) bits |= ((wd[u] >> (l[u] & 31)) & 1u) << u;
+        const int32_t rem = q.n - i;   // >= 1 while the lane walks
+        bits &= rem >= 4 ? 0xfu : ((1u << rem) - 1u);
+        if (bits) {
+          const int32_t u = __builtin_ctz(bits);
+          li = u == 0 ? l[0] : u == 1 ? l[1] : u == 2 ? l[2] : l[3];
+          D = u == 0 ? d[0] : u == 1 ? d[1] : u == 2 ? d[2] : d[3];
+          i += u + 1;
+          hit = true;
+          done = true;
+        } else {
+          li = l[3];
+          D = d[3];
+          i = min(i + 4, q.n);
+          done = i >= q.n;
+        }
       }
     }
     if (active) {
@@ -523,13 +551,14 @@ __device__ __forceinline__ long long wave_sum_i64(long long v) {
 // One saturating add per coded cell of a band of the code window.  The band
 // is split into octets (8 cells, one 16-byte access, 16-byte aligned because
 // the window starts on a 32-cell boundary); each thread keeps U octets in
-// flight.  An octet is owned by one thread, so the read-modify-write is
-// race-free; uncoded cells of a touched octet are written back unchanged.
-template <int NT>
+// flight, so a band costs few HBM round trips.  An octet is owned by one
+// thread, so the read-modify-write is race-free; uncoded cells of a touched
+// octet are written back unchanged, untouched octets are neither read nor
+// written.
+template <int NT, int U>
 __device__ __forceinline__ void apply_band(const EnvParams& P, const uint32_t* miss, const uint32_t* hitm,
                                            int32_t rows, int32_t nw, int16_t* band_base, int32_t s,
                                            const uint32_t* lut, long long& dh, int32_t& ncoded) {
-  constexpr int U = 4;
   const int32_t lpr = nw * 4;  // octets per row
   const int32_t total = rows * lpr;
   int32_t row = (int32_t)threadIdx.x / lpr;
@@ -537,7 +566,7 @@ __device__ __forceinline__ void apply_band(const EnvParams& P, const uint32_t* m
   const int32_t qa = NT / lpr, ra = NT - qa * lpr;
   const int32_t lc = P.lclamp;
   for (int32_t o = threadIdx.x; o < total; o += U * NT) {
-    uint32_t cm[U], ch[U];
+    uint32_t code[U];   // miss bits | hit bits << 8
     int32_t off[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -547,8 +576,7 @@ __device__ __forceinline__ void apply_band(const EnvParams& P, const uint32_t* m
         wh = hitm[row * nw + (col >> 2)];
       }
       const int32_t sh = (col & 3) * 8;
-      cm[u] = (wm >> sh) & 0xffu;
-      ch[u] = (wh >> sh) & 0xffu;
+      code[u] = ((wm >> sh) & 0xffu) | (((wh >> sh) & 0xffu) << 8);
       off[u] = row * s + col * 8;
       col += ra;
       row += qa;
@@ -557,11 +585,12 @@ __device__ __forceinline__ void apply_band(const EnvParams& P, const uint32_t* m
     int4 v[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      if (cm[u] | ch[u]) v[u] = *reinterpret_cast<const int4*>(band_base + off[u]);
+      if (code[u]) v[u] = *reinterpret_cast<const int4*>(band_base + off[u]);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const uint32_t any = cm[u] | ch[u];
+      const uint32_t ch = code[u] >> 8;
+      const uint32_t any = (code[u] | ch) & 0xffu;
       if (!any) continue;
       ncoded += __builtin_popcount(any);
       int32_t w[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
@@ -570,11 +599,11 @@ __device__ __forceinline__ void apply_band(const EnvParams& P, const uint32_t* m
         const int32_t l0 = (int16_t)(w[j] & 0xffff), l1 = w[j] >> 16;
         int32_t n0 = l0, n1 = l1;
         if ((any >> (2 * j)) & 1u) {
-          n0 = min(max(l0 + (((ch[u] >> (2 * j)) & 1u) ? P.lhit : P.lmiss), -lc), lc);
+          n0 = min(max(l0 + (((ch >> (2 * j)) & 1u) ? P.lhit : P.lmiss), -lc), lc);
           dh += (long long)lut[n0 + lc] - (long long)lut[l0 + lc];
         }
         if ((any >> (2 * j + 1)) & 1u) {
-          n1 = min(max(l1 + (((ch[u] >> (2 * j + 1)) & 1u) ? P.lhit : P.lmiss), -lc), lc);
+          n1 = min(max(l1 + (((ch >> (2 * j + 1)) & 1u) ? P.lhit : P.lmiss), -lc), lc);
           dh += (long long)lut[n1 + lc] - (long long)lut[l1 + lc];
         }
         w[j] = (n0 & 0xffff) | (n1 << 16);
@@ -583,6 +612,8 @@ __device__ __forceinline__ void apply_band(const EnvParams& P, const uint32_t* m
     }
   }
 }
+
+constexpr int kApplyInFlight = 4;
 
 // Map update from the estimated pose with the measured ranges, then the
 // reward.  rho_lds[k]: range (Q16) with bit 31 set when ray k hit.
@@ -619,6 +650,7 @@ __device__ void update_and_reward(const EnvParams& P, const StepArgs& A, const R
     for (int32_t by0 = y0; by0 <= y1; by0 += band) {
       const int32_t rows = min(band, y1 - by0 + 1);
       const uint32_t band_bits = (uint32_t)(rows * rowbits);
+      const bool one_band = y1 - y0 + 1 <= band;
       {
         uint4* u4 = reinterpret_cast<uint4*>(uni);
         const int32_t nclr = (2 * band * nw + 3) >> 2;
@@ -647,9 +679,23 @@ __device__ void update_and_reward(const EnvParams& P, const StepArgs& A, const R
           if ((uint32_t)wi < band_bits) atomicOr(&miss[wi >> 5], 1u << (wi & 31));
         }
         const int32_t w0 = wi;
-        // uniform trip count over the wave; lanes past their own count only step
+        // Uniform trip counts over the wave.  While every lane is within its
+        // own count and the band holds the whole window, every step lands in
+        // the bitmap (the window holds every visited cell), so the first
+        // loop marks without tests; the word index is clamped only to keep
+        // the store inside the bitmap.  The second loop finishes the longer
+        // walks, testing each step.
         const int32_t nmax = wave_max_i32(n);
-        for (int32_t i = 0; i < nmax; ++i) {
+        const int32_t nmin = one_band ? wave_min_i32(valid ? n : 0) : 0;
+        const uint32_t last_word = (band_bits >> 5) - 1u;
+        int32_t i = 0;
+        for (; i < nmin; ++i) {
+          const bool stepx = D <= 0;
+          wi += stepx ? sx : sy;
+          D += stepx ? q.DX : -q.DY;
+          atomicOr(&miss[min((uint32_t)wi >> 5, last_word)], 1u << (wi & 31));
+        }
+        for (; i < nmax; ++i) {
           const bool stepx = D <= 0;
           wi += stepx ? sx : sy;
           D += stepx ? q.DX : -q.DY;
@@ -663,7 +709,8 @@ __device__ void update_and_reward(const EnvParams& P, const StepArgs& A, const R
       }
       __syncthreads();
       // apply: each coded cell once (8 cells = one 16-byte access per octet)
-      apply_band<NT>(P, miss, hitm, rows, nw, P.belief + base + (int64_t)by0 * s + x0w, s, V.lut, dh, ncoded);
+      apply_band<NT, kApplyInFlight>(P, miss, hitm, rows, nw, P.belief + base + (int64_t)by0 * s + x0w, s, V.lut, dh,
+                                     ncoded);
       __syncthreads();
     }
   }
@@ -730,7 +777,7 @@ __global__ __launch_bounds__(NT) void k_march(EnvParams P, StepArgs A, LdsPlan L
   int32_t wy0;
   stage_world<NT>(P, m, sh->toy >> 16, L.world_halo, V.uni, wy0);
   __syncthreads();
-  march_rays<NT>(P, m, V, V.uni, wy0, A.ranges, true, r);
+  march_rays<NT>(P, m, V, V.uni, wy0, (L.union_bytes >> 2) - 1, A.ranges, true, r);
   if (threadIdx.x == 0) P.counters[3 * (int64_t)r + 1] += sh->cnt_march;
 }
 
@@ -769,8 +816,10 @@ __global__ __launch_bounds__(NT) void k_update(EnvParams P, StepArgs A, LdsPlan 
 }
 
 // Fused persistent step: workgroups pull robots in largest-grid-first order.
+// The register budget is capped at four waves per SIMD (128 VGPRs): at 512
+// threads that keeps two robots resident per CU instead of one.
 template <int NT>
-__global__ __launch_bounds__(NT) void k_fused(EnvParams P, StepArgs A, LdsPlan L) {
+__global__ __launch_bounds__(NT, 4) void k_fused(EnvParams P, StepArgs A, LdsPlan L) {
   extern __shared__ __align__(16) unsigned char smem[];
   const LdsView V = lds_view(smem, L);
   RobotShared* sh = V.sh;
@@ -791,7 +840,7 @@ __global__ __launch_bounds__(NT) void k_fused(EnvParams P, StepArgs A, LdsPlan L
     int32_t wy0;
     stage_world<NT>(P, m, sh->toy >> 16, L.world_halo, V.uni, wy0);
     __syncthreads();
-    march_rays<NT>(P, m, V, V.uni, wy0, A.ranges, L.record != 0, r);
+    march_rays<NT>(P, m, V, V.uni, wy0, (L.union_bytes >> 2) - 1, A.ranges, L.record != 0, r);
     endpoint_bbox<NT>(P, V.rho, sh->eox, sh->eoy, sh->ib_e, sh);
     __syncthreads();
     update_and_reward<NT>(P, A, m, V, L, r);
