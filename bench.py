@@ -209,6 +209,67 @@ def ppo_time(n_scan: int, batch: int, seed: int, reps: int = 10) -> dict:
             "flop_per_sample": {"forward": f_fwd, "backward_with_recompute": f_bwd}}
 
 
+def cpu_full_loop(name: str, seed: int, robots: int, T: int, epochs: int) -> dict:
+    """The oracle as it stands running one PPO iteration on the host: C oracle env (all host threads) and
+    the FP64 PyTorch policy (forward per step, loss gradient by autograd, Adam), one minibatch per epoch."""
+    import torch
+
+    from oracle import oracle as O
+    from oracle import policy_ref as PR
+    from paper_2603_25834_amd import synth
+    w = synth.WORKLOADS[name]
+    idx = np.arange(min(robots, w.n_robots))
+    n = len(idx)
+    b = synth.make_batch(name, seed, idx)
+    G = synth.noise(name, seed, T, idx)
+    env = O.OracleEnv(w.params(), b.sides, b.world, b.world_off)
+    env.reset(b.start)
+    shape = PR.PolicyShape(w.n_rays)
+    theta = torch.from_numpy(synth.init_policy_params(w.n_rays, seed)).double()
+    m = torch.zeros_like(theta)
+    v = torch.zeros_like(theta)
+    rng = np.random.default_rng([seed, 78])
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
+    threads = min(threads, os.cpu_count() or threads)
+    ranges = np.zeros((n, w.n_rays), np.float32)
+    obs = {"crop": [], "scan": [], "state": []}
+    act_l, logp_l, val_l, rew_l, done_l = [], [], [], [], []
+    t0 = time.time()
+    with torch.no_grad():
+        for t in range(T + 1):
+            crop, scan, state = env.observe(ranges)
+            mu, ls, val = PR.forward(theta, torch.from_numpy(crop), torch.from_numpy(scan), torch.from_numpy(state),
+                                     shape)
+            val_l.append(val)
+            if t == T:
+                break
+            for k, a in (("crop", crop), ("scan", scan), ("state", state)):
+                obs[k].append(a)
+            act = mu + torch.exp(ls) * torch.from_numpy(rng.standard_normal((n, 2)))
+            act_l.append(act.float())
+            logp_l.append(PR.gaussian_logp(mu, ls, act).float())
+            o = env.step(act.float().numpy(), G[t], threads=threads)
+            ranges = o.ranges
+            rew_l.append(torch.from_numpy(o.reward))
+            done_l.append(torch.from_numpy(o.done.astype(np.float64)))
+            if o.done.any():
+                env.reset(b.start, o.done)
+    adv, ret = PR.gae(torch.stack(rew_l), torch.stack(val_l[:T]), torch.stack(done_l), val_l[T])
+    flat = lambda xs: torch.from_numpy(np.concatenate(xs, 0))
+    crop, scan, state = flat(obs["crop"]), flat(obs["scan"]), flat(obs["state"])
+    act, old = torch.cat(act_l, 0), torch.cat(logp_l, 0)
+    for e in range(epochs):
+        th = theta.clone().requires_grad_(True)
+        loss, _ = PR.ppo_loss(th, crop, scan, state, act, old, adv.reshape(-1).float(), ret.reshape(-1).float(),
+                              shape)
+        (g,) = torch.autograd.grad(loss, th)
+        theta, m, v = PR.adam_step(theta, g, m, v, e + 1)
+    dt = time.time() - t0
+    return {"value": n * T / dt, "unit": "env-steps/s (PPO training loop)", "cores": threads, "kind": "oracle",
+            "sample": f"{name}: first {n} robots, one iteration of {T} rollout steps + {epochs} epochs "
+                      f"of one {n * T}-sample minibatch, FP64 policy ({dt:.1f} s)"}
+
+
 def cpu_baseline(name: str, seed: int, robots: int, steps: int) -> dict:
     """The oracle as it stands, all host threads, on a bounded sample of the workload."""
     from oracle import oracle as O
@@ -235,24 +296,79 @@ def cpu_baseline(name: str, seed: int, robots: int, steps: int) -> dict:
             "coded_cells_per_robot_step": float(cnt[2]) / rs, "world_cells_read_per_robot_step": float(cnt[3]) / rs}
 
 
+def train_loop(wb, horizon: int, epochs: int, minibatch: int, warmup: int, iters: int, seed: int) -> dict:
+    """Time `iters` PPO training iterations on the workbench's env after `warmup` untimed ones."""
+    import torch
+
+    from paper_2603_25834_amd import synth
+    from paper_2603_25834_amd.ppo import PPOTrainer
+    wb.env.reset(wb.world, wb.start)
+    params = torch.from_numpy(synth.init_policy_params(wb.R, seed)).cuda()
+    tr = PPOTrainer(wb.env, wb.world, wb.start, params, T=horizon, epochs=epochs, minibatch=minibatch)
+    noise, eps, perm = tr.draws(warmup + iters, seed)
+    for i in range(warmup):
+        tr.iteration(noise[i], eps[i], perm[i])
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for i in range(warmup, warmup + iters):
+        tr.iteration(noise[i], eps[i], perm[i])
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / iters
+    out = {"ms_per_iteration": ms, "env_steps_per_s": wb.n * horizon / (ms / 1e3),
+           "samples_per_iteration": tr.S, "minibatch": tr.mb, "minibatches_per_epoch": tr.n_mb,
+           "iterations": iters, "final_loss_terms": [float(x) for x in tr.loss.cpu()]}
+    del tr
+    torch.cuda.empty_cache()
+    return out
+
+
+def autotune_forms(wb) -> tuple:
+    """Autotune the fused and the plain form on the workbench's own batch, then reset it."""
+    from paper_2603_25834_amd import _lib
+    from paper_2603_25834_amd.autotune import THREADS, Candidate, default_candidates, tune
+    A, G = wb.dA[:8], wb.dG[:8]
+    out = (wb.ranges, wb.reward, wb.done)
+    rf = tune(wb.env, A, G, *out, candidates=default_candidates(wb.env), force=True)
+    fused = dict(rf["best"])
+    rp = tune(wb.env, A, G, *out, candidates=[Candidate(t, form=_lib.FORM_PLAIN) for t in THREADS], force=True)
+    plain = dict(rp["best"])
+    wb.env.set_exec(**fused)
+    wb.env.reset(wb.world, wb.start)
+    summary = {"fused_us": {f"{r['candidate']['threads']}/{r['candidate']['band_rows']}/{r['candidate']['grid']}":
+                            round(r["us_per_step"], 1) for r in rf["table"] if r["us_per_step"] is not None},
+               "plain_us": {str(r["candidate"]["threads"]): round(r["us_per_step"], 1)
+                            for r in rp["table"] if r["us_per_step"] is not None}}
+    return fused, plain, summary
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=10, help="timed PPO training iterations")
+    ap.add_argument("--warmup", type=int, default=2, help="untimed PPO training iterations")
+    ap.add_argument("--horizon", type=int, default=24, help="rollout steps per iteration")
+    ap.add_argument("--epochs", type=int, default=4)
+    ap.add_argument("--minibatch", type=int, default=16384)
+    ap.add_argument("--env-steps", type=int, default=1000, help="env-only timing: steps in one HIP graph")
+    ap.add_argument("--env-warmup", type=int, default=20)
     ap.add_argument("--workload", default="paper_750x256")
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--threads", type=int, default=256)
+    ap.add_argument("--threads", type=int, default=0, help="threads per robot; 0: autotune the launch shape")
     ap.add_argument("--band", type=int, default=0)
     ap.add_argument("--grid", type=int, default=0)
     ap.add_argument("--eager", action="store_true", help="eager launches instead of one HIP graph")
     ap.add_argument("--secondary", default="ragged_4096", help="second workload ('' to skip)")
     ap.add_argument("--secondary-steps", type=int, default=200)
+    ap.add_argument("--secondary-iters", type=int, default=2, help="timed training iterations of the secondary")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-ppo", action="store_true")
     ap.add_argument("--ppo-batch", type=int, default=16384)
-    ap.add_argument("--cpu-robots", type=int, default=750)
-    ap.add_argument("--cpu-steps", type=int, default=1000)
+    ap.add_argument("--cpu-robots", type=int, default=256, help="oracle training-loop sample: robots")
+    ap.add_argument("--cpu-env-robots", type=int, default=750, help="oracle env-step sample: robots")
+    ap.add_argument("--cpu-env-steps", type=int, default=100, help="oracle env-step sample: steps")
     ap.add_argument("--calib-copy", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration under rocprofv3)")
     args = ap.parse_args()
@@ -267,17 +383,22 @@ def main():
     from paper_2603_25834_amd.env import device_info
     lds, cus = device_info()
 
-    fused = dict(form=_lib.FORM_FUSED, threads=args.threads, band_rows=args.band, grid=args.grid)
-    plain = dict(form=_lib.FORM_PLAIN, threads=args.threads, band_rows=args.band)
+    fused = dict(form=_lib.FORM_FUSED, threads=args.threads or 256, band_rows=args.band, grid=args.grid)
+    plain = dict(form=_lib.FORM_PLAIN, threads=args.threads or 256, band_rows=args.band)
     print(f"[bench] {args.workload}: setting up", file=sys.stderr, flush=True)
-    wb = Workbench(args.workload, args.seed, args.warmup + args.steps, fused)
-    res = wb.run(args.warmup, args.steps, graph=not args.eager)
-    print(f"[bench] fused: {res['ms_per_step']*1e3:.1f} us/step", file=sys.stderr, flush=True)
+    wb = Workbench(args.workload, args.seed, args.env_warmup + args.env_steps, fused)
+    tuned = {}
+    if not args.threads:
+        fused, plain, tuned = autotune_forms(wb)
+        print(f"[bench] autotuned: fused {fused}, plain {plain}", file=sys.stderr, flush=True)
+    # ---- the env step alone: one HIP graph of env_steps fused steps, then the plain form
+    res = wb.run(args.env_warmup, args.env_steps, graph=not args.eager)
+    print(f"[bench] env step, fused: {res['ms_per_step']*1e3:.1f} us/step", file=sys.stderr, flush=True)
     obs_ms = wb.observe_time()
     wb.env.set_exec(**plain)
     wb.env.reset(wb.world, wb.start)
-    res_plain = wb.run(args.warmup, args.steps, graph=not args.eager)
-    print(f"[bench] plain: {res_plain['ms_per_step']*1e3:.1f} us/step", file=sys.stderr, flush=True)
+    res_plain = wb.run(args.env_warmup, args.env_steps, graph=not args.eager)
+    print(f"[bench] env step, plain: {res_plain['ms_per_step']*1e3:.1f} us/step", file=sys.stderr, flush=True)
     if args.calib_copy:
         src = torch.ones(args.calib_copy << 18, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -285,9 +406,13 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    step_ms = res["ms_per_step"] + obs_ms
-    value = wb.n / (step_ms / 1e3)
     traffic = read_traffic("k_fused", args.workload)
+    # ---- the bench step: one PPO training iteration (rollout of `horizon` steps + update)
+    wb.env.set_exec(**fused)
+    loop = train_loop(wb, args.horizon, args.epochs, args.minibatch, args.warmup, args.steps, args.seed)
+    print(f"[bench] training iteration: {loop['ms_per_iteration']:.2f} ms "
+          f"({loop['env_steps_per_s']:.4g} env-steps/s)", file=sys.stderr, flush=True)
+    value = loop["env_steps_per_s"]
 
     out = {
         "metric": METRIC,
@@ -296,19 +421,30 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": step_ms,
+        "ms_per_step": loop["ms_per_iteration"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "int32",
-        "data": "synthetic (seeded worlds, start poses, actions and normal draws)",
+        "dtype": "int32+bf16",
+        "data": "synthetic (seeded worlds, start poses, odometry and action noise, minibatch permutations; "
+                "random-init policy)",
         "config": {"workload": args.workload, "robots": wb.n, "grid_side": sorted(set(map(int, wb.b.sides))),
                    "rays": wb.R, "r_max_m": wb.p["r_max_m"], "cell_m": wb.p["cell_m"],
-                   "loop_closure": int(wb.p["loop_closure"]), "form": "fused persistent, HIP graph",
-                   "threads": args.threads, "lds_bytes": wb.env.get_exec()["lds_bytes"]},
+                   "loop_closure": int(wb.p["loop_closure"]),
+                   "step": f"one PPO iteration: {args.horizon} env steps (fused persistent form) with observe, "
+                           f"policy forward and action sampling per step, GAE, {args.epochs} epochs of "
+                           f"minibatches <= {args.minibatch} (gather, loss+gradient with recompute, Adam)",
+                   "horizon": args.horizon, "epochs": args.epochs, "minibatch": loop["minibatch"],
+                   "minibatches_per_epoch": loop["minibatches_per_epoch"],
+                   "threads": fused["threads"], "band_rows": fused.get("band_rows", 0),
+                   "grid": fused.get("grid", 0), "plain_threads": plain["threads"],
+                   "lds_bytes": wb.env.get_exec()["lds_bytes"]},
         "rays_per_s": value * wb.R,
-        "env_step_only": {"env_steps_per_s": res["env_steps_per_s"], "ms_per_step": res["ms_per_step"],
-                          "observe_ms": obs_ms},
+        "training_loop": loop,
+        "env_step_only": {"env_steps_per_s": wb.n / ((res["ms_per_step"] + obs_ms) / 1e3),
+                          "rays_per_s": wb.n * wb.R / ((res["ms_per_step"] + obs_ms) / 1e3),
+                          "step_ms": res["ms_per_step"], "observe_ms": obs_ms, "steps": args.env_steps,
+                          "form": "fused persistent, HIP graph"},
         "plain_form": {"env_steps_per_s": res_plain["env_steps_per_s"], "ms_per_step": res_plain["ms_per_step"],
                        "fused_speedup": res["env_steps_per_s"] / res_plain["env_steps_per_s"]},
         "roofline": {"bound": "hbm", "achieved": res["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -319,34 +455,45 @@ def main():
                      "cell_visits_per_robot_step": res["march_visits_per_robot_step"] +
                      res["update_visits_per_robot_step"]},
         "device": {"lds_per_block": lds, "compute_units": cus},
+        "autotune": tuned or None,
     }
+    del wb
+    torch.cuda.empty_cache()
+    if not args.no_ppo:
+        print(f"[bench] PPO minibatch {args.ppo_batch}", file=sys.stderr, flush=True)
+        out["ppo"] = ppo_time(out["config"]["rays"], args.ppo_batch, args.seed)
+        print(f"[bench] PPO fwd {out['ppo']['forward_ms']:.3f} ms, fwd+bwd(recompute) {out['ppo']['backward_ms']:.3f} ms",
+              file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
     if args.secondary:
         print(f"[bench] {args.secondary}: setting up", file=sys.stderr, flush=True)
-        del wb
-        torch.cuda.empty_cache()
-        wb2 = Workbench(args.secondary, args.seed, args.warmup + args.secondary_steps, fused)
-        r2 = wb2.run(args.warmup, args.secondary_steps)
-        wb2.env.set_exec(**plain)
+        wb2 = Workbench(args.secondary, args.seed, args.env_warmup + args.secondary_steps, fused)
+        f2, p2, t2 = autotune_forms(wb2) if not args.threads else (fused, plain, {})
+        r2 = wb2.run(args.env_warmup, args.secondary_steps)
+        wb2.env.set_exec(**p2)
         wb2.env.reset(wb2.world, wb2.start)
-        r2p = wb2.run(args.warmup, args.secondary_steps)
+        r2p = wb2.run(args.env_warmup, args.secondary_steps)
         out["secondary"] = {
             "workload": args.secondary, "robots": wb2.n, "steps": args.secondary_steps,
             "fused_env_steps_per_s": r2["env_steps_per_s"], "fused_rays_per_s": r2["rays_per_s"],
             "plain_env_steps_per_s": r2p["env_steps_per_s"], "fused_speedup": r2["env_steps_per_s"] / r2p["env_steps_per_s"],
             "fused_hbm_gbs": r2["achieved_gbs"], "fused_hbm_frac": r2["achieved_gbs"] / HBM_PEAK_GBS,
-            "coded_cells_per_robot_step": r2["coded_cells_per_robot_step"]}
+            "coded_cells_per_robot_step": r2["coded_cells_per_robot_step"],
+            "fused_exec": f2, "plain_exec": p2, "autotune": t2 or None}
         print(f"[bench] {args.secondary}: fused {r2['ms_per_step']*1e3:.1f} us/step, plain "
               f"{r2p['ms_per_step']*1e3:.1f} us/step", file=sys.stderr, flush=True)
+        if args.secondary_iters > 0:
+            wb2.env.set_exec(**f2)
+            l2 = train_loop(wb2, args.horizon, args.epochs, args.minibatch, 1, args.secondary_iters, args.seed)
+            out["secondary"]["training_loop"] = l2
+            print(f"[bench] {args.secondary}: training iteration {l2['ms_per_iteration']:.2f} ms", file=sys.stderr,
+                  flush=True)
         del wb2
-    if not args.no_ppo:
-        print(f"[bench] PPO minibatch {args.ppo_batch}", file=sys.stderr, flush=True)
-        torch.cuda.empty_cache()
-        out["ppo"] = ppo_time(out["config"]["rays"], args.ppo_batch, args.seed)
-        print(f"[bench] PPO fwd {out['ppo']['forward_ms']:.3f} ms, fwd+bwd(recompute) {out['ppo']['backward_ms']:.3f} ms",
-              file=sys.stderr, flush=True)
     if not args.no_cpu:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(args.workload, args.seed, args.cpu_robots, args.cpu_steps)
+        out["cpu_baseline"] = cpu_full_loop(args.workload, args.seed, args.cpu_robots, args.horizon, args.epochs)
+        out["cpu_baseline"]["env_step_only"] = cpu_baseline(args.workload, args.seed, args.cpu_env_robots,
+                                                            args.cpu_env_steps)
     print(json.dumps(out), flush=True)
 
 

@@ -216,6 +216,19 @@ int aslam_gae(const float* rewards_dev, const float* values_dev, const uint8_t* 
 int aslam_adam(float* params_dev, const float* grads_dev, float* m_dev, float* v_dev, int64_t n, int32_t step,
                float lr, float beta1, float beta2, float eps, aslam_stream_t stream);
 
+/* Action sampling of the Gaussian policy (Sec. III-F): act = mu + exp(log_std) * eps and
+ * logp = sum_d [-eps_d^2 / 2 - log_std_d - ln(2 pi) / 2], the log-density of act.  mu_dev and eps_dev
+ * are [batch,2] float (eps: standard normals drawn by the caller), log_std is read from params_dev;
+ * act_dev [batch,2] and logp_dev [batch] are written.  The env step clamps actions to its box. */
+int aslam_policy_sample(aslam_policy* pol, const float* params_dev, const float* mu_dev, const float* eps_dev,
+                        int32_t batch, float* act_dev, float* logp_dev, aslam_stream_t stream);
+
+/* Row gather for minibatch assembly: dst row i = src row idx_dev[i], i < n, rows of row_bytes bytes
+ * (a multiple of 4; src and dst 4-byte aligned).  Indices are not checked against the source size:
+ * the caller guarantees 0 <= idx < rows of src.  ASL_EINVAL on NULL pointers or bad sizes. */
+int aslam_gather_rows(const void* src_dev, int64_t row_bytes, const int32_t* idx_dev, int32_t n, void* dst_dev,
+                      aslam_stream_t stream);
+
 /* ------------------------------------------------------------------ misc */
 
 const char* aslam_last_error(void);

@@ -1,0 +1,493 @@
+// conv_fused.h -- the actor-critic's convolutional encoder in one kernel (gfx950).
+//
+// conv1 (1 -> 16) and conv2 (16 -> 32), both 3x3 with stride 2 and padding 1
+// and ReLU, for one sample at a time per workgroup, with the 32x32x16 conv1
+// activation kept in LDS: HBM sees only the 64x64 int16 crop coming in and the
+// 8192 BF16 features going out.  Both convolutions run on MFMA
+// (v_mfma_f32_16x16x32_bf16, FP32 accumulation) with the same rounding points
+// as the layer-by-layer path: crop L/256, weights and activations in BF16.
+//
+// conv1 is written as C'[co][px] = sum_k W'[co][k] P[k][px] over a 4x4 input
+// window per output pixel: the crop is stored in LDS space-to-depth (2x2
+// blocks of 8 bytes), so the window of pixel (y, x) is the four blocks at
+// block rows y-1, y and block columns x-1, x, and a lane's eight k values are
+// two adjacent blocks (two 8-byte reads).  k = 8r + 4c + 2dy + dx addresses
+// block row r, block column c and the element (dy, dx) inside it, which is
+// input row 2y - 2 + 2r + dy, i.e. tap ky = 2r + dy - 1 (likewise kx); taps
+// outside 0..2 carry a zero weight.  The transposed product hands each lane
+// four consecutive channels of one pixel, one 8-byte LDS store.
+//
+// conv2 is C[pos][co] = sum_k col[pos][k] W2[k][co] with k = tap*16 + ci
+// (K = 144 padded to 160): a lane's eight k values are eight channels of one
+// a1 pixel, one 16-byte LDS read; the weights stay in registers for the
+// workgroup's lifetime.  Each lane then holds four consecutive positions of
+// one output channel, one 8-byte store into a2[b][co*256 + pos].
+#pragma once
+
+#include "policy_kernels.h"
+
+namespace aslam {
+namespace pol {
+
+using gemm::bf16x8;
+using gemm::f32x4;
+
+constexpr int kBlk = 33;                 // crop 2x2 blocks per row and column, plus the zero block -1
+constexpr int kA1Row = 33;               // a1 pixels per row and column, plus the zero pixel -1
+constexpr int kCropLds = kBlk * kBlk * 4;            // BF16 elements
+constexpr int kA1Lds = kA1Row * kA1Row * kC1;        // BF16 elements
+
+__device__ __forceinline__ uint32_t pack_bf16x2(float lo, float hi) {
+  return (uint32_t)f2bf(lo) | ((uint32_t)f2bf(hi) << 16);
+}
+
+// conv1 weights as the A operand: lane supplies W'[co = lane % 16][k = 8 (lane / 16) + j].
+__device__ __forceinline__ bf16x8 conv1_weight_frag(const float* w1, int lr, int lg) {
+  uint16_t v[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int k = 8 * lg + j;
+    const int r = k >> 3, c = (k >> 2) & 1, dy = (k >> 1) & 1, dx = k & 1;
+    const int ky = 2 * r + dy - 1, kx = 2 * c + dx - 1;
+    v[j] = (lg < 2 && ky >= 0 && kx >= 0) ? f2bf(w1[lr * 9 + ky * 3 + kx]) : (uint16_t)0;
+  }
+  uint4 u;
+  u.x = v[0] | ((uint32_t)v[1] << 16);
+  u.y = v[2] | ((uint32_t)v[3] << 16);
+  u.z = v[4] | ((uint32_t)v[5] << 16);
+  u.w = v[6] | ((uint32_t)v[7] << 16);
+  return __builtin_bit_cast(bf16x8, u);
+}
+
+// conv2 weights as the B operand: lane supplies W2[k = 32 s + 8 (lane / 16) + j][co], k = tap*16 + ci.
+__device__ __forceinline__ bf16x8 conv2_weight_frag(const float* w2, int co, int s, int lg) {
+  uint16_t v[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int k = 32 * s + 8 * lg + j, tap = k >> 4, ci = k & 15;
+    v[j] = tap < 9 ? f2bf(w2[(co * kC1 + ci) * 9 + tap]) : (uint16_t)0;
+  }
+  uint4 u;
+  u.x = v[0] | ((uint32_t)v[1] << 16);
+  u.y = v[2] | ((uint32_t)v[3] << 16);
+  u.z = v[4] | ((uint32_t)v[5] << 16);
+  u.w = v[6] | ((uint32_t)v[7] << 16);
+  return __builtin_bit_cast(bf16x8, u);
+}
+
+// One 64x64 int16 crop into LDS, space-to-depth, as BF16(L / 256).  Block
+// (Y, X) sits at ((Y + 1) * 33 + X + 1) * 4; the row and column of index 0
+// are the zero padding and are never written here.
+__device__ __forceinline__ void stage_crop(const int16_t* src, uint16_t* s_crop) {
+  for (int v = threadIdx.x; v < kCrop * kCrop / 8; v += blockDim.x) {
+    const int y = v >> 3, x0 = (v & 7) * 8;
+    const int4 raw = *reinterpret_cast<const int4*>(src + y * kCrop + x0);
+    const int32_t w[4] = {raw.x, raw.y, raw.z, raw.w};
+    const int Y = y >> 1, dy = y & 1;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const float lo = (float)(int16_t)(w[q] & 0xffff) * (1.0f / 256.0f);
+      const float hi = (float)(int16_t)(w[q] >> 16) * (1.0f / 256.0f);
+      const int X = (x0 >> 1) + q;
+      *reinterpret_cast<uint32_t*>(s_crop + ((Y + 1) * kBlk + X + 1) * 4 + 2 * dy) = pack_bf16x2(lo, hi);
+    }
+  }
+}
+
+// conv1 + ReLU of the staged crop into s_a1 (pixel (y, x) at ((y+1)*33 + x+1)*16).
+__device__ __forceinline__ void conv1_lds(const uint16_t* s_crop, uint16_t* s_a1, const bf16x8& w1f,
+                                          const float b1[4], int wave, int lr, int lg) {
+  for (int t = wave; t < kA1 * kA1 / 16; t += 4) {
+    const int px = t * 16 + lr, y = px >> 5, x = px & 31;
+    uint4 u = make_uint4(0u, 0u, 0u, 0u);
+    if (lg < 2) {
+      const uint16_t* q = s_crop + ((y + lg) * kBlk + x) * 4;
+      const uint2 a = *reinterpret_cast<const uint2*>(q);
+      const uint2 c = *reinterpret_cast<const uint2*>(q + 4);
+      u = make_uint4(a.x, a.y, c.x, c.y);
+    }
+    const f32x4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1f, __builtin_bit_cast(bf16x8, u),
+                                                             f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+    const uint32_t lo = pack_bf16x2(fmaxf(acc[0] + b1[0], 0.0f), fmaxf(acc[1] + b1[1], 0.0f));
+    const uint32_t hi = pack_bf16x2(fmaxf(acc[2] + b1[2], 0.0f), fmaxf(acc[3] + b1[3], 0.0f));
+    *reinterpret_cast<uint2*>(s_a1 + ((y + 1) * kA1Row + x + 1) * kC1 + 4 * lg) = make_uint2(lo, hi);
+  }
+}
+
+// conv2 A fragment: eight channels of the a1 pixel under tap (32 s + 8 lg) / 16 of position (oy, ox).
+__device__ __forceinline__ bf16x8 conv2_col_frag(const uint16_t* s_a1, int oy, int ox, int s, int lg) {
+  const int k0 = 32 * s + 8 * lg, tap = k0 >> 4, ci0 = k0 & 15;
+  uint4 u = make_uint4(0u, 0u, 0u, 0u);
+  if (tap < 9) {
+    const int yy = 2 * oy + tap / 3 - 1, xx = 2 * ox + tap % 3 - 1;
+    u = *reinterpret_cast<const uint4*>(s_a1 + ((yy + 1) * kA1Row + xx + 1) * kC1 + ci0);
+  }
+  return __builtin_bit_cast(bf16x8, u);
+}
+
+// Encoder forward: a2[b][co*256 + oy*16 + ox] = bf16(relu(conv2(relu(conv1(crop_b))))).
+__global__ __launch_bounds__(256) void k_conv_fwd(const float* prm, Offsets o, const int16_t* crop, uint16_t* a2,
+                                                  int B) {
+  __shared__ __align__(16) uint16_t s_crop[kCropLds];
+  __shared__ __align__(16) uint16_t s_a1[kA1Lds];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
+  {
+    uint4* z = reinterpret_cast<uint4*>(s_crop);
+    for (int i = threadIdx.x; i < kCropLds / 8; i += 256) z[i] = make_uint4(0u, 0u, 0u, 0u);
+    z = reinterpret_cast<uint4*>(s_a1);
+    for (int i = threadIdx.x; i < kA1Lds / 8; i += 256) z[i] = make_uint4(0u, 0u, 0u, 0u);
+  }
+  const bf16x8 w1f = conv1_weight_frag(prm + o.c1w, lr, lg);
+  float b1[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) b1[i] = prm[o.c1b + 4 * lg + i];
+  bf16x8 w2f[2][5];
+#pragma unroll
+  for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+    for (int s = 0; s < 5; ++s) w2f[nt][s] = conv2_weight_frag(prm + o.c2w, 16 * nt + lr, s, lg);
+  const float b2[2] = {prm[o.c2b + lr], prm[o.c2b + 16 + lr]};
+  __syncthreads();
+  for (int b = blockIdx.x; b < B; b += gridDim.x) {
+    stage_crop(crop + (int64_t)b * kCrop * kCrop, s_crop);
+    __syncthreads();
+    conv1_lds(s_crop, s_a1, w1f, b1, wave, lr, lg);
+    __syncthreads();
+    for (int oy = wave; oy < kA2; oy += 4) {
+      f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int s = 0; s < 5; ++s) {
+        const bf16x8 af = conv2_col_frag(s_a1, oy, lr, s, lg);
+        acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, w2f[0][s], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, w2f[1][s], acc1, 0, 0, 0);
+      }
+      uint16_t* dst = a2 + (int64_t)b * kFeat + oy * kA2 + 4 * lg;
+      *reinterpret_cast<uint2*>(dst + lr * 256) =
+          make_uint2(pack_bf16x2(fmaxf(acc0[0] + b2[0], 0.0f), fmaxf(acc0[1] + b2[0], 0.0f)),
+                     pack_bf16x2(fmaxf(acc0[2] + b2[0], 0.0f), fmaxf(acc0[3] + b2[0], 0.0f)));
+      *reinterpret_cast<uint2*>(dst + (16 + lr) * 256) =
+          make_uint2(pack_bf16x2(fmaxf(acc1[0] + b2[1], 0.0f), fmaxf(acc1[1] + b2[1], 0.0f)),
+                     pack_bf16x2(fmaxf(acc1[2] + b2[1], 0.0f), fmaxf(acc1[3] + b2[1], 0.0f)));
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace pol
+}  // namespace aslam
+
+namespace aslam {
+namespace pol {
+
+// ------------------------------------------------------------ encoder backward
+//
+// One kernel for everything below the FC1 input gradient, per sample b:
+//   conv1 is recomputed from the crop; with dz2 = dL/d(conv2 pre-activation)
+//   (BF16 [b][co][pos], already masked by conv2's ReLU),
+//   dW2[co][ci][tap] += sum_pos dz2[co][pos] a1[ci][pixel(pos, tap)]
+//   da1[ci][y][x]     = sum_{co, tap} W2[co][ci][tap] dz2[co][pos(y, x, tap)]
+//   dz1 = bf16(da1) * [a1 > 0]
+//   dW1[co][tap]     += sum_px dz1[co][px] in[pixel(px, tap)]
+//   db1 += sum dz1,  db2 += sum dz2.
+// The workgroup (8 waves) keeps its gradient sums over all its samples and
+// writes them once, as partials [gridDim.x][kConvPart], reduced afterwards in
+// a fixed order.
+//
+// LDS layouts (BF16):
+//   crop   space-to-depth, as in the forward kernel;
+//   a1x    [kx][ci][y+1][ox] = a1[ci][y][2 ox + kx - 1]: for a fixed tap, eight
+//          consecutive output columns are eight consecutive elements, so the
+//          im2col operand of the dW2 product is one 16-byte read; y = -1 and
+//          x = -1 are zero;
+//   dz     [oy][ox][co] over 17 x 17 positions, row and column 16 zero: the
+//          operand of the input-gradient product (eight channels of one
+//          position per read);
+//   dz1    [ci][y][x % 2][x / 2]: the operand of the dW1 product.
+// da1 is computed one sub-pixel phase (y % 2, x % 2) at a time: the input
+// pixels of a phase form a 16 x 16 grid that receives taps ky = 1 (y even) or
+// ky in {0, 2} (y odd), likewise kx, each from the output position
+// (qy + (py + 1 - ky) / 2, qx + (px + 1 - kx) / 2).  K = 32 channels per tap.
+constexpr int kConvPartW2 = kC2 * 144;          // [co][tap*16 + ci]
+constexpr int kConvPartW1 = kC1 * 16;           // [co][tap], taps padded to 16
+constexpr int kConvPart = kConvPartW2 + kConvPartW1 + kC1 + kC2;
+constexpr int kA1xRow = 16, kA1xRows = 33;
+constexpr int kA1xLds = 3 * kC1 * kA1xRows * kA1xRow;   // BF16 elements
+constexpr int kDzSide = 17;
+constexpr int kDzLds = kDzSide * kDzSide * kC2;
+constexpr int kDz1Lds = kC1 * kA1 * kA1;
+constexpr int kBwdThreads = 512;
+
+struct PhaseTaps {
+  int n;                 // taps of the phase (1, 2 or 4)
+  int ky[4], kx[4], dy[4], dx[4];
+};
+
+__device__ __forceinline__ PhaseTaps phase_taps(int py, int px) {
+  PhaseTaps t;
+  const int nky = py ? 2 : 1, nkx = px ? 2 : 1;
+  t.n = nky * nkx;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int iy = j / nkx, ix = j % nkx;
+    const int ky = py ? 2 * iy : 1, kx = px ? 2 * ix : 1;
+    t.ky[j] = ky; t.kx[j] = kx;
+    t.dy[j] = (py + 1 - ky) / 2; t.dx[j] = (px + 1 - kx) / 2;
+  }
+  return t;
+}
+
+// B operand of the phase product for k-step (phase, j): lane supplies
+// W2[co = 8 lg + e][ci = lr][ky_j][kx_j], e < 8.
+__device__ __forceinline__ bf16x8 phase_weight_frag(const float* w2, int ky, int kx, int lr, int lg) {
+  uint16_t v[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) v[e] = f2bf(w2[((8 * lg + e) * kC1 + lr) * 9 + ky * 3 + kx]);
+  uint4 u;
+  u.x = v[0] | ((uint32_t)v[1] << 16);
+  u.y = v[2] | ((uint32_t)v[3] << 16);
+  u.z = v[4] | ((uint32_t)v[5] << 16);
+  u.w = v[6] | ((uint32_t)v[7] << 16);
+  return __builtin_bit_cast(bf16x8, u);
+}
+
+// conv1 weights as the B operand of C[px][co] = sum_k P[px][k] W'[k][co]: lane supplies W'[k = 8 lg + j][co = lr].
+__device__ __forceinline__ bf16x8 conv1_weight_frag_b(const float* w1, int lr, int lg) {
+  return conv1_weight_frag(w1, lr, lg);   // same values: W'[k][co] read at co = lane % 16
+}
+
+__global__ __launch_bounds__(kBwdThreads) void k_conv_bwd(const float* prm, Offsets o, const int16_t* crop,
+                                                          const uint16_t* dz2c, int B, float* part) {
+  __shared__ __align__(16) uint16_t s_crop[kCropLds];
+  __shared__ __align__(16) uint16_t s_a1x[kA1xLds];
+  __shared__ __align__(16) uint16_t s_dz[kDzLds];
+  __shared__ __align__(16) uint16_t s_dz1[kDz1Lds];
+  __shared__ float s_red[8][kC1 * 16 + kC1 + kC2];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
+  {
+    uint4* z = reinterpret_cast<uint4*>(s_crop);
+    for (int i = threadIdx.x; i < kCropLds / 8; i += kBwdThreads) z[i] = make_uint4(0u, 0u, 0u, 0u);
+    z = reinterpret_cast<uint4*>(s_a1x);
+    for (int i = threadIdx.x; i < kA1xLds / 8; i += kBwdThreads) z[i] = make_uint4(0u, 0u, 0u, 0u);
+    z = reinterpret_cast<uint4*>(s_dz);
+    for (int i = threadIdx.x; i < kDzLds / 8; i += kBwdThreads) z[i] = make_uint4(0u, 0u, 0u, 0u);
+  }
+  // registers that live for the whole workgroup
+  const bf16x8 w1f = conv1_weight_frag_b(prm + o.c1w, lr, lg);
+  const float b1c = prm[o.c1b + lr];
+  // phase weights: this wave's qy rows are {wave, wave + 8}; all four phases, 9 k-steps
+  bf16x8 wph[9];
+  {
+    int q = 0;
+#pragma unroll
+    for (int ph = 0; ph < 4; ++ph) {
+      const PhaseTaps t = phase_taps(ph >> 1, ph & 1);
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (j < t.n) wph[q++] = phase_weight_frag(prm + o.c2w, t.ky[j], t.kx[j], lr, lg);
+    }
+  }
+  // accumulators: dW2 tiles (mt, nt) for nt = wave (all k-steps) and nt = 8 (k-step = wave)
+  f32x4 gw2[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) gw2[a][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+  f32x4 gw1 = {0.f, 0.f, 0.f, 0.f};
+  float gb1 = 0.0f, gb2[2] = {0.f, 0.f};
+  __syncthreads();
+
+  for (int b = blockIdx.x; b < B; b += gridDim.x) {
+    // ---- stage the crop and dz2 (transposed to [pos][co]); db2 from the same reads
+    stage_crop(crop + (int64_t)b * kCrop * kCrop, s_crop);
+    {
+      const uint4* src = reinterpret_cast<const uint4*>(dz2c + (int64_t)b * kFeat);
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+        const int v = threadIdx.x + r * kBwdThreads;   // vector of 8 positions of channel co
+        const int co = v >> 5, p0 = (v & 31) * 8;
+        const uint4 u = src[v];
+        const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+        float s = 0.0f;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const uint16_t h = (uint16_t)(w[e >> 1] >> ((e & 1) * 16));
+          s += bf2f(h);
+          const int p = p0 + e, oy = p >> 4, ox = p & 15;
+          s_dz[(oy * kDzSide + ox) * kC2 + co] = h;
+        }
+        gb2[r] += s;
+      }
+    }
+    __syncthreads();
+    // ---- conv1 recompute: C[px][co], lane gets pixels 16 t + 4 lg + i of channel lr
+    for (int t = wave; t < kA1 * kA1 / 16; t += 8) {
+      const int pxa = t * 16 + lr, ya = pxa >> 5, xa = pxa & 31;
+      uint4 u = make_uint4(0u, 0u, 0u, 0u);
+      if (lg < 2) {
+        const uint16_t* q = s_crop + ((ya + lg) * kBlk + xa) * 4;
+        const uint2 a = *reinterpret_cast<const uint2*>(q);
+        const uint2 c = *reinterpret_cast<const uint2*>(q + 4);
+        u = make_uint4(a.x, a.y, c.x, c.y);
+      }
+      const f32x4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, u), w1f,
+                                                               f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+      const int px0 = t * 16 + 4 * lg, y = px0 >> 5, x0 = px0 & 31;   // x0 = 0 mod 4
+      uint16_t h[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) h[i] = f2bf(fmaxf(acc[i] + b1c, 0.0f));
+      uint16_t* row = s_a1x + (lr * kA1xRows + y + 1) * kA1xRow;    // kx plane 0
+      const int plane = kC1 * kA1xRows * kA1xRow;
+      // even x -> kx = 1 at ox = x / 2; odd x -> kx = 0 at (x + 1) / 2 and kx = 2 at (x - 1) / 2
+      *reinterpret_cast<uint32_t*>(row + plane + (x0 >> 1)) = (uint32_t)h[0] | ((uint32_t)h[2] << 16);
+      *reinterpret_cast<uint32_t*>(row + 2 * plane + (x0 >> 1)) = (uint32_t)h[1] | ((uint32_t)h[3] << 16);
+      row[(x0 >> 1) + 1] = h[1];
+      if ((x0 >> 1) + 2 < kA1xRow) row[(x0 >> 1) + 2] = h[3];
+    }
+    __syncthreads();
+    // ---- dW2: tiles (mt, nt = wave) over all 8 position k-steps, and (mt, nt = 8) at k-step = wave
+    {
+      const uint16_t* dzg = dz2c + (int64_t)b * kFeat;
+#pragma unroll
+      for (int u = 0; u < 9; ++u) {
+        const int nt = u < 8 ? wave : 8;
+        const int ks = u < 8 ? u : wave;
+        const int slot = u < 8 ? 0 : 1;
+        const int p0 = 32 * ks + 8 * lg, oy = p0 >> 4, ox0 = p0 & 15;
+        const int ky = nt / 3, kx = nt % 3;
+        const int yy = 2 * oy + ky - 1;
+        const bf16x8 bf = __builtin_bit_cast(
+            bf16x8, *reinterpret_cast<const uint4*>(s_a1x + ((kx * kC1 + lr) * kA1xRows + yy + 1) * kA1xRow + ox0));
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt) {
+          const bf16x8 af = __builtin_bit_cast(
+              bf16x8, *reinterpret_cast<const uint4*>(dzg + (16 * mt + lr) * 256 + p0));
+          gw2[slot][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bf, gw2[slot][mt], 0, 0, 0);
+        }
+      }
+    }
+    // ---- da1 by phases -> dz1 (masked, BF16) into s_dz1; db1
+    {
+      int q = 0;
+#pragma unroll
+      for (int ph = 0; ph < 4; ++ph) {
+        const int py = ph >> 1, px = ph & 1;
+        const PhaseTaps t = phase_taps(py, px);
+#pragma unroll
+        for (int rr = 0; rr < 2; ++rr) {
+          const int qy = wave + 8 * rr;
+          f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            if (j >= t.n) break;
+            const int oy = qy + t.dy[j], ox = lr + t.dx[j];
+            const bf16x8 af = __builtin_bit_cast(
+                bf16x8, *reinterpret_cast<const uint4*>(s_dz + (oy * kDzSide + ox) * kC2 + 8 * lg));
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, wph[q + j], acc, 0, 0, 0);
+          }
+          // lane: input pixels (2 qy + py, 2 (4 lg + i) + px), channel lr
+          const int y = 2 * qy + py;
+          const uint2 m = *reinterpret_cast<const uint2*>(
+              s_a1x + (((1 + px) * kC1 + lr) * kA1xRows + y + 1) * kA1xRow + 4 * lg);
+          const uint32_t mw[2] = {m.x, m.y};
+          uint16_t d[4];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const uint16_t a = (uint16_t)(mw[i >> 1] >> ((i & 1) * 16));
+            d[i] = bf2f(a) > 0.0f ? f2bf(acc[i]) : (uint16_t)0;
+            gb1 += bf2f(d[i]);
+          }
+          *reinterpret_cast<uint2*>(s_dz1 + (lr * kA1 + y) * kA1 + px * 16 + 4 * lg) =
+              make_uint2((uint32_t)d[0] | ((uint32_t)d[1] << 16), (uint32_t)d[2] | ((uint32_t)d[3] << 16));
+        }
+        q += t.n;
+      }
+    }
+    __syncthreads();
+    // ---- dW1: C[co][tap] = sum_kappa dz1[co][kappa] in(kappa, tap), kappa = y*32 + par*16 + xh; 4 k-steps per wave
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int ks = wave * 4 + r;
+      const int k0 = 32 * ks + 8 * lg;
+      const bf16x8 af = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(s_dz1 + lr * 1024 + k0));
+      // B: lane supplies in[(y, x = 2 (xh0 + e) + par), tap = lr] for e < 8
+      const int y = k0 >> 5, par = (k0 >> 4) & 1, xh0 = k0 & 15;
+      const int ky = lr / 3, kx = lr % 3;
+      uint16_t v[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int row = 2 * y + ky - 1, col = 2 * (2 * (xh0 + e) + par) + kx - 1;   // in [-1, 63]
+        const int Y = row >> 1, X = col >> 1;
+        v[e] = lr < 9 ? s_crop[((Y + 1) * kBlk + X + 1) * 4 + 2 * (row & 1) + (col & 1)] : (uint16_t)0;
+      }
+      uint4 u;
+      u.x = v[0] | ((uint32_t)v[1] << 16);
+      u.y = v[2] | ((uint32_t)v[3] << 16);
+      u.z = v[4] | ((uint32_t)v[5] << 16);
+      u.w = v[6] | ((uint32_t)v[7] << 16);
+      gw1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, __builtin_bit_cast(bf16x8, u), gw1, 0, 0, 0);
+    }
+    __syncthreads();
+  }
+
+  // ---- write the workgroup's partial sums (fixed order everywhere)
+  float* out = part + (int64_t)blockIdx.x * kConvPart;
+  // dW2 [co][nt*16 + ci]: tile (mt, nt) lane value C[4 lg + i][lr] = (co = 16 mt + 4 lg + i, ci = lr)
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) out[(16 * mt + 4 * lg + i) * 144 + wave * 16 + lr] = gw2[0][mt][i];
+  // nt = 8: sum of the eight waves' k-step partials, in wave order
+  float* red = &s_red[0][0];
+  constexpr int kRedW = kC1 * 16 + kC1 + kC2;
+  (void)red;
+  __syncthreads();
+  {
+    // stage nt = 8 partials of this wave through the (now free) dz1 buffer as floats
+    float* st8 = reinterpret_cast<float*>(s_dz1);   // [8 waves][32 co][16 ci]
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) st8[(wave * 32 + 16 * mt + 4 * lg + i) * 16 + lr] = gw2[1][mt][i];
+    // dW1 tile: C[4 lg + i][lr] = (co = 4 lg + i, tap = lr); db1 per lane (ci = lr); db2 per thread
+#pragma unroll
+    for (int i = 0; i < 4; ++i) s_red[wave][(4 * lg + i) * 16 + lr] = gw1[i];
+  }
+  __syncthreads();
+  {
+    float* st8 = reinterpret_cast<float*>(s_dz1);
+    for (int e = threadIdx.x; e < 32 * 16; e += kBwdThreads) {
+      float s = 0.0f;
+      for (int w = 0; w < 8; ++w) s += st8[w * 512 + e];
+      out[(e >> 4) * 144 + 128 + (e & 15)] = s;
+    }
+    for (int e = threadIdx.x; e < kC1 * 16; e += kBwdThreads) {
+      float s = 0.0f;
+      for (int w = 0; w < 8; ++w) s += s_red[w][e];
+      out[kConvPartW2 + e] = s;
+    }
+  }
+  __syncthreads();
+  {
+    // db1: lane lr of each wave holds a channel-lr sum; db2: thread t holds channels t / 32 and t / 32 + 16
+    float* st = reinterpret_cast<float*>(s_dz1);
+    st[threadIdx.x] = gb1;
+    st[kBwdThreads + threadIdx.x] = gb2[0];
+    st[2 * kBwdThreads + threadIdx.x] = gb2[1];
+    __syncthreads();
+    if (threadIdx.x < kC1) {
+      float s = 0.0f;
+      for (int t = 0; t < kBwdThreads; ++t)
+        if ((t & 15) == threadIdx.x) s += st[t];
+      out[kConvPartW2 + kConvPartW1 + threadIdx.x] = s;
+    } else if (threadIdx.x >= 64 && threadIdx.x < 64 + kC2) {
+      const int co = threadIdx.x - 64, r = co >> 4, t0 = (co & 15) * 32;
+      float s = 0.0f;
+      for (int t = t0; t < t0 + 32; ++t) s += st[(1 + r) * kBwdThreads + t];
+      out[kConvPartW2 + kConvPartW1 + kC1 + co] = s;
+    }
+  }
+  (void)kRedW;
+}
+
+}  // namespace pol
+}  // namespace aslam

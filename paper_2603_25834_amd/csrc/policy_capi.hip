@@ -10,6 +10,7 @@
 
 #include "aslam.h"
 #include "policy_kernels.h"
+#include "conv_fused.h"
 
 using namespace aslam;
 using namespace aslam::pol;
@@ -30,26 +31,35 @@ struct aslam_policy {
   aslam_policy_config cfg{};
   Offsets off{};
   int64_t max_b = 0;
-  uint16_t *a1 = nullptr, *a2 = nullptr, *h1 = nullptr, *dz2 = nullptr, *dz1 = nullptr, *dz2c = nullptr,
-           *dz1c = nullptr;
-  float *z2 = nullptr, *part = nullptr, *hpart = nullptr;
+  uint16_t *a2 = nullptr, *h1 = nullptr, *dz2 = nullptr, *dz1 = nullptr, *dz2c = nullptr;
+  float *z2 = nullptr, *part = nullptr, *hpart = nullptr, *hsum = nullptr;
+  uint16_t *w1b = nullptr, *w1t = nullptr, *w2b = nullptr, *w2t = nullptr;   // BF16 weight copies
+  int32_t k1p = 0;   // FC1 input width padded to a multiple of 8
   int64_t part_floats = 0;
 };
 
 namespace {
 
-constexpr int kBiasBlocks = 256;
+constexpr int kConvGrid = 2048;    // workgroups of the fused encoder forward (each loops over samples)
+constexpr int kConvBwdGrid = 256;  // encoder backward: one 8-wave workgroup per CU (LDS-bound)
+constexpr int64_t kFc1Splits = 4, kFc2Splits = 64;
 
 int64_t splits_for(int64_t K, int64_t min_chunk, int64_t max_splits) {
   return std::max<int64_t>(1, std::min<int64_t>(max_splits, K / min_chunk));
 }
 
+// Number of K slices gemm::run launches for `splits` requested splits (chunks rounded up to BK).
+int slices_used(int64_t K, int64_t splits, int BK) {
+  int64_t chunk = (K + splits - 1) / splits;
+  chunk = (chunk + BK - 1) / BK * BK;
+  return (int)((K + chunk - 1) / chunk);
+}
+
 int64_t part_need(const aslam_policy* p) {
   const int64_t k1 = p->off.k1;
-  int64_t need = 4 * 256 * k1;                               // FC1 weight, up to 4 splits
-  need = std::max<int64_t>(need, 64LL * kHid * kHid);        // FC2 weight, up to 64 splits
-  need = std::max<int64_t>(need, 512LL * kC2 * 144);         // conv2 weight, up to 512 splits
-  need = std::max<int64_t>(need, 1024LL * 16 * 16);          // conv1 weight, up to 1024 splits
+  int64_t need = kFc1Splits * 256 * k1;                      // FC1 weight partials
+  need = std::max<int64_t>(need, kFc2Splits * kHid * kHid);   // FC2 weight partials
+  need = std::max<int64_t>(need, (int64_t)kConvBwdGrid * kConvPart);   // encoder backward partials
   need = std::max<int64_t>(need, (int64_t)kBiasBlocks * 256);
   return need;
 }
@@ -60,21 +70,31 @@ int64_t part_need(const aslam_policy* p) {
     if (e_ != hipSuccess) return pfail(ASL_EHIP, hipGetErrorString(e_)); \
   } while (0)
 
+// Forward to the FC2 pre-activation z2 (FP32); need_transposed also prepares the transposed BF16
+// weights that the backward's input gradients read.
 int forward_core(aslam_policy* P, const float* prm, const int16_t* crop, const float* scan, const float* state,
-                 int B, hipStream_t st) {
+                 int B, hipStream_t st, bool need_transposed) {
   const Offsets& o = P->off;
   const int R = P->cfg.n_scan;
-  k_conv1<<<std::min(B, 4096), 256, 0, st>>>(prm, o, crop, P->a1, B);
+  // BF16 weight copies: W1 (rows padded), W2, and the transposes the backward's input gradients read
+  k_convert_bf16<<<1024, 256, 0, st>>>(prm + o.f1w, o.k1, kHid, o.k1, P->w1b, P->k1p);
   PCHK(hipGetLastError());
-  // conv2 as an implicit GEMM: [B*256 x 144] x [144 x 32]
-  PCHK((gemm::run<128, 32, 4, 1, 1>(LdIm2colK{P->a1, B * 256}, LdW2K{prm + o.c2w},
-                                    EpiConv2{P->a2, prm + o.c2b}, B * 256, kC2, 144, 1, st)));
+  k_convert_bf16<<<256, 256, 0, st>>>(prm + o.f2w, kHid, kHid, kHid, P->w2b, kHid);
+  PCHK(hipGetLastError());
+  if (need_transposed) {
+    k_transpose_bf16<<<dim3(kFeat / 32, kHid / 32), 256, 0, st>>>(prm + o.f1w, o.k1, kHid, kFeat, P->w1t, kHid);
+    PCHK(hipGetLastError());
+    k_transpose_bf16<<<dim3(kHid / 32, kHid / 32), 256, 0, st>>>(prm + o.f2w, kHid, kHid, kHid, P->w2t, kHid);
+    PCHK(hipGetLastError());
+  }
+  k_conv_fwd<<<std::min(B, kConvGrid), 256, 0, st>>>(prm, o, crop, P->a2, B);
+  PCHK(hipGetLastError());
   // FC1: [B x k1] x [k1 x 256]
   XSrc xs{P->a2, scan, state, R, B, o.k1};
-  PCHK((gemm::run<128, 128, 2, 2, 1>(LdXK{xs}, LdF32K{prm + o.f1w, o.k1, kHid, o.k1},
+  PCHK((gemm::run<128, 128, 128, 2, 2>(LdXK{xs}, LdBF16K{P->w1b, P->k1p, kHid, o.k1},
                                      EpiBiasReluBF16{P->h1, prm + o.f1b, kHid}, B, kHid, o.k1, 1, st)));
   // FC2 pre-activation (FP32): [B x 256] x [256 x 256]
-  PCHK((gemm::run<128, 128, 2, 2, 1>(LdBF16K{P->h1, kHid, B, kHid}, LdF32K{prm + o.f2w, kHid, kHid, kHid},
+  PCHK((gemm::run<128, 128, 64, 2, 2>(LdBF16K{P->h1, kHid, B, kHid}, LdBF16K{P->w2b, kHid, kHid, kHid},
                                      EpiBiasF32{P->z2, prm + o.f2b, kHid}, B, kHid, kHid, 1, st)));
   return ASL_OK;
 }
@@ -100,13 +120,16 @@ int aslam_policy_create(const aslam_policy_config* cfg, aslam_policy** out) {
   p->max_b = cfg->max_batch;
   const int64_t Bm = p->max_b;
   p->part_floats = part_need(p);
+  p->k1p = (p->off.k1 + 7) / 8 * 8;
   struct A { void** ptr; size_t bytes; } al[] = {
-      {(void**)&p->a1, 2 * (size_t)Bm * kA1 * kA1 * kC1}, {(void**)&p->a2, 2 * (size_t)Bm * kFeat},
-      {(void**)&p->h1, 2 * (size_t)Bm * kHid},            {(void**)&p->dz2, 2 * (size_t)Bm * kHid},
-      {(void**)&p->dz1, 2 * (size_t)Bm * kHid},           {(void**)&p->dz2c, 2 * (size_t)Bm * kFeat},
-      {(void**)&p->dz1c, 2 * (size_t)Bm * kA1 * kA1 * kC1}, {(void**)&p->z2, 4 * (size_t)Bm * kHid},
+      {(void**)&p->a2, 2 * (size_t)Bm * kFeat},  {(void**)&p->h1, 2 * (size_t)Bm * kHid},
+      {(void**)&p->dz2, 2 * (size_t)Bm * kHid},  {(void**)&p->dz1, 2 * (size_t)Bm * kHid},
+      {(void**)&p->dz2c, 2 * (size_t)Bm * kFeat}, {(void**)&p->z2, 4 * (size_t)Bm * kHid},
       {(void**)&p->part, 4 * (size_t)p->part_floats},
       {(void**)&p->hpart, 4 * (size_t)((Bm + kHeadRows - 1) / kHeadRows) * kHeadPart},
+      {(void**)&p->hsum, 4 * (size_t)kHeadPart},
+      {(void**)&p->w1b, 2 * (size_t)kHid * ((p->off.k1 + 7) / 8 * 8)}, {(void**)&p->w1t, 2 * (size_t)kFeat * kHid},
+      {(void**)&p->w2b, 2 * (size_t)kHid * kHid},                        {(void**)&p->w2t, 2 * (size_t)kHid * kHid},
   };
   for (auto& a : al) {
     if (hipMalloc(a.ptr, a.bytes) != hipSuccess) {
@@ -120,7 +143,8 @@ int aslam_policy_create(const aslam_policy_config* cfg, aslam_policy** out) {
 
 int aslam_policy_destroy(aslam_policy* p) {
   if (!p) return pfail(ASL_EINVAL, "policy is NULL");
-  void* ptrs[] = {p->a1, p->a2, p->h1, p->dz2, p->dz1, p->dz2c, p->dz1c, p->z2, p->part, p->hpart};
+  void* ptrs[] = {p->a2, p->h1, p->dz2, p->dz1, p->dz2c, p->z2, p->part, p->hpart, p->hsum,
+                  p->w1b, p->w1t, p->w2b, p->w2t};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   delete p;
@@ -132,7 +156,7 @@ int aslam_policy_forward(aslam_policy* P, const float* params, const int16_t* cr
   if (!P || !params || !crop || !scan || !state || !mu || !value) return pfail(ASL_EINVAL, "null argument");
   if (batch < 1 || batch > P->max_b) return pfail(ASL_EINVAL, "batch must be in [1, max_batch]");
   hipStream_t st = (hipStream_t)stream;
-  int rc = forward_core(P, params, crop, scan, state, batch, st);
+  int rc = forward_core(P, params, crop, scan, state, batch, st, false);
   if (rc) return rc;
   const int nb = (batch + kHeadRows - 1) / kHeadRows;
   k_heads<false><<<nb, 256, 0, st>>>(params, P->off, P->z2, batch, mu, value, nullptr, nullptr, nullptr, nullptr,
@@ -151,7 +175,7 @@ int aslam_policy_backward(aslam_policy* P, const float* params, const int16_t* c
   const Offsets& o = P->off;
   const int B = batch;
   const int R = P->cfg.n_scan;
-  int rc = forward_core(P, params, crop, scan, state, B, st);
+  int rc = forward_core(P, params, crop, scan, state, B, st, true);
   if (rc) return rc;
   // heads + loss -> dz2, head / fc2-bias / log-std partial sums
   const int nb = (B + kHeadRows - 1) / kHeadRows;
@@ -159,83 +183,73 @@ int aslam_policy_backward(aslam_policy* P, const float* params, const int16_t* c
   k_heads<true><<<nb, 256, 0, st>>>(params, o, P->z2, B, nullptr, nullptr, act, old_logp, adv, ret, lc, P->dz2,
                                     P->hpart);
   PCHK(hipGetLastError());
-  k_reduce_heads<<<1, 256, 0, st>>>(P->hpart, nb, grads, o, loss, P->cfg.c_entropy, P->cfg.c_value);
+  PCHK(launch_reduce(P->hpart, nb, kHeadPart, P->hsum, 3, kHeadPart, st));
+  k_scatter_heads<<<1, 256, 0, st>>>(P->hsum, grads, o, loss, P->cfg.c_entropy);
   PCHK(hipGetLastError());
   k_loss_total<<<1, 1, 0, st>>>(params, o, loss, P->cfg.c_value, P->cfg.c_entropy);
   PCHK(hipGetLastError());
   float* part = P->part;
   // FC2 weight: dW2[out][in] = sum_b dz2[b][out] h1[b][in]
   {
-    const int64_t S = splits_for(B, 256, 64);
-    const int64_t chunk = ((B + S - 1) / S + 31) / 32 * 32;
-    const int S_used = (int)((B + chunk - 1) / chunk);
-    PCHK((gemm::run<128, 128, 2, 2, 1>(LdBF16I{P->dz2, kHid, kHid, B}, LdBF16I{P->h1, kHid, kHid, B},
+    const int64_t S = splits_for(B, 256, kFc2Splits);
+    const int S_used = slices_used(B, S, 64);
+    PCHK((gemm::run<128, 128, 64, 2, 2>(LdBF16I{P->dz2, kHid, kHid, B}, LdBF16I{P->h1, kHid, kHid, B},
                                        EpiPartial{part, kHid, (int64_t)kHid * kHid}, kHid, kHid, B, (int)S, st)));
-    k_reduce<<<256, 256, 0, st>>>(part, S_used, (int64_t)kHid * kHid, grads + o.f2w, 0, (int64_t)kHid * kHid);
-    PCHK(hipGetLastError());
+    PCHK(launch_reduce(part, S_used, (int64_t)kHid * kHid, grads + o.f2w, 0, (int64_t)kHid * kHid, st));
   }
   // dh1 -> dz1 = (dz2 W2) * [h1 > 0]
-  PCHK((gemm::run<128, 128, 2, 2, 1>(LdBF16K{P->dz2, kHid, B, kHid}, LdF32I{params + o.f2w, kHid, kHid, kHid},
+  PCHK((gemm::run<128, 128, 64, 2, 2>(LdBF16K{P->dz2, kHid, B, kHid}, LdBF16K{P->w2t, kHid, kHid, kHid},
                                      EpiReluGradBF16{P->dz1, P->h1, kHid}, B, kHid, kHid, 1, st)));
   // FC1 bias
   k_bias_rows<<<kBiasBlocks, 256, 0, st>>>(P->dz1, B, kHid, part);
   PCHK(hipGetLastError());
-  k_reduce<<<1, 256, 0, st>>>(part, kBiasBlocks, kHid, grads + o.f1b, 0, kHid);
-  PCHK(hipGetLastError());
+  PCHK(launch_reduce(part, kBiasBlocks, kHid, grads + o.f1b, 0, kHid, st));
   // FC1 weight: dW1[out][k] = sum_b dz1[b][out] X[b][k]
   XSrc xs{P->a2, scan, state, R, B, o.k1};
   {
-    const int64_t S = splits_for(B, 4096, 4);
-    const int64_t chunk = ((B + S - 1) / S + 31) / 32 * 32;
-    const int S_used = (int)((B + chunk - 1) / chunk);
-    PCHK((gemm::run<128, 128, 2, 2, 1>(LdBF16I{P->dz1, kHid, kHid, B}, LdXI{xs},
+    const int64_t S = splits_for(B, 2048, kFc1Splits);
+    const int S_used = slices_used(B, S, 64);
+    PCHK((gemm::run<128, 128, 64, 2, 2>(LdBF16I{P->dz1, kHid, kHid, B}, LdXI{xs},
                                        EpiPartial{part, o.k1, (int64_t)kHid * o.k1}, kHid, o.k1, B, (int)S, st)));
-    k_reduce<<<1024, 256, 0, st>>>(part, S_used, (int64_t)kHid * o.k1, grads + o.f1w, 0, (int64_t)kHid * o.k1);
-    PCHK(hipGetLastError());
+    PCHK(launch_reduce(part, S_used, (int64_t)kHid * o.k1, grads + o.f1w, 0, (int64_t)kHid * o.k1, st));
   }
   // dA2 -> dz2c = (dz1 W1[:, :8192]) * [a2 > 0]
-  PCHK((gemm::run<128, 128, 2, 2, 1>(LdBF16K{P->dz1, kHid, B, kHid}, LdF32I{params + o.f1w, o.k1, kFeat, kHid},
+  PCHK((gemm::run<128, 128, 64, 2, 2>(LdBF16K{P->dz1, kHid, B, kHid}, LdBF16K{P->w1t, kHid, kFeat, kHid},
                                      EpiReluGradBF16{P->dz2c, P->a2, kFeat}, B, kFeat, kHid, 1, st)));
-  // conv2 bias
-  k_bias_c2<<<kBiasBlocks, 256, 0, st>>>(P->dz2c, B, part);
-  PCHK(hipGetLastError());
-  k_reduce<<<1, 64, 0, st>>>(part, kBiasBlocks, kC2, grads + o.c2b, 0, kC2);
-  PCHK(hipGetLastError());
-  // conv2 weight: dW2c[co][tap*16+ci] = sum_{b,p} dz2c[b][co][p] im2col(a1)[b,p][tap*16+ci]
+  // encoder: conv2 / conv1 weight and bias gradients in one pass over the minibatch
   {
-    const int64_t K = (int64_t)B * 256;
-    const int64_t S = splits_for(K, 8192, 512);
-    const int64_t chunk = ((K + S - 1) / S + 31) / 32 * 32;
-    const int S_used = (int)((K + chunk - 1) / chunk);
-    PCHK((gemm::run<32, 160, 2, 2, 1>(LdDz2cK{P->dz2c, (int)K}, LdIm2colI{P->a1, (int)K},
-                                      EpiPartial{part, 144, (int64_t)kC2 * 144}, kC2, 144, (int)K, (int)S, st)));
-    k_reduce<<<18, 256, 0, st>>>(part, S_used, (int64_t)kC2 * 144, grads + o.c2w, 1, (int64_t)kC2 * 144);
+    const int grid = std::min(B, kConvBwdGrid);
+    k_conv_bwd<<<grid, kBwdThreads, 0, st>>>(params, o, crop, P->dz2c, B, part);
     PCHK(hipGetLastError());
+    PCHK(launch_reduce(part, grid, kConvPartW2, grads + o.c2w, 1, kConvPart, st));
+    PCHK(launch_reduce(part + kConvPartW2, grid, kConvPartW1, grads + o.c1w, 2, kConvPart, st));
+    PCHK(launch_reduce(part + kConvPartW2 + kConvPartW1, grid, kC1, grads + o.c1b, 0, kConvPart, st));
+    PCHK(launch_reduce(part + kConvPartW2 + kConvPartW1 + kC1, grid, kC2, grads + o.c2b, 0, kConvPart, st));
   }
-  // conv2 input gradient, one sub-pixel phase at a time -> dz1c = da1 * [a1 > 0]
-  for (int ry = 0; ry < 2; ++ry)
-    for (int rx = 0; rx < 2; ++rx) {
-      const Phase ph = make_phase(ry, rx);
-      PCHK((gemm::run<128, 16, 4, 1, 1>(LdPhaseA{P->dz2c, B * 256, ph}, LdPhaseB{params + o.c2w, ph},
-                                        EpiPhase{P->dz1c, P->a1, ry, rx}, B * 256, kC1, 32 * ph.nty * ph.ntx, 1,
-                                        st)));
-    }
-  // conv1 bias
-  k_bias_rows<<<kBiasBlocks, 256, 0, st>>>(P->dz1c, (int64_t)B * kA1 * kA1, kC1, part);
+  return ASL_OK;
+}
+
+int aslam_policy_sample(aslam_policy* P, const float* params, const float* mu, const float* eps, int32_t batch,
+                        float* act, float* logp, aslam_stream_t stream) {
+  if (!P || !params || !mu || !eps || !act || !logp) return pfail(ASL_EINVAL, "null argument");
+  if (batch < 1) return pfail(ASL_EINVAL, "batch must be >= 1");
+  k_sample<<<(batch + 255) / 256, 256, 0, (hipStream_t)stream>>>(params, P->off, mu, eps, batch, act, logp);
   PCHK(hipGetLastError());
-  k_reduce<<<1, 64, 0, st>>>(part, kBiasBlocks, kC1, grads + o.c1b, 0, kC1);
+  return ASL_OK;
+}
+
+int aslam_gather_rows(const void* src, int64_t row_bytes, const int32_t* idx, int32_t n, void* dst,
+                      aslam_stream_t stream) {
+  if (!src || !idx || !dst) return pfail(ASL_EINVAL, "null argument");
+  if (n < 0 || row_bytes < 4 || (row_bytes & 3)) return pfail(ASL_EINVAL, "row_bytes must be a positive multiple of 4");
+  if (((uintptr_t)src & 3) || ((uintptr_t)dst & 3)) return pfail(ASL_EINVAL, "src and dst must be 4-byte aligned");
+  if (n == 0) return ASL_OK;
+  const int vec = ((row_bytes & 15) == 0 && ((uintptr_t)src & 15) == 0 && ((uintptr_t)dst & 15) == 0) ? 1 : 0;
+  const int64_t items = vec ? (int64_t)n * (row_bytes >> 4) : (int64_t)n * (row_bytes >> 2);
+  const int blocks = (int)std::min<int64_t>(8192, (items + 255) / 256);
+  k_gather_rows<<<blocks, 256, 0, (hipStream_t)stream>>>(static_cast<const uint32_t*>(src), row_bytes >> 2, idx, n,
+                                                         static_cast<uint32_t*>(dst), vec);
   PCHK(hipGetLastError());
-  // conv1 weight: dW1c[co][tap] = sum_{b,y,x} dz1c[b][y][x][co] in(b, 2y+ky-1, 2x+kx-1)
-  {
-    const int64_t K = (int64_t)B * kA1 * kA1;
-    const int64_t S = splits_for(K, 16384, 1024);
-    const int64_t chunk = ((K + S - 1) / S + 31) / 32 * 32;
-    const int S_used = (int)((K + chunk - 1) / chunk);
-    PCHK((gemm::run<16, 16, 1, 1, 4>(LdDz1cI{P->dz1c, (int)K}, LdCropTapK{crop, (int)K},
-                                     EpiPartial{part, 16, 256}, kC1, 16, (int)K, (int)S, st)));
-    k_reduce<<<1, 256, 0, st>>>(part, S_used, 256, grads + o.c1w, 2, 256);
-    PCHK(hipGetLastError());
-  }
   return ASL_OK;
 }
 

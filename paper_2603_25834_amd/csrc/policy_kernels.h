@@ -16,6 +16,7 @@
 // Backward recomputes the forward activations of the minibatch (only the
 // inputs are kept across the rollout); weight gradients are formed by split-K
 // GEMMs whose partial sums are reduced in a fixed order (deterministic).
+#pragma once
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -61,29 +62,23 @@ inline Offsets offsets(int32_t n_scan) {
 
 // ------------------------------------------------------------------ loaders
 
-__device__ __forceinline__ void zero8(uint16_t v[8]) {
-#pragma unroll
-  for (int j = 0; j < 8; ++j) v[j] = 0;
-}
-
-__device__ __forceinline__ void unpack8(const uint4 w, uint16_t v[8]) {
-  v[0] = w.x & 0xffff; v[1] = w.x >> 16; v[2] = w.y & 0xffff; v[3] = w.y >> 16;
-  v[4] = w.z & 0xffff; v[5] = w.z >> 16; v[6] = w.w & 0xffff; v[7] = w.w >> 16;
+__device__ __forceinline__ uint4 pack8(const uint16_t v[8]) {
+  return make_uint4(v[0] | ((uint32_t)v[1] << 16), v[2] | ((uint32_t)v[3] << 16), v[4] | ((uint32_t)v[5] << 16),
+                    v[6] | ((uint32_t)v[7] << 16));
 }
 
 // BF16 matrix, element (i, k) at p[i*ld + k]; contiguous along k.
 struct LdBF16K {
   static constexpr bool kMajor = true;
   const uint16_t* p; int64_t ld; int rows, cols;
-  __device__ void fetch(int i, int k, uint16_t v[8]) const {
-    if (i >= rows || k >= cols) { zero8(v); return; }
+  __device__ uint4 fetch(int i, int k) const {
+    if (i >= rows || k >= cols) return make_uint4(0u, 0u, 0u, 0u);
     const uint16_t* q = p + (int64_t)i * ld + k;
-    if (k + 8 <= cols && ((reinterpret_cast<uintptr_t>(q) & 15) == 0)) {
-      unpack8(*reinterpret_cast<const uint4*>(q), v);
-    } else {
+    if (k + 8 <= cols && ((reinterpret_cast<uintptr_t>(q) & 15) == 0)) return *reinterpret_cast<const uint4*>(q);
+    uint16_t v[8];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) v[j] = (k + j < cols) ? q[j] : (uint16_t)0;
-    }
+    for (int j = 0; j < 8; ++j) v[j] = (k + j < cols) ? q[j] : (uint16_t)0;
+    return pack8(v);
   }
 };
 
@@ -91,46 +86,14 @@ struct LdBF16K {
 struct LdBF16I {
   static constexpr bool kMajor = false;
   const uint16_t* p; int64_t ld; int rows, cols;
-  __device__ void fetch(int i, int k, uint16_t v[8]) const {
-    if (i >= rows || k >= cols) { zero8(v); return; }
+  __device__ uint4 fetch(int i, int k) const {
+    if (i >= rows || k >= cols) return make_uint4(0u, 0u, 0u, 0u);
     const uint16_t* q = p + (int64_t)k * ld + i;
-    if (i + 8 <= rows && ((reinterpret_cast<uintptr_t>(q) & 15) == 0)) {
-      unpack8(*reinterpret_cast<const uint4*>(q), v);
-    } else {
+    if (i + 8 <= rows && ((reinterpret_cast<uintptr_t>(q) & 15) == 0)) return *reinterpret_cast<const uint4*>(q);
+    uint16_t v[8];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) v[j] = (i + j < rows) ? q[j] : (uint16_t)0;
-    }
-  }
-};
-
-// FP32 matrix rounded to BF16 on load, element (i, k) at p[i*ld + k].
-struct LdF32K {
-  static constexpr bool kMajor = true;
-  const float* p; int64_t ld; int rows, cols;
-  __device__ void fetch(int i, int k, uint16_t v[8]) const {
-    if (i >= rows || k >= cols) { zero8(v); return; }
-    const float* q = p + (int64_t)i * ld + k;
-    if (k + 8 <= cols && ((reinterpret_cast<uintptr_t>(q) & 15) == 0)) {
-      const float4 a = *reinterpret_cast<const float4*>(q);
-      const float4 b = *reinterpret_cast<const float4*>(q + 4);
-      v[0] = f2bf(a.x); v[1] = f2bf(a.y); v[2] = f2bf(a.z); v[3] = f2bf(a.w);
-      v[4] = f2bf(b.x); v[5] = f2bf(b.y); v[6] = f2bf(b.z); v[7] = f2bf(b.w);
-    } else {
-#pragma unroll
-      for (int j = 0; j < 8; ++j) v[j] = (k + j < cols) ? f2bf(q[j]) : (uint16_t)0;
-    }
-  }
-};
-
-// FP32 matrix rounded to BF16 on load, element (i, k) at p[k*ld + i].
-struct LdF32I {
-  static constexpr bool kMajor = false;
-  const float* p; int64_t ld; int rows, cols;
-  __device__ void fetch(int i, int k, uint16_t v[8]) const {
-    if (i >= rows || k >= cols) { zero8(v); return; }
-    const float* q = p + (int64_t)k * ld + i;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) v[j] = (i + j < rows) ? f2bf(q[j]) : (uint16_t)0;
+    for (int j = 0; j < 8; ++j) v[j] = (i + j < rows) ? q[j] : (uint16_t)0;
+    return pack8(v);
   }
 };
 
@@ -149,14 +112,13 @@ struct XSrc {
 struct LdXK {
   static constexpr bool kMajor = true;
   XSrc x;
-  __device__ void fetch(int i, int k, uint16_t v[8]) const {
-    if (i >= x.B) { zero8(v); return; }
-    if (k + 8 <= kFeat) {
-      unpack8(*reinterpret_cast<const uint4*>(x.a2 + (int64_t)i * kFeat + k), v);
-    } else {
+  __device__ uint4 fetch(int i, int k) const {
+    if (i >= x.B) return make_uint4(0u, 0u, 0u, 0u);
+    if (k + 8 <= kFeat) return *reinterpret_cast<const uint4*>(x.a2 + (int64_t)i * kFeat + k);
+    uint16_t v[8];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) v[j] = x.at(i, k + j);
-    }
+    for (int j = 0; j < 8; ++j) v[j] = x.at(i, k + j);
+    return pack8(v);
   }
 };
 
@@ -164,249 +126,81 @@ struct LdXK {
 struct LdXI {
   static constexpr bool kMajor = false;
   XSrc x;
-  __device__ void fetch(int i, int k, uint16_t v[8]) const {
-    if (k >= x.B || i >= x.k1) { zero8(v); return; }
-    if (i + 8 <= kFeat) {
-      unpack8(*reinterpret_cast<const uint4*>(x.a2 + (int64_t)k * kFeat + i), v);
-    } else {
+  __device__ uint4 fetch(int i, int k) const {
+    if (k >= x.B || i >= x.k1) return make_uint4(0u, 0u, 0u, 0u);
+    if (i + 8 <= kFeat) return *reinterpret_cast<const uint4*>(x.a2 + (int64_t)k * kFeat + i);
+    uint16_t v[8];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) v[j] = x.at(k, i + j);
-    }
-  }
-};
-
-// conv2 input as im2col rows: A(m = b*256 + p, k = tap*16 + ci) from a1 [b][32][32][16] (BF16).
-struct LdIm2colK {
-  static constexpr bool kMajor = true;
-  const uint16_t* a1; int M;
-  __device__ void fetch(int m, int k, uint16_t v[8]) const {
-    const int tap = k >> 4, ci0 = k & 15;
-    if (m >= M || tap >= 9) { zero8(v); return; }
-    const int b = m >> 8, p = m & 255;
-    const int y = 2 * (p >> 4) + tap / 3 - 1, x = 2 * (p & 15) + tap % 3 - 1;
-    if (y < 0 || y >= kA1 || x < 0 || x >= kA1) { zero8(v); return; }
-    unpack8(*reinterpret_cast<const uint4*>(a1 + (((int64_t)b * kA1 + y) * kA1 + x) * kC1 + ci0), v);
-  }
-};
-
-// conv2 weights as B(k = tap*16 + ci, n = co) = W2[co][ci][tap] (FP32 params -> BF16).
-struct LdW2K {
-  static constexpr bool kMajor = true;
-  const float* w;  // [32][16][9]
-  __device__ void fetch(int co, int k, uint16_t v[8]) const {
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int kk = k + j, tap = kk >> 4, ci = kk & 15;
-      v[j] = (co < kC2 && tap < 9) ? f2bf(w[(co * kC1 + ci) * 9 + tap]) : (uint16_t)0;
-    }
-  }
-};
-
-// conv2 weight gradient: A(m = co, k = b*256 + p) = dz2c[b][co*256 + p] (contiguous along k).
-struct LdDz2cK {
-  static constexpr bool kMajor = true;
-  const uint16_t* d; int K;
-  __device__ void fetch(int co, int k, uint16_t v[8]) const {
-    if (co >= kC2 || k >= K) { zero8(v); return; }
-    const int b = k >> 8, p = k & 255;
-    unpack8(*reinterpret_cast<const uint4*>(d + (int64_t)b * kFeat + co * 256 + p), v);
-  }
-};
-
-// conv2 weight gradient: B(k = b*256 + p, n = tap*16 + ci) = im2col(a1), contiguous along n.
-struct LdIm2colI {
-  static constexpr bool kMajor = false;
-  const uint16_t* a1; int K;
-  __device__ void fetch(int n, int k, uint16_t v[8]) const {
-    const int tap = n >> 4, ci0 = n & 15;
-    if (k >= K || tap >= 9) { zero8(v); return; }
-    const int b = k >> 8, p = k & 255;
-    const int y = 2 * (p >> 4) + tap / 3 - 1, x = 2 * (p & 15) + tap % 3 - 1;
-    if (y < 0 || y >= kA1 || x < 0 || x >= kA1) { zero8(v); return; }
-    unpack8(*reinterpret_cast<const uint4*>(a1 + (((int64_t)b * kA1 + y) * kA1 + x) * kC1 + ci0), v);
-  }
-};
-
-// Input gradient of conv2 for one sub-pixel phase (ry, rx) of the 32x32 grid:
-// input pixel (2qy+ry, 2qx+rx) receives tap (ky, kx) of output pixel
-// (qy + (ry+1-ky)/2, qx + (rx+1-kx)/2) when ky = ry+1 (mod 2) and kx = rx+1 (mod 2).
-struct Phase {
-  int ry, rx, nty, ntx;
-  int ky[2], kx[2];
-};
-
-__host__ __device__ inline Phase make_phase(int ry, int rx) {
-  Phase ph;
-  ph.ry = ry; ph.rx = rx;
-  if (ry == 0) { ph.nty = 1; ph.ky[0] = 1; ph.ky[1] = 1; } else { ph.nty = 2; ph.ky[0] = 0; ph.ky[1] = 2; }
-  if (rx == 0) { ph.ntx = 1; ph.kx[0] = 1; ph.kx[1] = 1; } else { ph.ntx = 2; ph.kx[0] = 0; ph.kx[1] = 2; }
-  return ph;
-}
-
-// A(m = b*256 + qy*16 + qx, k = j*32 + co) = dz2c[b][co][py][px] for the phase's tap j.
-struct LdPhaseA {
-  static constexpr bool kMajor = false;
-  const uint16_t* d; int M; Phase ph;
-  __device__ void fetch(int m, int k, uint16_t v[8]) const {
-    const int j = k >> 5, co = k & 31;
-    if (m >= M || j >= ph.nty * ph.ntx) { zero8(v); return; }
-    const int ky = ph.ky[j / ph.ntx], kx = ph.kx[j % ph.ntx];
-    const int b = m >> 8, qy = (m >> 4) & 15, qx0 = m & 15;
-    const int py = qy + (ph.ry + 1 - ky) / 2;
-    const int dx = (ph.rx + 1 - kx) / 2;
-    const uint16_t* row = d + (int64_t)b * kFeat + co * 256 + py * 16;
-#pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      const int px = qx0 + t + dx;
-      v[t] = (py < kA2 && px < kA2) ? row[px] : (uint16_t)0;
-    }
-  }
-};
-
-// B(k = j*32 + co, n = ci) = W2[co][ci][ky_j][kx_j].
-struct LdPhaseB {
-  static constexpr bool kMajor = true;
-  const float* w; Phase ph;
-  __device__ void fetch(int ci, int k, uint16_t v[8]) const {
-#pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      const int kk = k + t, j = kk >> 5, co = kk & 31;
-      if (ci >= kC1 || j >= ph.nty * ph.ntx) { v[t] = 0; continue; }
-      const int ky = ph.ky[j / ph.ntx], kx = ph.kx[j % ph.ntx];
-      v[t] = f2bf(w[(co * kC1 + ci) * 9 + ky * 3 + kx]);
-    }
-  }
-};
-
-// conv1 weight gradient: A(m = co, k = b*1024 + y*32 + x) = dz1c[b][y][x][co] (contiguous along m).
-struct LdDz1cI {
-  static constexpr bool kMajor = false;
-  const uint16_t* d; int K;
-  __device__ void fetch(int co, int k, uint16_t v[8]) const {
-    if (k >= K || co >= kC1) { zero8(v); return; }
-    unpack8(*reinterpret_cast<const uint4*>(d + (int64_t)k * kC1 + co), v);
-  }
-};
-
-__device__ __forceinline__ uint16_t crop_in(const int16_t* crop, int b, int y, int x) {
-  if (y < 0 || y >= kCrop || x < 0 || x >= kCrop) return 0;
-  return f2bf((float)crop[((int64_t)b * kCrop + y) * kCrop + x] * (1.0f / 256.0f));
-}
-
-// conv1 weight gradient: B(k = b*1024 + y*32 + x, n = tap) = input (2y+ky-1, 2x+kx-1).
-struct LdCropTapK {
-  static constexpr bool kMajor = true;
-  const int16_t* crop; int K;
-  __device__ void fetch(int tap, int k, uint16_t v[8]) const {
-    if (tap >= 9) { zero8(v); return; }
-    const int ky = tap / 3, kx = tap % 3;
-#pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      const int kk = k + t;
-      if (kk >= K) { v[t] = 0; continue; }
-      const int b = kk >> 10, y = (kk >> 5) & 31, x = kk & 31;
-      v[t] = crop_in(crop, b, 2 * y + ky - 1, 2 * x + kx - 1);
-    }
+    for (int j = 0; j < 8; ++j) v[j] = x.at(k, i + j);
+    return pack8(v);
   }
 };
 
 // ---------------------------------------------------------------- epilogues
-
-struct EpiConv2 {  // a2[b][co*256 + p] = bf16(relu(v + bias))
-  uint16_t* a2; const float* bias;
-  __device__ void store(int m, int n, float v, bool ok) const {
-    if (!ok) return;
-    a2[(int64_t)(m >> 8) * kFeat + n * 256 + (m & 255)] = f2bf(fmaxf(v + bias[n], 0.0f));
-  }
-};
+// store8(m, n0, v, nvalid): row m, columns n0 .. n0 + nvalid - 1 (n0 multiple of 8).
 
 struct EpiBiasReluBF16 {
   uint16_t* out; const float* bias; int64_t ld;
-  __device__ void store(int m, int n, float v, bool ok) const {
-    if (ok) out[(int64_t)m * ld + n] = f2bf(fmaxf(v + bias[n], 0.0f));
+  __device__ void store8(int m, int n0, const float* v, int nvalid) const {
+    uint16_t h[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) h[j] = j < nvalid ? f2bf(fmaxf(v[j] + bias[n0 + j], 0.0f)) : (uint16_t)0;
+    uint16_t* q = out + (int64_t)m * ld + n0;
+    if (nvalid == 8 && ((reinterpret_cast<uintptr_t>(q) & 15) == 0)) {
+      *reinterpret_cast<uint4*>(q) = pack8(h);
+    } else {
+      for (int j = 0; j < nvalid; ++j) q[j] = h[j];
+    }
   }
 };
 
 struct EpiBiasF32 {
   float* out; const float* bias; int64_t ld;
-  __device__ void store(int m, int n, float v, bool ok) const {
-    if (ok) out[(int64_t)m * ld + n] = v + bias[n];
+  __device__ void store8(int m, int n0, const float* v, int nvalid) const {
+    float* q = out + (int64_t)m * ld + n0;
+    if (nvalid == 8 && ((reinterpret_cast<uintptr_t>(q) & 15) == 0)) {
+      *reinterpret_cast<float4*>(q) = make_float4(v[0] + bias[n0], v[1] + bias[n0 + 1], v[2] + bias[n0 + 2],
+                                                  v[3] + bias[n0 + 3]);
+      *reinterpret_cast<float4*>(q + 4) = make_float4(v[4] + bias[n0 + 4], v[5] + bias[n0 + 5],
+                                                      v[6] + bias[n0 + 6], v[7] + bias[n0 + 7]);
+    } else {
+      for (int j = 0; j < nvalid; ++j) q[j] = v[j] + bias[n0 + j];
+    }
   }
 };
 
 // Split-K partial sums: slice blockIdx.z of a [splits][M][N] FP32 buffer.
 struct EpiPartial {
   float* part; int64_t ld; int64_t slice;
-  __device__ void store(int m, int n, float v, bool ok) const {
-    if (ok) part[(int64_t)blockIdx.z * slice + (int64_t)m * ld + n] = v;
+  __device__ void store8(int m, int n0, const float* v, int nvalid) const {
+    float* q = part + (int64_t)blockIdx.z * slice + (int64_t)m * ld + n0;
+    if (nvalid == 8 && ((reinterpret_cast<uintptr_t>(q) & 15) == 0)) {
+      *reinterpret_cast<float4*>(q) = make_float4(v[0], v[1], v[2], v[3]);
+      *reinterpret_cast<float4*>(q + 4) = make_float4(v[4], v[5], v[6], v[7]);
+    } else {
+      for (int j = 0; j < nvalid; ++j) q[j] = v[j];
+    }
   }
 };
 
 // Gradient through a ReLU whose output (BF16) is `act`: out = bf16(act > 0 ? v : 0).
 struct EpiReluGradBF16 {
   uint16_t* out; const uint16_t* act; int64_t ld;
-  __device__ void store(int m, int n, float v, bool ok) const {
-    if (!ok) return;
-    const int64_t o = (int64_t)m * ld + n;
-    out[o] = bf2f(act[o]) > 0.0f ? f2bf(v) : (uint16_t)0;
-  }
-};
-
-// Input gradient of conv2 for one phase, masked by conv1's ReLU: dz1c[b][y][x][ci] (BF16).
-struct EpiPhase {
-  uint16_t* dz1c; const uint16_t* a1; int ry, rx;
-  __device__ void store(int m, int n, float v, bool ok) const {
-    if (!ok) return;
-    const int b = m >> 8, y = 2 * ((m >> 4) & 15) + ry, x = 2 * (m & 15) + rx;
-    const int64_t o = (((int64_t)b * kA1 + y) * kA1 + x) * kC1 + n;
-    dz1c[o] = bf2f(a1[o]) > 0.0f ? f2bf(v) : (uint16_t)0;
+  __device__ void store8(int m, int n0, const float* v, int nvalid) const {
+    const int64_t o = (int64_t)m * ld + n0;
+    if (nvalid == 8 && ((o & 7) == 0)) {
+      const uint4 a = *reinterpret_cast<const uint4*>(act + o);
+      uint16_t h[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) h[j] = bf2f(gemm::lane16(a, j)) > 0.0f ? f2bf(v[j]) : (uint16_t)0;
+      *reinterpret_cast<uint4*>(out + o) = pack8(h);
+    } else {
+      for (int j = 0; j < nvalid; ++j) out[o + j] = bf2f(act[o + j]) > 0.0f ? f2bf(v[j]) : (uint16_t)0;
+    }
   }
 };
 
 // ---------------------------------------------------------------- kernels
-
-// conv1 (1 -> 16, 3x3, stride 2, pad 1) + ReLU for one sample per workgroup:
-// a1[b][y][x][co] = bf16(relu(b1[co] + sum_tap bf16(w1[co][tap]) * bf16(L/256))).
-__global__ __launch_bounds__(256) void k_conv1(const float* prm, Offsets o, const int16_t* crop, uint16_t* a1,
-                                               int B) {
-  __shared__ float w[kC1 * 9];
-  __shared__ float bias[kC1];
-  __shared__ float in[kCrop * kCrop];
-  for (int i = threadIdx.x; i < kC1 * 9; i += 256) w[i] = bf2f(f2bf(prm[o.c1w + i]));
-  if (threadIdx.x < kC1) bias[threadIdx.x] = prm[o.c1b + threadIdx.x];
-  for (int b = blockIdx.x; b < B; b += gridDim.x) {
-    __syncthreads();
-    for (int i = threadIdx.x; i < kCrop * kCrop; i += 256)
-      in[i] = bf2f(f2bf((float)crop[(int64_t)b * kCrop * kCrop + i] * (1.0f / 256.0f)));
-    __syncthreads();
-    for (int px = threadIdx.x; px < kA1 * kA1; px += 256) {
-      const int y = px >> 5, x = px & 31;
-      float t[9];
-#pragma unroll
-      for (int ky = 0; ky < 3; ++ky)
-#pragma unroll
-        for (int kx = 0; kx < 3; ++kx) {
-          const int iy = 2 * y + ky - 1, ix = 2 * x + kx - 1;
-          t[ky * 3 + kx] = (iy >= 0 && iy < kCrop && ix >= 0 && ix < kCrop) ? in[iy * kCrop + ix] : 0.0f;
-        }
-      uint32_t packed[8];
-#pragma unroll
-      for (int c = 0; c < kC1; c += 2) {
-        float s0 = 0.0f, s1 = 0.0f;
-#pragma unroll
-        for (int k = 0; k < 9; ++k) {
-          s0 += w[c * 9 + k] * t[k];
-          s1 += w[(c + 1) * 9 + k] * t[k];
-        }
-        packed[c / 2] = (uint32_t)f2bf(fmaxf(s0 + bias[c], 0.0f)) |
-                        ((uint32_t)f2bf(fmaxf(s1 + bias[c + 1], 0.0f)) << 16);
-      }
-      uint4* dst = reinterpret_cast<uint4*>(a1 + ((int64_t)b * kA1 * kA1 + px) * kC1);
-      dst[0] = make_uint4(packed[0], packed[1], packed[2], packed[3]);
-      dst[1] = make_uint4(packed[4], packed[5], packed[6], packed[7]);
-    }
-  }
-}
 
 struct LossCoef {
   float eps, c_v, c_e, inv_b;
@@ -521,32 +315,100 @@ __global__ __launch_bounds__(256) void k_heads(const float* prm, Offsets o, cons
     part[(int64_t)blockIdx.x * kHeadPart + i] = acc[0][i] + acc[1][i] + acc[2][i] + acc[3][i];
 }
 
-// Sum of split-K partials [S][count] in a fixed order, added into dst[map(i)].
-// map: 0 identity; 1 conv2 weight (k' = tap*16 + ci -> ci*9 + tap within each co row of 144);
-//      2 conv1 weight (partial [16][16] tap-padded -> [16][9]).
-__global__ void k_reduce(const float* part, int S, int64_t count, float* dst, int map, int64_t slice) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x) {
-    float s = 0.0f;
-    for (int z = 0; z < S; ++z) s += part[(int64_t)z * slice + i];
-    int64_t d = i;
-    if (map == 1) {
-      const int co = (int)(i / 144), kk = (int)(i % 144), tap = kk >> 4, ci = kk & 15;
-      d = (int64_t)co * 144 + ci * 9 + tap;
-    } else if (map == 2) {
-      const int co = (int)(i / 16), tap = (int)(i % 16);
-      if (tap >= 9) continue;
-      d = (int64_t)co * 9 + tap;
+// Sum of split-K partials part[z * slice + i], z < S, in a fixed order, into
+// dst[map(i)].  A workgroup covers 4*CX consecutive outputs (CX groups of four)
+// and splits S over 256/CX lanes; each lane sums its share with four loads in
+// flight, then one lane per group adds the lanes' sums in lane order.
+// map: 0 identity (added), 3 identity (assigned), 1 conv2 weight
+// (k' = tap*16 + ci -> ci*9 + tap within each co row of 144), 2 conv1 weight
+// (partial [16][16] tap-padded -> [16][9]).
+constexpr int kReduceThreads = 256;
+
+__device__ __forceinline__ int64_t reduce_dst(int map, int64_t i, bool& skip) {
+  skip = false;
+  if (map == 1) {
+    const int co = (int)(i / 144), kk = (int)(i % 144), tap = kk >> 4, ci = kk & 15;
+    return (int64_t)co * 144 + ci * 9 + tap;
+  }
+  if (map == 2) {
+    const int co = (int)(i / 16), tap = (int)(i % 16);
+    skip = tap >= 9;
+    return (int64_t)co * 9 + tap;
+  }
+  return i;
+}
+
+__global__ __launch_bounds__(kReduceThreads) void k_reduce(const float* part, int S, int64_t count, float* dst,
+                                                           int map, int64_t slice, int cx_log2) {
+  __shared__ float4 red[kReduceThreads];
+  const int CX = 1 << cx_log2, LY = kReduceThreads >> cx_log2;
+  const int cx = threadIdx.x & (CX - 1), ly = threadIdx.x >> cx_log2;
+  const int64_t i0 = ((int64_t)blockIdx.x * CX + cx) * 4;
+  float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (i0 < count) {
+    if (i0 + 3 < count && (slice & 3) == 0) {
+      int z = ly;
+      for (; z + 3 * LY < S; z += 4 * LY) {
+        const float4 v0 = *reinterpret_cast<const float4*>(part + (int64_t)z * slice + i0);
+        const float4 v1 = *reinterpret_cast<const float4*>(part + (int64_t)(z + LY) * slice + i0);
+        const float4 v2 = *reinterpret_cast<const float4*>(part + (int64_t)(z + 2 * LY) * slice + i0);
+        const float4 v3 = *reinterpret_cast<const float4*>(part + (int64_t)(z + 3 * LY) * slice + i0);
+        acc.x += v0.x; acc.y += v0.y; acc.z += v0.z; acc.w += v0.w;
+        acc.x += v1.x; acc.y += v1.y; acc.z += v1.z; acc.w += v1.w;
+        acc.x += v2.x; acc.y += v2.y; acc.z += v2.z; acc.w += v2.w;
+        acc.x += v3.x; acc.y += v3.y; acc.z += v3.z; acc.w += v3.w;
+      }
+      for (; z < S; z += LY) {
+        const float4 v = *reinterpret_cast<const float4*>(part + (int64_t)z * slice + i0);
+        acc.x += v.x; acc.y += v.y; acc.z += v.z; acc.w += v.w;
+      }
+    } else {
+      for (int z = ly; z < S; z += LY) {
+        const float* q = part + (int64_t)z * slice + i0;
+        acc.x += q[0];
+        if (i0 + 1 < count) acc.y += q[1];
+        if (i0 + 2 < count) acc.z += q[2];
+        if (i0 + 3 < count) acc.w += q[3];
+      }
     }
-    dst[d] += s;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  if (ly == 0 && i0 < count) {
+    float4 t = red[cx];
+    for (int y = 1; y < LY; ++y) {
+      const float4 v = red[y * CX + cx];
+      t.x += v.x; t.y += v.y; t.z += v.z; t.w += v.w;
+    }
+    const float tv[4] = {t.x, t.y, t.z, t.w};
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int64_t i = i0 + e;
+      if (i >= count) break;
+      bool skip;
+      const int64_t d = reduce_dst(map, i, skip);
+      if (skip) continue;
+      if (map == 3) dst[d] = tv[e];
+      else dst[d] += tv[e];
+    }
   }
 }
 
-// Head partials [nb][kHeadPart] -> gradient vector and loss terms.
-__global__ void k_reduce_heads(const float* part, int nb, float* grad, Offsets o, float* loss, float c_e,
-                               float c_v) {
+// Launch helper: outputs in groups of four, S split over the remaining lanes.
+inline hipError_t launch_reduce(const float* part, int S, int64_t count, float* dst, int map, int64_t slice,
+                                hipStream_t st) {
+  int cx_log2 = 4;   // 16 groups x 16 lanes
+  const int64_t groups = (count + 3) / 4;
+  while (cx_log2 > 0 && (1LL << (cx_log2 - 1)) >= groups) --cx_log2;
+  const int64_t blocks = (groups + (1LL << cx_log2) - 1) >> cx_log2;
+  k_reduce<<<(unsigned)blocks, kReduceThreads, 0, st>>>(part, S, count, dst, map, slice, cx_log2);
+  return hipGetLastError();
+}
+
+// Head sums [kHeadPart] -> gradient vector and loss terms.
+__global__ void k_scatter_heads(const float* hs, float* grad, Offsets o, float* loss, float c_e) {
   for (int i = threadIdx.x; i < kHeadPart; i += blockDim.x) {
-    float s = 0.0f;
-    for (int z = 0; z < nb; ++z) s += part[(int64_t)z * kHeadPart + i];
+    const float s = hs[i];
     if (i < 512) grad[o.muw + i] += s;
     else if (i < 514) grad[o.mub + (i - 512)] += s;
     else if (i < 770) grad[o.vw + (i - 514)] += s;
@@ -564,41 +426,104 @@ __global__ void k_loss_total(const float* prm, Offsets o, float* loss, float c_v
   loss[0] = loss[1] + c_v * loss[2] - c_e * h;
 }
 
-// Bias gradients: column sums of a BF16 [rows][ch] tensor (ch divides 256)
-// into per-block partials [gridDim.x][ch]; thread t always sees channel t % ch.
-__global__ __launch_bounds__(256) void k_bias_rows(const uint16_t* src, int64_t rows, int ch, float* part) {
-  __shared__ float sacc[256];
-  const int64_t total = rows * ch;
-  const int64_t per = ((total + gridDim.x - 1) / gridDim.x + 255) / 256 * 256;
-  const int64_t beg = (int64_t)blockIdx.x * per, end = min(total, beg + per);
-  float s = 0.0f;
-  for (int64_t i = beg + threadIdx.x; i < end; i += 256) s += bf2f(src[i]);
-  sacc[threadIdx.x] = s;
-  __syncthreads();
-  if (threadIdx.x < ch) {  // fixed summation order: deterministic
-    float t = 0.0f;
-    for (int j = threadIdx.x; j < 256; j += ch) t += sacc[j];
-    part[(int64_t)blockIdx.x * ch + threadIdx.x] = t;
+// Bias gradients: column sums of a BF16 [rows][ch] tensor (ch divides 2048,
+// rows * ch a multiple of 8) into per-block partials [gridDim.x][ch].  Thread t
+// reads the 16-byte vectors t, t + 256, ... of its block's range; 256 vectors
+// span 2048 elements, so a thread always sees the same eight channels.  Four
+// loads are kept in flight; every sum is taken in a fixed order.
+constexpr int kBiasBlocks = 512;
+
+__device__ __forceinline__ void add_bf16x8(float* a, const uint4& v) {
+  const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    a[2 * j] += __uint_as_float(w[j] << 16);
+    a[2 * j + 1] += __uint_as_float(w[j] & 0xffff0000u);
   }
 }
 
-// conv2 bias gradient: sums of dz2c[b][co][p] over b and p; thread t owns co = t / 8.
-__global__ __launch_bounds__(256) void k_bias_c2(const uint16_t* dz2c, int B, float* part) {
-  __shared__ float sacc[256];
-  const int co = threadIdx.x >> 3, sub = threadIdx.x & 7;
-  const int per = (B + gridDim.x - 1) / gridDim.x;
-  const int b0 = blockIdx.x * per, b1 = min(B, b0 + per);
-  float s = 0.0f;
-  for (int b = b0; b < b1; ++b) {
-    const uint16_t* row = dz2c + (int64_t)b * kFeat + co * 256;
-    for (int p = sub; p < 256; p += 8) s += bf2f(row[p]);
+__global__ __launch_bounds__(256) void k_bias_rows(const uint16_t* src, int64_t rows, int ch, float* part) {
+  __shared__ float sacc[256 * 8];
+  const int64_t nvec = rows * ch / 8;
+  const int64_t per = ((nvec + gridDim.x - 1) / gridDim.x + 255) / 256 * 256;
+  const int64_t beg = (int64_t)blockIdx.x * per, end = min(nvec, beg + per);
+  const uint4* s4 = reinterpret_cast<const uint4*>(src);
+  float a[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  int64_t i = beg + threadIdx.x;
+  for (; i + 3 * 256 < end; i += 4 * 256) {
+    const uint4 v0 = s4[i], v1 = s4[i + 256], v2 = s4[i + 512], v3 = s4[i + 768];
+    add_bf16x8(a, v0);
+    add_bf16x8(a, v1);
+    add_bf16x8(a, v2);
+    add_bf16x8(a, v3);
   }
-  sacc[threadIdx.x] = s;
+  for (; i < end; i += 256) add_bf16x8(a, s4[i]);
+#pragma unroll
+  for (int j = 0; j < 8; ++j) sacc[threadIdx.x * 8 + j] = a[j];
   __syncthreads();
-  if (threadIdx.x < kC2) {  // fixed summation order: deterministic
+  if (threadIdx.x < ch) {
+    const int c = threadIdx.x, step = ch / 8;
     float t = 0.0f;
-    for (int j = 0; j < 8; ++j) t += sacc[threadIdx.x * 8 + j];
-    part[(int64_t)blockIdx.x * kC2 + threadIdx.x] = t;
+    for (int tt = (c >> 3); tt < 256; tt += step) t += sacc[tt * 8 + (c & 7)];
+    part[(int64_t)blockIdx.x * ch + c] = t;
+  }
+}
+
+// BF16 copies of FP32 weight matrices for the GEMMs (rounded to nearest even).
+// k_convert_bf16: dst[r][c] = bf16(src[r][c]) for c < cols, 0 for cols <= c < ld_dst.
+__global__ void k_convert_bf16(const float* src, int64_t ld_src, int rows, int cols, uint16_t* dst,
+                               int64_t ld_dst) {
+  const int64_t total = (int64_t)rows * ld_dst;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = i / ld_dst, c = i - r * ld_dst;
+    dst[i] = c < cols ? f2bf(src[r * ld_src + c]) : (uint16_t)0;
+  }
+}
+
+// k_transpose_bf16: dst[c][r] = bf16(src[r][c]) through 32 x 32 LDS tiles (256 threads).
+__global__ __launch_bounds__(256) void k_transpose_bf16(const float* src, int64_t ld_src, int rows, int cols,
+                                                        uint16_t* dst, int64_t ld_dst) {
+  __shared__ float tile[32][33];
+  const int c0 = blockIdx.x * 32, r0 = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int k = ty; k < 32; k += 8) {
+    const int r = r0 + k, c = c0 + tx;
+    tile[k][tx] = (r < rows && c < cols) ? src[(int64_t)r * ld_src + c] : 0.0f;
+  }
+  __syncthreads();
+  for (int k = ty; k < 32; k += 8) {
+    const int c = c0 + k, r = r0 + tx;
+    if (c < cols && r < rows) dst[(int64_t)c * ld_dst + r] = f2bf(tile[tx][k]);
+  }
+}
+
+// Gaussian action sampling: act = mu + exp(log_std) eps, logp = log N(act; mu, exp(log_std)).
+__global__ void k_sample(const float* prm, Offsets o, const float* mu, const float* eps, int B, float* act,
+                         float* logp) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  const float ls0 = prm[o.lstd], ls1 = prm[o.lstd + 1];
+  const float e0 = eps[2 * (int64_t)b], e1 = eps[2 * (int64_t)b + 1];
+  act[2 * (int64_t)b] = mu[2 * (int64_t)b] + expf(ls0) * e0;
+  act[2 * (int64_t)b + 1] = mu[2 * (int64_t)b + 1] + expf(ls1) * e1;
+  logp[b] = -0.5f * (e0 * e0 + e1 * e1) - (ls0 + ls1) - 1.8378770664093453f;
+}
+
+// dst row i = src row idx[i]; rows of `words` 32-bit words, 16-byte vectors when `vec`.
+__global__ void k_gather_rows(const uint32_t* src, int64_t words, const int32_t* idx, int n, uint32_t* dst,
+                              int vec) {
+  const int64_t total = vec ? (int64_t)n * (words >> 2) : (int64_t)n * words;
+  const int64_t per = vec ? (words >> 2) : words;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = i / per, c = i - r * per;
+    const int64_t s = idx[r];
+    if (vec) {
+      reinterpret_cast<uint4*>(dst)[r * per + c] = reinterpret_cast<const uint4*>(src)[s * per + c];
+    } else {
+      dst[r * per + c] = src[s * per + c];
+    }
   }
 }
 

@@ -75,6 +75,28 @@ class Policy:
         return loss
 
 
+    def sample(self, params, mu, eps, act=None, logp=None):
+        """act = mu + exp(log_std) eps and its log-density; eps are standard normals [B, 2]."""
+        B = mu.shape[0]
+        assert mu.dtype == torch.float32 and tuple(mu.shape) == (B, 2) and tuple(eps.shape) == (B, 2)
+        act = torch.empty_like(mu) if act is None else act
+        logp = torch.empty(B, device=mu.device) if logp is None else logp
+        check(lib().aslam_policy_sample(self.h, _p(params), _p(mu), _p(eps), B, _p(act), _p(logp), _stream()))
+        return act, logp
+
+
+def gather_rows(src, idx, out=None):
+    """out[i] = src[idx[i]] along dim 0 (rows of any dtype; row bytes a multiple of 4)."""
+    assert idx.dtype == torch.int32 and idx.is_cuda
+    n = idx.numel()
+    out = torch.empty((n,) + tuple(src.shape[1:]), dtype=src.dtype, device=src.device) if out is None else out
+    if n == 0:
+        return out
+    row_bytes = src[0].numel() * src.element_size()
+    check(lib().aslam_gather_rows(_p(src), row_bytes, _p(idx), n, _p(out), _stream()))
+    return out
+
+
 def gae(rewards, values, dones, last_value, gamma=0.99, lam=0.95):
     T, N = rewards.shape
     adv = torch.empty_like(rewards)

@@ -1,0 +1,116 @@
+"""PPO training iteration over the batched environment (rollout + update), on the library's kernels.
+
+Method: arXiv 2603.25834 Sec. III-F (PPO with the clipped surrogate of Eqs. 18-20 and GAE) driving the
+batched POMDP step of Sec. III-B.  One iteration:
+
+  rollout, t = 0 .. T-1:  observe (scan, pose + covariance, 64x64 belief crop) -> policy forward
+      (mean, value) -> Gaussian action sample -> env step (reward, done) -> masked reset of the
+      robots whose episode ended;
+  bootstrap value of the last observation; GAE over the [T, N] rollout;
+  update: `epochs` passes over the T*N samples in shuffled minibatches: row gather -> fused loss and
+      gradient (activations recomputed from the stored inputs) -> Adam.
+
+Every stage runs in the library's kernels; torch provides device memory, the stream and two
+`zero_()` fills (the gradient accumulator).  Random draws (odometry noise, action noise, minibatch
+permutations) are passed in, so an iteration is deterministic given its inputs.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from .policy import Policy, adam, gae, gather_rows
+
+
+class PPOTrainer:
+    def __init__(self, env, world: torch.Tensor, start: torch.Tensor, params: torch.Tensor, T: int = 24,
+                 epochs: int = 4, minibatch: int = 16384, lr: float = 3e-4, gamma: float = 0.99, lam: float = 0.95,
+                 seed: int = 0, crop: int = 64):
+        self.env, self.world, self.start = env, world, start
+        self.n, self.R = env.n, env.R
+        self.T, self.epochs = T, epochs
+        self.S = T * self.n
+        self.n_mb = max(1, -(-self.S // minibatch))
+        self.mb = -(-self.S // self.n_mb)              # equal minibatches of at most `minibatch`
+        self.lr, self.gamma, self.lam = lr, gamma, lam
+        dev = params.device
+        self.policy = Policy(self.R, max_batch=max(self.mb, self.n))
+        self.params = params
+        self.grads = torch.zeros_like(params)
+        self.m = torch.zeros_like(params)
+        self.v = torch.zeros_like(params)
+        self.step_count = 0
+        T, n, R = self.T, self.n, self.R
+        # rollout storage (time-major)
+        self.crop = torch.zeros((T + 1, n, crop, crop), dtype=torch.int16, device=dev)
+        self.scan = torch.zeros((T + 1, n, R), device=dev)
+        self.state = torch.zeros((T + 1, n, 12), device=dev)
+        self.mu = torch.zeros((n, 2), device=dev)
+        self.act = torch.zeros((T, n, 2), device=dev)
+        self.logp = torch.zeros((T, n), device=dev)
+        self.value = torch.zeros((T + 1, n), device=dev)
+        self.reward = torch.zeros((T, n), device=dev)
+        self.done = torch.zeros((T, n), dtype=torch.uint8, device=dev)
+        self.ranges = torch.zeros((n, R), device=dev)
+        # minibatch storage
+        mb = self.mb
+        self.mb_crop = torch.zeros((mb, crop, crop), dtype=torch.int16, device=dev)
+        self.mb_scan = torch.zeros((mb, R), device=dev)
+        self.mb_state = torch.zeros((mb, 12), device=dev)
+        self.mb_act = torch.zeros((mb, 2), device=dev)
+        self.mb_logp = torch.zeros(mb, device=dev)
+        self.mb_adv = torch.zeros(mb, device=dev)
+        self.mb_ret = torch.zeros(mb, device=dev)
+        self.loss = torch.zeros(4, device=dev)
+
+    def draws(self, iterations: int, seed: int):
+        """Seeded synthetic randomness for `iterations` iterations: odometry noise [I,T,n,5], action noise
+        [I,T,n,2] and one permutation of the T*n samples per epoch [I,epochs,T*n] (int32)."""
+        rng = np.random.default_rng([seed, 77])
+        I, T, n = iterations, self.T, self.n
+        dev = self.params.device
+        noise = torch.from_numpy(rng.standard_normal((I, T, n, 5), dtype=np.float32)).to(dev)
+        eps = torch.from_numpy(rng.standard_normal((I, T, n, 2), dtype=np.float32)).to(dev)
+        perm = np.stack([np.stack([rng.permutation(self.S) for _ in range(self.epochs)]) for _ in range(I)])
+        return noise, eps, torch.from_numpy(perm.astype(np.int32)).to(dev)
+
+    def iteration(self, noise: torch.Tensor, eps: torch.Tensor, perm: torch.Tensor) -> None:
+        """One rollout of T steps and `epochs` update passes (all launches on the current stream)."""
+        env, pol, p = self.env, self.policy, self.params
+        for t in range(self.T):
+            env.observe(self.ranges, self.crop[t], self.scan[t], self.state[t])
+            pol.forward(p, self.crop[t], self.scan[t], self.state[t], self.mu, self.value[t])
+            pol.sample(p, self.mu, eps[t], self.act[t], self.logp[t])
+            env.step(self.act[t], noise[t], self.ranges, self.reward[t], self.done[t])
+            env.reset(self.world, self.start, mask=self.done[t])
+        env.observe(self.ranges, self.crop[self.T], self.scan[self.T], self.state[self.T])
+        pol.forward(p, self.crop[self.T], self.scan[self.T], self.state[self.T], self.mu, self.value[self.T])
+        adv, ret = gae(self.reward, self.value[:self.T].contiguous(), self.done, self.value[self.T],
+                       self.gamma, self.lam)
+        flat = {
+            "crop": self.crop[:self.T].reshape(self.S, *self.crop.shape[2:]),
+            "scan": self.scan[:self.T].reshape(self.S, self.R),
+            "state": self.state[:self.T].reshape(self.S, 12),
+            "act": self.act.reshape(self.S, 2),
+            "logp": self.logp.reshape(self.S),
+            "adv": adv.reshape(self.S),
+            "ret": ret.reshape(self.S),
+        }
+        for e in range(self.epochs):
+            for k in range(self.n_mb):
+                lo = k * self.mb
+                idx = perm[e, lo:min(self.S, lo + self.mb)]
+                b = idx.numel()
+                mbs = {}
+                for name, dst in (("crop", self.mb_crop), ("scan", self.mb_scan), ("state", self.mb_state),
+                                  ("act", self.mb_act), ("logp", self.mb_logp), ("adv", self.mb_adv),
+                                  ("ret", self.mb_ret)):
+                    src = flat[name] if flat[name].dim() > 1 else flat[name].view(-1, 1)
+                    out = dst[:b] if dst.dim() > 1 else dst[:b].view(-1, 1)
+                    gather_rows(src, idx, out)
+                    mbs[name] = dst[:b]
+                self.grads.zero_()
+                pol.backward(p, mbs["crop"], mbs["scan"], mbs["state"], mbs["act"], mbs["logp"], mbs["adv"],
+                             mbs["ret"], self.grads, self.loss)
+                self.step_count += 1
+                adam(p, self.grads, self.m, self.v, self.step_count, lr=self.lr)

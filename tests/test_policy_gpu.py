@@ -75,6 +75,13 @@ def test_forward_matches_fp64(B):
     ev = np.linalg.norm(value.cpu().double().numpy() - vr.numpy()) / np.linalg.norm(vr.numpy())
     say(f"[policy] forward rel err mu {em:.2e} value {ev:.2e}")
     assert em < 2e-2 and ev < 2e-2
+    # same rounding points as the workload-precision reference: only FP32 summation order differs
+    with torch.no_grad():
+        mb, _, vb = PR.forward_bf16(torch.from_numpy(theta).double(), t["crop"], t["scan"], t["state"], SHAPE)
+    eb = max(np.linalg.norm(mu.cpu().double().numpy() - mb.numpy()) / np.linalg.norm(mb.numpy()),
+             np.linalg.norm(value.cpu().double().numpy() - vb.numpy()) / np.linalg.norm(vb.numpy()))
+    say(f"[policy] forward rel err vs workload precision {eb:.2e}")
+    assert eb < 2e-3
 
 
 def _coherent_case(B, seed):
@@ -224,3 +231,28 @@ def test_autograd_function_and_errors():
     small = Policy(R, max_batch=8)
     with pytest.raises(_lib.AslamError):
         small.forward(params, dev["crop"], dev["scan"], dev["state"])
+
+
+def test_sample_and_gather():
+    """Gaussian sampling vs the FP64 log-density; row gather vs plain indexing."""
+    from paper_2603_25834_amd.policy import Policy, gather_rows
+    theta = synth.init_policy_params(R, 9)
+    theta[-2:] = [-0.7, 0.3]   # log_std
+    rng = np.random.default_rng(9)
+    B = 1000
+    mu = rng.normal(size=(B, 2)).astype(np.float32)
+    eps = rng.normal(size=(B, 2)).astype(np.float32)
+    pol = Policy(R, max_batch=8)
+    act, logp = pol.sample(torch.from_numpy(theta).cuda(), torch.from_numpy(mu).cuda(), torch.from_numpy(eps).cuda())
+    act, logp = act.cpu().double(), logp.cpu().double()
+    ls = torch.tensor(theta[-2:], dtype=torch.float64)
+    want = torch.from_numpy(mu).double() + torch.exp(ls) * torch.from_numpy(eps).double()
+    assert torch.allclose(act, want, rtol=1e-6, atol=1e-6)
+    assert torch.allclose(logp, PR.gaussian_logp(torch.from_numpy(mu).double(), ls, act), rtol=1e-5, atol=1e-5)
+    crops = torch.from_numpy(rng.integers(-896, 897, size=(300, 64, 64)).astype(np.int16)).cuda()
+    scans = torch.from_numpy(rng.normal(size=(300, 13)).astype(np.float32)).cuda()   # 52-byte rows
+    idx = torch.from_numpy(rng.integers(0, 300, size=517).astype(np.int32)).cuda()
+    for src in (crops, scans):
+        got = gather_rows(src, idx)
+        assert torch.equal(got.cpu(), src.cpu()[idx.cpu().long()])
+    assert gather_rows(crops, idx[:0]).shape == (0, 64, 64)
