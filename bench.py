@@ -365,6 +365,7 @@ def main():
     ap.add_argument("--secondary-iters", type=int, default=2, help="timed training iterations of the secondary")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-ppo", action="store_true")
+    ap.add_argument("--only-ppo", action="store_true", help="time the PPO minibatch alone (profiling)")
     ap.add_argument("--ppo-batch", type=int, default=16384)
     ap.add_argument("--cpu-robots", type=int, default=256, help="oracle training-loop sample: robots")
     ap.add_argument("--cpu-env-robots", type=int, default=750, help="oracle env-step sample: robots")
@@ -383,6 +384,9 @@ def main():
     from paper_2603_25834_amd.env import device_info
     lds, cus = device_info()
 
+    if args.only_ppo:   # profiling aid: the PPO minibatch timing alone
+        print(json.dumps({"ppo": ppo_time(360, args.ppo_batch, args.seed)}), flush=True)
+        return
     fused = dict(form=_lib.FORM_FUSED, threads=args.threads or 256, band_rows=args.band, grid=args.grid)
     plain = dict(form=_lib.FORM_PLAIN, threads=args.threads or 256, band_rows=args.band)
     print(f"[bench] {args.workload}: setting up", file=sys.stderr, flush=True)

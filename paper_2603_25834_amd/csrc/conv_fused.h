@@ -37,6 +37,13 @@ constexpr int kA1Row = 33;               // a1 pixels per row and column, plus t
 constexpr int kCropLds = kBlk * kBlk * 4;            // BF16 elements
 constexpr int kA1Lds = kA1Row * kA1Row * kC1;        // BF16 elements
 
+// a1 pixel (y, x), x, y in [-1, 31], of the forward kernel's LDS copy: rows of 33
+// pixel slots with even x + 1 in slots 0..16 and odd x + 1 in slots 17..32, so
+// that conv2's stride-2 reads along x hit consecutive slots (different banks).
+__device__ __forceinline__ int a1_slot(int y, int x) {
+  return (y + 1) * kA1Row + ((x + 1) & 1) * 17 + ((x + 1) >> 1);
+}
+
 __device__ __forceinline__ uint32_t pack_bf16x2(float lo, float hi) {
   return (uint32_t)f2bf(lo) | ((uint32_t)f2bf(hi) << 16);
 }
@@ -75,14 +82,33 @@ __device__ __forceinline__ bf16x8 conv2_weight_frag(const float* w2, int co, int
   return __builtin_bit_cast(bf16x8, u);
 }
 
-// One 64x64 int16 crop into LDS, space-to-depth, as BF16(L / 256).  Block
-// (Y, X) sits at ((Y + 1) * 33 + X + 1) * 4; the row and column of index 0
-// are the zero padding and are never written here.
-__device__ __forceinline__ void stage_crop(const int16_t* src, uint16_t* s_crop) {
-  for (int v = threadIdx.x; v < kCrop * kCrop / 8; v += blockDim.x) {
+// A 64x64 int16 crop is 512 vectors of eight cells (row y = v / 8, columns
+// 8 (v % 8) .. + 7); a workgroup of NT threads holds 512 / NT of them per
+// thread in registers, so the next sample's crop can be in flight while the
+// current one is processed.
+template <int NT>
+struct CropRegs {
+  static constexpr int kPer = kCrop * kCrop / 8 / NT;
+  int4 v[kPer];
+};
+
+template <int NT>
+__device__ __forceinline__ void load_crop(const int16_t* src, CropRegs<NT>& r) {
+  const int4* s4 = reinterpret_cast<const int4*>(src);
+#pragma unroll
+  for (int i = 0; i < CropRegs<NT>::kPer; ++i) r.v[i] = s4[threadIdx.x + i * NT];
+}
+
+// Crop registers into LDS, space-to-depth, as BF16(L / 256).  Block (Y, X)
+// sits at ((Y + 1) * 33 + X + 1) * 4; the row and column of index 0 are the
+// zero padding and are never written here.
+template <int NT>
+__device__ __forceinline__ void store_crop(const CropRegs<NT>& r, uint16_t* s_crop) {
+#pragma unroll
+  for (int i = 0; i < CropRegs<NT>::kPer; ++i) {
+    const int v = threadIdx.x + i * NT;
     const int y = v >> 3, x0 = (v & 7) * 8;
-    const int4 raw = *reinterpret_cast<const int4*>(src + y * kCrop + x0);
-    const int32_t w[4] = {raw.x, raw.y, raw.z, raw.w};
+    const int32_t w[4] = {r.v[i].x, r.v[i].y, r.v[i].z, r.v[i].w};
     const int Y = y >> 1, dy = y & 1;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -94,7 +120,7 @@ __device__ __forceinline__ void stage_crop(const int16_t* src, uint16_t* s_crop)
   }
 }
 
-// conv1 + ReLU of the staged crop into s_a1 (pixel (y, x) at ((y+1)*33 + x+1)*16).
+// conv1 + ReLU of the staged crop into s_a1 (pixel (y, x) at a1_slot(y, x) * 16).
 __device__ __forceinline__ void conv1_lds(const uint16_t* s_crop, uint16_t* s_a1, const bf16x8& w1f,
                                           const float b1[4], int wave, int lr, int lg) {
   for (int t = wave; t < kA1 * kA1 / 16; t += 4) {
@@ -110,7 +136,7 @@ __device__ __forceinline__ void conv1_lds(const uint16_t* s_crop, uint16_t* s_a1
                                                              f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
     const uint32_t lo = pack_bf16x2(fmaxf(acc[0] + b1[0], 0.0f), fmaxf(acc[1] + b1[1], 0.0f));
     const uint32_t hi = pack_bf16x2(fmaxf(acc[2] + b1[2], 0.0f), fmaxf(acc[3] + b1[3], 0.0f));
-    *reinterpret_cast<uint2*>(s_a1 + ((y + 1) * kA1Row + x + 1) * kC1 + 4 * lg) = make_uint2(lo, hi);
+    *reinterpret_cast<uint2*>(s_a1 + a1_slot(y, x) * kC1 + 4 * lg) = make_uint2(lo, hi);
   }
 }
 
@@ -120,7 +146,7 @@ __device__ __forceinline__ bf16x8 conv2_col_frag(const uint16_t* s_a1, int oy, i
   uint4 u = make_uint4(0u, 0u, 0u, 0u);
   if (tap < 9) {
     const int yy = 2 * oy + tap / 3 - 1, xx = 2 * ox + tap % 3 - 1;
-    u = *reinterpret_cast<const uint4*>(s_a1 + ((yy + 1) * kA1Row + xx + 1) * kC1 + ci0);
+    u = *reinterpret_cast<const uint4*>(s_a1 + a1_slot(yy, xx) * kC1 + ci0);
   }
   return __builtin_bit_cast(bf16x8, u);
 }
@@ -147,10 +173,14 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const float* prm, Offsets o, c
 #pragma unroll
     for (int s = 0; s < 5; ++s) w2f[nt][s] = conv2_weight_frag(prm + o.c2w, 16 * nt + lr, s, lg);
   const float b2[2] = {prm[o.c2b + lr], prm[o.c2b + 16 + lr]};
+  CropRegs<256> cr;
+  if (blockIdx.x < B) load_crop<256>(crop + (int64_t)blockIdx.x * kCrop * kCrop, cr);
   __syncthreads();
   for (int b = blockIdx.x; b < B; b += gridDim.x) {
-    stage_crop(crop + (int64_t)b * kCrop * kCrop, s_crop);
+    store_crop<256>(cr, s_crop);
     __syncthreads();
+    // the next sample's crop is loaded while this one is processed
+    if (b + (int)gridDim.x < B) load_crop<256>(crop + (int64_t)(b + gridDim.x) * kCrop * kCrop, cr);
     conv1_lds(s_crop, s_a1, w1f, b1, wave, lr, lg);
     __syncthreads();
     for (int oy = wave; oy < kA2; oy += 4) {
@@ -195,14 +225,20 @@ namespace pol {
 //
 // LDS layouts (BF16):
 //   crop   space-to-depth, as in the forward kernel;
-//   a1x    [kx][ci][y+1][ox] = a1[ci][y][2 ox + kx - 1]: for a fixed tap, eight
+//   a1x    [kx][ci][y+1][ox] = a1[ci][y][2 ox + kx - 1] (channels padded by 8
+//          elements against bank conflicts): for a fixed tap, eight
 //          consecutive output columns are eight consecutive elements, so the
 //          im2col operand of the dW2 product is one 16-byte read; y = -1 and
 //          x = -1 are zero;
-//   dz     [oy][ox][co] over 17 x 17 positions, row and column 16 zero: the
-//          operand of the input-gradient product (eight channels of one
-//          position per read);
-//   dz1    [ci][y][x % 2][x / 2]: the operand of the dW1 product.
+//   dzT    [co][pos], rows padded to 264 elements: the dW2 operand is one
+//          16-byte read (eight positions of one channel);
+//   dz     [oy][ox][co] over 17 x 17 positions (row and column 16 zero),
+//          positions padded to 40 elements so that eight lanes' 16-byte
+//          accesses cover all banks: the operand of the input-gradient
+//          product (eight channels of one position per read), transposed
+//          from dzT once per sample;
+//   dz1    [ci][y][x % 2][x / 2] (channels padded by 8 elements): the operand
+//          of the dW1 product.
 // da1 is computed one sub-pixel phase (y % 2, x % 2) at a time: the input
 // pixels of a phase form a 16 x 16 grid that receives taps ky = 1 (y even) or
 // ky in {0, 2} (y odd), likewise kx, each from the output position
@@ -211,10 +247,14 @@ constexpr int kConvPartW2 = kC2 * 144;          // [co][tap*16 + ci]
 constexpr int kConvPartW1 = kC1 * 16;           // [co][tap], taps padded to 16
 constexpr int kConvPart = kConvPartW2 + kConvPartW1 + kC1 + kC2;
 constexpr int kA1xRow = 16, kA1xRows = 33;
-constexpr int kA1xLds = 3 * kC1 * kA1xRows * kA1xRow;   // BF16 elements
-constexpr int kDzSide = 17;
-constexpr int kDzLds = kDzSide * kDzSide * kC2;
-constexpr int kDz1Lds = kC1 * kA1 * kA1;
+constexpr int kA1xCi = kA1xRows * kA1xRow + 8;         // one channel's rows, padded against bank conflicts
+constexpr int kA1xLds = 3 * kC1 * kA1xCi;               // BF16 elements
+constexpr int kDzRow = 256 + 8;
+constexpr int kDzLds = kC2 * kDzRow;
+constexpr int kDzSide = 17, kDzPos = 40;
+constexpr int kDzPLds = kDzSide * kDzSide * kDzPos;
+constexpr int kDz1Ci = kA1 * kA1 + 8;   // one channel, padded against bank conflicts
+constexpr int kDz1Lds = kC1 * kDz1Ci;
 constexpr int kBwdThreads = 512;
 
 struct PhaseTaps {
@@ -260,6 +300,7 @@ __global__ __launch_bounds__(kBwdThreads) void k_conv_bwd(const float* prm, Offs
   __shared__ __align__(16) uint16_t s_crop[kCropLds];
   __shared__ __align__(16) uint16_t s_a1x[kA1xLds];
   __shared__ __align__(16) uint16_t s_dz[kDzLds];
+  __shared__ __align__(16) uint16_t s_dzp[kDzPLds];
   __shared__ __align__(16) uint16_t s_dz1[kDz1Lds];
   __shared__ float s_red[8][kC1 * 16 + kC1 + kC2];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
@@ -268,8 +309,8 @@ __global__ __launch_bounds__(kBwdThreads) void k_conv_bwd(const float* prm, Offs
     for (int i = threadIdx.x; i < kCropLds / 8; i += kBwdThreads) z[i] = make_uint4(0u, 0u, 0u, 0u);
     z = reinterpret_cast<uint4*>(s_a1x);
     for (int i = threadIdx.x; i < kA1xLds / 8; i += kBwdThreads) z[i] = make_uint4(0u, 0u, 0u, 0u);
-    z = reinterpret_cast<uint4*>(s_dz);
-    for (int i = threadIdx.x; i < kDzLds / 8; i += kBwdThreads) z[i] = make_uint4(0u, 0u, 0u, 0u);
+    z = reinterpret_cast<uint4*>(s_dzp);
+    for (int i = threadIdx.x; i < kDzPLds / 8; i += kBwdThreads) z[i] = make_uint4(0u, 0u, 0u, 0u);
   }
   // registers that live for the whole workgroup
   const bf16x8 w1f = conv1_weight_frag_b(prm + o.c1w, lr, lg);
@@ -294,31 +335,35 @@ __global__ __launch_bounds__(kBwdThreads) void k_conv_bwd(const float* prm, Offs
     for (int c = 0; c < 2; ++c) gw2[a][c] = f32x4{0.f, 0.f, 0.f, 0.f};
   f32x4 gw1 = {0.f, 0.f, 0.f, 0.f};
   float gb1 = 0.0f, gb2[2] = {0.f, 0.f};
+  // the sample's crop and dz2 in registers; the next sample's are loaded while this one is processed
+  CropRegs<kBwdThreads> cr;
+  uint4 dzr[2];
+  auto load_sample = [&](int bb) {
+    load_crop<kBwdThreads>(crop + (int64_t)bb * kCrop * kCrop, cr);
+    const uint4* src = reinterpret_cast<const uint4*>(dz2c + (int64_t)bb * kFeat);
+    dzr[0] = src[threadIdx.x];
+    dzr[1] = src[threadIdx.x + kBwdThreads];
+  };
+  if (blockIdx.x < B) load_sample(blockIdx.x);
   __syncthreads();
 
   for (int b = blockIdx.x; b < B; b += gridDim.x) {
-    // ---- stage the crop and dz2 (transposed to [pos][co]); db2 from the same reads
-    stage_crop(crop + (int64_t)b * kCrop * kCrop, s_crop);
+    // ---- stage the crop and dz2 ([co][pos]); db2 from the same values
+    store_crop<kBwdThreads>(cr, s_crop);
     {
-      const uint4* src = reinterpret_cast<const uint4*>(dz2c + (int64_t)b * kFeat);
 #pragma unroll
       for (int r = 0; r < 2; ++r) {
         const int v = threadIdx.x + r * kBwdThreads;   // vector of 8 positions of channel co
         const int co = v >> 5, p0 = (v & 31) * 8;
-        const uint4 u = src[v];
-        const uint32_t w[4] = {u.x, u.y, u.z, u.w};
-        float s = 0.0f;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const uint16_t h = (uint16_t)(w[e >> 1] >> ((e & 1) * 16));
-          s += bf2f(h);
-          const int p = p0 + e, oy = p >> 4, ox = p & 15;
-          s_dz[(oy * kDzSide + ox) * kC2 + co] = h;
-        }
-        gb2[r] += s;
+        const uint4 u = dzr[r];
+        *reinterpret_cast<uint4*>(s_dz + co * kDzRow + p0) = u;
+        float e[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        add_bf16x8(e, u);
+        gb2[r] += ((e[0] + e[1]) + (e[2] + e[3])) + ((e[4] + e[5]) + (e[6] + e[7]));
       }
     }
     __syncthreads();
+    if (b + (int)gridDim.x < B) load_sample(b + gridDim.x);
     // ---- conv1 recompute: C[px][co], lane gets pixels 16 t + 4 lg + i of channel lr
     for (int t = wave; t < kA1 * kA1 / 16; t += 8) {
       const int pxa = t * 16 + lr, ya = pxa >> 5, xa = pxa & 31;
@@ -335,18 +380,27 @@ __global__ __launch_bounds__(kBwdThreads) void k_conv_bwd(const float* prm, Offs
       uint16_t h[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) h[i] = f2bf(fmaxf(acc[i] + b1c, 0.0f));
-      uint16_t* row = s_a1x + (lr * kA1xRows + y + 1) * kA1xRow;    // kx plane 0
-      const int plane = kC1 * kA1xRows * kA1xRow;
+      uint16_t* row = s_a1x + lr * kA1xCi + (y + 1) * kA1xRow;    // kx plane 0
+      const int plane = kC1 * kA1xCi;
       // even x -> kx = 1 at ox = x / 2; odd x -> kx = 0 at (x + 1) / 2 and kx = 2 at (x - 1) / 2
       *reinterpret_cast<uint32_t*>(row + plane + (x0 >> 1)) = (uint32_t)h[0] | ((uint32_t)h[2] << 16);
       *reinterpret_cast<uint32_t*>(row + 2 * plane + (x0 >> 1)) = (uint32_t)h[1] | ((uint32_t)h[3] << 16);
       row[(x0 >> 1) + 1] = h[1];
       if ((x0 >> 1) + 2 < kA1xRow) row[(x0 >> 1) + 2] = h[3];
     }
+    // dz2 [co][pos] -> [pos][co]: thread takes position v % 256 and channels 8 (v / 256) .. + 7
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const int v = threadIdx.x + r * kBwdThreads;
+      const int pos = v & 255, cg = v >> 8;
+      uint16_t g[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) g[e] = s_dz[(8 * cg + e) * kDzRow + pos];
+      *reinterpret_cast<uint4*>(s_dzp + ((pos >> 4) * kDzSide + (pos & 15)) * kDzPos + 8 * cg) = pack8(g);
+    }
     __syncthreads();
     // ---- dW2: tiles (mt, nt = wave) over all 8 position k-steps, and (mt, nt = 8) at k-step = wave
     {
-      const uint16_t* dzg = dz2c + (int64_t)b * kFeat;
 #pragma unroll
       for (int u = 0; u < 9; ++u) {
         const int nt = u < 8 ? wave : 8;
@@ -356,11 +410,11 @@ __global__ __launch_bounds__(kBwdThreads) void k_conv_bwd(const float* prm, Offs
         const int ky = nt / 3, kx = nt % 3;
         const int yy = 2 * oy + ky - 1;
         const bf16x8 bf = __builtin_bit_cast(
-            bf16x8, *reinterpret_cast<const uint4*>(s_a1x + ((kx * kC1 + lr) * kA1xRows + yy + 1) * kA1xRow + ox0));
+            bf16x8, *reinterpret_cast<const uint4*>(s_a1x + (kx * kC1 + lr) * kA1xCi + (yy + 1) * kA1xRow + ox0));
 #pragma unroll
         for (int mt = 0; mt < 2; ++mt) {
           const bf16x8 af = __builtin_bit_cast(
-              bf16x8, *reinterpret_cast<const uint4*>(dzg + (16 * mt + lr) * 256 + p0));
+              bf16x8, *reinterpret_cast<const uint4*>(s_dz + (16 * mt + lr) * kDzRow + p0));
           gw2[slot][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bf, gw2[slot][mt], 0, 0, 0);
         }
       }
@@ -381,13 +435,13 @@ __global__ __launch_bounds__(kBwdThreads) void k_conv_bwd(const float* prm, Offs
             if (j >= t.n) break;
             const int oy = qy + t.dy[j], ox = lr + t.dx[j];
             const bf16x8 af = __builtin_bit_cast(
-                bf16x8, *reinterpret_cast<const uint4*>(s_dz + (oy * kDzSide + ox) * kC2 + 8 * lg));
+                bf16x8, *reinterpret_cast<const uint4*>(s_dzp + (oy * kDzSide + ox) * kDzPos + 8 * lg));
             acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, wph[q + j], acc, 0, 0, 0);
           }
           // lane: input pixels (2 qy + py, 2 (4 lg + i) + px), channel lr
           const int y = 2 * qy + py;
           const uint2 m = *reinterpret_cast<const uint2*>(
-              s_a1x + (((1 + px) * kC1 + lr) * kA1xRows + y + 1) * kA1xRow + 4 * lg);
+              s_a1x + ((1 + px) * kC1 + lr) * kA1xCi + (y + 1) * kA1xRow + 4 * lg);
           const uint32_t mw[2] = {m.x, m.y};
           uint16_t d[4];
 #pragma unroll
@@ -396,7 +450,7 @@ __global__ __launch_bounds__(kBwdThreads) void k_conv_bwd(const float* prm, Offs
             d[i] = bf2f(a) > 0.0f ? f2bf(acc[i]) : (uint16_t)0;
             gb1 += bf2f(d[i]);
           }
-          *reinterpret_cast<uint2*>(s_dz1 + (lr * kA1 + y) * kA1 + px * 16 + 4 * lg) =
+          *reinterpret_cast<uint2*>(s_dz1 + lr * kDz1Ci + y * kA1 + px * 16 + 4 * lg) =
               make_uint2((uint32_t)d[0] | ((uint32_t)d[1] << 16), (uint32_t)d[2] | ((uint32_t)d[3] << 16));
         }
         q += t.n;
@@ -408,17 +462,17 @@ __global__ __launch_bounds__(kBwdThreads) void k_conv_bwd(const float* prm, Offs
     for (int r = 0; r < 4; ++r) {
       const int ks = wave * 4 + r;
       const int k0 = 32 * ks + 8 * lg;
-      const bf16x8 af = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(s_dz1 + lr * 1024 + k0));
-      // B: lane supplies in[(y, x = 2 (xh0 + e) + par), tap = lr] for e < 8
+      const bf16x8 af = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(s_dz1 + lr * kDz1Ci + k0));
+      // B: lane supplies in[(y, x = 2 (xh0 + e) + par), tap = lr] for e < 8: input row
+      // 2 y + ky - 1 and column 4 (xh0 + e) + c0 with c0 = 2 par + kx - 1 in [-1, 3], i.e. block
+      // column 2 (xh0 + e) + (c0 >> 1) and element (row & 1, c0 & 1): consecutive e are 8 apart.
       const int y = k0 >> 5, par = (k0 >> 4) & 1, xh0 = k0 & 15;
       const int ky = lr / 3, kx = lr % 3;
+      const int row = 2 * y + ky - 1, c0 = 2 * par + kx - 1;
+      const int base = (((row >> 1) + 1) * kBlk + 2 * xh0 + (c0 >> 1) + 1) * 4 + 2 * (row & 1) + (c0 & 1);
       uint16_t v[8];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int row = 2 * y + ky - 1, col = 2 * (2 * (xh0 + e) + par) + kx - 1;   // in [-1, 63]
-        const int Y = row >> 1, X = col >> 1;
-        v[e] = lr < 9 ? s_crop[((Y + 1) * kBlk + X + 1) * 4 + 2 * (row & 1) + (col & 1)] : (uint16_t)0;
-      }
+      for (int e = 0; e < 8; ++e) v[e] = lr < 9 ? s_crop[base + 8 * e] : (uint16_t)0;
       uint4 u;
       u.x = v[0] | ((uint32_t)v[1] << 16);
       u.y = v[2] | ((uint32_t)v[3] << 16);

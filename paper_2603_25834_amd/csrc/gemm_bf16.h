@@ -7,11 +7,16 @@
 //
 // Tiling: a workgroup of 256 threads (4 waves) owns a BM x BN tile of C; the
 // waves are arranged WM x WN and each accumulates a (BM/WM) x (BN/WN) sub-tile
-// in 16x16 MFMA fragments.  K advances BK per stage: the A and B tiles are
-// staged in LDS as [row][k] (k contiguous, rows padded by 8 elements against
-// bank conflicts), double buffered, with the next stage's global loads in
-// registers while the current stage feeds the MFMAs.  A large BK keeps enough
-// bytes in flight per CU to cover HBM latency with one workgroup per CU.
+// in 16x16 MFMA fragments.  K advances BK per stage, double buffered in LDS,
+// with the next stage's global loads in registers while the current stage
+// feeds the MFMAs.  A large BK keeps enough bytes in flight per CU to cover HBM
+// latency with one workgroup per CU.  Both operands are staged as [row][k]
+// (rows padded by 8 elements) and read as one 16-byte fragment per lane.  An
+// operand whose source is contiguous along the row index is transposed on the
+// way in: a thread loads the same eight rows at k and k + 1 and stores eight
+// 32-bit (k, k + 1) pairs; the 16-byte chunks of a row are XOR-swizzled with
+// (row / 8) so that those stores, eight rows apart across lanes, spread over
+// the LDS banks.
 // The finished tile is staged through LDS as FP32 so that the epilogue sees
 // eight consecutive columns of a row per call (16-byte loads and stores).
 //
@@ -51,6 +56,17 @@ __device__ __forceinline__ uint16_t lane16(const uint4& v, int j) {
 // Epilogue contract: store8(m, n0, v, nvalid) for row m < M and the eight
 // columns n0 .. n0 + 7 (n0 multiple of 8), of which the first nvalid are < N.
 
+// LDS elements of one stage of an operand with ROWS rows ([row][k], rows padded by 8).
+template <bool KMAJOR, int ROWS, int BK>
+struct Stage {
+  static constexpr int kLd = BK + 8;
+  static constexpr int kElems = ROWS * kLd;
+  // element (r, k) of a transposed (!KMAJOR) stage: 16-byte chunk k / 8 swizzled with (r / 8)
+  __device__ static __forceinline__ int at(int r, int k) {
+    return KMAJOR ? r * kLd + k : r * kLd + ((((k >> 3) ^ (r >> 3)) & (BK / 8 - 1)) << 3) + (k & 7);
+  }
+};
+
 template <int BM, int BN, int BK, int WM, int WN>
 struct Cfg {
   static_assert(WM * WN == 4, "four waves");
@@ -58,27 +74,36 @@ struct Cfg {
   static constexpr int FM = TM / 16, FN = TN / 16;   // fragments per wave
   static_assert(FM * 16 == TM && FN * 16 == TN, "fragment tiling");
   static_assert(BK % 32 == 0, "BK is a multiple of the MFMA depth");
-  static constexpr int PADK = BK + 8;                 // LDS row length in elements
   static constexpr int VA = BM * BK / 8, VB = BN * BK / 8;            // 8-element vectors per stage
-  static constexpr int PA = (VA + 255) / 256, PB = (VB + 255) / 256;  // vectors per thread
-  static constexpr int kStageBytes = 2 * (BM + BN) * PADK * 2;        // double-buffered A and B
+  // vectors per thread, rounded up to even (a transposed operand is fetched in pairs)
+  static constexpr int PA = ((VA + 255) / 256 + 1) & ~1, PB = ((VB + 255) / 256 + 1) & ~1;
   static constexpr int kEpiBytes = BM * (BN + 4) * 4;                 // FP32 tile (rows padded)
-  static constexpr int kLds = kStageBytes > kEpiBytes ? kStageBytes : kEpiBytes;
 };
 
+// kMajor: register p holds vector v = tid + 256 p = (row v / (BK/8), k-chunk v % (BK/8)).
+// !kMajor: registers 2q, 2q + 1 hold pair w = tid + 256 q = (k = 2 (w / (ROWS/8)), row-chunk w % (ROWS/8))
+// at k and k + 1 (consecutive lanes read consecutive row-chunks of the same source rows).
 template <class L, int ROWS, int BK, int P>
 __device__ __forceinline__ void fetch_tile(const L& ld, int row0, int k0, uint4 (&regs)[P]) {
   constexpr int V = ROWS * BK / 8;
+  if (L::kMajor) {
 #pragma unroll
-  for (int p = 0; p < P; ++p) {
-    const int v = threadIdx.x + p * 256;
-    if (V % 256 == 0 || v < V) {
-      if (L::kMajor) {
+    for (int p = 0; p < P; ++p) {
+      const int v = threadIdx.x + p * 256;
+      if (V % 256 == 0 || v < V) {
         const int i = v / (BK / 8), kq = v % (BK / 8);
         regs[p] = ld.fetch(row0 + i, k0 + kq * 8);
-      } else {
-        const int k = v / (ROWS / 8), iq = v % (ROWS / 8);
-        regs[p] = ld.fetch(row0 + iq * 8, k0 + k);
+      }
+    }
+  } else {
+    constexpr int VP = V / 2;
+#pragma unroll
+    for (int q = 0; q < P / 2; ++q) {
+      const int w = threadIdx.x + q * 256;
+      if (VP % 256 == 0 || w < VP) {
+        const int k = 2 * (w / (ROWS / 8)), iq = w % (ROWS / 8);
+        regs[2 * q] = ld.fetch(row0 + iq * 8, k0 + k);
+        regs[2 * q + 1] = ld.fetch(row0 + iq * 8, k0 + k + 1);
       }
     }
   }
@@ -86,30 +111,53 @@ __device__ __forceinline__ void fetch_tile(const L& ld, int row0, int k0, uint4 
 
 template <class L, int ROWS, int BK, int P>
 __device__ __forceinline__ void store_tile(uint16_t* s, const uint4 (&regs)[P]) {
-  constexpr int V = ROWS * BK / 8, PADK = BK + 8;
+  using S = Stage<L::kMajor, ROWS, BK>;
+  constexpr int V = ROWS * BK / 8;
+  if (L::kMajor) {
 #pragma unroll
-  for (int p = 0; p < P; ++p) {
-    const int v = threadIdx.x + p * 256;
-    if (V % 256 == 0 || v < V) {
-      if (L::kMajor) {
+    for (int p = 0; p < P; ++p) {
+      const int v = threadIdx.x + p * 256;
+      if (V % 256 == 0 || v < V) {
         const int i = v / (BK / 8), kq = v % (BK / 8);
-        *reinterpret_cast<uint4*>(s + i * PADK + kq * 8) = regs[p];
-      } else {
-        const int k = v / (ROWS / 8), iq = v % (ROWS / 8);
+        *reinterpret_cast<uint4*>(s + S::at(i, kq * 8)) = regs[p];
+      }
+    }
+  } else {
+    constexpr int VP = V / 2;
 #pragma unroll
-        for (int j = 0; j < 8; ++j) s[(iq * 8 + j) * PADK + k] = lane16(regs[p], j);
+    for (int q = 0; q < P / 2; ++q) {
+      const int w = threadIdx.x + q * 256;
+      if (VP % 256 == 0 || w < VP) {
+        const int k = 2 * (w / (ROWS / 8)), iq = w % (ROWS / 8);
+        const uint4 a = regs[2 * q], b = regs[2 * q + 1];
+        const uint32_t wa[4] = {a.x, a.y, a.z, a.w}, wb[4] = {b.x, b.y, b.z, b.w};
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const uint32_t lo = (wa[j >> 1] >> ((j & 1) * 16)) & 0xffffu;
+          const uint32_t hi = (wb[j >> 1] >> ((j & 1) * 16)) & 0xffffu;
+          *reinterpret_cast<uint32_t*>(s + S::at(iq * 8 + j, k)) = lo | (hi << 16);
+        }
       }
     }
   }
 }
 
+// MFMA fragment of row r (tile-local) and k values kk .. kk + 7 (kk multiple of 8).
+template <bool KMAJOR, int ROWS, int BK>
+__device__ __forceinline__ bf16x8 load_frag(const uint16_t* s, int r, int kk) {
+  return __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(s + Stage<KMAJOR, ROWS, BK>::at(r, kk)));
+}
+
 template <int BM, int BN, int BK, int WM, int WN, class LA, class LB, class EPI>
 __global__ __launch_bounds__(256) void k_gemm(LA la, LB lb, EPI epi, int M, int N, int K, int k_split) {
   using C = Cfg<BM, BN, BK, WM, WN>;
-  constexpr int PADK = C::PADK;
-  __shared__ __align__(16) unsigned char smem[C::kLds];
-  uint16_t* sA = reinterpret_cast<uint16_t*>(smem);           // [2][BM * PADK]
-  uint16_t* sB = sA + 2 * BM * PADK;                          // [2][BN * PADK]
+  using SA = Stage<LA::kMajor, BM, BK>;
+  using SB = Stage<LB::kMajor, BN, BK>;
+  constexpr int kStageBytes = 2 * (SA::kElems + SB::kElems) * 2;   // double-buffered A and B
+  constexpr int kLds = kStageBytes > C::kEpiBytes ? kStageBytes : C::kEpiBytes;
+  __shared__ __align__(16) unsigned char smem[kLds];
+  uint16_t* sA = reinterpret_cast<uint16_t*>(smem);           // [2][SA::kElems]
+  uint16_t* sB = sA + 2 * SA::kElems;                         // [2][SB::kElems]
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int wm = wave / WN, wn = wave % WN;
   const int m_blk = blockIdx.x * BM, n_blk = blockIdx.y * BN;   // M tiles on x (up to 2^31 - 1)
@@ -137,25 +185,25 @@ __global__ __launch_bounds__(256) void k_gemm(LA la, LB lb, EPI epi, int M, int 
       fetch_tile<LA, BM, BK>(la, m_blk, kb + (t + 1) * BK, ra);
       fetch_tile<LB, BN, BK>(lb, n_blk, kb + (t + 1) * BK, rb);
     }
-    const uint16_t* a_base = sA + buf * BM * PADK + (wm * C::TM + (lane & 15)) * PADK + 8 * (lane >> 4);
-    const uint16_t* b_base = sB + buf * BN * PADK + (wn * C::TN + (lane & 15)) * PADK + 8 * (lane >> 4);
+    const uint16_t* a_st = sA + buf * SA::kElems;
+    const uint16_t* b_st = sB + buf * SB::kElems;
+    const int ra0 = wm * C::TM + (lane & 15), rb0 = wn * C::TN + (lane & 15), kl = 8 * (lane >> 4);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 32) {
       bf16x8 bf[C::FN];
 #pragma unroll
-      for (int j = 0; j < C::FN; ++j)
-        bf[j] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(b_base + j * 16 * PADK + kk));
+      for (int j = 0; j < C::FN; ++j) bf[j] = load_frag<LB::kMajor, BN, BK>(b_st, rb0 + j * 16, kk + kl);
 #pragma unroll
       for (int i = 0; i < C::FM; ++i) {
-        const bf16x8 af = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(a_base + i * 16 * PADK + kk));
+        const bf16x8 af = load_frag<LA::kMajor, BM, BK>(a_st, ra0 + i * 16, kk + kl);
 #pragma unroll
         for (int j = 0; j < C::FN; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bf[j], acc[i][j], 0, 0, 0);
       }
     }
     if (more) {
-      store_tile<LA, BM, BK>(sA + (buf ^ 1) * BM * PADK, ra);
-      store_tile<LB, BN, BK>(sB + (buf ^ 1) * BN * PADK, rb);
+      store_tile<LA, BM, BK>(sA + (buf ^ 1) * SA::kElems, ra);
+      store_tile<LB, BN, BK>(sB + (buf ^ 1) * SB::kElems, rb);
     }
     __syncthreads();
   }

@@ -42,10 +42,24 @@ namespace {
 
 constexpr int kConvGrid = 2048;    // workgroups of the fused encoder forward (each loops over samples)
 constexpr int kConvBwdGrid = 256;  // encoder backward: one 8-wave workgroup per CU (LDS-bound)
-constexpr int64_t kFc1Splits = 4, kFc2Splits = 64;
+constexpr int64_t kFc1Splits = 12, kFc2Splits = 64;
+constexpr int kFc1MinBlocks = 512;   // FC1 forward: split K until the grid has this many workgroups
 
 int64_t splits_for(int64_t K, int64_t min_chunk, int64_t max_splits) {
   return std::max<int64_t>(1, std::min<int64_t>(max_splits, K / min_chunk));
+}
+
+// K splits of a split-K GEMM with `tiles` output tiles: the count that minimises (rounds of
+// `slots` resident workgroups) x (BK steps per workgroup), the smaller on ties.
+int64_t splits_balanced(int64_t K, int BK, int64_t tiles, int64_t slots, int64_t max_splits) {
+  int64_t best = 1, best_cost = -1;
+  for (int64_t s = 1; s <= max_splits; ++s) {
+    const int64_t rounds = (tiles * s + slots - 1) / slots;
+    const int64_t steps = (K + s * BK - 1) / (s * BK);
+    const int64_t cost = rounds * steps;
+    if (best_cost < 0 || cost < best_cost) { best = s; best_cost = cost; }
+  }
+  return best;
 }
 
 // Number of K slices gemm::run launches for `splits` requested splits (chunks rounded up to BK).
@@ -61,6 +75,7 @@ int64_t part_need(const aslam_policy* p) {
   need = std::max<int64_t>(need, kFc2Splits * kHid * kHid);   // FC2 weight partials
   need = std::max<int64_t>(need, (int64_t)kConvBwdGrid * kConvPart);   // encoder backward partials
   need = std::max<int64_t>(need, (int64_t)kBiasBlocks * 256);
+  need = std::max<int64_t>(need, 2LL * kFc1MinBlocks * 64 * kHid);   // FC1 forward split-K: S * B < 2 * 64 * 256
   return need;
 }
 
@@ -89,10 +104,23 @@ int forward_core(aslam_policy* P, const float* prm, const int16_t* crop, const f
   }
   k_conv_fwd<<<std::min(B, kConvGrid), 256, 0, st>>>(prm, o, crop, P->a2, B);
   PCHK(hipGetLastError());
-  // FC1: [B x k1] x [k1 x 256]
+  // FC1: [B x k1] x [k1 x 256]; small batches split K so that the launch fills the chip
   XSrc xs{P->a2, scan, state, R, B, o.k1};
-  PCHK((gemm::run<128, 128, 128, 2, 2>(LdXK{xs}, LdBF16K{P->w1b, P->k1p, kHid, o.k1},
-                                     EpiBiasReluBF16{P->h1, prm + o.f1b, kHid}, B, kHid, o.k1, 1, st)));
+  const int tiles = ((B + 127) / 128) * (kHid / 128);
+  int S = 1;
+  while (tiles * S < kFc1MinBlocks && S < 32) S *= 2;
+  if (S == 1) {
+    PCHK((gemm::run<128, 128, 64, 2, 2>(LdXK{xs}, LdBF16K{P->w1b, P->k1p, kHid, o.k1},
+                                         EpiBiasReluBF16{P->h1, prm + o.f1b, kHid}, B, kHid, o.k1, 1, st)));
+  } else {
+    const int used = slices_used(o.k1, S, 64);
+    PCHK((gemm::run<128, 128, 64, 2, 2>(LdXK{xs}, LdBF16K{P->w1b, P->k1p, kHid, o.k1},
+                                         EpiPartial{P->part, kHid, (int64_t)B * kHid}, B, kHid, o.k1, S, st)));
+    const int64_t groups = (int64_t)B * (kHid / 8);
+    k_reduce_bias_relu_bf16<<<(int)std::min<int64_t>(4096, (groups + 255) / 256), 256, 0, st>>>(
+        P->part, used, B, kHid, prm + o.f1b, P->h1, kHid);
+    PCHK(hipGetLastError());
+  }
   // FC2 pre-activation (FP32): [B x 256] x [256 x 256]
   PCHK((gemm::run<128, 128, 64, 2, 2>(LdBF16K{P->h1, kHid, B, kHid}, LdBF16K{P->w2b, kHid, kHid, kHid},
                                      EpiBiasF32{P->z2, prm + o.f2b, kHid}, B, kHid, kHid, 1, st)));
@@ -207,7 +235,7 @@ int aslam_policy_backward(aslam_policy* P, const float* params, const int16_t* c
   // FC1 weight: dW1[out][k] = sum_b dz1[b][out] X[b][k]
   XSrc xs{P->a2, scan, state, R, B, o.k1};
   {
-    const int64_t S = splits_for(B, 2048, kFc1Splits);
+    const int64_t S = splits_balanced(B, 64, 2 * (int64_t)((o.k1 + 127) / 128), 512, kFc1Splits);
     const int S_used = slices_used(B, S, 64);
     PCHK((gemm::run<128, 128, 64, 2, 2>(LdBF16I{P->dz1, kHid, kHid, B}, LdXI{xs},
                                        EpiPartial{part, o.k1, (int64_t)kHid * o.k1}, kHid, o.k1, B, (int)S, st)));

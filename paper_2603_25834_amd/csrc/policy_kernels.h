@@ -394,6 +394,32 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce(const float* part, in
   }
 }
 
+// Split-K finish of a GEMM with a bias + ReLU + BF16 epilogue: out[m][n] =
+// bf16(relu(bias[n] + sum_z part[z][m][n])), z in order; 8 columns per thread (N % 8 == 0).
+__global__ void k_reduce_bias_relu_bf16(const float* part, int S, int M, int N, const float* bias, uint16_t* out,
+                                        int64_t ldo) {
+  const int64_t groups = (int64_t)M * (N / 8);
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < groups;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t m = g / (N / 8);
+    const int n0 = (int)(g - m * (N / 8)) * 8;
+    float a[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) a[j] = 0.0f;
+    const float* q = part + m * N + n0;
+    for (int z = 0; z < S; ++z) {
+      const float4 lo = *reinterpret_cast<const float4*>(q + (int64_t)z * M * N);
+      const float4 hi = *reinterpret_cast<const float4*>(q + (int64_t)z * M * N + 4);
+      a[0] += lo.x; a[1] += lo.y; a[2] += lo.z; a[3] += lo.w;
+      a[4] += hi.x; a[5] += hi.y; a[6] += hi.z; a[7] += hi.w;
+    }
+    uint16_t h[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) h[j] = f2bf(fmaxf(a[j] + bias[n0 + j], 0.0f));
+    *reinterpret_cast<uint4*>(out + m * ldo + n0) = pack8(h);
+  }
+}
+
 // Launch helper: outputs in groups of four, S split over the remaining lanes.
 inline hipError_t launch_reduce(const float* part, int S, int64_t count, float* dst, int map, int64_t slice,
                                 hipStream_t st) {
