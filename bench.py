@@ -46,10 +46,10 @@ def kernel_source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def read_traffic(kernel: str, workload: str):
-    """HBM traffic per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.txt")
+def read_traffic(kernel: str, workload: str, threads: int):
+    """HBM traffic per launch from the committed rocprofv3 counter summary for this kernel, workload and
+    workgroup size, if it was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_t{threads}_{workload}.txt")
     if not os.path.exists(path):
         return None
     kv = {}
@@ -366,10 +366,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-ppo", action="store_true")
     ap.add_argument("--only-ppo", action="store_true", help="time the PPO minibatch alone (profiling)")
+    ap.add_argument("--only-env", action="store_true", help="time the env step alone (profiling)")
     ap.add_argument("--ppo-batch", type=int, default=16384)
-    ap.add_argument("--cpu-robots", type=int, default=256, help="oracle training-loop sample: robots")
+    ap.add_argument("--cpu-robots", type=int, default=640, help="oracle training-loop sample: robots")
     ap.add_argument("--cpu-env-robots", type=int, default=750, help="oracle env-step sample: robots")
-    ap.add_argument("--cpu-env-steps", type=int, default=100, help="oracle env-step sample: steps")
+    ap.add_argument("--cpu-env-steps", type=int, default=400, help="oracle env-step sample: steps")
     ap.add_argument("--calib-copy", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration under rocprofv3)")
     args = ap.parse_args()
@@ -410,7 +411,12 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    traffic = read_traffic("k_fused", args.workload)
+    traffic = read_traffic("k_fused", args.workload, fused["threads"])
+    if args.only_env:   # profiling aid: the env-step timings alone
+        print(json.dumps({"env_step_ms": res["ms_per_step"], "plain_step_ms": res_plain["ms_per_step"],
+                          "observe_ms": obs_ms, "alg_bytes_per_launch": res["alg_bytes_per_step"],
+                          "achieved_gbs": res["achieved_gbs"], "traffic": traffic}), flush=True)
+        return
     # ---- the bench step: one PPO training iteration (rollout of `horizon` steps + update)
     wb.env.set_exec(**fused)
     loop = train_loop(wb, args.horizon, args.epochs, args.minibatch, args.warmup, args.steps, args.seed)
@@ -453,7 +459,7 @@ def main():
                        "fused_speedup": res["env_steps_per_s"] / res_plain["env_steps_per_s"]},
         "roofline": {"bound": "hbm", "achieved": res["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": res["achieved_gbs"] / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_fused", "alg_bytes_per_launch": res["alg_bytes_per_step"],
+                     "kernel": f"k_fused<{fused['threads']}>", "alg_bytes_per_launch": res["alg_bytes_per_step"],
                      "avg_launch_ms": res["ms_per_step"],
                      "coded_cells_per_robot_step": res["coded_cells_per_robot_step"],
                      "cell_visits_per_robot_step": res["march_visits_per_robot_step"] +

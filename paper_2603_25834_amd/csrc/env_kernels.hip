@@ -815,35 +815,51 @@ __global__ __launch_bounds__(NT) void k_update(EnvParams P, StepArgs A, LdsPlan 
   update_and_reward<NT>(P, A, m, V, L, r);
 }
 
-// Fused persistent step: workgroups pull robots in largest-grid-first order.
-// The register budget is capped at four waves per SIMD (128 VGPRs): at 512
-// threads that keeps two robots resident per CU instead of one.
+// One robot of the fused step (motion, march, update, reward) by the whole workgroup.
 template <int NT>
-__global__ __launch_bounds__(NT, 4) void k_fused(EnvParams P, StepArgs A, LdsPlan L) {
+__device__ __forceinline__ void fused_robot(const EnvParams& P, const StepArgs& A, const LdsPlan& L,
+                                            const LdsView& V, int32_t r) {
+  RobotShared* sh = V.sh;
+  const RobotMeta m = P.meta[r];
+  if (threadIdx.x == 0) {
+    const MotionOut o = robot_motion(P, A, r);
+    sh->tox = o.tox; sh->toy = o.toy; sh->ib_t = o.ib_t;
+    sh->eox = o.eox; sh->eoy = o.eoy; sh->ib_e = o.ib_e;
+    sh->collided = o.collided;
+    sh->cnt_march = 0;
+    sh->cnt_upd = 0;
+    init_bbox(sh);
+  }
+  __syncthreads();
+  int32_t wy0;
+  stage_world<NT>(P, m, sh->toy >> 16, L.world_halo, V.uni, wy0);
+  __syncthreads();
+  march_rays<NT>(P, m, V, V.uni, wy0, (L.union_bytes >> 2) - 1, A.ranges, L.record != 0, r);
+  endpoint_bbox<NT>(P, V.rho, sh->eox, sh->eoy, sh->ib_e, sh);
+  __syncthreads();
+  update_and_reward<NT>(P, A, m, V, L, r);
+}
+
+// Fused step, one workgroup per robot: workgroup b takes the b-th robot of the
+// largest-grid-first order, so the dispatcher hands out the big grids first.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_fused(EnvParams P, StepArgs A, LdsPlan L) {
   extern __shared__ __align__(16) unsigned char smem[];
   const LdsView V = lds_view(smem, L);
-  RobotShared* sh = V.sh;
+  for (int32_t i = threadIdx.x; i < 2 * P.lclamp + 1; i += NT) V.lut[i] = P.hq_lut[i];
+  fused_robot<NT>(P, A, L, V, P.order[blockIdx.x]);
+}
+
+// Fused persistent step on a smaller grid: workgroups pull robots in largest-grid-first
+// order.  The register budget is capped at four waves per SIMD (128 VGPRs); the
+// loop-carried state would otherwise double it.
+template <int NT>
+__global__ __launch_bounds__(NT, 4) void k_fused_persist(EnvParams P, StepArgs A, LdsPlan L) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const LdsView V = lds_view(smem, L);
   for (int32_t i = threadIdx.x; i < 2 * P.lclamp + 1; i += NT) V.lut[i] = P.hq_lut[i];
   for (int32_t w = blockIdx.x; w < P.n; w += gridDim.x) {
-    const int32_t r = P.order[w];
-    const RobotMeta m = P.meta[r];
-    if (threadIdx.x == 0) {
-      const MotionOut o = robot_motion(P, A, r);
-      sh->tox = o.tox; sh->toy = o.toy; sh->ib_t = o.ib_t;
-      sh->eox = o.eox; sh->eoy = o.eoy; sh->ib_e = o.ib_e;
-      sh->collided = o.collided;
-      sh->cnt_march = 0;
-      sh->cnt_upd = 0;
-      init_bbox(sh);
-    }
-    __syncthreads();
-    int32_t wy0;
-    stage_world<NT>(P, m, sh->toy >> 16, L.world_halo, V.uni, wy0);
-    __syncthreads();
-    march_rays<NT>(P, m, V, V.uni, wy0, (L.union_bytes >> 2) - 1, A.ranges, L.record != 0, r);
-    endpoint_bbox<NT>(P, V.rho, sh->eox, sh->eoy, sh->ib_e, sh);
-    __syncthreads();
-    update_and_reward<NT>(P, A, m, V, L, r);
+    fused_robot<NT>(P, A, L, V, P.order[w]);
     __syncthreads();
   }
 }
@@ -926,7 +942,11 @@ hipError_t plain_nt(const EnvParams& P, const StepArgs& A, const LdsPlan& L, hip
 
 template <int NT>
 hipError_t fused_nt(const EnvParams& P, const StepArgs& A, const LdsPlan& L, int grid, hipStream_t st) {
-  k_fused<NT><<<grid, NT, L.total, st>>>(P, A, L);
+  if (grid >= P.n) {
+    k_fused<NT><<<P.n, NT, L.total, st>>>(P, A, L);
+  } else {
+    k_fused_persist<NT><<<grid, NT, L.total, st>>>(P, A, L);
+  }
   return hipGetLastError();
 }
 
@@ -937,7 +957,9 @@ hipError_t set_lds_nt(int bytes) {
                                hipFuncAttributeMaxDynamicSharedMemorySize, bytes)) != hipSuccess) return e;
   if ((e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_update<NT>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, bytes)) != hipSuccess) return e;
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fused<NT>),
+  if ((e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fused<NT>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes)) != hipSuccess) return e;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fused_persist<NT>),
                              hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
