@@ -151,9 +151,9 @@ __device__ __forceinline__ bf16x8 conv2_col_frag(const uint16_t* s_a1, int oy, i
   return __builtin_bit_cast(bf16x8, u);
 }
 
-// Encoder forward: a2[b][co*256 + oy*16 + ox] = bf16(relu(conv2(relu(conv1(crop_b))))).
+// Encoder forward: a2[b * lda2 + co*256 + oy*16 + ox] = bf16(relu(conv2(relu(conv1(crop_b))))).
 __global__ __launch_bounds__(256) void k_conv_fwd(const float* prm, Offsets o, const int16_t* crop, uint16_t* a2,
-                                                  int B) {
+                                                  int64_t lda2, int B) {
   __shared__ __align__(16) uint16_t s_crop[kCropLds];
   __shared__ __align__(16) uint16_t s_a1[kA1Lds];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
@@ -191,7 +191,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const float* prm, Offsets o, c
         acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, w2f[0][s], acc0, 0, 0, 0);
         acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, w2f[1][s], acc1, 0, 0, 0);
       }
-      uint16_t* dst = a2 + (int64_t)b * kFeat + oy * kA2 + 4 * lg;
+      uint16_t* dst = a2 + (int64_t)b * lda2 + oy * kA2 + 4 * lg;
       *reinterpret_cast<uint2*>(dst + lr * 256) =
           make_uint2(pack_bf16x2(fmaxf(acc0[0] + b2[0], 0.0f), fmaxf(acc0[1] + b2[0], 0.0f)),
                      pack_bf16x2(fmaxf(acc0[2] + b2[0], 0.0f), fmaxf(acc0[3] + b2[0], 0.0f)));

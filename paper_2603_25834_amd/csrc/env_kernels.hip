@@ -432,6 +432,8 @@ __device__ void stage_world(const EnvParams& P, const RobotMeta& m, int32_t cy, 
   wy0 = y0;
 }
 
+constexpr int kLook = 8;   // DDA steps per LDS round trip in the march
+
 // LiDAR march of every ray of the robot from the true pose (lanes = rays).
 template <int NT>
 __device__ void march_rays(const EnvParams& P, const RobotMeta& m, const LdsView& V, const uint32_t* sw,
@@ -468,41 +470,46 @@ __device__ void march_rays(const EnvParams& P, const RobotMeta& m, const LdsView
       hit = (sw[li >> 5] >> (li & 31)) & 1u;
       done = hit || q.n == 0;
     }
-    // Four cells per iteration: the next four DDA steps are taken first and
-    // their world words read together, so one LDS round trip covers four
+    // kLook cells per iteration: the next kLook DDA steps are taken first and
+    // their world words read together, so one LDS round trip covers kLook
     // cells.  Steps past the walk's own count n are read (word index clamped
     // to the staged buffer) but never count as hits.
     while (__builtin_amdgcn_ballot_w64(!done) != 0) {
       if (!done) {
-        int32_t l[4], d[4];
+        int32_t l[kLook], d[kLook];
         int32_t lc = li, dc = D;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < kLook; ++u) {
           const bool stepx = dc <= 0;
           lc += stepx ? sx : sy;
           dc += stepx ? q.DX : -q.DY;
           l[u] = lc;
           d[u] = dc;
         }
-        uint32_t wd[4];
+        uint32_t wd[kLook];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) wd[u] = sw[min(max(l[u] >> 5, 0), wmax)];
+        for (int u = 0; u < kLook; ++u) wd[u] = sw[min(max(l[u] >> 5, 0), wmax)];
         uint32_t bits = 0u;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) bits |= ((wd[u] >> (l[u] & 31)) & 1u) << u;
+        for (int u = 0; u < kLook; ++u) bits |= ((wd[u] >> (l[u] & 31)) & 1u) << u;
         const int32_t rem = q.n - i;   // >= 1 while the lane walks
-        bits &= rem >= 4 ? 0xfu : ((1u << rem) - 1u);
+        bits &= rem >= kLook ? (1u << kLook) - 1u : ((1u << rem) - 1u);
         if (bits) {
           const int32_t u = __builtin_ctz(bits);
-          li = u == 0 ? l[0] : u == 1 ? l[1] : u == 2 ? l[2] : l[3];
-          D = u == 0 ? d[0] : u == 1 ? d[1] : u == 2 ? d[2] : d[3];
+#pragma unroll
+          for (int j = 0; j < kLook; ++j) {
+            if (u == j) {
+              li = l[j];
+              D = d[j];
+            }
+          }
           i += u + 1;
           hit = true;
           done = true;
         } else {
-          li = l[3];
-          D = d[3];
-          i = min(i + 4, q.n);
+          li = l[kLook - 1];
+          D = d[kLook - 1];
+          i = min(i + kLook, q.n);
           done = i >= q.n;
         }
       }

@@ -31,7 +31,8 @@ struct aslam_policy {
   aslam_policy_config cfg{};
   Offsets off{};
   int64_t max_b = 0;
-  uint16_t *a2 = nullptr, *h1 = nullptr, *dz2 = nullptr, *dz1 = nullptr, *dz2c = nullptr;
+  uint16_t *x = nullptr;   // FC1 input [B][k1p]: conv features (8192) | scan | state | zero pad, BF16
+  uint16_t *h1 = nullptr, *dz2 = nullptr, *dz1 = nullptr, *dz2c = nullptr;
   float *z2 = nullptr, *part = nullptr, *hpart = nullptr, *hsum = nullptr;
   uint16_t *w1b = nullptr, *w1t = nullptr, *w2b = nullptr, *w2t = nullptr;   // BF16 weight copies
   int32_t k1p = 0;   // FC1 input width padded to a multiple of 8
@@ -102,20 +103,25 @@ int forward_core(aslam_policy* P, const float* prm, const int16_t* crop, const f
     k_transpose_bf16<<<dim3(kHid / 32, kHid / 32), 256, 0, st>>>(prm + o.f2w, kHid, kHid, kHid, P->w2t, kHid);
     PCHK(hipGetLastError());
   }
-  k_conv_fwd<<<std::min(B, kConvGrid), 256, 0, st>>>(prm, o, crop, P->a2, B);
+  k_conv_fwd<<<std::min(B, kConvGrid), 256, 0, st>>>(prm, o, crop, P->x, P->k1p, B);
   PCHK(hipGetLastError());
-  // FC1: [B x k1] x [k1 x 256]; small batches split K so that the launch fills the chip
-  XSrc xs{P->a2, scan, state, R, B, o.k1};
+  k_pack_tail<<<(int)std::min<int64_t>(1024, ((int64_t)B * (P->k1p - kFeat) + 255) / 256), 256, 0, st>>>(
+      scan, state, R, B, P->x, P->k1p);
+  PCHK(hipGetLastError());
+  // FC1: [B x k1p] x [k1p x 256] (both operands zero-padded from k1 to k1p); small batches split K
+  // so that the launch fills the chip
+  const int K1 = P->k1p;
+  const LdBF16K xa{P->x, K1, B, K1};
+  const LdBF16K wa{P->w1b, K1, kHid, K1};
   const int tiles = ((B + 127) / 128) * (kHid / 128);
   int S = 1;
   while (tiles * S < kFc1MinBlocks && S < 32) S *= 2;
   if (S == 1) {
-    PCHK((gemm::run<128, 128, 64, 2, 2>(LdXK{xs}, LdBF16K{P->w1b, P->k1p, kHid, o.k1},
-                                         EpiBiasReluBF16{P->h1, prm + o.f1b, kHid}, B, kHid, o.k1, 1, st)));
+    PCHK((gemm::run<128, 128, 64, 2, 2>(xa, wa, EpiBiasReluBF16{P->h1, prm + o.f1b, kHid}, B, kHid, K1, 1, st)));
   } else {
-    const int used = slices_used(o.k1, S, 64);
-    PCHK((gemm::run<128, 128, 64, 2, 2>(LdXK{xs}, LdBF16K{P->w1b, P->k1p, kHid, o.k1},
-                                         EpiPartial{P->part, kHid, (int64_t)B * kHid}, B, kHid, o.k1, S, st)));
+    const int used = slices_used(K1, S, 64);
+    PCHK((gemm::run<128, 128, 64, 2, 2>(xa, wa, EpiPartial{P->part, kHid, (int64_t)B * kHid}, B, kHid, K1, S,
+                                         st)));
     const int64_t groups = (int64_t)B * (kHid / 8);
     k_reduce_bias_relu_bf16<<<(int)std::min<int64_t>(4096, (groups + 255) / 256), 256, 0, st>>>(
         P->part, used, B, kHid, prm + o.f1b, P->h1, kHid);
@@ -150,7 +156,7 @@ int aslam_policy_create(const aslam_policy_config* cfg, aslam_policy** out) {
   p->part_floats = part_need(p);
   p->k1p = (p->off.k1 + 7) / 8 * 8;
   struct A { void** ptr; size_t bytes; } al[] = {
-      {(void**)&p->a2, 2 * (size_t)Bm * kFeat},  {(void**)&p->h1, 2 * (size_t)Bm * kHid},
+      {(void**)&p->x, 2 * (size_t)Bm * ((p->off.k1 + 7) / 8 * 8)},  {(void**)&p->h1, 2 * (size_t)Bm * kHid},
       {(void**)&p->dz2, 2 * (size_t)Bm * kHid},  {(void**)&p->dz1, 2 * (size_t)Bm * kHid},
       {(void**)&p->dz2c, 2 * (size_t)Bm * kFeat}, {(void**)&p->z2, 4 * (size_t)Bm * kHid},
       {(void**)&p->part, 4 * (size_t)p->part_floats},
@@ -171,7 +177,7 @@ int aslam_policy_create(const aslam_policy_config* cfg, aslam_policy** out) {
 
 int aslam_policy_destroy(aslam_policy* p) {
   if (!p) return pfail(ASL_EINVAL, "policy is NULL");
-  void* ptrs[] = {p->a2, p->h1, p->dz2, p->dz1, p->dz2c, p->z2, p->part, p->hpart, p->hsum,
+  void* ptrs[] = {p->x, p->h1, p->dz2, p->dz1, p->dz2c, p->z2, p->part, p->hpart, p->hsum,
                   p->w1b, p->w1t, p->w2b, p->w2t};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
@@ -227,23 +233,22 @@ int aslam_policy_backward(aslam_policy* P, const float* params, const int16_t* c
   }
   // dh1 -> dz1 = (dz2 W2) * [h1 > 0]
   PCHK((gemm::run<128, 128, 64, 2, 2>(LdBF16K{P->dz2, kHid, B, kHid}, LdBF16K{P->w2t, kHid, kHid, kHid},
-                                     EpiReluGradBF16{P->dz1, P->h1, kHid}, B, kHid, kHid, 1, st)));
+                                     EpiReluGradBF16{P->dz1, P->h1, kHid, kHid}, B, kHid, kHid, 1, st)));
   // FC1 bias
   k_bias_rows<<<kBiasBlocks, 256, 0, st>>>(P->dz1, B, kHid, part);
   PCHK(hipGetLastError());
   PCHK(launch_reduce(part, kBiasBlocks, kHid, grads + o.f1b, 0, kHid, st));
   // FC1 weight: dW1[out][k] = sum_b dz1[b][out] X[b][k]
-  XSrc xs{P->a2, scan, state, R, B, o.k1};
   {
     const int64_t S = splits_balanced(B, 64, 2 * (int64_t)((o.k1 + 127) / 128), 512, kFc1Splits);
     const int S_used = slices_used(B, S, 64);
-    PCHK((gemm::run<128, 128, 64, 2, 2>(LdBF16I{P->dz1, kHid, kHid, B}, LdXI{xs},
+    PCHK((gemm::run<128, 128, 64, 2, 2>(LdBF16I{P->dz1, kHid, kHid, B}, LdBF16I{P->x, P->k1p, o.k1, B},
                                        EpiPartial{part, o.k1, (int64_t)kHid * o.k1}, kHid, o.k1, B, (int)S, st)));
     PCHK(launch_reduce(part, S_used, (int64_t)kHid * o.k1, grads + o.f1w, 0, (int64_t)kHid * o.k1, st));
   }
   // dA2 -> dz2c = (dz1 W1[:, :8192]) * [a2 > 0]
   PCHK((gemm::run<128, 128, 64, 2, 2>(LdBF16K{P->dz1, kHid, B, kHid}, LdBF16K{P->w1t, kHid, kFeat, kHid},
-                                     EpiReluGradBF16{P->dz2c, P->a2, kFeat}, B, kFeat, kHid, 1, st)));
+                                     EpiReluGradBF16{P->dz2c, P->x, kFeat, P->k1p}, B, kFeat, kHid, 1, st)));
   // encoder: conv2 / conv1 weight and bias gradients in one pass over the minibatch
   {
     const int grid = std::min(B, kConvBwdGrid);

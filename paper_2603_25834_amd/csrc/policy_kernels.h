@@ -97,45 +97,6 @@ struct LdBF16I {
   }
 };
 
-// FC1 input X[b][k] = [a2 (BF16, 8192) | scan (FP32, R) | state (FP32, 12)].
-struct XSrc {
-  const uint16_t* a2; const float* scan; const float* state; int R; int B; int k1;
-  __device__ __forceinline__ uint16_t at(int b, int k) const {
-    if (k < kFeat) return a2[(int64_t)b * kFeat + k];
-    if (k < kFeat + R) return f2bf(scan[(int64_t)b * R + (k - kFeat)]);
-    if (k < k1) return f2bf(state[(int64_t)b * 12 + (k - kFeat - R)]);
-    return 0;
-  }
-};
-
-// A operand of FC1 forward: (i = b, k).
-struct LdXK {
-  static constexpr bool kMajor = true;
-  XSrc x;
-  __device__ uint4 fetch(int i, int k) const {
-    if (i >= x.B) return make_uint4(0u, 0u, 0u, 0u);
-    if (k + 8 <= kFeat) return *reinterpret_cast<const uint4*>(x.a2 + (int64_t)i * kFeat + k);
-    uint16_t v[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) v[j] = x.at(i, k + j);
-    return pack8(v);
-  }
-};
-
-// B operand of the FC1 weight gradient: B(k = b, n = i) = X[b][i], contiguous along i.
-struct LdXI {
-  static constexpr bool kMajor = false;
-  XSrc x;
-  __device__ uint4 fetch(int i, int k) const {
-    if (k >= x.B || i >= x.k1) return make_uint4(0u, 0u, 0u, 0u);
-    if (i + 8 <= kFeat) return *reinterpret_cast<const uint4*>(x.a2 + (int64_t)k * kFeat + i);
-    uint16_t v[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) v[j] = x.at(k, i + j);
-    return pack8(v);
-  }
-};
-
 // ---------------------------------------------------------------- epilogues
 // store8(m, n0, v, nvalid): row m, columns n0 .. n0 + nvalid - 1 (n0 multiple of 8).
 
@@ -185,17 +146,17 @@ struct EpiPartial {
 
 // Gradient through a ReLU whose output (BF16) is `act`: out = bf16(act > 0 ? v : 0).
 struct EpiReluGradBF16 {
-  uint16_t* out; const uint16_t* act; int64_t ld;
+  uint16_t* out; const uint16_t* act; int64_t ld, ld_act;
   __device__ void store8(int m, int n0, const float* v, int nvalid) const {
-    const int64_t o = (int64_t)m * ld + n0;
-    if (nvalid == 8 && ((o & 7) == 0)) {
-      const uint4 a = *reinterpret_cast<const uint4*>(act + o);
+    const int64_t o = (int64_t)m * ld + n0, oa = (int64_t)m * ld_act + n0;
+    if (nvalid == 8 && ((o & 7) == 0) && ((oa & 7) == 0)) {
+      const uint4 a = *reinterpret_cast<const uint4*>(act + oa);
       uint16_t h[8];
 #pragma unroll
       for (int j = 0; j < 8; ++j) h[j] = bf2f(gemm::lane16(a, j)) > 0.0f ? f2bf(v[j]) : (uint16_t)0;
       *reinterpret_cast<uint4*>(out + o) = pack8(h);
     } else {
-      for (int j = 0; j < nvalid; ++j) out[o + j] = bf2f(act[o + j]) > 0.0f ? f2bf(v[j]) : (uint16_t)0;
+      for (int j = 0; j < nvalid; ++j) out[o + j] = bf2f(act[oa + j]) > 0.0f ? f2bf(v[j]) : (uint16_t)0;
     }
   }
 };
@@ -521,6 +482,22 @@ __global__ __launch_bounds__(256) void k_transpose_bf16(const float* src, int64_
   for (int k = ty; k < 32; k += 8) {
     const int c = c0 + k, r = r0 + tx;
     if (c < cols && r < rows) dst[(int64_t)c * ld_dst + r] = f2bf(tile[tx][k]);
+  }
+}
+
+// FC1 input tail: X[b][8192 + j] = bf16(scan[b][j]), X[b][8192 + R + j] = bf16(state[b][j]), zero up
+// to the padded width ldx (the conv features X[b][0 .. 8191] are written by the encoder).
+__global__ void k_pack_tail(const float* scan, const float* state, int R, int B, uint16_t* x, int64_t ldx) {
+  const int tail = (int)(ldx - kFeat);
+  const int64_t total = (int64_t)B * tail;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = i / tail;
+    const int j = (int)(i - b * tail);
+    float v = 0.0f;
+    if (j < R) v = scan[b * R + j];
+    else if (j < R + 12) v = state[b * 12 + (j - R)];
+    x[b * ldx + kFeat + j] = j < R + 12 ? f2bf(v) : (uint16_t)0;
   }
 }
 
