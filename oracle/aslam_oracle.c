@@ -193,6 +193,87 @@ static int32_t visit_side(const orc_config* cfg, int32_t s) {
   return (int32_t)ceil((double)s * (double)cfg->cell_m / (double)cfg->lc_cell_m);
 }
 
+/* The visit grid is kept for loop closure and for the paper's exploration reward. */
+static int uses_visits(const orc_config* cfg) { return cfg->loop_closure || cfg->reward_mode == 1; }
+
+/* Ray fan (Sec. IV-A): R rays equally spaced over fov heading steps; a full
+ * circle starts along the heading, a partial fan at -fov/2 (reading). */
+static int32_t fan_steps(const orc_config* cfg) {
+  return (cfg->fov_steps > 0 && cfg->fov_steps < ORC_NANG) ? cfg->fov_steps : ORC_NANG;
+}
+static int32_t fan_start(const orc_config* cfg) {
+  int32_t f = fan_steps(cfg);
+  return f == ORC_NANG ? 0 : ORC_NANG - f / 2;
+}
+
+int32_t orc_noise_width(const orc_config* cfg) { return 5 + (cfg->range_sigma_m > 0.0f ? cfg->n_rays : 0); }
+
+/* The reported range goes through the sensor model (noise, quantisation,
+ * minimum range) when any of its parameters is set. */
+static int sensor_model(const orc_config* cfg) {
+  return cfg->range_sigma_m > 0.0f || cfg->range_quant_m > 0.0f || cfg->r_min_m > 0.0f;
+}
+
+/* det Sigma by cofactors along row 0, FP64 from the FP32 entries. */
+static double cov_det(const float* c) {
+  return (double)c[0] * ((double)c[3] * c[5] - (double)c[4] * c[4]) -
+         (double)c[1] * ((double)c[1] * c[5] - (double)c[4] * c[2]) +
+         (double)c[2] * ((double)c[1] * c[4] - (double)c[3] * c[2]);
+}
+
+/* SLAM uncertainty scalar U_t (reading: the cube root of det Sigma, the
+ * geometric mean of the covariance eigenvalues; 0 if det <= 0). */
+static double uncertainty(const float* c) {
+  double d = cov_det(c);
+  return d > 0.0 ? cbrt(d) : 0.0;
+}
+
+static double clip01(double v) { return v < 0.0 ? 0.0 : (v > 1.0 ? 1.0 : v); }
+
+/* Eq. (7): -lambda_col on collision, else R*_explore - R_abs + R*_Delta with
+ *   R_explore = lambda_explore * dcells * I                         (Eq. 8)
+ *   I = c + (1 - c) iota, c = clip((U_hi - U_{t-1}) / U_hi)^2,
+ *   iota = clip(max(U_{t-1} - U_t, 0) / kappa)                     (Eqs. 10-12)
+ *   R_abs = lambda_abs e^{U_{t-1}} U_{t-1}                           (Eq. 13)
+ *   R_Delta = lambda_Delta e^{U_{t-1}} (U_{t-1} - U_t)               (Eq. 14)
+ *   alpha = clip((d_min - d_crash) / (d_full - d_crash))             (Eq. 15)
+ *   R*_explore = alpha R_explore; R*_Delta = alpha R_Delta if U fell, else R_Delta (Eqs. 16-17). */
+double orc_paper_reward(const orc_config* cfg, int collided, double dcells, double u_prev, double u,
+                        double d_min) {
+  if (collided) return -(double)cfg->lambda_col;
+  double cg = clip01(((double)cfg->u_hi - u_prev) / (double)cfg->u_hi);
+  cg = cg * cg;
+  double iota = clip01(fmax(u_prev - u, 0.0) / (double)cfg->kappa);
+  double in = cg + (1.0 - cg) * iota;
+  double r_explore = (double)cfg->lambda_explore * dcells * in;
+  double eu = exp(u_prev);
+  double r_abs = (double)cfg->lambda_abs * eu * u_prev;
+  double r_delta = (double)cfg->lambda_delta * eu * (u_prev - u);
+  double alpha = clip01((d_min - (double)cfg->d_crash_m) / ((double)cfg->d_full_m - (double)cfg->d_crash_m));
+  return r_explore * alpha - r_abs + (u_prev - u > 0.0 ? r_delta * alpha : r_delta);
+}
+
+/* Proximity collision (Sec. IV-A): some occupied (or off-grid) cell within
+ * d_crash of the Q16 point, by the exact integer point-to-square distance. */
+static int near_obstacle(const orc_config* cfg, const uint32_t* W, int32_t s, int64_t px, int64_t py) {
+  int64_t rc = llround((double)cfg->d_crash_m / (double)cfg->cell_m * 65536.0);
+  int64_t cx = floor_div_q16(px), cy = floor_div_q16(py);
+  int64_t m = rc / ORC_Q16 + 1;
+  for (int64_t j = cy - m; j <= cy + m; ++j)
+    for (int64_t i = cx - m; i <= cx + m; ++i) {
+      int occ = (i < 0 || j < 0 || i >= s || j >= s) ? 1 : world_occ(W, s, (int32_t)i, (int32_t)j);
+      if (!occ) continue;
+      int64_t dx = i * ORC_Q16 - px, dy = j * ORC_Q16 - py;
+      int64_t ux = px - (i + 1) * ORC_Q16, uy = py - (j + 1) * ORC_Q16;
+      if (ux > dx) dx = ux;
+      if (uy > dy) dy = uy;
+      if (dx < 0) dx = 0;
+      if (dy < 0) dy = 0;
+      if (dx * dx + dy * dy < rc * rc) return 1;
+    }
+  return 0;
+}
+
 void orc_reset(const orc_config* cfg, orc_state* st, const float* init_pose, const uint8_t* mask) {
   int32_t lc = orc_logodds_q(cfg->l_clamp);
   uint32_t* hq = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)(2 * lc + 1));
@@ -212,12 +293,15 @@ void orc_reset(const orc_config* cfg, orc_state* st, const float* init_pose, con
     st->h_q[r] = (int64_t)s * (int64_t)s * (int64_t)hq[lc];
     st->step[r] = 0;
     st->last_lc[r] = -(1 << 30);
-    if (cfg->loop_closure) {
+    st->prev_vcell[r] = -1;
+    st->u_prev[r] = uncertainty(c);
+    if (uses_visits(cfg)) {
       int32_t nv = visit_side(cfg, s);
       for (int64_t k = 0; k < (int64_t)nv * nv; ++k) {
         st->visit_t[st->visit_off[r] + k] = -1;
         st->visit_x[st->visit_off[r] + k] = 0.0f;
         st->visit_y[st->visit_off[r] + k] = 0.0f;
+        st->visit_last[st->visit_off[r] + k] = -1;
       }
     }
   }
@@ -277,6 +361,10 @@ static void step_robot(const orc_config* cfg, const orc_tables* T, orc_state* st
   } else {
     p[0] = nx; p[1] = ny; p[2] = nth;
   }
+  /* the paper's collision: closer than d_crash to an obstacle (the move stands) */
+  if (cfg->d_crash_m > 0.0f && !collided &&
+      near_obstacle(cfg, W, s, to_q16(p[0], inv_c16), to_q16(p[1], inv_c16)))
+    collided = 1;
 
   /* --- EKF predict with the commanded motion (F from the heading before the step) */
   {
@@ -300,9 +388,10 @@ static void step_robot(const orc_config* cfg, const orc_tables* T, orc_state* st
     e[2] = wrap_pi(e[2] + phi);
   }
 
-  /* --- loop closure: GT position back within the radius of its first visit */
-  int closed = 0;
-  if (cfg->loop_closure) {
+  /* --- visit cell of the GT position (loop closure, exploration reward) */
+  int64_t vk = -1;
+  int32_t vcell = -1;
+  if (uses_visits(cfg)) {
     int32_t nv = visit_side(cfg, s);
     float inv_lc = (float)(1.0 / (double)cfg->lc_cell_m);
     int32_t vxi = (int32_t)floorf(p[0] * inv_lc);
@@ -311,7 +400,26 @@ static void step_robot(const orc_config* cfg, const orc_tables* T, orc_state* st
     if (vxi > nv - 1) vxi = nv - 1;
     if (vyi < 0) vyi = 0;
     if (vyi > nv - 1) vyi = nv - 1;
-    int64_t vk = st->visit_off[r] + (int64_t)vyi * nv + vxi;
+    vcell = vyi * nv + vxi;
+    vk = st->visit_off[r] + vcell;
+  }
+  /* --- exploration novelty (Eq. 9): 1 on entering a never-visited cell, half the
+   * fraction of an episode since the last visit on re-entering one, 0 while the
+   * robot stays in the cell it was in at the previous step */
+  double dcells = 0.0;
+  if (cfg->reward_mode == 1) {
+    if (vcell != st->prev_vcell[r]) {
+      int32_t last = st->visit_last[vk];
+      double tep = (double)(cfg->episode_len > 0 ? cfg->episode_len : 2048);
+      dcells = last < 0 ? 1.0 : fmin(1.0, 0.5 * (double)(t - last) / tep);
+    }
+    st->visit_last[vk] = t;
+    st->prev_vcell[r] = vcell;
+  }
+
+  /* --- loop closure: GT position back within the radius of its first visit */
+  int closed = 0;
+  if (cfg->loop_closure) {
     if (st->visit_t[vk] < 0) {
       st->visit_t[vk] = t;
       st->visit_x[vk] = p[0];
@@ -353,7 +461,12 @@ static void step_robot(const orc_config* cfg, const orc_tables* T, orc_state* st
 
   /* --- LiDAR march from the true pose through the world */
   const int64_t rmax_q = llround((double)cfg->r_max_m / (double)cfg->cell_m * 65536.0);
-  const int32_t step_ang = ORC_NANG / R;
+  const int32_t step_ang = fan_steps(cfg) / R;
+  const int32_t ray0 = fan_start(cfg);
+  const int32_t G = orc_noise_width(cfg);
+  const int sensed = sensor_model(cfg);
+  const float inv_quant = cfg->range_quant_m > 0.0f ? (float)(1.0 / (double)cfg->range_quant_m) : 0.0f;
+  double d_min = 1.0e30;
   const float c16 = (float)((double)cfg->cell_m / 65536.0);
   float* ranges = out->ranges + (int64_t)r * R;
   int32_t* rho = out->rho_q + (int64_t)r * R;
@@ -363,7 +476,7 @@ static void step_robot(const orc_config* cfg, const orc_tables* T, orc_state* st
     int32_t ib = orc_heading_index(p[2]);
     int64_t tx = to_q16(p[0], inv_c16), ty = to_q16(p[1], inv_c16);
     for (int32_t k = 0; k < R; ++k) {
-      int32_t id = (ib + k * step_ang) % ORC_NANG;
+      int32_t id = (ib + ray0 + k * step_ang) % ORC_NANG;
       int64_t a = T->cq[id], b = T->sq[id];
       walker wk;
       walk_init(&wk, tx, ty, a, b, ORC_DIR_ONE, rmax_q, s);
@@ -385,9 +498,20 @@ static void step_robot(const orc_config* cfg, const orc_tables* T, orc_state* st
           break;
         }
       }
-      rho[k] = (int32_t)rq;
+      /* reported range (Sec. IV-A sensor): true range + sigma * normal, rounded
+       * to the quantum, clamped to [r_min, r_max]; the map update walks to it */
+      float rep = (float)rq * c16;
+      int64_t rho_u = rq;
+      if (sensed) {
+        if (cfg->range_sigma_m > 0.0f) rep = rep + cfg->range_sigma_m * g[5 + k];
+        if (cfg->range_quant_m > 0.0f) rep = rintf(rep * inv_quant) * cfg->range_quant_m;
+        rep = fminf(fmaxf(rep, cfg->r_min_m), cfg->r_max_m);
+        rho_u = to_q16(rep, inv_c16);
+      }
+      rho[k] = (int32_t)rho_u;
       hitc[k] = hc;
-      ranges[k] = (float)rq * c16;
+      ranges[k] = rep;
+      if ((double)rep < d_min) d_min = (double)rep;
     }
   }
   memset(code, 0, (size_t)s * (size_t)s);
@@ -401,7 +525,7 @@ static void step_robot(const orc_config* cfg, const orc_tables* T, orc_state* st
     if (ecx >= 0 && ecx < s && ecy >= 0 && ecy < s) {
       int32_t ib = orc_heading_index(e[2]);
       for (int32_t k = 0; k < R; ++k) {
-        int32_t id = (ib + k * step_ang) % ORC_NANG;
+        int32_t id = (ib + ray0 + k * step_ang) % ORC_NANG;
         walker wk;
         walk_init(&wk, ex, ey, T->cq[id], T->sq[id], ORC_DIR_ONE, rho[k], s);
         int64_t last = -1;
@@ -426,16 +550,21 @@ static void step_robot(const orc_config* cfg, const orc_tables* T, orc_state* st
   }
   st->h_q[r] += dH;
 
-  /* --- reward: entropy decrease + D-opt (-ln det Sigma) - collision penalty */
+  /* --- reward: entropy decrease + D-opt (-ln det Sigma) - collision penalty, or
+   * the paper's Eq. (7) */
   double rH = (double)(-dH) / 4294967296.0;
-  double det = (double)c[0] * ((double)c[3] * c[5] - (double)c[4] * c[4]) -
-               (double)c[1] * ((double)c[1] * c[5] - (double)c[4] * c[2]) +
-               (double)c[2] * ((double)c[1] * c[4] - (double)c[3] * c[2]);
+  double det = cov_det(c);
   double ld = det > 0.0 ? log(det) : log(1.17549435e-38);
   out->r_entropy[r] = rH;
   out->logdet[r] = ld;
-  out->reward[r] = (double)cfg->w_entropy * rH - (double)cfg->w_dopt * ld -
-                   (double)cfg->lambda_col * (double)collided;
+  if (cfg->reward_mode == 1) {
+    double u = uncertainty(c);
+    out->reward[r] = orc_paper_reward(cfg, collided, dcells, st->u_prev[r], u, d_min);
+    st->u_prev[r] = u;
+  } else {
+    out->reward[r] = (double)cfg->w_entropy * rH - (double)cfg->w_dopt * ld -
+                     (double)cfg->lambda_col * (double)collided;
+  }
   out->collided[r] = (uint8_t)collided;
   out->closed[r] = (uint8_t)closed;
   out->done[r] = (uint8_t)(collided || (cfg->episode_len > 0 && t + 1 >= cfg->episode_len));
@@ -462,7 +591,7 @@ void orc_step(const orc_config* cfg, orc_state* st, const float* actions, const 
     uint8_t* code = (uint8_t*)malloc((size_t)smax * (size_t)smax);
 #pragma omp for schedule(dynamic, 1)
     for (int32_t r = 0; r < st->n; ++r)
-      step_robot(cfg, T, st, r, actions + 2 * (int64_t)r, noise + 5 * (int64_t)r, out, code);
+      step_robot(cfg, T, st, r, actions + 2 * (int64_t)r, noise + (int64_t)orc_noise_width(cfg) * r, out, code);
     free(code);
   }
   free(T->hq);
@@ -485,10 +614,17 @@ void orc_observe(const orc_config* cfg, const orc_state* st, const float* ranges
     for (int32_t k = 0; k < R; ++k) scan[(int64_t)r * R + k] = ranges[(int64_t)r * R + k] * inv_r;
     const float inv_ext = (float)(1.0 / ((double)s * (double)cfg->cell_m));
     float* o = state12 + 12 * (int64_t)r;
-    o[0] = e[0] * inv_ext; o[1] = e[1] * inv_ext; o[2] = e[2] * inv_pi;
-    o[3] = c[0]; o[4] = c[1]; o[5] = c[2];
-    o[6] = c[1]; o[7] = c[3]; o[8] = c[4];
-    o[9] = c[2]; o[10] = c[4]; o[11] = c[5];
+    if (cfg->reward_mode == 1) {
+      /* Eq. (3): [LiDAR, yaw, U_t]; yaw from the IMU (true heading), U_t of the filter */
+      for (int k = 0; k < 12; ++k) o[k] = 0.0f;
+      o[0] = st->pose[3 * r + 2] * inv_pi;
+      o[1] = (float)uncertainty(c);
+    } else {
+      o[0] = e[0] * inv_ext; o[1] = e[1] * inv_ext; o[2] = e[2] * inv_pi;
+      o[3] = c[0]; o[4] = c[1]; o[5] = c[2];
+      o[6] = c[1]; o[7] = c[3]; o[8] = c[4];
+      o[9] = c[2]; o[10] = c[4]; o[11] = c[5];
+    }
     int64_t ecx = floor_div_q16(to_q16(e[0], inv_c16));
     int64_t ecy = floor_div_q16(to_q16(e[1], inv_c16));
     const int16_t* L = st->belief + st->cell_off[r];

@@ -16,6 +16,11 @@
  *   - pose covariance as the uncertainty source, D-optimality: Sec. III-D,
  *     Eq. (6); Sec. II (Table I, "D-opt").
  *   - collision penalty and episode end: Sec. III-E, Eq. (7); Sec. IV-A.
+ *   - the paper's reward (reward_mode 1): Sec. III-E, Eqs. (7)-(17) -- exploration
+ *     reward with the cell-novelty factor and the intrinsic scaling, absolute and
+ *     differential uncertainty terms, anti-wall-hugging factor; sensor model of
+ *     Sec. IV-A (front field of view, minimum range, range noise, quantisation,
+ *     proximity collision); observation [LiDAR, yaw, U_t] of Sec. III-C, Eq. (3).
  * Where the paper is silent the readings are listed in DESIGN.md ("Readings").
  *
  * Parity status: every function here is pinned by a CPU test (closed forms,
@@ -47,6 +52,15 @@ typedef struct {
   float lc_cell_m, lc_radius_m, lc_sigma_m; /* loop-closure visit cell, radius, fix std */
   float l_hit, l_miss, l_clamp;      /* log-odds increments and clamp (nats) */
   float w_entropy, w_dopt, lambda_col; /* reward weights */
+  /* sensor model and the paper's reward (zeros keep the workload's step) */
+  int32_t fov_steps;     /* heading steps spanned by the ray fan; 0 or ORC_NANG = full circle */
+  int32_t reward_mode;   /* 0 workload reward, 1 the paper's Eq. (7) */
+  float r_min_m;         /* reported ranges below this are raised to it */
+  float range_sigma_m;   /* range noise std; then the noise input has R more normals per robot */
+  float range_quant_m;   /* reported ranges rounded to multiples of this */
+  float d_crash_m;       /* proximity collision distance (0 = off) */
+  float d_full_m;        /* clearance at which the wall-hugging factor reaches 1 */
+  float lambda_explore, lambda_abs, lambda_delta, u_hi, kappa;
 } orc_config;
 
 /* Per-robot state, caller-owned arrays (robots are independent). */
@@ -67,6 +81,9 @@ typedef struct {
   int32_t* visit_t;          /* ragged first-visit step (-1 none) */
   float* visit_x;            /* ragged first-visit position */
   float* visit_y;
+  int32_t* visit_last;       /* ragged last-visit step (-1 none; reward_mode 1) */
+  int32_t* prev_vcell;       /* [n] visit cell of the previous step (-1 none; reward_mode 1) */
+  double* u_prev;            /* [n] U_{t-1} = cbrt(det Sigma) of the previous step (reward_mode 1) */
 } orc_state;
 
 typedef struct {
@@ -98,6 +115,11 @@ int32_t orc_walk(int64_t ox, int64_t oy, int64_t a, int64_t b, int64_t scale, in
                  int32_t max_out, int32_t* end_reason);
 
 void orc_reset(const orc_config* cfg, orc_state* st, const float* init_pose, const uint8_t* mask);
+/* Normal draws per robot and step in the noise input: 5, plus R with range noise. */
+int32_t orc_noise_width(const orc_config* cfg);
+/* The paper's reward, Eq. (7) with Eqs. (8)-(17), from its inputs (all FP64). */
+double orc_paper_reward(const orc_config* cfg, int collided, double delta_cells, double u_prev, double u,
+                        double d_min);
 void orc_step(const orc_config* cfg, orc_state* st, const float* actions, const float* noise,
               orc_out* out, int32_t n_threads);
 void orc_observe(const orc_config* cfg, const orc_state* st, const float* ranges, int16_t* crop,

@@ -45,6 +45,11 @@ class OrcConfig(ctypes.Structure):
         ("lc_cell_m", ctypes.c_float), ("lc_radius_m", ctypes.c_float), ("lc_sigma_m", ctypes.c_float),
         ("l_hit", ctypes.c_float), ("l_miss", ctypes.c_float), ("l_clamp", ctypes.c_float),
         ("w_entropy", ctypes.c_float), ("w_dopt", ctypes.c_float), ("lambda_col", ctypes.c_float),
+        ("fov_steps", ctypes.c_int32), ("reward_mode", ctypes.c_int32),
+        ("r_min_m", ctypes.c_float), ("range_sigma_m", ctypes.c_float), ("range_quant_m", ctypes.c_float),
+        ("d_crash_m", ctypes.c_float), ("d_full_m", ctypes.c_float),
+        ("lambda_explore", ctypes.c_float), ("lambda_abs", ctypes.c_float), ("lambda_delta", ctypes.c_float),
+        ("u_hi", ctypes.c_float), ("kappa", ctypes.c_float),
     ]
 
 
@@ -54,7 +59,7 @@ _P = ctypes.c_void_p
 class OrcState(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32)] + [(f, _P) for f in (
         "side", "world_off", "cell_off", "visit_off", "world", "belief", "pose", "est", "cov",
-        "h_q", "step", "last_lc", "visit_t", "visit_x", "visit_y")]
+        "h_q", "step", "last_lc", "visit_t", "visit_x", "visit_y", "visit_last", "prev_vcell", "u_prev")]
 
 
 class OrcOut(ctypes.Structure):
@@ -85,6 +90,11 @@ def lib():
                                ctypes.POINTER(OrcOut), ctypes.c_int32]
         L.orc_observe.argtypes = [ctypes.POINTER(OrcConfig), ctypes.POINTER(OrcState), _P, _P,
                                   ctypes.c_int32, _P, _P]
+        L.orc_noise_width.argtypes = [ctypes.POINTER(OrcConfig)]
+        L.orc_noise_width.restype = ctypes.c_int32
+        L.orc_paper_reward.argtypes = [ctypes.POINTER(OrcConfig), ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                       ctypes.c_double, ctypes.c_double]
+        L.orc_paper_reward.restype = ctypes.c_double
         _lib = L
     return _lib
 
@@ -134,6 +144,18 @@ def make_config(p: dict) -> OrcConfig:
     return c
 
 
+def noise_width(p: dict) -> int:
+    """Normal draws per robot and step the step expects (5, plus R with range noise)."""
+    c = make_config(p)
+    return int(lib().orc_noise_width(ctypes.byref(c)))
+
+
+def paper_reward(p: dict, collided: bool, dcells: float, u_prev: float, u: float, d_min: float) -> float:
+    """The paper's Eq. (7) reward from its inputs (the oracle's own function)."""
+    c = make_config(p)
+    return float(lib().orc_paper_reward(ctypes.byref(c), int(bool(collided)), dcells, u_prev, u, d_min))
+
+
 @dataclass
 class StepOut:
     ranges: np.ndarray
@@ -168,6 +190,9 @@ class OracleEnv:
         self.visit_t = np.full(max(nvt, 1), -1, np.int32)
         self.visit_x = np.zeros(max(nvt, 1), np.float32)
         self.visit_y = np.zeros(max(nvt, 1), np.float32)
+        self.visit_last = np.full(max(nvt, 1), -1, np.int32)
+        self.prev_vcell = np.full(n, -1, np.int32)
+        self.u_prev = np.zeros(n, np.float64)
         self.pose = np.zeros((n, 3), np.float32)
         self.est = np.zeros((n, 3), np.float32)
         self.cov = np.zeros((n, 6), np.float32)
@@ -183,7 +208,8 @@ class OracleEnv:
                      ("visit_off", self.visit_off), ("world", self.world), ("belief", self.belief),
                      ("pose", self.pose), ("est", self.est), ("cov", self.cov), ("h_q", self.h_q),
                      ("step", self.step_ct), ("last_lc", self.last_lc), ("visit_t", self.visit_t),
-                     ("visit_x", self.visit_x), ("visit_y", self.visit_y)):
+                     ("visit_x", self.visit_x), ("visit_y", self.visit_y), ("visit_last", self.visit_last),
+                     ("prev_vcell", self.prev_vcell), ("u_prev", self.u_prev)):
             setattr(st, f, _ptr(a))
         return st
 
@@ -196,7 +222,7 @@ class OracleEnv:
     def step(self, actions: np.ndarray, noise: np.ndarray, threads: int = 0) -> StepOut:
         n, R = self.n, self.R
         a = np.ascontiguousarray(actions, np.float32).reshape(n, 2)
-        g = np.ascontiguousarray(noise, np.float32).reshape(n, 5)
+        g = np.ascontiguousarray(noise, np.float32).reshape(n, int(lib().orc_noise_width(ctypes.byref(self.cfg))))
         o = StepOut(ranges=np.zeros((n, R), np.float32), rho_q=np.zeros((n, R), np.int32),
                     hit_cell=np.zeros((n, R), np.int32), reward=np.zeros(n, np.float64),
                     done=np.zeros(n, np.uint8), collided=np.zeros(n, np.uint8),

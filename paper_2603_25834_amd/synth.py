@@ -27,6 +27,19 @@ ENV_DEFAULTS = dict(
     l_hit=0.85, l_miss=-0.4, l_clamp=3.5,
     w_entropy=1.0, w_dopt=1.0, lambda_col=10.0,
     episode_len=0,
+    # sensor model and the paper's reward (zeros: full-circle fan, exact ranges, workload reward)
+    fov_steps=0, reward_mode=0, r_min_m=0.0, range_sigma_m=0.0, range_quant_m=0.0,
+    d_crash_m=0.0, d_full_m=0.0, lambda_explore=0.0, lambda_abs=0.0, lambda_delta=0.0, u_hi=0.0, kappa=0.0,
+)
+
+# The paper's sensor, collision rule and reward (Sec. IV-A, Sec. III-E): 128 rays over the 180-degree
+# front field of view, 0.1 m minimum range, N(0, 0.01 m) range noise, 0.01 m quantisation, collision
+# closer than 0.15 m, Eq. (7); v in [0, 0.4] m/s (Eq. 4), 2048-step episodes.  The reward weights are
+# not printed in the paper; these values are readings.
+PAPER_MODE = dict(
+    n_rays=128, fov_steps=23040, reward_mode=1, r_min_m=0.1, range_sigma_m=0.01, range_quant_m=0.01,
+    d_crash_m=0.15, d_full_m=0.5, lambda_explore=1.0, lambda_abs=0.1, lambda_delta=10.0, u_hi=0.05,
+    kappa=0.005, v_max=0.4, episode_len=2048,
 )
 
 
@@ -66,6 +79,10 @@ WORKLOADS = {
     # 4096 robots, grid side uniform in {128,...,512}, 360 rays, 10 m, 1000 steps.
     "ragged_4096": Workload("ragged_4096", 4096, (128, 192, 256, 384, 512), 0.05, 360, 10.0, 1000, 1,
                             rects=(20, 40), rect_side=(4, 24), thin_walls=(4, 8), thin_len=(16, 64)),
+    # The 750-robot scene with the paper's sensor model, collision rule and reward.
+    "paper_sensor_750x256": Workload("paper_sensor_750x256", 750, (256,), 0.05, 128, 10.0, 1000, 0,
+                                     rects=(20, 40), rect_side=(4, 24), thin_walls=(4, 8), thin_len=(16, 64),
+                                     extra=dict(PAPER_MODE)),
     # 8192 robots in 512x512 worlds, 720 rays, 15 m.
     "full_8192x512": Workload("full_8192x512", 8192, (512,), 0.05, 720, 15.0, 1000, 1,
                               rects=(80, 160), rect_side=(4, 24), thin_walls=(16, 32), thin_len=(16, 64),
@@ -170,11 +187,17 @@ def actions(name: str, seed: int, steps: int, robots=None) -> np.ndarray:
     return a if robots is None else np.ascontiguousarray(a[:, np.asarray(robots)])
 
 
+def noise_width(p: dict) -> int:
+    """Normal draws per robot and step: odometry (x, y, theta), loop-closure fix (x, y), then one
+    per ray when the range noise is on."""
+    return 5 + (int(p["n_rays"]) if p.get("range_sigma_m", 0.0) > 0.0 else 0)
+
+
 def noise(name: str, seed: int, steps: int, robots=None) -> np.ndarray:
-    """Standard-normal draws [steps, n, 5]: odometry (x, y, theta), loop-closure fix (x, y)."""
+    """Standard-normal draws [steps, n, noise_width]."""
     w = WORKLOADS[name]
     rng = np.random.default_rng([seed, 3])
-    g = rng.standard_normal((steps, w.n_robots, 5), dtype=np.float32)
+    g = rng.standard_normal((steps, w.n_robots, noise_width(w.params())), dtype=np.float32)
     return g if robots is None else np.ascontiguousarray(g[:, np.asarray(robots)])
 
 

@@ -1,0 +1,174 @@
+"""Pins of the oracle's paper mode: sensor model, proximity collision, Eq. (7) reward (CPU only).
+
+Paper passages (arXiv 2603.25834): the LiDAR of Sec. IV-A (128 rays over the 180-degree front field
+of view, 0.1 m minimum range, Gaussian noise of 0.01 m, two-decimal ranges) and its collision rule
+(closer than 0.15 m to an obstacle); the reward of Sec. III-E, Eq. (7) with the exploration reward and
+its novelty and intrinsic factors (Eqs. 8-12), the absolute and differential uncertainty terms
+(Eqs. 13-14) and the anti-wall-hugging factor (Eqs. 15-17); the observation [LiDAR, yaw, U_t] of
+Eq. (3).  Expected values are closed forms of special cases, distances in an empty room, or
+bookkeeping recomputed here from the robot's own trajectory -- never the oracle's output.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2603_25834_amd import synth
+from test_oracle_env import room_env
+
+P = synth.WORKLOADS["paper_sensor_750x256"].params()
+
+
+def f32(v):
+    """The configuration carries FP32 values; expected values use the same rounded weights."""
+    return float(np.float32(v))
+
+
+def reward(O, collided=False, dcells=0.0, u_prev=0.0, u=0.0, d_min=10.0, **over):
+    p = dict(P)
+    p.update(over)
+    return O.paper_reward(p, collided, dcells, u_prev, u, d_min)
+
+
+def test_reward_special_cases(oracle_mod):
+    O = oracle_mod
+    lc, le, la, ld = (f32(P[k]) for k in ("lambda_col", "lambda_explore", "lambda_abs", "lambda_delta"))
+    kappa, u_hi = f32(P["kappa"]), f32(P["u_hi"])
+    # collision dominates everything (Eq. 7)
+    for args in (dict(dcells=1.0), dict(u_prev=0.03, u=0.01), dict(d_min=0.0)):
+        assert reward(O, collided=True, **args) == -lc
+    # U_{t-1} = 0: gate c = 1 so I = 1, R_abs = 0, R_Delta = -lambda_D u <= 0 keeps its full weight
+    assert reward(O, dcells=1.0, u_prev=0.0, u=0.02) == pytest.approx(le * 1.0 - ld * 0.02, rel=1e-14)
+    # U_{t-1} >= U_hi: gate c = 0 so I = iota; a drop of at least kappa saturates iota = 1
+    up, u = 0.08, 0.08 - 2 * kappa
+    want = le * 0.5 * 1.0 - la * math.exp(up) * up + ld * math.exp(up) * (up - u)
+    assert reward(O, dcells=0.5, u_prev=up, u=u) == pytest.approx(want, rel=1e-14)
+    # half the saturation drop -> iota = 1/2
+    u2 = up - 0.5 * kappa
+    want2 = le * 0.5 * 0.5 - la * math.exp(up) * up + ld * math.exp(up) * (up - u2)
+    assert reward(O, dcells=0.5, u_prev=up, u=u2) == pytest.approx(want2, rel=1e-14)
+    # intermediate gate: c = ((U_hi - U)/U_hi)^2 with U constant (iota = 0, R_Delta = 0)
+    up = 0.25 * u_hi
+    want3 = le * 1.0 * 0.75 ** 2 - la * math.exp(up) * up
+    assert reward(O, dcells=1.0, u_prev=up, u=up) == pytest.approx(want3, rel=1e-14)
+
+
+def test_wall_hugging_factor(oracle_mod):
+    O = oracle_mod
+    dc, df = f32(P["d_crash_m"]), f32(P["d_full_m"])
+    base = dict(dcells=1.0, u_prev=0.02, u=0.019)
+    full = reward(O, d_min=df + 1.0, **base)
+    gone = reward(O, d_min=dc, **base)
+    half = reward(O, d_min=0.5 * (dc + df), **base)
+    up, u = 0.02, 0.019
+    rabs = f32(P["lambda_abs"]) * math.exp(up) * up
+    # positive parts scale with alpha, the absolute penalty never does
+    assert gone == pytest.approx(-rabs, rel=1e-12)
+    assert half == pytest.approx(0.5 * (full + rabs) - rabs, rel=1e-12)
+    # an uncertainty increase is a penalty and is not weakened near walls (Eq. 17)
+    worse = dict(dcells=0.0, u_prev=0.02, u=0.03)
+    assert reward(O, d_min=dc, **worse) == reward(O, d_min=df + 1.0, **worse)
+
+
+def test_noise_width(oracle_mod):
+    assert oracle_mod.noise_width(P) == 5 + 128
+    p = dict(P, range_sigma_m=0.0)
+    assert oracle_mod.noise_width(p) == 5
+
+
+def _room(O, poses, **over):
+    kw = dict(fov_steps=23040, reward_mode=1, r_min_m=0.0, range_sigma_m=0.0, range_quant_m=0.0,
+              d_crash_m=0.15, d_full_m=0.5, lambda_explore=1.0, lambda_abs=0.1, lambda_delta=10.0, u_hi=0.05,
+              kappa=0.005, v_max=0.4)
+    kw.update(over)
+    return room_env(O, R=128, rmax=5.0, poses=poses, **kw)
+
+
+def _step(env, n, a=(0.0, 0.0)):
+    act = np.tile(np.array(a, np.float32), (n, 1))
+    g = np.zeros((n, env.cfg.n_rays + 5 if env.cfg.range_sigma_m > 0 else 5), np.float32)
+    return env.step(act, g)
+
+
+def test_front_fan_in_an_empty_corner(oracle_mod):
+    """Robot at (1.25, 1.05) m facing +x in the 64x64 room (walls one cell thick at 0.1 m, the block at
+    cells x 30..40, y 20..25 far away): ray 0 looks at -90 deg, ray 64 straight ahead, and the fan never
+    looks behind."""
+    O = oracle_mod
+    env = _room(O, ((1.25, 1.05, 0.0),))
+    o = _step(env, 1)
+    r = o.ranges[0]
+    # ray 0 (heading - 90 deg) hits the bottom wall's top face at y = 0.1 m
+    assert r[0] == pytest.approx(1.05 - 0.1, abs=2e-6)
+    # ray 64 (along the heading) hits the right wall at x = 6.3 m, beyond r_max = 5 m
+    assert r[64] == pytest.approx(5.0, abs=1e-6)
+    # ray 32 (-45 deg) reaches y = 0.1 after 0.95 m along -y; ranges are measured along the Q14 table
+    # direction (llround(sin 45 deg * 2^14) = 11585 per axis), so the range is 0.95 * 2^14 / 11585
+    q = round(math.sin(math.pi / 4) * 16384)
+    assert r[32] == pytest.approx(0.95 * 16384 / q, abs=2e-6)
+    # no ray points backwards: the left wall (x = 0.1 m, 1.15 m behind) is never the nearest return
+    assert r.min() == pytest.approx(0.95, abs=2e-6)
+
+
+def test_quantised_clamped_ranges_and_min_range(oracle_mod):
+    O = oracle_mod
+    env = _room(O, ((1.25, 1.05, 0.0), (0.21, 3.0, math.pi)), range_quant_m=0.01, r_min_m=0.2)
+    o = _step(env, 2)
+    r = o.ranges.astype(np.float64)
+    k = np.rint(r * 100.0)
+    assert np.all(np.abs(r * 100.0 - k) < 1e-3), "ranges are multiples of 0.01 m"
+    assert r.min() >= np.float32(0.2) and r.max() <= np.float32(5.0)
+    # robot 2 faces the left wall 0.11 m away: the straight-ahead return is raised to r_min
+    assert r[1, 64] == pytest.approx(0.2, abs=1e-6)
+
+
+def test_proximity_collision(oracle_mod):
+    O = oracle_mod
+    env = _room(O, ((0.22, 3.0, 0.0), (0.30, 3.0, 0.0), (3.0, 3.0, 0.0)))
+    o = _step(env, 3)
+    # the left wall's face is at x = 0.1 m: 0.12 m < 0.15 m collides, 0.20 m and open space do not
+    assert list(o.collided) == [1, 0, 0]
+    assert list(o.done) == [1, 0, 0]
+    assert o.reward[0] == -f32(P["lambda_col"])
+
+
+def test_observation_yaw_and_uncertainty(oracle_mod):
+    O = oracle_mod
+    env = _room(O, ((3.0, 3.0, 0.5),))
+    crop, scan, state = env.observe(np.full((1, 128), 2.5, np.float32))
+    # U_0 = cbrt(det diag(1e-4, 1e-4, 1e-4)) = 1e-4; yaw / pi
+    assert state[0, 1] == pytest.approx(1e-4, rel=1e-6)
+    assert state[0, 0] == pytest.approx(0.5 / math.pi, rel=1e-6)
+    assert np.all(state[0, 2:] == 0.0)
+    assert np.allclose(scan, 0.5)
+
+
+def test_exploration_novelty_along_a_trajectory(oracle_mod):
+    """With lambda_abs = lambda_Delta = 0, U_hi huge and d_full tiny, the reward is the novelty factor:
+    1 when the ground truth enters a never-visited 0.5 m cell, 0 while it stays, and half the episode
+    fraction since the last visit when it re-enters a cell.  The expectation is recomputed here from the
+    oracle's own ground-truth poses."""
+    O = oracle_mod
+    T_ep = 400
+    env = _room(O, ((0.9, 3.05, 0.0),), lambda_abs=0.0, lambda_delta=0.0, u_hi=1e9, d_full_m=0.16,
+                d_crash_m=0.15, episode_len=T_ep, sigma_x=0.0, sigma_y=0.0, sigma_th=0.0)
+    nv = math.ceil(64 * 0.1 / 0.5)
+    last = {}
+    prev = None
+    # drive +x for 60 steps (0.04 m per step), turn around in place, drive back
+    plan = [(0.4, 0.0)] * 60 + [(0.0, 1.0)] * 31 + [(0.4, 0.0)] * 60
+    for t, a in enumerate(plan):
+        o = _step(env, 1, a)
+        x, y = float(env.pose[0, 0]), float(env.pose[0, 1])
+        vx = min(max(int(math.floor(x / 0.5)), 0), nv - 1)
+        vy = min(max(int(math.floor(y / 0.5)), 0), nv - 1)
+        cell = (vx, vy)
+        if cell != prev:
+            want = 1.0 if cell not in last else min(1.0, 0.5 * (t - last[cell]) / T_ep)
+        else:
+            want = 0.0
+        last[cell] = t
+        prev = cell
+        assert not o.collided[0]
+        # I = c with c = ((U_hi - U)/U_hi)^2, 1 to within 1e-10 here; alpha = 1 away from walls
+        assert o.reward[0] == pytest.approx(want, abs=1e-9), (t, cell)
