@@ -108,7 +108,7 @@ class Workbench:
         for t in range(warmup):
             e.step(self.dA[t], self.dG[t], self.ranges, self.reward, self.done)
         if graph:
-            e.graph_build(steps, self.dA[warmup:], 2 * n, self.dG[warmup:], 5 * n, self.ranges, 0, self.reward, 0,
+            e.graph_build(steps, self.dA[warmup:], 2 * n, self.dG[warmup:], e.G * n, self.ranges, 0, self.reward, 0,
                           self.done, 0)
         torch.cuda.synchronize()
         c0 = e.read(_lib.FIELD_COUNTERS).sum(0).cpu().numpy()

@@ -65,10 +65,27 @@ typedef struct {
   float v_max, w_max;   /* action box [0, v_max] x [-w_max, w_max] (Eq. 4) */
   float sigma_x, sigma_y, sigma_th; /* odometry noise std per step (world frame) */
   float var0_xy, var0_th;           /* initial covariance diagonal */
-  float lc_cell_m, lc_radius_m, lc_sigma_m; /* visit cell (m), fix radius (m), fix std (m) */
+  float lc_cell_m, lc_radius_m, lc_sigma_m; /* visit cell (m; also the novelty cell of Eq. 9), fix radius (m), fix std (m) */
   float l_hit, l_miss, l_clamp;     /* log-odds increments and clamp (nats); stored in 1/256 nat */
   float w_entropy, w_dopt, lambda_col; /* reward = w_entropy*dH - w_dopt*ln det(Sigma) - lambda_col*collided */
+  /* Sensor, collision and reward of the paper (Sec. IV-A, Eq. 7).  All zero
+   * keeps the full-circle noiseless scan and the entropy / D-opt reward. */
+  int32_t fov_steps;    /* fan width in heading steps (46080 = 360 deg); 0 or 46080 = full circle from the
+                           heading; else rays start at heading - fov/2; n_rays must divide the fan */
+  int32_t reward_mode;  /* 0: entropy / D-opt reward above; 1: Eq. (7) with the observation of Eq. (3) */
+  float r_min_m;        /* reported ranges are clamped to [r_min, r_max] (with the sensor model) */
+  float range_sigma_m;  /* range noise std (m); > 0 adds n_rays normal draws per robot to the noise row */
+  float range_quant_m;  /* reported ranges rounded to this quantum (m); 0 = no rounding */
+  float d_crash_m;      /* > 0: collided when an occupied or off-grid cell is closer than this (<= 32 cells) */
+  float d_full_m;       /* Eq. 15: the positive reward terms reach full weight at this clearance (> d_crash) */
+  float lambda_explore, lambda_abs, lambda_delta; /* Eqs. 8, 13, 14 */
+  float u_hi, kappa;    /* Eq. 11 uncertainty gate, Eq. 12 saturation drop (both > 0 in mode 1) */
 } aslam_env_config;
+
+/* Standard-normal draws per robot in the step's noise row: 5 (odometry x,
+ * y, theta, loop-closure x, y), plus n_rays range draws when range_sigma_m
+ * > 0.  Returns -1 for a NULL handle. */
+int32_t aslam_env_noise_width(const aslam_env* env);
 
 /* Execution form of env_step.  PLAIN issues one launch per stage (motion and
  * EKF, LiDAR march, map update and reward); FUSED issues one persistent launch
@@ -97,6 +114,7 @@ int aslam_env_destroy(aslam_env* env);
 /* Device-state sizes, for callers that export or import state. */
 int64_t aslam_env_world_words(const aslam_env* env); /* sum s_i^2 / 32 */
 int64_t aslam_env_cells(const aslam_env* env);       /* sum s_i^2 */
+int64_t aslam_env_visit_cells(const aslam_env* env); /* sum v_i^2 (visit grids), 0 when none is kept */
 
 int aslam_env_set_exec(aslam_env* env, const aslam_exec_config* ex);
 int aslam_env_get_exec(const aslam_env* env, aslam_exec_config* ex);
@@ -113,12 +131,16 @@ int aslam_env_reset(aslam_env* env, const uint32_t* world_dev, const float* init
 
 /* One environment step for every robot (Sec. III-B, one POMDP transition).
  *   actions_dev float [n,2] (v, w), clamped to the box; NaN -> 0.
- *   noise_dev   float [n,5] standard-normal draws: odometry x, y, theta and
- *               the loop-closure measurement x, y.
+ *   noise_dev   float [n,G] standard-normal draws, G = aslam_env_noise_width:
+ *               odometry x, y, theta, the loop-closure measurement x, y, then
+ *               (with range noise) one draw per ray.
  *   ranges_dev  float [n,R] out: range (m) to the entry face of the first
- *               occupied cell, r_max when none within range.
+ *               occupied cell, r_max when none within range; with the sensor
+ *               model, plus noise, rounded to the quantum and clamped to
+ *               [r_min, r_max].  The map update walks the reported range.
  *   reward_dev  float [n]   out.
- *   done_dev    uint8 [n]   out: collided this step, or episode length reached.
+ *   done_dev    uint8 [n]   out: collided this step (swept into an occupied
+ *               cell, or within d_crash of one), or episode length reached.
  * Errors: ASL_EINVAL (null pointer), ASL_ESTATE (before the first reset). */
 int aslam_env_step(aslam_env* env, const float* actions_dev, const float* noise_dev, float* ranges_dev,
                    float* reward_dev, uint8_t* done_dev, aslam_stream_t stream);
@@ -127,7 +149,8 @@ int aslam_env_step(aslam_env* env, const float* actions_dev, const float* noise_
  *   crop_dev  int16 [n,crop,crop]: belief log-odds (1/256 nat) in an
  *             axis-aligned window centred on the estimated cell, 0 off-map.
  *   scan_dev  float [n,R]: ranges / r_max.
- *   state_dev float [n,12]: x/(s c), y/(s c), theta/pi, Sigma (9, row-major). */
+ *   state_dev float [n,12]: x/(s c), y/(s c), theta/pi, Sigma (9, row-major);
+ *             reward_mode 1 (Eq. 3): true yaw/pi, U_t = cbrt(det Sigma), 0 x 10. */
 int aslam_env_observe(aslam_env* env, const float* ranges_dev, int16_t* crop_dev, int32_t crop,
                       float* scan_dev, float* state_dev, aslam_stream_t stream);
 
@@ -144,6 +167,9 @@ int aslam_env_observe(aslam_env* env, const float* ranges_dev, int16_t* crop_dev
 #define ASLAM_FIELD_TERMS 9      /* float [n,2] entropy decrease (nats), ln det Sigma (last step) */
 #define ASLAM_FIELD_COUNTERS 10  /* int64 [n,3] since reset: coded (updated) cells, LiDAR-march cell
                                     visits, map-update cell visits -- the work measures of the step */
+#define ASLAM_FIELD_U_PREV 11    /* double [n] U of the last step (reward_mode 1), cbrt(det Sigma) */
+#define ASLAM_FIELD_VISIT_LAST 12 /* int32 [sum v_i^2] last step each visit cell held the robot, -1 never
+                                     (v_i = ceil(s_i c / lc_cell_m); loop closure or reward_mode 1) */
 int aslam_env_read(const aslam_env* env, int32_t field, void* dst_dev, aslam_stream_t stream);
 
 /* HIP graph of K consecutive env_step calls.  Step k reads

@@ -18,7 +18,7 @@ FORM_PLAIN = 0
 FORM_FUSED = 1
 
 FIELD_BELIEF, FIELD_POSE, FIELD_EST, FIELD_COV, FIELD_RHO_Q, FIELD_HIT_CELL, FIELD_ENTROPY_Q, \
-    FIELD_STEP, FIELD_FLAGS, FIELD_TERMS, FIELD_COUNTERS = range(11)
+    FIELD_STEP, FIELD_FLAGS, FIELD_TERMS, FIELD_COUNTERS, FIELD_U_PREV, FIELD_VISIT_LAST = range(13)
 
 
 class AslamError(RuntimeError):
@@ -38,6 +38,11 @@ class EnvConfig(ctypes.Structure):
         ("lc_cell_m", ctypes.c_float), ("lc_radius_m", ctypes.c_float), ("lc_sigma_m", ctypes.c_float),
         ("l_hit", ctypes.c_float), ("l_miss", ctypes.c_float), ("l_clamp", ctypes.c_float),
         ("w_entropy", ctypes.c_float), ("w_dopt", ctypes.c_float), ("lambda_col", ctypes.c_float),
+        ("fov_steps", ctypes.c_int32), ("reward_mode", ctypes.c_int32),
+        ("r_min_m", ctypes.c_float), ("range_sigma_m", ctypes.c_float), ("range_quant_m", ctypes.c_float),
+        ("d_crash_m", ctypes.c_float), ("d_full_m", ctypes.c_float),
+        ("lambda_explore", ctypes.c_float), ("lambda_abs", ctypes.c_float), ("lambda_delta", ctypes.c_float),
+        ("u_hi", ctypes.c_float), ("kappa", ctypes.c_float),
     ]
 
 
@@ -57,6 +62,8 @@ SIGNATURES = {
     "aslam_env_destroy": (ctypes.c_int, [_P]),
     "aslam_env_world_words": (_I64, [_P]),
     "aslam_env_cells": (_I64, [_P]),
+    "aslam_env_noise_width": (_I32, [_P]),
+    "aslam_env_visit_cells": (_I64, [_P]),
     "aslam_env_set_exec": (ctypes.c_int, [_P, ctypes.POINTER(ExecConfig)]),
     "aslam_env_get_exec": (ctypes.c_int, [_P, ctypes.POINTER(ExecConfig)]),
     "aslam_env_reset": (ctypes.c_int, [_P, _P, _P, _P, _P]),

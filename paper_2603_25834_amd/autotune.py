@@ -106,7 +106,7 @@ def tune(env: Env, actions: torch.Tensor, noise: torch.Tensor, ranges: torch.Ten
          cache_path: str | None = None, force: bool = False) -> dict:
     """Pick the fastest launch shape for this env's batch and apply it with ``Env.set_exec``.
 
-    actions [T, n, 2] and noise [T, n, 5] are device tensors of per-step inputs
+    actions [T, n, 2] and noise [T, n, env.G] are device tensors of per-step inputs
     (cycled if T is short).  Returns {"signature", "best", "table"} with the
     per-candidate time in microseconds per step."""
     key = signature(env)

@@ -79,6 +79,11 @@ struct aslam_env {
   void* d_raylen = nullptr;
   void* d_dirtab = nullptr;
   void* d_hq_lut = nullptr;
+  void* d_visit_last = nullptr;
+  void* d_prev_vcell = nullptr;
+  void* d_u_prev = nullptr;
+  void* d_dcells = nullptr;
+  void* d_dmin = nullptr;
   // captured step sequence
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
@@ -90,7 +95,8 @@ namespace {
 void free_env(aslam_env* e) {
   void** ptrs[] = {&e->d_meta, &e->d_order, &e->d_world, &e->d_belief, &e->d_pose, &e->d_est, &e->d_cov,
                    &e->d_hq_total, &e->d_step, &e->d_last_lc, &e->d_visit_t, &e->d_visit_xy, &e->d_rho,
-                   &e->d_hitc, &e->d_flags, &e->d_terms, &e->d_counters, &e->d_raylen, &e->d_dirtab, &e->d_hq_lut};
+                   &e->d_hitc, &e->d_flags, &e->d_terms, &e->d_counters, &e->d_raylen, &e->d_dirtab, &e->d_hq_lut,
+                   &e->d_visit_last, &e->d_prev_vcell, &e->d_u_prev, &e->d_dcells, &e->d_dmin};
   for (void** p : ptrs) {
     if (*p) (void)hipFree(*p);
     *p = nullptr;
@@ -125,10 +131,20 @@ void build_entropy_lut(int32_t lc, std::vector<uint32_t>& h) {
   }
 }
 
+// Ray fan width in heading steps: the configured fov, or the full circle.
+int32_t fan_steps(const aslam_env_config* c) {
+  return (c->fov_steps > 0 && c->fov_steps < kNang) ? c->fov_steps : kNang;
+}
+
+bool uses_visits(const aslam_env_config* c) { return c->loop_closure || c->reward_mode == 1; }
+
+int32_t noise_width(const aslam_env_config* c) { return 5 + (c->range_sigma_m > 0.0f ? c->n_rays : 0); }
+
 int validate_config(const aslam_env_config* c) {
   if (!c) return fail(ASL_EINVAL, "config is NULL");
-  if (c->n_rays < 1 || c->n_rays > 4096 || kNang % c->n_rays != 0)
-    return fail(ASL_EINVAL, "n_rays must divide 46080 and be in [1, 4096]");
+  if (c->fov_steps < 0 || c->fov_steps > kNang) return fail(ASL_EINVAL, "fov_steps must be in [0, 46080]");
+  if (c->n_rays < 1 || c->n_rays > 4096 || fan_steps(c) % c->n_rays != 0)
+    return fail(ASL_EINVAL, "n_rays must divide the fan (46080 heading steps for a full circle) and be in [1, 4096]");
   if (!(c->cell_m > 0.0f) || !(c->r_max_m > 0.0f)) return fail(ASL_EINVAL, "cell_m and r_max_m must be > 0");
   if ((double)c->r_max_m / (double)c->cell_m > 4096.0) return fail(ASL_EINVAL, "r_max_m exceeds 4096 cells");
   if (!(c->dt >= 0.0f) || !(c->v_max >= 0.0f) || !(c->w_max >= 0.0f)) return fail(ASL_EINVAL, "bad action box");
@@ -136,6 +152,17 @@ int validate_config(const aslam_env_config* c) {
   if (lc < 1 || lc > 16384) return fail(ASL_EINVAL, "l_clamp out of range");
   if (c->loop_closure && (!(c->lc_cell_m > 0.0f) || c->lc_gap < 0))
     return fail(ASL_EINVAL, "bad loop-closure parameters");
+  if (c->reward_mode != 0 && c->reward_mode != 1) return fail(ASL_EINVAL, "reward_mode must be 0 or 1");
+  if (!(c->r_min_m >= 0.0f) || !(c->range_sigma_m >= 0.0f) || !(c->range_quant_m >= 0.0f) ||
+      !(c->r_min_m <= c->r_max_m))
+    return fail(ASL_EINVAL, "sensor model needs 0 <= r_min <= r_max, sigma >= 0, quantum >= 0");
+  if (!(c->d_crash_m >= 0.0f) || (double)c->d_crash_m / (double)c->cell_m > 32.0)
+    return fail(ASL_EINVAL, "d_crash_m must be in [0, 32 cells]");
+  if (c->reward_mode == 1) {
+    if (!(c->lc_cell_m > 0.0f)) return fail(ASL_EINVAL, "reward_mode 1 needs lc_cell_m > 0 (novelty cells)");
+    if (!(c->u_hi > 0.0f) || !(c->kappa > 0.0f) || !(c->d_full_m > c->d_crash_m))
+      return fail(ASL_EINVAL, "reward_mode 1 needs u_hi > 0, kappa > 0 and d_full > d_crash");
+  }
   return ASL_OK;
 }
 
@@ -218,7 +245,7 @@ int aslam_env_create(const aslam_env_config* cfg, int32_t n_robots, const int32_
     const int32_t s = e->sides[i];
     RobotMeta& m = e->meta_h[i];
     m.side = s;
-    m.visit_side = cfg->loop_closure
+    m.visit_side = uses_visits(cfg)
                        ? (int32_t)std::ceil((double)s * (double)cfg->cell_m / (double)cfg->lc_cell_m)
                        : 0;
     m.world_off = e->world_words;
@@ -261,6 +288,11 @@ int aslam_env_create(const aslam_env_config* cfg, int32_t n_robots, const int32_
       {&e->d_raylen, sizeof(int16_t) * (size_t)(R * n_robots)},
       {&e->d_dirtab, sizeof(int32_t) * (size_t)kNang},
       {&e->d_hq_lut, sizeof(uint32_t) * (size_t)(2 * quantise_logodds(cfg->l_clamp) + 1)},
+      {&e->d_visit_last, sizeof(int32_t) * (size_t)std::max<int64_t>(e->visits, 1)},
+      {&e->d_prev_vcell, sizeof(int32_t) * (size_t)n_robots},
+      {&e->d_u_prev, sizeof(double) * (size_t)n_robots},
+      {&e->d_dcells, sizeof(double) * (size_t)n_robots},
+      {&e->d_dmin, sizeof(int32_t) * (size_t)n_robots},
   };
   for (auto& a : allocs) {
     hipError_t he = hipMalloc(a.p, a.bytes);
@@ -290,7 +322,7 @@ int aslam_env_create(const aslam_env_config* cfg, int32_t n_robots, const int32_
   EnvParams& P = e->P;
   P.n = n_robots;
   P.R = cfg->n_rays;
-  P.step_ang = kNang / cfg->n_rays;
+  P.step_ang = fan_steps(cfg) / cfg->n_rays;
   P.loop_closure = cfg->loop_closure ? 1 : 0;
   P.lc_gap = cfg->lc_gap;
   P.episode_len = cfg->episode_len;
@@ -313,7 +345,7 @@ int aslam_env_create(const aslam_env_config* cfg, int32_t n_robots, const int32_
   P.inv_c16 = (float)(65536.0 / (double)cfg->cell_m);
   P.c16 = (float)((double)cfg->cell_m / 65536.0);
   P.k_ang = (float)((double)kNang / (2.0 * M_PI));
-  P.inv_lc = cfg->loop_closure ? (float)(1.0 / (double)cfg->lc_cell_m) : 0.0f;
+  P.inv_lc = uses_visits(cfg) ? (float)(1.0 / (double)cfg->lc_cell_m) : 0.0f;
   P.lc_r2 = cfg->lc_radius_m * cfg->lc_radius_m;
   P.lc_sigma = cfg->lc_sigma_m;
   P.lc_var = cfg->lc_sigma_m * cfg->lc_sigma_m;
@@ -322,6 +354,25 @@ int aslam_env_create(const aslam_env_config* cfg, int32_t n_robots, const int32_
   P.lambda_col = cfg->lambda_col;
   P.inv_rmax = (float)(1.0 / (double)cfg->r_max_m);
   P.inv_pi = (float)(1.0 / M_PI);
+  P.ray0 = fan_steps(cfg) == kNang ? 0 : kNang - fan_steps(cfg) / 2;
+  P.reward_mode = cfg->reward_mode;
+  P.uses_visits = uses_visits(cfg) ? 1 : 0;
+  P.G = noise_width(cfg);
+  P.sensed = (cfg->range_sigma_m > 0.0f || cfg->range_quant_m > 0.0f || cfg->r_min_m > 0.0f) ? 1 : 0;
+  P.crash_q = (int32_t)std::llround((double)cfg->d_crash_m / (double)cfg->cell_m * 65536.0);
+  P.tep = cfg->episode_len > 0 ? cfg->episode_len : 2048;
+  P.r_max = cfg->r_max_m;
+  P.r_min = cfg->r_min_m;
+  P.range_sigma = cfg->range_sigma_m;
+  P.range_quant = cfg->range_quant_m;
+  P.inv_quant = cfg->range_quant_m > 0.0f ? (float)(1.0 / (double)cfg->range_quant_m) : 0.0f;
+  P.d_crash = cfg->d_crash_m;
+  P.d_full = cfg->d_full_m;
+  P.lambda_explore = cfg->lambda_explore;
+  P.lambda_abs = cfg->lambda_abs;
+  P.lambda_delta = cfg->lambda_delta;
+  P.u_hi = cfg->u_hi;
+  P.kappa = cfg->kappa;
   P.meta = (const RobotMeta*)e->d_meta;
   P.order = (const int32_t*)e->d_order;
   P.world = (const uint32_t*)e->d_world;
@@ -342,6 +393,11 @@ int aslam_env_create(const aslam_env_config* cfg, int32_t n_robots, const int32_
   P.raylen = (int16_t*)e->d_raylen;
   P.dirtab = (const int32_t*)e->d_dirtab;
   P.hq_lut = (const uint32_t*)e->d_hq_lut;
+  P.visit_last = (int32_t*)e->d_visit_last;
+  P.prev_vcell = (int32_t*)e->d_prev_vcell;
+  P.u_prev = (double*)e->d_u_prev;
+  P.dcells = (double*)e->d_dcells;
+  P.dmin_bits = (int32_t*)e->d_dmin;
 
   he = set_kernel_lds_limits(e->lds_max);
   if (he != hipSuccess) {
@@ -376,6 +432,8 @@ int aslam_env_destroy(aslam_env* env) {
 
 int64_t aslam_env_world_words(const aslam_env* env) { return env ? env->world_words : -1; }
 int64_t aslam_env_cells(const aslam_env* env) { return env ? env->cells : -1; }
+int32_t aslam_env_noise_width(const aslam_env* env) { return env ? noise_width(&env->cfg) : -1; }
+int64_t aslam_env_visit_cells(const aslam_env* env) { return env ? env->visits : -1; }
 
 int aslam_env_set_exec(aslam_env* env, const aslam_exec_config* ex) {
   if (!env || !ex) return fail(ASL_EINVAL, "env or exec config is NULL");
@@ -454,6 +512,8 @@ int aslam_env_read(const aslam_env* env, int32_t field, void* dst_dev, aslam_str
     case ASLAM_FIELD_FLAGS: src = env->d_flags; bytes = 2 * n; break;
     case ASLAM_FIELD_TERMS: src = env->d_terms; bytes = 8 * n; break;
     case ASLAM_FIELD_COUNTERS: src = env->d_counters; bytes = 24 * n; break;
+    case ASLAM_FIELD_U_PREV: src = env->d_u_prev; bytes = 8 * n; break;
+    case ASLAM_FIELD_VISIT_LAST: src = env->d_visit_last; bytes = 4 * (size_t)env->visits; break;
     default: return fail(ASL_EINVAL, "unknown field");
   }
   HIP_TRY(hipMemcpyAsync(dst_dev, src, bytes, hipMemcpyDeviceToDevice, (hipStream_t)stream), "read");

@@ -3,7 +3,7 @@
 // Not part of the public ABI (include/aslam.h).  Device layout of the batch:
 //   world   : uint32 bits, robot-major, row-major inside a robot (bit j*s+i)
 //   belief  : int16 log-odds in 1/256 nat, robot-major, row-major
-//   visit   : per robot a (ceil(s c / lc_cell))^2 grid of first visits
+//   visit   : per robot a (ceil(s c / lc_cell))^2 grid of first and last visits
 // Robots are independent; one workgroup owns one robot at a time.
 #pragma once
 #include <hip/hip_runtime.h>
@@ -44,6 +44,16 @@ struct EnvParams {
   float lc_sigma, lc_var;
   float w_entropy, w_dopt, lambda_col;
   float inv_rmax, inv_pi;
+  // sensor, proximity collision and reward of the paper (Sec. IV-A, Eq. 7)
+  int32_t ray0;          // heading steps from the heading to ray 0 (0 for a full circle)
+  int32_t reward_mode;   // 0: entropy / D-opt, 1: Eq. (7)
+  int32_t uses_visits;   // visit grid kept (loop closure or reward_mode 1)
+  int32_t G;             // noise row width: 5, + R with range noise
+  int32_t sensed;        // reported range goes through the sensor model
+  int32_t crash_q;       // d_crash in 1/65536 cell; 0 = no proximity test
+  int32_t tep;           // episode length used by the novelty factor
+  float r_max, r_min, range_sigma, range_quant, inv_quant;
+  float d_crash, d_full, lambda_explore, lambda_abs, lambda_delta, u_hi, kappa;
   const RobotMeta* meta;
   const int32_t* order;  // robots, largest grid first
   const uint32_t* world;
@@ -64,11 +74,16 @@ struct EnvParams {
   int16_t* raylen;       // [n,R] steps of each ray's last LiDAR walk (lane-order key)
   const int32_t* dirtab; // [kNang] (cos & 0xffff) | (sin << 16), Q14
   const uint32_t* hq_lut;// [2*lclamp+1] binary entropy, 2^-32 nat
+  int32_t* visit_last;   // [sum v^2] last step the robot was in each visit cell, -1 never
+  int32_t* prev_vcell;   // [n] visit cell of the previous step, -1 after reset
+  double* u_prev;        // [n] U_{t-1} = cbrt(det Sigma) of the previous step
+  double* dcells;        // [n] novelty of this step's visit cell (motion -> reward)
+  int32_t* dmin_bits;    // [n] FP32 bits of the smallest reported range (march -> reward)
 };
 
 struct StepArgs {
   const float* actions;  // [n,2]
-  const float* noise;    // [n,5]
+  const float* noise;    // [n,G]
   float* ranges;         // [n,R]
   float* reward;         // [n]
   uint8_t* done;         // [n]

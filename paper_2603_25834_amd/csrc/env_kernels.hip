@@ -85,6 +85,65 @@ __device__ bool segment_blocked(const uint32_t* w, int32_t s, int32_t ox, int32_
   return true;
 }
 
+// Proximity collision (Sec. IV-A): an occupied or off-grid cell lies closer
+// than rc (1/65536 cell) to the Q16 point, by the exact integer distance from
+// the point to the cell's square.
+__device__ bool near_obstacle(const uint32_t* w, int32_t s, int32_t px, int32_t py, int32_t rc) {
+  const int32_t cx = px >> 16, cy = py >> 16;
+  const int32_t m = rc / kQ16 + 1;
+  const int64_t rc2 = (int64_t)rc * rc;
+  for (int32_t j = cy - m; j <= cy + m; ++j) {
+    for (int32_t i = cx - m; i <= cx + m; ++i) {
+      const bool occ = (i < 0 || j < 0 || i >= s || j >= s) || world_bit(w, s, i, j);
+      if (!occ) continue;
+      const int64_t dx = max(max((int64_t)i * kQ16 - px, (int64_t)px - (int64_t)(i + 1) * kQ16), (int64_t)0);
+      const int64_t dy = max(max((int64_t)j * kQ16 - py, (int64_t)py - (int64_t)(j + 1) * kQ16), (int64_t)0);
+      if (dx * dx + dy * dy < rc2) return true;
+    }
+  }
+  return false;
+}
+
+// Heading index of ray 0 of the fan whose heading index is ib.
+__device__ __forceinline__ int32_t fan_base(const EnvParams& P, int32_t ib) {
+  const int32_t id = ib + P.ray0;
+  return id >= kNang ? id - kNang : id;
+}
+
+__device__ __forceinline__ double cov_det(const float* c) {
+  return (double)c[0] * ((double)c[3] * c[5] - (double)c[4] * c[4]) -
+         (double)c[1] * ((double)c[1] * c[5] - (double)c[4] * c[2]) +
+         (double)c[2] * ((double)c[1] * c[4] - (double)c[3] * c[2]);
+}
+
+// SLAM uncertainty scalar U = cbrt(det Sigma) (0 when det <= 0).
+__device__ __forceinline__ double uncertainty(const float* c) {
+  const double d = cov_det(c);
+  return d > 0.0 ? cbrt(d) : 0.0;
+}
+
+__device__ __forceinline__ double clip01(double v) { return v < 0.0 ? 0.0 : (v > 1.0 ? 1.0 : v); }
+
+// Reward of Eq. (7): the collision penalty alone on a collision, else the
+// exploration reward (Eq. 8, novelty of Eq. 9 times the intrinsic factor of
+// Eqs. 10-12) minus the absolute uncertainty penalty (Eq. 13) plus the
+// differential term (Eq. 14); the clearance factor of Eq. 15 scales the
+// exploration term and a falling-uncertainty differential term (Eqs. 16-17).
+__device__ double paper_reward(const EnvParams& P, int32_t collided, double dcells, double up, double u,
+                               double d_min) {
+  if (collided) return -(double)P.lambda_col;
+  double cg = clip01(((double)P.u_hi - up) / (double)P.u_hi);
+  cg = cg * cg;
+  const double iota = clip01(fmax(up - u, 0.0) / (double)P.kappa);
+  const double in = cg + (1.0 - cg) * iota;
+  const double r_explore = (double)P.lambda_explore * dcells * in;
+  const double eu = exp(up);
+  const double r_abs = (double)P.lambda_abs * eu * up;
+  const double r_delta = (double)P.lambda_delta * eu * (up - u);
+  const double alpha = clip01((d_min - (double)P.d_crash) / ((double)P.d_full - (double)P.d_crash));
+  return r_explore * alpha - r_abs + (up - u > 0.0 ? r_delta * alpha : r_delta);
+}
+
 __device__ __forceinline__ int32_t wave_sum_i32(int32_t v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -92,8 +151,8 @@ __device__ __forceinline__ int32_t wave_sum_i32(int32_t v) {
 }
 
 struct MotionOut {
-  int32_t tox, toy, ib_t;   // true origin (Q16) and heading index
-  int32_t eox, eoy, ib_e;   // estimated origin and heading index
+  int32_t tox, toy, ib_t;   // true origin (Q16) and heading index of ray 0
+  int32_t eox, eoy, ib_e;   // estimated origin and heading index of ray 0
   int32_t collided, closed;
 };
 
@@ -102,7 +161,7 @@ __device__ MotionOut robot_motion(const EnvParams& P, const StepArgs& A, int32_t
   const RobotMeta m = P.meta[r];
   const int32_t s = m.side;
   const float a0 = A.actions[2 * r], a1 = A.actions[2 * r + 1];
-  const float* g = A.noise + 5 * (int64_t)r;
+  const float* g = A.noise + (int64_t)P.G * r;
   float v = fminf(fmaxf(a0, 0.0f), P.v_max);
   float w = fminf(fmaxf(a1, -P.w_max), P.w_max);
   if (v != v) v = 0.0f;
@@ -126,6 +185,10 @@ __device__ MotionOut robot_motion(const EnvParams& P, const StepArgs& A, int32_t
     px = nx; py = ny; pth = nth;
     p[0] = px; p[1] = py; p[2] = pth;
   }
+  // the paper's collision: closer than d_crash to an obstacle (the move stands)
+  int32_t collided = col;
+  if (P.crash_q > 0 && !col && near_obstacle(W, s, to_q16(px, P.inv_c16), to_q16(py, P.inv_c16), P.crash_q))
+    collided = 1;
 
   // EKF predict; F uses the estimated heading before the step.
   float* e = P.est + 3 * (int64_t)r;
@@ -150,14 +213,32 @@ __device__ MotionOut robot_motion(const EnvParams& P, const StepArgs& A, int32_t
   }
 
   const int32_t t = P.step[r];
-  int32_t closed = 0;
-  if (P.loop_closure) {
+  // visit cell of the true position (loop closure, exploration novelty)
+  int32_t vcell = -1;
+  int64_t vk = 0;
+  if (P.uses_visits) {
     const int32_t nv = m.visit_side;
     int32_t vx = (int32_t)floorf(px * P.inv_lc);
     int32_t vy = (int32_t)floorf(py * P.inv_lc);
     vx = min(max(vx, 0), nv - 1);
     vy = min(max(vy, 0), nv - 1);
-    const int64_t vk = m.visit_off + (int64_t)vy * nv + vx;
+    vcell = vy * nv + vx;
+    vk = m.visit_off + vcell;
+  }
+  // novelty (Eq. 9): 1 on entering a never-visited cell, half the episode
+  // fraction since the last visit on re-entering one, 0 while staying
+  if (P.reward_mode == 1) {
+    double dcells = 0.0;
+    if (vcell != P.prev_vcell[r]) {
+      const int32_t last = P.visit_last[vk];
+      dcells = last < 0 ? 1.0 : fmin(1.0, 0.5 * (double)(t - last) / (double)P.tep);
+    }
+    P.visit_last[vk] = t;
+    P.prev_vcell[r] = vcell;
+    P.dcells[r] = dcells;
+  }
+  int32_t closed = 0;
+  if (P.loop_closure) {
     const int32_t t0 = P.visit_t[vk];
     if (t0 < 0) {
       P.visit_t[vk] = t;
@@ -194,17 +275,17 @@ __device__ MotionOut robot_motion(const EnvParams& P, const StepArgs& A, int32_t
   e[0] = ex; e[1] = ey; e[2] = eth;
   c[0] = c0; c[1] = c1; c[2] = c2; c[3] = c3; c[4] = c4; c[5] = c5;
   P.step[r] = t + 1;
-  P.flags[2 * (int64_t)r] = (uint8_t)col;
+  P.flags[2 * (int64_t)r] = (uint8_t)collided;
   P.flags[2 * (int64_t)r + 1] = (uint8_t)closed;
 
   MotionOut o;
   o.tox = to_q16(px, P.inv_c16);
   o.toy = to_q16(py, P.inv_c16);
-  o.ib_t = heading_index(pth, P.k_ang);
+  o.ib_t = fan_base(P, heading_index(pth, P.k_ang));
   o.eox = to_q16(ex, P.inv_c16);
   o.eoy = to_q16(ey, P.inv_c16);
-  o.ib_e = heading_index(eth, P.k_ang);
-  o.collided = col;
+  o.ib_e = fan_base(P, heading_index(eth, P.k_ang));
+  o.collided = collided;
   o.closed = closed;
   return o;
 }
@@ -217,7 +298,8 @@ struct RobotShared {
   int32_t collided;
   int32_t cnt_march, cnt_upd;
   int32_t bx0, bx1, by0, by1;   // cell bounding box of the ray end points (estimated pose)
-  int32_t pad[2];
+  int32_t dmin_bits;            // FP32 bits of the smallest reported range (non-negative)
+  int32_t pad;
   long long part[16];
   int32_t dpart[16];
 };
@@ -434,10 +516,13 @@ __device__ void stage_world(const EnvParams& P, const RobotMeta& m, int32_t cy, 
 
 constexpr int kLook = 8;   // DDA steps per LDS round trip in the march
 
-// LiDAR march of every ray of the robot from the true pose (lanes = rays).
+// LiDAR march of every ray of the robot from the true pose (lanes = rays),
+// then the reported range of each ray (sensor model of Sec. IV-A: true range
+// plus noise, rounded to the quantum, clamped to [r_min, r_max]).  The map
+// update walks the reported range; gr holds the ray noise draws.
 template <int NT>
 __device__ void march_rays(const EnvParams& P, const RobotMeta& m, const LdsView& V, const uint32_t* sw,
-                           int32_t wy0, int32_t wmax, float* ranges_out, bool record, int32_t r) {
+                           int32_t wy0, int32_t wmax, float* ranges_out, const float* gr, bool record, int32_t r) {
   RobotShared* sh = V.sh;
   int32_t* rho_lds = V.rho;
   const int32_t s = m.side;
@@ -448,6 +533,7 @@ __device__ void march_rays(const EnvParams& P, const RobotMeta& m, const LdsView
   // lane slots ordered by the previous step's walk length of each ray
   sort_rays<NT>(P.R, V.perm, V.hist, [&](int32_t k) { return (int32_t)raylen[k] >> 2; });
   int32_t visits = 0;
+  float dmin = __int_as_float(0x7f800000);
   for (int32_t k0 = 0; k0 < P.R; k0 += NT) {
     const int32_t j = k0 + (int32_t)threadIdx.x;
     const int32_t k = j < P.R ? V.perm[j] : P.R;
@@ -458,9 +544,7 @@ __device__ void march_rays(const EnvParams& P, const RobotMeta& m, const LdsView
     int32_t li = 0, D = 0, i = 0, sx = 0, sy = 0;
     bool hit = false, done = true;
     if (active) {
-      int32_t id = ib + k * P.step_ang;
-      id -= (id >= kNang) ? kNang : 0;
-      const int32_t dv = P.dirtab[id];
+      const int32_t dv = ray_dir(P, ib, k);
       const int32_t a = (int16_t)(dv & 0xffff), b = dv >> 16;
       q = ray_setup(tox, toy, a, b, P.rhat_q, s);
       li = (cy0 - wy0) * s + cx0;
@@ -536,16 +620,31 @@ __device__ void march_rays(const EnvParams& P, const RobotMeta& m, const LdsView
       }
     }
     if (k < P.R) {
-      rho_lds[k] = rq | (cell >= 0 ? (int32_t)0x80000000 : 0);
-      ranges_out[(int64_t)r * P.R + k] = (float)rq * P.c16;
+      float rep = (float)rq * P.c16;
+      int32_t rho_u = rq;
+      if (P.sensed) {
+        if (P.range_sigma > 0.0f) rep = rep + P.range_sigma * gr[k];
+        if (P.range_quant > 0.0f) rep = rintf(rep * P.inv_quant) * P.range_quant;
+        rep = fminf(fmaxf(rep, P.r_min), P.r_max);
+        rho_u = to_q16(rep, P.inv_c16);
+      }
+      dmin = fminf(dmin, rep);
+      rho_lds[k] = rho_u | (cell >= 0 ? (int32_t)0x80000000 : 0);
+      ranges_out[(int64_t)r * P.R + k] = rep;
       if (record) {
-        P.rho[(int64_t)r * P.R + k] = rq;
+        P.rho[(int64_t)r * P.R + k] = rho_u;
         P.hitc[(int64_t)r * P.R + k] = cell;
       }
     }
   }
   visits = wave_sum_i32(visits);
   if ((threadIdx.x & 63) == 0 && visits) atomicAdd(&sh->cnt_march, visits);
+  if (P.reward_mode == 1) {
+    // reported ranges are >= 0, so their FP32 bits order as integers
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) dmin = fminf(dmin, __shfl_xor(dmin, o, 64));
+    if ((threadIdx.x & 63) == 0) atomicMin(&sh->dmin_bits, __float_as_int(dmin));
+  }
   __syncthreads();
 }
 
@@ -744,12 +843,17 @@ __device__ void update_and_reward(const EnvParams& P, const StepArgs& A, const R
     P.hq_total[r] += tot;
     const double rH = (double)(-tot) * (1.0 / 4294967296.0);
     const float* c = P.cov + 6 * (int64_t)r;
-    const double det = (double)c[0] * ((double)c[3] * c[5] - (double)c[4] * c[4]) -
-                       (double)c[1] * ((double)c[1] * c[5] - (double)c[4] * c[2]) +
-                       (double)c[2] * ((double)c[1] * c[4] - (double)c[3] * c[2]);
+    const double det = cov_det(c);
     const double ld = det > 0.0 ? log(det) : log(1.17549435e-38);
     const int32_t col = sh->collided;
-    const double rew = (double)P.w_entropy * rH - (double)P.w_dopt * ld - (double)P.lambda_col * (double)col;
+    double rew;
+    if (P.reward_mode == 1) {
+      const double u = det > 0.0 ? cbrt(det) : 0.0;
+      rew = paper_reward(P, col, P.dcells[r], P.u_prev[r], u, (double)__int_as_float(sh->dmin_bits));
+      P.u_prev[r] = u;
+    } else {
+      rew = (double)P.w_entropy * rH - (double)P.w_dopt * ld - (double)P.lambda_col * (double)col;
+    }
     A.reward[r] = (float)rew;
     const int32_t t = P.step[r];
     A.done[r] = (uint8_t)(col || (P.episode_len > 0 && t >= P.episode_len));
@@ -777,15 +881,20 @@ __global__ __launch_bounds__(NT) void k_march(EnvParams P, StepArgs A, LdsPlan L
     const float* p = P.pose + 3 * (int64_t)r;
     sh->tox = to_q16(p[0], P.inv_c16);
     sh->toy = to_q16(p[1], P.inv_c16);
-    sh->ib_t = heading_index(p[2], P.k_ang);
+    sh->ib_t = fan_base(P, heading_index(p[2], P.k_ang));
     sh->cnt_march = 0;
+    sh->dmin_bits = 0x7f800000;
   }
   __syncthreads();
   int32_t wy0;
   stage_world<NT>(P, m, sh->toy >> 16, L.world_halo, V.uni, wy0);
   __syncthreads();
-  march_rays<NT>(P, m, V, V.uni, wy0, (L.union_bytes >> 2) - 1, A.ranges, true, r);
-  if (threadIdx.x == 0) P.counters[3 * (int64_t)r + 1] += sh->cnt_march;
+  march_rays<NT>(P, m, V, V.uni, wy0, (L.union_bytes >> 2) - 1, A.ranges, A.noise + (int64_t)P.G * r + 5, true,
+                 r);
+  if (threadIdx.x == 0) {
+    P.counters[3 * (int64_t)r + 1] += sh->cnt_march;
+    P.dmin_bits[r] = sh->dmin_bits;
+  }
 }
 
 __device__ __forceinline__ void init_bbox(RobotShared* sh) {
@@ -805,10 +914,11 @@ __global__ __launch_bounds__(NT) void k_update(EnvParams P, StepArgs A, LdsPlan 
     const float* e = P.est + 3 * (int64_t)r;
     sh->eox = to_q16(e[0], P.inv_c16);
     sh->eoy = to_q16(e[1], P.inv_c16);
-    sh->ib_e = heading_index(e[2], P.k_ang);
+    sh->ib_e = fan_base(P, heading_index(e[2], P.k_ang));
     sh->collided = P.flags[2 * (int64_t)r];
     sh->cnt_march = 0;
     sh->cnt_upd = 0;
+    sh->dmin_bits = P.dmin_bits[r];
     init_bbox(sh);
   }
   for (int32_t k = threadIdx.x; k < P.R; k += NT) {
@@ -835,13 +945,15 @@ __device__ __forceinline__ void fused_robot(const EnvParams& P, const StepArgs& 
     sh->collided = o.collided;
     sh->cnt_march = 0;
     sh->cnt_upd = 0;
+    sh->dmin_bits = 0x7f800000;
     init_bbox(sh);
   }
   __syncthreads();
   int32_t wy0;
   stage_world<NT>(P, m, sh->toy >> 16, L.world_halo, V.uni, wy0);
   __syncthreads();
-  march_rays<NT>(P, m, V, V.uni, wy0, (L.union_bytes >> 2) - 1, A.ranges, L.record != 0, r);
+  march_rays<NT>(P, m, V, V.uni, wy0, (L.union_bytes >> 2) - 1, A.ranges, A.noise + (int64_t)P.G * r + 5,
+                 L.record != 0, r);
   endpoint_bbox<NT>(P, V.rho, sh->eox, sh->eoy, sh->ib_e, sh);
   __syncthreads();
   update_and_reward<NT>(P, A, m, V, L, r);
@@ -883,12 +995,13 @@ __global__ void k_reset(EnvParams P, const uint32_t* world_src, const float* ini
   uint32_t* wd = const_cast<uint32_t*>(P.world) + m.world_off;
   const uint32_t* ws = world_src + m.world_off;
   for (int64_t k = threadIdx.x; k < nw; k += blockDim.x) wd[k] = ws[k];
-  if (P.loop_closure) {
+  if (P.uses_visits) {
     const int64_t nv = (int64_t)m.visit_side * m.visit_side;
     for (int64_t k = threadIdx.x; k < nv; k += blockDim.x) {
       P.visit_t[m.visit_off + k] = -1;
       P.visit_xy[2 * (m.visit_off + k)] = 0.0f;
       P.visit_xy[2 * (m.visit_off + k) + 1] = 0.0f;
+      P.visit_last[m.visit_off + k] = -1;
     }
   }
   if (threadIdx.x == 0) {
@@ -902,6 +1015,10 @@ __global__ void k_reset(EnvParams P, const uint32_t* world_src, const float* ini
     P.hq_total[r] = (int64_t)s * (int64_t)s * (int64_t)P.hq_lut[P.lclamp];
     P.step[r] = 0;
     P.last_lc[r] = -(1 << 30);
+    P.prev_vcell[r] = -1;
+    P.u_prev[r] = uncertainty(c);
+    P.dcells[r] = 0.0;
+    P.dmin_bits[r] = 0x7f800000;
     P.flags[2 * (int64_t)r] = 0;
     P.flags[2 * (int64_t)r + 1] = 0;
     P.counters[3 * (int64_t)r] = 0;
@@ -931,11 +1048,18 @@ __global__ void k_observe(EnvParams P, const float* ranges, int16_t* crop, int32
   if (threadIdx.x == 0) {
     const float* c = P.cov + 6 * (int64_t)r;
     float* o = state + 12 * (int64_t)r;
-    const float inv_ext = m.inv_ext;
-    o[0] = e[0] * inv_ext; o[1] = e[1] * inv_ext; o[2] = e[2] * inv_pi;
-    o[3] = c[0]; o[4] = c[1]; o[5] = c[2];
-    o[6] = c[1]; o[7] = c[3]; o[8] = c[4];
-    o[9] = c[2]; o[10] = c[4]; o[11] = c[5];
+    if (P.reward_mode == 1) {
+      // Eq. (3): [LiDAR, yaw, U_t]; yaw of the true heading (IMU), U_t of the filter
+      for (int k = 2; k < 12; ++k) o[k] = 0.0f;
+      o[0] = P.pose[3 * (int64_t)r + 2] * inv_pi;
+      o[1] = (float)uncertainty(c);
+    } else {
+      const float inv_ext = m.inv_ext;
+      o[0] = e[0] * inv_ext; o[1] = e[1] * inv_ext; o[2] = e[2] * inv_pi;
+      o[3] = c[0]; o[4] = c[1]; o[5] = c[2];
+      o[6] = c[1]; o[7] = c[3]; o[8] = c[4];
+      o[9] = c[2]; o[10] = c[4]; o[11] = c[5];
+    }
   }
 }
 

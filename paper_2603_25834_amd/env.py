@@ -48,6 +48,8 @@ class Env:
         self.h = h
         self.cells = int(lib().aslam_env_cells(h))
         self.world_words = int(lib().aslam_env_world_words(h))
+        self.visit_cells = int(lib().aslam_env_visit_cells(h))
+        self.G = int(lib().aslam_env_noise_width(h))     # normal draws per robot and step
         cells = self.sides.astype(np.int64) ** 2
         self.cell_off = np.concatenate([[0], np.cumsum(cells)[:-1]]).astype(np.int64)
 
@@ -84,7 +86,7 @@ class Env:
     def step(self, actions: torch.Tensor, noise: torch.Tensor, ranges: torch.Tensor, reward: torch.Tensor,
              done: torch.Tensor):
         assert actions.dtype == torch.float32 and actions.numel() == 2 * self.n
-        assert noise.dtype == torch.float32 and noise.numel() == 5 * self.n
+        assert noise.dtype == torch.float32 and noise.numel() == self.G * self.n
         assert ranges.dtype == torch.float32 and ranges.numel() == self.R * self.n
         assert reward.dtype == torch.float32 and reward.numel() == self.n
         assert done.dtype == torch.uint8 and done.numel() == self.n
@@ -110,19 +112,22 @@ class Env:
         _lib.FIELD_FLAGS: (torch.uint8, lambda s: (s.n, 2)),
         _lib.FIELD_TERMS: (torch.float32, lambda s: (s.n, 2)),
         _lib.FIELD_COUNTERS: (torch.int64, lambda s: (s.n, 3)),
+        _lib.FIELD_U_PREV: (torch.float64, lambda s: (s.n,)),
+        _lib.FIELD_VISIT_LAST: (torch.int32, lambda s: (s.visit_cells,)),
     }
 
     def read(self, field: int) -> torch.Tensor:
         dt, shape = self._FIELDS[field]
         out = torch.empty(shape(self), dtype=dt, device=self.device)
-        check(lib().aslam_env_read(self.h, field, _ptr(out), _stream()))
+        if out.numel():            # an empty field (no visit grid) has no storage to copy into
+            check(lib().aslam_env_read(self.h, field, _ptr(out), _stream()))
         return out
 
     def graph_build(self, k_steps: int, actions: torch.Tensor, a_stride: int, noise: torch.Tensor, g_stride: int,
                     ranges: torch.Tensor, r_stride: int, reward: torch.Tensor, w_stride: int,
                     done: torch.Tensor, d_stride: int):
         # the buffers must hold k_steps strided slices
-        for t, st, per in ((actions, a_stride, 2 * self.n), (noise, g_stride, 5 * self.n),
+        for t, st, per in ((actions, a_stride, 2 * self.n), (noise, g_stride, self.G * self.n),
                            (ranges, r_stride, self.R * self.n), (reward, w_stride, self.n), (done, d_stride, self.n)):
             assert t.is_contiguous() and t.numel() >= (k_steps - 1) * st + per
         check(lib().aslam_env_graph_build(self.h, k_steps, _ptr(actions), a_stride, _ptr(noise), g_stride,

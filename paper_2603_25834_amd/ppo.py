@@ -64,12 +64,12 @@ class PPOTrainer:
         self.loss = torch.zeros(4, device=dev)
 
     def draws(self, iterations: int, seed: int):
-        """Seeded synthetic randomness for `iterations` iterations: odometry noise [I,T,n,5], action noise
+        """Seeded synthetic randomness for `iterations` iterations: step noise [I,T,n,G], action noise
         [I,T,n,2] and one permutation of the T*n samples per epoch [I,epochs,T*n] (int32)."""
         rng = np.random.default_rng([seed, 77])
         I, T, n = iterations, self.T, self.n
         dev = self.params.device
-        noise = torch.from_numpy(rng.standard_normal((I, T, n, 5), dtype=np.float32)).to(dev)
+        noise = torch.from_numpy(rng.standard_normal((I, T, n, self.env.G), dtype=np.float32)).to(dev)
         eps = torch.from_numpy(rng.standard_normal((I, T, n, 2), dtype=np.float32)).to(dev)
         perm = np.stack([np.stack([rng.permutation(self.S) for _ in range(self.epochs)]) for _ in range(I)])
         return noise, eps, torch.from_numpy(perm.astype(np.int32)).to(dev)

@@ -34,6 +34,13 @@ class Pair:
         self.R = int(self.p["n_rays"])
         self.A = synth.actions(name, seed, steps, robots)
         self.G = synth.noise(name, seed, steps, robots)
+        gw = synth.noise_width(self.p)
+        if self.G.shape[-1] > gw:          # an override turned the range noise off
+            self.G = np.ascontiguousarray(self.G[..., :gw])
+        elif self.G.shape[-1] < gw:        # ... or on: draw the ray noise separately
+            rng = np.random.default_rng([seed, 5])
+            extra = rng.standard_normal(self.G.shape[:-1] + (gw - self.G.shape[-1],), dtype=np.float32)
+            self.G = np.ascontiguousarray(np.concatenate([self.G, extra], axis=-1))
         self.orc = None
         if oracle:
             self.orc = O.OracleEnv(self.p, self.b.sides, self.b.world, self.b.world_off)
@@ -85,6 +92,7 @@ class Pair:
             flags=e.read(_lib.FIELD_FLAGS).cpu().numpy(), terms=e.read(_lib.FIELD_TERMS).cpu().numpy(),
             rho=e.read(_lib.FIELD_RHO_Q).cpu().numpy(), hitc=e.read(_lib.FIELD_HIT_CELL).cpu().numpy(),
             counters=e.read(_lib.FIELD_COUNTERS).cpu().numpy(),
+            u_prev=e.read(_lib.FIELD_U_PREV).cpu().numpy(), visit_last=e.read(_lib.FIELD_VISIT_LAST).cpu().numpy(),
             ranges=self.ranges.cpu().numpy(), reward=self.reward.cpu().numpy(), done=self.done.cpu().numpy())
 
     def compare(self, o, rays: bool = True, belief: bool = True, tag: str = ""):
@@ -113,4 +121,9 @@ class Pair:
         assert np.allclose(g["terms"][:, 1], o.logdet, rtol=1e-5, atol=1e-4), f"logdet term {where}"
         assert np.all(np.abs(g["reward"] - o.reward) <= 1e-4 * np.maximum(1.0, np.abs(o.reward))), \
             f"reward differs {where}: max {np.max(np.abs(g['reward'] - o.reward))}"
+        if int(self.p.get("reward_mode", 0)) == 1:
+            # U = cbrt(det Sigma) of bit-identical covariances: FP64 library cbrt, within a few ulp
+            assert np.allclose(g["u_prev"], orc.u_prev, rtol=1e-13, atol=0), f"U_t differs {where}"
+            nv = g["visit_last"].size
+            assert np.array_equal(g["visit_last"], orc.visit_last[:nv]), f"visit bookkeeping differs {where}"
         return g

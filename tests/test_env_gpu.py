@@ -159,7 +159,7 @@ def test_graph_replay_matches_eager(form):
     rng = torch.zeros((K, n, R), device="cuda")
     rew = torch.zeros((K, n), device="cuda")
     dn = torch.zeros((K, n), dtype=torch.uint8, device="cuda")
-    graph.env.graph_build(K, graph.dA, 2 * n, graph.dG, 5 * n, rng, n * R, rew, n, dn, n)
+    graph.env.graph_build(K, graph.dA, 2 * n, graph.dG, graph.env.G * n, rng, n * R, rew, n, dn, n)
     for rep in range(3):
         say(f"[graph] form={form} replay {rep}")
         graph.env.graph_launch()
