@@ -27,15 +27,19 @@ BF16_PEAK_TFLOPS = 2500.0
 METRIC = "env-steps/s and rays/s at 750 & 4096 robots; % HBM roofline; PPO fwd+bwd/s"
 
 
-def alg_bytes_per_robot_step(D: float, R: int, loop_closure: bool) -> float:
+def alg_bytes_per_robot_step(D: float, R: int, loop_closure: bool, noise_width: int = 5,
+                             paper_reward: bool = False) -> float:
     """Algorithmic HBM bytes of one robot-step.
 
     Map: read + write each coded int16 cell (4 B); world bits of the cells the
     rays cross, taken equal to the coded cells (D/8 B); ranges out (4R B);
-    per-robot state and I/O: action 8, normal draws 20, true pose r/w 24,
-    estimate r/w 24, covariance r/w 48, step r/w 8, entropy r/w 16, reward 4,
-    done 1 (153 B); loop-closure visit record read 12 B."""
-    return 4.0 * D + D / 8.0 + 4.0 * R + 153.0 + (12.0 if loop_closure else 0.0)
+    per-robot state and I/O: action 8, normal draws 4G (G = 5, or 5 + R with
+    range noise), true pose r/w 24, estimate r/w 24, covariance r/w 48, step
+    r/w 8, entropy r/w 16, reward 4, done 1 (133 B + 4G); loop-closure visit
+    record read 12 B; Eq. (7) reward state: U_{t-1} r/w 16, previous visit
+    cell r/w 8, last visit r/w 8 (32 B)."""
+    return (4.0 * D + D / 8.0 + 4.0 * R + 133.0 + 4.0 * noise_width + (12.0 if loop_closure else 0.0) +
+            (32.0 if paper_reward else 0.0))
 
 
 def kernel_source_digest() -> str:
@@ -128,7 +132,8 @@ class Workbench:
         D = float(c1[0] - c0[0]) / (n * steps)
         vm = float(c1[1] - c0[1]) / (n * steps)
         vu = float(c1[2] - c0[2]) / (n * steps)
-        bytes_step = n * alg_bytes_per_robot_step(D, self.R, bool(self.p["loop_closure"]))
+        bytes_step = n * alg_bytes_per_robot_step(D, self.R, bool(self.p["loop_closure"]), e.G,
+                                                  int(self.p.get("reward_mode", 0)) == 1)
         s = ms / 1e3
         return dict(ms=ms, ms_per_step=ms / steps, env_steps_per_s=n * steps / s, rays_per_s=n * steps * self.R / s,
                     coded_cells_per_robot_step=D, march_visits_per_robot_step=vm, update_visits_per_robot_step=vu,
@@ -344,6 +349,37 @@ def autotune_forms(wb) -> tuple:
     return fused, plain, summary
 
 
+def side_workload(name: str, args, fused: dict, plain: dict) -> dict:
+    """Env-step timings (fused and plain, each autotuned on this batch) and a few training iterations of a
+    workload besides the headline one."""
+    import torch
+    print(f"[bench] {name}: setting up", file=sys.stderr, flush=True)
+    wb2 = Workbench(name, args.seed, args.env_warmup + args.secondary_steps, fused)
+    f2, p2, t2 = autotune_forms(wb2) if not args.threads else (fused, plain, {})
+    r2 = wb2.run(args.env_warmup, args.secondary_steps)
+    wb2.env.set_exec(**p2)
+    wb2.env.reset(wb2.world, wb2.start)
+    r2p = wb2.run(args.env_warmup, args.secondary_steps)
+    res = {
+        "workload": name, "robots": wb2.n, "rays": wb2.R, "steps": args.secondary_steps,
+        "fused_env_steps_per_s": r2["env_steps_per_s"], "fused_rays_per_s": r2["rays_per_s"],
+        "fused_us_per_step": r2["ms_per_step"] * 1e3, "plain_us_per_step": r2p["ms_per_step"] * 1e3,
+        "plain_env_steps_per_s": r2p["env_steps_per_s"], "fused_speedup": r2["env_steps_per_s"] / r2p["env_steps_per_s"],
+        "fused_hbm_gbs": r2["achieved_gbs"], "fused_hbm_frac": r2["achieved_gbs"] / HBM_PEAK_GBS,
+        "coded_cells_per_robot_step": r2["coded_cells_per_robot_step"],
+        "fused_exec": f2, "plain_exec": p2, "autotune": t2 or None}
+    print(f"[bench] {name}: fused {r2['ms_per_step']*1e3:.1f} us/step, plain "
+          f"{r2p['ms_per_step']*1e3:.1f} us/step", file=sys.stderr, flush=True)
+    if args.secondary_iters > 0:
+        wb2.env.set_exec(**f2)
+        l2 = train_loop(wb2, args.horizon, args.epochs, args.minibatch, 1, args.secondary_iters, args.seed)
+        res["training_loop"] = l2
+        print(f"[bench] {name}: training iteration {l2['ms_per_iteration']:.2f} ms", file=sys.stderr, flush=True)
+    del wb2
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -363,6 +399,8 @@ def main():
     ap.add_argument("--secondary", default="ragged_4096", help="second workload ('' to skip)")
     ap.add_argument("--secondary-steps", type=int, default=200)
     ap.add_argument("--secondary-iters", type=int, default=2, help="timed training iterations of the secondary")
+    ap.add_argument("--paper-mode", default="paper_sensor_750x256",
+                    help="workload of the paper's sensor / Eq. (7) reward mode, timed like the secondary ('' to skip)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-ppo", action="store_true")
     ap.add_argument("--only-ppo", action="store_true", help="time the PPO minibatch alone (profiling)")
@@ -475,30 +513,9 @@ def main():
         print(f"[bench] PPO fwd {out['ppo']['forward_ms']:.3f} ms, fwd+bwd(recompute) {out['ppo']['backward_ms']:.3f} ms",
               file=sys.stderr, flush=True)
         torch.cuda.empty_cache()
-    if args.secondary:
-        print(f"[bench] {args.secondary}: setting up", file=sys.stderr, flush=True)
-        wb2 = Workbench(args.secondary, args.seed, args.env_warmup + args.secondary_steps, fused)
-        f2, p2, t2 = autotune_forms(wb2) if not args.threads else (fused, plain, {})
-        r2 = wb2.run(args.env_warmup, args.secondary_steps)
-        wb2.env.set_exec(**p2)
-        wb2.env.reset(wb2.world, wb2.start)
-        r2p = wb2.run(args.env_warmup, args.secondary_steps)
-        out["secondary"] = {
-            "workload": args.secondary, "robots": wb2.n, "steps": args.secondary_steps,
-            "fused_env_steps_per_s": r2["env_steps_per_s"], "fused_rays_per_s": r2["rays_per_s"],
-            "plain_env_steps_per_s": r2p["env_steps_per_s"], "fused_speedup": r2["env_steps_per_s"] / r2p["env_steps_per_s"],
-            "fused_hbm_gbs": r2["achieved_gbs"], "fused_hbm_frac": r2["achieved_gbs"] / HBM_PEAK_GBS,
-            "coded_cells_per_robot_step": r2["coded_cells_per_robot_step"],
-            "fused_exec": f2, "plain_exec": p2, "autotune": t2 or None}
-        print(f"[bench] {args.secondary}: fused {r2['ms_per_step']*1e3:.1f} us/step, plain "
-              f"{r2p['ms_per_step']*1e3:.1f} us/step", file=sys.stderr, flush=True)
-        if args.secondary_iters > 0:
-            wb2.env.set_exec(**f2)
-            l2 = train_loop(wb2, args.horizon, args.epochs, args.minibatch, 1, args.secondary_iters, args.seed)
-            out["secondary"]["training_loop"] = l2
-            print(f"[bench] {args.secondary}: training iteration {l2['ms_per_iteration']:.2f} ms", file=sys.stderr,
-                  flush=True)
-        del wb2
+    for key, name in (("secondary", args.secondary), ("paper_mode", args.paper_mode)):
+        if name:
+            out[key] = side_workload(name, args, fused, plain)
     if not args.no_cpu:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_full_loop(args.workload, args.seed, args.cpu_robots, args.horizon, args.epochs)

@@ -39,12 +39,15 @@ class Candidate:
 
 
 def signature(env: Env) -> str:
-    """Workload key: device (CUs, LDS), sides histogram, rays, range, cell size, loop closure."""
+    """Workload key: device (CUs, LDS), sides histogram, rays, range, cell size, loop closure, fan width,
+    reward mode and range noise."""
     lds, cus = device_info()
     sides, counts = np.unique(env.sides, return_counts=True)
     p = env.params
     parts = [f"cu{cus}", f"lds{lds}", "sides" + ",".join(f"{s}x{c}" for s, c in zip(sides, counts)),
-             f"R{p['n_rays']}", f"r{p['r_max_m']:g}", f"c{p['cell_m']:g}", f"lc{int(p['loop_closure'])}"]
+             f"R{p['n_rays']}", f"r{p['r_max_m']:g}", f"c{p['cell_m']:g}", f"lc{int(p['loop_closure'])}",
+             f"fov{int(p.get('fov_steps', 0))}", f"rm{int(p.get('reward_mode', 0))}",
+             f"sn{p.get('range_sigma_m', 0.0):g}"]
     return "/".join(parts)
 
 
