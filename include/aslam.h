@@ -219,6 +219,26 @@ int aslam_policy_forward(aslam_policy* pol, const float* params_dev, const int16
                          const float* state_dev, int32_t batch, float* mu_dev, float* value_dev,
                          aslam_stream_t stream);
 
+/* BF16 copies of the weights that the forward reads (FC1 and FC2), formed
+ * from params_dev into the handle.  aslam_policy_forward, _act (prepared = 0)
+ * and _backward form them themselves; a caller whose parameters do not change
+ * between calls (a rollout) prepares once and passes prepared = 1 to
+ * aslam_policy_act. */
+int aslam_policy_prepare(aslam_policy* pol, const float* params_dev, aslam_stream_t stream);
+
+/* Rollout step of the actor (Sec. III-F): the forward pass and the Gaussian
+ * action sample in one call.  Inputs as aslam_policy_forward; eps_dev [B,2]
+ * standard normals drawn by the caller.  Writes value_dev [B], act_dev [B,2],
+ * logp_dev [B] and, if mu_dev is not NULL, mu_dev [B,2]; the results equal
+ * aslam_policy_forward followed by aslam_policy_sample bit for bit.
+ * prepared = 1 uses the weight copies of the last prepare, forward, act or
+ * backward call on this handle: the caller guarantees that params_dev has not
+ * changed since (ASL_ESTATE if no such call was made); prepared = 0 forms
+ * them first. */
+int aslam_policy_act(aslam_policy* pol, const float* params_dev, int32_t prepared, const int16_t* crop_dev,
+                     const float* scan_dev, const float* state_dev, int32_t batch, const float* eps_dev,
+                     float* mu_dev, float* value_dev, float* act_dev, float* logp_dev, aslam_stream_t stream);
+
 /* PPO loss and its gradient over one minibatch, recomputing the forward
  * activations (only the inputs are stored across the rollout).
  *   loss = L_clip + c_value * mean((V - ret)^2) - c_entropy * H[pi],

@@ -151,8 +151,11 @@ __device__ __forceinline__ bf16x8 conv2_col_frag(const uint16_t* s_a1, int oy, i
   return __builtin_bit_cast(bf16x8, u);
 }
 
-// Encoder forward: a2[b * lda2 + co*256 + oy*16 + ox] = bf16(relu(conv2(relu(conv1(crop_b))))).
-__global__ __launch_bounds__(256) void k_conv_fwd(const float* prm, Offsets o, const int16_t* crop, uint16_t* a2,
+// Encoder forward: a2[b * lda2 + co*256 + oy*16 + ox] = bf16(relu(conv2(relu(conv1(crop_b))))), and
+// the rest of the FC1 input row: a2[b * lda2 + 8192 + j] = bf16(scan_b[j]), then bf16(state_b), then
+// zeros up to lda2.
+__global__ __launch_bounds__(256) void k_conv_fwd(const float* prm, Offsets o, const int16_t* crop,
+                                                  const float* scan, const float* state, int R, uint16_t* a2,
                                                   int64_t lda2, int B) {
   __shared__ __align__(16) uint16_t s_crop[kCropLds];
   __shared__ __align__(16) uint16_t s_a1[kA1Lds];
@@ -182,6 +185,12 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const float* prm, Offsets o, c
     // the next sample's crop is loaded while this one is processed
     if (b + (int)gridDim.x < B) load_crop<256>(crop + (int64_t)(b + gridDim.x) * kCrop * kCrop, cr);
     conv1_lds(s_crop, s_a1, w1f, b1, wave, lr, lg);
+    for (int j = threadIdx.x; j < (int)(lda2 - kFeat); j += 256) {
+      float v = 0.0f;
+      if (j < R) v = scan[(int64_t)b * R + j];
+      else if (j < R + 12) v = state[(int64_t)b * 12 + (j - R)];
+      a2[(int64_t)b * lda2 + kFeat + j] = j < R + 12 ? f2bf(v) : (uint16_t)0;
+    }
     __syncthreads();
     for (int oy = wave; oy < kA2; oy += 4) {
       f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};

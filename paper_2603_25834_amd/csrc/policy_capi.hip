@@ -37,6 +37,7 @@ struct aslam_policy {
   uint16_t *w1b = nullptr, *w1t = nullptr, *w2b = nullptr, *w2t = nullptr;   // BF16 weight copies
   int32_t k1p = 0;   // FC1 input width padded to a multiple of 8
   int64_t part_floats = 0;
+  bool prepared = false;   // w1b / w2b hold the weights of some params (the caller tracks which)
 };
 
 namespace {
@@ -86,30 +87,33 @@ int64_t part_need(const aslam_policy* p) {
     if (e_ != hipSuccess) return pfail(ASL_EHIP, hipGetErrorString(e_)); \
   } while (0)
 
-// Forward to the FC2 pre-activation z2 (FP32); need_transposed also prepares the transposed BF16
-// weights that the backward's input gradients read.
-int forward_core(aslam_policy* P, const float* prm, const int16_t* crop, const float* scan, const float* state,
-                 int B, hipStream_t st, bool need_transposed) {
+// BF16 copies of W1 (rows padded to k1p) and W2 that the forward reads; with `transposed` also the
+// transposes that the backward's input gradients read.
+int convert_weights(aslam_policy* P, const float* prm, hipStream_t st, bool transposed) {
   const Offsets& o = P->off;
-  const int R = P->cfg.n_scan;
-  // BF16 weight copies: W1 (rows padded), W2, and the transposes the backward's input gradients read
   k_convert_bf16<<<1024, 256, 0, st>>>(prm + o.f1w, o.k1, kHid, o.k1, P->w1b, P->k1p);
   PCHK(hipGetLastError());
   k_convert_bf16<<<256, 256, 0, st>>>(prm + o.f2w, kHid, kHid, kHid, P->w2b, kHid);
   PCHK(hipGetLastError());
-  if (need_transposed) {
+  if (transposed) {
     k_transpose_bf16<<<dim3(kFeat / 32, kHid / 32), 256, 0, st>>>(prm + o.f1w, o.k1, kHid, kFeat, P->w1t, kHid);
     PCHK(hipGetLastError());
     k_transpose_bf16<<<dim3(kHid / 32, kHid / 32), 256, 0, st>>>(prm + o.f2w, kHid, kHid, kHid, P->w2t, kHid);
     PCHK(hipGetLastError());
   }
-  k_conv_fwd<<<std::min(B, kConvGrid), 256, 0, st>>>(prm, o, crop, P->x, P->k1p, B);
+  P->prepared = true;
+  return ASL_OK;
+}
+
+// Encoder (conv features and the scan / state tail into the FC1 input x) and FC1.  Small batches
+// split K so that the launch fills the chip: then *S_used split-K slices are left in P->part;
+// otherwise FC1 writes h1 = bf16(relu(. + b1)) and *S_used = 0.
+int encode_fc1(aslam_policy* P, const float* prm, const int16_t* crop, const float* scan, const float* state, int B,
+               hipStream_t st, int* S_used) {
+  const Offsets& o = P->off;
+  k_conv_fwd<<<std::min(B, kConvGrid), 256, 0, st>>>(prm, o, crop, scan, state, P->cfg.n_scan, P->x, P->k1p, B);
   PCHK(hipGetLastError());
-  k_pack_tail<<<(int)std::min<int64_t>(1024, ((int64_t)B * (P->k1p - kFeat) + 255) / 256), 256, 0, st>>>(
-      scan, state, R, B, P->x, P->k1p);
-  PCHK(hipGetLastError());
-  // FC1: [B x k1p] x [k1p x 256] (both operands zero-padded from k1 to k1p); small batches split K
-  // so that the launch fills the chip
+  // FC1: [B x k1p] x [k1p x 256] (both operands zero-padded from k1 to k1p)
   const int K1 = P->k1p;
   const LdBF16K xa{P->x, K1, B, K1};
   const LdBF16K wa{P->w1b, K1, kHid, K1};
@@ -118,18 +122,49 @@ int forward_core(aslam_policy* P, const float* prm, const int16_t* crop, const f
   while (tiles * S < kFc1MinBlocks && S < 32) S *= 2;
   if (S == 1) {
     PCHK((gemm::run<128, 128, 64, 2, 2>(xa, wa, EpiBiasReluBF16{P->h1, prm + o.f1b, kHid}, B, kHid, K1, 1, st)));
+    *S_used = 0;
   } else {
-    const int used = slices_used(K1, S, 64);
+    *S_used = slices_used(K1, S, 64);
     PCHK((gemm::run<128, 128, 64, 2, 2>(xa, wa, EpiPartial{P->part, kHid, (int64_t)B * kHid}, B, kHid, K1, S,
                                          st)));
+  }
+  return ASL_OK;
+}
+
+// The backward's forward: every weight copy, the encoder, FC1 to h1 and the FC2 pre-activation z2 (FP32).
+int forward_core(aslam_policy* P, const float* prm, const int16_t* crop, const float* scan, const float* state,
+                 int B, hipStream_t st) {
+  const Offsets& o = P->off;
+  int rc = convert_weights(P, prm, st, true);
+  if (rc) return rc;
+  int S = 0;
+  rc = encode_fc1(P, prm, crop, scan, state, B, st, &S);
+  if (rc) return rc;
+  if (S > 0) {
     const int64_t groups = (int64_t)B * (kHid / 8);
     k_reduce_bias_relu_bf16<<<(int)std::min<int64_t>(4096, (groups + 255) / 256), 256, 0, st>>>(
-        P->part, used, B, kHid, prm + o.f1b, P->h1, kHid);
+        P->part, S, B, kHid, prm + o.f1b, P->h1, kHid);
     PCHK(hipGetLastError());
   }
-  // FC2 pre-activation (FP32): [B x 256] x [256 x 256]
   PCHK((gemm::run<128, 128, 64, 2, 2>(LdBF16K{P->h1, kHid, B, kHid}, LdBF16K{P->w2b, kHid, kHid, kHid},
                                      EpiBiasF32{P->z2, prm + o.f2b, kHid}, B, kHid, kHid, 1, st)));
+  return ASL_OK;
+}
+
+// Forward-only pass: encoder, FC1, then the fused tail (FC2, heads and, with eps, the sample).
+int act_core(aslam_policy* P, const float* prm, bool prepared, const int16_t* crop, const float* scan,
+             const float* state, int B, const float* eps, float* mu, float* value, float* act, float* logp,
+             hipStream_t st) {
+  if (!prepared) {
+    int rc = convert_weights(P, prm, st, false);
+    if (rc) return rc;
+  }
+  int S = 0;
+  int rc = encode_fc1(P, prm, crop, scan, state, B, st, &S);
+  if (rc) return rc;
+  k_fwd_tail<<<(B + kTailRows - 1) / kTailRows, 256, 0, st>>>(prm, P->off, P->part, S, P->h1, P->w2b, B, mu, value,
+                                                              eps, act, logp);
+  PCHK(hipGetLastError());
   return ASL_OK;
 }
 
@@ -189,14 +224,24 @@ int aslam_policy_forward(aslam_policy* P, const float* params, const int16_t* cr
                          const float* state, int32_t batch, float* mu, float* value, aslam_stream_t stream) {
   if (!P || !params || !crop || !scan || !state || !mu || !value) return pfail(ASL_EINVAL, "null argument");
   if (batch < 1 || batch > P->max_b) return pfail(ASL_EINVAL, "batch must be in [1, max_batch]");
-  hipStream_t st = (hipStream_t)stream;
-  int rc = forward_core(P, params, crop, scan, state, batch, st, false);
-  if (rc) return rc;
-  const int nb = (batch + kHeadRows - 1) / kHeadRows;
-  k_heads<false><<<nb, 256, 0, st>>>(params, P->off, P->z2, batch, mu, value, nullptr, nullptr, nullptr, nullptr,
-                                     LossCoef{0, 0, 0, 0}, nullptr, nullptr);
-  PCHK(hipGetLastError());
-  return ASL_OK;
+  return act_core(P, params, false, crop, scan, state, batch, nullptr, mu, value, nullptr, nullptr,
+                  (hipStream_t)stream);
+}
+
+int aslam_policy_prepare(aslam_policy* P, const float* params, aslam_stream_t stream) {
+  if (!P || !params) return pfail(ASL_EINVAL, "null argument");
+  return convert_weights(P, params, (hipStream_t)stream, false);
+}
+
+int aslam_policy_act(aslam_policy* P, const float* params, int32_t prepared, const int16_t* crop, const float* scan,
+                     const float* state, int32_t batch, const float* eps, float* mu, float* value, float* act,
+                     float* logp, aslam_stream_t stream) {
+  if (!P || !params || !crop || !scan || !state || !eps || !value || !act || !logp)
+    return pfail(ASL_EINVAL, "null argument");
+  if (batch < 1 || batch > P->max_b) return pfail(ASL_EINVAL, "batch must be in [1, max_batch]");
+  if (prepared && !P->prepared) return pfail(ASL_ESTATE, "act with prepared = 1 before any prepare");
+  return act_core(P, params, prepared != 0, crop, scan, state, batch, eps, mu, value, act, logp,
+                  (hipStream_t)stream);
 }
 
 int aslam_policy_backward(aslam_policy* P, const float* params, const int16_t* crop, const float* scan,
@@ -209,7 +254,7 @@ int aslam_policy_backward(aslam_policy* P, const float* params, const int16_t* c
   const Offsets& o = P->off;
   const int B = batch;
   const int R = P->cfg.n_scan;
-  int rc = forward_core(P, params, crop, scan, state, B, st, true);
+  int rc = forward_core(P, params, crop, scan, state, B, st);
   if (rc) return rc;
   // heads + loss -> dz2, head / fc2-bias / log-std partial sums
   const int nb = (B + kHeadRows - 1) / kHeadRows;

@@ -485,19 +485,118 @@ __global__ __launch_bounds__(256) void k_transpose_bf16(const float* src, int64_
   }
 }
 
-// FC1 input tail: X[b][8192 + j] = bf16(scan[b][j]), X[b][8192 + R + j] = bf16(state[b][j]), zero up
-// to the padded width ldx (the conv features X[b][0 .. 8191] are written by the encoder).
-__global__ void k_pack_tail(const float* scan, const float* state, int R, int B, uint16_t* x, int64_t ldx) {
-  const int tail = (int)(ldx - kFeat);
-  const int64_t total = (int64_t)B * tail;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t b = i / tail;
-    const int j = (int)(i - b * tail);
-    float v = 0.0f;
-    if (j < R) v = scan[b * R + j];
-    else if (j < R + 12) v = state[b * 12 + (j - R)];
-    x[b * ldx + kFeat + j] = j < R + 12 ? f2bf(v) : (uint16_t)0;
+// Forward tail of a tile of kTailRows rows, for the forward-only calls: the FC1 split-K sum (slices in
+// order) + bias + ReLU rounded to BF16 (or the BF16 h1 rows when S == 0), FC2 on MFMA with the k
+// chunks in the GEMM engine's order, + bias, then the heads and, when eps is given, the Gaussian
+// action sample.  Every value is formed by the same operations in the same order as the unfused
+// sequence (split-K reduce, FC2 GEMM, k_heads, k_sample), so the outputs are bit-identical to it.
+constexpr int kTailRows = 16;
+constexpr int kTailLdH = kHid + 8;   // BF16 h1 rows in LDS, padded
+constexpr int kTailLdZ = kHid + 4;   // FP32 z2 rows in LDS, padded
+
+__global__ __launch_bounds__(256) void k_fwd_tail(const float* prm, Offsets o, const float* part, int S,
+                                                  const uint16_t* h1, const uint16_t* w2b, int B, float* mu_out,
+                                                  float* v_out, const float* eps, float* act, float* logp) {
+  __shared__ __align__(16) uint16_t s_h[kTailRows * kTailLdH];
+  __shared__ __align__(16) float s_z[kTailRows * kTailLdZ];
+  const int row0 = blockIdx.x * kTailRows;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
+  const float* b1 = prm + o.f1b;
+  for (int g = threadIdx.x; g < kTailRows * (kHid / 8); g += 256) {
+    const int r = g / (kHid / 8), n0 = (g % (kHid / 8)) * 8;
+    const int64_t m = row0 + r;
+    uint4 v = make_uint4(0u, 0u, 0u, 0u);
+    if (m < B) {
+      if (S > 0) {
+        float a[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) a[j] = 0.0f;
+        const float* q = part + m * kHid + n0;
+        for (int z = 0; z < S; ++z) {
+          const float4 lo = *reinterpret_cast<const float4*>(q + (int64_t)z * B * kHid);
+          const float4 hi = *reinterpret_cast<const float4*>(q + (int64_t)z * B * kHid + 4);
+          a[0] += lo.x; a[1] += lo.y; a[2] += lo.z; a[3] += lo.w;
+          a[4] += hi.x; a[5] += hi.y; a[6] += hi.z; a[7] += hi.w;
+        }
+        uint16_t h[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) h[j] = f2bf(fmaxf(a[j] + b1[n0 + j], 0.0f));
+        v = pack8(h);
+      } else {
+        v = *reinterpret_cast<const uint4*>(h1 + m * kHid + n0);
+      }
+    }
+    *reinterpret_cast<uint4*>(s_h + r * kTailLdH + n0) = v;
+  }
+  __syncthreads();
+  // FC2: wave w owns columns 64 w .. 64 w + 63 (four 16-column fragments)
+  gemm::f32x4 acc[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) acc[j] = gemm::f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int k0 = 0; k0 < kHid; k0 += 32) {
+    const gemm::bf16x8 af =
+        __builtin_bit_cast(gemm::bf16x8, *reinterpret_cast<const uint4*>(s_h + lr * kTailLdH + k0 + 8 * lg));
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int n = 64 * wave + 16 * j + lr;
+      const gemm::bf16x8 bf =
+          __builtin_bit_cast(gemm::bf16x8, *reinterpret_cast<const uint4*>(w2b + (int64_t)n * kHid + k0 + 8 * lg));
+      acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bf, acc[j], 0, 0, 0);
+    }
+  }
+  const float* b2 = prm + o.f2b;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int c = 64 * wave + 16 * j + lr;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) s_z[(4 * lg + i) * kTailLdZ + c] = acc[j][i] + b2[c];
+  }
+  __syncthreads();
+  // heads: wave w takes rows 4 w .. 4 w + 3, lane l holds z2 columns 4 l .. 4 l + 3 (as k_heads)
+  float wmu0[4], wmu1[4], wv[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    wmu0[e] = prm[o.muw + lane * 4 + e];
+    wmu1[e] = prm[o.muw + kHid + lane * 4 + e];
+    wv[e] = prm[o.vw + lane * 4 + e];
+  }
+  const float bmu0 = prm[o.mub], bmu1 = prm[o.mub + 1], bv = prm[o.vb];
+  for (int rr = 0; rr < kTailRows / 4; ++rr) {
+    const int r = 4 * wave + rr;
+    const int64_t row = row0 + r;
+    if (row >= B) break;
+    const float4 zz = *reinterpret_cast<const float4*>(s_z + r * kTailLdZ + lane * 4);
+    const float z[4] = {zz.x, zz.y, zz.z, zz.w};
+    float s0 = 0, s1 = 0, sv = 0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const float h = fmaxf(z[e], 0.0f);
+      s0 += wmu0[e] * h;
+      s1 += wmu1[e] * h;
+      sv += wv[e] * h;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      s0 += __shfl_xor(s0, off, 64);
+      s1 += __shfl_xor(s1, off, 64);
+      sv += __shfl_xor(sv, off, 64);
+    }
+    if (lane == 0) {
+      const float m0 = s0 + bmu0, m1 = s1 + bmu1;
+      if (mu_out) {
+        mu_out[2 * row] = m0;
+        mu_out[2 * row + 1] = m1;
+      }
+      v_out[row] = sv + bv;
+      if (eps) {
+        const float ls0 = prm[o.lstd], ls1 = prm[o.lstd + 1];
+        const float e0 = eps[2 * row], e1 = eps[2 * row + 1];
+        act[2 * row] = m0 + expf(ls0) * e0;
+        act[2 * row + 1] = m1 + expf(ls1) * e1;
+        logp[row] = -0.5f * (e0 * e0 + e1 * e1) - (ls0 + ls1) - 1.8378770664093453f;
+      }
+    }
   }
 }
 

@@ -14,6 +14,8 @@ from ._lib import PolicyConfig, check, lib
 
 
 def _p(t):
+    if t is None:
+        return None
     assert t.is_cuda and t.is_contiguous(), "device tensors must be contiguous CUDA tensors"
     return ctypes.c_void_p(t.data_ptr())
 
@@ -62,6 +64,24 @@ class Policy:
         check(lib().aslam_policy_forward(self.h, _p(params), _p(crop), _p(scan), _p(state), B, _p(mu), _p(value),
                                          _stream()))
         return mu, value
+
+    def prepare(self, params):
+        """Form the BF16 weight copies of the forward from `params` (for act(prepared=True))."""
+        assert params.dtype == torch.float32 and params.numel() == self.n_params
+        check(lib().aslam_policy_prepare(self.h, _p(params), _stream()))
+
+    def act(self, params, crop, scan, state, eps, value=None, act=None, logp=None, mu=None, prepared=False):
+        """Forward + Gaussian sample in one call: value [B], act [B, 2], logp [B] (and mu [B, 2] if given).
+        prepared=True reuses the weight copies of the last prepare/forward/act/backward call; the caller
+        guarantees that `params` has not changed since."""
+        B = self._check_obs(params, crop, scan, state)
+        assert eps.dtype == torch.float32 and tuple(eps.shape) == (B, 2)
+        value = torch.empty(B, device=crop.device) if value is None else value
+        act = torch.empty((B, 2), device=crop.device) if act is None else act
+        logp = torch.empty(B, device=crop.device) if logp is None else logp
+        check(lib().aslam_policy_act(self.h, _p(params), int(bool(prepared)), _p(crop), _p(scan), _p(state), B,
+                                     _p(eps), _p(mu), _p(value), _p(act), _p(logp), _stream()))
+        return value, act, logp
 
     def backward(self, params, crop, scan, state, act, old_logp, adv, ret, grads, loss=None):
         """Adds the PPO loss gradient of this minibatch to `grads`; returns loss terms [4]."""

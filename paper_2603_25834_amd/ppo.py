@@ -3,9 +3,9 @@
 Method: arXiv 2603.25834 Sec. III-F (PPO with the clipped surrogate of Eqs. 18-20 and GAE) driving the
 batched POMDP step of Sec. III-B.  One iteration:
 
-  rollout, t = 0 .. T-1:  observe (scan, pose + covariance, 64x64 belief crop) -> policy forward
-      (mean, value) -> Gaussian action sample -> env step (reward, done) -> masked reset of the
-      robots whose episode ended;
+  rollout, t = 0 .. T-1:  observe (scan, pose + covariance, 64x64 belief crop) -> policy forward and
+      Gaussian action sample in one call (value, action, log-prob; the BF16 weight copies are formed
+      once per rollout) -> env step (reward, done) -> masked reset of the robots whose episode ended;
   bootstrap value of the last observation; GAE over the [T, N] rollout;
   update: `epochs` passes over the T*N samples in shuffled minibatches: row gather -> fused loss and
       gradient (activations recomputed from the stored inputs) -> Adam.
@@ -45,7 +45,8 @@ class PPOTrainer:
         self.crop = torch.zeros((T + 1, n, crop, crop), dtype=torch.int16, device=dev)
         self.scan = torch.zeros((T + 1, n, R), device=dev)
         self.state = torch.zeros((T + 1, n, 12), device=dev)
-        self.mu = torch.zeros((n, 2), device=dev)
+        self.act_boot = torch.zeros((n, 2), device=dev)   # the bootstrap step's sample (unused)
+        self.logp_boot = torch.zeros(n, device=dev)
         self.act = torch.zeros((T, n, 2), device=dev)
         self.logp = torch.zeros((T, n), device=dev)
         self.value = torch.zeros((T + 1, n), device=dev)
@@ -77,14 +78,16 @@ class PPOTrainer:
     def iteration(self, noise: torch.Tensor, eps: torch.Tensor, perm: torch.Tensor) -> None:
         """One rollout of T steps and `epochs` update passes (all launches on the current stream)."""
         env, pol, p = self.env, self.policy, self.params
+        pol.prepare(p)   # the parameters are fixed during the rollout
         for t in range(self.T):
             env.observe(self.ranges, self.crop[t], self.scan[t], self.state[t])
-            pol.forward(p, self.crop[t], self.scan[t], self.state[t], self.mu, self.value[t])
-            pol.sample(p, self.mu, eps[t], self.act[t], self.logp[t])
+            pol.act(p, self.crop[t], self.scan[t], self.state[t], eps[t], self.value[t], self.act[t], self.logp[t],
+                    prepared=True)
             env.step(self.act[t], noise[t], self.ranges, self.reward[t], self.done[t])
             env.reset(self.world, self.start, mask=self.done[t])
         env.observe(self.ranges, self.crop[self.T], self.scan[self.T], self.state[self.T])
-        pol.forward(p, self.crop[self.T], self.scan[self.T], self.state[self.T], self.mu, self.value[self.T])
+        pol.act(p, self.crop[self.T], self.scan[self.T], self.state[self.T], eps[self.T - 1], self.value[self.T],
+                self.act_boot, self.logp_boot, prepared=True)
         adv, ret = gae(self.reward, self.value[:self.T].contiguous(), self.done, self.value[self.T],
                        self.gamma, self.lam)
         flat = {

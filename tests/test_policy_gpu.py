@@ -256,3 +256,52 @@ def test_sample_and_gather():
         got = gather_rows(src, idx)
         assert torch.equal(got.cpu(), src.cpu()[idx.cpu().long()])
     assert gather_rows(crops, idx[:0]).shape == (0, 64, 64)
+
+
+@pytest.mark.parametrize("B", [1, 750, 4096])
+def test_act_equals_forward_and_sample(B):
+    """The rollout call (forward and sample in one, the FC1 split-K sum, FC2, heads and sample fused)
+    equals forward followed by sample bit for bit, with freshly formed and with prepared weights."""
+    from paper_2603_25834_amd import _lib
+    from paper_2603_25834_amd.policy import Policy
+    theta, t = _case(B, 12)
+    theta[-2:] = [-0.4, 0.2]
+    say(f"[policy] act B={B}")
+    pol, params, dev = _gpu(theta, t)
+    eps = torch.from_numpy(np.random.default_rng(12).normal(size=(B, 2)).astype(np.float32)).cuda()
+    fresh = Policy(R, max_batch=8)
+    with pytest.raises(_lib.AslamError) as ei:
+        fresh.act(params, dev["crop"][:1], dev["scan"][:1], dev["state"][:1], eps[:1], prepared=True)
+    assert ei.value.code == -4
+    mu, value = pol.forward(params, dev["crop"], dev["scan"], dev["state"])
+    act, logp = pol.sample(params, mu, eps)
+    v1, a1, l1 = pol.act(params, dev["crop"], dev["scan"], dev["state"], eps)
+    mu2 = torch.empty_like(mu)
+    pol.prepare(params)
+    v2, a2, l2 = pol.act(params, dev["crop"], dev["scan"], dev["state"], eps, mu=mu2, prepared=True)
+    torch.cuda.synchronize()
+    for x, y in ((v1, value), (a1, act), (l1, logp), (v2, value), (a2, act), (l2, logp), (mu2, mu)):
+        assert torch.equal(x, y)
+
+
+def test_forward_unsplit_fc1_sampled_rows():
+    """B = 32769 fills the chip without K splits, so FC1 writes h1 itself and the fused tail reads it;
+    64 sampled rows checked against the workload-precision oracle."""
+    from paper_2603_25834_amd.policy import Policy
+    B = 32769
+    theta = synth.init_policy_params(R, 13)
+    d = synth.policy_batch(B, R, 13)
+    say(f"[policy] forward B={B} (sampled rows)")
+    pol = Policy(R, max_batch=B)
+    params = torch.from_numpy(theta).cuda()
+    mu, value = pol.forward(params, *(torch.from_numpy(d[k]).cuda() for k in ("crop", "scan", "state")))
+    torch.cuda.synchronize()
+    rows = np.sort(np.random.default_rng(13).choice(B, 64, replace=False))
+    sub = {k: torch.from_numpy(d[k][rows]) for k in ("crop", "scan", "state")}
+    with torch.no_grad():
+        mb, _, vb = PR.forward_bf16(torch.from_numpy(theta).double(), sub["crop"], sub["scan"], sub["state"], SHAPE)
+    gm, gv = mu.cpu().double().numpy()[rows], value.cpu().double().numpy()[rows]
+    eb = max(np.linalg.norm(gm - mb.numpy()) / np.linalg.norm(mb.numpy()),
+             np.linalg.norm(gv - vb.numpy()) / np.linalg.norm(vb.numpy()))
+    say(f"[policy] unsplit forward rel err vs workload precision {eb:.2e}")
+    assert eb < 2e-3
