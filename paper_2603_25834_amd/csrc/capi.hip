@@ -181,7 +181,7 @@ int plan_lds(aslam_env* e, const aslam_exec_config& ex, LdsPlan& L) {
   const int32_t hu = rhat_cells + 3;
   for (int32_t s : e->sides) {
     const int64_t rows = std::min<int64_t>(s, 2 * (int64_t)L.world_halo + 1);
-    world_max = std::max<int64_t>(world_max, rows * (s / 32) * 4);
+    world_max = std::max<int64_t>(world_max, (rows * (s / 32) + 2 * (int64_t)march_guard_words(s)) * 4);
     const int64_t span = std::min<int64_t>(s, 2 * (int64_t)hu + 1);
     nw_max = std::max<int64_t>(nw_max, std::min<int64_t>(s / 32, (span + 31) / 32 + 1));
     rows_max = std::max<int64_t>(rows_max, span);

@@ -82,6 +82,23 @@ __device__ __forceinline__ bf16x8 conv2_weight_frag(const float* w2, int co, int
   return __builtin_bit_cast(bf16x8, u);
 }
 
+// The forward's weight fragments, formed once per parameter update: fragment f < 11 of lane l at
+// frag[64 f + l]; f = 0 is conv1's A operand, f = 1 + 5 nt + s is conv2's B operand for output
+// channels 16 nt .. 16 nt + 15 and k slice s (the values conv1_weight_frag / conv2_weight_frag give).
+constexpr int kConvFrags = 11;
+
+__global__ __launch_bounds__(64 * kConvFrags) void k_conv_frags(const float* prm, Offsets o, uint4* frag) {
+  const int f = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
+  bf16x8 v;
+  if (f == 0) {
+    v = conv1_weight_frag(prm + o.c1w, lr, lg);
+  } else {
+    const int nt = (f - 1) / 5, s = (f - 1) % 5;
+    v = conv2_weight_frag(prm + o.c2w, 16 * nt + lr, s, lg);
+  }
+  frag[threadIdx.x] = __builtin_bit_cast(uint4, v);
+}
+
 // A 64x64 int16 crop is 512 vectors of eight cells (row y = v / 8, columns
 // 8 (v % 8) .. + 7); a workgroup of NT threads holds 512 / NT of them per
 // thread in registers, so the next sample's crop can be in flight while the
@@ -154,9 +171,9 @@ __device__ __forceinline__ bf16x8 conv2_col_frag(const uint16_t* s_a1, int oy, i
 // Encoder forward: a2[b * lda2 + co*256 + oy*16 + ox] = bf16(relu(conv2(relu(conv1(crop_b))))), and
 // the rest of the FC1 input row: a2[b * lda2 + 8192 + j] = bf16(scan_b[j]), then bf16(state_b), then
 // zeros up to lda2.
-__global__ __launch_bounds__(256) void k_conv_fwd(const float* prm, Offsets o, const int16_t* crop,
-                                                  const float* scan, const float* state, int R, uint16_t* a2,
-                                                  int64_t lda2, int B) {
+__global__ __launch_bounds__(256) void k_conv_fwd(const float* prm, Offsets o, const uint4* frag,
+                                                  const int16_t* crop, const float* scan, const float* state, int R,
+                                                  uint16_t* a2, int64_t lda2, int B) {
   __shared__ __align__(16) uint16_t s_crop[kCropLds];
   __shared__ __align__(16) uint16_t s_a1[kA1Lds];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
@@ -166,7 +183,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const float* prm, Offsets o, c
     z = reinterpret_cast<uint4*>(s_a1);
     for (int i = threadIdx.x; i < kA1Lds / 8; i += 256) z[i] = make_uint4(0u, 0u, 0u, 0u);
   }
-  const bf16x8 w1f = conv1_weight_frag(prm + o.c1w, lr, lg);
+  const bf16x8 w1f = __builtin_bit_cast(bf16x8, frag[lane]);
   float b1[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) b1[i] = prm[o.c1b + 4 * lg + i];
@@ -174,7 +191,7 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const float* prm, Offsets o, c
 #pragma unroll
   for (int nt = 0; nt < 2; ++nt)
 #pragma unroll
-    for (int s = 0; s < 5; ++s) w2f[nt][s] = conv2_weight_frag(prm + o.c2w, 16 * nt + lr, s, lg);
+    for (int s = 0; s < 5; ++s) w2f[nt][s] = __builtin_bit_cast(bf16x8, frag[64 * (1 + 5 * nt + s) + lane]);
   const float b2[2] = {prm[o.c2b + lr], prm[o.c2b + 16 + lr]};
   CropRegs<256> cr;
   if (blockIdx.x < B) load_crop<256>(crop + (int64_t)blockIdx.x * kCrop * kCrop, cr);

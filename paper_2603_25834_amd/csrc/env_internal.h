@@ -14,6 +14,13 @@ namespace aslam {
 constexpr int kNang = 46080;     // heading steps per turn
 constexpr int kQ16 = 65536;      // position unit: 1/65536 cell
 constexpr int kDirOne = 16384;   // direction unit in the heading table (Q14)
+constexpr int kMarchLook = 8;    // DDA steps per LDS round trip in the LiDAR march
+
+// Guard words before and after the staged world rows of a grid of side s: a
+// lane reads up to kMarchLook steps past the end of its walk (never counted
+// as hits), i.e. at most kMarchLook rows and one word beyond the window, so
+// with this much addressable LDS on both sides no read needs a clamp.
+__host__ __device__ inline int32_t march_guard_words(int32_t s) { return (kMarchLook * (s >> 5) + 1 + 3) & ~3; }
 
 struct RobotMeta {
   int32_t side;        // s

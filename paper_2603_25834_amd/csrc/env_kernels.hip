@@ -104,6 +104,25 @@ __device__ bool near_obstacle(const uint32_t* w, int32_t s, int32_t px, int32_t 
   return false;
 }
 
+// The same test by a whole workgroup, one cell per thread; sets *flag (LDS) when some cell is near.
+template <int NT>
+__device__ void near_obstacle_wg(const uint32_t* w, int32_t s, int32_t px, int32_t py, int32_t rc, int32_t* flag) {
+  const int32_t cx = px >> 16, cy = py >> 16;
+  const int32_t m = rc / kQ16 + 1, side = 2 * m + 1;
+  const int64_t rc2 = (int64_t)rc * rc;
+  bool near = false;
+  for (int32_t k = threadIdx.x; k < side * side; k += NT) {
+    const int32_t j = cy - m + k / side, i = cx - m + k % side;
+    const bool occ = (i < 0 || j < 0 || i >= s || j >= s) || world_bit(w, s, i, j);
+    if (occ) {
+      const int64_t dx = max(max((int64_t)i * kQ16 - px, (int64_t)px - (int64_t)(i + 1) * kQ16), (int64_t)0);
+      const int64_t dy = max(max((int64_t)j * kQ16 - py, (int64_t)py - (int64_t)(j + 1) * kQ16), (int64_t)0);
+      near = near || dx * dx + dy * dy < rc2;
+    }
+  }
+  if (__builtin_amdgcn_ballot_w64(near) != 0 && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
+}
+
 // Heading index of ray 0 of the fan whose heading index is ib.
 __device__ __forceinline__ int32_t fan_base(const EnvParams& P, int32_t ib) {
   const int32_t id = ib + P.ray0;
@@ -156,8 +175,9 @@ struct MotionOut {
   int32_t collided, closed;
 };
 
-// Motion, collision, EKF predict and loop closure of robot r (one thread).
-__device__ MotionOut robot_motion(const EnvParams& P, const StepArgs& A, int32_t r) {
+// Motion, collision, EKF predict and loop closure of robot r (one thread).  The proximity part of the
+// collision test is done here when `proximity` is set; the fused step does it with the whole workgroup.
+__device__ MotionOut robot_motion(const EnvParams& P, const StepArgs& A, int32_t r, bool proximity) {
   const RobotMeta m = P.meta[r];
   const int32_t s = m.side;
   const float a0 = A.actions[2 * r], a1 = A.actions[2 * r + 1];
@@ -187,7 +207,8 @@ __device__ MotionOut robot_motion(const EnvParams& P, const StepArgs& A, int32_t
   }
   // the paper's collision: closer than d_crash to an obstacle (the move stands)
   int32_t collided = col;
-  if (P.crash_q > 0 && !col && near_obstacle(W, s, to_q16(px, P.inv_c16), to_q16(py, P.inv_c16), P.crash_q))
+  if (proximity && P.crash_q > 0 && !col &&
+      near_obstacle(W, s, to_q16(px, P.inv_c16), to_q16(py, P.inv_c16), P.crash_q))
     collided = 1;
 
   // EKF predict; F uses the estimated heading before the step.
@@ -299,7 +320,7 @@ struct RobotShared {
   int32_t cnt_march, cnt_upd;
   int32_t bx0, bx1, by0, by1;   // cell bounding box of the ray end points (estimated pose)
   int32_t dmin_bits;            // FP32 bits of the smallest reported range (non-negative)
-  int32_t pad;
+  int32_t near;                 // proximity collision found by the workgroup
   long long part[16];
   int32_t dpart[16];
 };
@@ -514,7 +535,7 @@ __device__ void stage_world(const EnvParams& P, const RobotMeta& m, int32_t cy, 
   wy0 = y0;
 }
 
-constexpr int kLook = 8;   // DDA steps per LDS round trip in the march
+constexpr int kLook = kMarchLook;
 
 // LiDAR march of every ray of the robot from the true pose (lanes = rays),
 // then the reported range of each ray (sensor model of Sec. IV-A: true range
@@ -522,7 +543,7 @@ constexpr int kLook = 8;   // DDA steps per LDS round trip in the march
 // update walks the reported range; gr holds the ray noise draws.
 template <int NT>
 __device__ void march_rays(const EnvParams& P, const RobotMeta& m, const LdsView& V, const uint32_t* sw,
-                           int32_t wy0, int32_t wmax, float* ranges_out, const float* gr, bool record, int32_t r) {
+                           int32_t wy0, float* ranges_out, const float* gr, bool record, int32_t r) {
   RobotShared* sh = V.sh;
   int32_t* rho_lds = V.rho;
   const int32_t s = m.side;
@@ -556,8 +577,8 @@ __device__ void march_rays(const EnvParams& P, const RobotMeta& m, const LdsView
     }
     // kLook cells per iteration: the next kLook DDA steps are taken first and
     // their world words read together, so one LDS round trip covers kLook
-    // cells.  Steps past the walk's own count n are read (word index clamped
-    // to the staged buffer) but never count as hits.
+    // cells.  Steps past the walk's own count n are read (from the guard
+    // words around the staged rows) but never count as hits.
     while (__builtin_amdgcn_ballot_w64(!done) != 0) {
       if (!done) {
         int32_t l[kLook], d[kLook];
@@ -572,7 +593,7 @@ __device__ void march_rays(const EnvParams& P, const RobotMeta& m, const LdsView
         }
         uint32_t wd[kLook];
 #pragma unroll
-        for (int u = 0; u < kLook; ++u) wd[u] = sw[min(max(l[u] >> 5, 0), wmax)];
+        for (int u = 0; u < kLook; ++u) wd[u] = sw[l[u] >> 5];   // inside the guard words
         uint32_t bits = 0u;
 #pragma unroll
         for (int u = 0; u < kLook; ++u) bits |= ((wd[u] >> (l[u] & 31)) & 1u) << u;
@@ -867,7 +888,7 @@ __device__ void update_and_reward(const EnvParams& P, const StepArgs& A, const R
 __global__ void k_motion(EnvParams P, StepArgs A) {
   const int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= P.n) return;
-  robot_motion(P, A, r);
+  robot_motion(P, A, r, true);
 }
 
 template <int NT>
@@ -887,10 +908,10 @@ __global__ __launch_bounds__(NT) void k_march(EnvParams P, StepArgs A, LdsPlan L
   }
   __syncthreads();
   int32_t wy0;
-  stage_world<NT>(P, m, sh->toy >> 16, L.world_halo, V.uni, wy0);
+  uint32_t* sw = V.uni + march_guard_words(m.side);
+  stage_world<NT>(P, m, sh->toy >> 16, L.world_halo, sw, wy0);
   __syncthreads();
-  march_rays<NT>(P, m, V, V.uni, wy0, (L.union_bytes >> 2) - 1, A.ranges, A.noise + (int64_t)P.G * r + 5, true,
-                 r);
+  march_rays<NT>(P, m, V, sw, wy0, A.ranges, A.noise + (int64_t)P.G * r + 5, true, r);
   if (threadIdx.x == 0) {
     P.counters[3 * (int64_t)r + 1] += sh->cnt_march;
     P.dmin_bits[r] = sh->dmin_bits;
@@ -939,21 +960,29 @@ __device__ __forceinline__ void fused_robot(const EnvParams& P, const StepArgs& 
   RobotShared* sh = V.sh;
   const RobotMeta m = P.meta[r];
   if (threadIdx.x == 0) {
-    const MotionOut o = robot_motion(P, A, r);
+    const MotionOut o = robot_motion(P, A, r, false);
     sh->tox = o.tox; sh->toy = o.toy; sh->ib_t = o.ib_t;
     sh->eox = o.eox; sh->eoy = o.eoy; sh->ib_e = o.ib_e;
     sh->collided = o.collided;
     sh->cnt_march = 0;
     sh->cnt_upd = 0;
     sh->dmin_bits = 0x7f800000;
+    sh->near = 0;
     init_bbox(sh);
   }
   __syncthreads();
+  // the paper's proximity collision (the move stands), one cell per thread
+  const bool prox = P.crash_q > 0 && !sh->collided;
+  if (prox) near_obstacle_wg<NT>(P.world + m.world_off, m.side, sh->tox, sh->toy, P.crash_q, &sh->near);
   int32_t wy0;
-  stage_world<NT>(P, m, sh->toy >> 16, L.world_halo, V.uni, wy0);
+  uint32_t* sw = V.uni + march_guard_words(m.side);
+  stage_world<NT>(P, m, sh->toy >> 16, L.world_halo, sw, wy0);
   __syncthreads();
-  march_rays<NT>(P, m, V, V.uni, wy0, (L.union_bytes >> 2) - 1, A.ranges, A.noise + (int64_t)P.G * r + 5,
-                 L.record != 0, r);
+  if (prox && threadIdx.x == 0 && sh->near) {
+    sh->collided = 1;
+    P.flags[2 * (int64_t)r] = 1;
+  }
+  march_rays<NT>(P, m, V, sw, wy0, A.ranges, A.noise + (int64_t)P.G * r + 5, L.record != 0, r);
   endpoint_bbox<NT>(P, V.rho, sh->eox, sh->eoy, sh->ib_e, sh);
   __syncthreads();
   update_and_reward<NT>(P, A, m, V, L, r);

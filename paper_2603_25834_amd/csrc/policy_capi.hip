@@ -35,6 +35,7 @@ struct aslam_policy {
   uint16_t *h1 = nullptr, *dz2 = nullptr, *dz1 = nullptr, *dz2c = nullptr;
   float *z2 = nullptr, *part = nullptr, *hpart = nullptr, *hsum = nullptr;
   uint16_t *w1b = nullptr, *w1t = nullptr, *w2b = nullptr, *w2t = nullptr;   // BF16 weight copies
+  uint4* cfrag = nullptr;   // the encoder forward's weight fragments (k_conv_frags)
   int32_t k1p = 0;   // FC1 input width padded to a multiple of 8
   int64_t part_floats = 0;
   bool prepared = false;   // w1b / w2b hold the weights of some params (the caller tracks which)
@@ -87,13 +88,15 @@ int64_t part_need(const aslam_policy* p) {
     if (e_ != hipSuccess) return pfail(ASL_EHIP, hipGetErrorString(e_)); \
   } while (0)
 
-// BF16 copies of W1 (rows padded to k1p) and W2 that the forward reads; with `transposed` also the
-// transposes that the backward's input gradients read.
+// BF16 copies of W1 (rows padded to k1p) and W2 and the encoder's weight fragments that the forward
+// reads; with `transposed` also the transposes that the backward's input gradients read.
 int convert_weights(aslam_policy* P, const float* prm, hipStream_t st, bool transposed) {
   const Offsets& o = P->off;
   k_convert_bf16<<<1024, 256, 0, st>>>(prm + o.f1w, o.k1, kHid, o.k1, P->w1b, P->k1p);
   PCHK(hipGetLastError());
   k_convert_bf16<<<256, 256, 0, st>>>(prm + o.f2w, kHid, kHid, kHid, P->w2b, kHid);
+  PCHK(hipGetLastError());
+  k_conv_frags<<<1, 64 * kConvFrags, 0, st>>>(prm, o, P->cfrag);
   PCHK(hipGetLastError());
   if (transposed) {
     k_transpose_bf16<<<dim3(kFeat / 32, kHid / 32), 256, 0, st>>>(prm + o.f1w, o.k1, kHid, kFeat, P->w1t, kHid);
@@ -111,7 +114,8 @@ int convert_weights(aslam_policy* P, const float* prm, hipStream_t st, bool tran
 int encode_fc1(aslam_policy* P, const float* prm, const int16_t* crop, const float* scan, const float* state, int B,
                hipStream_t st, int* S_used) {
   const Offsets& o = P->off;
-  k_conv_fwd<<<std::min(B, kConvGrid), 256, 0, st>>>(prm, o, crop, scan, state, P->cfg.n_scan, P->x, P->k1p, B);
+  k_conv_fwd<<<std::min(B, kConvGrid), 256, 0, st>>>(prm, o, P->cfrag, crop, scan, state, P->cfg.n_scan, P->x,
+                                                      P->k1p, B);
   PCHK(hipGetLastError());
   // FC1: [B x k1p] x [k1p x 256] (both operands zero-padded from k1 to k1p)
   const int K1 = P->k1p;
@@ -199,6 +203,7 @@ int aslam_policy_create(const aslam_policy_config* cfg, aslam_policy** out) {
       {(void**)&p->hsum, 4 * (size_t)kHeadPart},
       {(void**)&p->w1b, 2 * (size_t)kHid * ((p->off.k1 + 7) / 8 * 8)}, {(void**)&p->w1t, 2 * (size_t)kFeat * kHid},
       {(void**)&p->w2b, 2 * (size_t)kHid * kHid},                        {(void**)&p->w2t, 2 * (size_t)kHid * kHid},
+      {(void**)&p->cfrag, sizeof(uint4) * 64 * kConvFrags},
   };
   for (auto& a : al) {
     if (hipMalloc(a.ptr, a.bytes) != hipSuccess) {
@@ -213,7 +218,7 @@ int aslam_policy_create(const aslam_policy_config* cfg, aslam_policy** out) {
 int aslam_policy_destroy(aslam_policy* p) {
   if (!p) return pfail(ASL_EINVAL, "policy is NULL");
   void* ptrs[] = {p->x, p->h1, p->dz2, p->dz1, p->dz2c, p->z2, p->part, p->hpart, p->hsum,
-                  p->w1b, p->w1t, p->w2b, p->w2t};
+                  p->w1b, p->w1t, p->w2b, p->w2t, p->cfrag};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   delete p;
