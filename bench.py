@@ -413,8 +413,8 @@ def main():
                     help="also run a plain device copy of this many MiB (counter calibration under rocprofv3)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); robots shard across GPUs "
-              "with no exchange, see DESIGN.md", file=sys.stderr)
+        print(f"bench.py runs on one GPU (asked for --gpus {args.gpus}): the robots of a batch are independent "
+              "and would be split across GPUs with no exchange, each GPU stepping its own share", file=sys.stderr)
         sys.exit(2)
 
     import torch

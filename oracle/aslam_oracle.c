@@ -14,7 +14,8 @@
  * collision ends the episode).  The EKF stands in for the fixed-lag backend
  * of Sec. III-D, and the reward is the map-entropy decrease plus a
  * D-optimality term (Table I "D-opt"; map entropy as in the related work of
- * Sec. II).  Readings where the paper is silent: DESIGN.md, "Readings".
+ * Sec. II).  Where the paper is silent, each function's comment states the
+ * reading it takes.
  */
 #include "aslam_oracle.h"
 #include <math.h>
@@ -602,7 +603,7 @@ void orc_step(const orc_config* cfg, orc_state* st, const float* actions, const 
  * axis-aligned crop of the belief centred on the estimated cell (zero off
  * the map).  Reading: the configured observation replaces Eq. (3). */
 void orc_observe(const orc_config* cfg, const orc_state* st, const float* ranges, int16_t* crop,
-                 int32_t cs, float* scan, float* state12) {
+                 int32_t cs, float* scan, float* state12, const float* u_new, double alpha) {
   const int32_t R = cfg->n_rays;
   const float inv_c16 = (float)(65536.0 / (double)cfg->cell_m);
   const float inv_r = (float)(1.0 / (double)cfg->r_max_m);
@@ -618,7 +619,10 @@ void orc_observe(const orc_config* cfg, const orc_state* st, const float* ranges
       /* Eq. (3): [LiDAR, yaw, U_t]; yaw from the IMU (true heading), U_t of the filter */
       for (int k = 0; k < 12; ++k) o[k] = 0.0f;
       o[0] = st->pose[3 * r + 2] * inv_pi;
-      o[1] = (float)uncertainty(c);
+      double u = uncertainty(c);
+      /* uncertainty bridge (Sec. III-G): blend in the external estimator's U */
+      if (u_new) u = alpha * (double)u_new[r] + (1.0 - alpha) * u;
+      o[1] = (float)u;
     } else {
       o[0] = e[0] * inv_ext; o[1] = e[1] * inv_ext; o[2] = e[2] * inv_pi;
       o[3] = c[0]; o[4] = c[1]; o[5] = c[2];

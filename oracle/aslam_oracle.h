@@ -21,7 +21,7 @@
  *     differential uncertainty terms, anti-wall-hugging factor; sensor model of
  *     Sec. IV-A (front field of view, minimum range, range noise, quantisation,
  *     proximity collision); observation [LiDAR, yaw, U_t] of Sec. III-C, Eq. (3).
- * Where the paper is silent the readings are listed in DESIGN.md ("Readings").
+ * Where the paper is silent, the comment of each function states the reading it takes.
  *
  * Parity status: every function here is pinned by a CPU test (closed forms,
  * brute force, invariants) -- see tests/test_oracle_*.py.
@@ -122,8 +122,11 @@ double orc_paper_reward(const orc_config* cfg, int collided, double delta_cells,
                         double d_min);
 void orc_step(const orc_config* cfg, orc_state* st, const float* actions, const float* noise,
               orc_out* out, int32_t n_threads);
+/* Observation.  With reward_mode 1 and u_new != NULL the uncertainty entry is
+ * the bridged U of the fine-tuning wrapper (Sec. III-G, Eqs. 21-22): alpha * U_new + (1 - alpha) * U_t,
+ * alpha = min(1, t / T_bridge) given by the caller. */
 void orc_observe(const orc_config* cfg, const orc_state* st, const float* ranges, int16_t* crop,
-                 int32_t crop_side, float* scan, float* state12);
+                 int32_t crop_side, float* scan, float* state12, const float* u_new, double alpha);
 
 #ifdef __cplusplus
 }

@@ -89,7 +89,7 @@ def lib():
         L.orc_step.argtypes = [ctypes.POINTER(OrcConfig), ctypes.POINTER(OrcState), _P, _P,
                                ctypes.POINTER(OrcOut), ctypes.c_int32]
         L.orc_observe.argtypes = [ctypes.POINTER(OrcConfig), ctypes.POINTER(OrcState), _P, _P,
-                                  ctypes.c_int32, _P, _P]
+                                  ctypes.c_int32, _P, _P, _P, ctypes.c_double]
         L.orc_noise_width.argtypes = [ctypes.POINTER(OrcConfig)]
         L.orc_noise_width.restype = ctypes.c_int32
         L.orc_paper_reward.argtypes = [ctypes.POINTER(OrcConfig), ctypes.c_int, ctypes.c_double, ctypes.c_double,
@@ -142,6 +142,11 @@ def make_config(p: dict) -> OrcConfig:
     for name, _ in OrcConfig._fields_:
         setattr(c, name, p[name])
     return c
+
+
+def bridge_alpha(t: int, t_bridge: int) -> float:
+    """Blending coefficient of the uncertainty bridge, Sec. III-G, Eq. (21): min(1, t / T_bridge)."""
+    return min(1.0, float(t) / float(t_bridge))
 
 
 def noise_width(p: dict) -> int:
@@ -236,15 +241,20 @@ class OracleEnv:
         lib().orc_step(ctypes.byref(self.cfg), ctypes.byref(st), _ptr(a), _ptr(g), ctypes.byref(co), th)
         return o
 
-    def observe(self, ranges: np.ndarray, crop_side: int = 64):
+    def observe(self, ranges: np.ndarray, crop_side: int = 64, u_new: np.ndarray | None = None, t: int = 0,
+                t_bridge: int = 1):
+        """Observation; with u_new (reward_mode 1) the uncertainty entry is bridged with
+        alpha = min(1, t / T_bridge) (Sec. III-G)."""
         n, R = self.n, self.R
         rg = np.ascontiguousarray(ranges, np.float32)
         crop = np.zeros((n, crop_side, crop_side), np.int16)
         scan = np.zeros((n, R), np.float32)
         state = np.zeros((n, 12), np.float32)
         st = self._state()
+        un = None if u_new is None else np.ascontiguousarray(u_new, np.float32)
+        alpha = bridge_alpha(t, t_bridge)
         lib().orc_observe(ctypes.byref(self.cfg), ctypes.byref(st), _ptr(rg), _ptr(crop), crop_side,
-                          _ptr(scan), _ptr(state))
+                          _ptr(scan), _ptr(state), None if un is None else _ptr(un), alpha)
         return crop, scan, state
 
     def belief_of(self, i: int) -> np.ndarray:

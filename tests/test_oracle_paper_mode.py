@@ -172,3 +172,23 @@ def test_exploration_novelty_along_a_trajectory(oracle_mod):
         assert not o.collided[0]
         # I = c with c = ((U_hi - U)/U_hi)^2, 1 to within 1e-10 here; alpha = 1 away from walls
         assert o.reward[0] == pytest.approx(want, abs=1e-9), (t, cell)
+
+
+def test_uncertainty_bridge(oracle_mod):
+    """Sec. III-G: alpha = min(1, t / T_bridge); U_bridge = alpha U_new + (1 - alpha) U_old in the
+    observation.  t = 0 gives the backend's own U, t >= T_bridge the external one, the midpoint their mean."""
+    O = oracle_mod
+    assert O.bridge_alpha(0, 400) == 0.0 and O.bridge_alpha(100, 400) == 0.25
+    assert O.bridge_alpha(400, 400) == 1.0 and O.bridge_alpha(10 ** 6, 400) == 1.0
+    env = _room(O, ((3.0, 3.0, 0.5), (2.0, 4.0, -1.0)))
+    rg = np.full((2, 128), 2.5, np.float32)
+    u_old = 1e-4                                  # cbrt(det diag(1e-4, 1e-4, 1e-4))
+    u_new = np.array([0.03, 0.001], np.float32)
+    for t, want in ((0, [u_old, u_old]), (800, [float(u_new[0]), float(u_new[1])]),
+                    (200, [0.5 * (u_old + float(u_new[0])), 0.5 * (u_old + float(u_new[1]))])):
+        _, _, st = env.observe(rg, u_new=u_new, t=t, t_bridge=400)
+        assert st[:, 1] == pytest.approx(want, rel=1e-6), t
+        assert st[0, 0] == pytest.approx(0.5 / math.pi, rel=1e-6)
+    # without an external signal the observation is unchanged
+    _, _, st0 = env.observe(rg)
+    assert st0[:, 1] == pytest.approx([u_old, u_old], rel=1e-6)
