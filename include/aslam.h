@@ -154,6 +154,16 @@ int aslam_env_step(aslam_env* env, const float* actions_dev, const float* noise_
 int aslam_env_observe(aslam_env* env, const float* ranges_dev, int16_t* crop_dev, int32_t crop,
                       float* scan_dev, float* state_dev, aslam_stream_t stream);
 
+/* Observation with the uncertainty bridge of the fine-tuning wrapper
+ * (Sec. III-G, Eqs. 21-22): as aslam_env_observe in reward_mode 1, with the
+ * uncertainty entry alpha * U_new + (1 - alpha) * U_t, alpha = min(1, t / t_bridge),
+ * formed in FP64.  u_new_dev float [n]: the external estimator's uncertainty
+ * per robot; t >= 0 fine-tuning steps so far, t_bridge >= 1.  ASL_EINVAL for
+ * reward_mode 0 (its observation carries no U_t) or bad t / t_bridge. */
+int aslam_env_observe_bridge(aslam_env* env, const float* ranges_dev, int16_t* crop_dev, int32_t crop,
+                             float* scan_dev, float* state_dev, const float* u_new_dev, int64_t t,
+                             int64_t t_bridge, aslam_stream_t stream);
+
 /* Copy a state field into caller memory (device), for checks and export. */
 #define ASLAM_FIELD_BELIEF 0     /* int16 [sum s^2] */
 #define ASLAM_FIELD_POSE 1       /* float [n,3] true pose */

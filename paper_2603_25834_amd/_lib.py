@@ -63,6 +63,7 @@ SIGNATURES = {
     "aslam_env_world_words": (_I64, [_P]),
     "aslam_env_cells": (_I64, [_P]),
     "aslam_env_noise_width": (_I32, [_P]),
+    "aslam_env_observe_bridge": (ctypes.c_int, [_P, _P, _P, _I32, _P, _P, _P, _I64, _I64, _P]),
     "aslam_env_visit_cells": (_I64, [_P]),
     "aslam_env_set_exec": (ctypes.c_int, [_P, ctypes.POINTER(ExecConfig)]),
     "aslam_env_get_exec": (ctypes.c_int, [_P, ctypes.POINTER(ExecConfig)]),

@@ -491,7 +491,24 @@ int aslam_env_observe(aslam_env* env, const float* ranges_dev, int16_t* crop_dev
   if (!env || !ranges_dev || !crop_dev || !scan_dev || !state_dev) return fail(ASL_EINVAL, "null argument");
   if (crop < 2 || crop > 1024 || crop % 2) return fail(ASL_EINVAL, "crop must be even in [2, 1024]");
   if (!env->was_reset) return fail(ASL_ESTATE, "observe called before env_reset");
-  HIP_TRY(launch_observe(env->P, ranges_dev, crop_dev, crop, scan_dev, state_dev, (hipStream_t)stream), "observe");
+  HIP_TRY(launch_observe(env->P, ranges_dev, crop_dev, crop, scan_dev, state_dev, nullptr, 0.0, (hipStream_t)stream),
+          "observe");
+  return ASL_OK;
+}
+
+int aslam_env_observe_bridge(aslam_env* env, const float* ranges_dev, int16_t* crop_dev, int32_t crop,
+                             float* scan_dev, float* state_dev, const float* u_new_dev, int64_t t, int64_t t_bridge,
+                             aslam_stream_t stream) {
+  if (!env || !ranges_dev || !crop_dev || !scan_dev || !state_dev || !u_new_dev)
+    return fail(ASL_EINVAL, "null argument");
+  if (crop < 2 || crop > 1024 || crop % 2) return fail(ASL_EINVAL, "crop must be even in [2, 1024]");
+  if (env->cfg.reward_mode != 1) return fail(ASL_EINVAL, "the bridge needs reward_mode 1 (U_t in the observation)");
+  if (t < 0 || t_bridge < 1) return fail(ASL_EINVAL, "need t >= 0 and t_bridge >= 1");
+  if (!env->was_reset) return fail(ASL_ESTATE, "observe called before env_reset");
+  const double alpha = std::min(1.0, (double)t / (double)t_bridge);
+  HIP_TRY(launch_observe(env->P, ranges_dev, crop_dev, crop, scan_dev, state_dev, u_new_dev, alpha,
+                         (hipStream_t)stream),
+          "observe");
   return ASL_OK;
 }
 

@@ -116,7 +116,7 @@ hipError_t launch_step_plain(const EnvParams& P, const StepArgs& A, const LdsPla
 hipError_t launch_step_fused(const EnvParams& P, const StepArgs& A, const LdsPlan& L, int threads,
                              int grid, hipStream_t stream);
 hipError_t launch_observe(const EnvParams& P, const float* ranges, int16_t* crop, int32_t cs,
-                          float* scan, float* state, hipStream_t stream);
+                          float* scan, float* state, const float* u_new, double alpha, hipStream_t stream);
 hipError_t set_kernel_lds_limits(int bytes);
 
 }  // namespace aslam

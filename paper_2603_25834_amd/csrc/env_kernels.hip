@@ -1058,7 +1058,7 @@ __global__ void k_reset(EnvParams P, const uint32_t* world_src, const float* ini
 }
 
 __global__ void k_observe(EnvParams P, const float* ranges, int16_t* crop, int32_t cs, float* scan, float* state,
-                          float inv_r, float inv_pi) {
+                          float inv_r, float inv_pi, const float* u_new, double alpha) {
   const int32_t r = blockIdx.x;
   const RobotMeta m = P.meta[r];
   const int32_t s = m.side;
@@ -1067,10 +1067,26 @@ __global__ void k_observe(EnvParams P, const float* ranges, int16_t* crop, int32
   const int32_t ecy = to_q16(e[1], P.inv_c16) >> 16;
   const int16_t* bel = P.belief + m.cell_off;
   int16_t* out = crop + (int64_t)r * cs * cs;
-  for (int32_t k = threadIdx.x; k < cs * cs; k += blockDim.x) {
-    const int32_t ii = k % cs, jj = k / cs;
-    const int32_t i = ecx - cs / 2 + ii, j = ecy - cs / 2 + jj;
-    out[k] = (i >= 0 && i < s && j >= 0 && j < s) ? bel[(int64_t)j * s + i] : (int16_t)0;
+  // eight crop cells per item: the loads of an item are independent and its store is one 16-byte
+  // store when the crop side is a multiple of 8
+  const int32_t chunks = (cs + 7) >> 3;
+  for (int32_t q = threadIdx.x; q < cs * chunks; q += blockDim.x) {
+    const int32_t jj = q / chunks, i8 = (q - jj * chunks) * 8;
+    const int32_t j = ecy - cs / 2 + jj, i0 = ecx - cs / 2 + i8;
+    const bool row_in = j >= 0 && j < s;
+    uint16_t v[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int32_t i = i0 + e;
+      v[e] = (row_in && i >= 0 && i < s) ? (uint16_t)bel[(int64_t)j * s + i] : (uint16_t)0;
+    }
+    int16_t* dst = out + (int64_t)jj * cs + i8;
+    if ((cs & 7) == 0 && (reinterpret_cast<uintptr_t>(dst) & 15) == 0) {
+      *reinterpret_cast<uint4*>(dst) = make_uint4(v[0] | ((uint32_t)v[1] << 16), v[2] | ((uint32_t)v[3] << 16),
+                                                  v[4] | ((uint32_t)v[5] << 16), v[6] | ((uint32_t)v[7] << 16));
+    } else {
+      for (int e = 0; e < 8 && i8 + e < cs; ++e) dst[e] = (int16_t)v[e];
+    }
   }
   for (int32_t k = threadIdx.x; k < P.R; k += blockDim.x)
     scan[(int64_t)r * P.R + k] = ranges[(int64_t)r * P.R + k] * inv_r;
@@ -1081,7 +1097,10 @@ __global__ void k_observe(EnvParams P, const float* ranges, int16_t* crop, int32
       // Eq. (3): [LiDAR, yaw, U_t]; yaw of the true heading (IMU), U_t of the filter
       for (int k = 2; k < 12; ++k) o[k] = 0.0f;
       o[0] = P.pose[3 * (int64_t)r + 2] * inv_pi;
-      o[1] = (float)uncertainty(c);
+      double u = uncertainty(c);
+      // uncertainty bridge (Sec. III-G): blend in the external estimator's U
+      if (u_new) u = alpha * (double)u_new[r] + (1.0 - alpha) * u;
+      o[1] = (float)u;
     } else {
       const float inv_ext = m.inv_ext;
       o[0] = e[0] * inv_ext; o[1] = e[1] * inv_ext; o[2] = e[2] * inv_pi;
@@ -1156,8 +1175,8 @@ hipError_t launch_step_fused(const EnvParams& P, const StepArgs& A, const LdsPla
 }
 
 hipError_t launch_observe(const EnvParams& P, const float* ranges, int16_t* crop, int32_t cs, float* scan,
-                          float* state, hipStream_t stream) {
-  k_observe<<<P.n, 256, 0, stream>>>(P, ranges, crop, cs, scan, state, P.inv_rmax, P.inv_pi);
+                          float* state, const float* u_new, double alpha, hipStream_t stream) {
+  k_observe<<<P.n, 256, 0, stream>>>(P, ranges, crop, cs, scan, state, P.inv_rmax, P.inv_pi, u_new, alpha);
   return hipGetLastError();
 }
 

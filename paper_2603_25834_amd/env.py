@@ -100,6 +100,18 @@ class Env:
         assert state.dtype == torch.float32 and state.numel() == self.n * 12
         check(lib().aslam_env_observe(self.h, _ptr(ranges), _ptr(crop), cs, _ptr(scan), _ptr(state), _stream()))
 
+    def observe_bridge(self, ranges: torch.Tensor, crop: torch.Tensor, scan: torch.Tensor, state: torch.Tensor,
+                       u_new: torch.Tensor, t: int, t_bridge: int):
+        """Observation with the uncertainty entry bridged towards an external estimator's u_new [n]:
+        alpha u_new + (1 - alpha) U_t, alpha = min(1, t / t_bridge) (Sec. III-G)."""
+        cs = crop.shape[-1]
+        assert crop.dtype == torch.int16 and crop.numel() == self.n * cs * cs
+        assert scan.dtype == torch.float32 and scan.numel() == self.n * self.R
+        assert state.dtype == torch.float32 and state.numel() == self.n * 12
+        assert u_new.dtype == torch.float32 and u_new.numel() == self.n
+        check(lib().aslam_env_observe_bridge(self.h, _ptr(ranges), _ptr(crop), cs, _ptr(scan), _ptr(state),
+                                             _ptr(u_new), int(t), int(t_bridge), _stream()))
+
     _FIELDS = {
         _lib.FIELD_BELIEF: (torch.int16, lambda s: (s.cells,)),
         _lib.FIELD_POSE: (torch.float32, lambda s: (s.n, 3)),

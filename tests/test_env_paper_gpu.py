@@ -147,3 +147,36 @@ def test_paper_mode_config_errors():
         assert ei.value.code == -1, over
     env = Env(p, sides)
     assert env.G == 5 + 128 and env.visit_cells == int(np.ceil(256 * 0.05 / 0.5)) ** 2
+
+
+def test_uncertainty_bridge_matches_oracle():
+    """Sec. III-G: the observation's U blended towards an external estimator's, alpha = min(1, t / T_bridge)."""
+    import torch
+    from paper_2603_25834_amd import _lib
+    from paper_2603_25834_amd.env import Env
+    pr = Pair(NAME, 7, robots=SUBSET[:8], exec_kw=FUSED, steps=10)
+    for t in range(10):
+        o = pr.step()
+    u_new = np.random.default_rng(7).uniform(1e-4, 0.05, pr.n).astype(np.float32)
+    du = torch.from_numpy(u_new).cuda()
+    crop = torch.zeros((pr.n, 64, 64), dtype=torch.int16, device="cuda")
+    scan = torch.zeros((pr.n, pr.R), dtype=torch.float32, device="cuda")
+    state = torch.zeros((pr.n, 12), dtype=torch.float32, device="cuda")
+    for t in (0, 137, 400, 5000):
+        pr.env.observe_bridge(pr.ranges, crop, scan, state, du, t, 400)
+        torch.cuda.synchronize()
+        c2, s2, st2 = pr.orc.observe(o.ranges, u_new=u_new, t=t, t_bridge=400)
+        st = state.cpu().numpy()
+        assert np.array_equal(crop.cpu().numpy(), c2) and np.array_equal(scan.cpu().numpy(), s2)
+        assert np.array_equal(st[:, 0], st2[:, 0]) and np.all(st[:, 2:] == 0.0)
+        assert np.allclose(st[:, 1], st2[:, 1], rtol=2.5e-7, atol=0), t
+    assert np.array_equal(state.cpu().numpy()[:, 1], u_new)      # t past T_bridge: the external U
+    with pytest.raises(_lib.AslamError) as ei:
+        pr.env.observe_bridge(pr.ranges, crop, scan, state, du, 5, 0)
+    assert ei.value.code == -1
+    p0 = synth.WORKLOADS["small_16x64"].params()
+    e0 = Env(p0, np.array([64], np.int32))
+    with pytest.raises(_lib.AslamError) as ei:
+        e0.observe_bridge(torch.zeros((1, 180), device="cuda"), crop[:1], torch.zeros((1, 180), device="cuda"),
+                          state[:1], du[:1], 0, 10)
+    assert ei.value.code == -1
