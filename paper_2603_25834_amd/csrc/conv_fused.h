@@ -316,13 +316,32 @@ __device__ __forceinline__ bf16x8 phase_weight_frag(const float* w2, int ky, int
   return __builtin_bit_cast(bf16x8, u);
 }
 
-// conv1 weights as the B operand of C[px][co] = sum_k P[px][k] W'[k][co]: lane supplies W'[k = 8 lg + j][co = lr].
-__device__ __forceinline__ bf16x8 conv1_weight_frag_b(const float* w1, int lr, int lg) {
-  return conv1_weight_frag(w1, lr, lg);   // same values: W'[k][co] read at co = lane % 16
+// The backward's phase weight fragments, formed once per parameter update after the forward's
+// kConvFrags: fragment kConvFrags + q of lane l at frag[64 (kConvFrags + q) + l], q enumerating the
+// (phase, tap) pairs in phase order (9 in all).
+constexpr int kConvPhaseFrags = 9;
+
+__global__ __launch_bounds__(64 * kConvPhaseFrags) void k_conv_bwd_frags(const float* prm, Offsets o, uint4* frag) {
+  const int f = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
+  int q = 0;
+#pragma unroll
+  for (int ph = 0; ph < 4; ++ph) {
+    const PhaseTaps t = phase_taps(ph >> 1, ph & 1);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (j < t.n) {
+        if (q == f)
+          frag[64 * (kConvFrags + q) + lane] =
+              __builtin_bit_cast(uint4, phase_weight_frag(prm + o.c2w, t.ky[j], t.kx[j], lr, lg));
+        ++q;
+      }
+    }
+  }
 }
 
-__global__ __launch_bounds__(kBwdThreads) void k_conv_bwd(const float* prm, Offsets o, const int16_t* crop,
-                                                          const uint16_t* dz2c, int B, float* part) {
+__global__ __launch_bounds__(kBwdThreads) void k_conv_bwd(const float* prm, Offsets o, const uint4* frag,
+                                                          const int16_t* crop, const uint16_t* dz2c, int B,
+                                                          float* part) {
   __shared__ __align__(16) uint16_t s_crop[kCropLds];
   __shared__ __align__(16) uint16_t s_a1x[kA1xLds];
   __shared__ __align__(16) uint16_t s_dz[kDzLds];
@@ -339,20 +358,13 @@ __global__ __launch_bounds__(kBwdThreads) void k_conv_bwd(const float* prm, Offs
     for (int i = threadIdx.x; i < kDzPLds / 8; i += kBwdThreads) z[i] = make_uint4(0u, 0u, 0u, 0u);
   }
   // registers that live for the whole workgroup
-  const bf16x8 w1f = conv1_weight_frag_b(prm + o.c1w, lr, lg);
+  // conv1's weights as the B operand: the same values as the forward's A fragment (W'[k][co] at co = lane % 16)
+  const bf16x8 w1f = __builtin_bit_cast(bf16x8, frag[lane]);
   const float b1c = prm[o.c1b + lr];
   // phase weights: this wave's qy rows are {wave, wave + 8}; all four phases, 9 k-steps
-  bf16x8 wph[9];
-  {
-    int q = 0;
+  bf16x8 wph[kConvPhaseFrags];
 #pragma unroll
-    for (int ph = 0; ph < 4; ++ph) {
-      const PhaseTaps t = phase_taps(ph >> 1, ph & 1);
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-        if (j < t.n) wph[q++] = phase_weight_frag(prm + o.c2w, t.ky[j], t.kx[j], lr, lg);
-    }
-  }
+  for (int q = 0; q < kConvPhaseFrags; ++q) wph[q] = __builtin_bit_cast(bf16x8, frag[64 * (kConvFrags + q) + lane]);
   // accumulators: dW2 tiles (mt, nt) for nt = wave (all k-steps) and nt = 8 (k-step = wave)
   f32x4 gw2[2][2];
 #pragma unroll

@@ -55,6 +55,10 @@ __device__ __forceinline__ uint16_t lane16(const uint4& v, int j) {
 //
 // Epilogue contract: store8(m, n0, v, nvalid) for row m < M and the eight
 // columns n0 .. n0 + 7 (n0 multiple of 8), of which the first nvalid are < N.
+// An epilogue that reads global memory declares kPrefetch = true and provides
+// fetch(m, n0, nvalid) -> uint4 and store8_pre(m, n0, v, nvalid, fetched): the
+// engine issues those reads at kernel start, so their latency hides behind the
+// main loop (others declare kPrefetch = false).
 
 // LDS elements of one stage of an operand with ROWS rows ([row][k], rows padded by 8).
 template <bool KMAJOR, int ROWS, int BK>
@@ -169,6 +173,19 @@ __global__ __launch_bounds__(256) void k_gemm(LA la, LB lb, EPI epi, int M, int 
 #pragma unroll
     for (int j = 0; j < C::FN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
+  // epilogue vectors of this thread: v = threadIdx.x + 256 i, row v / (BN/8), columns 8 (v % (BN/8)) ..
+  constexpr int kVecPerRow = BN / 8;
+  constexpr int kEpiVec = (BM * kVecPerRow + 255) / 256;
+  uint4 epre[EPI::kPrefetch ? kEpiVec : 1];
+  if constexpr (EPI::kPrefetch) {
+#pragma unroll
+    for (int i = 0; i < kEpiVec; ++i) {
+      const int v = threadIdx.x + 256 * i;
+      const int m = m_blk + v / kVecPerRow, n0 = n_blk + (v % kVecPerRow) * 8;
+      epre[i] = (v < BM * kVecPerRow && m < M && n0 < N) ? epi.fetch(m, n0, min(8, N - n0))
+                                                           : make_uint4(0u, 0u, 0u, 0u);
+    }
+  }
   uint4 ra[C::PA], rb[C::PB];
   const int nsteps = (ke - kb + BK - 1) / BK;
   if (nsteps > 0) {
@@ -221,15 +238,17 @@ __global__ __launch_bounds__(256) void k_gemm(LA la, LB lb, EPI epi, int M, int 
         sc[r * LDC + c] = acc[i][j][e];
       }
   __syncthreads();
-  constexpr int kVecPerRow = BN / 8;
-  for (int v = threadIdx.x; v < BM * kVecPerRow; v += 256) {
+#pragma unroll
+  for (int i = 0; i < kEpiVec; ++i) {
+    const int v = threadIdx.x + 256 * i;
     const int r = v / kVecPerRow, c0 = (v % kVecPerRow) * 8;
     const int m = m_blk + r, n0 = n_blk + c0;
-    if (m >= M || n0 >= N) continue;
+    if (v >= BM * kVecPerRow || m >= M || n0 >= N) continue;
     const float4 lo = *reinterpret_cast<const float4*>(sc + r * LDC + c0);
     const float4 hi = *reinterpret_cast<const float4*>(sc + r * LDC + c0 + 4);
     const float vals[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
-    epi.store8(m, n0, vals, min(8, N - n0));
+    if constexpr (EPI::kPrefetch) epi.store8_pre(m, n0, vals, min(8, N - n0), epre[i]);
+    else epi.store8(m, n0, vals, min(8, N - n0));
   }
 }
 

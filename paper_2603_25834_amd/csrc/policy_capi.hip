@@ -35,7 +35,7 @@ struct aslam_policy {
   uint16_t *h1 = nullptr, *dz2 = nullptr, *dz1 = nullptr, *dz2c = nullptr;
   float *z2 = nullptr, *part = nullptr, *hpart = nullptr, *hsum = nullptr;
   uint16_t *w1b = nullptr, *w1t = nullptr, *w2b = nullptr, *w2t = nullptr;   // BF16 weight copies
-  uint4* cfrag = nullptr;   // the encoder forward's weight fragments (k_conv_frags)
+  uint4* cfrag = nullptr;   // the encoder's weight fragments (k_conv_frags, k_conv_bwd_frags)
   int32_t k1p = 0;   // FC1 input width padded to a multiple of 8
   int64_t part_floats = 0;
   bool prepared = false;   // w1b / w2b hold the weights of some params (the caller tracks which)
@@ -46,7 +46,7 @@ namespace {
 constexpr int kConvGrid = 2048;    // workgroups of the fused encoder forward (each loops over samples)
 constexpr int kConvBwdGrid = 256;  // encoder backward: one 8-wave workgroup per CU (LDS-bound)
 constexpr int64_t kFc1Splits = 12, kFc2Splits = 64;
-constexpr int kFc1MinBlocks = 512;   // FC1 forward: split K until the grid has this many workgroups
+constexpr int kFc1MinBlocks = 512;   // FC1 forward: resident workgroups (two per CU) that its K splits fill
 
 int64_t splits_for(int64_t K, int64_t min_chunk, int64_t max_splits) {
   return std::max<int64_t>(1, std::min<int64_t>(max_splits, K / min_chunk));
@@ -78,7 +78,7 @@ int64_t part_need(const aslam_policy* p) {
   need = std::max<int64_t>(need, kFc2Splits * kHid * kHid);   // FC2 weight partials
   need = std::max<int64_t>(need, (int64_t)kConvBwdGrid * kConvPart);   // encoder backward partials
   need = std::max<int64_t>(need, (int64_t)kBiasBlocks * 256);
-  need = std::max<int64_t>(need, 2LL * kFc1MinBlocks * 64 * kHid);   // FC1 forward split-K: S * B < 2 * 64 * 256
+  need = std::max<int64_t>(need, (int64_t)kFc1MinBlocks * 64 * kHid);   // FC1 forward split-K: S * B <= 512 * 64
   return need;
 }
 
@@ -89,7 +89,8 @@ int64_t part_need(const aslam_policy* p) {
   } while (0)
 
 // BF16 copies of W1 (rows padded to k1p) and W2 and the encoder's weight fragments that the forward
-// reads; with `transposed` also the transposes that the backward's input gradients read.
+// reads; with `transposed` also what only the backward reads (the transposes for the input gradients,
+// the encoder backward's phase fragments).
 int convert_weights(aslam_policy* P, const float* prm, hipStream_t st, bool transposed) {
   const Offsets& o = P->off;
   k_convert_bf16<<<1024, 256, 0, st>>>(prm + o.f1w, o.k1, kHid, o.k1, P->w1b, P->k1p);
@@ -99,6 +100,8 @@ int convert_weights(aslam_policy* P, const float* prm, hipStream_t st, bool tran
   k_conv_frags<<<1, 64 * kConvFrags, 0, st>>>(prm, o, P->cfrag);
   PCHK(hipGetLastError());
   if (transposed) {
+    k_conv_bwd_frags<<<1, 64 * kConvPhaseFrags, 0, st>>>(prm, o, P->cfrag);
+    PCHK(hipGetLastError());
     k_transpose_bf16<<<dim3(kFeat / 32, kHid / 32), 256, 0, st>>>(prm + o.f1w, o.k1, kHid, kFeat, P->w1t, kHid);
     PCHK(hipGetLastError());
     k_transpose_bf16<<<dim3(kHid / 32, kHid / 32), 256, 0, st>>>(prm + o.f2w, kHid, kHid, kHid, P->w2t, kHid);
@@ -121,9 +124,9 @@ int encode_fc1(aslam_policy* P, const float* prm, const int16_t* crop, const flo
   const int K1 = P->k1p;
   const LdBF16K xa{P->x, K1, B, K1};
   const LdBF16K wa{P->w1b, K1, kHid, K1};
+  // as many K splits as keep the grid within one round of kFc1MinBlocks resident workgroups
   const int tiles = ((B + 127) / 128) * (kHid / 128);
-  int S = 1;
-  while (tiles * S < kFc1MinBlocks && S < 32) S *= 2;
+  const int S = std::max(1, std::min(32, kFc1MinBlocks / tiles));
   if (S == 1) {
     PCHK((gemm::run<128, 128, 64, 2, 2>(xa, wa, EpiBiasReluBF16{P->h1, prm + o.f1b, kHid}, B, kHid, K1, 1, st)));
     *S_used = 0;
@@ -203,7 +206,7 @@ int aslam_policy_create(const aslam_policy_config* cfg, aslam_policy** out) {
       {(void**)&p->hsum, 4 * (size_t)kHeadPart},
       {(void**)&p->w1b, 2 * (size_t)kHid * ((p->off.k1 + 7) / 8 * 8)}, {(void**)&p->w1t, 2 * (size_t)kFeat * kHid},
       {(void**)&p->w2b, 2 * (size_t)kHid * kHid},                        {(void**)&p->w2t, 2 * (size_t)kHid * kHid},
-      {(void**)&p->cfrag, sizeof(uint4) * 64 * kConvFrags},
+      {(void**)&p->cfrag, sizeof(uint4) * 64 * (kConvFrags + kConvPhaseFrags)},
   };
   for (auto& a : al) {
     if (hipMalloc(a.ptr, a.bytes) != hipSuccess) {
@@ -302,7 +305,7 @@ int aslam_policy_backward(aslam_policy* P, const float* params, const int16_t* c
   // encoder: conv2 / conv1 weight and bias gradients in one pass over the minibatch
   {
     const int grid = std::min(B, kConvBwdGrid);
-    k_conv_bwd<<<grid, kBwdThreads, 0, st>>>(params, o, crop, P->dz2c, B, part);
+    k_conv_bwd<<<grid, kBwdThreads, 0, st>>>(params, o, P->cfrag, crop, P->dz2c, B, part);
     PCHK(hipGetLastError());
     PCHK(launch_reduce(part, grid, kConvPartW2, grads + o.c2w, 1, kConvPart, st));
     PCHK(launch_reduce(part + kConvPartW2, grid, kConvPartW1, grads + o.c1w, 2, kConvPart, st));

@@ -102,6 +102,7 @@ struct LdBF16I {
 
 struct EpiBiasReluBF16 {
   uint16_t* out; const float* bias; int64_t ld;
+  static constexpr bool kPrefetch = false;
   __device__ void store8(int m, int n0, const float* v, int nvalid) const {
     uint16_t h[8];
 #pragma unroll
@@ -117,6 +118,7 @@ struct EpiBiasReluBF16 {
 
 struct EpiBiasF32 {
   float* out; const float* bias; int64_t ld;
+  static constexpr bool kPrefetch = false;
   __device__ void store8(int m, int n0, const float* v, int nvalid) const {
     float* q = out + (int64_t)m * ld + n0;
     if (nvalid == 8 && ((reinterpret_cast<uintptr_t>(q) & 15) == 0)) {
@@ -133,6 +135,7 @@ struct EpiBiasF32 {
 // Split-K partial sums: slice blockIdx.z of a [splits][M][N] FP32 buffer.
 struct EpiPartial {
   float* part; int64_t ld; int64_t slice;
+  static constexpr bool kPrefetch = false;
   __device__ void store8(int m, int n0, const float* v, int nvalid) const {
     float* q = part + (int64_t)blockIdx.z * slice + (int64_t)m * ld + n0;
     if (nvalid == 8 && ((reinterpret_cast<uintptr_t>(q) & 15) == 0)) {
@@ -147,6 +150,25 @@ struct EpiPartial {
 // Gradient through a ReLU whose output (BF16) is `act`: out = bf16(act > 0 ? v : 0).
 struct EpiReluGradBF16 {
   uint16_t* out; const uint16_t* act; int64_t ld, ld_act;
+  // the engine loads the mask at kernel start (fetch) and hands it to store8_pre
+  static constexpr bool kPrefetch = true;
+  __device__ bool vec_ok(int m, int n0, int nvalid) const {
+    return nvalid == 8 && ((((int64_t)m * ld + n0) & 7) == 0) && ((((int64_t)m * ld_act + n0) & 7) == 0);
+  }
+  __device__ uint4 fetch(int m, int n0, int nvalid) const {
+    return vec_ok(m, n0, nvalid) ? *reinterpret_cast<const uint4*>(act + (int64_t)m * ld_act + n0)
+                                 : make_uint4(0u, 0u, 0u, 0u);
+  }
+  __device__ void store8_pre(int m, int n0, const float* v, int nvalid, const uint4& a) const {
+    if (vec_ok(m, n0, nvalid)) {
+      uint16_t h[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) h[j] = bf2f(gemm::lane16(a, j)) > 0.0f ? f2bf(v[j]) : (uint16_t)0;
+      *reinterpret_cast<uint4*>(out + (int64_t)m * ld + n0) = pack8(h);
+    } else {
+      store8(m, n0, v, nvalid);
+    }
+  }
   __device__ void store8(int m, int n0, const float* v, int nvalid) const {
     const int64_t o = (int64_t)m * ld + n0, oa = (int64_t)m * ld_act + n0;
     if (nvalid == 8 && ((o & 7) == 0) && ((oa & 7) == 0)) {
