@@ -261,6 +261,16 @@ int aslam_policy_backward(aslam_policy* pol, const float* params_dev, const int1
                           const float* old_logp_dev, const float* adv_dev, const float* ret_dev, float* grads_dev,
                           float* loss_dev, aslam_stream_t stream);
 
+/* The same over the rows rows_dev[0 .. batch-1] (int32, device) of rollout-sized
+ * arrays: sample b of the minibatch is row rows_dev[b] of crop_dev, scan_dev,
+ * state_dev, act_dev, old_logp_dev, adv_dev and ret_dev, so a shuffled
+ * minibatch needs no gathered copy.  Rows are not checked against the arrays'
+ * size: the caller guarantees 0 <= rows_dev[b] < their row count. */
+int aslam_policy_backward_rows(aslam_policy* pol, const float* params_dev, const int16_t* crop_dev,
+                               const float* scan_dev, const float* state_dev, const int32_t* rows_dev, int32_t batch,
+                               const float* act_dev, const float* old_logp_dev, const float* adv_dev,
+                               const float* ret_dev, float* grads_dev, float* loss_dev, aslam_stream_t stream);
+
 /* Generalized Advantage Estimation (Sec. III-F) over a [T,N] rollout (time-major):
  *   delta_t = r_t + gamma V_{t+1} (1 - d_t) - V_t,  A_t = delta_t + gamma lam (1 - d_t) A_{t+1},
  * V_T = last_value_dev [N].  Writes adv_dev and ret_dev = adv + values, [T,N] float. */

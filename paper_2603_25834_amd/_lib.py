@@ -80,6 +80,7 @@ SIGNATURES = {
     "aslam_policy_backward": (ctypes.c_int, [_P, _P, _P, _P, _P, _I32, _P, _P, _P, _P, _P, _P, _P]),
     "aslam_policy_sample": (ctypes.c_int, [_P, _P, _P, _P, _I32, _P, _P, _P]),
     "aslam_policy_prepare": (ctypes.c_int, [_P, _P, _P]),
+    "aslam_policy_backward_rows": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _I32, _P, _P, _P, _P, _P, _P, _P]),
     "aslam_policy_act": (ctypes.c_int, [_P, _P, _I32, _P, _P, _P, _I32, _P, _P, _P, _P, _P, _P]),
     "aslam_gather_rows": (ctypes.c_int, [_P, _I64, _P, _I32, _P, _P]),
     "aslam_gae": (ctypes.c_int, [_P, _P, _P, _P, _I32, _I32, ctypes.c_float, ctypes.c_float, _P, _P, _P]),

@@ -170,10 +170,10 @@ __device__ __forceinline__ bf16x8 conv2_col_frag(const uint16_t* s_a1, int oy, i
 
 // Encoder forward: a2[b * lda2 + co*256 + oy*16 + ox] = bf16(relu(conv2(relu(conv1(crop_b))))), and
 // the rest of the FC1 input row: a2[b * lda2 + 8192 + j] = bf16(scan_b[j]), then bf16(state_b), then
-// zeros up to lda2.
+// zeros up to lda2.  Input row b is rows[b] of crop / scan / state (b itself when rows is NULL).
 __global__ __launch_bounds__(256) void k_conv_fwd(const float* prm, Offsets o, const uint4* frag,
                                                   const int16_t* crop, const float* scan, const float* state, int R,
-                                                  uint16_t* a2, int64_t lda2, int B) {
+                                                  const int32_t* rows, uint16_t* a2, int64_t lda2, int B) {
   __shared__ __align__(16) uint16_t s_crop[kCropLds];
   __shared__ __align__(16) uint16_t s_a1[kA1Lds];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
@@ -193,19 +193,21 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const float* prm, Offsets o, c
 #pragma unroll
     for (int s = 0; s < 5; ++s) w2f[nt][s] = __builtin_bit_cast(bf16x8, frag[64 * (1 + 5 * nt + s) + lane]);
   const float b2[2] = {prm[o.c2b + lr], prm[o.c2b + 16 + lr]};
+  auto src = [&](int b) -> int64_t { return rows ? (int64_t)rows[b] : (int64_t)b; };
   CropRegs<256> cr;
-  if (blockIdx.x < B) load_crop<256>(crop + (int64_t)blockIdx.x * kCrop * kCrop, cr);
+  if (blockIdx.x < B) load_crop<256>(crop + src(blockIdx.x) * kCrop * kCrop, cr);
   __syncthreads();
   for (int b = blockIdx.x; b < B; b += gridDim.x) {
     store_crop<256>(cr, s_crop);
     __syncthreads();
     // the next sample's crop is loaded while this one is processed
-    if (b + (int)gridDim.x < B) load_crop<256>(crop + (int64_t)(b + gridDim.x) * kCrop * kCrop, cr);
+    if (b + (int)gridDim.x < B) load_crop<256>(crop + src(b + gridDim.x) * kCrop * kCrop, cr);
     conv1_lds(s_crop, s_a1, w1f, b1, wave, lr, lg);
+    const int64_t sb = src(b);
     for (int j = threadIdx.x; j < (int)(lda2 - kFeat); j += 256) {
       float v = 0.0f;
-      if (j < R) v = scan[(int64_t)b * R + j];
-      else if (j < R + 12) v = state[(int64_t)b * 12 + (j - R)];
+      if (j < R) v = scan[sb * R + j];
+      else if (j < R + 12) v = state[sb * 12 + (j - R)];
       a2[(int64_t)b * lda2 + kFeat + j] = j < R + 12 ? f2bf(v) : (uint16_t)0;
     }
     __syncthreads();
@@ -340,8 +342,8 @@ __global__ __launch_bounds__(64 * kConvPhaseFrags) void k_conv_bwd_frags(const f
 }
 
 __global__ __launch_bounds__(kBwdThreads) void k_conv_bwd(const float* prm, Offsets o, const uint4* frag,
-                                                          const int16_t* crop, const uint16_t* dz2c, int B,
-                                                          float* part) {
+                                                          const int16_t* crop, const int32_t* rows,
+                                                          const uint16_t* dz2c, int B, float* part) {
   __shared__ __align__(16) uint16_t s_crop[kCropLds];
   __shared__ __align__(16) uint16_t s_a1x[kA1xLds];
   __shared__ __align__(16) uint16_t s_dz[kDzLds];
@@ -377,7 +379,7 @@ __global__ __launch_bounds__(kBwdThreads) void k_conv_bwd(const float* prm, Offs
   CropRegs<kBwdThreads> cr;
   uint4 dzr[2];
   auto load_sample = [&](int bb) {
-    load_crop<kBwdThreads>(crop + (int64_t)bb * kCrop * kCrop, cr);
+    load_crop<kBwdThreads>(crop + (rows ? (int64_t)rows[bb] : (int64_t)bb) * kCrop * kCrop, cr);
     const uint4* src = reinterpret_cast<const uint4*>(dz2c + (int64_t)bb * kFeat);
     dzr[0] = src[threadIdx.x];
     dzr[1] = src[threadIdx.x + kBwdThreads];

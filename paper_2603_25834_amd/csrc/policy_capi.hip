@@ -114,10 +114,10 @@ int convert_weights(aslam_policy* P, const float* prm, hipStream_t st, bool tran
 // Encoder (conv features and the scan / state tail into the FC1 input x) and FC1.  Small batches
 // split K so that the launch fills the chip: then *S_used split-K slices are left in P->part;
 // otherwise FC1 writes h1 = bf16(relu(. + b1)) and *S_used = 0.
-int encode_fc1(aslam_policy* P, const float* prm, const int16_t* crop, const float* scan, const float* state, int B,
-               hipStream_t st, int* S_used) {
+int encode_fc1(aslam_policy* P, const float* prm, const int16_t* crop, const float* scan, const float* state,
+               const int32_t* rows, int B, hipStream_t st, int* S_used) {
   const Offsets& o = P->off;
-  k_conv_fwd<<<std::min(B, kConvGrid), 256, 0, st>>>(prm, o, P->cfrag, crop, scan, state, P->cfg.n_scan, P->x,
+  k_conv_fwd<<<std::min(B, kConvGrid), 256, 0, st>>>(prm, o, P->cfrag, crop, scan, state, P->cfg.n_scan, rows, P->x,
                                                       P->k1p, B);
   PCHK(hipGetLastError());
   // FC1: [B x k1p] x [k1p x 256] (both operands zero-padded from k1 to k1p)
@@ -140,12 +140,12 @@ int encode_fc1(aslam_policy* P, const float* prm, const int16_t* crop, const flo
 
 // The backward's forward: every weight copy, the encoder, FC1 to h1 and the FC2 pre-activation z2 (FP32).
 int forward_core(aslam_policy* P, const float* prm, const int16_t* crop, const float* scan, const float* state,
-                 int B, hipStream_t st) {
+                 const int32_t* rows, int B, hipStream_t st) {
   const Offsets& o = P->off;
   int rc = convert_weights(P, prm, st, true);
   if (rc) return rc;
   int S = 0;
-  rc = encode_fc1(P, prm, crop, scan, state, B, st, &S);
+  rc = encode_fc1(P, prm, crop, scan, state, rows, B, st, &S);
   if (rc) return rc;
   if (S > 0) {
     const int64_t groups = (int64_t)B * (kHid / 8);
@@ -167,7 +167,7 @@ int act_core(aslam_policy* P, const float* prm, bool prepared, const int16_t* cr
     if (rc) return rc;
   }
   int S = 0;
-  int rc = encode_fc1(P, prm, crop, scan, state, B, st, &S);
+  int rc = encode_fc1(P, prm, crop, scan, state, nullptr, B, st, &S);
   if (rc) return rc;
   k_fwd_tail<<<(B + kTailRows - 1) / kTailRows, 256, 0, st>>>(prm, P->off, P->part, S, P->h1, P->w2b, B, mu, value,
                                                               eps, act, logp);
@@ -255,6 +255,14 @@ int aslam_policy_act(aslam_policy* P, const float* params, int32_t prepared, con
 int aslam_policy_backward(aslam_policy* P, const float* params, const int16_t* crop, const float* scan,
                           const float* state, int32_t batch, const float* act, const float* old_logp,
                           const float* adv, const float* ret, float* grads, float* loss, aslam_stream_t stream) {
+  return aslam_policy_backward_rows(P, params, crop, scan, state, nullptr, batch, act, old_logp, adv, ret, grads,
+                                    loss, stream);
+}
+
+int aslam_policy_backward_rows(aslam_policy* P, const float* params, const int16_t* crop, const float* scan,
+                               const float* state, const int32_t* rows, int32_t batch, const float* act,
+                               const float* old_logp, const float* adv, const float* ret, float* grads, float* loss,
+                               aslam_stream_t stream) {
   if (!P || !params || !crop || !scan || !state || !act || !old_logp || !adv || !ret || !grads || !loss)
     return pfail(ASL_EINVAL, "null argument");
   if (batch < 1 || batch > P->max_b) return pfail(ASL_EINVAL, "batch must be in [1, max_batch]");
@@ -262,12 +270,12 @@ int aslam_policy_backward(aslam_policy* P, const float* params, const int16_t* c
   const Offsets& o = P->off;
   const int B = batch;
   const int R = P->cfg.n_scan;
-  int rc = forward_core(P, params, crop, scan, state, B, st);
+  int rc = forward_core(P, params, crop, scan, state, rows, B, st);
   if (rc) return rc;
   // heads + loss -> dz2, head / fc2-bias / log-std partial sums
   const int nb = (B + kHeadRows - 1) / kHeadRows;
   LossCoef lc{P->cfg.clip_eps, P->cfg.c_value, P->cfg.c_entropy, 1.0f / (float)B};
-  k_heads<true><<<nb, 256, 0, st>>>(params, o, P->z2, B, nullptr, nullptr, act, old_logp, adv, ret, lc, P->dz2,
+  k_heads<true><<<nb, 256, 0, st>>>(params, o, P->z2, B, nullptr, nullptr, act, old_logp, adv, ret, rows, lc, P->dz2,
                                     P->hpart);
   PCHK(hipGetLastError());
   PCHK(launch_reduce(P->hpart, nb, kHeadPart, P->hsum, 3, kHeadPart, st));
@@ -305,7 +313,7 @@ int aslam_policy_backward(aslam_policy* P, const float* params, const int16_t* c
   // encoder: conv2 / conv1 weight and bias gradients in one pass over the minibatch
   {
     const int grid = std::min(B, kConvBwdGrid);
-    k_conv_bwd<<<grid, kBwdThreads, 0, st>>>(params, o, P->cfrag, crop, P->dz2c, B, part);
+    k_conv_bwd<<<grid, kBwdThreads, 0, st>>>(params, o, P->cfrag, crop, rows, P->dz2c, B, part);
     PCHK(hipGetLastError());
     PCHK(launch_reduce(part, grid, kConvPartW2, grads + o.c2w, 1, kConvPart, st));
     PCHK(launch_reduce(part + kConvPartW2, grid, kConvPartW1, grads + o.c1w, 2, kConvPart, st));

@@ -200,8 +200,8 @@ constexpr int kHeadRows = 64;   // rows per workgroup (16 per wave)
 template <bool GRAD>
 __global__ __launch_bounds__(256) void k_heads(const float* prm, Offsets o, const float* z2, int B, float* mu_out,
                                                float* v_out, const float* act, const float* old_logp,
-                                               const float* adv, const float* ret, LossCoef lc, uint16_t* dz2,
-                                               float* part) {
+                                               const float* adv, const float* ret, const int32_t* rows, LossCoef lc,
+                                               uint16_t* dz2, float* part) {
   __shared__ float acc[4][kHeadPart];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   float wmu0[4], wmu1[4], wv[4];
@@ -244,19 +244,20 @@ __global__ __launch_bounds__(256) void k_heads(const float* prm, Offsets o, cons
       }
       continue;
     }
-    // PPO loss of this row (Eqs. 18-20) with value and entropy terms
+    // PPO loss of this row (Eqs. 18-20) with value and entropy terms; its rollout data at row rows[row]
+    const int64_t sr = rows ? (int64_t)rows[row] : (int64_t)row;
     const float is0 = expf(-ls0), is1 = expf(-ls1);
-    const float u0 = (act[2 * (int64_t)row] - m0) * is0, u1 = (act[2 * (int64_t)row + 1] - m1) * is1;
+    const float u0 = (act[2 * sr] - m0) * is0, u1 = (act[2 * sr + 1] - m1) * is1;
     const float logp = -0.5f * (u0 * u0 + u1 * u1) - (ls0 + ls1) - log2pi;
-    const float ratio = expf(logp - old_logp[row]);
-    const float A = adv[row];
+    const float ratio = expf(logp - old_logp[sr]);
+    const float A = adv[sr];
     const float clipped = fminf(fmaxf(ratio, 1.0f - lc.eps), 1.0f + lc.eps);
     const float surr = fminf(ratio * A, clipped * A);
     // d(-surr)/dlogp is -A*ratio when the unclipped term is the minimum, else 0
     const bool active = ratio * A <= clipped * A;
     const float g_logp = active ? -A * ratio * lc.inv_b : 0.0f;
     const float dm0 = g_logp * (u0 * is0), dm1 = g_logp * (u1 * is1);
-    const float dV = lc.c_v * 2.0f * (val - ret[row]) * lc.inv_b;
+    const float dV = lc.c_v * 2.0f * (val - ret[sr]) * lc.inv_b;
     if (lane == 0) {
       gls0 += g_logp * (u0 * u0 - 1.0f);
       gls1 += g_logp * (u1 * u1 - 1.0f);
@@ -264,7 +265,7 @@ __global__ __launch_bounds__(256) void k_heads(const float* prm, Offsets o, cons
       gbm1 += dm1;
       gbv += dV;
       lclip += -surr * lc.inv_b;
-      lval += (val - ret[row]) * (val - ret[row]) * lc.inv_b;
+      lval += (val - ret[sr]) * (val - ret[sr]) * lc.inv_b;
     }
     uint32_t dzp[2];
 #pragma unroll

@@ -83,15 +83,22 @@ class Policy:
                                      _p(eps), _p(mu), _p(value), _p(act), _p(logp), _stream()))
         return value, act, logp
 
-    def backward(self, params, crop, scan, state, act, old_logp, adv, ret, grads, loss=None):
-        """Adds the PPO loss gradient of this minibatch to `grads`; returns loss terms [4]."""
+    def backward(self, params, crop, scan, state, act, old_logp, adv, ret, grads, loss=None, rows=None):
+        """Adds the PPO loss gradient of this minibatch to `grads`; returns loss terms [4].  With `rows`
+        (int32 [B]) the minibatch is those rows of rollout-sized inputs (no gathered copy)."""
         B = self._check_obs(params, crop, scan, state)
         for t, shp in ((act, (B, 2)), (old_logp, (B,)), (adv, (B,)), (ret, (B,))):
             assert t.dtype == torch.float32 and tuple(t.shape) == shp
         assert grads.dtype == torch.float32 and grads.numel() == self.n_params
         loss = torch.empty(4, device=crop.device) if loss is None else loss
-        check(lib().aslam_policy_backward(self.h, _p(params), _p(crop), _p(scan), _p(state), B, _p(act),
-                                          _p(old_logp), _p(adv), _p(ret), _p(grads), _p(loss), _stream()))
+        if rows is None:
+            check(lib().aslam_policy_backward(self.h, _p(params), _p(crop), _p(scan), _p(state), B, _p(act),
+                                              _p(old_logp), _p(adv), _p(ret), _p(grads), _p(loss), _stream()))
+        else:
+            assert rows.dtype == torch.int32 and rows.is_cuda and rows.dim() == 1
+            check(lib().aslam_policy_backward_rows(self.h, _p(params), _p(crop), _p(scan), _p(state), _p(rows),
+                                                   rows.numel(), _p(act), _p(old_logp), _p(adv), _p(ret), _p(grads),
+                                                   _p(loss), _stream()))
         return loss
 
 

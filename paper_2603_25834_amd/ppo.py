@@ -7,8 +7,9 @@ batched POMDP step of Sec. III-B.  One iteration:
       Gaussian action sample in one call (value, action, log-prob; the BF16 weight copies are formed
       once per rollout) -> env step (reward, done) -> masked reset of the robots whose episode ended;
   bootstrap value of the last observation; GAE over the [T, N] rollout;
-  update: `epochs` passes over the T*N samples in shuffled minibatches: row gather -> fused loss and
-      gradient (activations recomputed from the stored inputs) -> Adam.
+  update: `epochs` passes over the T*N samples in shuffled minibatches: fused loss and gradient over
+      the minibatch's rows of the rollout arrays, read in place (activations recomputed from the stored
+      inputs) -> Adam.
 
 Every stage runs in the library's kernels; torch provides device memory, the stream and two
 `zero_()` fills (the gradient accumulator).  Random draws (odometry noise, action noise, minibatch
@@ -19,7 +20,7 @@ from __future__ import annotations
 import numpy as np
 import torch
 
-from .policy import Policy, adam, gae, gather_rows
+from .policy import Policy, adam, gae
 
 
 class PPOTrainer:
@@ -53,15 +54,6 @@ class PPOTrainer:
         self.reward = torch.zeros((T, n), device=dev)
         self.done = torch.zeros((T, n), dtype=torch.uint8, device=dev)
         self.ranges = torch.zeros((n, R), device=dev)
-        # minibatch storage
-        mb = self.mb
-        self.mb_crop = torch.zeros((mb, crop, crop), dtype=torch.int16, device=dev)
-        self.mb_scan = torch.zeros((mb, R), device=dev)
-        self.mb_state = torch.zeros((mb, 12), device=dev)
-        self.mb_act = torch.zeros((mb, 2), device=dev)
-        self.mb_logp = torch.zeros(mb, device=dev)
-        self.mb_adv = torch.zeros(mb, device=dev)
-        self.mb_ret = torch.zeros(mb, device=dev)
         self.loss = torch.zeros(4, device=dev)
 
     def draws(self, iterations: int, seed: int):
@@ -103,17 +95,9 @@ class PPOTrainer:
             for k in range(self.n_mb):
                 lo = k * self.mb
                 idx = perm[e, lo:min(self.S, lo + self.mb)]
-                b = idx.numel()
-                mbs = {}
-                for name, dst in (("crop", self.mb_crop), ("scan", self.mb_scan), ("state", self.mb_state),
-                                  ("act", self.mb_act), ("logp", self.mb_logp), ("adv", self.mb_adv),
-                                  ("ret", self.mb_ret)):
-                    src = flat[name] if flat[name].dim() > 1 else flat[name].view(-1, 1)
-                    out = dst[:b] if dst.dim() > 1 else dst[:b].view(-1, 1)
-                    gather_rows(src, idx, out)
-                    mbs[name] = dst[:b]
                 self.grads.zero_()
-                pol.backward(p, mbs["crop"], mbs["scan"], mbs["state"], mbs["act"], mbs["logp"], mbs["adv"],
-                             mbs["ret"], self.grads, self.loss)
+                # the minibatch is the rows idx of the rollout arrays: the kernels read them in place
+                pol.backward(p, flat["crop"], flat["scan"], flat["state"], flat["act"], flat["logp"], flat["adv"],
+                             flat["ret"], self.grads, self.loss, rows=idx)
                 self.step_count += 1
                 adam(p, self.grads, self.m, self.v, self.step_count, lr=self.lr)

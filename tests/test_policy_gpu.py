@@ -305,3 +305,22 @@ def test_forward_unsplit_fc1_sampled_rows():
              np.linalg.norm(gv - vb.numpy()) / np.linalg.norm(vb.numpy()))
     say(f"[policy] unsplit forward rel err vs workload precision {eb:.2e}")
     assert eb < 2e-3
+
+
+def test_backward_rows_equals_gathered_backward():
+    """A minibatch given as rows of rollout-sized arrays gives bit-identical gradients and loss terms to the
+    same minibatch gathered into its own arrays first."""
+    from paper_2603_25834_amd.policy import gather_rows
+    S, B = 3000, 1100
+    theta, t = _case(S, 14)
+    pol, params, dev = _gpu(theta, t)
+    idx = torch.from_numpy(np.random.default_rng(14).permutation(S)[:B].astype(np.int32)).cuda()
+    g1, g2 = torch.zeros_like(params), torch.zeros_like(params)
+    l1 = pol.backward(params, dev["crop"], dev["scan"], dev["state"], dev["act"], dev["old_logp"], dev["adv"],
+                      dev["ret"], g1, rows=idx)
+    mb = {k: gather_rows(v if v.dim() > 1 else v.view(-1, 1), idx) for k, v in dev.items()}
+    mb = {k: (v.view(-1) if dev[k].dim() == 1 else v) for k, v in mb.items()}
+    l2 = pol.backward(params, mb["crop"], mb["scan"], mb["state"], mb["act"], mb["old_logp"], mb["adv"], mb["ret"],
+                      g2)
+    torch.cuda.synchronize()
+    assert torch.equal(g1, g2) and torch.equal(l1, l2)
