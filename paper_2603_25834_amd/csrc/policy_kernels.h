@@ -378,6 +378,32 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce(const float* part, in
   }
 }
 
+// a[j] += q[z * stride + j] for z = 0 .. S-1 in order, j < 8.  The loads of eight slices are issued
+// before their adds, so the slices cost one memory round trip per eight, not one each; the additions
+// keep the order of z.
+__device__ __forceinline__ void sum_slices8(const float* q, int S, int64_t stride, float a[8]) {
+  int z = 0;
+  for (; z + 8 <= S; z += 8) {
+    float4 lo[8], hi[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      lo[u] = *reinterpret_cast<const float4*>(q + (int64_t)(z + u) * stride);
+      hi[u] = *reinterpret_cast<const float4*>(q + (int64_t)(z + u) * stride + 4);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      a[0] += lo[u].x; a[1] += lo[u].y; a[2] += lo[u].z; a[3] += lo[u].w;
+      a[4] += hi[u].x; a[5] += hi[u].y; a[6] += hi[u].z; a[7] += hi[u].w;
+    }
+  }
+  for (; z < S; ++z) {
+    const float4 lo = *reinterpret_cast<const float4*>(q + (int64_t)z * stride);
+    const float4 hi = *reinterpret_cast<const float4*>(q + (int64_t)z * stride + 4);
+    a[0] += lo.x; a[1] += lo.y; a[2] += lo.z; a[3] += lo.w;
+    a[4] += hi.x; a[5] += hi.y; a[6] += hi.z; a[7] += hi.w;
+  }
+}
+
 // Split-K finish of a GEMM with a bias + ReLU + BF16 epilogue: out[m][n] =
 // bf16(relu(bias[n] + sum_z part[z][m][n])), z in order; 8 columns per thread (N % 8 == 0).
 __global__ void k_reduce_bias_relu_bf16(const float* part, int S, int M, int N, const float* bias, uint16_t* out,
@@ -390,13 +416,7 @@ __global__ void k_reduce_bias_relu_bf16(const float* part, int S, int M, int N, 
     float a[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) a[j] = 0.0f;
-    const float* q = part + m * N + n0;
-    for (int z = 0; z < S; ++z) {
-      const float4 lo = *reinterpret_cast<const float4*>(q + (int64_t)z * M * N);
-      const float4 hi = *reinterpret_cast<const float4*>(q + (int64_t)z * M * N + 4);
-      a[0] += lo.x; a[1] += lo.y; a[2] += lo.z; a[3] += lo.w;
-      a[4] += hi.x; a[5] += hi.y; a[6] += hi.z; a[7] += hi.w;
-    }
+    sum_slices8(part + m * N + n0, S, (int64_t)M * N, a);
     uint16_t h[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) h[j] = f2bf(fmaxf(a[j] + bias[n0 + j], 0.0f));
@@ -534,13 +554,7 @@ __global__ __launch_bounds__(256) void k_fwd_tail(const float* prm, Offsets o, c
         float a[8];
 #pragma unroll
         for (int j = 0; j < 8; ++j) a[j] = 0.0f;
-        const float* q = part + m * kHid + n0;
-        for (int z = 0; z < S; ++z) {
-          const float4 lo = *reinterpret_cast<const float4*>(q + (int64_t)z * B * kHid);
-          const float4 hi = *reinterpret_cast<const float4*>(q + (int64_t)z * B * kHid + 4);
-          a[0] += lo.x; a[1] += lo.y; a[2] += lo.z; a[3] += lo.w;
-          a[4] += hi.x; a[5] += hi.y; a[6] += hi.z; a[7] += hi.w;
-        }
+        sum_slices8(part + m * kHid + n0, S, (int64_t)B * kHid, a);
         uint16_t h[8];
 #pragma unroll
         for (int j = 0; j < 8; ++j) h[j] = f2bf(fmaxf(a[j] + b1[n0 + j], 0.0f));
