@@ -231,6 +231,50 @@ def init_policy_params(n_scan: int = 360, seed: int = 0) -> np.ndarray:
     return np.concatenate(parts)
 
 
+def recurrent_param_layout(n_scan: int = 128):
+    """(name, shape) of the recurrent actor-critic's flat FP32 parameter vector: the feed-forward
+    layout with FC2 replaced by a GRU of 256 units (input and hidden weights [768, 256], gate rows in
+    the order reset / update / new, then their biases [768] each)."""
+    out = []
+    for name, shp in policy_param_layout(n_scan):
+        if name == "fc2.w":
+            out += [("gru.w_ih", (768, 256)), ("gru.w_hh", (768, 256)), ("gru.b_ih", (768,)), ("gru.b_hh", (768,))]
+        elif name != "fc2.b":
+            out.append((name, shp))
+    return out
+
+
+def init_recurrent_params(n_scan: int = 128, seed: int = 0) -> np.ndarray:
+    """Seeded initialisation of the recurrent layout: as init_policy_params, GRU weights and biases
+    uniform in +-1/sqrt(256)."""
+    rng = np.random.default_rng([seed, 12])
+    parts = []
+    for name, shp in recurrent_param_layout(n_scan):
+        n = int(np.prod(shp))
+        if name == "log_std":
+            parts.append(np.full(n, -0.5, np.float32))
+        elif name.startswith("gru."):
+            parts.append(rng.uniform(-1.0 / 16.0, 1.0 / 16.0, n).astype(np.float32))
+        elif name.endswith(".b"):
+            parts.append(rng.uniform(-0.05, 0.05, n).astype(np.float32))
+        else:
+            bound = 1.0 / math.sqrt(int(np.prod(shp[1:])))
+            parts.append(rng.uniform(-bound, bound, n).astype(np.float32))
+    return np.concatenate(parts)
+
+
+def recurrent_batch(T: int, nb: int, n_scan: int = 128, seed: int = 0, reset_p: float = 0.05):
+    """A synthetic rollout segment of T steps for nb robots (time-major [T, nb, ...]): the arrays of
+    policy_batch, an entering hidden state h0 [nb, 256] in (-0.5, 0.5) and episode starts first [T, nb]
+    (uint8, each step starts an episode with probability reset_p)."""
+    d = policy_batch(T * nb, n_scan, seed)
+    out = {k: v.reshape((T, nb) + v.shape[1:]) for k, v in d.items()}
+    rng = np.random.default_rng([seed, 13])
+    out["h0"] = rng.uniform(-0.5, 0.5, size=(nb, 256)).astype(np.float32)
+    out["first"] = (rng.random((T, nb)) < reset_p).astype(np.uint8)
+    return out
+
+
 def policy_batch(n: int, n_scan: int = 360, seed: int = 0):
     """Synthetic PPO minibatch shaped like rollout data: belief crops (int16 log-odds made of
     hit/miss counts, clamped), normalised scans, pose/covariance states, actions, old log-probs,
