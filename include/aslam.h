@@ -214,10 +214,16 @@ typedef struct {
   float clip_eps;     /* PPO clip epsilon (Eq. 19) */
   float c_value;      /* value-loss weight */
   float c_entropy;    /* entropy-bonus weight */
+  int32_t recurrent;  /* 1: the GRU of Sec. III-F ("Recurrent Layer", 256 units) in place of FC2, layout
+                         below; such a handle takes aslam_policy_act_rnn / _backward_seq only */
 } aslam_policy_config;
 
-/* Number of parameters for scan length n_scan (2,264,005 for R = 360). */
+/* Number of parameters for scan length n_scan (2,264,005 for R = 360), feed-forward layout. */
 int64_t aslam_policy_num_params(int32_t n_scan);
+/* Number of parameters of either layout (-1 for a bad config).  The recurrent
+ * layout replaces fc2.w, fc2.b by gru.w_ih [768,256], gru.w_hh [768,256],
+ * gru.b_ih [768], gru.b_hh [768] (gate rows reset, update, new). */
+int64_t aslam_policy_param_count(const aslam_policy_config* cfg);
 /* Allocates the minibatch workspaces (about 100 KB per sample of max_batch). */
 int aslam_policy_create(const aslam_policy_config* cfg, aslam_policy** out);
 int aslam_policy_destroy(aslam_policy* pol);
@@ -270,6 +276,35 @@ int aslam_policy_backward_rows(aslam_policy* pol, const float* params_dev, const
                                const float* scan_dev, const float* state_dev, const int32_t* rows_dev, int32_t batch,
                                const float* act_dev, const float* old_logp_dev, const float* adv_dev,
                                const float* ret_dev, float* grads_dev, float* loss_dev, aslam_stream_t stream);
+
+/* Recurrent rollout step (Sec. III-F, a single-layer GRU of 256 units):
+ *   r = sigmoid(W_ir x + b_ir + W_hr h + b_hr), z = sigmoid(W_iz x + b_iz + W_hz h + b_hz),
+ *   n = tanh(W_in x + b_in + r (W_hn h + b_hn)), h' = (1 - z) n + z h,
+ * x = the FC1 output, h = h_in_dev [B,256] FP32 row b, or 0 where first_dev[b]
+ * (uint8 [B], may be NULL) marks the first step of an episode.  Writes the new
+ * state h_out_dev [B,256] (may alias h_in_dev) and, from the heads on h', as
+ * aslam_policy_act: value_dev, act_dev, logp_dev and mu_dev if not NULL.
+ * prepared as in aslam_policy_act.  BF16 products with FP32 accumulation;
+ * gate math and state in FP32. */
+int aslam_policy_act_rnn(aslam_policy* pol, const float* params_dev, int32_t prepared, const int16_t* crop_dev,
+                         const float* scan_dev, const float* state_dev, int32_t batch, const float* h_in_dev,
+                         const uint8_t* first_dev, const float* eps_dev, float* mu_dev, float* value_dev,
+                         float* act_dev, float* logp_dev, float* h_out_dev, aslam_stream_t stream);
+
+/* PPO loss and its gradient for the recurrent policy over whole sequences,
+ * with backpropagation through time.  The rollout arrays are time-major:
+ * crop_dev [T,N,64,64], scan_dev [T,N,R], state_dev [T,N,12], act_dev [T,N,2],
+ * old_logp_dev / adv_dev / ret_dev [T,N], first_dev uint8 [T,N] (step t of
+ * robot n starts an episode: its state is zeroed before the step), h0_dev
+ * [N,256] the state entering step 0.  The minibatch is the nb robots
+ * robots_dev[0 .. nb-1] (int32, device) over all T steps: T * nb samples,
+ * at most max_batch; the loss is the mean over them.  grads_dev is ADDED to;
+ * loss_dev [4] as aslam_policy_backward. */
+int aslam_policy_backward_seq(aslam_policy* pol, const float* params_dev, const int16_t* crop_dev,
+                              const float* scan_dev, const float* state_dev, int32_t T, int32_t N,
+                              const int32_t* robots_dev, int32_t nb, const float* h0_dev, const uint8_t* first_dev,
+                              const float* act_dev, const float* old_logp_dev, const float* adv_dev,
+                              const float* ret_dev, float* grads_dev, float* loss_dev, aslam_stream_t stream);
 
 /* Generalized Advantage Estimation (Sec. III-F) over a [T,N] rollout (time-major):
  *   delta_t = r_t + gamma V_{t+1} (1 - d_t) - V_t,  A_t = delta_t + gamma lam (1 - d_t) A_{t+1},

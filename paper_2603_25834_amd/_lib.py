@@ -74,6 +74,10 @@ SIGNATURES = {
     "aslam_env_graph_build": (ctypes.c_int, [_P, _I32, _P, _I64, _P, _I64, _P, _I64, _P, _I64, _P, _I64]),
     "aslam_env_graph_launch": (ctypes.c_int, [_P, _P]),
     "aslam_policy_num_params": (_I64, [_I32]),
+    "aslam_policy_param_count": (_I64, [_P]),
+    "aslam_policy_act_rnn": (ctypes.c_int, [_P, _P, _I32, _P, _P, _P, _I32, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "aslam_policy_backward_seq": (ctypes.c_int, [_P, _P, _P, _P, _P, _I32, _I32, _P, _I32, _P, _P, _P, _P, _P, _P, _P,
+                                                 _P, _P]),
     "aslam_policy_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_P)]),
     "aslam_policy_destroy": (ctypes.c_int, [_P]),
     "aslam_policy_forward": (ctypes.c_int, [_P, _P, _P, _P, _P, _I32, _P, _P, _P]),
@@ -114,4 +118,4 @@ def check(rc: int) -> None:
 
 class PolicyConfig(ctypes.Structure):
     _fields_ = [("n_scan", ctypes.c_int32), ("max_batch", ctypes.c_int32), ("clip_eps", ctypes.c_float),
-                ("c_value", ctypes.c_float), ("c_entropy", ctypes.c_float)]
+                ("c_value", ctypes.c_float), ("c_entropy", ctypes.c_float), ("recurrent", ctypes.c_int32)]

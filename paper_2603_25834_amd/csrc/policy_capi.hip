@@ -11,6 +11,7 @@
 #include "aslam.h"
 #include "policy_kernels.h"
 #include "conv_fused.h"
+#include "gru_kernels.h"
 
 using namespace aslam;
 using namespace aslam::pol;
@@ -39,6 +40,13 @@ struct aslam_policy {
   int32_t k1p = 0;   // FC1 input width padded to a multiple of 8
   int64_t part_floats = 0;
   bool prepared = false;   // w1b / w2b hold the weights of some params (the caller tracks which)
+  // recurrent handle: the GRU's weight copies and the sequence minibatch's buffers
+  bool rec = false;
+  uint16_t *wihb = nullptr, *whhb = nullptr, *wiht = nullptr, *whht = nullptr;
+  float *hst = nullptr, *g_r = nullptr, *g_z = nullptr, *g_n = nullptr, *g_ghn = nullptr, *hp_used = nullptr;
+  float *dh_head = nullptr, *dh_buf = nullptr;
+  uint16_t *hp_bf = nullptr, *dgi = nullptr, *dgh = nullptr;
+  int32_t* rows = nullptr;
 };
 
 namespace {
@@ -76,6 +84,8 @@ int64_t part_need(const aslam_policy* p) {
   const int64_t k1 = p->off.k1;
   int64_t need = kFc1Splits * 256 * k1;                      // FC1 weight partials
   need = std::max<int64_t>(need, kFc2Splits * kHid * kHid);   // FC2 weight partials
+  if (p->rec) need = std::max<int64_t>(need, (int64_t)kFc2Splits * kGates * kHid);   // GRU weight partials
+  if (p->rec) need = std::max<int64_t>(need, (int64_t)kBiasBlocks * kGates);         // GRU bias partials
   need = std::max<int64_t>(need, (int64_t)kConvBwdGrid * kConvPart);   // encoder backward partials
   need = std::max<int64_t>(need, (int64_t)kBiasBlocks * 256);
   need = std::max<int64_t>(need, (int64_t)kFc1MinBlocks * 64 * kHid);   // FC1 forward split-K: S * B <= 512 * 64
@@ -95,6 +105,26 @@ int convert_weights(aslam_policy* P, const float* prm, hipStream_t st, bool tran
   const Offsets& o = P->off;
   k_convert_bf16<<<1024, 256, 0, st>>>(prm + o.f1w, o.k1, kHid, o.k1, P->w1b, P->k1p);
   PCHK(hipGetLastError());
+  if (P->rec) {
+    k_convert_bf16<<<768, 256, 0, st>>>(prm + o.gih, kHid, kGates, kHid, P->wihb, kHid);
+    PCHK(hipGetLastError());
+    k_convert_bf16<<<768, 256, 0, st>>>(prm + o.ghh, kHid, kGates, kHid, P->whhb, kHid);
+    PCHK(hipGetLastError());
+    k_conv_frags<<<1, 64 * kConvFrags, 0, st>>>(prm, o, P->cfrag);
+    PCHK(hipGetLastError());
+    if (transposed) {
+      k_conv_bwd_frags<<<1, 64 * kConvPhaseFrags, 0, st>>>(prm, o, P->cfrag);
+      PCHK(hipGetLastError());
+      k_transpose_bf16<<<dim3(kFeat / 32, kHid / 32), 256, 0, st>>>(prm + o.f1w, o.k1, kHid, kFeat, P->w1t, kHid);
+      PCHK(hipGetLastError());
+      k_transpose_bf16<<<dim3(kHid / 32, kGates / 32), 256, 0, st>>>(prm + o.gih, kHid, kGates, kHid, P->wiht, kGates);
+      PCHK(hipGetLastError());
+      k_transpose_bf16<<<dim3(kHid / 32, kGates / 32), 256, 0, st>>>(prm + o.ghh, kHid, kGates, kHid, P->whht, kGates);
+      PCHK(hipGetLastError());
+    }
+    P->prepared = true;
+    return ASL_OK;
+  }
   k_convert_bf16<<<256, 256, 0, st>>>(prm + o.f2w, kHid, kHid, kHid, P->w2b, kHid);
   PCHK(hipGetLastError());
   k_conv_frags<<<1, 64 * kConvFrags, 0, st>>>(prm, o, P->cfrag);
@@ -175,6 +205,9 @@ int act_core(aslam_policy* P, const float* prm, bool prepared, const int16_t* cr
   return ASL_OK;
 }
 
+int backward_fc1_encoder(aslam_policy* P, const float* params, const int16_t* crop, const int32_t* rows, int B,
+                         float* grads, hipStream_t st);
+
 }  // namespace
 
 extern "C" {
@@ -189,10 +222,12 @@ int aslam_policy_create(const aslam_policy_config* cfg, aslam_policy** out) {
   *out = nullptr;
   if (cfg->n_scan < 1 || cfg->n_scan > 4096) return pfail(ASL_EINVAL, "n_scan must be in [1, 4096]");
   if (cfg->max_batch < 1 || cfg->max_batch > (1 << 20)) return pfail(ASL_EINVAL, "max_batch must be in [1, 2^20]");
+  if (cfg->recurrent != 0 && cfg->recurrent != 1) return pfail(ASL_EINVAL, "recurrent must be 0 or 1");
   aslam_policy* p = new (std::nothrow) aslam_policy();
   if (!p) return pfail(ASL_ENOMEM, "host allocation failed");
   p->cfg = *cfg;
-  p->off = offsets(cfg->n_scan);
+  p->rec = cfg->recurrent == 1;
+  p->off = offsets(cfg->n_scan, p->rec);
   p->max_b = cfg->max_batch;
   const int64_t Bm = p->max_b;
   p->part_floats = part_need(p);
@@ -214,14 +249,38 @@ int aslam_policy_create(const aslam_policy_config* cfg, aslam_policy** out) {
       return pfail(ASL_ENOMEM, "hipMalloc of policy workspace failed");
     }
   }
+  if (p->rec) {
+    const size_t f = 4 * (size_t)Bm * kHid, h = 2 * (size_t)Bm * kHid, g = 2 * (size_t)Bm * kGates;
+    const size_t w = 2 * (size_t)kGates * kHid;
+    struct A rl[] = {
+        {(void**)&p->wihb, w}, {(void**)&p->whhb, w}, {(void**)&p->wiht, w}, {(void**)&p->whht, w},
+        {(void**)&p->hst, f}, {(void**)&p->g_r, f}, {(void**)&p->g_z, f}, {(void**)&p->g_n, f},
+        {(void**)&p->g_ghn, f}, {(void**)&p->hp_used, f}, {(void**)&p->dh_head, f}, {(void**)&p->dh_buf, 2 * f},
+        {(void**)&p->hp_bf, h}, {(void**)&p->dgi, g}, {(void**)&p->dgh, g},
+        {(void**)&p->rows, 4 * (size_t)Bm},
+    };
+    for (auto& a : rl) {
+      if (hipMalloc(a.ptr, a.bytes) != hipSuccess) {
+        aslam_policy_destroy(p);
+        return pfail(ASL_ENOMEM, "hipMalloc of policy workspace failed");
+      }
+    }
+  }
   *out = p;
   return ASL_OK;
+}
+
+int64_t aslam_policy_param_count(const aslam_policy_config* cfg) {
+  if (!cfg || cfg->n_scan < 0 || (cfg->recurrent != 0 && cfg->recurrent != 1)) return -1;
+  return offsets(cfg->n_scan, cfg->recurrent == 1).total;
 }
 
 int aslam_policy_destroy(aslam_policy* p) {
   if (!p) return pfail(ASL_EINVAL, "policy is NULL");
   void* ptrs[] = {p->x, p->h1, p->dz2, p->dz1, p->dz2c, p->z2, p->part, p->hpart, p->hsum,
-                  p->w1b, p->w1t, p->w2b, p->w2t, p->cfrag};
+                  p->w1b, p->w1t, p->w2b, p->w2t, p->cfrag,
+                  p->wihb, p->whhb, p->wiht, p->whht, p->hst, p->g_r, p->g_z, p->g_n, p->g_ghn, p->hp_used,
+                  p->dh_head, p->dh_buf, p->hp_bf, p->dgi, p->dgh, p->rows};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   delete p;
@@ -232,6 +291,7 @@ int aslam_policy_forward(aslam_policy* P, const float* params, const int16_t* cr
                          const float* state, int32_t batch, float* mu, float* value, aslam_stream_t stream) {
   if (!P || !params || !crop || !scan || !state || !mu || !value) return pfail(ASL_EINVAL, "null argument");
   if (batch < 1 || batch > P->max_b) return pfail(ASL_EINVAL, "batch must be in [1, max_batch]");
+  if (P->rec) return pfail(ASL_EINVAL, "recurrent policy: use aslam_policy_act_rnn");
   return act_core(P, params, false, crop, scan, state, batch, nullptr, mu, value, nullptr, nullptr,
                   (hipStream_t)stream);
 }
@@ -247,6 +307,7 @@ int aslam_policy_act(aslam_policy* P, const float* params, int32_t prepared, con
   if (!P || !params || !crop || !scan || !state || !eps || !value || !act || !logp)
     return pfail(ASL_EINVAL, "null argument");
   if (batch < 1 || batch > P->max_b) return pfail(ASL_EINVAL, "batch must be in [1, max_batch]");
+  if (P->rec) return pfail(ASL_EINVAL, "recurrent policy: use aslam_policy_act_rnn");
   if (prepared && !P->prepared) return pfail(ASL_ESTATE, "act with prepared = 1 before any prepare");
   return act_core(P, params, prepared != 0, crop, scan, state, batch, eps, mu, value, act, logp,
                   (hipStream_t)stream);
@@ -266,10 +327,10 @@ int aslam_policy_backward_rows(aslam_policy* P, const float* params, const int16
   if (!P || !params || !crop || !scan || !state || !act || !old_logp || !adv || !ret || !grads || !loss)
     return pfail(ASL_EINVAL, "null argument");
   if (batch < 1 || batch > P->max_b) return pfail(ASL_EINVAL, "batch must be in [1, max_batch]");
+  if (P->rec) return pfail(ASL_EINVAL, "recurrent policy: use aslam_policy_backward_seq");
   hipStream_t st = (hipStream_t)stream;
   const Offsets& o = P->off;
   const int B = batch;
-  const int R = P->cfg.n_scan;
   int rc = forward_core(P, params, crop, scan, state, rows, B, st);
   if (rc) return rc;
   // heads + loss -> dz2, head / fc2-bias / log-std partial sums
@@ -295,6 +356,19 @@ int aslam_policy_backward_rows(aslam_policy* P, const float* params, const int16
   // dh1 -> dz1 = (dz2 W2) * [h1 > 0]
   PCHK((gemm::run<128, 128, 64, 2, 2>(LdBF16K{P->dz2, kHid, B, kHid}, LdBF16K{P->w2t, kHid, kHid, kHid},
                                      EpiReluGradBF16{P->dz1, P->h1, kHid, kHid}, B, kHid, kHid, 1, st)));
+  return backward_fc1_encoder(P, params, crop, rows, B, grads, st);
+}
+
+}  // extern "C"
+
+namespace {
+
+// Everything below the FC1 output gradient dz1 (BF16, already masked by FC1's ReLU): the FC1 bias and
+// weight gradients, the conv-feature gradient and the encoder backward.
+int backward_fc1_encoder(aslam_policy* P, const float* params, const int16_t* crop, const int32_t* rows, int B,
+                         float* grads, hipStream_t st) {
+  const Offsets& o = P->off;
+  float* part = P->part;
   // FC1 bias
   k_bias_rows<<<kBiasBlocks, 256, 0, st>>>(P->dz1, B, kHid, part);
   PCHK(hipGetLastError());
@@ -322,6 +396,10 @@ int aslam_policy_backward_rows(aslam_policy* P, const float* params, const int16
   }
   return ASL_OK;
 }
+
+}  // namespace
+
+extern "C" {
 
 int aslam_policy_sample(aslam_policy* P, const float* params, const float* mu, const float* eps, int32_t batch,
                         float* act, float* logp, aslam_stream_t stream) {
@@ -367,6 +445,125 @@ int aslam_adam(float* params, const float* grads, float* m, float* v, int64_t n,
   k_adam<<<blocks, 256, 0, (hipStream_t)stream>>>(params, grads, m, v, n, lr, beta1, beta2, eps, bc1, bc2);
   PCHK(hipGetLastError());
   return ASL_OK;
+}
+
+int aslam_policy_act_rnn(aslam_policy* P, const float* params, int32_t prepared, const int16_t* crop,
+                         const float* scan, const float* state, int32_t batch, const float* h_in, const uint8_t* first,
+                         const float* eps, float* mu, float* value, float* act, float* logp, float* h_out,
+                         aslam_stream_t stream) {
+  if (!P || !params || !crop || !scan || !state || !h_in || !eps || !value || !act || !logp || !h_out)
+    return pfail(ASL_EINVAL, "null argument");
+  if (!P->rec) return pfail(ASL_EINVAL, "feed-forward policy: use aslam_policy_act");
+  if (batch < 1 || batch > P->max_b) return pfail(ASL_EINVAL, "batch must be in [1, max_batch]");
+  if (prepared && !P->prepared) return pfail(ASL_ESTATE, "act_rnn with prepared = 1 before any prepare");
+  hipStream_t st = (hipStream_t)stream;
+  if (!prepared) {
+    int rc = convert_weights(P, params, st, false);
+    if (rc) return rc;
+  }
+  int S = 0;
+  int rc = encode_fc1(P, params, crop, scan, state, nullptr, batch, st, &S);
+  if (rc) return rc;
+  GruFwdArgs a{};
+  a.prm = params; a.o = P->off; a.rows = batch; a.s0 = 0;
+  a.part = P->part; a.S = S; a.part_rows = batch; a.h1 = P->h1;
+  a.wih = P->wihb; a.whh = P->whhb;
+  a.hp = h_in; a.hp_map = nullptr; a.first = first; a.first_map = nullptr;
+  a.h_out = h_out;
+  a.mu = mu; a.value = value; a.eps = eps; a.act = act; a.logp = logp;
+  k_gru_fwd<true><<<(batch + kGruRows - 1) / kGruRows, 256, 0, st>>>(a);
+  PCHK(hipGetLastError());
+  return ASL_OK;
+}
+
+int aslam_policy_backward_seq(aslam_policy* P, const float* params, const int16_t* crop, const float* scan,
+                              const float* state, int32_t T, int32_t N, const int32_t* robots, int32_t nb,
+                              const float* h0, const uint8_t* first, const float* act, const float* old_logp,
+                              const float* adv, const float* ret, float* grads, float* loss, aslam_stream_t stream) {
+  if (!P || !params || !crop || !scan || !state || !robots || !h0 || !first || !act || !old_logp || !adv || !ret ||
+      !grads || !loss)
+    return pfail(ASL_EINVAL, "null argument");
+  if (!P->rec) return pfail(ASL_EINVAL, "feed-forward policy: use aslam_policy_backward");
+  if (T < 1 || N < 1 || nb < 1 || nb > N) return pfail(ASL_EINVAL, "need T >= 1 and 1 <= nb <= N");
+  if ((int64_t)T * nb > P->max_b) return pfail(ASL_EINVAL, "T * nb exceeds max_batch");
+  hipStream_t st = (hipStream_t)stream;
+  const Offsets& o = P->off;
+  const int B = T * nb;
+  k_seq_rows<<<(B + 255) / 256, 256, 0, st>>>(robots, nb, T, N, P->rows);
+  PCHK(hipGetLastError());
+  int rc = convert_weights(P, params, st, true);
+  if (rc) return rc;
+  int S = 0;
+  rc = encode_fc1(P, params, crop, scan, state, P->rows, B, st, &S);
+  if (rc) return rc;
+  if (S > 0) {
+    const int64_t groups = (int64_t)B * (kHid / 8);
+    k_reduce_bias_relu_bf16<<<(int)std::min<int64_t>(4096, (groups + 255) / 256), 256, 0, st>>>(
+        P->part, S, B, kHid, params + o.f1b, P->h1, kHid);
+    PCHK(hipGetLastError());
+  }
+  // the GRU over the T steps, keeping what the backward reads
+  const int grid = (nb + kGruRows - 1) / kGruRows;
+  for (int t = 0; t < T; ++t) {
+    GruFwdArgs a{};
+    a.prm = params; a.o = o; a.rows = nb; a.s0 = (int64_t)t * nb;
+    a.part = nullptr; a.S = 0; a.part_rows = 0; a.h1 = P->h1;
+    a.wih = P->wihb; a.whh = P->whhb;
+    a.hp = t == 0 ? h0 : P->hst + (int64_t)(t - 1) * nb * kHid;
+    a.hp_map = t == 0 ? robots : nullptr;
+    a.first = first + (int64_t)t * N; a.first_map = robots;
+    a.h_out = P->hst;
+    a.g_r = P->g_r; a.g_z = P->g_z; a.g_n = P->g_n; a.g_ghn = P->g_ghn; a.hp_used = P->hp_used; a.hp_bf = P->hp_bf;
+    k_gru_fwd<false><<<grid, 256, 0, st>>>(a);
+    PCHK(hipGetLastError());
+  }
+  // heads + loss on every sample -> dh (FP32), head / log-std partial sums
+  const int nh = (B + kHeadRows - 1) / kHeadRows;
+  LossCoef lc{P->cfg.clip_eps, P->cfg.c_value, P->cfg.c_entropy, 1.0f / (float)B};
+  k_heads<true, true><<<nh, 256, 0, st>>>(params, o, P->hst, B, nullptr, nullptr, act, old_logp, adv, ret, P->rows,
+                                          lc, nullptr, P->hpart, P->dh_head);
+  PCHK(hipGetLastError());
+  PCHK(launch_reduce(P->hpart, nh, kHeadPart, P->hsum, 3, kHeadPart, st));
+  k_scatter_heads<<<1, 256, 0, st>>>(P->hsum, grads, o, loss, P->cfg.c_entropy);
+  PCHK(hipGetLastError());
+  k_loss_total<<<1, 1, 0, st>>>(params, o, loss, P->cfg.c_value, P->cfg.c_entropy);
+  PCHK(hipGetLastError());
+  // backpropagation through time
+  for (int t = T - 1; t >= 0; --t) {
+    GruBwdArgs b{};
+    b.rows = nb; b.s0 = (int64_t)t * nb;
+    b.dh_head = P->dh_head;
+    b.dh_next = t == T - 1 ? nullptr : P->dh_buf + (int64_t)((t + 1) & 1) * nb * kHid;
+    b.g_r = P->g_r; b.g_z = P->g_z; b.g_n = P->g_n; b.g_ghn = P->g_ghn; b.hp_used = P->hp_used;
+    b.first = first + (int64_t)t * N; b.first_map = robots;
+    b.whht = P->whht; b.dgi = P->dgi; b.dgh = P->dgh;
+    b.dh_prev = P->dh_buf + (int64_t)(t & 1) * nb * kHid;
+    k_gru_bwd_step<<<grid, 256, 0, st>>>(b);
+    PCHK(hipGetLastError());
+  }
+  float* part = P->part;
+  // GRU weights: dW_ih = sum_s dgi[s] h1[s]^T, dW_hh = sum_s dgh[s] hp[s]^T; biases: column sums
+  {
+    const int64_t S2 = splits_for(B, 256, kFc2Splits);
+    const int S2u = slices_used(B, S2, 64);
+    const int64_t n = (int64_t)kGates * kHid;
+    PCHK((gemm::run<128, 128, 64, 2, 2>(LdBF16I{P->dgi, kGates, kGates, B}, LdBF16I{P->h1, kHid, kHid, B},
+                                       EpiPartial{part, kHid, n}, kGates, kHid, B, (int)S2, st)));
+    PCHK(launch_reduce(part, S2u, n, grads + o.gih, 0, n, st));
+    PCHK((gemm::run<128, 128, 64, 2, 2>(LdBF16I{P->dgh, kGates, kGates, B}, LdBF16I{P->hp_bf, kHid, kHid, B},
+                                       EpiPartial{part, kHid, n}, kGates, kHid, B, (int)S2, st)));
+    PCHK(launch_reduce(part, S2u, n, grads + o.ghh, 0, n, st));
+    k_colsum_bf16<<<kBiasBlocks, 256, 0, st>>>(P->dgi, B, kGates, part);
+    PCHK(hipGetLastError());
+    PCHK(launch_reduce(part, kBiasBlocks, kGates, grads + o.gbi, 0, kGates, st));
+    k_colsum_bf16<<<kBiasBlocks, 256, 0, st>>>(P->dgh, B, kGates, part);
+    PCHK(hipGetLastError());
+    PCHK(launch_reduce(part, kBiasBlocks, kGates, grads + o.gbh, 0, kGates, st));
+  }
+  // FC1 output gradient: dz1 = (dgi W_ih) * [h1 > 0]
+  PCHK((gemm::run<128, 128, 64, 2, 2>(LdBF16K{P->dgi, kGates, B, kGates}, LdBF16K{P->wiht, kGates, kHid, kGates},
+                                     EpiReluGradBF16{P->dz1, P->h1, kHid, kHid}, B, kHid, kGates, 1, st)));
+  return backward_fc1_encoder(P, params, crop, P->rows, B, grads, st);
 }
 
 }  // extern "C"

@@ -34,14 +34,20 @@ using gemm::f2bf;
 
 constexpr int kCrop = 64, kA1 = 32, kA2 = 16, kC1 = 16, kC2 = 32, kHid = 256, kFeat = kC2 * kA2 * kA2;
 
+constexpr int kGates = 3 * kHid;   // GRU gate rows: reset, update, new
+
 struct Offsets {
   int64_t c1w, c1b, c2w, c2b, f1w, f1b, f2w, f2b, muw, mub, vw, vb, lstd, total;
+  int64_t gih, ghh, gbi, gbh;   // recurrent layout: GRU weights [768][256] and biases [768]; -1 otherwise
   int32_t k1;  // FC1 input width = 8192 + R + 12
+  int32_t recurrent;
 };
 
-inline Offsets offsets(int32_t n_scan) {
+// Flat parameter layout: the feed-forward network, or with `recurrent` the GRU in place of FC2.
+inline Offsets offsets(int32_t n_scan, bool recurrent = false) {
   Offsets o;
   o.k1 = kFeat + n_scan + 12;
+  o.recurrent = recurrent ? 1 : 0;
   int64_t p = 0;
   o.c1w = p; p += kC1 * 9;
   o.c1b = p; p += kC1;
@@ -49,8 +55,17 @@ inline Offsets offsets(int32_t n_scan) {
   o.c2b = p; p += kC2;
   o.f1w = p; p += (int64_t)kHid * o.k1;
   o.f1b = p; p += kHid;
-  o.f2w = p; p += kHid * kHid;
-  o.f2b = p; p += kHid;
+  if (recurrent) {
+    o.f2w = o.f2b = -1;
+    o.gih = p; p += (int64_t)kGates * kHid;
+    o.ghh = p; p += (int64_t)kGates * kHid;
+    o.gbi = p; p += kGates;
+    o.gbh = p; p += kGates;
+  } else {
+    o.gih = o.ghh = o.gbi = o.gbh = -1;
+    o.f2w = p; p += kHid * kHid;
+    o.f2b = p; p += kHid;
+  }
   o.muw = p; p += 2 * kHid;
   o.mub = p; p += 2;
   o.vw = p; p += kHid;
@@ -197,11 +212,13 @@ struct LossCoef {
 constexpr int kHeadPart = 512 + 2 + 256 + 1 + 2 + 256 + 4;
 constexpr int kHeadRows = 64;   // rows per workgroup (16 per wave)
 
-template <bool GRAD>
+// RECUR: the heads read the GRU state directly (no ReLU) and, with GRAD, write its gradient dh (FP32)
+// to dh_out instead of the masked BF16 dz2.
+template <bool GRAD, bool RECUR = false>
 __global__ __launch_bounds__(256) void k_heads(const float* prm, Offsets o, const float* z2, int B, float* mu_out,
                                                float* v_out, const float* act, const float* old_logp,
                                                const float* adv, const float* ret, const int32_t* rows, LossCoef lc,
-                                               uint16_t* dz2, float* part) {
+                                               uint16_t* dz2, float* part, float* dh_out = nullptr) {
   __shared__ float acc[4][kHeadPart];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   float wmu0[4], wmu1[4], wv[4];
@@ -224,7 +241,7 @@ __global__ __launch_bounds__(256) void k_heads(const float* prm, Offsets o, cons
     float h[4], s0 = 0, s1 = 0, sv = 0;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      h[e] = fmaxf(z[e], 0.0f);
+      h[e] = RECUR ? z[e] : fmaxf(z[e], 0.0f);
       s0 += wmu0[e] * h[e];
       s1 += wmu1[e] * h[e];
       sv += wv[e] * h[e];
@@ -268,18 +285,23 @@ __global__ __launch_bounds__(256) void k_heads(const float* prm, Offsets o, cons
       lval += (val - ret[sr]) * (val - ret[sr]) * lc.inv_b;
     }
     uint32_t dzp[2];
+    float dhv[4];
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       gw0[e] += dm0 * h[e];
       gw1[e] += dm1 * h[e];
       gwv[e] += dV * h[e];
       const float dh = dm0 * wmu0[e] + dm1 * wmu1[e] + dV * wv[e];
+      dhv[e] = dh;
       const float dz = z[e] > 0.0f ? dh : 0.0f;
       const uint32_t bits = f2bf(dz);
       gb2[e] += bf2f((uint16_t)bits);  // the bias gradient sums the same BF16 values the GEMMs consume
       if (e & 1) dzp[e >> 1] |= bits << 16; else dzp[e >> 1] = bits;
     }
-    *reinterpret_cast<uint2*>(dz2 + (int64_t)row * kHid + lane * 4) = make_uint2(dzp[0], dzp[1]);
+    if (RECUR)
+      *reinterpret_cast<float4*>(dh_out + (int64_t)row * kHid + lane * 4) = make_float4(dhv[0], dhv[1], dhv[2], dhv[3]);
+    else
+      *reinterpret_cast<uint2*>(dz2 + (int64_t)row * kHid + lane * 4) = make_uint2(dzp[0], dzp[1]);
   }
   if (!GRAD) return;
   float* a = acc[wave];
@@ -444,7 +466,7 @@ __global__ void k_scatter_heads(const float* hs, float* grad, Offsets o, float* 
     else if (i < 770) grad[o.vw + (i - 514)] += s;
     else if (i == 770) grad[o.vb] += s;
     else if (i < 773) grad[o.lstd + (i - 771)] += s - c_e;  // entropy term: -c_e dH/dlog_std
-    else if (i < 1029) grad[o.f2b + (i - 773)] += s;
+    else if (i < 1029) { if (o.f2b >= 0) grad[o.f2b + (i - 773)] += s; }
     else if (i == 1029) loss[1] = s;
     else if (i == 1030) loss[2] = s;
   }

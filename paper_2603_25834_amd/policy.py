@@ -30,13 +30,13 @@ def num_params(n_scan: int) -> int:
 
 class Policy:
     def __init__(self, n_scan: int = 360, max_batch: int = 16384, clip_eps: float = 0.2, c_value: float = 0.5,
-                 c_entropy: float = 0.005):
-        self.n_scan, self.max_batch = n_scan, max_batch
-        self.cfg = PolicyConfig(n_scan, max_batch, clip_eps, c_value, c_entropy)
+                 c_entropy: float = 0.005, recurrent: bool = False):
+        self.n_scan, self.max_batch, self.recurrent = n_scan, max_batch, bool(recurrent)
+        self.cfg = PolicyConfig(n_scan, max_batch, clip_eps, c_value, c_entropy, int(self.recurrent))
         h = ctypes.c_void_p()
         check(lib().aslam_policy_create(ctypes.byref(self.cfg), ctypes.byref(h)))
         self.h = h
-        self.n_params = num_params(n_scan)
+        self.n_params = int(lib().aslam_policy_param_count(ctypes.byref(self.cfg)))
 
     def close(self):
         if getattr(self, "h", None):
@@ -82,6 +82,41 @@ class Policy:
         check(lib().aslam_policy_act(self.h, _p(params), int(bool(prepared)), _p(crop), _p(scan), _p(state), B,
                                      _p(eps), _p(mu), _p(value), _p(act), _p(logp), _stream()))
         return value, act, logp
+
+    def act_rnn(self, params, crop, scan, state, h_in, first, eps, value=None, act=None, logp=None, h_out=None,
+                mu=None, prepared=False):
+        """Recurrent rollout step: the GRU state h_in [B, 256] (zeroed where first [B] uint8 is set, may be
+        None) advances to h_out (may be h_in itself); value, action and log-prob as act()."""
+        B = self._check_obs(params, crop, scan, state)
+        assert h_in.dtype == torch.float32 and tuple(h_in.shape) == (B, 256)
+        assert eps.dtype == torch.float32 and tuple(eps.shape) == (B, 2)
+        if first is not None:
+            assert first.dtype == torch.uint8 and first.numel() == B
+        value = torch.empty(B, device=crop.device) if value is None else value
+        act = torch.empty((B, 2), device=crop.device) if act is None else act
+        logp = torch.empty(B, device=crop.device) if logp is None else logp
+        h_out = torch.empty_like(h_in) if h_out is None else h_out
+        check(lib().aslam_policy_act_rnn(self.h, _p(params), int(bool(prepared)), _p(crop), _p(scan), _p(state), B,
+                                         _p(h_in), _p(first), _p(eps), _p(mu), _p(value), _p(act), _p(logp),
+                                         _p(h_out), _stream()))
+        return value, act, logp, h_out
+
+    def backward_seq(self, params, crop, scan, state, h0, first, act, old_logp, adv, ret, robots, grads, loss=None):
+        """Recurrent PPO loss gradient over the sequences of `robots` (int32 [nb]) in time-major rollout
+        arrays [T, N, ...]; h0 [N, 256] the state entering step 0, first [T, N] episode starts."""
+        T, N = crop.shape[0], crop.shape[1]
+        assert crop.dtype == torch.int16 and tuple(crop.shape[2:]) == (64, 64)
+        assert tuple(scan.shape) == (T, N, self.n_scan) and tuple(state.shape) == (T, N, 12)
+        assert tuple(h0.shape) == (N, 256) and first.dtype == torch.uint8 and tuple(first.shape) == (T, N)
+        for t_, shp in ((act, (T, N, 2)), (old_logp, (T, N)), (adv, (T, N)), (ret, (T, N))):
+            assert t_.dtype == torch.float32 and tuple(t_.shape) == shp
+        assert robots.dtype == torch.int32 and robots.dim() == 1
+        assert grads.dtype == torch.float32 and grads.numel() == self.n_params
+        loss = torch.empty(4, device=crop.device) if loss is None else loss
+        check(lib().aslam_policy_backward_seq(self.h, _p(params), _p(crop), _p(scan), _p(state), T, N, _p(robots),
+                                              robots.numel(), _p(h0), _p(first), _p(act), _p(old_logp), _p(adv),
+                                              _p(ret), _p(grads), _p(loss), _stream()))
+        return loss
 
     def backward(self, params, crop, scan, state, act, old_logp, adv, ret, grads, loss=None, rows=None):
         """Adds the PPO loss gradient of this minibatch to `grads`; returns loss terms [4].  With `rows`
