@@ -11,9 +11,15 @@ batched POMDP step of Sec. III-B.  One iteration:
       the minibatch's rows of the rollout arrays, read in place (activations recomputed from the stored
       inputs) -> Adam.
 
-Every stage runs in the library's kernels; torch provides device memory, the stream and two
-`zero_()` fills (the gradient accumulator).  Random draws (odometry noise, action noise, minibatch
-permutations) are passed in, so an iteration is deterministic given its inputs.
+With `recurrent` the policy is the GRU actor-critic of Sec. III-F ("Recurrent Layer"): the rollout
+carries each robot's GRU state from step to step (zeroed at the first step of an episode), and the
+update takes minibatches of whole robot sequences (all T steps of a shuffled set of robots) through
+backpropagation through time, starting from the state each robot had entering the rollout.
+
+Every stage runs in the library's kernels; torch provides device memory, the stream, the
+gradient accumulator's `zero_()` fill and a few small device copies (recurrent bookkeeping).
+Random draws (odometry noise, action noise, minibatch permutations) are passed in, so an iteration
+is deterministic given its inputs.
 """
 from __future__ import annotations
 
@@ -26,16 +32,24 @@ from .policy import Policy, adam, gae
 class PPOTrainer:
     def __init__(self, env, world: torch.Tensor, start: torch.Tensor, params: torch.Tensor, T: int = 24,
                  epochs: int = 4, minibatch: int = 16384, lr: float = 3e-4, gamma: float = 0.99, lam: float = 0.95,
-                 seed: int = 0, crop: int = 64):
+                 seed: int = 0, crop: int = 64, recurrent: bool = False):
         self.env, self.world, self.start = env, world, start
         self.n, self.R = env.n, env.R
         self.T, self.epochs = T, epochs
+        self.recurrent = bool(recurrent)
         self.S = T * self.n
-        self.n_mb = max(1, -(-self.S // minibatch))
-        self.mb = -(-self.S // self.n_mb)              # equal minibatches of at most `minibatch`
+        if self.recurrent:
+            # minibatches of whole sequences: equal sets of at most minibatch // T robots
+            self.n_mb = max(1, -(-self.n // max(1, minibatch // T)))
+            self.mb = -(-self.n // self.n_mb)          # robots per minibatch
+            max_b = max(self.mb * T, self.n)
+        else:
+            self.n_mb = max(1, -(-self.S // minibatch))
+            self.mb = -(-self.S // self.n_mb)          # equal minibatches of at most `minibatch`
+            max_b = max(self.mb, self.n)
         self.lr, self.gamma, self.lam = lr, gamma, lam
         dev = params.device
-        self.policy = Policy(self.R, max_batch=max(self.mb, self.n))
+        self.policy = Policy(self.R, max_batch=max_b, recurrent=self.recurrent)
         self.params = params
         self.grads = torch.zeros_like(params)
         self.m = torch.zeros_like(params)
@@ -55,20 +69,29 @@ class PPOTrainer:
         self.done = torch.zeros((T, n), dtype=torch.uint8, device=dev)
         self.ranges = torch.zeros((n, R), device=dev)
         self.loss = torch.zeros(4, device=dev)
+        if self.recurrent:
+            self.h = torch.zeros((n, 256), device=dev)            # GRU state after the last step
+            self.h0 = torch.zeros((n, 256), device=dev)           # state entering step 0 of this rollout
+            self.h_boot = torch.zeros((n, 256), device=dev)       # the bootstrap step's state (unused)
+            self.first = torch.ones((T + 1, n), dtype=torch.uint8, device=dev)   # episode starts per step
 
     def draws(self, iterations: int, seed: int):
         """Seeded synthetic randomness for `iterations` iterations: step noise [I,T,n,G], action noise
-        [I,T,n,2] and one permutation of the T*n samples per epoch [I,epochs,T*n] (int32)."""
+        [I,T,n,2] and one permutation per epoch [I,epochs,*] (int32) of the T*n samples, or with a
+        recurrent policy of the n robots."""
         rng = np.random.default_rng([seed, 77])
         I, T, n = iterations, self.T, self.n
         dev = self.params.device
         noise = torch.from_numpy(rng.standard_normal((I, T, n, self.env.G), dtype=np.float32)).to(dev)
         eps = torch.from_numpy(rng.standard_normal((I, T, n, 2), dtype=np.float32)).to(dev)
-        perm = np.stack([np.stack([rng.permutation(self.S) for _ in range(self.epochs)]) for _ in range(I)])
+        units = n if self.recurrent else self.S
+        perm = np.stack([np.stack([rng.permutation(units) for _ in range(self.epochs)]) for _ in range(I)])
         return noise, eps, torch.from_numpy(perm.astype(np.int32)).to(dev)
 
     def iteration(self, noise: torch.Tensor, eps: torch.Tensor, perm: torch.Tensor) -> None:
         """One rollout of T steps and `epochs` update passes (all launches on the current stream)."""
+        if self.recurrent:
+            return self._iteration_recurrent(noise, eps, perm)
         env, pol, p = self.env, self.policy, self.params
         pol.prepare(p)   # the parameters are fixed during the rollout
         for t in range(self.T):
@@ -99,5 +122,32 @@ class PPOTrainer:
                 # the minibatch is the rows idx of the rollout arrays: the kernels read them in place
                 pol.backward(p, flat["crop"], flat["scan"], flat["state"], flat["act"], flat["logp"], flat["adv"],
                              flat["ret"], self.grads, self.loss, rows=idx)
+                self.step_count += 1
+                adam(p, self.grads, self.m, self.v, self.step_count, lr=self.lr)
+
+    def _iteration_recurrent(self, noise: torch.Tensor, eps: torch.Tensor, perm: torch.Tensor) -> None:
+        env, pol, p, T = self.env, self.policy, self.params, self.T
+        pol.prepare(p)
+        self.h0.copy_(self.h)
+        self.first[0].copy_(self.first[T])     # episode starts carried over from the last rollout's end
+        for t in range(T):
+            env.observe(self.ranges, self.crop[t], self.scan[t], self.state[t])
+            pol.act_rnn(p, self.crop[t], self.scan[t], self.state[t], self.h, self.first[t], eps[t], self.value[t],
+                        self.act[t], self.logp[t], h_out=self.h, prepared=True)
+            env.step(self.act[t], noise[t], self.ranges, self.reward[t], self.done[t])
+            env.reset(self.world, self.start, mask=self.done[t])
+            self.first[t + 1].copy_(self.done[t])
+        env.observe(self.ranges, self.crop[T], self.scan[T], self.state[T])
+        pol.act_rnn(p, self.crop[T], self.scan[T], self.state[T], self.h, self.first[T], eps[T - 1], self.value[T],
+                    self.act_boot, self.logp_boot, h_out=self.h_boot, prepared=True)
+        adv, ret = gae(self.reward, self.value[:T].contiguous(), self.done, self.value[T], self.gamma, self.lam)
+        first = self.first[:T]
+        for e in range(self.epochs):
+            for k in range(self.n_mb):
+                lo = k * self.mb
+                robots = perm[e, lo:min(self.n, lo + self.mb)]
+                self.grads.zero_()
+                pol.backward_seq(p, self.crop[:T], self.scan[:T], self.state[:T], self.h0, first, self.act,
+                                 self.logp, adv, ret, robots, self.grads, self.loss)
                 self.step_count += 1
                 adam(p, self.grads, self.m, self.v, self.step_count, lr=self.lr)

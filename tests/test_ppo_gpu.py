@@ -15,23 +15,28 @@ from paper_2603_25834_amd.ppo import PPOTrainer
 pytestmark = pytest.mark.gpu
 
 
-def _trainer(seed):
-    w = synth.WORKLOADS["small_16x64"]
-    b = synth.make_batch("small_16x64", seed)
+def _trainer(seed, recurrent=False, name="small_16x64"):
+    w = synth.WORKLOADS[name]
+    b = synth.make_batch(name, seed, np.arange(16) if w.n_robots > 16 else None)
     env = Env(w.params(), b.sides)
     env.set_exec(form=1, threads=128)
     world = torch.from_numpy(b.world.view(np.int32).copy()).cuda()
     start = torch.from_numpy(b.start).cuda()
     env.reset(world, start)
-    params = torch.from_numpy(synth.init_policy_params(w.n_rays, seed)).cuda()
-    tr = PPOTrainer(env, world, start, params, T=6, epochs=2, minibatch=40, lr=1e-3)
+    init = synth.init_recurrent_params if recurrent else synth.init_policy_params
+    params = torch.from_numpy(init(w.n_rays, seed)).cuda()
+    tr = PPOTrainer(env, world, start, params, T=6, epochs=2, minibatch=40, lr=1e-3, recurrent=recurrent)
     return tr, params.clone()
 
 
-def test_iteration_runs_and_is_deterministic():
+@pytest.mark.parametrize("recurrent,name", [(False, "small_16x64"), (True, "paper_sensor_750x256")],
+                         ids=["mlp", "gru_paper_mode"])
+def test_iteration_runs_and_is_deterministic(recurrent, name):
+    """The feed-forward policy on the small workload, and the GRU policy in the paper's sensor / reward
+    mode on 16 robots of the 750-robot scene (minibatches of whole robot sequences, BPTT)."""
     finals = []
     for _ in range(2):
-        tr, p0 = _trainer(3)
+        tr, p0 = _trainer(3, recurrent, name)
         noise, eps, perm = tr.draws(2, seed=5)
         for i in range(2):
             tr.iteration(noise[i], eps[i], perm[i])
