@@ -301,15 +301,19 @@ def cpu_baseline(name: str, seed: int, robots: int, steps: int) -> dict:
             "coded_cells_per_robot_step": float(cnt[2]) / rs, "world_cells_read_per_robot_step": float(cnt[3]) / rs}
 
 
-def train_loop(wb, horizon: int, epochs: int, minibatch: int, warmup: int, iters: int, seed: int) -> dict:
-    """Time `iters` PPO training iterations on the workbench's env after `warmup` untimed ones."""
+def train_loop(wb, horizon: int, epochs: int, minibatch: int, warmup: int, iters: int, seed: int,
+               recurrent: bool = False) -> dict:
+    """Time `iters` PPO training iterations on the workbench's env after `warmup` untimed ones (with
+    `recurrent`, the GRU policy and sequence minibatches)."""
     import torch
 
     from paper_2603_25834_amd import synth
     from paper_2603_25834_amd.ppo import PPOTrainer
     wb.env.reset(wb.world, wb.start)
-    params = torch.from_numpy(synth.init_policy_params(wb.R, seed)).cuda()
-    tr = PPOTrainer(wb.env, wb.world, wb.start, params, T=horizon, epochs=epochs, minibatch=minibatch)
+    init = synth.init_recurrent_params if recurrent else synth.init_policy_params
+    params = torch.from_numpy(init(wb.R, seed)).cuda()
+    tr = PPOTrainer(wb.env, wb.world, wb.start, params, T=horizon, epochs=epochs, minibatch=minibatch,
+                    recurrent=recurrent)
     noise, eps, perm = tr.draws(warmup + iters, seed)
     for i in range(warmup):
         tr.iteration(noise[i], eps[i], perm[i])
@@ -349,9 +353,9 @@ def autotune_forms(wb) -> tuple:
     return fused, plain, summary
 
 
-def side_workload(name: str, args, fused: dict, plain: dict) -> dict:
+def side_workload(name: str, args, fused: dict, plain: dict, recurrent: bool = False) -> dict:
     """Env-step timings (fused and plain, each autotuned on this batch) and a few training iterations of a
-    workload besides the headline one."""
+    workload besides the headline one (with `recurrent`, also with the GRU policy)."""
     import torch
     print(f"[bench] {name}: setting up", file=sys.stderr, flush=True)
     wb2 = Workbench(name, args.seed, args.env_warmup + args.secondary_steps, fused)
@@ -375,6 +379,12 @@ def side_workload(name: str, args, fused: dict, plain: dict) -> dict:
         l2 = train_loop(wb2, args.horizon, args.epochs, args.minibatch, 1, args.secondary_iters, args.seed)
         res["training_loop"] = l2
         print(f"[bench] {name}: training iteration {l2['ms_per_iteration']:.2f} ms", file=sys.stderr, flush=True)
+        if recurrent:
+            l3 = train_loop(wb2, args.horizon, args.epochs, args.minibatch, 1, args.secondary_iters, args.seed,
+                            recurrent=True)
+            res["training_loop_gru"] = l3
+            print(f"[bench] {name}: training iteration with the GRU policy {l3['ms_per_iteration']:.2f} ms",
+                  file=sys.stderr, flush=True)
     del wb2
     torch.cuda.empty_cache()
     return res
@@ -515,7 +525,7 @@ def main():
         torch.cuda.empty_cache()
     for key, name in (("secondary", args.secondary), ("paper_mode", args.paper_mode)):
         if name:
-            out[key] = side_workload(name, args, fused, plain)
+            out[key] = side_workload(name, args, fused, plain, recurrent=key == "paper_mode")
     if not args.no_cpu:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_full_loop(args.workload, args.seed, args.cpu_robots, args.horizon, args.epochs)
