@@ -219,6 +219,96 @@ __global__ __launch_bounds__(256) void k_gru_fwd(GruFwdArgs a) {
   }
 }
 
+// Training forward step: as k_gru_fwd<false>, with the 256 units split over gridDim.y = 4 workgroups
+// per row tile (64 units each, 16 per wave), so a workgroup reads a quarter of the weights and a step
+// of a few hundred rows still spreads over many CUs.  Values and accumulation order per unit are
+// those of k_gru_fwd.
+constexpr int kGruSlices = 4;
+
+__global__ __launch_bounds__(256) void k_gru_fwd_train(GruFwdArgs a) {
+  __shared__ __align__(16) uint16_t s_x[kGruRows * kGruLdX];
+  __shared__ __align__(16) uint16_t s_hb[kGruRows * kGruLdX];
+  __shared__ __align__(16) float s_hp[kGruRows * kGruLdF];
+  const int row0 = blockIdx.x * kGruRows;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
+  const Offsets& o = a.o;
+  for (int g = threadIdx.x; g < kGruRows * (kHid / 8); g += 256) {
+    const int r = g / (kHid / 8), n0 = (g % (kHid / 8)) * 8;
+    const int i = row0 + r;
+    uint4 vx = make_uint4(0u, 0u, 0u, 0u);
+    float hv[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (i < a.rows) {
+      vx = *reinterpret_cast<const uint4*>(a.h1 + (a.s0 + i) * kHid + n0);
+      const bool reset = a.first && a.first[a.first_map ? a.first_map[i] : i];
+      if (!reset) {
+        const float* q = a.hp + (int64_t)(a.hp_map ? a.hp_map[i] : i) * kHid + n0;
+        const float4 lo = *reinterpret_cast<const float4*>(q), hi = *reinterpret_cast<const float4*>(q + 4);
+        hv[0] = lo.x; hv[1] = lo.y; hv[2] = lo.z; hv[3] = lo.w;
+        hv[4] = hi.x; hv[5] = hi.y; hv[6] = hi.z; hv[7] = hi.w;
+      }
+    }
+    *reinterpret_cast<uint4*>(s_x + r * kGruLdX + n0) = vx;
+    uint16_t hb[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      s_hp[r * kGruLdF + n0 + j] = hv[j];
+      hb[j] = f2bf(hv[j]);
+    }
+    *reinterpret_cast<uint4*>(s_hb + r * kGruLdX + n0) = pack8(hb);
+  }
+  __syncthreads();
+  const int64_t u = 64 * blockIdx.y + 16 * wave + lr;
+  gemm::f32x4 ar = {0.f, 0.f, 0.f, 0.f}, az = ar, an = ar, ahn = ar;
+#pragma unroll
+  for (int k0 = 0; k0 < kHid; k0 += 32) {
+    const int kk = k0 + 8 * lg;
+    const auto ax = __builtin_bit_cast(gemm::bf16x8, *reinterpret_cast<const uint4*>(s_x + lr * kGruLdX + kk));
+    ar = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+        ax, __builtin_bit_cast(gemm::bf16x8, *reinterpret_cast<const uint4*>(a.wih + u * kHid + kk)), ar, 0, 0, 0);
+    az = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+        ax, __builtin_bit_cast(gemm::bf16x8, *reinterpret_cast<const uint4*>(a.wih + (u + kHid) * kHid + kk)), az,
+        0, 0, 0);
+    an = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+        ax, __builtin_bit_cast(gemm::bf16x8, *reinterpret_cast<const uint4*>(a.wih + (u + 2 * kHid) * kHid + kk)),
+        an, 0, 0, 0);
+  }
+#pragma unroll
+  for (int k0 = 0; k0 < kHid; k0 += 32) {
+    const int kk = k0 + 8 * lg;
+    const auto ah = __builtin_bit_cast(gemm::bf16x8, *reinterpret_cast<const uint4*>(s_hb + lr * kGruLdX + kk));
+    ar = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+        ah, __builtin_bit_cast(gemm::bf16x8, *reinterpret_cast<const uint4*>(a.whh + u * kHid + kk)), ar, 0, 0, 0);
+    az = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+        ah, __builtin_bit_cast(gemm::bf16x8, *reinterpret_cast<const uint4*>(a.whh + (u + kHid) * kHid + kk)), az,
+        0, 0, 0);
+    ahn = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+        ah, __builtin_bit_cast(gemm::bf16x8, *reinterpret_cast<const uint4*>(a.whh + (u + 2 * kHid) * kHid + kk)),
+        ahn, 0, 0, 0);
+  }
+  const float* bi = a.prm + o.gbi;
+  const float* bh = a.prm + o.gbh;
+  const float bir = bi[u], biz = bi[u + kHid], bin = bi[u + 2 * kHid];
+  const float bhr = bh[u], bhz = bh[u + kHid], bhn = bh[u + 2 * kHid];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int r = 4 * lg + e, i = row0 + r;
+    if (i >= a.rows) continue;
+    const float rg = sigmoidf_((ar[e] + bir) + bhr);
+    const float zg = sigmoidf_((az[e] + biz) + bhz);
+    const float ghn = ahn[e] + bhn;
+    const float ng = tanhf((an[e] + bin) + rg * ghn);
+    const float hpv = s_hp[r * kGruLdF + u];
+    const int64_t q = (a.s0 + i) * kHid + u;
+    a.h_out[q] = (1.0f - zg) * ng + zg * hpv;
+    a.g_r[q] = rg;
+    a.g_z[q] = zg;
+    a.g_n[q] = ng;
+    a.g_ghn[q] = ghn;
+    a.hp_used[q] = hpv;
+    a.hp_bf[q] = s_hb[r * kGruLdX + u];
+  }
+}
+
 // One step of backpropagation through time, rows s0 + i (i < rows) of step t:
 //   dh = dh_head + dh_next (the gradient reaching h_t from the heads and from step t + 1),
 //   gate pre-activation gradients dgi = [dr', dz', dn'], dgh = [dr', dz', dn' r] (BF16, the operands
@@ -238,6 +328,8 @@ struct GruBwdArgs {
   float* dh_prev;                  // [rows][256]
 };
 
+// gridDim.y = kGruSlices workgroups share a row tile: each forms the tile's gate gradients (slice 0
+// alone writes them out) and the state gradient for its 64 columns.
 __global__ __launch_bounds__(256) void k_gru_bwd_step(GruBwdArgs a) {
   __shared__ __align__(16) uint16_t s_g[kGruRows * kGruLdG];
   __shared__ __align__(16) float s_d[kGruRows * kGruLdF];
@@ -256,13 +348,15 @@ __global__ __launch_bounds__(256) void k_gru_bwd_step(GruBwdArgs a) {
       dr = (dn_pre * ghn) * (rg * (1.0f - rg));
       dn = dn_pre;
       dnr = dn_pre * rg;
-      const int64_t g = (a.s0 + i) * kGates + u;
-      a.dgi[g] = f2bf(dr);
-      a.dgi[g + kHid] = f2bf(dz);
-      a.dgi[g + 2 * kHid] = f2bf(dn);
-      a.dgh[g] = f2bf(dr);
-      a.dgh[g + kHid] = f2bf(dz);
-      a.dgh[g + 2 * kHid] = f2bf(dnr);
+      if (blockIdx.y == 0) {
+        const int64_t g = (a.s0 + i) * kGates + u;
+        a.dgi[g] = f2bf(dr);
+        a.dgi[g + kHid] = f2bf(dz);
+        a.dgi[g + 2 * kHid] = f2bf(dn);
+        a.dgh[g] = f2bf(dr);
+        a.dgh[g + kHid] = f2bf(dz);
+        a.dgh[g + 2 * kHid] = f2bf(dnr);
+      }
     }
     s_g[r * kGruLdG + u] = f2bf(dr);
     s_g[r * kGruLdG + u + kHid] = f2bf(dz);
@@ -270,32 +364,23 @@ __global__ __launch_bounds__(256) void k_gru_bwd_step(GruBwdArgs a) {
     s_d[r * kGruLdF + u] = dd;
   }
   __syncthreads();
-  // dgh [16 x 768] x W_hh [768 x 256]: wave w owns columns 64 w .. 64 w + 63
+  // dgh [16 x 768] x W_hh [768 x 256]: this workgroup's columns 64 y .. 64 y + 63, 16 per wave
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
-  gemm::f32x4 acc[4];
-#pragma unroll
-  for (int j = 0; j < 4; ++j) acc[j] = gemm::f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 4
+  const int64_t n = 64 * blockIdx.y + 16 * wave + lr;
+  gemm::f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 8
   for (int k0 = 0; k0 < kGates; k0 += 32) {
     const int kk = k0 + 8 * lg;
     const gemm::bf16x8 ag = __builtin_bit_cast(gemm::bf16x8, *reinterpret_cast<const uint4*>(s_g + lr * kGruLdG + kk));
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int64_t n = 64 * wave + 16 * j + lr;
-      const auto wb = __builtin_bit_cast(gemm::bf16x8, *reinterpret_cast<const uint4*>(a.whht + n * kGates + kk));
-      acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ag, wb, acc[j], 0, 0, 0);
-    }
+    const auto wb = __builtin_bit_cast(gemm::bf16x8, *reinterpret_cast<const uint4*>(a.whht + n * kGates + kk));
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ag, wb, acc, 0, 0, 0);
   }
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int n = 64 * wave + 16 * j + lr;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int r = 4 * lg + e, i = row0 + r;
-      if (i >= a.rows) continue;
-      const bool reset = a.first && a.first[a.first_map ? a.first_map[i] : i];
-      a.dh_prev[(int64_t)i * kHid + n] = reset ? 0.0f : s_d[r * kGruLdF + n] + acc[j][e];
-    }
+  for (int e = 0; e < 4; ++e) {
+    const int r = 4 * lg + e, i = row0 + r;
+    if (i >= a.rows) continue;
+    const bool reset = a.first && a.first[a.first_map ? a.first_map[i] : i];
+    a.dh_prev[(int64_t)i * kHid + n] = reset ? 0.0f : s_d[r * kGruLdF + n] + acc[e];
   }
 }
 

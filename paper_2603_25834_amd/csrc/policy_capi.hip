@@ -503,7 +503,7 @@ int aslam_policy_backward_seq(aslam_policy* P, const float* params, const int16_
     PCHK(hipGetLastError());
   }
   // the GRU over the T steps, keeping what the backward reads
-  const int grid = (nb + kGruRows - 1) / kGruRows;
+  const dim3 grid((nb + kGruRows - 1) / kGruRows, kGruSlices);
   for (int t = 0; t < T; ++t) {
     GruFwdArgs a{};
     a.prm = params; a.o = o; a.rows = nb; a.s0 = (int64_t)t * nb;
@@ -514,7 +514,7 @@ int aslam_policy_backward_seq(aslam_policy* P, const float* params, const int16_
     a.first = first + (int64_t)t * N; a.first_map = robots;
     a.h_out = P->hst;
     a.g_r = P->g_r; a.g_z = P->g_z; a.g_n = P->g_n; a.g_ghn = P->g_ghn; a.hp_used = P->hp_used; a.hp_bf = P->hp_bf;
-    k_gru_fwd<false><<<grid, 256, 0, st>>>(a);
+    k_gru_fwd_train<<<grid, 256, 0, st>>>(a);
     PCHK(hipGetLastError());
   }
   // heads + loss on every sample -> dh (FP32), head / log-std partial sums
