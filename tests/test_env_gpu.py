@@ -174,3 +174,44 @@ def test_graph_replay_matches_eager(form):
         for key in ("pose", "est", "cov", "belief", "hq", "rho", "hitc"):
             assert np.array_equal(ge[key], gg[key]), (rep, key)
         del junk
+
+
+@pytest.mark.parametrize("name,steps,threads", [("paper_750x256", 60, 512), ("ragged_4096", 20, 512)],
+                         ids=["paper_750x256", "ragged_4096"])
+def test_full_batch_sampled(name, steps, threads):
+    """The whole batch stepped in the fused launch the benchmark times (512 threads per robot, steps
+    captured in a HIP graph); 16 sampled robots re-run alone by the oracle (robots are independent, so
+    a sample sees the same inputs) and compared bit for bit: ranges, rewards, poses, covariances,
+    beliefs and entropies."""
+    import torch
+    from oracle import oracle as O
+    from paper_2603_25834_amd import _lib
+    full = Pair(name, 8, exec_kw=dict(form=1, threads=threads), steps=steps, oracle=False)
+    n = full.n
+    pick = np.unique(np.linspace(3, n - 1, 16).astype(np.int64))
+    b = synth.make_batch(name, 8, pick)
+    orc = O.OracleEnv(full.p, b.sides, b.world, b.world_off)
+    orc.reset(b.start)
+    A = synth.actions(name, 8, steps, pick)
+    G = synth.noise(name, 8, steps, pick)
+    rng_ = torch.zeros((steps, n, full.R), device="cuda")
+    rew = torch.zeros((steps, n), device="cuda")
+    dn = torch.zeros((steps, n), dtype=torch.uint8, device="cuda")
+    full.env.graph_build(steps, full.dA, 2 * n, full.dG, full.env.G * n, rng_, n * full.R, rew, n, dn, n)
+    full.env.graph_launch()
+    torch.cuda.synchronize()
+    say(f"[full] {name}: {steps} graph steps of {n} robots, sample {len(pick)}")
+    gr, gw, gd = rng_.cpu().numpy(), rew.cpu().numpy(), dn.cpu().numpy()
+    for t in range(steps):
+        o = orc.step(A[t], G[t])
+        assert np.array_equal(gr[t][pick], o.ranges), t
+        assert np.all(np.abs(gw[t][pick] - o.reward) <= 1e-4 * np.maximum(1.0, np.abs(o.reward))), t
+        assert np.array_equal(gd[t][pick], o.done), t
+    e = full.env
+    assert np.array_equal(e.read(_lib.FIELD_POSE).cpu().numpy()[pick].view(np.int32), orc.pose.view(np.int32))
+    assert np.array_equal(e.read(_lib.FIELD_COV).cpu().numpy()[pick].view(np.int32), orc.cov.view(np.int32))
+    assert np.array_equal(e.read(_lib.FIELD_ENTROPY_Q).cpu().numpy()[pick], orc.h_q)
+    bel = e.read(_lib.FIELD_BELIEF).cpu().numpy()
+    offs = np.concatenate([[0], np.cumsum(full.b.sides.astype(np.int64) ** 2)])
+    got = np.concatenate([bel[offs[i]:offs[i + 1]] for i in pick])
+    assert np.array_equal(got, orc.belief)
