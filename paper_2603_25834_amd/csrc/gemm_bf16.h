@@ -84,9 +84,61 @@ struct Cfg {
 // kMajor: register p holds vector v = tid + 256 p = (row v / (BK/8), k-chunk v % (BK/8)).
 // !kMajor: registers 2q, 2q + 1 hold pair w = tid + 256 q = (k = 2 (w / (ROWS/8)), row-chunk w % (ROWS/8))
 // at k and k + 1 (consecutive lanes read consecutive row-chunks of the same source rows).
+// Element offsets, from the tile origin, of the vectors fetch_tile loads into this thread's registers
+// (the same assignment as fetch_tile); used by the unchecked path for tiles that lie wholly inside
+// a plain strided matrix (loader fields p, ld, rows, cols).
 template <class L, int ROWS, int BK, int P>
-__device__ __forceinline__ void fetch_tile(const L& ld, int row0, int k0, uint4 (&regs)[P]) {
+__device__ __forceinline__ void tile_offsets(const L& ld, int64_t (&off)[P]) {
   constexpr int V = ROWS * BK / 8;
+  if (L::kMajor) {
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      const int v = threadIdx.x + p * 256;
+      const int i = (V % 256 == 0 || v < V) ? v / (BK / 8) : 0, kq = v % (BK / 8);
+      off[p] = (int64_t)i * ld.ld + kq * 8;
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < P / 2; ++q) {
+      const int w = threadIdx.x + q * 256;
+      const int k = 2 * (w / (ROWS / 8)), iq = w % (ROWS / 8);
+      const int kk = (V / 2 % 256 == 0 || w < V / 2) ? k : 0;
+      off[2 * q] = (int64_t)kk * ld.ld + iq * 8;
+      off[2 * q + 1] = (int64_t)(kk + 1) * ld.ld + iq * 8;
+    }
+  }
+}
+
+// The tile at (row0, k0) lies wholly inside the matrix and its rows start on 16-byte boundaries.
+template <class L, int ROWS, int BK>
+__device__ __forceinline__ bool tile_interior(const L& ld, int row0, int k0) {
+  return row0 + ROWS <= ld.rows && k0 + BK <= ld.cols && (ld.ld & 7) == 0 &&
+         (reinterpret_cast<uintptr_t>(ld.p) & 15) == 0;
+}
+
+template <class L, int ROWS, int BK, int P>
+__device__ __forceinline__ void fetch_tile(const L& ld, int row0, int k0, uint4 (&regs)[P], const int64_t (&off)[P]) {
+  constexpr int V = ROWS * BK / 8;
+  if (tile_interior<L, ROWS, BK>(ld, row0, k0)) {
+    const uint16_t* base = L::kMajor ? ld.p + (int64_t)row0 * ld.ld + k0 : ld.p + (int64_t)k0 * ld.ld + row0;
+    if (L::kMajor) {
+#pragma unroll
+      for (int p = 0; p < P; ++p) {
+        const int v = threadIdx.x + p * 256;
+        if (V % 256 == 0 || v < V) regs[p] = *reinterpret_cast<const uint4*>(base + off[p]);
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < P / 2; ++q) {
+        const int w = threadIdx.x + q * 256;
+        if (V / 2 % 256 == 0 || w < V / 2) {
+          regs[2 * q] = *reinterpret_cast<const uint4*>(base + off[2 * q]);
+          regs[2 * q + 1] = *reinterpret_cast<const uint4*>(base + off[2 * q + 1]);
+        }
+      }
+    }
+    return;
+  }
   if (L::kMajor) {
 #pragma unroll
     for (int p = 0; p < P; ++p) {
@@ -184,10 +236,13 @@ __global__ __launch_bounds__(256) void k_gemm(LA la, LB lb, EPI epi, int M, int 
     }
   }
   uint4 ra[C::PA], rb[C::PB];
+  int64_t oa[C::PA], ob[C::PB];
+  tile_offsets<LA, BM, BK>(la, oa);
+  tile_offsets<LB, BN, BK>(lb, ob);
   const int nsteps = (ke - kb + BK - 1) / BK;
   if (nsteps > 0) {
-    fetch_tile<LA, BM, BK>(la, m_blk, kb, ra);
-    fetch_tile<LB, BN, BK>(lb, n_blk, kb, rb);
+    fetch_tile<LA, BM, BK>(la, m_blk, kb, ra, oa);
+    fetch_tile<LB, BN, BK>(lb, n_blk, kb, rb, ob);
     store_tile<LA, BM, BK>(sA, ra);
     store_tile<LB, BN, BK>(sB, rb);
   }
@@ -196,8 +251,8 @@ __global__ __launch_bounds__(256) void k_gemm(LA la, LB lb, EPI epi, int M, int 
     const int buf = t & 1;
     const bool more = t + 1 < nsteps;
     if (more) {
-      fetch_tile<LA, BM, BK>(la, m_blk, kb + (t + 1) * BK, ra);
-      fetch_tile<LB, BN, BK>(lb, n_blk, kb + (t + 1) * BK, rb);
+      fetch_tile<LA, BM, BK>(la, m_blk, kb + (t + 1) * BK, ra, oa);
+      fetch_tile<LB, BN, BK>(lb, n_blk, kb + (t + 1) * BK, rb, ob);
     }
     const uint16_t* a_st = sA + buf * SA::kElems;
     const uint16_t* b_st = sB + buf * SB::kElems;
