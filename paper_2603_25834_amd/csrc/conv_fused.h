@@ -137,23 +137,32 @@ __device__ __forceinline__ void store_crop(const CropRegs<NT>& r, uint16_t* s_cr
   }
 }
 
-// conv1 + ReLU of the staged crop into s_a1 (pixel (y, x) at a1_slot(y, x) * 16).
+// conv1 + ReLU of the staged crop into s_a1 (pixel (y, x) at a1_slot(y, x) * 16): 64 tiles of 16
+// pixels, 16 per wave, taken four at a time so that their operand reads are in flight together.
 __device__ __forceinline__ void conv1_lds(const uint16_t* s_crop, uint16_t* s_a1, const bf16x8& w1f,
                                           const float b1[4], int wave, int lr, int lg) {
-  for (int t = wave; t < kA1 * kA1 / 16; t += 4) {
-    const int px = t * 16 + lr, y = px >> 5, x = px & 31;
-    uint4 u = make_uint4(0u, 0u, 0u, 0u);
-    if (lg < 2) {
-      const uint16_t* q = s_crop + ((y + lg) * kBlk + x) * 4;
-      const uint2 a = *reinterpret_cast<const uint2*>(q);
-      const uint2 c = *reinterpret_cast<const uint2*>(q + 4);
-      u = make_uint4(a.x, a.y, c.x, c.y);
+  for (int t0 = wave; t0 < kA1 * kA1 / 16; t0 += 16) {
+    uint4 u[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int px = (t0 + 4 * i) * 16 + lr, y = px >> 5, x = px & 31;
+      u[i] = make_uint4(0u, 0u, 0u, 0u);
+      if (lg < 2) {
+        const uint16_t* q = s_crop + ((y + lg) * kBlk + x) * 4;
+        const uint2 a = *reinterpret_cast<const uint2*>(q);
+        const uint2 c = *reinterpret_cast<const uint2*>(q + 4);
+        u[i] = make_uint4(a.x, a.y, c.x, c.y);
+      }
     }
-    const f32x4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1f, __builtin_bit_cast(bf16x8, u),
-                                                             f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
-    const uint32_t lo = pack_bf16x2(fmaxf(acc[0] + b1[0], 0.0f), fmaxf(acc[1] + b1[1], 0.0f));
-    const uint32_t hi = pack_bf16x2(fmaxf(acc[2] + b1[2], 0.0f), fmaxf(acc[3] + b1[3], 0.0f));
-    *reinterpret_cast<uint2*>(s_a1 + a1_slot(y, x) * kC1 + 4 * lg) = make_uint2(lo, hi);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int px = (t0 + 4 * i) * 16 + lr, y = px >> 5, x = px & 31;
+      const f32x4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1f, __builtin_bit_cast(bf16x8, u[i]),
+                                                               f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+      const uint32_t lo = pack_bf16x2(fmaxf(acc[0] + b1[0], 0.0f), fmaxf(acc[1] + b1[1], 0.0f));
+      const uint32_t hi = pack_bf16x2(fmaxf(acc[2] + b1[2], 0.0f), fmaxf(acc[3] + b1[3], 0.0f));
+      *reinterpret_cast<uint2*>(s_a1 + a1_slot(y, x) * kC1 + 4 * lg) = make_uint2(lo, hi);
+    }
   }
 }
 
@@ -171,6 +180,11 @@ __device__ __forceinline__ bf16x8 conv2_col_frag(const uint16_t* s_a1, int oy, i
 // Encoder forward: a2[b * lda2 + co*256 + oy*16 + ox] = bf16(relu(conv2(relu(conv1(crop_b))))), and
 // the rest of the FC1 input row: a2[b * lda2 + 8192 + j] = bf16(scan_b[j]), then bf16(state_b), then
 // zeros up to lda2.  Input row b is rows[b] of crop / scan / state (b itself when rows is NULL).
+// The workgroup loops over samples; the next sample's crop and the first 512 elements of its
+// scan / state tail are loaded into registers while the current one is processed, so no global read
+// is waited on inside a sample (a longer tail, R > 500, reads its remainder directly).
+constexpr int kConvFwdTailPre = 2;   // tail elements per thread held in registers
+
 __global__ __launch_bounds__(256) void k_conv_fwd(const float* prm, Offsets o, const uint4* frag,
                                                   const int16_t* crop, const float* scan, const float* state, int R,
                                                   const int32_t* rows, uint16_t* a2, int64_t lda2, int B) {
@@ -193,23 +207,38 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const float* prm, Offsets o, c
 #pragma unroll
     for (int s = 0; s < 5; ++s) w2f[nt][s] = __builtin_bit_cast(bf16x8, frag[64 * (1 + 5 * nt + s) + lane]);
   const float b2[2] = {prm[o.c2b + lr], prm[o.c2b + 16 + lr]};
+  const int tail = (int)(lda2 - kFeat);
   auto src = [&](int b) -> int64_t { return rows ? (int64_t)rows[b] : (int64_t)b; };
+  auto tail_value = [&](int64_t sb, int j) -> float {
+    return j < R ? scan[sb * R + j] : (j < R + 12 ? state[sb * 12 + (j - R)] : 0.0f);
+  };
   CropRegs<256> cr;
-  if (blockIdx.x < B) load_crop<256>(crop + src(blockIdx.x) * kCrop * kCrop, cr);
+  float tv[kConvFwdTailPre];
+  auto load_sample = [&](int b) {
+    const int64_t sb = src(b);
+    load_crop<256>(crop + sb * kCrop * kCrop, cr);
+#pragma unroll
+    for (int i = 0; i < kConvFwdTailPre; ++i) {
+      const int j = threadIdx.x + 256 * i;
+      tv[i] = j < tail ? tail_value(sb, j) : 0.0f;
+    }
+  };
+  if (blockIdx.x < B) load_sample(blockIdx.x);
   __syncthreads();
   for (int b = blockIdx.x; b < B; b += gridDim.x) {
     store_crop<256>(cr, s_crop);
-    __syncthreads();
-    // the next sample's crop is loaded while this one is processed
-    if (b + (int)gridDim.x < B) load_crop<256>(crop + src(b + gridDim.x) * kCrop * kCrop, cr);
-    conv1_lds(s_crop, s_a1, w1f, b1, wave, lr, lg);
-    const int64_t sb = src(b);
-    for (int j = threadIdx.x; j < (int)(lda2 - kFeat); j += 256) {
-      float v = 0.0f;
-      if (j < R) v = scan[sb * R + j];
-      else if (j < R + 12) v = state[sb * 12 + (j - R)];
-      a2[(int64_t)b * lda2 + kFeat + j] = j < R + 12 ? f2bf(v) : (uint16_t)0;
+    uint16_t* row = a2 + (int64_t)b * lda2 + kFeat;
+#pragma unroll
+    for (int i = 0; i < kConvFwdTailPre; ++i) {
+      const int j = threadIdx.x + 256 * i;
+      if (j < tail) row[j] = j < R + 12 ? f2bf(tv[i]) : (uint16_t)0;
     }
+    for (int j = threadIdx.x + 256 * kConvFwdTailPre; j < tail; j += 256)
+      row[j] = j < R + 12 ? f2bf(tail_value(src(b), j)) : (uint16_t)0;
+    __syncthreads();
+    // the next sample's crop and tail are loaded while this one is processed
+    if (b + (int)gridDim.x < B) load_sample(b + gridDim.x);
+    conv1_lds(s_crop, s_a1, w1f, b1, wave, lr, lg);
     __syncthreads();
     for (int oy = wave; oy < kA2; oy += 4) {
       f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};

@@ -51,7 +51,9 @@ __device__ __forceinline__ uint16_t lane16(const uint4& v, int j) {
 // Out-of-range elements must read as 0.
 //
 // Epilogue contract: store8(m, n0, v, nvalid) for row m < M and the eight
-// columns n0 .. n0 + 7 (n0 multiple of 8), of which the first nvalid are < N.
+// columns n0 .. n0 + 7 (n0 multiple of 8), of which the first nvalid are < N;
+// an epilogue of split-K partial sums declares kSliced = true and provides
+// store8z(z, m, n0, v, nvalid) instead, z being the K slice of the workgroup.
 // An epilogue that reads global memory declares kPrefetch = true and provides
 // fetch(m, n0, nvalid) -> uint4 and store8_pre(m, n0, v, nvalid, fetched): the
 // engine issues those reads at kernel start, so their latency hides behind the
@@ -201,6 +203,35 @@ __device__ __forceinline__ bf16x8 load_frag(const uint16_t* s, int r, int kk) {
   return __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(s + Stage<KMAJOR, ROWS, BK>::at(r, kk)));
 }
 
+// Tile (tm, tn, tz) of the workgroup.  The dispatcher hands consecutive workgroups of a grid to the
+// eight XCDs in turn, and each XCD has its own L2, so the tiles that share an operand are given to
+// workgroups eight apart: workgroup L runs on XCD L % 8 as that XCD's (L / 8)-th, and the XCDs take
+// consecutive runs of the tile order.  That order walks groups of kGroupM tile rows: within a group,
+// the rows vary fastest and the columns next, so a B panel is read by kGroupM workgroups in a row
+// and the group's A panels stay in the XCD's L2 across all columns; the K slice varies slowest.
+constexpr int kGroupM = 8;
+
+struct TileId {
+  int tm, tn, tz;
+};
+
+__device__ __forceinline__ TileId xcd_tile() {
+  const int nx = gridDim.x, ny = gridDim.y;
+  const int64_t total = (int64_t)nx * ny * gridDim.z;
+  const int64_t L = blockIdx.x + (int64_t)nx * (blockIdx.y + (int64_t)ny * blockIdx.z);
+  const int64_t q = total >> 3, r = total & 7, xcd = L & 7, j = L >> 3;
+  const int64_t V = xcd < r ? xcd * (q + 1) + j : r * (q + 1) + (xcd - r) * q + j;
+  TileId t;
+  const int64_t plane = (int64_t)nx * ny;
+  t.tz = (int)(V / plane);
+  const int64_t w = V - (int64_t)t.tz * plane;
+  const int64_t g = w / ((int64_t)kGroupM * ny), rg = w - g * kGroupM * ny;
+  const int gm = min(kGroupM, nx - (int)g * kGroupM);
+  t.tm = (int)g * kGroupM + (int)(rg % gm);
+  t.tn = (int)(rg / gm);
+  return t;
+}
+
 template <int BM, int BN, int BK, int WM, int WN, class LA, class LB, class EPI>
 __global__ __launch_bounds__(256) void k_gemm(LA la, LB lb, EPI epi, int M, int N, int K, int k_split) {
   using C = Cfg<BM, BN, BK, WM, WN>;
@@ -213,8 +244,9 @@ __global__ __launch_bounds__(256) void k_gemm(LA la, LB lb, EPI epi, int M, int 
   uint16_t* sB = sA + 2 * SA::kElems;                         // [2][SB::kElems]
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int wm = wave / WN, wn = wave % WN;
-  const int m_blk = blockIdx.x * BM, n_blk = blockIdx.y * BN;   // M tiles on x (up to 2^31 - 1)
-  const int kb = blockIdx.z * k_split;
+  const TileId tile = xcd_tile();
+  const int m_blk = tile.tm * BM, n_blk = tile.tn * BN;   // M tiles on x (up to 2^31 - 1)
+  const int kb = tile.tz * k_split;
   const int ke = min(K, kb + k_split);
   f32x4 acc[C::FM][C::FN];
 #pragma unroll
@@ -300,6 +332,7 @@ __global__ __launch_bounds__(256) void k_gemm(LA la, LB lb, EPI epi, int M, int 
     const float4 hi = *reinterpret_cast<const float4*>(sc + r * LDC + c0 + 4);
     const float vals[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
     if constexpr (EPI::kPrefetch) epi.store8_pre(m, n0, vals, min(8, N - n0), epre[i]);
+    else if constexpr (EPI::kSliced) epi.store8z(tile.tz, m, n0, vals, min(8, N - n0));
     else epi.store8(m, n0, vals, min(8, N - n0));
   }
 }

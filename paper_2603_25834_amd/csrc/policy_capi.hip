@@ -51,7 +51,7 @@ struct aslam_policy {
 
 namespace {
 
-constexpr int kConvGrid = 2048;    // workgroups of the fused encoder forward (each loops over samples)
+constexpr int kConvGrid = 768;     // encoder forward: the resident workgroups (three per CU, LDS-bound), each looping over samples
 constexpr int kConvBwdGrid = 256;  // encoder backward: one 8-wave workgroup per CU (LDS-bound)
 constexpr int64_t kFc1Splits = 12, kFc2Splits = 64;
 constexpr int kFc1MinBlocks = 512;   // FC1 forward: resident workgroups (two per CU) that its K splits fill

@@ -114,10 +114,11 @@ struct LdBF16I {
 
 // ---------------------------------------------------------------- epilogues
 // store8(m, n0, v, nvalid): row m, columns n0 .. n0 + nvalid - 1 (n0 multiple of 8).
+// kSliced: the epilogue stores a split-K slice and takes its index (store8z(z, ...)).
 
 struct EpiBiasReluBF16 {
   uint16_t* out; const float* bias; int64_t ld;
-  static constexpr bool kPrefetch = false;
+  static constexpr bool kPrefetch = false, kSliced = false;
   __device__ void store8(int m, int n0, const float* v, int nvalid) const {
     uint16_t h[8];
 #pragma unroll
@@ -133,7 +134,7 @@ struct EpiBiasReluBF16 {
 
 struct EpiBiasF32 {
   float* out; const float* bias; int64_t ld;
-  static constexpr bool kPrefetch = false;
+  static constexpr bool kPrefetch = false, kSliced = false;
   __device__ void store8(int m, int n0, const float* v, int nvalid) const {
     float* q = out + (int64_t)m * ld + n0;
     if (nvalid == 8 && ((reinterpret_cast<uintptr_t>(q) & 15) == 0)) {
@@ -147,12 +148,12 @@ struct EpiBiasF32 {
   }
 };
 
-// Split-K partial sums: slice blockIdx.z of a [splits][M][N] FP32 buffer.
+// Split-K partial sums: slice z of a [splits][M][N] FP32 buffer.
 struct EpiPartial {
   float* part; int64_t ld; int64_t slice;
-  static constexpr bool kPrefetch = false;
-  __device__ void store8(int m, int n0, const float* v, int nvalid) const {
-    float* q = part + (int64_t)blockIdx.z * slice + (int64_t)m * ld + n0;
+  static constexpr bool kPrefetch = false, kSliced = true;
+  __device__ void store8z(int z, int m, int n0, const float* v, int nvalid) const {
+    float* q = part + (int64_t)z * slice + (int64_t)m * ld + n0;
     if (nvalid == 8 && ((reinterpret_cast<uintptr_t>(q) & 15) == 0)) {
       *reinterpret_cast<float4*>(q) = make_float4(v[0], v[1], v[2], v[3]);
       *reinterpret_cast<float4*>(q + 4) = make_float4(v[4], v[5], v[6], v[7]);
@@ -166,7 +167,7 @@ struct EpiPartial {
 struct EpiReluGradBF16 {
   uint16_t* out; const uint16_t* act; int64_t ld, ld_act;
   // the engine loads the mask at kernel start (fetch) and hands it to store8_pre
-  static constexpr bool kPrefetch = true;
+  static constexpr bool kPrefetch = true, kSliced = false;
   __device__ bool vec_ok(int m, int n0, int nvalid) const {
     return nvalid == 8 && ((((int64_t)m * ld + n0) & 7) == 0) && ((((int64_t)m * ld_act + n0) & 7) == 0);
   }
