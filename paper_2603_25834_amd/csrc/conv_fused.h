@@ -185,9 +185,11 @@ __device__ __forceinline__ bf16x8 conv2_col_frag(const uint16_t* s_a1, int oy, i
 // is waited on inside a sample (a longer tail, R > 500, reads its remainder directly).
 constexpr int kConvFwdTailPre = 2;   // tail elements per thread held in registers
 
-__global__ __launch_bounds__(256) void k_conv_fwd(const float* prm, Offsets o, const uint4* frag,
-                                                  const int16_t* crop, const float* scan, const float* state, int R,
-                                                  const int32_t* rows, uint16_t* a2, int64_t lda2, int B) {
+__global__ __launch_bounds__(256) void k_conv_fwd(const float* __restrict__ prm, Offsets o,
+                                                  const uint4* __restrict__ frag, const int16_t* __restrict__ crop,
+                                                  const float* __restrict__ scan, const float* __restrict__ state,
+                                                  int R, const int32_t* __restrict__ rows, uint16_t* __restrict__ a2,
+                                                  int64_t lda2, int B) {
   __shared__ __align__(16) uint16_t s_crop[kCropLds];
   __shared__ __align__(16) uint16_t s_a1[kA1Lds];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
@@ -240,7 +242,9 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const float* prm, Offsets o, c
     if (b + (int)gridDim.x < B) load_sample(b + gridDim.x);
     conv1_lds(s_crop, s_a1, w1f, b1, wave, lr, lg);
     __syncthreads();
-    for (int oy = wave; oy < kA2; oy += 4) {
+#pragma unroll
+    for (int i = 0; i < kA2 / 4; ++i) {
+      const int oy = wave + 4 * i;
       f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int s = 0; s < 5; ++s) {
@@ -370,9 +374,12 @@ __global__ __launch_bounds__(64 * kConvPhaseFrags) void k_conv_bwd_frags(const f
   }
 }
 
-__global__ __launch_bounds__(kBwdThreads) void k_conv_bwd(const float* prm, Offsets o, const uint4* frag,
-                                                          const int16_t* crop, const int32_t* rows,
-                                                          const uint16_t* dz2c, int B, float* part) {
+__global__ __launch_bounds__(kBwdThreads) void k_conv_bwd(const float* __restrict__ prm, Offsets o,
+                                                          const uint4* __restrict__ frag,
+                                                          const int16_t* __restrict__ crop,
+                                                          const int32_t* __restrict__ rows,
+                                                          const uint16_t* __restrict__ dz2c, int B,
+                                                          float* __restrict__ part) {
   __shared__ __align__(16) uint16_t s_crop[kCropLds];
   __shared__ __align__(16) uint16_t s_a1x[kA1xLds];
   __shared__ __align__(16) uint16_t s_dz[kDzLds];
@@ -433,29 +440,40 @@ __global__ __launch_bounds__(kBwdThreads) void k_conv_bwd(const float* prm, Offs
     }
     __syncthreads();
     if (b + (int)gridDim.x < B) load_sample(b + gridDim.x);
-    // ---- conv1 recompute: C[px][co], lane gets pixels 16 t + 4 lg + i of channel lr
-    for (int t = wave; t < kA1 * kA1 / 16; t += 8) {
-      const int pxa = t * 16 + lr, ya = pxa >> 5, xa = pxa & 31;
-      uint4 u = make_uint4(0u, 0u, 0u, 0u);
-      if (lg < 2) {
-        const uint16_t* q = s_crop + ((ya + lg) * kBlk + xa) * 4;
-        const uint2 a = *reinterpret_cast<const uint2*>(q);
-        const uint2 c = *reinterpret_cast<const uint2*>(q + 4);
-        u = make_uint4(a.x, a.y, c.x, c.y);
-      }
-      const f32x4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, u), w1f,
-                                                               f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
-      const int px0 = t * 16 + 4 * lg, y = px0 >> 5, x0 = px0 & 31;   // x0 = 0 mod 4
-      uint16_t h[4];
+    // ---- conv1 recompute: C[px][co], lane gets pixels 16 t + 4 lg + i of channel lr; the wave's
+    // eight tiles t = wave + 8 m are taken four at a time so that their operand reads overlap
 #pragma unroll
-      for (int i = 0; i < 4; ++i) h[i] = f2bf(fmaxf(acc[i] + b1c, 0.0f));
-      uint16_t* row = s_a1x + lr * kA1xCi + (y + 1) * kA1xRow;    // kx plane 0
-      const int plane = kC1 * kA1xCi;
-      // even x -> kx = 1 at ox = x / 2; odd x -> kx = 0 at (x + 1) / 2 and kx = 2 at (x - 1) / 2
-      *reinterpret_cast<uint32_t*>(row + plane + (x0 >> 1)) = (uint32_t)h[0] | ((uint32_t)h[2] << 16);
-      *reinterpret_cast<uint32_t*>(row + 2 * plane + (x0 >> 1)) = (uint32_t)h[1] | ((uint32_t)h[3] << 16);
-      row[(x0 >> 1) + 1] = h[1];
-      if ((x0 >> 1) + 2 < kA1xRow) row[(x0 >> 1) + 2] = h[3];
+    for (int h = 0; h < 2; ++h) {
+      uint4 u[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int t = wave + 8 * (4 * h + i);
+        const int pxa = t * 16 + lr, ya = pxa >> 5, xa = pxa & 31;
+        u[i] = make_uint4(0u, 0u, 0u, 0u);
+        if (lg < 2) {
+          const uint16_t* q = s_crop + ((ya + lg) * kBlk + xa) * 4;
+          const uint2 a = *reinterpret_cast<const uint2*>(q);
+          const uint2 c = *reinterpret_cast<const uint2*>(q + 4);
+          u[i] = make_uint4(a.x, a.y, c.x, c.y);
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int t = wave + 8 * (4 * h + i);
+        const f32x4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, u[i]), w1f,
+                                                                 f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+        const int px0 = t * 16 + 4 * lg, y = px0 >> 5, x0 = px0 & 31;   // x0 = 0 mod 4
+        uint16_t hv[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) hv[e] = f2bf(fmaxf(acc[e] + b1c, 0.0f));
+        uint16_t* row = s_a1x + lr * kA1xCi + (y + 1) * kA1xRow;    // kx plane 0
+        const int plane = kC1 * kA1xCi;
+        // even x -> kx = 1 at ox = x / 2; odd x -> kx = 0 at (x + 1) / 2 and kx = 2 at (x - 1) / 2
+        *reinterpret_cast<uint32_t*>(row + plane + (x0 >> 1)) = (uint32_t)hv[0] | ((uint32_t)hv[2] << 16);
+        *reinterpret_cast<uint32_t*>(row + 2 * plane + (x0 >> 1)) = (uint32_t)hv[1] | ((uint32_t)hv[3] << 16);
+        row[(x0 >> 1) + 1] = hv[1];
+        if ((x0 >> 1) + 2 < kA1xRow) row[(x0 >> 1) + 2] = hv[3];
+      }
     }
     // dz2 [co][pos] -> [pos][co]: thread takes position v % 256 and channels 8 (v / 256) .. + 7
 #pragma unroll
