@@ -285,7 +285,12 @@ namespace pol {
 // a fixed order.
 //
 // LDS layouts (BF16):
-//   crop   space-to-depth, as in the forward kernel;
+//   crop   space-to-depth, as in the forward kernel (conv1's operand);
+//   inq    the crop again as five column-residue planes, inq[p][y+1][X] =
+//          in[y][4X + p] for p < 4 and inq[4][y+1][X] = in[y][4X - 1] (row 0 and
+//          inq[4][.][0] zero): the operand of the dW1 product, where a lane
+//          needs the input under one tap at four pixels 2 apart, i.e. four
+//          input columns 4 apart -- four consecutive elements of one plane;
 //   a1x    [kx][ci][y+1][ox] = a1[ci][y][2 ox + kx - 1] (channels padded by 8
 //          elements against bank conflicts): for a fixed tap, eight
 //          consecutive output columns are eight consecutive elements, so the
@@ -297,13 +302,16 @@ namespace pol {
 //          positions padded to 40 elements so that eight lanes' 16-byte
 //          accesses cover all banks: the operand of the input-gradient
 //          product (eight channels of one position per read), transposed
-//          from dzT once per sample;
-//   dz1    [ci][y][x % 2][x / 2] (channels padded by 8 elements): the operand
-//          of the dW1 product.
+//          from dzT once per sample.
 // da1 is computed one sub-pixel phase (y % 2, x % 2) at a time: the input
 // pixels of a phase form a 16 x 16 grid that receives taps ky = 1 (y even) or
 // ky in {0, 2} (y odd), likewise kx, each from the output position
 // (qy + (py + 1 - ky) / 2, qx + (px + 1 - kx) / 2).  K = 32 channels per tap.
+// dz1 = bf16(da1) * [a1 > 0] never leaves registers: a lane holds channel
+// lr at the pixels 4 lg + i of the phase rows qy = wave and wave + 8, and
+// those eight values are exactly its A operand of one dW1 MFMA (K = the
+// wave's 32 pixels of the phase), so dW1 is accumulated right after each
+// phase's two da1 products.
 constexpr int kConvPartW2 = kC2 * 144;          // [co][tap*16 + ci]
 constexpr int kConvPartW1 = kC1 * 16;           // [co][tap], taps padded to 16
 constexpr int kConvPart = kConvPartW2 + kConvPartW1 + kC1 + kC2;
@@ -314,8 +322,8 @@ constexpr int kDzRow = 256 + 8;
 constexpr int kDzLds = kC2 * kDzRow;
 constexpr int kDzSide = 17, kDzPos = 40;
 constexpr int kDzPLds = kDzSide * kDzSide * kDzPos;
-constexpr int kDz1Ci = kA1 * kA1 + 8;   // one channel, padded against bank conflicts
-constexpr int kDz1Lds = kC1 * kDz1Ci;
+constexpr int kInqRow = kCrop / 4, kInqPlane = (kCrop + 1) * kInqRow;   // 16 columns, 65 rows (row 0 zero)
+constexpr int kInqLds = 5 * kInqPlane;
 constexpr int kBwdThreads = 512;
 
 struct PhaseTaps {
@@ -384,7 +392,7 @@ __global__ __launch_bounds__(kBwdThreads) void k_conv_bwd(const float* __restric
   __shared__ __align__(16) uint16_t s_a1x[kA1xLds];
   __shared__ __align__(16) uint16_t s_dz[kDzLds];
   __shared__ __align__(16) uint16_t s_dzp[kDzPLds];
-  __shared__ __align__(16) uint16_t s_dz1[kDz1Lds];
+  __shared__ __align__(16) uint16_t s_inq[kInqLds];
   __shared__ float s_red[8][kC1 * 16 + kC1 + kC2];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
   {
@@ -394,6 +402,8 @@ __global__ __launch_bounds__(kBwdThreads) void k_conv_bwd(const float* __restric
     for (int i = threadIdx.x; i < kA1xLds / 8; i += kBwdThreads) z[i] = make_uint4(0u, 0u, 0u, 0u);
     z = reinterpret_cast<uint4*>(s_dzp);
     for (int i = threadIdx.x; i < kDzPLds / 8; i += kBwdThreads) z[i] = make_uint4(0u, 0u, 0u, 0u);
+    z = reinterpret_cast<uint4*>(s_inq);
+    for (int i = threadIdx.x; i < kInqLds / 8; i += kBwdThreads) z[i] = make_uint4(0u, 0u, 0u, 0u);
   }
   // registers that live for the whole workgroup
   // conv1's weights as the B operand: the same values as the forward's A fragment (W'[k][co] at co = lane % 16)
@@ -426,6 +436,23 @@ __global__ __launch_bounds__(kBwdThreads) void k_conv_bwd(const float* __restric
   for (int b = blockIdx.x; b < B; b += gridDim.x) {
     // ---- stage the crop and dz2 ([co][pos]); db2 from the same values
     store_crop<kBwdThreads>(cr, s_crop);
+    {
+      // the thread's eight cells: row y = v / 8, columns 8 (v % 8) + j, i.e. X = 2 (v % 8) + (j >= 4)
+      // and residue j % 4
+      static_assert(CropRegs<kBwdThreads>::kPer == 1, "one crop vector per thread");
+      const int v = threadIdx.x, y = v >> 3, X0 = 2 * (v & 7);
+      const int32_t w[4] = {cr.v[0].x, cr.v[0].y, cr.v[0].z, cr.v[0].w};
+      uint16_t c[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        c[j] = f2bf((float)(int16_t)(w[j >> 1] >> ((j & 1) * 16)) * (1.0f / 256.0f));
+      uint16_t* rowp = s_inq + (y + 1) * kInqRow + X0;
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+        *reinterpret_cast<uint32_t*>(rowp + p * kInqPlane) = (uint32_t)c[p] | ((uint32_t)c[4 + p] << 16);
+      rowp[4 * kInqPlane + 1] = c[3];
+      if (X0 + 2 < kInqRow) rowp[4 * kInqPlane + 2] = c[7];
+    }
     {
 #pragma unroll
       for (int r = 0; r < 2; ++r) {
@@ -506,13 +533,14 @@ __global__ __launch_bounds__(kBwdThreads) void k_conv_bwd(const float* __restric
         }
       }
     }
-    // ---- da1 by phases -> dz1 (masked, BF16) into s_dz1; db1
+    // ---- da1 by phases -> dz1 (masked, BF16, in registers); db1; dW1 per phase
     {
       int q = 0;
 #pragma unroll
       for (int ph = 0; ph < 4; ++ph) {
         const int py = ph >> 1, px = ph & 1;
         const PhaseTaps t = phase_taps(py, px);
+        uint32_t dpk[4];
 #pragma unroll
         for (int rr = 0; rr < 2; ++rr) {
           const int qy = wave + 8 * rr;
@@ -537,35 +565,29 @@ __global__ __launch_bounds__(kBwdThreads) void k_conv_bwd(const float* __restric
             d[i] = bf2f(a) > 0.0f ? f2bf(acc[i]) : (uint16_t)0;
             gb1 += bf2f(d[i]);
           }
-          *reinterpret_cast<uint2*>(s_dz1 + lr * kDz1Ci + y * kA1 + px * 16 + 4 * lg) =
-              make_uint2((uint32_t)d[0] | ((uint32_t)d[1] << 16), (uint32_t)d[2] | ((uint32_t)d[3] << 16));
+          dpk[2 * rr] = (uint32_t)d[0] | ((uint32_t)d[1] << 16);
+          dpk[2 * rr + 1] = (uint32_t)d[2] | ((uint32_t)d[3] << 16);
         }
         q += t.n;
+        // dW1: C[co][tap] += sum_k dz1[co][k] in(k, tap) over the wave's 32 pixels of the phase, k = 8 lg
+        // + 4 rr + i <-> pixel (2 (wave + 8 rr) + py, 2 (4 lg + i) + px).  B: lane (tap = lr, lg) reads
+        // in[4 qy + 2 py + ky - 1][16 lg + 4 i + r], r = 2 px + kx - 1, i < 4: plane r (plane 4 for
+        // r = -1), four consecutive elements from column 4 lg.
+        uint2 bw[2] = {make_uint2(0u, 0u), make_uint2(0u, 0u)};
+        if (lr < 9) {
+          const int ky = lr / 3, kx = lr % 3, r = 2 * px + kx - 1;
+          const uint16_t* pl = s_inq + (r < 0 ? 4 : r) * kInqPlane + 4 * lg;
+#pragma unroll
+          for (int rr = 0; rr < 2; ++rr) {
+            const int row = 4 * (wave + 8 * rr) + 2 * py + ky - 1;
+            bw[rr] = *reinterpret_cast<const uint2*>(pl + (row + 1) * kInqRow);
+          }
+        }
+        const uint4 au = make_uint4(dpk[0], dpk[1], dpk[2], dpk[3]);
+        const uint4 bu = make_uint4(bw[0].x, bw[0].y, bw[1].x, bw[1].y);
+        gw1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, au), __builtin_bit_cast(bf16x8, bu),
+                                                      gw1, 0, 0, 0);
       }
-    }
-    __syncthreads();
-    // ---- dW1: C[co][tap] = sum_kappa dz1[co][kappa] in(kappa, tap), kappa = y*32 + par*16 + xh; 4 k-steps per wave
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int ks = wave * 4 + r;
-      const int k0 = 32 * ks + 8 * lg;
-      const bf16x8 af = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(s_dz1 + lr * kDz1Ci + k0));
-      // B: lane supplies in[(y, x = 2 (xh0 + e) + par), tap = lr] for e < 8: input row
-      // 2 y + ky - 1 and column 4 (xh0 + e) + c0 with c0 = 2 par + kx - 1 in [-1, 3], i.e. block
-      // column 2 (xh0 + e) + (c0 >> 1) and element (row & 1, c0 & 1): consecutive e are 8 apart.
-      const int y = k0 >> 5, par = (k0 >> 4) & 1, xh0 = k0 & 15;
-      const int ky = lr / 3, kx = lr % 3;
-      const int row = 2 * y + ky - 1, c0 = 2 * par + kx - 1;
-      const int base = (((row >> 1) + 1) * kBlk + 2 * xh0 + (c0 >> 1) + 1) * 4 + 2 * (row & 1) + (c0 & 1);
-      uint16_t v[8];
-#pragma unroll
-      for (int e = 0; e < 8; ++e) v[e] = lr < 9 ? s_crop[base + 8 * e] : (uint16_t)0;
-      uint4 u;
-      u.x = v[0] | ((uint32_t)v[1] << 16);
-      u.y = v[2] | ((uint32_t)v[3] << 16);
-      u.z = v[4] | ((uint32_t)v[5] << 16);
-      u.w = v[6] | ((uint32_t)v[7] << 16);
-      gw1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, __builtin_bit_cast(bf16x8, u), gw1, 0, 0, 0);
     }
     __syncthreads();
   }
@@ -583,8 +605,8 @@ __global__ __launch_bounds__(kBwdThreads) void k_conv_bwd(const float* __restric
   (void)red;
   __syncthreads();
   {
-    // stage nt = 8 partials of this wave through the (now free) dz1 buffer as floats
-    float* st8 = reinterpret_cast<float*>(s_dz1);   // [8 waves][32 co][16 ci]
+    // stage nt = 8 partials of this wave through the (now free) a1x buffer as floats
+    float* st8 = reinterpret_cast<float*>(s_a1x);   // [8 waves][32 co][16 ci]
 #pragma unroll
     for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
@@ -595,7 +617,7 @@ __global__ __launch_bounds__(kBwdThreads) void k_conv_bwd(const float* __restric
   }
   __syncthreads();
   {
-    float* st8 = reinterpret_cast<float*>(s_dz1);
+    float* st8 = reinterpret_cast<float*>(s_a1x);
     for (int e = threadIdx.x; e < 32 * 16; e += kBwdThreads) {
       float s = 0.0f;
       for (int w = 0; w < 8; ++w) s += st8[w * 512 + e];
@@ -610,7 +632,7 @@ __global__ __launch_bounds__(kBwdThreads) void k_conv_bwd(const float* __restric
   __syncthreads();
   {
     // db1: lane lr of each wave holds a channel-lr sum; db2: thread t holds channels t / 32 and t / 32 + 16
-    float* st = reinterpret_cast<float*>(s_dz1);
+    float* st = reinterpret_cast<float*>(s_a1x);
     st[threadIdx.x] = gb1;
     st[kBwdThreads + threadIdx.x] = gb2[0];
     st[2 * kBwdThreads + threadIdx.x] = gb2[1];
