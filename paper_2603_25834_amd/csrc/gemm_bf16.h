@@ -8,9 +8,8 @@
 // Tiling: a workgroup of 256 threads (4 waves) owns a BM x BN tile of C; the
 // waves are arranged WM x WN and each accumulates a (BM/WM) x (BN/WN) sub-tile
 // in 16x16 MFMA fragments.  K advances BK per stage, double buffered in LDS,
-// with the next stage's global loads in registers while the current stage
-// feeds the MFMAs.  A large BK keeps enough bytes in flight per CU to cover HBM
-// latency with one workgroup per CU.  Both operands are staged as [row][k]
+// with the global loads of the next two stages in registers while the current
+// stage feeds the MFMAs (one stage ahead on edge tiles).  Both operands are staged as [row][k]
 // (rows padded by 8 elements) and read as one 16-byte fragment per lane.  An
 // operand whose source is contiguous along the row index is transposed on the
 // way in: a thread loads the same eight rows at k and k + 1 and stores eight
@@ -32,6 +31,7 @@ namespace gemm {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));   // staged loads (a plain vector type stays in registers)
 
 // Round-to-nearest-even FP32 -> BF16 bits: the hardware conversion (v_cvt_pk_bf16_f32 on gfx950,
 // two values per instruction when the compiler pairs them).
@@ -87,28 +87,25 @@ struct Cfg {
 // !kMajor: registers 2q, 2q + 1 hold pair w = tid + 256 q = (k = 2 (w / (ROWS/8)), row-chunk w % (ROWS/8))
 // at k and k + 1 (consecutive lanes read consecutive row-chunks of the same source rows).
 // Element offsets, from the tile origin, of the vectors fetch_tile loads into this thread's registers
-// (the same assignment as fetch_tile); used by the unchecked path for tiles that lie wholly inside
-// a plain strided matrix (loader fields p, ld, rows, cols).
-template <class L, int ROWS, int BK, int P>
-__device__ __forceinline__ void tile_offsets(const L& ld, int64_t (&off)[P]) {
-  constexpr int V = ROWS * BK / 8;
+// (the same assignment as fetch_tile), used by the unchecked path for tiles that lie wholly inside a
+// plain strided matrix (loader fields p, ld, rows, cols): 256 threads cover whole rows (k-major) or
+// whole k pairs, so the offset of register p (pair q) is base + p * step (base + q * step, + ld for k + 1).
+struct TileOff {
+  int64_t base, step;
+};
+
+template <class L, int ROWS, int BK>
+__device__ __forceinline__ TileOff tile_offsets(const L& ld) {
+  static_assert(256 % (BK / 8) == 0 && 256 % (ROWS / 8) == 0, "256 threads cover whole rows / k pairs");
+  TileOff o;
   if (L::kMajor) {
-#pragma unroll
-    for (int p = 0; p < P; ++p) {
-      const int v = threadIdx.x + p * 256;
-      const int i = (V % 256 == 0 || v < V) ? v / (BK / 8) : 0, kq = v % (BK / 8);
-      off[p] = (int64_t)i * ld.ld + kq * 8;
-    }
+    o.base = (int64_t)(threadIdx.x / (BK / 8)) * ld.ld + (threadIdx.x % (BK / 8)) * 8;
+    o.step = (int64_t)(256 / (BK / 8)) * ld.ld;
   } else {
-#pragma unroll
-    for (int q = 0; q < P / 2; ++q) {
-      const int w = threadIdx.x + q * 256;
-      const int k = 2 * (w / (ROWS / 8)), iq = w % (ROWS / 8);
-      const int kk = (V / 2 % 256 == 0 || w < V / 2) ? k : 0;
-      off[2 * q] = (int64_t)kk * ld.ld + iq * 8;
-      off[2 * q + 1] = (int64_t)(kk + 1) * ld.ld + iq * 8;
-    }
+    o.base = (int64_t)(2 * (threadIdx.x / (ROWS / 8))) * ld.ld + (threadIdx.x % (ROWS / 8)) * 8;
+    o.step = (int64_t)(2 * (256 / (ROWS / 8))) * ld.ld;
   }
+  return o;
 }
 
 // The tile at (row0, k0) lies wholly inside the matrix and its rows start on 16-byte boundaries.
@@ -118,27 +115,35 @@ __device__ __forceinline__ bool tile_interior(const L& ld, int row0, int k0) {
          (reinterpret_cast<uintptr_t>(ld.p) & 15) == 0;
 }
 
+// The loads of a tile known to lie wholly inside the matrix, with no branch, so that a
+// software-pipelined loop issues a fixed number of loads per step.
 template <class L, int ROWS, int BK, int P>
-__device__ __forceinline__ void fetch_tile(const L& ld, int row0, int k0, uint4 (&regs)[P], const int64_t (&off)[P]) {
+__device__ __forceinline__ void fetch_fast(const L& ld, int row0, int k0, u32x4 (&regs)[P], const TileOff& off) {
   constexpr int V = ROWS * BK / 8;
-  if (tile_interior<L, ROWS, BK>(ld, row0, k0)) {
-    const uint16_t* base = L::kMajor ? ld.p + (int64_t)row0 * ld.ld + k0 : ld.p + (int64_t)k0 * ld.ld + row0;
-    if (L::kMajor) {
+  const uint16_t* base = (L::kMajor ? ld.p + (int64_t)row0 * ld.ld + k0 : ld.p + (int64_t)k0 * ld.ld + row0) + off.base;
+  if (L::kMajor) {
 #pragma unroll
-      for (int p = 0; p < P; ++p) {
-        const int v = threadIdx.x + p * 256;
-        if (V % 256 == 0 || v < V) regs[p] = *reinterpret_cast<const uint4*>(base + off[p]);
-      }
-    } else {
+    for (int p = 0; p < P; ++p) {
+      const int v = threadIdx.x + p * 256;
+      if (V % 256 == 0 || v < V) regs[p] = *reinterpret_cast<const u32x4*>(base + p * off.step);
+    }
+  } else {
 #pragma unroll
-      for (int q = 0; q < P / 2; ++q) {
-        const int w = threadIdx.x + q * 256;
-        if (V / 2 % 256 == 0 || w < V / 2) {
-          regs[2 * q] = *reinterpret_cast<const uint4*>(base + off[2 * q]);
-          regs[2 * q + 1] = *reinterpret_cast<const uint4*>(base + off[2 * q + 1]);
-        }
+    for (int q = 0; q < P / 2; ++q) {
+      const int w = threadIdx.x + q * 256;
+      if (V / 2 % 256 == 0 || w < V / 2) {
+        regs[2 * q] = *reinterpret_cast<const u32x4*>(base + q * off.step);
+        regs[2 * q + 1] = *reinterpret_cast<const u32x4*>(base + q * off.step + ld.ld);
       }
     }
+  }
+}
+
+template <class L, int ROWS, int BK, int P>
+__device__ __forceinline__ void fetch_tile(const L& ld, int row0, int k0, u32x4 (&regs)[P], const TileOff& off) {
+  constexpr int V = ROWS * BK / 8;
+  if (tile_interior<L, ROWS, BK>(ld, row0, k0)) {
+    fetch_fast<L, ROWS, BK>(ld, row0, k0, regs, off);
     return;
   }
   if (L::kMajor) {
@@ -147,7 +152,8 @@ __device__ __forceinline__ void fetch_tile(const L& ld, int row0, int k0, uint4 
       const int v = threadIdx.x + p * 256;
       if (V % 256 == 0 || v < V) {
         const int i = v / (BK / 8), kq = v % (BK / 8);
-        regs[p] = ld.fetch(row0 + i, k0 + kq * 8);
+        const uint4 u = ld.fetch(row0 + i, k0 + kq * 8);
+        regs[p] = u32x4{u.x, u.y, u.z, u.w};
       }
     }
   } else {
@@ -157,15 +163,23 @@ __device__ __forceinline__ void fetch_tile(const L& ld, int row0, int k0, uint4 
       const int w = threadIdx.x + q * 256;
       if (VP % 256 == 0 || w < VP) {
         const int k = 2 * (w / (ROWS / 8)), iq = w % (ROWS / 8);
-        regs[2 * q] = ld.fetch(row0 + iq * 8, k0 + k);
-        regs[2 * q + 1] = ld.fetch(row0 + iq * 8, k0 + k + 1);
+        const uint4 u0 = ld.fetch(row0 + iq * 8, k0 + k), u1 = ld.fetch(row0 + iq * 8, k0 + k + 1);
+        regs[2 * q] = u32x4{u0.x, u0.y, u0.z, u0.w};
+        regs[2 * q + 1] = u32x4{u1.x, u1.y, u1.z, u1.w};
       }
     }
   }
 }
 
+// The rows row0 .. row0 + ROWS - 1 of the operand lie inside the matrix and its rows start on 16-byte
+// boundaries (every K step of such a tile that ends by ld.cols is interior).
+template <class L, int ROWS>
+__device__ __forceinline__ bool rows_interior(const L& ld, int row0) {
+  return row0 + ROWS <= ld.rows && (ld.ld & 7) == 0 && (reinterpret_cast<uintptr_t>(ld.p) & 15) == 0;
+}
+
 template <class L, int ROWS, int BK, int P>
-__device__ __forceinline__ void store_tile(uint16_t* s, const uint4 (&regs)[P]) {
+__device__ __forceinline__ void store_tile(uint16_t* s, const u32x4 (&regs)[P]) {
   using S = Stage<L::kMajor, ROWS, BK>;
   constexpr int V = ROWS * BK / 8;
   if (L::kMajor) {
@@ -174,7 +188,7 @@ __device__ __forceinline__ void store_tile(uint16_t* s, const uint4 (&regs)[P]) 
       const int v = threadIdx.x + p * 256;
       if (V % 256 == 0 || v < V) {
         const int i = v / (BK / 8), kq = v % (BK / 8);
-        *reinterpret_cast<uint4*>(s + S::at(i, kq * 8)) = regs[p];
+        *reinterpret_cast<u32x4*>(s + S::at(i, kq * 8)) = regs[p];
       }
     }
   } else {
@@ -184,8 +198,8 @@ __device__ __forceinline__ void store_tile(uint16_t* s, const uint4 (&regs)[P]) 
       const int w = threadIdx.x + q * 256;
       if (VP % 256 == 0 || w < VP) {
         const int k = 2 * (w / (ROWS / 8)), iq = w % (ROWS / 8);
-        const uint4 a = regs[2 * q], b = regs[2 * q + 1];
-        const uint32_t wa[4] = {a.x, a.y, a.z, a.w}, wb[4] = {b.x, b.y, b.z, b.w};
+        const u32x4 a = regs[2 * q], b = regs[2 * q + 1];
+        const uint32_t wa[4] = {a[0], a[1], a[2], a[3]}, wb[4] = {b[0], b[1], b[2], b[3]};
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
           const uint32_t lo = (wa[j >> 1] >> ((j & 1) * 16)) & 0xffffu;
@@ -201,6 +215,25 @@ __device__ __forceinline__ void store_tile(uint16_t* s, const uint4 (&regs)[P]) 
 template <bool KMAJOR, int ROWS, int BK>
 __device__ __forceinline__ bf16x8 load_frag(const uint16_t* s, int r, int kk) {
   return __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(s + Stage<KMAJOR, ROWS, BK>::at(r, kk)));
+}
+
+// The MFMAs of one staged K step: the wave's FM x FN fragments of C, BK / 32 products each.
+template <int BM, int BN, int BK, int WM, int WN, bool AMAJ, bool BMAJ>
+__device__ __forceinline__ void mma_stage(const uint16_t* a_st, const uint16_t* b_st, int ra0, int rb0, int kl,
+                                          f32x4 (&acc)[Cfg<BM, BN, BK, WM, WN>::FM][Cfg<BM, BN, BK, WM, WN>::FN]) {
+  using C = Cfg<BM, BN, BK, WM, WN>;
+#pragma unroll
+  for (int kk = 0; kk < BK; kk += 32) {
+    bf16x8 bf[C::FN];
+#pragma unroll
+    for (int j = 0; j < C::FN; ++j) bf[j] = load_frag<BMAJ, BN, BK>(b_st, rb0 + j * 16, kk + kl);
+#pragma unroll
+    for (int i = 0; i < C::FM; ++i) {
+      const bf16x8 af = load_frag<AMAJ, BM, BK>(a_st, ra0 + i * 16, kk + kl);
+#pragma unroll
+      for (int j = 0; j < C::FN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bf[j], acc[i][j], 0, 0, 0);
+    }
+  }
 }
 
 // Tile (tm, tn, tz) of the workgroup.  The dispatcher hands consecutive workgroups of a grid to the
@@ -267,46 +300,76 @@ __global__ __launch_bounds__(256) void k_gemm(LA la, LB lb, EPI epi, int M, int 
                                                            : make_uint4(0u, 0u, 0u, 0u);
     }
   }
-  uint4 ra[C::PA], rb[C::PB];
-  int64_t oa[C::PA], ob[C::PB];
-  tile_offsets<LA, BM, BK>(la, oa);
-  tile_offsets<LB, BN, BK>(lb, ob);
+  const TileOff oa = tile_offsets<LA, BM, BK>(la), ob = tile_offsets<LB, BN, BK>(lb);
   const int nsteps = (ke - kb + BK - 1) / BK;
-  if (nsteps > 0) {
-    fetch_tile<LA, BM, BK>(la, m_blk, kb, ra, oa);
-    fetch_tile<LB, BN, BK>(lb, n_blk, kb, rb, ob);
-    store_tile<LA, BM, BK>(sA, ra);
-    store_tile<LB, BN, BK>(sB, rb);
-  }
-  __syncthreads();
-  for (int t = 0; t < nsteps; ++t) {
-    const int buf = t & 1;
-    const bool more = t + 1 < nsteps;
-    if (more) {
-      fetch_tile<LA, BM, BK>(la, m_blk, kb + (t + 1) * BK, ra, oa);
-      fetch_tile<LB, BN, BK>(lb, n_blk, kb + (t + 1) * BK, rb, ob);
-    }
-    const uint16_t* a_st = sA + buf * SA::kElems;
-    const uint16_t* b_st = sB + buf * SB::kElems;
-    const int ra0 = wm * C::TM + (lane & 15), rb0 = wn * C::TN + (lane & 15), kl = 8 * (lane >> 4);
-#pragma unroll
-    for (int kk = 0; kk < BK; kk += 32) {
-      bf16x8 bf[C::FN];
-#pragma unroll
-      for (int j = 0; j < C::FN; ++j) bf[j] = load_frag<LB::kMajor, BN, BK>(b_st, rb0 + j * 16, kk + kl);
-#pragma unroll
-      for (int i = 0; i < C::FM; ++i) {
-        const bf16x8 af = load_frag<LA::kMajor, BM, BK>(a_st, ra0 + i * 16, kk + kl);
-#pragma unroll
-        for (int j = 0; j < C::FN; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bf[j], acc[i][j], 0, 0, 0);
-      }
-    }
-    if (more) {
-      store_tile<LA, BM, BK>(sA + (buf ^ 1) * SA::kElems, ra);
-      store_tile<LB, BN, BK>(sB + (buf ^ 1) * SB::kElems, rb);
-    }
+  const int ra0 = wm * C::TM + (lane & 15), rb0 = wn * C::TN + (lane & 15), kl = 8 * (lane >> 4);
+  uint16_t* const sA1 = sA + SA::kElems;
+  uint16_t* const sB1 = sB + SB::kElems;
+  // Steps whose tiles are interior in both operands (rows inside, K step whole) run a loop with two
+  // stages of loads in registers: step t's MFMAs overlap the loads of step t + 2, and the stores of
+  // step t + 1 wait only for loads issued a whole step earlier.  Every step issues the same loads
+  // (past the last step they re-read it), so the waits are exact counts.
+  // (An epilogue that prefetches holds its own registers through the loop: one stage there.)
+  int nfast = 0;
+  if (!EPI::kPrefetch && rows_interior<LA, BM>(la, m_blk) && rows_interior<LB, BN>(lb, n_blk))
+    nfast = max(0, (min(ke, min(la.cols, lb.cols)) - kb) / BK);
+  int t = 0;
+  u32x4 ra_e[C::PA], rb_e[C::PB], ra_o[C::PA], rb_o[C::PB];   // even / odd steps (the edge loop: ra_e, rb_e)
+  if (nfast > 0) {
+    fetch_fast<LA, BM, BK>(la, m_blk, kb, ra_e, oa);
+    fetch_fast<LB, BN, BK>(lb, n_blk, kb, rb_e, ob);
+    const int k1 = kb + BK * min(1, nfast - 1);
+    fetch_fast<LA, BM, BK>(la, m_blk, k1, ra_o, oa);
+    fetch_fast<LB, BN, BK>(lb, n_blk, k1, rb_o, ob);
+    store_tile<LA, BM, BK>(sA, ra_e);
+    store_tile<LB, BN, BK>(sB, rb_e);
     __syncthreads();
+    for (; t + 2 <= nfast; t += 2) {
+      const int k2 = kb + BK * min(t + 2, nfast - 1);
+      fetch_fast<LA, BM, BK>(la, m_blk, k2, ra_e, oa);
+      fetch_fast<LB, BN, BK>(lb, n_blk, k2, rb_e, ob);
+      mma_stage<BM, BN, BK, WM, WN, LA::kMajor, LB::kMajor>(sA, sB, ra0, rb0, kl, acc);
+      store_tile<LA, BM, BK>(sA1, ra_o);
+      store_tile<LB, BN, BK>(sB1, rb_o);
+      __syncthreads();
+      const int k3 = kb + BK * min(t + 3, nfast - 1);
+      fetch_fast<LA, BM, BK>(la, m_blk, k3, ra_o, oa);
+      fetch_fast<LB, BN, BK>(lb, n_blk, k3, rb_o, ob);
+      mma_stage<BM, BN, BK, WM, WN, LA::kMajor, LB::kMajor>(sA1, sB1, ra0, rb0, kl, acc);
+      if (t + 2 < nfast) {
+        store_tile<LA, BM, BK>(sA, ra_e);
+        store_tile<LB, BN, BK>(sB, rb_e);
+      }
+      __syncthreads();
+    }
+    if (t < nfast) {   // an odd count: the last step is in buffer 0
+      mma_stage<BM, BN, BK, WM, WN, LA::kMajor, LB::kMajor>(sA, sB, ra0, rb0, kl, acc);
+      __syncthreads();
+      ++t;
+    }
+  }
+  // the remaining steps (edge tiles, a partial last K step): bounds-checked loads, one stage ahead
+  if (t < nsteps) {
+    fetch_tile<LA, BM, BK>(la, m_blk, kb + t * BK, ra_e, oa);
+    fetch_tile<LB, BN, BK>(lb, n_blk, kb + t * BK, rb_e, ob);
+    store_tile<LA, BM, BK>(sA, ra_e);
+    store_tile<LB, BN, BK>(sB, rb_e);
+    __syncthreads();
+    for (int u = 0; t < nsteps; ++t, ++u) {
+      const int buf = u & 1;
+      const bool more = t + 1 < nsteps;
+      if (more) {
+        fetch_tile<LA, BM, BK>(la, m_blk, kb + (t + 1) * BK, ra_e, oa);
+        fetch_tile<LB, BN, BK>(lb, n_blk, kb + (t + 1) * BK, rb_e, ob);
+      }
+      mma_stage<BM, BN, BK, WM, WN, LA::kMajor, LB::kMajor>(sA + buf * SA::kElems, sB + buf * SB::kElems, ra0, rb0, kl,
+                                                             acc);
+      if (more) {
+        store_tile<LA, BM, BK>(sA + (buf ^ 1) * SA::kElems, ra_e);
+        store_tile<LB, BN, BK>(sB + (buf ^ 1) * SB::kElems, rb_e);
+      }
+      __syncthreads();
+    }
   }
   // stage the FP32 tile through LDS, then hand rows of eight columns to the epilogue
   float* sc = reinterpret_cast<float*>(smem);
