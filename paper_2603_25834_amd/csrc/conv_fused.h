@@ -393,7 +393,7 @@ __global__ __launch_bounds__(kBwdThreads) void k_conv_bwd(const float* __restric
   __shared__ __align__(16) uint16_t s_dz[kDzLds];
   __shared__ __align__(16) uint16_t s_dzp[kDzPLds];
   __shared__ __align__(16) uint16_t s_inq[kInqLds];
-  __shared__ float s_red[8][kC1 * 16 + kC1 + kC2];
+  __shared__ float s_red[8][kC1 * 16];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
   {
     uint4* z = reinterpret_cast<uint4*>(s_crop);
@@ -413,10 +413,11 @@ __global__ __launch_bounds__(kBwdThreads) void k_conv_bwd(const float* __restric
   bf16x8 wph[kConvPhaseFrags];
 #pragma unroll
   for (int q = 0; q < kConvPhaseFrags; ++q) wph[q] = __builtin_bit_cast(bf16x8, frag[64 * (kConvFrags + q) + lane]);
-  // accumulators: dW2 tiles (mt, nt) for nt = wave (all k-steps) and nt = 8 (k-step = wave)
-  f32x4 gw2[2][2];
+  // accumulators: every dW2 tile (nt = tap, mt = output-channel half) over this wave's k-step
+  // (positions 32 wave .. 32 wave + 31) of every sample
+  f32x4 gw2[9][2];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < 9; ++a)
 #pragma unroll
     for (int c = 0; c < 2; ++c) gw2[a][c] = f32x4{0.f, 0.f, 0.f, 0.f};
   f32x4 gw1 = {0.f, 0.f, 0.f, 0.f};
@@ -513,24 +514,23 @@ __global__ __launch_bounds__(kBwdThreads) void k_conv_bwd(const float* __restric
       *reinterpret_cast<uint4*>(s_dzp + ((pos >> 4) * kDzSide + (pos & 15)) * kDzPos + 8 * cg) = pack8(g);
     }
     __syncthreads();
-    // ---- dW2: tiles (mt, nt = wave) over all 8 position k-steps, and (mt, nt = 8) at k-step = wave
+    // ---- dW2: the wave's k-step (positions p0 = 32 wave + 8 lg .. + 7 of the lane) for all nine taps;
+    // the dz operand is read once and serves every tap
     {
+      const int p0 = 32 * wave + 8 * lg, oy = p0 >> 4, ox0 = p0 & 15;
+      bf16x8 af[2];
 #pragma unroll
-      for (int u = 0; u < 9; ++u) {
-        const int nt = u < 8 ? wave : 8;
-        const int ks = u < 8 ? u : wave;
-        const int slot = u < 8 ? 0 : 1;
-        const int p0 = 32 * ks + 8 * lg, oy = p0 >> 4, ox0 = p0 & 15;
+      for (int mt = 0; mt < 2; ++mt)
+        af[mt] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(s_dz + (16 * mt + lr) * kDzRow + p0));
+#pragma unroll
+      for (int nt = 0; nt < 9; ++nt) {
         const int ky = nt / 3, kx = nt % 3;
         const int yy = 2 * oy + ky - 1;
         const bf16x8 bf = __builtin_bit_cast(
             bf16x8, *reinterpret_cast<const uint4*>(s_a1x + (kx * kC1 + lr) * kA1xCi + (yy + 1) * kA1xRow + ox0));
 #pragma unroll
-        for (int mt = 0; mt < 2; ++mt) {
-          const bf16x8 af = __builtin_bit_cast(
-              bf16x8, *reinterpret_cast<const uint4*>(s_dz + (16 * mt + lr) * kDzRow + p0));
-          gw2[slot][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bf, gw2[slot][mt], 0, 0, 0);
-        }
+        for (int mt = 0; mt < 2; ++mt)
+          gw2[nt][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[mt], bf, gw2[nt][mt], 0, 0, 0);
       }
     }
     // ---- da1 by phases -> dz1 (masked, BF16, in registers); db1; dW1 per phase
@@ -594,45 +594,38 @@ __global__ __launch_bounds__(kBwdThreads) void k_conv_bwd(const float* __restric
 
   // ---- write the workgroup's partial sums (fixed order everywhere)
   float* out = part + (int64_t)blockIdx.x * kConvPart;
-  // dW2 [co][nt*16 + ci]: tile (mt, nt) lane value C[4 lg + i][lr] = (co = 16 mt + 4 lg + i, ci = lr)
+  float* st = reinterpret_cast<float*>(s_a1x);   // free after the sample loop
+  // dW2 [co][nt*16 + ci]: lane value C[4 lg + i][lr] of tile (nt, mt) = (co = 16 mt + 4 lg + i, ci = lr), the
+  // eight waves' k-step partials summed in wave order, three taps at a time through LDS
 #pragma unroll
-  for (int mt = 0; mt < 2; ++mt)
+  for (int g = 0; g < 3; ++g) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) out[(16 * mt + 4 * lg + i) * 144 + wave * 16 + lr] = gw2[0][mt][i];
-  // nt = 8: sum of the eight waves' k-step partials, in wave order
-  float* red = &s_red[0][0];
-  constexpr int kRedW = kC1 * 16 + kC1 + kC2;
-  (void)red;
-  __syncthreads();
-  {
-    // stage nt = 8 partials of this wave through the (now free) a1x buffer as floats
-    float* st8 = reinterpret_cast<float*>(s_a1x);   // [8 waves][32 co][16 ci]
+    for (int j = 0; j < 3; ++j)
 #pragma unroll
-    for (int mt = 0; mt < 2; ++mt)
+      for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) st8[(wave * 32 + 16 * mt + 4 * lg + i) * 16 + lr] = gw2[1][mt][i];
-    // dW1 tile: C[4 lg + i][lr] = (co = 4 lg + i, tap = lr); db1 per lane (ci = lr); db2 per thread
-#pragma unroll
-    for (int i = 0; i < 4; ++i) s_red[wave][(4 * lg + i) * 16 + lr] = gw1[i];
+        for (int i = 0; i < 4; ++i) st[((wave * 3 + j) * 32 + 16 * mt + 4 * lg + i) * 16 + lr] = gw2[3 * g + j][mt][i];
+    __syncthreads();
+    for (int e = threadIdx.x; e < 3 * 512; e += kBwdThreads) {
+      const int j = e >> 9, r = e & 511;
+      float sum = 0.0f;
+      for (int w = 0; w < 8; ++w) sum += st[(w * 3 + j) * 512 + r];
+      out[(r >> 4) * 144 + (3 * g + j) * 16 + (r & 15)] = sum;
+    }
+    __syncthreads();
   }
+  // dW1 tile: C[4 lg + i][lr] = (co = 4 lg + i, tap = lr), summed over the waves in wave order
+#pragma unroll
+  for (int i = 0; i < 4; ++i) s_red[wave][(4 * lg + i) * 16 + lr] = gw1[i];
   __syncthreads();
-  {
-    float* st8 = reinterpret_cast<float*>(s_a1x);
-    for (int e = threadIdx.x; e < 32 * 16; e += kBwdThreads) {
-      float s = 0.0f;
-      for (int w = 0; w < 8; ++w) s += st8[w * 512 + e];
-      out[(e >> 4) * 144 + 128 + (e & 15)] = s;
-    }
-    for (int e = threadIdx.x; e < kC1 * 16; e += kBwdThreads) {
-      float s = 0.0f;
-      for (int w = 0; w < 8; ++w) s += s_red[w][e];
-      out[kConvPartW2 + e] = s;
-    }
+  for (int e = threadIdx.x; e < kC1 * 16; e += kBwdThreads) {
+    float sum = 0.0f;
+    for (int w = 0; w < 8; ++w) sum += s_red[w][e];
+    out[kConvPartW2 + e] = sum;
   }
   __syncthreads();
   {
     // db1: lane lr of each wave holds a channel-lr sum; db2: thread t holds channels t / 32 and t / 32 + 16
-    float* st = reinterpret_cast<float*>(s_a1x);
     st[threadIdx.x] = gb1;
     st[kBwdThreads + threadIdx.x] = gb2[0];
     st[2 * kBwdThreads + threadIdx.x] = gb2[1];
@@ -649,7 +642,6 @@ __global__ __launch_bounds__(kBwdThreads) void k_conv_bwd(const float* __restric
       out[kConvPartW2 + kConvPartW1 + kC1 + co] = s;
     }
   }
-  (void)kRedW;
 }
 
 }  // namespace pol
