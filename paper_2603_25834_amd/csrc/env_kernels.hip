@@ -1012,18 +1012,28 @@ __global__ __launch_bounds__(NT, 4) void k_fused_persist(EnvParams P, StepArgs A
   }
 }
 
+template <bool kVecSrc>   // world_src on a 16-byte boundary: the world copy in 16-byte vectors
 __global__ void k_reset(EnvParams P, const uint32_t* world_src, const float* init_pose, const uint8_t* mask) {
   const int32_t r = blockIdx.x;
   if (mask && !mask[r]) return;
   const RobotMeta m = P.meta[r];
   const int32_t s = m.side;
-  int32_t* bel = reinterpret_cast<int32_t*>(P.belief + m.cell_off);
-  const int64_t npair = (int64_t)s * s / 2;
-  for (int64_t k = threadIdx.x; k < npair; k += blockDim.x) bel[k] = 0;
-  const int64_t nw = (int64_t)s * s / 32;
-  uint32_t* wd = const_cast<uint32_t*>(P.world) + m.world_off;
-  const uint32_t* ws = world_src + m.world_off;
-  for (int64_t k = threadIdx.x; k < nw; k += blockDim.x) wd[k] = ws[k];
+  // sides are multiples of 32, so a robot's map (s^2 int16) and world (s^2 / 32 words) are whole 16-byte
+  // vectors starting on 16-byte boundaries
+  uint4* bel = reinterpret_cast<uint4*>(P.belief + m.cell_off);
+  const int64_t nvec = (int64_t)s * s / 8;
+  for (int64_t k = threadIdx.x; k < nvec; k += blockDim.x) bel[k] = make_uint4(0u, 0u, 0u, 0u);
+  if (kVecSrc) {
+    const int64_t nw = (int64_t)s * s / 128;
+    uint4* wd = reinterpret_cast<uint4*>(const_cast<uint32_t*>(P.world) + m.world_off);
+    const uint4* ws = reinterpret_cast<const uint4*>(world_src + m.world_off);
+    for (int64_t k = threadIdx.x; k < nw; k += blockDim.x) wd[k] = ws[k];
+  } else {
+    const int64_t nw = (int64_t)s * s / 32;
+    uint32_t* wd = const_cast<uint32_t*>(P.world) + m.world_off;
+    const uint32_t* ws = world_src + m.world_off;
+    for (int64_t k = threadIdx.x; k < nw; k += blockDim.x) wd[k] = ws[k];
+  }
   if (P.uses_visits) {
     const int64_t nv = (int64_t)m.visit_side * m.visit_side;
     for (int64_t k = threadIdx.x; k < nv; k += blockDim.x) {
@@ -1146,7 +1156,8 @@ hipError_t set_lds_nt(int bytes) {
 
 hipError_t launch_reset(const EnvParams& P, const uint32_t* world_src, const float* init_pose,
                         const uint8_t* mask, int32_t, hipStream_t stream) {
-  k_reset<<<P.n, 256, 0, stream>>>(P, world_src, init_pose, mask);
+  if ((reinterpret_cast<uintptr_t>(world_src) & 15) == 0) k_reset<true><<<P.n, 256, 0, stream>>>(P, world_src, init_pose, mask);
+  else k_reset<false><<<P.n, 256, 0, stream>>>(P, world_src, init_pose, mask);
   return hipGetLastError();
 }
 

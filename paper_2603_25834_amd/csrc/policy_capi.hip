@@ -199,6 +199,14 @@ int act_core(aslam_policy* P, const float* prm, bool prepared, const int16_t* cr
   int S = 0;
   int rc = encode_fc1(P, prm, crop, scan, state, nullptr, B, st, &S);
   if (rc) return rc;
+  if (S > 8) {
+    // many split-K slices: their sum is spread over the chip first (the tail kernel has B / 16 workgroups)
+    const int64_t groups = (int64_t)B * (kHid / 8);
+    k_reduce_bias_relu_bf16_q<<<(unsigned)((groups + 63) / 64), 256, 0, st>>>(P->part, S, B, kHid, prm + P->off.f1b,
+                                                                              P->h1, kHid);
+    PCHK(hipGetLastError());
+    S = 0;
+  }
   k_fwd_tail<<<(B + kTailRows - 1) / kTailRows, 256, 0, st>>>(prm, P->off, P->part, S, P->h1, P->w2b, B, mu, value,
                                                               eps, act, logp);
   PCHK(hipGetLastError());
@@ -464,6 +472,13 @@ int aslam_policy_act_rnn(aslam_policy* P, const float* params, int32_t prepared,
   int S = 0;
   int rc = encode_fc1(P, params, crop, scan, state, nullptr, batch, st, &S);
   if (rc) return rc;
+  if (S > 8) {   // as in act_core: many slices are summed over the whole chip first
+    const int64_t groups = (int64_t)batch * (kHid / 8);
+    k_reduce_bias_relu_bf16_q<<<(unsigned)((groups + 63) / 64), 256, 0, st>>>(P->part, S, batch, kHid,
+                                                                              params + P->off.f1b, P->h1, kHid);
+    PCHK(hipGetLastError());
+    S = 0;
+  }
   GruFwdArgs a{};
   a.prm = params; a.o = P->off; a.rows = batch; a.s0 = 0;
   a.part = P->part; a.S = S; a.part_rows = batch; a.h1 = P->h1;

@@ -447,6 +447,38 @@ __global__ void k_reduce_bias_relu_bf16(const float* part, int S, int M, int N, 
   }
 }
 
+// The same for many slices (a small batch split many ways): each wave sums a quarter of the slices
+// for 64 consecutive 8-column groups, and wave 0 adds the four quarters in order.
+__global__ __launch_bounds__(256) void k_reduce_bias_relu_bf16_q(const float* part, int S, int M, int N,
+                                                                 const float* bias, uint16_t* out, int64_t ldo) {
+  __shared__ float s_q[3][64][9];
+  const int64_t groups = (int64_t)M * (N / 8);
+  const int64_t g = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
+  const int q = threadIdx.x >> 6, sq = (S + 3) / 4;
+  const int z0 = min(S, q * sq), z1 = min(S, z0 + sq);
+  const int64_t m = g / (N / 8);
+  const int n0 = (int)(g - m * (N / 8)) * 8;
+  float a[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) a[j] = 0.0f;
+  if (g < groups) sum_slices8(part + (int64_t)z0 * M * N + m * N + n0, z1 - z0, (int64_t)M * N, a);
+  if (q > 0) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) s_q[q - 1][threadIdx.x & 63][j] = a[j];
+  }
+  __syncthreads();
+  if (q == 0 && g < groups) {
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) a[j] += s_q[r][threadIdx.x][j];
+    uint16_t h[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) h[j] = f2bf(fmaxf(a[j] + bias[n0 + j], 0.0f));
+    *reinterpret_cast<uint4*>(out + m * ldo + n0) = pack8(h);
+  }
+}
+
 // Launch helper: outputs in groups of four, S split over the remaining lanes.
 inline hipError_t launch_reduce(const float* part, int S, int64_t count, float* dst, int map, int64_t slice,
                                 hipStream_t st) {
