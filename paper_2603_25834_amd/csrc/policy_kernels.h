@@ -479,11 +479,14 @@ __global__ __launch_bounds__(256) void k_reduce_bias_relu_bf16_q(const float* pa
   }
 }
 
-// Launch helper: outputs in groups of four, S split over the remaining lanes.
+// Launch helper: outputs in groups of four, S split over the remaining lanes.  Large outputs
+// (at least 2048 workgroups with every lane on its own group) give each lane a group and all the
+// slices, so a wave reads 1 KB contiguous per slice; otherwise 16 groups x 16 lanes, fewer groups
+// for tiny outputs.
 inline hipError_t launch_reduce(const float* part, int S, int64_t count, float* dst, int map, int64_t slice,
                                 hipStream_t st) {
-  int cx_log2 = 4;   // 16 groups x 16 lanes
   const int64_t groups = (count + 3) / 4;
+  int cx_log2 = groups >= 2048LL * kReduceThreads ? 8 : 4;
   while (cx_log2 > 0 && (1LL << (cx_log2 - 1)) >= groups) --cx_log2;
   const int64_t blocks = (groups + (1LL << cx_log2) - 1) >> cx_log2;
   k_reduce<<<(unsigned)blocks, kReduceThreads, 0, st>>>(part, S, count, dst, map, slice, cx_log2);
