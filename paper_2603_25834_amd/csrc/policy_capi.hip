@@ -472,21 +472,26 @@ int aslam_policy_act_rnn(aslam_policy* P, const float* params, int32_t prepared,
   int S = 0;
   int rc = encode_fc1(P, params, crop, scan, state, nullptr, batch, st, &S);
   if (rc) return rc;
-  if (S > 8) {   // as in act_core: many slices are summed over the whole chip first
+  if (S > 0) {   // the split-K slices summed over the whole chip first (h1 = bf16(relu(. + b1)))
     const int64_t groups = (int64_t)batch * (kHid / 8);
-    k_reduce_bias_relu_bf16_q<<<(unsigned)((groups + 63) / 64), 256, 0, st>>>(P->part, S, batch, kHid,
-                                                                              params + P->off.f1b, P->h1, kHid);
+    if (S > 8)
+      k_reduce_bias_relu_bf16_q<<<(unsigned)((groups + 63) / 64), 256, 0, st>>>(P->part, S, batch, kHid,
+                                                                                params + P->off.f1b, P->h1, kHid);
+    else
+      k_reduce_bias_relu_bf16<<<(int)std::min<int64_t>(4096, (groups + 255) / 256), 256, 0, st>>>(
+          P->part, S, batch, kHid, params + P->off.f1b, P->h1, kHid);
     PCHK(hipGetLastError());
-    S = 0;
   }
+  // the step writes the new state to a workspace (h_out may alias h_in); the heads copy it out
   GruFwdArgs a{};
   a.prm = params; a.o = P->off; a.rows = batch; a.s0 = 0;
-  a.part = P->part; a.S = S; a.part_rows = batch; a.h1 = P->h1;
+  a.h1 = P->h1;
   a.wih = P->wihb; a.whh = P->whhb;
   a.hp = h_in; a.hp_map = nullptr; a.first = first; a.first_map = nullptr;
-  a.h_out = h_out;
-  a.mu = mu; a.value = value; a.eps = eps; a.act = act; a.logp = logp;
-  k_gru_fwd<true><<<(batch + kGruRows - 1) / kGruRows, 256, 0, st>>>(a);
+  a.h_out = P->hst;
+  k_gru_fwd<false><<<dim3((batch + kGruRows - 1) / kGruRows, kGruSlices), 256, 0, st>>>(a);
+  PCHK(hipGetLastError());
+  k_gru_heads<<<(batch + 3) / 4, 256, 0, st>>>(params, P->off, P->hst, batch, h_out, mu, value, eps, act, logp);
   PCHK(hipGetLastError());
   return ASL_OK;
 }
@@ -522,14 +527,14 @@ int aslam_policy_backward_seq(aslam_policy* P, const float* params, const int16_
   for (int t = 0; t < T; ++t) {
     GruFwdArgs a{};
     a.prm = params; a.o = o; a.rows = nb; a.s0 = (int64_t)t * nb;
-    a.part = nullptr; a.S = 0; a.part_rows = 0; a.h1 = P->h1;
+    a.h1 = P->h1;
     a.wih = P->wihb; a.whh = P->whhb;
     a.hp = t == 0 ? h0 : P->hst + (int64_t)(t - 1) * nb * kHid;
     a.hp_map = t == 0 ? robots : nullptr;
     a.first = first + (int64_t)t * N; a.first_map = robots;
     a.h_out = P->hst;
     a.g_r = P->g_r; a.g_z = P->g_z; a.g_n = P->g_n; a.g_ghn = P->g_ghn; a.hp_used = P->hp_used; a.hp_bf = P->hp_bf;
-    k_gru_fwd_train<<<grid, 256, 0, st>>>(a);
+    k_gru_fwd<true><<<grid, 256, 0, st>>>(a);
     PCHK(hipGetLastError());
   }
   // heads + loss on every sample -> dh (FP32), head / log-std partial sums
