@@ -49,14 +49,30 @@ __device__ __forceinline__ float sigmoidf_(float x) { return 1.0f / (1.0f + expf
 
 // One GRU step over rows s0 .. s0 + rows - 1; with TRAIN also the gate values the backward reads.
 // h_out must not alias hp (other workgroups of the tile still read the entering state).
+// The lane's weight fragments (unit u, gate g, k-step s) of a [768][256] BF16 matrix, all loads
+// issued together: the step is latency-bound, so its 24 fragments cost one memory round trip.
+__device__ __forceinline__ void gru_weight_frags(const uint16_t* w, int64_t u, int lg, gemm::bf16x8 (&f)[3][8]) {
+#pragma unroll
+  for (int g = 0; g < 3; ++g)
+#pragma unroll
+    for (int s = 0; s < 8; ++s)
+      f[g][s] = __builtin_bit_cast(gemm::bf16x8,
+                                   *reinterpret_cast<const uint4*>(w + (u + g * kHid) * kHid + 32 * s + 8 * lg));
+}
+
 template <bool TRAIN>
-__global__ __launch_bounds__(256) void k_gru_fwd(GruFwdArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_gru_fwd(GruFwdArgs a) {
   __shared__ __align__(16) uint16_t s_x[kGruRows * kGruLdX];
   __shared__ __align__(16) uint16_t s_hb[kGruRows * kGruLdX];
   __shared__ __align__(16) float s_hp[kGruRows * kGruLdF];
   const int row0 = blockIdx.x * kGruRows;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
   const Offsets& o = a.o;
+  const int64_t u = 64 * blockIdx.y + 16 * wave + lr;
+  gemm::bf16x8 wi[3][8], wh[3][8];
+  gru_weight_frags(a.wih, u, lg, wi);
+  gru_weight_frags(a.whh, u, lg, wh);
+#pragma unroll
   for (int g = threadIdx.x; g < kGruRows * (kHid / 8); g += 256) {
     const int r = g / (kHid / 8), n0 = (g % (kHid / 8)) * 8;
     const int i = row0 + r;
@@ -83,33 +99,22 @@ __global__ __launch_bounds__(256) void k_gru_fwd(GruFwdArgs a) {
   }
   __syncthreads();
   // r and z accumulate the input and the state part in one accumulator (input first); n keeps them apart
-  const int64_t u = 64 * blockIdx.y + 16 * wave + lr;
   gemm::f32x4 ar = {0.f, 0.f, 0.f, 0.f}, az = ar, an = ar, ahn = ar;
 #pragma unroll
-  for (int k0 = 0; k0 < kHid; k0 += 32) {
-    const int kk = k0 + 8 * lg;
-    const auto ax = __builtin_bit_cast(gemm::bf16x8, *reinterpret_cast<const uint4*>(s_x + lr * kGruLdX + kk));
-    ar = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-        ax, __builtin_bit_cast(gemm::bf16x8, *reinterpret_cast<const uint4*>(a.wih + u * kHid + kk)), ar, 0, 0, 0);
-    az = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-        ax, __builtin_bit_cast(gemm::bf16x8, *reinterpret_cast<const uint4*>(a.wih + (u + kHid) * kHid + kk)), az,
-        0, 0, 0);
-    an = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-        ax, __builtin_bit_cast(gemm::bf16x8, *reinterpret_cast<const uint4*>(a.wih + (u + 2 * kHid) * kHid + kk)),
-        an, 0, 0, 0);
+  for (int s = 0; s < 8; ++s) {
+    const auto ax =
+        __builtin_bit_cast(gemm::bf16x8, *reinterpret_cast<const uint4*>(s_x + lr * kGruLdX + 32 * s + 8 * lg));
+    ar = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ax, wi[0][s], ar, 0, 0, 0);
+    az = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ax, wi[1][s], az, 0, 0, 0);
+    an = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ax, wi[2][s], an, 0, 0, 0);
   }
 #pragma unroll
-  for (int k0 = 0; k0 < kHid; k0 += 32) {
-    const int kk = k0 + 8 * lg;
-    const auto ah = __builtin_bit_cast(gemm::bf16x8, *reinterpret_cast<const uint4*>(s_hb + lr * kGruLdX + kk));
-    ar = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-        ah, __builtin_bit_cast(gemm::bf16x8, *reinterpret_cast<const uint4*>(a.whh + u * kHid + kk)), ar, 0, 0, 0);
-    az = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-        ah, __builtin_bit_cast(gemm::bf16x8, *reinterpret_cast<const uint4*>(a.whh + (u + kHid) * kHid + kk)), az,
-        0, 0, 0);
-    ahn = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-        ah, __builtin_bit_cast(gemm::bf16x8, *reinterpret_cast<const uint4*>(a.whh + (u + 2 * kHid) * kHid + kk)),
-        ahn, 0, 0, 0);
+  for (int s = 0; s < 8; ++s) {
+    const auto ah =
+        __builtin_bit_cast(gemm::bf16x8, *reinterpret_cast<const uint4*>(s_hb + lr * kGruLdX + 32 * s + 8 * lg));
+    ar = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, wh[0][s], ar, 0, 0, 0);
+    az = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, wh[1][s], az, 0, 0, 0);
+    ahn = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, wh[2][s], ahn, 0, 0, 0);
   }
   // gates and the new state: lane holds unit u of rows 4 lg + e
   const float* bi = a.prm + o.gbi;
@@ -199,50 +204,68 @@ struct GruBwdArgs {
 
 // gridDim.y = kGruSlices workgroups share a row tile: each forms the tile's gate gradients (slice 0
 // alone writes them out) and the state gradient for its 64 columns.
-__global__ __launch_bounds__(256) void k_gru_bwd_step(GruBwdArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_gru_bwd_step(GruBwdArgs a) {
   __shared__ __align__(16) uint16_t s_g[kGruRows * kGruLdG];
   __shared__ __align__(16) float s_d[kGruRows * kGruLdF];
   const int row0 = blockIdx.x * kGruRows;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
+  // W_hh^T fragments of this lane's output column n (k-steps of 32 over the 768 gate rows), loaded
+  // first so that they arrive while the gate gradients are formed
+  const int64_t n = 64 * blockIdx.y + 16 * wave + lr;
+  gemm::bf16x8 wf[kGates / 32];
+#pragma unroll
+  for (int s = 0; s < kGates / 32; ++s)
+    wf[s] = __builtin_bit_cast(gemm::bf16x8, *reinterpret_cast<const uint4*>(a.whht + n * kGates + 32 * s + 8 * lg));
   const int u = threadIdx.x;   // one unit per thread
-  for (int r = 0; r < kGruRows; ++r) {
-    const int i = row0 + r;
-    float dr = 0.f, dz = 0.f, dn = 0.f, dnr = 0.f, dd = 0.f;
-    if (i < a.rows) {
-      const int64_t q = (a.s0 + i) * kHid + u;
-      const float dh = a.dh_head[q] + (a.dh_next ? a.dh_next[(int64_t)i * kHid + u] : 0.0f);
-      const float rg = a.g_r[q], zg = a.g_z[q], ng = a.g_n[q], ghn = a.g_ghn[q], hp = a.hp_used[q];
-      dd = dh * zg;
-      const float dn_pre = (dh * (1.0f - zg)) * (1.0f - ng * ng);
-      dz = (dh * (hp - ng)) * (zg * (1.0f - zg));
-      dr = (dn_pre * ghn) * (rg * (1.0f - rg));
-      dn = dn_pre;
-      dnr = dn_pre * rg;
-      if (blockIdx.y == 0) {
-        const int64_t g = (a.s0 + i) * kGates + u;
-        a.dgi[g] = f2bf(dr);
-        a.dgi[g + kHid] = f2bf(dz);
-        a.dgi[g + 2 * kHid] = f2bf(dn);
-        a.dgh[g] = f2bf(dr);
-        a.dgh[g + kHid] = f2bf(dz);
-        a.dgh[g + 2 * kHid] = f2bf(dnr);
+  // the rows four at a time, so that their loads are in flight together
+#pragma unroll
+  for (int r0 = 0; r0 < kGruRows; r0 += 4) {
+    float dh[4], rg[4], zg[4], ng[4], ghn[4], hp[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int i = row0 + r0 + e;
+      dh[e] = rg[e] = zg[e] = ng[e] = ghn[e] = hp[e] = 0.0f;
+      if (i < a.rows) {
+        const int64_t q = (a.s0 + i) * kHid + u;
+        dh[e] = a.dh_head[q] + (a.dh_next ? a.dh_next[(int64_t)i * kHid + u] : 0.0f);
+        rg[e] = a.g_r[q]; zg[e] = a.g_z[q]; ng[e] = a.g_n[q]; ghn[e] = a.g_ghn[q]; hp[e] = a.hp_used[q];
       }
     }
-    s_g[r * kGruLdG + u] = f2bf(dr);
-    s_g[r * kGruLdG + u + kHid] = f2bf(dz);
-    s_g[r * kGruLdG + u + 2 * kHid] = f2bf(dnr);
-    s_d[r * kGruLdF + u] = dd;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int r = r0 + e, i = row0 + r;
+      float dr = 0.f, dz = 0.f, dn = 0.f, dnr = 0.f, dd = 0.f;
+      if (i < a.rows) {
+        dd = dh[e] * zg[e];
+        const float dn_pre = (dh[e] * (1.0f - zg[e])) * (1.0f - ng[e] * ng[e]);
+        dz = (dh[e] * (hp[e] - ng[e])) * (zg[e] * (1.0f - zg[e]));
+        dr = (dn_pre * ghn[e]) * (rg[e] * (1.0f - rg[e]));
+        dn = dn_pre;
+        dnr = dn_pre * rg[e];
+        if (blockIdx.y == 0) {
+          const int64_t g = (a.s0 + i) * kGates + u;
+          a.dgi[g] = f2bf(dr);
+          a.dgi[g + kHid] = f2bf(dz);
+          a.dgi[g + 2 * kHid] = f2bf(dn);
+          a.dgh[g] = f2bf(dr);
+          a.dgh[g + kHid] = f2bf(dz);
+          a.dgh[g + 2 * kHid] = f2bf(dnr);
+        }
+      }
+      s_g[r * kGruLdG + u] = f2bf(dr);
+      s_g[r * kGruLdG + u + kHid] = f2bf(dz);
+      s_g[r * kGruLdG + u + 2 * kHid] = f2bf(dnr);
+      s_d[r * kGruLdF + u] = dd;
+    }
   }
   __syncthreads();
   // dgh [16 x 768] x W_hh [768 x 256]: this workgroup's columns 64 y .. 64 y + 63, 16 per wave
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
-  const int64_t n = 64 * blockIdx.y + 16 * wave + lr;
   gemm::f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll 8
-  for (int k0 = 0; k0 < kGates; k0 += 32) {
-    const int kk = k0 + 8 * lg;
-    const gemm::bf16x8 ag = __builtin_bit_cast(gemm::bf16x8, *reinterpret_cast<const uint4*>(s_g + lr * kGruLdG + kk));
-    const auto wb = __builtin_bit_cast(gemm::bf16x8, *reinterpret_cast<const uint4*>(a.whht + n * kGates + kk));
-    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ag, wb, acc, 0, 0, 0);
+#pragma unroll
+  for (int s = 0; s < kGates / 32; ++s) {
+    const gemm::bf16x8 ag =
+        __builtin_bit_cast(gemm::bf16x8, *reinterpret_cast<const uint4*>(s_g + lr * kGruLdG + 32 * s + 8 * lg));
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ag, wf[s], acc, 0, 0, 0);
   }
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
