@@ -1012,37 +1012,47 @@ __global__ __launch_bounds__(NT, 4) void k_fused_persist(EnvParams P, StepArgs A
   }
 }
 
+// Robot r = blockIdx.x; its maps are cleared by gridDim.y workgroups, each taking a contiguous
+// share; workgroup y = 0 also resets the per-robot state.
 template <bool kVecSrc>   // world_src on a 16-byte boundary: the world copy in 16-byte vectors
 __global__ void k_reset(EnvParams P, const uint32_t* world_src, const float* init_pose, const uint8_t* mask) {
   const int32_t r = blockIdx.x;
   if (mask && !mask[r]) return;
   const RobotMeta m = P.meta[r];
   const int32_t s = m.side;
+  const int64_t ny = gridDim.y, y = blockIdx.y;
+  auto share = [&](int64_t total, int64_t& b, int64_t& e) {
+    const int64_t per = (total + ny - 1) / ny;
+    b = min(total, y * per);
+    e = min(total, b + per);
+  };
+  int64_t b0, e0;
   // sides are multiples of 32, so a robot's map (s^2 int16) and world (s^2 / 32 words) are whole 16-byte
   // vectors starting on 16-byte boundaries
   uint4* bel = reinterpret_cast<uint4*>(P.belief + m.cell_off);
-  const int64_t nvec = (int64_t)s * s / 8;
-  for (int64_t k = threadIdx.x; k < nvec; k += blockDim.x) bel[k] = make_uint4(0u, 0u, 0u, 0u);
+  share((int64_t)s * s / 8, b0, e0);
+  for (int64_t k = b0 + threadIdx.x; k < e0; k += blockDim.x) bel[k] = make_uint4(0u, 0u, 0u, 0u);
   if (kVecSrc) {
-    const int64_t nw = (int64_t)s * s / 128;
     uint4* wd = reinterpret_cast<uint4*>(const_cast<uint32_t*>(P.world) + m.world_off);
     const uint4* ws = reinterpret_cast<const uint4*>(world_src + m.world_off);
-    for (int64_t k = threadIdx.x; k < nw; k += blockDim.x) wd[k] = ws[k];
+    share((int64_t)s * s / 128, b0, e0);
+    for (int64_t k = b0 + threadIdx.x; k < e0; k += blockDim.x) wd[k] = ws[k];
   } else {
-    const int64_t nw = (int64_t)s * s / 32;
     uint32_t* wd = const_cast<uint32_t*>(P.world) + m.world_off;
     const uint32_t* ws = world_src + m.world_off;
-    for (int64_t k = threadIdx.x; k < nw; k += blockDim.x) wd[k] = ws[k];
+    share((int64_t)s * s / 32, b0, e0);
+    for (int64_t k = b0 + threadIdx.x; k < e0; k += blockDim.x) wd[k] = ws[k];
   }
   if (P.uses_visits) {
-    const int64_t nv = (int64_t)m.visit_side * m.visit_side;
-    for (int64_t k = threadIdx.x; k < nv; k += blockDim.x) {
+    share((int64_t)m.visit_side * m.visit_side, b0, e0);
+    for (int64_t k = b0 + threadIdx.x; k < e0; k += blockDim.x) {
       P.visit_t[m.visit_off + k] = -1;
       P.visit_xy[2 * (m.visit_off + k)] = 0.0f;
       P.visit_xy[2 * (m.visit_off + k) + 1] = 0.0f;
       P.visit_last[m.visit_off + k] = -1;
     }
   }
+  if (y != 0) return;
   if (threadIdx.x == 0) {
     for (int k = 0; k < 3; ++k) {
       P.pose[3 * (int64_t)r + k] = init_pose[3 * (int64_t)r + k];
@@ -1154,10 +1164,13 @@ hipError_t set_lds_nt(int bytes) {
 
 }  // namespace
 
+constexpr int kResetSplit = 8;   // workgroups per reset robot
+
 hipError_t launch_reset(const EnvParams& P, const uint32_t* world_src, const float* init_pose,
                         const uint8_t* mask, int32_t, hipStream_t stream) {
-  if ((reinterpret_cast<uintptr_t>(world_src) & 15) == 0) k_reset<true><<<P.n, 256, 0, stream>>>(P, world_src, init_pose, mask);
-  else k_reset<false><<<P.n, 256, 0, stream>>>(P, world_src, init_pose, mask);
+  const dim3 grid(P.n, kResetSplit);
+  if ((reinterpret_cast<uintptr_t>(world_src) & 15) == 0) k_reset<true><<<grid, 256, 0, stream>>>(P, world_src, init_pose, mask);
+  else k_reset<false><<<grid, 256, 0, stream>>>(P, world_src, init_pose, mask);
   return hipGetLastError();
 }
 
