@@ -234,10 +234,28 @@ __global__ __launch_bounds__(256) void k_heads(const float* prm, Offsets o, cons
   float gw0[4] = {0, 0, 0, 0}, gw1[4] = {0, 0, 0, 0}, gwv[4] = {0, 0, 0, 0}, gb2[4] = {0, 0, 0, 0};
   float gbm0 = 0, gbm1 = 0, gbv = 0, gls0 = 0, gls1 = 0, lclip = 0, lval = 0;
   const float log2pi = 1.8378770664093453f;
-  for (int rr = 0; rr < kHeadRows / 4; ++rr) {
-    const int row = blockIdx.x * kHeadRows + wave * (kHeadRows / 4) + rr;
+  // the wave's 16 rows: lane j < 16 fetches row j's rollout data up front (handed out by shuffles), and
+  // all 16 rows of z2 are loaded up front (one memory round trip for the wave)
+  constexpr int kWaveRows = kHeadRows / 4;
+  const int wrow0 = blockIdx.x * kHeadRows + wave * kWaveRows;
+  float q_a0 = 0.f, q_a1 = 0.f, q_olp = 0.f, q_adv = 0.f, q_ret = 0.f;
+  if (GRAD && lane < kWaveRows && wrow0 + lane < B) {
+    const int64_t sr = rows ? (int64_t)rows[wrow0 + lane] : (int64_t)(wrow0 + lane);
+    q_a0 = act[2 * sr];
+    q_a1 = act[2 * sr + 1];
+    q_olp = old_logp[sr];
+    q_adv = adv[sr];
+    q_ret = ret[sr];
+  }
+  float4 zr[kWaveRows];
+#pragma unroll
+  for (int rr = 0; rr < kWaveRows; ++rr)
+    zr[rr] = *reinterpret_cast<const float4*>(z2 + (int64_t)min(wrow0 + rr, B - 1) * kHid + lane * 4);
+#pragma unroll
+  for (int rr = 0; rr < kWaveRows; ++rr) {
+    const int row = wrow0 + rr;
     if (row >= B) break;
-    const float4 zz = *reinterpret_cast<const float4*>(z2 + (int64_t)row * kHid + lane * 4);
+    const float4 zz = zr[rr];
     const float z[4] = {zz.x, zz.y, zz.z, zz.w};
     float h[4], s0 = 0, s1 = 0, sv = 0;
 #pragma unroll
@@ -262,20 +280,20 @@ __global__ __launch_bounds__(256) void k_heads(const float* prm, Offsets o, cons
       }
       continue;
     }
-    // PPO loss of this row (Eqs. 18-20) with value and entropy terms; its rollout data at row rows[row]
-    const int64_t sr = rows ? (int64_t)rows[row] : (int64_t)row;
+    // PPO loss of this row (Eqs. 18-20) with value and entropy terms; its rollout data (row rows[row])
+    const float a0 = __shfl(q_a0, rr, 64), a1 = __shfl(q_a1, rr, 64), olp = __shfl(q_olp, rr, 64);
+    const float A = __shfl(q_adv, rr, 64), rt = __shfl(q_ret, rr, 64);
     const float is0 = expf(-ls0), is1 = expf(-ls1);
-    const float u0 = (act[2 * sr] - m0) * is0, u1 = (act[2 * sr + 1] - m1) * is1;
+    const float u0 = (a0 - m0) * is0, u1 = (a1 - m1) * is1;
     const float logp = -0.5f * (u0 * u0 + u1 * u1) - (ls0 + ls1) - log2pi;
-    const float ratio = expf(logp - old_logp[sr]);
-    const float A = adv[sr];
+    const float ratio = expf(logp - olp);
     const float clipped = fminf(fmaxf(ratio, 1.0f - lc.eps), 1.0f + lc.eps);
     const float surr = fminf(ratio * A, clipped * A);
     // d(-surr)/dlogp is -A*ratio when the unclipped term is the minimum, else 0
     const bool active = ratio * A <= clipped * A;
     const float g_logp = active ? -A * ratio * lc.inv_b : 0.0f;
     const float dm0 = g_logp * (u0 * is0), dm1 = g_logp * (u1 * is1);
-    const float dV = lc.c_v * 2.0f * (val - ret[sr]) * lc.inv_b;
+    const float dV = lc.c_v * 2.0f * (val - rt) * lc.inv_b;
     if (lane == 0) {
       gls0 += g_logp * (u0 * u0 - 1.0f);
       gls1 += g_logp * (u1 * u1 - 1.0f);
@@ -283,7 +301,7 @@ __global__ __launch_bounds__(256) void k_heads(const float* prm, Offsets o, cons
       gbm1 += dm1;
       gbv += dV;
       lclip += -surr * lc.inv_b;
-      lval += (val - ret[sr]) * (val - ret[sr]) * lc.inv_b;
+      lval += (val - rt) * (val - rt) * lc.inv_b;
     }
     uint32_t dzp[2];
     float dhv[4];
