@@ -330,6 +330,68 @@ int aslam_policy_sample(aslam_policy* pol, const float* params_dev, const float*
 int aslam_gather_rows(const void* src_dev, int64_t row_bytes, const int32_t* idx_dev, int32_t n, void* dst_dev,
                       aslam_stream_t stream);
 
+/* ------------------------------------------------------------------ fixed-lag SLAM backbone
+ *
+ * The pose estimator of Sec. III-D as three batched calls: correlative scan matching of each
+ * robot's scan against its log-odds grid, the scan factor of the match, and the Gauss-Newton solve of
+ * a sliding window of poses with the newest pose's covariance.  The paper gives the method but not its
+ * constants or exact rules; the rules below are this library's reading of it. */
+
+typedef struct {
+  int32_t W;          /* translation half-width of the candidate lattice, in steps, 0..8 */
+  int32_t V;          /* heading half-width, in steps, 0..8 */
+  int32_t step_xy_q;  /* translation step, Q16 cells (65536 = one cell), 1..2^20 */
+  int32_t step_h;     /* heading step, in steps of the 46080-per-turn heading table, 0..46080 */
+} aslam_csm_config;
+
+/* Correlative scan matching (Sec. III-D, "a discretized neighborhood ... evaluated against the
+ * log-odds occupancy grid") for n robots, one workgroup each, exact integer arithmetic.
+ *   belief_dev   int16 log-odds; robot r's s x s grid starts at element cell_off_dev[r] (int64 [n]),
+ *                cell (cx, cy) at cy * s + cx, s = side_dev[r] (int32 [n]);
+ *   pose_q_dev   int32 [n,3]: predicted pose, x and y in Q16 cells, heading index in [0, 46080);
+ *   rho_q_dev    int32 [n,R]: ray ranges in Q16 cells, < 0 = no return;
+ *   a_off_dev    int32 [R]: ray heading offsets (table steps) relative to the robot heading.
+ * The endpoint of ray q under pose (x, y, h) is x + ((rho * cos_q) >> 14), y + ((rho * sin_q) >> 14)
+ * with (cos_q, sin_q) the Q14 table direction of (h + a_off) mod 46080 (cos, sin of 2 pi k / 46080
+ * rounded to the nearest 1/16384); its cell is (ex >> 16, ey >> 16).  Candidate (i, j, k), |i|,|j| <= W,
+ * |k| <= V, is (x + i step_xy_q, y + j step_xy_q, h + k step_h); its score is the int32 sum of the
+ * log-odds of its rays' endpoint cells inside the grid.  out_dev int32 [n,6]: best i, j, k (highest
+ * score, lowest index ((k+V)(2W+1) + j+W)(2W+1) + i+W on ties), best score, second score (highest at
+ * lattice Chebyshev distance >= 2 from the best; INT32_MIN if none), rays with a return.
+ * Device arrays are not checked: the caller guarantees grids inside belief_dev, 0 <= rho_q < 2^31.
+ * ASL_EINVAL on NULL pointers, n < 0 or a config outside the ranges above, or (2V + 1) R > 8192. */
+int aslam_csm_match(const int16_t* belief_dev, const int64_t* cell_off_dev, const int32_t* side_dev, int32_t n,
+                    const int32_t* pose_q_dev, const int32_t* rho_q_dev, int32_t R, const int32_t* a_off_dev,
+                    const aslam_csm_config* cfg, int32_t* out_dev, aslam_stream_t stream);
+
+/* The scan factor of a match (Sec. III-D: an absolute pose measurement whose information is scaled
+ * by the normalised score and the ambiguity margin).  match_dev int32 [n,6] (aslam_csm_match's output),
+ * pose_q_dev the poses it was matched around.  meas_dev double [n,3]: the best candidate in metres /
+ * radians (theta wrapped to [-pi, pi]); info_dev double [n,3]: the information diagonal
+ * w (1 / sigma_xy^2, 1 / sigma_xy^2, 1 / sigma_th^2), w = q m, q = clamp(best / (rays * l_max), 0, 1),
+ * m = clamp((best - second) / max(best, 1), 0, 1).  ASL_EINVAL on NULL pointers or non-positive scales. */
+int aslam_csm_factor(const int32_t* match_dev, const int32_t* pose_q_dev, int32_t n, const aslam_csm_config* cfg,
+                     double cell_m, double l_max, double sigma_xy, double sigma_th, double* meas_dev,
+                     double* info_dev, aslam_stream_t stream);
+
+/* Doubles of workspace aslam_fixedlag_solve needs for n windows of L poses (21 n L); -1 on bad sizes. */
+int64_t aslam_fixedlag_work_doubles(int32_t n, int32_t L);
+
+/* Fixed-lag pose graph (Sec. III-D; the minimisation of the weighted residuals and the covariance
+ * of the newest pose as the last block of the inverse Gauss-Newton Hessian), n windows of L poses in
+ * FP64, one thread each.  Factors: a prior on pose 0, prior_dev [n,6] (mean x, y, theta; information
+ * diagonal); odometry between poses i and i+1, odo_dev [n,L-1,6] (the motion in the frame of pose i,
+ * residual (R(th_i)^T (t_{i+1} - t_i) - u_t, wrap(th_{i+1} - th_i - u_th)); information diagonal; may
+ * be NULL when L = 1); scan factors scan_dev [n,L,6] (measurement; information diagonal, all zero = no
+ * factor).  From x0_dev [n,L,3] it takes `iters` Gauss-Newton steps (analytic Jacobians, block
+ * elimination of the block-tridiagonal normal equations) into x_dev [n,L,3], then writes the newest
+ * pose's covariance, formed at the result, to cov_dev [n,3,3].  work_dev: caller-owned scratch of
+ * aslam_fixedlag_work_doubles(n, L) doubles.  ASL_EINVAL on NULL pointers, n < 0, L outside [1, 64] or
+ * iters outside [0, 100].  A singular window (no prior information) gives non-finite results. */
+int aslam_fixedlag_solve(int32_t n, int32_t L, const double* x0_dev, const double* prior_dev, const double* odo_dev,
+                         const double* scan_dev, int32_t iters, double* x_dev, double* cov_dev, double* work_dev,
+                         aslam_stream_t stream);
+
 /* ------------------------------------------------------------------ misc */
 
 const char* aslam_last_error(void);

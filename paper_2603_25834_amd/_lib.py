@@ -46,6 +46,10 @@ class EnvConfig(ctypes.Structure):
     ]
 
 
+class CsmConfig(ctypes.Structure):
+    _fields_ = [("W", ctypes.c_int32), ("V", ctypes.c_int32), ("step_xy_q", ctypes.c_int32), ("step_h", ctypes.c_int32)]
+
+
 class ExecConfig(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in ("form", "threads", "band_rows", "grid", "record_rays", "lds_bytes")]
 
@@ -90,6 +94,11 @@ SIGNATURES = {
     "aslam_gae": (ctypes.c_int, [_P, _P, _P, _P, _I32, _I32, ctypes.c_float, ctypes.c_float, _P, _P, _P]),
     "aslam_adam": (ctypes.c_int, [_P, _P, _P, _P, _I64, _I32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                   ctypes.c_float, _P]),
+    "aslam_csm_match": (ctypes.c_int, [_P, _P, _P, _I32, _P, _P, _I32, _P, ctypes.POINTER(CsmConfig), _P, _P]),
+    "aslam_csm_factor": (ctypes.c_int, [_P, _P, _I32, ctypes.POINTER(CsmConfig), ctypes.c_double, ctypes.c_double,
+                                        ctypes.c_double, ctypes.c_double, _P, _P, _P]),
+    "aslam_fixedlag_work_doubles": (_I64, [_I32, _I32]),
+    "aslam_fixedlag_solve": (ctypes.c_int, [_I32, _I32, _P, _P, _P, _P, _I32, _P, _P, _P, _P]),
 }
 
 _lib = None

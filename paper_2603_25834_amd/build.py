@@ -15,7 +15,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libaslam.so")
 
-SOURCES = ["capi.hip", "env_kernels.hip", "policy_capi.hip"]
+SOURCES = ["capi.hip", "env_kernels.hip", "policy_capi.hip", "slam.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -1,0 +1,462 @@
+// slam.hip -- the fixed-lag SLAM backbone on gfx950 (arXiv 2603.25834, Sec. III-D).
+//
+// Three batched calls, one robot per workgroup or thread:
+//  * correlative scan matching: every candidate of a (dx, dy, dheading) lattice around the predicted
+//    pose scored against the robot's int16 log-odds grid -- exact integer arithmetic (Q16 positions,
+//    the Q14 heading table), so results equal the definition bit for bit;
+//  * the scan factor of a match: the best pose and an information matrix scaled by the normalised
+//    score and the margin to the second-best separate peak;
+//  * the fixed-lag pose graph: a few Gauss-Newton steps over a window of L poses (a prior on the
+//    oldest, odometry factors between neighbours, unary scan factors) in FP64, solved by block
+//    elimination of the block-tridiagonal normal equations; the newest pose's marginal covariance,
+//    the last diagonal block of the inverse Hessian, is the inverse of the last Schur complement.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "aslam.h"
+#include "env_internal.h"
+
+namespace aslam {
+void set_last_error(const std::string& msg);
+}
+
+namespace {
+
+using aslam::kDirOne;
+using aslam::kNang;
+
+int sfail(int code, const std::string& m) {
+  aslam::set_last_error(m);
+  return code;
+}
+
+#define SCHK(call)                                                            \
+  do {                                                                        \
+    hipError_t e_ = (call);                                                   \
+    if (e_ != hipSuccess) return sfail(ASL_EHIP, hipGetErrorString(e_));      \
+  } while (0)
+
+constexpr int kCsmThreads = 256;
+constexpr int kCsmMaxHalf = 8;                      // W, V <= 8
+constexpr int kCsmMaxRayHeadings = 8192;            // (2V + 1) * R ray offsets staged in LDS
+constexpr int kCsmMaxCand = (2 * kCsmMaxHalf + 1) * (2 * kCsmMaxHalf + 1) * (2 * kCsmMaxHalf + 1);
+
+// ------------------------------------------------------------------ correlative scan matching
+
+// One workgroup per robot.  Stage: the endpoint offsets (Q16) of every ray under every heading
+// candidate.  Score: each thread takes candidates t, t + 256, ... and sums the log-odds of its rays'
+// endpoint cells (rays without a return and endpoints off the grid add nothing).  Then the best
+// (highest, smallest index on ties) and the highest score at lattice Chebyshev distance >= 2 from it.
+__global__ __launch_bounds__(kCsmThreads) void k_csm(const int16_t* __restrict__ belief,
+                                                     const int64_t* __restrict__ cell_off,
+                                                     const int32_t* __restrict__ side,
+                                                     const int32_t* __restrict__ pose_q,
+                                                     const int32_t* __restrict__ rho_q, int R,
+                                                     const int32_t* __restrict__ a_off,
+                                                     const int32_t* __restrict__ dirtab, int W, int V, int step_xy,
+                                                     int step_h, int32_t* __restrict__ out) {
+  __shared__ int2 s_off[kCsmMaxRayHeadings];
+  __shared__ int32_t s_score[kCsmMaxCand];
+  __shared__ int32_t s_red[kCsmThreads / 64][2];
+  const int r = blockIdx.x;
+  const int nw = 2 * W + 1, nk = 2 * V + 1, ncand = nk * nw * nw;
+  const int32_t px = pose_q[3 * r], py = pose_q[3 * r + 1], ph = pose_q[3 * r + 2];
+  const int32_t* rho = rho_q + (int64_t)r * R;
+  int used = 0;
+  for (int e = threadIdx.x; e < nk * R; e += kCsmThreads) {
+    const int k = e / R, q = e - k * R;
+    const int32_t rq = rho[q];
+    int2 o = make_int2(INT32_MIN, 0);
+    if (rq >= 0) {
+      int64_t h = ((int64_t)ph + (int64_t)(k - V) * step_h + a_off[q]) % kNang;
+      if (h < 0) h += kNang;
+      const int32_t d = dirtab[h];
+      const int32_t c = (int32_t)(int16_t)(d & 0xffff), s = d >> 16;
+      o.x = (int32_t)(((int64_t)rq * c) >> 14);
+      o.y = (int32_t)(((int64_t)rq * s) >> 14);
+      if (k == 0) ++used;
+    }
+    s_off[e] = o;
+  }
+  __syncthreads();
+  const int32_t sd = side[r];
+  const int16_t* g = belief + cell_off[r];
+  for (int c = threadIdx.x; c < ncand; c += kCsmThreads) {
+    const int k = c / (nw * nw), rem = c - k * nw * nw, j = rem / nw, i = rem - j * nw;
+    const int64_t x = (int64_t)px + (int64_t)(i - W) * step_xy, y = (int64_t)py + (int64_t)(j - W) * step_xy;
+    const int2* o = s_off + k * R;
+    int32_t sc = 0;
+    for (int q = 0; q < R; ++q) {
+      const int2 v = o[q];
+      if (v.x == INT32_MIN) continue;
+      const int64_t cx = (x + v.x) >> 16, cy = (y + v.y) >> 16;
+      if (cx >= 0 && cx < sd && cy >= 0 && cy < sd) sc += g[cy * sd + cx];
+    }
+    s_score[c] = sc;
+  }
+  __syncthreads();
+  // best: the highest score, the smallest index on ties
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int32_t bs = INT32_MIN, bi = INT32_MAX;
+  for (int c = threadIdx.x; c < ncand; c += kCsmThreads) {
+    const int32_t v = s_score[c];
+    if (v > bs || (v == bs && c < bi)) { bs = v; bi = c; }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const int32_t os = __shfl_xor(bs, off, 64), oi = __shfl_xor(bi, off, 64);
+    if (os > bs || (os == bs && oi < bi)) { bs = os; bi = oi; }
+  }
+  if (lane == 0) { s_red[wave][0] = bs; s_red[wave][1] = bi; }
+  __syncthreads();
+  bs = s_red[0][0]; bi = s_red[0][1];
+  for (int w = 1; w < kCsmThreads / 64; ++w) {
+    const int32_t os = s_red[w][0], oi = s_red[w][1];
+    if (os > bs || (os == bs && oi < bi)) { bs = os; bi = oi; }
+  }
+  const int bk = bi / (nw * nw), brem = bi - bk * nw * nw, bj = brem / nw, bii = brem - bj * nw;
+  // second: the highest score outside the best's 3 x 3 x 3 neighbourhood
+  int32_t ss = INT32_MIN;
+  for (int c = threadIdx.x; c < ncand; c += kCsmThreads) {
+    const int k = c / (nw * nw), rem = c - k * nw * nw, j = rem / nw, i = rem - j * nw;
+    const int dist = max(max(abs(i - bii), abs(j - bj)), abs(k - bk));
+    if (dist >= 2) ss = max(ss, s_score[c]);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) ss = max(ss, __shfl_xor(ss, off, 64));
+  // rays used: counted by the threads that staged heading candidate 0
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) used += __shfl_xor(used, off, 64);
+  __syncthreads();
+  if (lane == 0) { s_red[wave][0] = ss; s_red[wave][1] = used; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int32_t s2 = s_red[0][0], u = s_red[0][1];
+    for (int w = 1; w < kCsmThreads / 64; ++w) { s2 = max(s2, s_red[w][0]); u += s_red[w][1]; }
+    int32_t* o = out + 6 * (int64_t)r;
+    o[0] = bii - W; o[1] = bj - W; o[2] = bk - V; o[3] = bs; o[4] = s2; o[5] = u;
+  }
+}
+
+// ------------------------------------------------------------------ scan factor
+
+__device__ __forceinline__ double wrap_pi(double a) {
+  const double two_pi = 6.283185307179586;
+  return a - two_pi * rint(a / two_pi);
+}
+
+__global__ void k_csm_factor(const int32_t* __restrict__ match, const int32_t* __restrict__ pose_q, int n,
+                             int step_xy, int step_h, double cell_m, double l_max, double sig_xy, double sig_th,
+                             double* __restrict__ meas, double* __restrict__ info) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  const int32_t* m = match + 6 * (int64_t)r;
+  const int32_t* p = pose_q + 3 * (int64_t)r;
+  const double x = (double)((int64_t)p[0] + (int64_t)m[0] * step_xy) / 65536.0 * cell_m;
+  const double y = (double)((int64_t)p[1] + (int64_t)m[1] * step_xy) / 65536.0 * cell_m;
+  int64_t h = ((int64_t)p[2] + (int64_t)m[2] * step_h) % kNang;
+  if (h < 0) h += kNang;
+  const double th = wrap_pi(2.0 * 3.141592653589793 * (double)h / (double)kNang);
+  const double best = (double)m[3], second = (double)m[4];
+  const double q = m[5] <= 0 ? 0.0 : fmin(fmax(best / ((double)m[5] * l_max), 0.0), 1.0);
+  const double mg = fmin(fmax((best - second) / fmax(best, 1.0), 0.0), 1.0);
+  const double w = q * mg;
+  meas[3 * (int64_t)r] = x; meas[3 * (int64_t)r + 1] = y; meas[3 * (int64_t)r + 2] = th;
+  info[3 * (int64_t)r] = w / (sig_xy * sig_xy);
+  info[3 * (int64_t)r + 1] = w / (sig_xy * sig_xy);
+  info[3 * (int64_t)r + 2] = w / (sig_th * sig_th);
+}
+
+// ------------------------------------------------------------------ fixed-lag Gauss-Newton
+
+struct M3 {
+  double a[3][3];
+};
+
+__device__ __forceinline__ M3 inv3(const M3& m) {
+  const double (*a)[3] = m.a;
+  const double c00 = a[1][1] * a[2][2] - a[1][2] * a[2][1];
+  const double c01 = a[1][2] * a[2][0] - a[1][0] * a[2][2];
+  const double c02 = a[1][0] * a[2][1] - a[1][1] * a[2][0];
+  const double det = a[0][0] * c00 + a[0][1] * c01 + a[0][2] * c02;
+  const double id = 1.0 / det;
+  M3 r;
+  r.a[0][0] = c00 * id;
+  r.a[0][1] = (a[0][2] * a[2][1] - a[0][1] * a[2][2]) * id;
+  r.a[0][2] = (a[0][1] * a[1][2] - a[0][2] * a[1][1]) * id;
+  r.a[1][0] = c01 * id;
+  r.a[1][1] = (a[0][0] * a[2][2] - a[0][2] * a[2][0]) * id;
+  r.a[1][2] = (a[0][2] * a[1][0] - a[0][0] * a[1][2]) * id;
+  r.a[2][0] = c02 * id;
+  r.a[2][1] = (a[0][1] * a[2][0] - a[0][0] * a[2][1]) * id;
+  r.a[2][2] = (a[0][0] * a[1][1] - a[0][1] * a[1][0]) * id;
+  return r;
+}
+
+// Odometry factor between poses xi and xj: residual, and its Jacobians Ji (wrt xi) and Jj (wrt xj).
+__device__ __forceinline__ void odo_factor(const double* xi, const double* xj, const double* u, double r[3],
+                                           double Ji[3][3], double Jj[3][3]) {
+  const double c = cos(xi[2]), s = sin(xi[2]);
+  const double dx = xj[0] - xi[0], dy = xj[1] - xi[1];
+  r[0] = (c * dx + s * dy) - u[0];
+  r[1] = (-s * dx + c * dy) - u[1];
+  r[2] = wrap_pi(xj[2] - xi[2] - u[2]);
+  Ji[0][0] = -c; Ji[0][1] = -s; Ji[0][2] = -s * dx + c * dy;
+  Ji[1][0] = s;  Ji[1][1] = -c; Ji[1][2] = -c * dx - s * dy;
+  Ji[2][0] = 0;  Ji[2][1] = 0;  Ji[2][2] = -1.0;
+  Jj[0][0] = c;  Jj[0][1] = s;  Jj[0][2] = 0;
+  Jj[1][0] = -s; Jj[1][1] = c;  Jj[1][2] = 0;
+  Jj[2][0] = 0;  Jj[2][1] = 0;  Jj[2][2] = 1.0;
+}
+
+// acc += P^T diag(w) Q (3 x 3)
+__device__ __forceinline__ void add_jtwj(double acc[3][3], const double P[3][3], const double* w, const double Q[3][3]) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      double t = 0.0;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) t += P[k][a] * w[k] * Q[k][b];
+      acc[a][b] += t;
+    }
+}
+
+__device__ __forceinline__ void add_jtwr(double* acc, const double P[3][3], const double* w, const double* rr) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    double t = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) t += P[k][a] * w[k] * rr[k];
+    acc[a] += t;
+  }
+}
+
+// Block elimination of the window's normal equations at x (the caller's [L][3]): for each pose i the
+// diagonal block A_i, the coupling B_i = H[i][i+1] and the gradient g_i are formed as the sweep reaches
+// them; D_i = A_i - B_{i-1}^T D_{i-1}^{-1} B_{i-1}, y_i = -g_i - B_{i-1}^T D_{i-1}^{-1} y_{i-1}.  Work per
+// pose: D_i^{-1} (9), C_i = D_i^{-1} B_i (9), y_i (3).  Returns D_{L-1}^{-1} in *last.
+__device__ void eliminate(const double* x, int L, const double* prior, const double* odo, const double* scan,
+                          double* work, M3* last) {
+  double Bprev[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  double Ajn[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};   // the next pose's share of the last odometry factor
+  double gjn[3] = {0, 0, 0};
+  for (int i = 0; i < L; ++i) {
+    double A[3][3], g[3], B[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      g[a] = gjn[a];
+#pragma unroll
+      for (int b = 0; b < 3; ++b) A[a][b] = Ajn[a][b];
+    }
+    const double* xi = x + 3 * i;
+    if (i == 0) {
+      double r[3] = {xi[0] - prior[0], xi[1] - prior[1], wrap_pi(xi[2] - prior[2])};
+#pragma unroll
+      for (int a = 0; a < 3; ++a) { A[a][a] += prior[3 + a]; g[a] += prior[3 + a] * r[a]; }
+    }
+    const double* sc = scan + 6 * i;
+    if (sc[3] != 0.0 || sc[4] != 0.0 || sc[5] != 0.0) {
+      double r[3] = {xi[0] - sc[0], xi[1] - sc[1], wrap_pi(xi[2] - sc[2])};
+#pragma unroll
+      for (int a = 0; a < 3; ++a) { A[a][a] += sc[3 + a]; g[a] += sc[3 + a] * r[a]; }
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      gjn[a] = 0.0;
+#pragma unroll
+      for (int b = 0; b < 3; ++b) Ajn[a][b] = 0.0;
+    }
+    if (i + 1 < L) {
+      const double* o = odo + 6 * i;
+      double r[3], Ji[3][3], Jj[3][3];
+      odo_factor(xi, x + 3 * (i + 1), o, r, Ji, Jj);
+      add_jtwj(A, Ji, o + 3, Ji);
+      add_jtwj(B, Ji, o + 3, Jj);
+      add_jtwr(g, Ji, o + 3, r);
+      add_jtwj(Ajn, Jj, o + 3, Jj);
+      add_jtwr(gjn, Jj, o + 3, r);
+    }
+    // Schur complement with the previous pose
+    double y[3] = {-g[0], -g[1], -g[2]};
+    if (i > 0) {
+      const double* Dp = work + 21 * (i - 1);        // D_{i-1}^{-1}
+      const double* Cp = Dp + 9;                      // C_{i-1} = D_{i-1}^{-1} B_{i-1}
+      const double* yp = Dp + 18;
+      // A -= B_{i-1}^T C_{i-1};  y -= B_{i-1}^T (D_{i-1}^{-1} y_{i-1})
+      double t[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) t[a] = Dp[3 * a] * yp[0] + Dp[3 * a + 1] * yp[1] + Dp[3 * a + 2] * yp[2];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+          A[a][b] -= Bprev[0][a] * Cp[b] + Bprev[1][a] * Cp[3 + b] + Bprev[2][a] * Cp[6 + b];
+        y[a] -= Bprev[0][a] * t[0] + Bprev[1][a] * t[1] + Bprev[2][a] * t[2];
+      }
+    }
+    M3 D;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) D.a[a][b] = A[a][b];
+    const M3 Di = inv3(D);
+    double* wk = work + 21 * i;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        wk[3 * a + b] = Di.a[a][b];
+        wk[9 + 3 * a + b] = Di.a[a][0] * B[0][b] + Di.a[a][1] * B[1][b] + Di.a[a][2] * B[2][b];
+      }
+    wk[18] = y[0]; wk[19] = y[1]; wk[20] = y[2];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) Bprev[a][b] = B[a][b];
+    if (i == L - 1) *last = Di;
+  }
+}
+
+// One thread per window: K steps (x <- x + delta, H delta = -g) then Sigma = D_{L-1}^{-1} at the result.
+__global__ void k_fixedlag(int n, int L, const double* __restrict__ x0, const double* __restrict__ prior,
+                           const double* __restrict__ odo, const double* __restrict__ scan, int iters,
+                           double* __restrict__ xout, double* __restrict__ cov, double* __restrict__ work) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  double* x = xout + (int64_t)r * L * 3;
+  for (int e = 0; e < 3 * L; ++e) x[e] = x0[(int64_t)r * L * 3 + e];
+  const double* pr = prior + 6 * (int64_t)r;
+  const double* od = odo + (int64_t)r * (L > 1 ? L - 1 : 0) * 6;
+  const double* sc = scan + (int64_t)r * L * 6;
+  double* wk = work + (int64_t)r * L * 21;
+  M3 last;
+  for (int it = 0; it < iters; ++it) {
+    eliminate(x, L, pr, od, sc, wk, &last);
+    // back substitution: delta_{L-1} = D^{-1} y;  delta_i = D_i^{-1} y_i - C_i delta_{i+1}
+    double dn[3] = {0, 0, 0};
+    for (int i = L - 1; i >= 0; --i) {
+      const double* w = wk + 21 * i;
+      double d[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        d[a] = w[3 * a] * w[18] + w[3 * a + 1] * w[19] + w[3 * a + 2] * w[20];
+        if (i < L - 1) d[a] -= w[9 + 3 * a] * dn[0] + w[9 + 3 * a + 1] * dn[1] + w[9 + 3 * a + 2] * dn[2];
+      }
+#pragma unroll
+      for (int a = 0; a < 3; ++a) { x[3 * i + a] += d[a]; dn[a] = d[a]; }
+    }
+  }
+  eliminate(x, L, pr, od, sc, wk, &last);
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) cov[9 * (int64_t)r + 3 * a + b] = last.a[a][b];
+}
+
+// ------------------------------------------------------------------ heading table (per device)
+
+std::mutex g_tab_mu;
+std::vector<int32_t*> g_tab;   // per device, built once
+
+int dirtab_for_current_device(const int32_t** out) {
+  int dev = 0;
+  SCHK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_tab_mu);
+  if ((int)g_tab.size() <= dev) g_tab.resize(dev + 1, nullptr);
+  if (!g_tab[dev]) {
+    std::vector<int32_t> t(kNang);
+    for (int k = 0; k < kNang; ++k) {
+      const double ang = (2.0 * M_PI * (double)k) / (double)kNang;
+      const int32_t c = (int32_t)std::llround(std::cos(ang) * (double)kDirOne);
+      const int32_t s = (int32_t)std::llround(std::sin(ang) * (double)kDirOne);
+      t[k] = (int32_t)(((uint32_t)c & 0xffffu) | ((uint32_t)s << 16));
+    }
+    int32_t* d = nullptr;
+    SCHK(hipMalloc(&d, sizeof(int32_t) * kNang));
+    const hipError_t e = hipMemcpy(d, t.data(), sizeof(int32_t) * kNang, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      (void)hipFree(d);
+      return sfail(ASL_EHIP, hipGetErrorString(e));
+    }
+    g_tab[dev] = d;
+  }
+  *out = g_tab[dev];
+  return ASL_OK;
+}
+
+int check_csm_config(const aslam_csm_config* c, int32_t R) {
+  if (!c) return sfail(ASL_EINVAL, "csm config is NULL");
+  if (c->W < 0 || c->W > kCsmMaxHalf || c->V < 0 || c->V > kCsmMaxHalf)
+    return sfail(ASL_EINVAL, "csm half-widths W and V must be in [0, 8]");
+  if (c->step_xy_q < 1 || c->step_xy_q > (1 << 20) || c->step_h < 0 || c->step_h > kNang)
+    return sfail(ASL_EINVAL, "csm steps out of range (step_xy_q in [1, 2^20], step_h in [0, 46080])");
+  if (R < 1 || (int64_t)(2 * c->V + 1) * R > kCsmMaxRayHeadings)
+    return sfail(ASL_EINVAL, "csm needs R >= 1 and (2V + 1) * R <= 8192");
+  return ASL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int aslam_csm_match(const int16_t* belief_dev, const int64_t* cell_off_dev, const int32_t* side_dev, int32_t n,
+                    const int32_t* pose_q_dev, const int32_t* rho_q_dev, int32_t R, const int32_t* a_off_dev,
+                    const aslam_csm_config* cfg, int32_t* out_dev, aslam_stream_t stream) {
+  int rc = check_csm_config(cfg, R);
+  if (rc) return rc;
+  if (n < 0) return sfail(ASL_EINVAL, "n must be >= 0");
+  if (n == 0) return ASL_OK;
+  if (!belief_dev || !cell_off_dev || !side_dev || !pose_q_dev || !rho_q_dev || !a_off_dev || !out_dev)
+    return sfail(ASL_EINVAL, "null argument to csm_match");
+  const int32_t* tab = nullptr;
+  rc = dirtab_for_current_device(&tab);
+  if (rc) return rc;
+  k_csm<<<n, kCsmThreads, 0, (hipStream_t)stream>>>(belief_dev, cell_off_dev, side_dev, pose_q_dev, rho_q_dev, R,
+                                                     a_off_dev, tab, cfg->W, cfg->V, cfg->step_xy_q, cfg->step_h,
+                                                     out_dev);
+  SCHK(hipGetLastError());
+  return ASL_OK;
+}
+
+int aslam_csm_factor(const int32_t* match_dev, const int32_t* pose_q_dev, int32_t n, const aslam_csm_config* cfg,
+                     double cell_m, double l_max, double sigma_xy, double sigma_th, double* meas_dev,
+                     double* info_dev, aslam_stream_t stream) {
+  if (!cfg) return sfail(ASL_EINVAL, "csm config is NULL");
+  if (n < 0) return sfail(ASL_EINVAL, "n must be >= 0");
+  if (!(cell_m > 0.0) || !(l_max > 0.0) || !(sigma_xy > 0.0) || !(sigma_th > 0.0))
+    return sfail(ASL_EINVAL, "cell_m, l_max and the sigmas must be positive");
+  if (n == 0) return ASL_OK;
+  if (!match_dev || !pose_q_dev || !meas_dev || !info_dev) return sfail(ASL_EINVAL, "null argument to csm_factor");
+  k_csm_factor<<<(n + 255) / 256, 256, 0, (hipStream_t)stream>>>(match_dev, pose_q_dev, n, cfg->step_xy_q,
+                                                                  cfg->step_h, cell_m, l_max, sigma_xy, sigma_th,
+                                                                  meas_dev, info_dev);
+  SCHK(hipGetLastError());
+  return ASL_OK;
+}
+
+int64_t aslam_fixedlag_work_doubles(int32_t n, int32_t L) {
+  if (n < 0 || L < 1) return -1;
+  return (int64_t)n * L * 21;
+}
+
+int aslam_fixedlag_solve(int32_t n, int32_t L, const double* x0_dev, const double* prior_dev, const double* odo_dev,
+                         const double* scan_dev, int32_t iters, double* x_dev, double* cov_dev, double* work_dev,
+                         aslam_stream_t stream) {
+  if (n < 0 || L < 1 || L > 64 || iters < 0 || iters > 100)
+    return sfail(ASL_EINVAL, "need n >= 0, 1 <= L <= 64, 0 <= iters <= 100");
+  if (n == 0) return ASL_OK;
+  if (!x0_dev || !prior_dev || (L > 1 && !odo_dev) || !scan_dev || !x_dev || !cov_dev || !work_dev)
+    return sfail(ASL_EINVAL, "null argument to fixedlag_solve");
+  k_fixedlag<<<(n + 63) / 64, 64, 0, (hipStream_t)stream>>>(n, L, x0_dev, prior_dev, odo_dev, scan_dev, iters,
+                                                             x_dev, cov_dev, work_dev);
+  SCHK(hipGetLastError());
+  return ASL_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,64 @@
+"""The fixed-lag SLAM backbone (arXiv 2603.25834, Sec. III-D) over the C-ABI: correlative scan
+matching, the scan factor of a match, and the Gauss-Newton solve of a window of poses with the newest
+pose's covariance.  Argument marshalling only: the arithmetic runs in the library's HIP kernels."""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from ._lib import CsmConfig, check, lib
+
+
+def _p(t):
+    if t is None:
+        return None
+    assert t.is_cuda and t.is_contiguous(), "device tensors must be contiguous CUDA tensors"
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def csm_config(W: int, V: int, step_xy_q: int, step_h: int) -> CsmConfig:
+    return CsmConfig(W, V, step_xy_q, step_h)
+
+
+def csm_match(belief: torch.Tensor, cell_off: torch.Tensor, side: torch.Tensor, pose_q: torch.Tensor,
+              rho_q: torch.Tensor, a_off: torch.Tensor, cfg: CsmConfig, out: torch.Tensor | None = None):
+    """Best candidate (i, j, k), best and second scores and rays used per robot: int32 [n, 6]."""
+    n, R = rho_q.shape
+    assert belief.dtype == torch.int16 and cell_off.dtype == torch.int64 and side.dtype == torch.int32
+    assert pose_q.dtype == torch.int32 and tuple(pose_q.shape) == (n, 3)
+    assert rho_q.dtype == torch.int32 and a_off.dtype == torch.int32 and a_off.numel() == R
+    out = torch.empty((n, 6), dtype=torch.int32, device=rho_q.device) if out is None else out
+    check(lib().aslam_csm_match(_p(belief), _p(cell_off), _p(side), n, _p(pose_q), _p(rho_q), R, _p(a_off),
+                                ctypes.byref(cfg), _p(out), _stream()))
+    return out
+
+
+def csm_factor(match: torch.Tensor, pose_q: torch.Tensor, cfg: CsmConfig, cell_m: float, l_max: float,
+               sigma_xy: float, sigma_th: float):
+    """Scan factor of each match: measurement (x, y, theta) [n, 3] and information diagonal [n, 3], FP64."""
+    n = match.shape[0]
+    meas = torch.empty((n, 3), dtype=torch.float64, device=match.device)
+    info = torch.empty((n, 3), dtype=torch.float64, device=match.device)
+    check(lib().aslam_csm_factor(_p(match), _p(pose_q), n, ctypes.byref(cfg), cell_m, l_max, sigma_xy, sigma_th,
+                                 _p(meas), _p(info), _stream()))
+    return meas, info
+
+
+def fixedlag_solve(x0: torch.Tensor, prior: torch.Tensor, odo: torch.Tensor | None, scan: torch.Tensor, iters: int,
+                   x: torch.Tensor | None = None, cov: torch.Tensor | None = None, work: torch.Tensor | None = None):
+    """Gauss-Newton over n windows of L poses: (x [n, L, 3], newest pose's covariance [n, 3, 3]), FP64."""
+    n, L, _ = x0.shape
+    for t in (x0, prior, scan) + ((odo,) if odo is not None else ()):
+        assert t.dtype == torch.float64
+    x = torch.empty_like(x0) if x is None else x
+    cov = torch.empty((n, 3, 3), dtype=torch.float64, device=x0.device) if cov is None else cov
+    if work is None:
+        work = torch.empty(int(lib().aslam_fixedlag_work_doubles(n, L)), dtype=torch.float64, device=x0.device)
+    check(lib().aslam_fixedlag_solve(n, L, _p(x0), _p(prior), _p(odo), _p(scan), iters, _p(x), _p(cov), _p(work),
+                                     _stream()))
+    return x, cov
