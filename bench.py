@@ -151,6 +151,79 @@ class Workbench:
         return t0.elapsed_time(t1) / reps
 
 
+def slam_time(wb, reps: int = 20, L: int = 10, iters: int = 3) -> dict:
+    """The fixed-lag SLAM backbone on the env's state after its timed steps: correlative scan matching of
+    every robot's last scan against its belief grid (a 9 x 9 x 11 lattice: one-cell and 64-table-step
+    (0.5 degree) steps), the scan factors, and Gauss-Newton over an L-pose window per robot with the
+    newest pose's covariance.  Each call timed alone with HIP events on the current stream."""
+    torch = wb.torch
+    from paper_2603_25834_amd import _lib, slam
+    n, R, p = wb.n, wb.R, wb.p
+    cell, rmax = float(p["cell_m"]), float(p["r_max_m"])
+    nang = 46080
+    a_off = (torch.arange(R, dtype=torch.int32, device="cuda") * (nang // R)).contiguous()
+    belief = wb.env.read(_lib.FIELD_BELIEF)
+    sides = torch.tensor(np.asarray(wb.b.sides, np.int64), device="cuda")
+    cell_off = (torch.cumsum(sides * sides, 0) - sides * sides).contiguous()
+    side32 = sides.to(torch.int32).contiguous()
+    est = wb.env.read(_lib.FIELD_EST).double()
+    pose_q = torch.stack([torch.floor(est[:, 0] / cell * 65536), torch.floor(est[:, 1] / cell * 65536),
+                          torch.remainder(torch.round(est[:, 2] * (nang / (2 * np.pi))), nang)], 1)
+    pose_q = pose_q.to(torch.int32).contiguous()
+    rho_q = torch.where(wb.ranges < rmax - 1e-4, torch.round(wb.ranges / cell * 65536),
+                        torch.full_like(wb.ranges, -1.0)).to(torch.int32).contiguous()
+    cfg = slam.csm_config(4, 5, 65536, 64)
+    match = torch.empty((n, 6), dtype=torch.int32, device="cuda")
+    # windows: L poses along the estimate, odometry between them, the prior on the oldest
+    g = torch.Generator(device="cpu").manual_seed(0)
+    x0 = est[:, None, :].repeat(1, L, 1) + 0.01 * torch.randn((n, L, 3), generator=g, dtype=torch.float64).cuda()
+    prior = torch.cat([est, torch.full((n, 3), 400.0, dtype=torch.float64, device="cuda")], 1).contiguous()
+    odo = torch.cat([torch.zeros((n, L - 1, 3), dtype=torch.float64, device="cuda"),
+                     torch.full((n, L - 1, 3), 2500.0, dtype=torch.float64, device="cuda")], 2).contiguous()
+    scan = torch.zeros((n, L, 6), dtype=torch.float64, device="cuda")
+    xo = torch.empty_like(x0)
+    cov = torch.empty((n, 3, 3), dtype=torch.float64, device="cuda")
+    work = torch.empty(int(_lib.lib().aslam_fixedlag_work_doubles(n, L)), dtype=torch.float64, device="cuda")
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0.record()
+        for _ in range(reps):
+            fn()
+        t1.record()
+        torch.cuda.synchronize()
+        return t0.elapsed_time(t1) / reps
+
+    csm_ms = timed(lambda: slam.csm_match(belief, cell_off, side32, pose_q, rho_q, a_off, cfg, out=match))
+    meas, info = slam.csm_factor(match, pose_q, cfg, cell, 896.0, 0.05, 0.02)
+    fac_ms = timed(lambda: slam.csm_factor(match, pose_q, cfg, cell, 896.0, 0.05, 0.02))
+    scan[:, -1, :3] = meas
+    scan[:, -1, 3:] = info
+    gn_ms = timed(lambda: slam.fixedlag_solve(x0, prior, odo, scan, iters, x=xo, cov=cov, work=work))
+    m = match.cpu().numpy()
+    ncand = 9 * 9 * 11
+    # a few robots' inputs on the host, for the oracle's timing in the CPU-baseline leg
+    k = min(8, n)
+    bel = belief.cpu().numpy()
+    offs = cell_off.cpu().numpy()
+    sd = wb.b.sides
+    wb.slam_sample = dict(grids=[bel[offs[r]:offs[r] + sd[r] * sd[r]].reshape(sd[r], sd[r]) for r in range(k)],
+                          pose=pose_q[:k].cpu().numpy(), rho=rho_q[:k].cpu().numpy(), a_off=a_off.cpu().numpy(),
+                          x0=x0[:64].cpu().numpy(), prior=prior[:64].cpu().numpy(), odo=odo[:64].cpu().numpy(),
+                          scan=scan[:64].cpu().numpy(), L=L, iters=iters)
+    used = float(m[:, 5].mean())
+    return {"robots": n, "rays": R, "lattice": [9, 9, 11], "candidates": ncand,
+            "csm_us": csm_ms * 1e3, "factor_us": fac_ms * 1e3, "fixedlag_us": gn_ms * 1e3,
+            "window_poses": L, "gn_iters": iters,
+            "candidate_ray_evals_per_s": n * ncand * used / (csm_ms / 1e3),
+            "robots_per_s": n / ((csm_ms + fac_ms + gn_ms) / 1e3),
+            "rays_with_return": used,
+            "mean_best_offset_cells": float(np.abs(m[:, :2]).mean()),
+            "factor_weight_mean": float((info[:, 0] * 0.05 ** 2).mean().item())}
+
+
 def policy_flops(n_scan: int) -> tuple:
     """Algorithmic FLOP per sample of the actor-critic: forward, and backward with the forward recomputed.
 
@@ -273,6 +346,27 @@ def cpu_full_loop(name: str, seed: int, robots: int, T: int, epochs: int) -> dic
     return {"value": n * T / dt, "unit": "env-steps/s (PPO training loop)", "cores": threads, "kind": "oracle",
             "sample": f"{name}: first {n} robots, one iteration of {T} rollout steps + {epochs} epochs "
                       f"of one {n * T}-sample minibatch, FP64 policy ({dt:.1f} s)"}
+
+
+def cpu_slam(sample: dict) -> dict:
+    """The SLAM oracle as it stands on a few robots' inputs: scan matching (numpy, integer) and the
+    fixed-lag solve (numpy FP64), per robot."""
+    from oracle import slam_ref as S
+    trig = S._trig()
+    t0 = time.time()
+    for r in range(len(sample["grids"])):
+        p = sample["pose"][r]
+        S.csm_match(sample["grids"][r], int(p[0]), int(p[1]), int(p[2]), sample["rho"][r], sample["a_off"], 4, 5,
+                    65536, 64, trig)
+    t_csm = (time.time() - t0) / len(sample["grids"])
+    t0 = time.time()
+    nw = sample["x0"].shape[0]
+    for w in range(nw):
+        S.fixedlag_solve(sample["x0"][w], sample["prior"][w], sample["odo"][w], sample["scan"][w], sample["iters"])
+    t_gn = (time.time() - t0) / nw
+    return {"kind": "oracle", "cores": 1, "robots_per_s": 1.0 / (t_csm + t_gn), "csm_ms_per_robot": t_csm * 1e3,
+            "fixedlag_ms_per_window": t_gn * 1e3,
+            "sample": f"{len(sample['grids'])} robots' scan matching, {nw} windows of {sample['L']} poses"}
 
 
 def cpu_baseline(name: str, seed: int, robots: int, steps: int) -> dict:
@@ -415,6 +509,7 @@ def main():
     ap.add_argument("--no-ppo", action="store_true")
     ap.add_argument("--only-ppo", action="store_true", help="time the PPO minibatch alone (profiling)")
     ap.add_argument("--only-env", action="store_true", help="time the env step alone (profiling)")
+    ap.add_argument("--only-slam", action="store_true", help="time the SLAM backbone alone (profiling)")
     ap.add_argument("--ppo-batch", type=int, default=16384)
     ap.add_argument("--cpu-robots", type=int, default=640, help="oracle training-loop sample: robots")
     ap.add_argument("--cpu-env-robots", type=int, default=750, help="oracle env-step sample: robots")
@@ -465,6 +560,12 @@ def main():
                           "observe_ms": obs_ms, "alg_bytes_per_launch": res["alg_bytes_per_step"],
                           "achieved_gbs": res["achieved_gbs"], "traffic": traffic}), flush=True)
         return
+    slam_res = slam_time(wb)
+    print(f"[bench] SLAM backbone: scan matching {slam_res['csm_us']:.1f} us, factors {slam_res['factor_us']:.1f} us, "
+          f"fixed-lag solve {slam_res['fixedlag_us']:.1f} us for {wb.n} robots", file=sys.stderr, flush=True)
+    if args.only_slam:   # profiling aid: the SLAM backbone alone
+        print(json.dumps({"slam": slam_res}), flush=True)
+        return
     # ---- the bench step: one PPO training iteration (rollout of `horizon` steps + update)
     wb.env.set_exec(**fused)
     loop = train_loop(wb, args.horizon, args.epochs, args.minibatch, args.warmup, args.steps, args.seed)
@@ -498,6 +599,7 @@ def main():
                    "grid": fused.get("grid", 0), "plain_threads": plain["threads"],
                    "lds_bytes": wb.env.get_exec()["lds_bytes"]},
         "rays_per_s": value * wb.R,
+        "slam": slam_res,
         "training_loop": loop,
         "env_step_only": {"env_steps_per_s": wb.n / ((res["ms_per_step"] + obs_ms) / 1e3),
                           "rays_per_s": wb.n * wb.R / ((res["ms_per_step"] + obs_ms) / 1e3),
@@ -531,6 +633,7 @@ def main():
         out["cpu_baseline"] = cpu_full_loop(args.workload, args.seed, args.cpu_robots, args.horizon, args.epochs)
         out["cpu_baseline"]["env_step_only"] = cpu_baseline(args.workload, args.seed, args.cpu_env_robots,
                                                             args.cpu_env_steps)
+        out["cpu_baseline"]["slam"] = cpu_slam(wb.slam_sample)
     print(json.dumps(out), flush=True)
 
 
