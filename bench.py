@@ -196,7 +196,9 @@ def slam_time(wb, reps: int = 20, L: int = 10, iters: int = 3) -> dict:
         torch.cuda.synchronize()
         return t0.elapsed_time(t1) / reps
 
-    csm_ms = timed(lambda: slam.csm_match(belief, cell_off, side32, pose_q, rho_q, a_off, cfg, out=match))
+    max_side = int(max(wb.b.sides))
+    csm_ms = timed(lambda: slam.csm_match(belief, cell_off, side32, pose_q, rho_q, a_off, cfg, out=match,
+                                          max_side=max_side))
     meas, info = slam.csm_factor(match, pose_q, cfg, cell, 896.0, 0.05, 0.02)
     fac_ms = timed(lambda: slam.csm_factor(match, pose_q, cfg, cell, 896.0, 0.05, 0.02))
     scan[:, -1, :3] = meas

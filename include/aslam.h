@@ -358,11 +358,14 @@ typedef struct {
  * log-odds of its rays' endpoint cells inside the grid.  out_dev int32 [n,6]: best i, j, k (highest
  * score, lowest index ((k+V)(2W+1) + j+W)(2W+1) + i+W on ties), best score, second score (highest at
  * lattice Chebyshev distance >= 2 from the best; INT32_MIN if none), rays with a return.
+ * max_side: the largest side (a host value): lattices of at most 1024 candidates stage each grid of at
+ * most this side in LDS when it fits beside the ray offsets (a robot with a larger side reads global
+ * memory; results do not depend on it).
  * Device arrays are not checked: the caller guarantees grids inside belief_dev, 0 <= rho_q < 2^31.
  * ASL_EINVAL on NULL pointers, n < 0 or a config outside the ranges above, or (2V + 1) R > 8192. */
-int aslam_csm_match(const int16_t* belief_dev, const int64_t* cell_off_dev, const int32_t* side_dev, int32_t n,
-                    const int32_t* pose_q_dev, const int32_t* rho_q_dev, int32_t R, const int32_t* a_off_dev,
-                    const aslam_csm_config* cfg, int32_t* out_dev, aslam_stream_t stream);
+int aslam_csm_match(const int16_t* belief_dev, const int64_t* cell_off_dev, const int32_t* side_dev,
+                    int32_t max_side, int32_t n, const int32_t* pose_q_dev, const int32_t* rho_q_dev, int32_t R,
+                    const int32_t* a_off_dev, const aslam_csm_config* cfg, int32_t* out_dev, aslam_stream_t stream);
 
 /* The scan factor of a match (Sec. III-D: an absolute pose measurement whose information is scaled
  * by the normalised score and the ambiguity margin).  match_dev int32 [n,6] (aslam_csm_match's output),

@@ -94,7 +94,7 @@ SIGNATURES = {
     "aslam_gae": (ctypes.c_int, [_P, _P, _P, _P, _I32, _I32, ctypes.c_float, ctypes.c_float, _P, _P, _P]),
     "aslam_adam": (ctypes.c_int, [_P, _P, _P, _P, _I64, _I32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                   ctypes.c_float, _P]),
-    "aslam_csm_match": (ctypes.c_int, [_P, _P, _P, _I32, _P, _P, _I32, _P, ctypes.POINTER(CsmConfig), _P, _P]),
+    "aslam_csm_match": (ctypes.c_int, [_P, _P, _P, _I32, _I32, _P, _P, _I32, _P, ctypes.POINTER(CsmConfig), _P, _P]),
     "aslam_csm_factor": (ctypes.c_int, [_P, _P, _I32, ctypes.POINTER(CsmConfig), ctypes.c_double, ctypes.c_double,
                                         ctypes.c_double, ctypes.c_double, _P, _P, _P]),
     "aslam_fixedlag_work_doubles": (_I64, [_I32, _I32]),

@@ -12,6 +12,7 @@
 //    the last diagonal block of the inverse Hessian, is the inverse of the last Schur complement.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <mutex>
@@ -45,6 +46,7 @@ constexpr int kCsmThreads = 256;
 constexpr int kCsmMaxHalf = 8;                      // W, V <= 8
 constexpr int kCsmMaxRayHeadings = 8192;            // (2V + 1) * R ray offsets staged in LDS
 constexpr int kCsmMaxCand = (2 * kCsmMaxHalf + 1) * (2 * kCsmMaxHalf + 1) * (2 * kCsmMaxHalf + 1);
+constexpr int64_t kCsmLdsBudget = 163840 - 64;      // dynamic LDS of the staged kernel (160 KB less its reductions)
 
 // ------------------------------------------------------------------ correlative scan matching
 
@@ -138,6 +140,156 @@ __global__ __launch_bounds__(kCsmThreads) void k_csm(const int16_t* __restrict__
   if (threadIdx.x == 0) {
     int32_t s2 = s_red[0][0], u = s_red[0][1];
     for (int w = 1; w < kCsmThreads / 64; ++w) { s2 = max(s2, s_red[w][0]); u += s_red[w][1]; }
+    int32_t* o = out + 6 * (int64_t)r;
+    o[0] = bii - W; o[1] = bj - W; o[2] = bk - V; o[3] = bs; o[4] = s2; o[5] = u;
+  }
+}
+
+// The same with the robot's whole grid staged in LDS (when it fits beside the ray offsets), for
+// lattices of at most 9 translations per axis and 1024 candidates.  Thread (row, chunk) takes one
+// (heading k, row j) line of nine x candidates over a chunk of the rays, so one offset read serves the
+// whole line (the line's cells are read side by side); the chunks' partial sums are then added in
+// chunk order.  A robot whose side exceeds the staged size reads its grid from global memory instead.
+// Dynamic LDS: the grid (lds_cells int16, a multiple of 8), then the (2V + 1) R ray offsets, whose
+// space takes the partial sums once every line is done.
+constexpr int kCsmLdsThreads = 512;
+constexpr int kCsmLdsMaxCand = 1024;
+constexpr int kCsmLdsMaxLine = 9;                  // 2W + 1 <= 9
+constexpr int32_t kNoReturn = -(1 << 30);         // offset of a ray without a return: off every grid
+
+__global__ __launch_bounds__(kCsmLdsThreads) void k_csm_lds(const int16_t* __restrict__ belief,
+                                                            const int64_t* __restrict__ cell_off,
+                                                            const int32_t* __restrict__ side,
+                                                            const int32_t* __restrict__ pose_q,
+                                                            const int32_t* __restrict__ rho_q, int R,
+                                                            const int32_t* __restrict__ a_off,
+                                                            const int32_t* __restrict__ dirtab, int W, int V,
+                                                            int step_xy, int step_h, int lds_side,
+                                                            int32_t* __restrict__ out) {
+  extern __shared__ __align__(16) unsigned char s_dyn[];
+  const int lds_cells = (lds_side * lds_side + 7) & ~7;
+  int16_t* s_grid = reinterpret_cast<int16_t*>(s_dyn);
+  int2* s_off = reinterpret_cast<int2*>(s_dyn + 2 * (int64_t)lds_cells);
+  int32_t* s_part = reinterpret_cast<int32_t*>(s_off);
+  __shared__ int32_t s_red[kCsmLdsThreads / 64][2];
+  const int r = blockIdx.x;
+  const int nw = 2 * W + 1, nk = 2 * V + 1, ncand = nk * nw * nw, nline = nk * nw;
+  const int32_t px = pose_q[3 * r], py = pose_q[3 * r + 1], ph = pose_q[3 * r + 2];
+  const int32_t* rho = rho_q + (int64_t)r * R;
+  int used = 0;
+  for (int e = threadIdx.x; e < nk * R; e += kCsmLdsThreads) {
+    const int k = e / R, q = e - k * R;
+    const int32_t rq = rho[q];
+    int2 o = make_int2(kNoReturn, kNoReturn);
+    if (rq >= 0) {
+      int64_t h = ((int64_t)ph + (int64_t)(k - V) * step_h + a_off[q]) % kNang;
+      if (h < 0) h += kNang;
+      const int32_t d = dirtab[h];
+      const int32_t c = (int32_t)(int16_t)(d & 0xffff), s = d >> 16;
+      o.x = (int32_t)(((int64_t)rq * c) >> 14);
+      o.y = (int32_t)(((int64_t)rq * s) >> 14);
+      if (k == 0) ++used;
+    }
+    s_off[e] = o;
+  }
+  const int32_t sd = side[r];
+  const int64_t base = cell_off[r];
+  const bool staged = sd > 0 && sd <= lds_side;
+  if (staged) {
+    const int64_t cells = (int64_t)sd * sd;
+    if ((reinterpret_cast<uintptr_t>(belief + base) & 15) == 0) {
+      const uint4* src = reinterpret_cast<const uint4*>(belief + base);
+      uint4* dst = reinterpret_cast<uint4*>(s_grid);
+      for (int64_t v = threadIdx.x; v < cells / 8; v += kCsmLdsThreads) dst[v] = src[v];
+      for (int64_t e = (cells / 8) * 8 + threadIdx.x; e < cells; e += kCsmLdsThreads) s_grid[e] = belief[base + e];
+    } else {
+      for (int64_t e = threadIdx.x; e < cells; e += kCsmLdsThreads) s_grid[e] = belief[base + e];
+    }
+  }
+  __syncthreads();
+  const int16_t* g = staged ? s_grid : belief + base;
+  // lines x chunks of rays
+  const int chunks = max(1, min(R, kCsmLdsThreads / nline));
+  int32_t acc[kCsmLdsMaxLine];
+#pragma unroll
+  for (int i = 0; i < kCsmLdsMaxLine; ++i) acc[i] = 0;
+  const int line = threadIdx.x / chunks, ch = threadIdx.x - line * chunks;
+  if (line < nline) {
+    const int k = line / nw, j = line - k * nw;
+    const int q0 = (int)((int64_t)ch * R / chunks), q1 = (int)((int64_t)(ch + 1) * R / chunks);
+    const int64_t x0 = (int64_t)px - (int64_t)W * step_xy, y = (int64_t)py + (int64_t)(j - W) * step_xy;
+    const int2* o = s_off + k * R;
+    for (int q = q0; q < q1; ++q) {
+      const int2 v = o[q];
+      const int64_t cy = (y + v.y) >> 16;
+      if (cy < 0 || cy >= sd) continue;
+      const int16_t* grow = g + cy * sd;
+      const int64_t ex = x0 + v.x;
+#pragma unroll
+      for (int i = 0; i < kCsmLdsMaxLine; ++i) {
+        if (i < nw) {
+          const int64_t cx = (ex + (int64_t)i * step_xy) >> 16;
+          if (cx >= 0 && cx < sd) acc[i] += grow[cx];
+        }
+      }
+    }
+  }
+  __syncthreads();   // every line is done with the offsets: their space takes the partial sums
+  if (line < nline) {
+#pragma unroll
+    for (int i = 0; i < kCsmLdsMaxLine; ++i)
+      if (i < nw) s_part[ch * ncand + line * nw + i] = acc[i];
+  }
+  __syncthreads();
+  int32_t sc[2];
+#pragma unroll
+  for (int m = 0; m < 2; ++m) {
+    const int c = threadIdx.x + m * kCsmLdsThreads;
+    sc[m] = INT32_MIN;
+    if (c < ncand) {
+      int32_t t = 0;
+      for (int z = 0; z < chunks; ++z) t += s_part[z * ncand + c];
+      sc[m] = t;
+    }
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int32_t bs = INT32_MIN, bi = INT32_MAX;
+#pragma unroll
+  for (int m = 0; m < 2; ++m) {
+    const int c = threadIdx.x + m * kCsmLdsThreads;
+    if (c < ncand && (sc[m] > bs || (sc[m] == bs && c < bi))) { bs = sc[m]; bi = c; }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const int32_t os = __shfl_xor(bs, off, 64), oi = __shfl_xor(bi, off, 64);
+    if (os > bs || (os == bs && oi < bi)) { bs = os; bi = oi; }
+  }
+  if (lane == 0) { s_red[wave][0] = bs; s_red[wave][1] = bi; }
+  __syncthreads();
+  bs = s_red[0][0]; bi = s_red[0][1];
+  for (int w = 1; w < kCsmLdsThreads / 64; ++w) {
+    const int32_t os = s_red[w][0], oi = s_red[w][1];
+    if (os > bs || (os == bs && oi < bi)) { bs = os; bi = oi; }
+  }
+  const int bk = bi / (nw * nw), brem = bi - bk * nw * nw, bj = brem / nw, bii = brem - bj * nw;
+  int32_t ss = INT32_MIN;
+#pragma unroll
+  for (int m = 0; m < 2; ++m) {
+    const int c = threadIdx.x + m * kCsmLdsThreads;
+    if (c >= ncand) continue;
+    const int k = c / (nw * nw), rem = c - k * nw * nw, j = rem / nw, i = rem - j * nw;
+    if (max(max(abs(i - bii), abs(j - bj)), abs(k - bk)) >= 2) ss = max(ss, sc[m]);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) ss = max(ss, __shfl_xor(ss, off, 64));
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) used += __shfl_xor(used, off, 64);
+  __syncthreads();
+  if (lane == 0) { s_red[wave][0] = ss; s_red[wave][1] = used; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int32_t s2 = s_red[0][0], u = s_red[0][1];
+    for (int w = 1; w < kCsmLdsThreads / 64; ++w) { s2 = max(s2, s_red[w][0]); u += s_red[w][1]; }
     int32_t* o = out + 6 * (int64_t)r;
     o[0] = bii - W; o[1] = bj - W; o[2] = bk - V; o[3] = bs; o[4] = s2; o[5] = u;
   }
@@ -241,8 +393,8 @@ __device__ __forceinline__ void add_jtwr(double* acc, const double P[3][3], cons
 // diagonal block A_i, the coupling B_i = H[i][i+1] and the gradient g_i are formed as the sweep reaches
 // them; D_i = A_i - B_{i-1}^T D_{i-1}^{-1} B_{i-1}, y_i = -g_i - B_{i-1}^T D_{i-1}^{-1} y_{i-1}.  Work per
 // pose: D_i^{-1} (9), C_i = D_i^{-1} B_i (9), y_i (3).  Returns D_{L-1}^{-1} in *last.
-__device__ void eliminate(const double* x, int L, const double* prior, const double* odo, const double* scan,
-                          double* work, M3* last) {
+__device__ __forceinline__ void eliminate(const double* x, int L, const double* prior, const double* odo,
+                                          const double* scan, double* work, M3& last) {
   double Bprev[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
   double Ajn[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};   // the next pose's share of the last odometry factor
   double gjn[3] = {0, 0, 0};
@@ -319,7 +471,7 @@ __device__ void eliminate(const double* x, int L, const double* prior, const dou
     for (int a = 0; a < 3; ++a)
 #pragma unroll
       for (int b = 0; b < 3; ++b) Bprev[a][b] = B[a][b];
-    if (i == L - 1) *last = Di;
+    if (i == L - 1) last = Di;
   }
 }
 
@@ -337,7 +489,7 @@ __global__ void k_fixedlag(int n, int L, const double* __restrict__ x0, const do
   double* wk = work + (int64_t)r * L * 21;
   M3 last;
   for (int it = 0; it < iters; ++it) {
-    eliminate(x, L, pr, od, sc, wk, &last);
+    eliminate(x, L, pr, od, sc, wk, last);
     // back substitution: delta_{L-1} = D^{-1} y;  delta_i = D_i^{-1} y_i - C_i delta_{i+1}
     double dn[3] = {0, 0, 0};
     for (int i = L - 1; i >= 0; --i) {
@@ -352,7 +504,7 @@ __global__ void k_fixedlag(int n, int L, const double* __restrict__ x0, const do
       for (int a = 0; a < 3; ++a) { x[3 * i + a] += d[a]; dn[a] = d[a]; }
     }
   }
-  eliminate(x, L, pr, od, sc, wk, &last);
+  eliminate(x, L, pr, od, sc, wk, last);
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
@@ -405,21 +557,40 @@ int check_csm_config(const aslam_csm_config* c, int32_t R) {
 
 extern "C" {
 
-int aslam_csm_match(const int16_t* belief_dev, const int64_t* cell_off_dev, const int32_t* side_dev, int32_t n,
-                    const int32_t* pose_q_dev, const int32_t* rho_q_dev, int32_t R, const int32_t* a_off_dev,
-                    const aslam_csm_config* cfg, int32_t* out_dev, aslam_stream_t stream) {
+int aslam_csm_match(const int16_t* belief_dev, const int64_t* cell_off_dev, const int32_t* side_dev,
+                    int32_t max_side, int32_t n, const int32_t* pose_q_dev, const int32_t* rho_q_dev, int32_t R,
+                    const int32_t* a_off_dev, const aslam_csm_config* cfg, int32_t* out_dev, aslam_stream_t stream) {
   int rc = check_csm_config(cfg, R);
   if (rc) return rc;
   if (n < 0) return sfail(ASL_EINVAL, "n must be >= 0");
+  if (max_side < 0) return sfail(ASL_EINVAL, "max_side must be >= 0");
   if (n == 0) return ASL_OK;
   if (!belief_dev || !cell_off_dev || !side_dev || !pose_q_dev || !rho_q_dev || !a_off_dev || !out_dev)
     return sfail(ASL_EINVAL, "null argument to csm_match");
   const int32_t* tab = nullptr;
   rc = dirtab_for_current_device(&tab);
   if (rc) return rc;
-  k_csm<<<n, kCsmThreads, 0, (hipStream_t)stream>>>(belief_dev, cell_off_dev, side_dev, pose_q_dev, rho_q_dev, R,
-                                                     a_off_dev, tab, cfg->W, cfg->V, cfg->step_xy_q, cfg->step_h,
-                                                     out_dev);
+  const int ncand = (2 * cfg->V + 1) * (2 * cfg->W + 1) * (2 * cfg->W + 1);
+  const int64_t off_bytes = (int64_t)(2 * cfg->V + 1) * R * (int64_t)sizeof(int2);
+  if (ncand <= kCsmLdsMaxCand && 2 * cfg->W + 1 <= kCsmLdsMaxLine &&
+      off_bytes >= (int64_t)sizeof(int32_t) * ncand * std::max(1, std::min((int)R, kCsmLdsThreads / ((2 * cfg->V + 1) *
+                                                                                       (2 * cfg->W + 1))))) {
+    // the grids staged in LDS when the largest fits beside the ray offsets (a 256 x 256 grid does with
+    // 11 headings x 360 rays), else read from global memory
+    int64_t grid_bytes = 2 * ((((int64_t)max_side * max_side) + 7) & ~(int64_t)7);
+    int lds_side = max_side;
+    if (grid_bytes + off_bytes > kCsmLdsBudget) { grid_bytes = 0; lds_side = 0; }
+    const int bytes = (int)(grid_bytes + off_bytes);
+    SCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_csm_lds), hipFuncAttributeMaxDynamicSharedMemorySize,
+                             bytes));
+    k_csm_lds<<<n, kCsmLdsThreads, bytes, (hipStream_t)stream>>>(belief_dev, cell_off_dev, side_dev, pose_q_dev,
+                                                              rho_q_dev, R, a_off_dev, tab, cfg->W, cfg->V,
+                                                              cfg->step_xy_q, cfg->step_h, lds_side, out_dev);
+  } else {
+    k_csm<<<n, kCsmThreads, 0, (hipStream_t)stream>>>(belief_dev, cell_off_dev, side_dev, pose_q_dev, rho_q_dev, R,
+                                                       a_off_dev, tab, cfg->W, cfg->V, cfg->step_xy_q, cfg->step_h,
+                                                       out_dev);
+  }
   SCHK(hipGetLastError());
   return ASL_OK;
 }

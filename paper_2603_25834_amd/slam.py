@@ -26,15 +26,19 @@ def csm_config(W: int, V: int, step_xy_q: int, step_h: int) -> CsmConfig:
 
 
 def csm_match(belief: torch.Tensor, cell_off: torch.Tensor, side: torch.Tensor, pose_q: torch.Tensor,
-              rho_q: torch.Tensor, a_off: torch.Tensor, cfg: CsmConfig, out: torch.Tensor | None = None):
-    """Best candidate (i, j, k), best and second scores and rays used per robot: int32 [n, 6]."""
+              rho_q: torch.Tensor, a_off: torch.Tensor, cfg: CsmConfig, out: torch.Tensor | None = None,
+              max_side: int | None = None):
+    """Best candidate (i, j, k), best and second scores and rays used per robot: int32 [n, 6].  max_side:
+    the largest grid side (read from `side` when not given)."""
+    if max_side is None:
+        max_side = int(side.max().item()) if side.numel() else 0
     n, R = rho_q.shape
     assert belief.dtype == torch.int16 and cell_off.dtype == torch.int64 and side.dtype == torch.int32
     assert pose_q.dtype == torch.int32 and tuple(pose_q.shape) == (n, 3)
     assert rho_q.dtype == torch.int32 and a_off.dtype == torch.int32 and a_off.numel() == R
     out = torch.empty((n, 6), dtype=torch.int32, device=rho_q.device) if out is None else out
-    check(lib().aslam_csm_match(_p(belief), _p(cell_off), _p(side), n, _p(pose_q), _p(rho_q), R, _p(a_off),
-                                ctypes.byref(cfg), _p(out), _stream()))
+    check(lib().aslam_csm_match(_p(belief), _p(cell_off), _p(side), max_side, n, _p(pose_q), _p(rho_q), R,
+                                _p(a_off), ctypes.byref(cfg), _p(out), _stream()))
     return out
 
 

@@ -72,6 +72,24 @@ def test_match_bit_exact(W, V, sxy, sh, R):
         assert tuple(int(v) for v in got[r]) == want, (r, got[r], want)
 
 
+@pytest.mark.parametrize("sides,max_side", [([300, 64, 128], None), ([256, 64, 200, 96], 96)],
+                         ids=["grid_too_big_for_lds", "mixed_staged_and_global"])
+def test_match_staged_and_global_grids(sides, max_side):
+    """Grids staged in LDS or read from global memory give the same (exact) answers."""
+    W, V, sxy, sh, R = 4, 5, 65536, 64, 360
+    grids, belief, cell_off, side, pose, rho, a_off = _batch(17 + len(sides), sides, R, W, V, sxy, sh)
+    cfg = slam.csm_config(W, V, sxy, sh)
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    got = slam.csm_match(d(belief), d(cell_off), d(side), d(pose), d(rho), d(a_off), cfg, max_side=max_side)
+    torch.cuda.synchronize()
+    got = got.cpu().numpy()
+    trig = S._trig()
+    for r in range(len(sides)):
+        want = S.csm_match(grids[r], int(pose[r, 0]), int(pose[r, 1]), int(pose[r, 2]), rho[r], a_off, W, V, sxy, sh,
+                           trig)
+        assert tuple(int(v) for v in got[r]) == want, (r, got[r], want)
+
+
 def test_factor_matches_oracle_exactly():
     W, V, sxy, sh, R = 4, 5, 32768, 48, 90
     sides = [64, 96, 128, 256, 32, 64]
