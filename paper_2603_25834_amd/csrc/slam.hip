@@ -476,17 +476,26 @@ __device__ __forceinline__ void eliminate(const double* x, int L, const double* 
 }
 
 // One thread per window: K steps (x <- x + delta, H delta = -g) then Sigma = D_{L-1}^{-1} at the result.
-__global__ void k_fixedlag(int n, int L, const double* __restrict__ x0, const double* __restrict__ prior,
-                           const double* __restrict__ odo, const double* __restrict__ scan, int iters,
-                           double* __restrict__ xout, double* __restrict__ cov, double* __restrict__ work) {
+// With lds_lag > 0 (L <= lds_lag) the thread keeps its poses and elimination workspace in LDS (the
+// sweeps read back what they just wrote), else in the global workspace.
+constexpr int kLagThreads = 32;
+constexpr int kLagLdsMax = 24;    // windows of at most 24 poses use LDS: 32 x 24 x 24 doubles = 144 KB
+
+__global__ __launch_bounds__(kLagThreads) void k_fixedlag(int n, int L, const double* __restrict__ x0,
+                                                          const double* __restrict__ prior,
+                                                          const double* __restrict__ odo,
+                                                          const double* __restrict__ scan, int iters,
+                                                          double* __restrict__ xout, double* __restrict__ cov,
+                                                          double* __restrict__ work, int use_lds) {
+  extern __shared__ __align__(16) double s_lag[];
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n) return;
-  double* x = xout + (int64_t)r * L * 3;
+  double* x = use_lds ? s_lag + (int64_t)threadIdx.x * L * 24 : xout + (int64_t)r * L * 3;
+  double* wk = use_lds ? x + 3 * L : work + (int64_t)r * L * 21;
   for (int e = 0; e < 3 * L; ++e) x[e] = x0[(int64_t)r * L * 3 + e];
   const double* pr = prior + 6 * (int64_t)r;
   const double* od = odo + (int64_t)r * (L > 1 ? L - 1 : 0) * 6;
   const double* sc = scan + (int64_t)r * L * 6;
-  double* wk = work + (int64_t)r * L * 21;
   M3 last;
   for (int it = 0; it < iters; ++it) {
     eliminate(x, L, pr, od, sc, wk, last);
@@ -509,6 +518,8 @@ __global__ void k_fixedlag(int n, int L, const double* __restrict__ x0, const do
   for (int a = 0; a < 3; ++a)
 #pragma unroll
     for (int b = 0; b < 3; ++b) cov[9 * (int64_t)r + 3 * a + b] = last.a[a][b];
+  if (use_lds)
+    for (int e = 0; e < 3 * L; ++e) xout[(int64_t)r * L * 3 + e] = x[e];
 }
 
 // ------------------------------------------------------------------ heading table (per device)
@@ -624,8 +635,13 @@ int aslam_fixedlag_solve(int32_t n, int32_t L, const double* x0_dev, const doubl
   if (n == 0) return ASL_OK;
   if (!x0_dev || !prior_dev || (L > 1 && !odo_dev) || !scan_dev || !x_dev || !cov_dev || !work_dev)
     return sfail(ASL_EINVAL, "null argument to fixedlag_solve");
-  k_fixedlag<<<(n + 63) / 64, 64, 0, (hipStream_t)stream>>>(n, L, x0_dev, prior_dev, odo_dev, scan_dev, iters,
-                                                             x_dev, cov_dev, work_dev);
+  const int use_lds = L <= kLagLdsMax ? 1 : 0;
+  const int bytes = use_lds ? (int)(sizeof(double) * kLagThreads * L * 24) : 0;
+  if (use_lds)
+    SCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fixedlag), hipFuncAttributeMaxDynamicSharedMemorySize,
+                             bytes));
+  k_fixedlag<<<(n + kLagThreads - 1) / kLagThreads, kLagThreads, bytes, (hipStream_t)stream>>>(
+      n, L, x0_dev, prior_dev, odo_dev, scan_dev, iters, x_dev, cov_dev, work_dev, use_lds);
   SCHK(hipGetLastError());
   return ASL_OK;
 }
