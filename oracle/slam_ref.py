@@ -31,6 +31,14 @@ constants or exact rules; the readings taken here are:
   S6  K Gauss-Newton steps x <- x - H^{-1} g (H = sum J^T Omega J, g = sum J^T Omega r, analytic
       Jacobians), then H re-formed at the final estimate; Sigma = the last 3x3 block of H^{-1}.
   S7  wrap(a) = a - 2 pi rint(a / (2 pi)).
+  S8  Confidence-weighted map integration: the scan is cast into the grid from the best candidate's
+      pose by the exact traversal of the env step's map update (every cell a ray passes up to its
+      range is a MISS, the cell where a ray with a return ends is a HIT unless the ray left the grid
+      first, HIT beats MISS, rays without a return pass free space up to the maximum range), and each
+      coded cell gets one saturating add of the log-odds increment scaled by the scan weight w of S4.
+      w is quantised to w_q = rint(256 w) and the increment is floor((w_q l + 128) / 256): at w = 1 the
+      update is the unweighted one, at w = 0 the grid is unchanged.  An aligned pose outside the grid
+      leaves the grid unchanged.
 """
 from __future__ import annotations
 
@@ -97,10 +105,53 @@ def scan_factor(best_i, best_j, best_k, best, second, n_used, px, py, ph, step_x
     y = (py + best_j * step_xy) / 65536.0 * cell_m
     h = (ph + best_k * step_h) % NANG
     th = wrap(2.0 * np.pi * h / NANG)
+    w = match_weight(best, second, n_used, l_max)
+    return np.array([x, y, th]), np.array([w / sig_xy ** 2, w / sig_xy ** 2, w / sig_th ** 2])
+
+
+def match_weight(best, second, n_used, l_max) -> float:
+    """w = q m of S4: the normalised score times the margin to the second peak."""
     q = 0.0 if n_used <= 0 else min(max(best / (n_used * float(l_max)), 0.0), 1.0)
     m = min(max((best - second) / max(float(best), 1.0), 0.0), 1.0)
-    w = q * m
-    return np.array([x, y, th]), np.array([w / sig_xy ** 2, w / sig_xy ** 2, w / sig_th ** 2])
+    return q * m
+
+
+# ------------------------------------------------------------------ weighted map integration (S8)
+
+def weighted_increment(w_q: int, l: int) -> int:
+    """round(w_q l / 256), halves up (S8)."""
+    return (int(w_q) * int(l) + 128) >> 8
+
+
+def integrate(grid: np.ndarray, px: int, py: int, ph: int, rho_q: np.ndarray, a_off: np.ndarray, rmax_q: int,
+              l_hit: int, l_miss: int, l_clamp: int, match=None, step_xy: int = 0, step_h: int = 0,
+              l_max: float = 1.0):
+    """The grid after integrating the scan from the aligned pose (S8), and the number of coded cells.
+    `match` = (best_i, best_j, best_k, best, second, n_used) of csm_match, or None for the unweighted
+    update from (px, py, ph) itself."""
+    from oracle import oracle as O
+    cq, sq = _trig()
+    s = grid.shape[0]
+    if match is None:
+        ax, ay, ah, w_q = px, py, ph, 256
+    else:
+        bi, bj, bk, best, second, n_used = (int(v) for v in match)
+        ax, ay, ah = px + bi * step_xy, py + bj * step_xy, (ph + bk * step_h) % NANG
+        w_q = int(np.rint(256.0 * match_weight(best, second, n_used, l_max)))
+    code = np.zeros((s, s), np.int8)
+    for k in range(len(rho_q)):
+        d = (ah + int(a_off[k])) % NANG
+        ret = int(rho_q[k]) >= 0
+        cells, _, _, end = O.walk(ax, ay, int(cq[d]), int(sq[d]), 16384, int(rho_q[k]) if ret else rmax_q, s)
+        if len(cells) == 0:
+            continue
+        code[cells[:, 1], cells[:, 0]] = np.maximum(code[cells[:, 1], cells[:, 0]], 1)
+        if ret and end == 0:
+            code[cells[-1, 1], cells[-1, 0]] = 2
+    inc = np.where(code == 2, weighted_increment(w_q, l_hit), weighted_increment(w_q, l_miss))
+    out = grid.astype(np.int64)
+    out = np.where(code > 0, np.clip(out + inc, -l_clamp, l_clamp), out)
+    return out.astype(np.int16), int((code > 0).sum())
 
 
 # ------------------------------------------------------------------ fixed-lag graph (S5-S7)

@@ -7,7 +7,10 @@ by a scene built around a known pose (the search must return it and the score bo
 equivariances of the lattice (a shifted grid shifts the best candidate; a heading step on the
 candidate equals the same step on every ray) and by its tie and second-peak rules.  The graph solve is
 pinned by closed forms (a prior alone, a prior plus a scan factor, a motionless chain), by convergence
-to exact poses from consistent factors, and by finite differences of the residuals.
+to exact poses from consistent factors, and by finite differences of the residuals.  The weighted
+map integration is pinned against the env oracle's own map update (unweighted case), by closed forms
+along axis rays (cells, end rule, rounding of the weighted increments, saturation) and by its weight
+extremes.
 """
 import numpy as np
 import pytest
@@ -216,3 +219,107 @@ def test_jacobians_match_finite_differences():
         J[:, c] = (stacked(x.reshape(-1) + e)[0] - stacked(x.reshape(-1) - e)[0]) / (2 * eps)
     assert np.allclose(H, J.T @ (om[:, None] * J), rtol=1e-6, atol=1e-5)
     assert np.allclose(g, J.T @ (om * r0), rtol=1e-6, atol=1e-7)
+
+
+# ------------------------------------------------------------------ weighted map integration
+
+def test_unweighted_integration_equals_the_env_update():
+    """With no match (w = 1) the integration reproduces the env oracle's map update of a step, taken from
+    the step's estimated pose with its measured ranges (rays without a hit walk to the maximum range)."""
+    from oracle import oracle as O
+    from paper_2603_25834_amd import synth
+    name = "small_16x64"
+    w = synth.WORKLOADS[name]
+    p = w.params()
+    b = synth.make_batch(name, 5)
+    env = O.OracleEnv(p, b.sides, b.world, b.world_off)
+    env.reset(b.start)
+    A = synth.actions(name, 5, 6)
+    G = synth.noise(name, 5, 6)
+    for t in range(5):
+        env.step(A[t], G[t])
+    before = [env.belief_of(i).copy() for i in range(env.n)]
+    out = env.step(A[5], G[5])
+    R = int(p["n_rays"])
+    inv_c16 = np.float32(65536.0 / float(np.float32(p["cell_m"])))
+    rmax_q = int(round(float(np.float32(p["r_max_m"])) / float(np.float32(p["cell_m"])) * 65536.0))
+    a_off = (np.arange(R) * (S.NANG // R)).astype(np.int32)
+    changed = 0
+    for i in range(env.n):
+        e = env.est[i]
+        px = int(np.rint(np.float32(e[0]) * inv_c16))
+        py = int(np.rint(np.float32(e[1]) * inv_c16))
+        ph = O.heading_index(float(e[2]))
+        rho = np.where(out.hit_cell[i] >= 0, out.rho_q[i], -1).astype(np.int32)
+        got, n_coded = S.integrate(before[i], px, py, ph, rho, a_off, rmax_q, 218, -102, 896)
+        assert np.array_equal(got, env.belief_of(i)), i
+        assert n_coded == int(out.counters[i, 2])          # the env's count of distinct updated cells
+        changed += n_coded
+    assert changed > 0
+
+
+def _axis_rays(s=64):
+    """Origin at the centre of cell (20, 30); ray directions along +x (a_off 0) and -x (a_off NANG/2)."""
+    return 20 * 65536 + 32768, 30 * 65536 + 32768, 0
+
+
+def test_axis_ray_cells_end_rule_and_weighted_increments():
+    s = 64
+    px, py, ph = _axis_rays(s)
+    g = np.zeros((s, s), np.int16)
+    g[30, 23] = 880          # a MISS that stays below the clamp
+    g[30, 30] = 850          # the HIT, saturating at +896
+    g[30, 25] = -880         # a MISS saturating at -896
+    rho = np.array([int(10.25 * 65536)], np.int32)           # ends inside cell 30
+    a_off = np.zeros(1, np.int32)
+    # w = q m = 1 * 0.5: best = n_used * l_max, second = best / 2  ->  w_q = 128
+    match = (0, 0, 0, 896, 448, 1)
+    got, n_coded = S.integrate(g, px, py, ph, rho, a_off, 40 * 65536, 218, -102, 896, match=match,
+                               step_xy=65536, step_h=64, l_max=896.0)
+    want = g.astype(np.int64)
+    want[30, 20:30] += -51                                   # round(0.5 * -102) = -51
+    want[30, 30] += 109                                      # round(0.5 * 218) = 109
+    want = np.clip(want, -896, 896).astype(np.int16)
+    assert n_coded == 11 and np.array_equal(got, want)
+    # a range ending exactly on a cell boundary enters that cell (entry distance = range)
+    got2, n2 = S.integrate(np.zeros((s, s), np.int16), px, py, ph, np.array([int(10.5 * 65536)], np.int32), a_off,
+                           40 * 65536, 218, -102, 896)
+    assert n2 == 12 and got2[30, 31] == 218 and np.all(got2[30, 20:31] == -102)
+
+
+def test_hit_beats_miss_grid_exit_and_no_return():
+    s = 64
+    px, py, ph = _axis_rays(s)
+    half = S.NANG // 2
+    rho = np.array([int(10.25 * 65536), int(5.25 * 65536), int(40.0 * 65536), -1], np.int32)
+    a_off = np.array([0, 0, half, S.NANG // 4], np.int32)   # +x, +x, -x (leaves the grid), +y (no return)
+    got, n_coded = S.integrate(np.zeros((s, s), np.int16), px, py, ph, rho, a_off, int(12.5 * 65536), 218, -102, 896)
+    want = np.zeros((s, s), np.int16)
+    want[30, 0:31] = -102          # +x to cell 30 and -x out of the grid past cell 0 (no HIT there)
+    want[30, 30] = 218             # HIT of the long +x ray
+    want[30, 25] = 218             # HIT of the short +x ray beats the long ray's MISS
+    want[31:44, 20] = -102         # +y without a return: free space up to 12.5 cells (cell 43 entered at 12.5)
+    assert np.array_equal(got, want)
+    assert n_coded == 31 + 13
+
+
+def test_weight_extremes():
+    """w = 0 leaves the grid as it was; w = 1 equals the unweighted update from the aligned pose."""
+    rng = np.random.default_rng(9)
+    s, R = 80, 90
+    g = rng.integers(-400, 400, (s, s)).astype(np.int16)
+    px, py, ph = 40 * 65536 + 1234, 38 * 65536 + 50000, 12345
+    rho = (rng.uniform(2.0, 30.0, R) * 65536).astype(np.int32)
+    rho[rng.random(R) < 0.2] = -1
+    a_off = (np.arange(R) * (S.NANG // R)).astype(np.int32)
+    n_used = int((rho >= 0).sum())
+    zero, nz = S.integrate(g, px, py, ph, rho, a_off, 35 * 65536, 218, -102, 896, match=(1, -2, 3, 0, -5, n_used),
+                           step_xy=32768, step_h=64, l_max=896.0)
+    assert np.array_equal(zero, g) and nz > 0
+    full, nf = S.integrate(g, px, py, ph, rho, a_off, 35 * 65536, 218, -102, 896,
+                           match=(1, -2, 3, 896 * n_used, 0, n_used), step_xy=32768, step_h=64, l_max=896.0)
+    ref, nr = S.integrate(g, px + 32768, py - 65536, ph + 192, rho, a_off, 35 * 65536, 218, -102, 896)
+    assert np.array_equal(full, ref) and nf == nr
+    # an aligned pose off the grid leaves it unchanged
+    off, no = S.integrate(g, -3 * 65536, py, ph, rho, a_off, 35 * 65536, 218, -102, 896)
+    assert np.array_equal(off, g) and no == 0
