@@ -200,10 +200,18 @@ def slam_time(wb, reps: int = 20, L: int = 10, iters: int = 3) -> dict:
     csm_ms = timed(lambda: slam.csm_match(belief, cell_off, side32, pose_q, rho_q, a_off, cfg, out=match,
                                           max_side=max_side))
     meas, info = slam.csm_factor(match, pose_q, cfg, cell, 896.0, 0.05, 0.02)
-    fac_ms = timed(lambda: slam.csm_factor(match, pose_q, cfg, cell, 896.0, 0.05, 0.02))
+    fac_ms = timed(lambda: slam.csm_factor(match, pose_q, cfg, cell, 896.0, 0.05, 0.02, meas=meas, info=info))
     scan[:, -1, :3] = meas
     scan[:, -1, 3:] = info
     gn_ms = timed(lambda: slam.fixedlag_solve(x0, prior, odo, scan, iters, x=xo, cov=cov, work=work))
+    # confidence-weighted integration of each scan from its matched pose, on a copy of the grids
+    lq = [int(round(float(p[k]) * 256.0)) for k in ("l_hit", "l_miss", "l_clamp")]
+    rmax_q = int(round(rmax / cell * 65536.0))
+    bel_w = belief.clone()
+    coded = torch.empty(n, dtype=torch.int32, device="cuda")
+    int_ms = timed(lambda: slam.csm_integrate(bel_w, cell_off, side32, pose_q, rho_q, a_off, rmax_q, *lq, match=match,
+                                              cfg=cfg, l_max=float(lq[2]), coded=coded, max_side=max_side))
+    del bel_w
     m = match.cpu().numpy()
     ncand = 9 * 9 * 11
     # a few robots' inputs on the host, for the oracle's timing in the CPU-baseline leg
@@ -214,13 +222,14 @@ def slam_time(wb, reps: int = 20, L: int = 10, iters: int = 3) -> dict:
     wb.slam_sample = dict(grids=[bel[offs[r]:offs[r] + sd[r] * sd[r]].reshape(sd[r], sd[r]) for r in range(k)],
                           pose=pose_q[:k].cpu().numpy(), rho=rho_q[:k].cpu().numpy(), a_off=a_off.cpu().numpy(),
                           x0=x0[:64].cpu().numpy(), prior=prior[:64].cpu().numpy(), odo=odo[:64].cpu().numpy(),
-                          scan=scan[:64].cpu().numpy(), L=L, iters=iters)
+                          scan=scan[:64].cpu().numpy(), L=L, iters=iters, match=m[:k], rmax_q=rmax_q, lq=lq)
     used = float(m[:, 5].mean())
     return {"robots": n, "rays": R, "lattice": [9, 9, 11], "candidates": ncand,
-            "csm_us": csm_ms * 1e3, "factor_us": fac_ms * 1e3, "fixedlag_us": gn_ms * 1e3,
-            "window_poses": L, "gn_iters": iters,
+            "csm_us": csm_ms * 1e3, "factor_us": fac_ms * 1e3, "integrate_us": int_ms * 1e3,
+            "fixedlag_us": gn_ms * 1e3, "window_poses": L, "gn_iters": iters,
             "candidate_ray_evals_per_s": n * ncand * used / (csm_ms / 1e3),
-            "robots_per_s": n / ((csm_ms + fac_ms + gn_ms) / 1e3),
+            "coded_cells_per_robot": float(coded.double().mean().item()),
+            "robots_per_s": n / ((csm_ms + fac_ms + int_ms + gn_ms) / 1e3),
             "rays_with_return": used,
             "mean_best_offset_cells": float(np.abs(m[:, :2]).mean()),
             "factor_weight_mean": float((info[:, 0] * 0.05 ** 2).mean().item())}
@@ -362,11 +371,19 @@ def cpu_slam(sample: dict) -> dict:
                     65536, 64, trig)
     t_csm = (time.time() - t0) / len(sample["grids"])
     t0 = time.time()
+    for r in range(len(sample["grids"])):
+        p = sample["pose"][r]
+        S.integrate(sample["grids"][r], int(p[0]), int(p[1]), int(p[2]), sample["rho"][r], sample["a_off"],
+                    sample["rmax_q"], *sample["lq"], match=sample["match"][r], step_xy=65536, step_h=64,
+                    l_max=float(sample["lq"][2]))
+    t_int = (time.time() - t0) / len(sample["grids"])
+    t0 = time.time()
     nw = sample["x0"].shape[0]
     for w in range(nw):
         S.fixedlag_solve(sample["x0"][w], sample["prior"][w], sample["odo"][w], sample["scan"][w], sample["iters"])
     t_gn = (time.time() - t0) / nw
-    return {"kind": "oracle", "cores": 1, "robots_per_s": 1.0 / (t_csm + t_gn), "csm_ms_per_robot": t_csm * 1e3,
+    return {"kind": "oracle", "cores": 1, "robots_per_s": 1.0 / (t_csm + t_int + t_gn),
+            "csm_ms_per_robot": t_csm * 1e3, "integrate_ms_per_robot": t_int * 1e3,
             "fixedlag_ms_per_window": t_gn * 1e3,
             "sample": f"{len(sample['grids'])} robots' scan matching, {nw} windows of {sample['L']} poses"}
 
@@ -564,7 +581,7 @@ def main():
         return
     slam_res = slam_time(wb)
     print(f"[bench] SLAM backbone: scan matching {slam_res['csm_us']:.1f} us, factors {slam_res['factor_us']:.1f} us, "
-          f"fixed-lag solve {slam_res['fixedlag_us']:.1f} us for {wb.n} robots", file=sys.stderr, flush=True)
+          f"weighted integration {slam_res['integrate_us']:.1f} us, fixed-lag solve {slam_res['fixedlag_us']:.1f} us for {wb.n} robots", file=sys.stderr, flush=True)
     if args.only_slam:   # profiling aid: the SLAM backbone alone
         print(json.dumps({"slam": slam_res}), flush=True)
         return
@@ -619,6 +636,7 @@ def main():
         "device": {"lds_per_block": lds, "compute_units": cus},
         "autotune": tuned or None,
     }
+    slam_sample = wb.slam_sample
     del wb
     torch.cuda.empty_cache()
     if not args.no_ppo:
@@ -635,7 +653,7 @@ def main():
         out["cpu_baseline"] = cpu_full_loop(args.workload, args.seed, args.cpu_robots, args.horizon, args.epochs)
         out["cpu_baseline"]["env_step_only"] = cpu_baseline(args.workload, args.seed, args.cpu_env_robots,
                                                             args.cpu_env_steps)
-        out["cpu_baseline"]["slam"] = cpu_slam(wb.slam_sample)
+        out["cpu_baseline"]["slam"] = cpu_slam(slam_sample)
     print(json.dumps(out), flush=True)
 
 

@@ -332,9 +332,10 @@ int aslam_gather_rows(const void* src_dev, int64_t row_bytes, const int32_t* idx
 
 /* ------------------------------------------------------------------ fixed-lag SLAM backbone
  *
- * The pose estimator of Sec. III-D as three batched calls: correlative scan matching of each
- * robot's scan against its log-odds grid, the scan factor of the match, and the Gauss-Newton solve of
- * a sliding window of poses with the newest pose's covariance.  The paper gives the method but not its
+ * The pose estimator of Sec. III-D as batched calls: correlative scan matching of each robot's scan
+ * against its log-odds grid, the scan factor of the match, the confidence-weighted integration of the
+ * aligned scan into the grid, and the Gauss-Newton solve of a sliding window of poses with the newest
+ * pose's covariance.  The paper gives the method but not its
  * constants or exact rules; the rules below are this library's reading of it. */
 
 typedef struct {
@@ -344,8 +345,8 @@ typedef struct {
   int32_t step_h;     /* heading step, in steps of the 46080-per-turn heading table, 0..46080 */
 } aslam_csm_config;
 
-/* Correlative scan matching (Sec. III-D, "a discretized neighborhood ... evaluated against the
- * log-odds occupancy grid") for n robots, one workgroup each, exact integer arithmetic.
+/* Correlative scan matching (Sec. III-D: candidate poses on a discrete lattice around the prediction,
+ * each scored on the log-odds grid) for n robots, one workgroup each, exact integer arithmetic.
  *   belief_dev   int16 log-odds; robot r's s x s grid starts at element cell_off_dev[r] (int64 [n]),
  *                cell (cx, cy) at cy * s + cx, s = side_dev[r] (int32 [n]);
  *   pose_q_dev   int32 [n,3]: predicted pose, x and y in Q16 cells, heading index in [0, 46080);
@@ -376,6 +377,31 @@ int aslam_csm_match(const int16_t* belief_dev, const int64_t* cell_off_dev, cons
 int aslam_csm_factor(const int32_t* match_dev, const int32_t* pose_q_dev, int32_t n, const aslam_csm_config* cfg,
                      double cell_m, double l_max, double sigma_xy, double sigma_th, double* meas_dev,
                      double* info_dev, aslam_stream_t stream);
+
+/* Confidence-weighted map integration (Sec. III-D: the aligned scan enters the grid with a weight that
+ * grows with the match score) for n robots, one workgroup each, in place on belief_dev (layout as for
+ * aslam_csm_match).  The aligned pose is pose_q_dev[r] moved by match_dev[r]'s lattice offsets
+ * (i step_xy_q, j step_xy_q, k step_h); the weight w = q m as in aslam_csm_factor, quantised to
+ * w_q = rint(256 w).  With match_dev NULL the pose is pose_q_dev[r] itself and w_q = 256 (cfg and l_max
+ * are then unused).  Each ray walks from the aligned position along the Q14 table direction of
+ * (heading + a_off_dev[q]) mod 46080 with the exact traversal of the env step: a cell is visited when
+ * its entry distance is within the range (rho_q_dev, Q16 cells; rays with rho < 0 have no return and
+ * walk rmax_q), an x crossing before a y crossing at equal distance, stopping at the grid's edge.
+ * Visited cells are MISS; the last cell of a ray with a return that stopped at its range is HIT (HIT
+ * beats MISS).  Each coded cell gets one add, L <- clamp(L + floor((w_q l + 128) / 256), -l_clamp,
+ * l_clamp), l = l_hit or l_miss (log-odds units of the grid).  An aligned position outside the grid
+ * leaves it unchanged.  coded_dev int32 [n] (may be NULL): coded cells per robot (-1: side above 65536,
+ * grid left unchanged).  max_side: the largest side (a host value) sizes the LDS bitmaps so that such a
+ * grid is one band of rows (at most 64 KB; larger grids take several bands; results do not depend on
+ * it).  The result does not depend on ray order.  Device arrays are not checked (the caller guarantees
+ * grids inside belief_dev).  ASL_EINVAL on NULL pointers, n < 0, max_side < 0, R outside [1, 65536],
+ * rmax_q < 0, l_clamp outside [1, 32767], increments outside [-32767, 32767], or, with a
+ * match, a NULL cfg, steps outside aslam_csm_config's ranges or l_max <= 0. */
+int aslam_csm_integrate(int16_t* belief_dev, const int64_t* cell_off_dev, const int32_t* side_dev, int32_t n,
+                        const int32_t* pose_q_dev, const int32_t* rho_q_dev, int32_t R, const int32_t* a_off_dev,
+                        int32_t max_side, int32_t rmax_q, const int32_t* match_dev, const aslam_csm_config* cfg,
+                        double l_max, int32_t l_hit, int32_t l_miss, int32_t l_clamp, int32_t* coded_dev,
+                        aslam_stream_t stream);
 
 /* Doubles of workspace aslam_fixedlag_solve needs for n windows of L poses (21 n L); -1 on bad sizes. */
 int64_t aslam_fixedlag_work_doubles(int32_t n, int32_t L);

@@ -98,6 +98,8 @@ SIGNATURES = {
     "aslam_csm_factor": (ctypes.c_int, [_P, _P, _I32, ctypes.POINTER(CsmConfig), ctypes.c_double, ctypes.c_double,
                                         ctypes.c_double, ctypes.c_double, _P, _P, _P]),
     "aslam_fixedlag_work_doubles": (_I64, [_I32, _I32]),
+    "aslam_csm_integrate": (ctypes.c_int, [_P, _P, _P, _I32, _P, _P, _I32, _P, _I32, _I32, _P, ctypes.POINTER(CsmConfig),
+                                            ctypes.c_double, _I32, _I32, _I32, _P, _P]),
     "aslam_fixedlag_solve": (ctypes.c_int, [_I32, _I32, _P, _P, _P, _P, _I32, _P, _P, _P, _P]),
 }
 

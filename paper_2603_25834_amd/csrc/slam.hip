@@ -9,7 +9,10 @@
 //  * the fixed-lag pose graph: a few Gauss-Newton steps over a window of L poses (a prior on the
 //    oldest, odometry factors between neighbours, unary scan factors) in FP64, solved by block
 //    elimination of the block-tridiagonal normal equations; the newest pose's marginal covariance,
-//    the last diagonal block of the inverse Hessian, is the inverse of the last Schur complement.
+//    the last diagonal block of the inverse Hessian, is the inverse of the last Schur complement;
+//  * the confidence-weighted map integration: the scan cast into the grid from the matched pose by
+//    the exact traversal of the env step's map update, each coded cell's log-odds increment scaled by
+//    the match weight quantised to 1/256.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -302,6 +305,14 @@ __device__ __forceinline__ double wrap_pi(double a) {
   return a - two_pi * rint(a / two_pi);
 }
 
+// Weight of a match: the normalised score times the margin to the second peak, both clamped to [0, 1].
+__device__ __forceinline__ double match_weight(const int32_t* m, double l_max) {
+  const double best = (double)m[3], second = (double)m[4];
+  const double q = m[5] <= 0 ? 0.0 : fmin(fmax(best / ((double)m[5] * l_max), 0.0), 1.0);
+  const double mg = fmin(fmax((best - second) / fmax(best, 1.0), 0.0), 1.0);
+  return q * mg;
+}
+
 __global__ void k_csm_factor(const int32_t* __restrict__ match, const int32_t* __restrict__ pose_q, int n,
                              int step_xy, int step_h, double cell_m, double l_max, double sig_xy, double sig_th,
                              double* __restrict__ meas, double* __restrict__ info) {
@@ -314,14 +325,190 @@ __global__ void k_csm_factor(const int32_t* __restrict__ match, const int32_t* _
   int64_t h = ((int64_t)p[2] + (int64_t)m[2] * step_h) % kNang;
   if (h < 0) h += kNang;
   const double th = wrap_pi(2.0 * 3.141592653589793 * (double)h / (double)kNang);
-  const double best = (double)m[3], second = (double)m[4];
-  const double q = m[5] <= 0 ? 0.0 : fmin(fmax(best / ((double)m[5] * l_max), 0.0), 1.0);
-  const double mg = fmin(fmax((best - second) / fmax(best, 1.0), 0.0), 1.0);
-  const double w = q * mg;
+  const double w = match_weight(m, l_max);
   meas[3 * (int64_t)r] = x; meas[3 * (int64_t)r + 1] = y; meas[3 * (int64_t)r + 2] = th;
   info[3 * (int64_t)r] = w / (sig_xy * sig_xy);
   info[3 * (int64_t)r + 1] = w / (sig_xy * sig_xy);
   info[3 * (int64_t)r + 2] = w / (sig_th * sig_th);
+}
+
+// ------------------------------------------------------------------ weighted map integration
+
+constexpr int kIntThreads = 512;
+constexpr int kIntLdsMinWords = 4096;    // LDS bitmaps of at least 16 KB: a band holds a row of any side <= 65536
+constexpr int kIntLdsMaxWords = 16384;   // and at most 64 KB
+constexpr int kIntMaxSide = 65536;
+constexpr int kIntInFlight = 4;          // octets (8 cells, 16 bytes) each thread keeps in flight in the apply pass
+
+// Saturating add of the increment of each coded cell of an octet (bit j of `any`: cell j coded, of `hit`:
+// a HIT) to the 8 int16 values packed in v.
+__device__ __forceinline__ int4 apply_octet(int4 v, uint32_t any, uint32_t hit, int32_t d_hit, int32_t d_miss,
+                                            int32_t lc) {
+  int32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    int32_t lo = (int16_t)(w[j] & 0xffff), hi = w[j] >> 16;
+    if ((any >> (2 * j)) & 1u) lo = min(max(lo + (((hit >> (2 * j)) & 1u) ? d_hit : d_miss), -lc), lc);
+    if ((any >> (2 * j + 1)) & 1u) hi = min(max(hi + (((hit >> (2 * j + 1)) & 1u) ? d_hit : d_miss), -lc), lc);
+    w[j] = (lo & 0xffff) | (hi << 16);
+  }
+  return make_int4(w[0], w[1], w[2], w[3]);
+}
+
+// One workgroup per robot.  The aligned pose is the predicted pose moved by the match's lattice
+// offsets; the increments are round(w_q l / 256) with w_q = rint(256 w).  Rows are processed in bands
+// whose two bitmaps fit the launch's LDS (sized for the largest side, up to 64 KB: a 512 x 512 grid is
+// one band).  Per band: clear; one lane per ray walks it from the aligned origin with the exact
+// traversal and sets MISS bits for the band's cells and the HIT bit of the end cell of a ray with a
+// return that ended at its range; then the apply pass: one saturating add per coded cell (HIT beats
+// MISS), an octet of 8 cells owned by one thread -- the result does not depend on ray or lane order.
+//
+// The walk: with (a, b) the Q14 direction and the origin's fractional position, the k-th x crossing lies
+// at axis distance ex0 + 65536 k and is within the range iff (ex0 + 65536 k) 2^14 <= rho |a|, so the
+// numbers of x and y crossings allowed by the range and by the grid's edge are known up front; crossings
+// are taken in order of distance by the sign of D = ex |b| - ey |a| (x first when D <= 0), a 32-bit
+// value that stays in (-65536 |a|, 65536 |b|].  The walk stops at the first crossing that is not
+// allowed; it ended at its range unless that crossing was barred by the grid's edge alone.
+__global__ __launch_bounds__(kIntThreads) void k_csm_integrate(
+    int16_t* __restrict__ belief, const int64_t* __restrict__ cell_off, const int32_t* __restrict__ side,
+    const int32_t* __restrict__ pose_q, const int32_t* __restrict__ rho_q, int R, const int32_t* __restrict__ a_off,
+    const int32_t* __restrict__ dirtab, int32_t rmax_q, const int32_t* __restrict__ match, int step_xy, int step_h,
+    double l_max, int l_hit, int l_miss, int l_clamp, int32_t* __restrict__ coded, int lds_words) {
+  extern __shared__ __align__(16) uint32_t bits[];
+  __shared__ int32_t s_cnt[kIntThreads / 64];
+  const int r = blockIdx.x;
+  const int64_t s = side[r];
+  const int64_t base = cell_off[r];
+  int64_t ax = pose_q[3 * (int64_t)r], ay = pose_q[3 * (int64_t)r + 1], ah = pose_q[3 * (int64_t)r + 2];
+  int32_t wq = 256;
+  if (match) {
+    const int32_t* m = match + 6 * (int64_t)r;
+    ax += (int64_t)m[0] * step_xy;
+    ay += (int64_t)m[1] * step_xy;
+    ah += (int64_t)m[2] * step_h;
+    wq = (int32_t)rint(256.0 * match_weight(m, l_max));
+  }
+  ah %= kNang;
+  if (ah < 0) ah += kNang;
+  const int32_t d_hit = (wq * l_hit + 128) >> 8, d_miss = (wq * l_miss + 128) >> 8;
+  const int64_t ocx = ax >> 16, ocy = ay >> 16;
+  if (s <= 0 || s > kIntMaxSide || ocx < 0 || ocx >= s || ocy < 0 || ocy >= s) {   // uniform over the workgroup
+    if (coded && threadIdx.x == 0) coded[r] = s > kIntMaxSide ? -1 : 0;
+    return;
+  }
+  const int32_t si = (int32_t)s, cx0 = (int32_t)ocx, cy0 = (int32_t)ocy;
+  const int32_t fx = (int32_t)(ax - (ocx << 16)), fy = (int32_t)(ay - (ocy << 16));
+  const int32_t nw = (si + 31) >> 5;
+  const int32_t band = min(si, lds_words / (2 * nw));
+  uint32_t* miss = bits;
+  uint32_t* hitm = bits + band * nw;
+  // 16-byte accesses when every row starts on an 8-cell boundary
+  const bool vec = ((base | s) & 7) == 0;
+  int32_t cnt = 0;
+  for (int32_t by0 = 0; by0 < si; by0 += band) {
+    const int32_t rows = min(band, si - by0);
+    for (int32_t w = threadIdx.x; w < 2 * band * nw; w += kIntThreads) bits[w] = 0u;
+    __syncthreads();
+    for (int k = threadIdx.x; k < R; k += kIntThreads) {
+      const int32_t rho = rho_q[(int64_t)r * R + k];
+      const int64_t lim = rho >= 0 ? (int64_t)rho : (int64_t)rmax_q;
+      int64_t di = (ah + (int64_t)a_off[k]) % kNang;
+      if (di < 0) di += kNang;
+      const int32_t dv = dirtab[di];
+      const int32_t a = (int16_t)(dv & 0xffff), b = dv >> 16;
+      const int32_t aa = abs(a), bb = abs(b);
+      const int32_t ex0 = a > 0 ? 65536 - fx : fx, ey0 = b > 0 ? 65536 - fy : fy;
+      const int64_t emx = (lim * aa) >> 14, emy = (lim * bb) >> 14;
+      const int64_t nxl = (aa == 0 || emx < ex0) ? 0 : ((emx - ex0) >> 16) + 1;
+      const int64_t nyl = (bb == 0 || emy < ey0) ? 0 : ((emy - ey0) >> 16) + 1;
+      const int32_t nxg = a > 0 ? si - 1 - cx0 : cx0, nyg = b > 0 ? si - 1 - cy0 : cy0;
+      const int32_t nx = (int32_t)min((int64_t)nxg, nxl), ny = (int32_t)min((int64_t)nyg, nyl);
+      const bool gx = nxg < nxl, gy = nyg < nyl;
+      const int32_t sx = a > 0 ? 1 : -1, sy = b > 0 ? 1 : -1;
+      const int32_t DX = bb << 16, DY = aa << 16;
+      // D <= 0 steps x; a direction along an axis never steps the other one
+      int32_t D = aa == 0 ? 1 : (bb == 0 ? -1 : ex0 * bb - ey0 * aa);
+      const int32_t dX = bb == 0 ? 0 : DX, dY = aa == 0 ? 0 : DY;
+      int32_t cx = cx0, cy = cy0, kx = 0, ky = 0;
+      bool at_limit = true;
+      for (;;) {
+        const int32_t row = cy - by0;
+        if ((uint32_t)row < (uint32_t)rows) atomicOr(&miss[row * nw + (cx >> 5)], 1u << (cx & 31));
+        if (D <= 0) {
+          if (kx == nx) { at_limit = !gx; break; }
+          ++kx;
+          cx += sx;
+          D += dX;
+        } else {
+          if (ky == ny) { at_limit = !gy; break; }
+          ++ky;
+          cy += sy;
+          D -= dY;
+        }
+      }
+      const int32_t row = cy - by0;
+      if (rho >= 0 && at_limit && (uint32_t)row < (uint32_t)rows)
+        atomicOr(&hitm[row * nw + (cx >> 5)], 1u << (cx & 31));
+    }
+    __syncthreads();
+    // apply: octet o covers cells 8 (o mod 4nw) .. + 7 of band row o / 4nw
+    const int32_t opr = 4 * nw, total = rows * opr;
+    int16_t* band_base = belief + base + (int64_t)by0 * s;
+    for (int32_t o0 = threadIdx.x; o0 < total; o0 += kIntInFlight * kIntThreads) {
+      uint32_t any[kIntInFlight], hit[kIntInFlight];
+      int64_t off[kIntInFlight];
+#pragma unroll
+      for (int u = 0; u < kIntInFlight; ++u) {
+        const int32_t o = o0 + u * kIntThreads;
+        any[u] = 0u;
+        hit[u] = 0u;
+        off[u] = 0;
+        if (o < total) {
+          const int32_t row = o / opr, oc = o - row * opr, sh = (oc & 3) * 8;
+          const uint32_t wm = miss[row * nw + (oc >> 2)], wh = hitm[row * nw + (oc >> 2)];
+          hit[u] = (wh >> sh) & 0xffu;
+          any[u] = ((wm >> sh) & 0xffu) | hit[u];
+          off[u] = (int64_t)row * s + 8 * oc;
+        }
+        cnt += __builtin_popcount(any[u]);
+      }
+      if (vec) {
+        int4 v[kIntInFlight];
+#pragma unroll
+        for (int u = 0; u < kIntInFlight; ++u)
+          if (any[u]) v[u] = *reinterpret_cast<const int4*>(band_base + off[u]);
+#pragma unroll
+        for (int u = 0; u < kIntInFlight; ++u)
+          if (any[u])
+            *reinterpret_cast<int4*>(band_base + off[u]) = apply_octet(v[u], any[u], hit[u], d_hit, d_miss, l_clamp);
+      } else {
+#pragma unroll
+        for (int u = 0; u < kIntInFlight; ++u) {
+          int16_t* c = band_base + off[u];
+          int16_t v[8];
+#pragma unroll
+          for (int j = 0; j < 8; ++j)
+            if ((any[u] >> j) & 1u) v[j] = c[j];
+#pragma unroll
+          for (int j = 0; j < 8; ++j)
+            if ((any[u] >> j) & 1u)
+              c[j] = (int16_t)min(max((int32_t)v[j] + (((hit[u] >> j) & 1u) ? d_hit : d_miss), -l_clamp), l_clamp);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (coded) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
+    if ((threadIdx.x & 63) == 0) s_cnt[threadIdx.x >> 6] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int32_t t = 0;
+      for (int i = 0; i < kIntThreads / 64; ++i) t += s_cnt[i];
+      coded[r] = t;
+    }
+  }
 }
 
 // ------------------------------------------------------------------ fixed-lag Gauss-Newton
@@ -618,6 +805,46 @@ int aslam_csm_factor(const int32_t* match_dev, const int32_t* pose_q_dev, int32_
   k_csm_factor<<<(n + 255) / 256, 256, 0, (hipStream_t)stream>>>(match_dev, pose_q_dev, n, cfg->step_xy_q,
                                                                   cfg->step_h, cell_m, l_max, sigma_xy, sigma_th,
                                                                   meas_dev, info_dev);
+  SCHK(hipGetLastError());
+  return ASL_OK;
+}
+
+int aslam_csm_integrate(int16_t* belief_dev, const int64_t* cell_off_dev, const int32_t* side_dev, int32_t n,
+                        const int32_t* pose_q_dev, const int32_t* rho_q_dev, int32_t R, const int32_t* a_off_dev,
+                        int32_t max_side, int32_t rmax_q, const int32_t* match_dev, const aslam_csm_config* cfg,
+                        double l_max, int32_t l_hit, int32_t l_miss, int32_t l_clamp, int32_t* coded_dev,
+                        aslam_stream_t stream) {
+  if (n < 0) return sfail(ASL_EINVAL, "n must be >= 0");
+  if (max_side < 0) return sfail(ASL_EINVAL, "max_side must be >= 0");
+  if (R < 1 || R > (1 << 16)) return sfail(ASL_EINVAL, "R must be in [1, 65536]");
+  if (rmax_q < 0) return sfail(ASL_EINVAL, "rmax_q must be >= 0");
+  if (l_clamp < 1 || l_clamp > 32767 || l_hit < -32767 || l_hit > 32767 || l_miss < -32767 || l_miss > 32767)
+    return sfail(ASL_EINVAL, "l_clamp must be in [1, 32767] and the increments in [-32767, 32767]");
+  int step_xy = 0, step_h = 0;
+  if (match_dev) {
+    if (!cfg) return sfail(ASL_EINVAL, "csm config is NULL");
+    if (cfg->step_xy_q < 1 || cfg->step_xy_q > (1 << 20) || cfg->step_h < 0 || cfg->step_h > kNang)
+      return sfail(ASL_EINVAL, "csm steps out of range (step_xy_q in [1, 2^20], step_h in [0, 46080])");
+    if (!(l_max > 0.0)) return sfail(ASL_EINVAL, "l_max must be positive");
+    step_xy = cfg->step_xy_q;
+    step_h = cfg->step_h;
+  }
+  if (n == 0) return ASL_OK;
+  if (!belief_dev || !cell_off_dev || !side_dev || !pose_q_dev || !rho_q_dev || !a_off_dev)
+    return sfail(ASL_EINVAL, "null argument to csm_integrate");
+  const int32_t* tab = nullptr;
+  const int rc = dirtab_for_current_device(&tab);
+  if (rc) return rc;
+  // bitmaps of one band holding the largest grid whole, within [16 KB, 64 KB]
+  const int64_t nw_max = ((int64_t)std::min(max_side, kIntMaxSide) + 31) >> 5;
+  const int words = (int)std::min<int64_t>(kIntLdsMaxWords, std::max<int64_t>(kIntLdsMinWords, 2 * nw_max * max_side));
+  const int bytes = (int)sizeof(uint32_t) * words;
+  SCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_csm_integrate),
+                           hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
+  k_csm_integrate<<<n, kIntThreads, bytes, (hipStream_t)stream>>>(belief_dev, cell_off_dev, side_dev, pose_q_dev,
+                                                                  rho_q_dev, R, a_off_dev, tab, rmax_q, match_dev,
+                                                                  step_xy, step_h, match_dev ? l_max : 1.0, l_hit,
+                                                                  l_miss, l_clamp, coded_dev, words);
   SCHK(hipGetLastError());
   return ASL_OK;
 }

@@ -1,5 +1,6 @@
 """The fixed-lag SLAM backbone (arXiv 2603.25834, Sec. III-D) over the C-ABI: correlative scan
-matching, the scan factor of a match, and the Gauss-Newton solve of a window of poses with the newest
+matching, the scan factor of a match, the confidence-weighted integration of the aligned scan into the
+grid, and the Gauss-Newton solve of a window of poses with the newest
 pose's covariance.  Argument marshalling only: the arithmetic runs in the library's HIP kernels."""
 from __future__ import annotations
 
@@ -43,14 +44,42 @@ def csm_match(belief: torch.Tensor, cell_off: torch.Tensor, side: torch.Tensor, 
 
 
 def csm_factor(match: torch.Tensor, pose_q: torch.Tensor, cfg: CsmConfig, cell_m: float, l_max: float,
-               sigma_xy: float, sigma_th: float):
-    """Scan factor of each match: measurement (x, y, theta) [n, 3] and information diagonal [n, 3], FP64."""
+               sigma_xy: float, sigma_th: float, meas: torch.Tensor | None = None, info: torch.Tensor | None = None):
+    """Scan factor of each match: measurement (x, y, theta) [n, 3] and information diagonal [n, 3], FP64
+    (written into `meas` / `info` when given)."""
     n = match.shape[0]
-    meas = torch.empty((n, 3), dtype=torch.float64, device=match.device)
-    info = torch.empty((n, 3), dtype=torch.float64, device=match.device)
+    if meas is None:
+        meas = torch.empty((n, 3), dtype=torch.float64, device=match.device)
+    if info is None:
+        info = torch.empty((n, 3), dtype=torch.float64, device=match.device)
+    for t in (meas, info):
+        if t.shape != (n, 3) or t.dtype != torch.float64 or not t.is_contiguous() or t.device != match.device:
+            raise ValueError("csm_factor: outputs must be contiguous float64 [n, 3] on the match's device")
     check(lib().aslam_csm_factor(_p(match), _p(pose_q), n, ctypes.byref(cfg), cell_m, l_max, sigma_xy, sigma_th,
                                  _p(meas), _p(info), _stream()))
     return meas, info
+
+
+def csm_integrate(belief: torch.Tensor, cell_off: torch.Tensor, side: torch.Tensor, pose_q: torch.Tensor,
+                  rho_q: torch.Tensor, a_off: torch.Tensor, rmax_q: int, l_hit: int, l_miss: int, l_clamp: int,
+                  match: torch.Tensor | None = None, cfg: CsmConfig | None = None, l_max: float = 1.0,
+                  coded: torch.Tensor | None = None, max_side: int | None = None):
+    """Integrate each robot's scan into its grid, in place, from the matched pose with increments scaled by
+    the match weight (unweighted from pose_q when `match` is None).  Returns the coded cells per robot,
+    int32 [n].  max_side: the largest grid side (read from `side` when not given)."""
+    if max_side is None:
+        max_side = int(side.max().item()) if side.numel() else 0
+    n, R = rho_q.shape
+    assert belief.dtype == torch.int16 and cell_off.dtype == torch.int64 and side.dtype == torch.int32
+    assert pose_q.dtype == torch.int32 and tuple(pose_q.shape) == (n, 3)
+    assert rho_q.dtype == torch.int32 and a_off.dtype == torch.int32 and a_off.numel() == R
+    if match is not None:
+        assert match.dtype == torch.int32 and tuple(match.shape) == (n, 6) and cfg is not None
+    coded = torch.empty(n, dtype=torch.int32, device=rho_q.device) if coded is None else coded
+    check(lib().aslam_csm_integrate(_p(belief), _p(cell_off), _p(side), n, _p(pose_q), _p(rho_q), R, _p(a_off),
+                                    int(max_side), int(rmax_q), _p(match), None if cfg is None else ctypes.byref(cfg), float(l_max),
+                                    int(l_hit), int(l_miss), int(l_clamp), _p(coded), _stream()))
+    return coded
 
 
 def fixedlag_solve(x0: torch.Tensor, prior: torch.Tensor, odo: torch.Tensor | None, scan: torch.Tensor, iters: int,

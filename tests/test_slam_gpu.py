@@ -170,3 +170,81 @@ def test_full_batch_sampled_and_errors():
     with pytest.raises(_lib.AslamError):   # (2V + 1) R > 8192
         slam.csm_match(d(belief[:16]), d(cell_off[:1]), d(side[:1]), d(pose[:1]), d(np.zeros((1, 1000), np.int32)),
                        d(np.zeros(1000, np.int32)), slam.csm_config(1, 8, 65536, 1))
+
+
+# ------------------------------------------------------------------ weighted map integration
+
+def _integrate_case(seed, sides, R, W, V, sxy, sh, rmax_q, weighted=True, max_side=None):
+    grids, belief, cell_off, side, pose, rho, a_off = _batch(seed, sides, R, W, V, sxy, sh)
+    trig = S._trig()
+    rng = np.random.default_rng(seed + 1)
+    match = None
+    if weighted:
+        # the oracle's own matches, with a few margins moved so that weights span [0, 1]
+        match = np.array([S.csm_match(grids[r], int(pose[r, 0]), int(pose[r, 1]), int(pose[r, 2]), rho[r], a_off,
+                                      W, V, sxy, sh, trig) for r in range(len(sides))], np.int64)
+        for r in range(0, len(sides), 3):
+            match[r, 3] = int((match[r, 5]) * 896 * rng.uniform(0.2, 1.0))
+            match[r, 4] = int(match[r, 3] * rng.uniform(-0.5, 0.9))
+        match = match.astype(np.int32)
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    bel = d(belief)
+    cfg = slam.csm_config(W, V, sxy, sh)
+    coded = slam.csm_integrate(bel, d(cell_off), d(side), d(pose), d(rho), d(a_off), rmax_q, 218, -102, 896,
+                               match=None if match is None else d(match), cfg=cfg, l_max=896.0, max_side=max_side)
+    torch.cuda.synchronize()
+    got = bel.cpu().numpy()
+    coded = coded.cpu().numpy()
+    for r in range(len(sides)):
+        want, nc = S.integrate(grids[r], int(pose[r, 0]), int(pose[r, 1]), int(pose[r, 2]), rho[r], a_off, rmax_q,
+                               218, -102, 896, match=None if match is None else match[r], step_xy=sxy, step_h=sh,
+                               l_max=896.0)
+        s = sides[r]
+        o = int(cell_off[r])
+        assert np.array_equal(got[o:o + s * s].reshape(s, s), want), r
+        assert int(coded[r]) == nc, (r, coded[r], nc)
+    return coded
+
+
+@pytest.mark.parametrize("weighted", [True, False], ids=["weighted", "unweighted"])
+def test_integrate_bit_exact(weighted):
+    sides = [64, 96, 128, 256, 32, 64, 160, 128, 64, 96]
+    say(f"[slam] integrate weighted={weighted} robots={len(sides)}")
+    coded = _integrate_case(41, sides, 90, 4, 5, 32768, 48, 30 * 65536, weighted)
+    assert (coded > 0).sum() >= 3
+
+
+def test_integrate_bands_and_max_side():
+    """Grids larger than one band of the LDS bitmaps (side 600 with a 64 KB budget; side 300 with the
+    bitmaps sized for side 64) give the same exact answers."""
+    say("[slam] integrate in bands")
+    _integrate_case(43, [600, 64, 128], 120, 2, 2, 65536, 64, 200 * 65536)
+    _integrate_case(44, [300, 64, 200, 96], 90, 2, 2, 65536, 64, 120 * 65536, max_side=64)
+
+
+def test_integrate_full_batch_sampled_and_errors():
+    """750 robots of 256^2 grids and 360 rays from the scan matcher's own output on the GPU (inputs only:
+    each sampled robot is checked with the oracle on that match); then the argument checks."""
+    from paper_2603_25834_amd import _lib
+    W, V, sxy, sh, R = 4, 5, 65536, 64, 360
+    sides = [256] * 750
+    grids, belief, cell_off, side, pose, rho, a_off = _batch(23, sides, R, W, V, sxy, sh, invalid_p=0.05)
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    cfg = slam.csm_config(W, V, sxy, sh)
+    match = slam.csm_match(d(belief), d(cell_off), d(side), d(pose), d(rho), d(a_off), cfg)
+    bel = d(belief)
+    coded = slam.csm_integrate(bel, d(cell_off), d(side), d(pose), d(rho), d(a_off), 200 * 65536, 218, -102, 896,
+                               match=match, cfg=cfg, l_max=896.0)
+    torch.cuda.synchronize()
+    got, m, coded = bel.cpu().numpy(), match.cpu().numpy(), coded.cpu().numpy()
+    for r in np.random.default_rng(4).choice(750, 12, replace=False):
+        want, nc = S.integrate(grids[r], int(pose[r, 0]), int(pose[r, 1]), int(pose[r, 2]), rho[r], a_off,
+                               200 * 65536, 218, -102, 896, match=m[r], step_xy=sxy, step_h=sh, l_max=896.0)
+        o = int(cell_off[r])
+        assert np.array_equal(got[o:o + 65536].reshape(256, 256), want) and int(coded[r]) == nc, r
+    with pytest.raises(_lib.AslamError):   # l_clamp out of range
+        slam.csm_integrate(bel, d(cell_off), d(side), d(pose), d(rho), d(a_off), 65536, 218, -102, 0)
+    with pytest.raises(_lib.AslamError):   # a match without a config
+        _lib.check(_lib.lib().aslam_csm_integrate(slam._p(bel), slam._p(d(cell_off)), slam._p(d(side)), 750,
+                                                  slam._p(d(pose)), slam._p(d(rho)), R, slam._p(d(a_off)), 256, 65536,
+                                                  slam._p(match), None, 896.0, 218, -102, 896, None, slam._stream()))
