@@ -429,23 +429,22 @@ __global__ __launch_bounds__(kIntThreads) void k_csm_integrate(
       // D <= 0 steps x; a direction along an axis never steps the other one
       int32_t D = aa == 0 ? 1 : (bb == 0 ? -1 : ex0 * bb - ey0 * aa);
       const int32_t dX = bb == 0 ? 0 : DX, dY = aa == 0 ? 0 : DY;
+      // branch-free steps (the crossing is selected, not branched on); a lane leaves when its next
+      // crossing is not allowed
       int32_t cx = cx0, cy = cy0, kx = 0, ky = 0;
-      bool at_limit = true;
+      bool stepx;
       for (;;) {
         const int32_t row = cy - by0;
         if ((uint32_t)row < (uint32_t)rows) atomicOr(&miss[row * nw + (cx >> 5)], 1u << (cx & 31));
-        if (D <= 0) {
-          if (kx == nx) { at_limit = !gx; break; }
-          ++kx;
-          cx += sx;
-          D += dX;
-        } else {
-          if (ky == ny) { at_limit = !gy; break; }
-          ++ky;
-          cy += sy;
-          D -= dY;
-        }
+        stepx = D <= 0;
+        if (stepx ? kx == nx : ky == ny) break;
+        kx += stepx ? 1 : 0;
+        ky += stepx ? 0 : 1;
+        cx += stepx ? sx : 0;
+        cy += stepx ? 0 : sy;
+        D += stepx ? dX : -dY;
       }
+      const bool at_limit = !(stepx ? gx : gy);
       const int32_t row = cy - by0;
       if (rho >= 0 && at_limit && (uint32_t)row < (uint32_t)rows)
         atomicOr(&hitm[row * nw + (cx >> 5)], 1u << (cx & 31));
