@@ -339,6 +339,8 @@ constexpr int kIntLdsMinWords = 4096;    // LDS bitmaps of at least 16 KB: a ban
 constexpr int kIntLdsMaxWords = 16384;   // and at most 64 KB
 constexpr int kIntMaxSide = 65536;
 constexpr int kIntInFlight = 4;          // octets (8 cells, 16 bytes) each thread keeps in flight in the apply pass
+constexpr int kIntSortMax = 2048;        // rays are ordered by walk length when R <= this
+constexpr int kIntBins = 64;             // length classes of 8 steps
 
 // Saturating add of the increment of each coded cell of an octet (bit j of `any`: cell j coded, of `hit`:
 // a HIT) to the 8 int16 values packed in v.
@@ -361,7 +363,9 @@ __device__ __forceinline__ int4 apply_octet(int4 v, uint32_t any, uint32_t hit, 
 // one band).  Per band: clear; one lane per ray walks it from the aligned origin with the exact
 // traversal and sets MISS bits for the band's cells and the HIT bit of the end cell of a ray with a
 // return that ended at its range; then the apply pass: one saturating add per coded cell (HIT beats
-// MISS), an octet of 8 cells owned by one thread -- the result does not depend on ray or lane order.
+// MISS), an octet of 8 cells owned by one thread -- the result does not depend on ray or lane order,
+// so lanes take the rays longest first (a counting sort on the walk's length bound), which keeps the
+// rays of a wave alike in length and the workgroups that share a compute unit from issuing idle steps.
 //
 // The walk: with (a, b) the Q14 direction and the origin's fractional position, the k-th x crossing lies
 // at axis distance ex0 + 65536 k and is within the range iff (ex0 + 65536 k) 2^14 <= rho |a|, so the
@@ -376,6 +380,8 @@ __global__ __launch_bounds__(kIntThreads) void k_csm_integrate(
     double l_max, int l_hit, int l_miss, int l_clamp, int32_t* __restrict__ coded, int lds_words) {
   extern __shared__ __align__(16) uint32_t bits[];
   __shared__ int32_t s_cnt[kIntThreads / 64];
+  __shared__ uint16_t s_perm[kIntSortMax];
+  __shared__ int32_t s_hist[kIntBins];
   const int r = blockIdx.x;
   const int64_t s = side[r];
   const int64_t base = cell_off[r];
@@ -404,12 +410,52 @@ __global__ __launch_bounds__(kIntThreads) void k_csm_integrate(
   uint32_t* hitm = bits + band * nw;
   // 16-byte accesses when every row starts on an 8-cell boundary
   const bool vec = ((base | s) & 7) == 0;
+  const bool sorted = R <= kIntSortMax;
+  if (sorted) {
+    // length class of a ray: its Manhattan length in cells (an upper bound of its steps) / 8
+    auto ray_class = [&](int k) {
+      const int32_t rho = rho_q[(int64_t)r * R + k];
+      const int64_t lim = rho >= 0 ? (int64_t)rho : (int64_t)rmax_q;
+      int64_t di = (ah + (int64_t)a_off[k]) % kNang;
+      if (di < 0) di += kNang;
+      const int32_t dv = dirtab[di];
+      const int64_t ab = abs((int32_t)(int16_t)(dv & 0xffff)) + abs(dv >> 16);
+      return (int32_t)min<int64_t>(kIntBins - 1, ((lim >> 16) * ab) >> 17);
+    };
+    constexpr int kPer = kIntSortMax / kIntThreads;
+    int32_t cls[kPer];
+    for (int i = threadIdx.x; i < kIntBins; i += kIntThreads) s_hist[i] = 0;
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int k = threadIdx.x + u * kIntThreads;
+      cls[u] = k < R ? ray_class(k) : 0;
+      if (k < R) atomicAdd(&s_hist[cls[u]], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {   // start of each class, longest class first
+      int32_t acc = 0;
+      for (int c = kIntBins - 1; c >= 0; --c) {
+        const int32_t h = s_hist[c];
+        s_hist[c] = acc;
+        acc += h;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int k = threadIdx.x + u * kIntThreads;
+      if (k < R) s_perm[atomicAdd(&s_hist[cls[u]], 1)] = (uint16_t)k;
+    }
+    __syncthreads();
+  }
   int32_t cnt = 0;
   for (int32_t by0 = 0; by0 < si; by0 += band) {
     const int32_t rows = min(band, si - by0);
     for (int32_t w = threadIdx.x; w < 2 * band * nw; w += kIntThreads) bits[w] = 0u;
     __syncthreads();
-    for (int k = threadIdx.x; k < R; k += kIntThreads) {
+    for (int j = threadIdx.x; j < R; j += kIntThreads) {
+      const int k = sorted ? (int)s_perm[j] : j;
       const int32_t rho = rho_q[(int64_t)r * R + k];
       const int64_t lim = rho >= 0 ? (int64_t)rho : (int64_t)rmax_q;
       int64_t di = (ah + (int64_t)a_off[k]) % kNang;
