@@ -183,7 +183,6 @@ def slam_time(wb, reps: int = 20, L: int = 10, iters: int = 3) -> dict:
     scan = torch.zeros((n, L, 6), dtype=torch.float64, device="cuda")
     xo = torch.empty_like(x0)
     cov = torch.empty((n, 3, 3), dtype=torch.float64, device="cuda")
-    work = torch.empty(int(_lib.lib().aslam_fixedlag_work_doubles(n, L)), dtype=torch.float64, device="cuda")
 
     def timed(fn):
         fn()
@@ -203,7 +202,7 @@ def slam_time(wb, reps: int = 20, L: int = 10, iters: int = 3) -> dict:
     fac_ms = timed(lambda: slam.csm_factor(match, pose_q, cfg, cell, 896.0, 0.05, 0.02, meas=meas, info=info))
     scan[:, -1, :3] = meas
     scan[:, -1, 3:] = info
-    gn_ms = timed(lambda: slam.fixedlag_solve(x0, prior, odo, scan, iters, x=xo, cov=cov, work=work))
+    gn_ms = timed(lambda: slam.fixedlag_solve(x0, prior, odo, scan, iters, x=xo, cov=cov))
     # confidence-weighted integration of each scan from its matched pose, on a copy of the grids
     lq = [int(round(float(p[k]) * 256.0)) for k in ("l_hit", "l_miss", "l_clamp")]
     rmax_q = int(round(rmax / cell * 65536.0))

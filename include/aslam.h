@@ -403,19 +403,21 @@ int aslam_csm_integrate(int16_t* belief_dev, const int64_t* cell_off_dev, const 
                         double l_max, int32_t l_hit, int32_t l_miss, int32_t l_clamp, int32_t* coded_dev,
                         aslam_stream_t stream);
 
-/* Doubles of workspace aslam_fixedlag_solve needs for n windows of L poses (21 n L); -1 on bad sizes. */
+/* Doubles of workspace a caller may pass to aslam_fixedlag_solve for n windows of L poses (21 n L);
+ * -1 on bad sizes.  The solver keeps its workspace in LDS and does not touch the buffer. */
 int64_t aslam_fixedlag_work_doubles(int32_t n, int32_t L);
 
 /* Fixed-lag pose graph (Sec. III-D; the minimisation of the weighted residuals and the covariance
  * of the newest pose as the last block of the inverse Gauss-Newton Hessian), n windows of L poses in
- * FP64, one thread each.  Factors: a prior on pose 0, prior_dev [n,6] (mean x, y, theta; information
+ * FP64, one wavefront each (the poses are linearised in parallel, one lane each; one lane runs the
+ * elimination sweep; the window lives in LDS).  Factors: a prior on pose 0, prior_dev [n,6] (mean x, y, theta; information
  * diagonal); odometry between poses i and i+1, odo_dev [n,L-1,6] (the motion in the frame of pose i,
  * residual (R(th_i)^T (t_{i+1} - t_i) - u_t, wrap(th_{i+1} - th_i - u_th)); information diagonal; may
  * be NULL when L = 1); scan factors scan_dev [n,L,6] (measurement; information diagonal, all zero = no
  * factor).  From x0_dev [n,L,3] it takes `iters` Gauss-Newton steps (analytic Jacobians, block
  * elimination of the block-tridiagonal normal equations) into x_dev [n,L,3], then writes the newest
- * pose's covariance, formed at the result, to cov_dev [n,3,3].  work_dev: caller-owned scratch of
- * aslam_fixedlag_work_doubles(n, L) doubles.  ASL_EINVAL on NULL pointers, n < 0, L outside [1, 64] or
+ * pose's covariance, formed at the result, to cov_dev [n,3,3].  work_dev: unused, may be NULL.
+ * ASL_EINVAL on NULL pointers (other than work_dev), n < 0, L outside [1, 64] or
  * iters outside [0, 100].  A singular window (no prior information) gives non-finite results. */
 int aslam_fixedlag_solve(int32_t n, int32_t L, const double* x0_dev, const double* prior_dev, const double* odo_dev,
                          const double* scan_dev, int32_t iters, double* x_dev, double* cov_dev, double* work_dev,

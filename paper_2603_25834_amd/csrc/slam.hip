@@ -621,137 +621,150 @@ __device__ __forceinline__ void add_jtwr(double* acc, const double P[3][3], cons
   }
 }
 
-// Block elimination of the window's normal equations at x (the caller's [L][3]): for each pose i the
-// diagonal block A_i, the coupling B_i = H[i][i+1] and the gradient g_i are formed as the sweep reaches
-// them; D_i = A_i - B_{i-1}^T D_{i-1}^{-1} B_{i-1}, y_i = -g_i - B_{i-1}^T D_{i-1}^{-1} y_{i-1}.  Work per
-// pose: D_i^{-1} (9), C_i = D_i^{-1} B_i (9), y_i (3).  Returns D_{L-1}^{-1} in *last.
-__device__ __forceinline__ void eliminate(const double* x, int L, const double* prior, const double* odo,
-                                          const double* scan, double* work, M3& last) {
-  double Bprev[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-  double Ajn[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};   // the next pose's share of the last odometry factor
-  double gjn[3] = {0, 0, 0};
+// One wavefront per window.  Each Gauss-Newton step linearises every pose in parallel, lane i < L
+// forming the diagonal block A_i, the coupling B_i = H[i][i+1] and the gradient g_i from the factors
+// that touch pose i (the prior on pose 0, its scan factor, the odometry factors to i-1 and to i+1,
+// each with analytic Jacobians).  Lane 0 then eliminates the block-tridiagonal system pose by pose,
+// D_i = A_i - B_{i-1}^T D_{i-1}^{-1} B_{i-1}, y_i = -g_i - B_{i-1}^T D_{i-1}^{-1} y_{i-1}, keeping
+// D_i^{-1}, C_i = D_i^{-1} B_i and y_i, and back-substitutes delta_{L-1} = D_{L-1}^{-1} y_{L-1},
+// delta_i = D_i^{-1} y_i - C_i delta_{i+1}.  After K steps one more linearisation and elimination at
+// the result gives Sigma = D_{L-1}^{-1}, the last diagonal block of the inverse Hessian.  Everything
+// lives in LDS: 45 L doubles per window.
+constexpr int kLagThreads = 64;
+constexpr int kLagMaxL = 64;
+
+__device__ __forceinline__ void linearise_pose(const double* x, int L, int i, const double* prior, const double* odo,
+                                               const double* scan, double* A_out, double* B_out, double* g_out) {
+  double A[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, B[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  double g[3] = {0, 0, 0};
+  const double* xi = x + 3 * i;
+  if (i == 0) {
+    const double r[3] = {xi[0] - prior[0], xi[1] - prior[1], wrap_pi(xi[2] - prior[2])};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) { A[a][a] += prior[3 + a]; g[a] += prior[3 + a] * r[a]; }
+  }
+  const double* sc = scan + 6 * i;
+  if (sc[3] != 0.0 || sc[4] != 0.0 || sc[5] != 0.0) {
+    const double r[3] = {xi[0] - sc[0], xi[1] - sc[1], wrap_pi(xi[2] - sc[2])};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) { A[a][a] += sc[3 + a]; g[a] += sc[3 + a] * r[a]; }
+  }
+  if (i > 0) {   // odometry factor (i-1, i): pose i's share
+    const double* o = odo + 6 * (i - 1);
+    double r[3], Ji[3][3], Jj[3][3];
+    odo_factor(x + 3 * (i - 1), xi, o, r, Ji, Jj);
+    add_jtwj(A, Jj, o + 3, Jj);
+    add_jtwr(g, Jj, o + 3, r);
+  }
+  if (i + 1 < L) {   // odometry factor (i, i+1): pose i's share and the coupling
+    const double* o = odo + 6 * i;
+    double r[3], Ji[3][3], Jj[3][3];
+    odo_factor(xi, x + 3 * (i + 1), o, r, Ji, Jj);
+    add_jtwj(A, Ji, o + 3, Ji);
+    add_jtwj(B, Ji, o + 3, Jj);
+    add_jtwr(g, Ji, o + 3, r);
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    g_out[a] = g[a];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) { A_out[3 * a + b] = A[a][b]; B_out[3 * a + b] = B[a][b]; }
+  }
+}
+
+// Lane 0: the elimination sweep over the linearised window; returns D_{L-1}^{-1} in *last.
+__device__ __forceinline__ void eliminate_sweep(int L, const double* sA, const double* sB, const double* sg,
+                                                double* sDi, double* sC, double* sy, M3& last) {
   for (int i = 0; i < L; ++i) {
-    double A[3][3], g[3], B[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    M3 D;
+    double y[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      g[a] = gjn[a];
+      y[a] = -sg[3 * i + a];
 #pragma unroll
-      for (int b = 0; b < 3; ++b) A[a][b] = Ajn[a][b];
+      for (int b = 0; b < 3; ++b) D.a[a][b] = sA[9 * i + 3 * a + b];
     }
-    const double* xi = x + 3 * i;
-    if (i == 0) {
-      double r[3] = {xi[0] - prior[0], xi[1] - prior[1], wrap_pi(xi[2] - prior[2])};
-#pragma unroll
-      for (int a = 0; a < 3; ++a) { A[a][a] += prior[3 + a]; g[a] += prior[3 + a] * r[a]; }
-    }
-    const double* sc = scan + 6 * i;
-    if (sc[3] != 0.0 || sc[4] != 0.0 || sc[5] != 0.0) {
-      double r[3] = {xi[0] - sc[0], xi[1] - sc[1], wrap_pi(xi[2] - sc[2])};
-#pragma unroll
-      for (int a = 0; a < 3; ++a) { A[a][a] += sc[3 + a]; g[a] += sc[3 + a] * r[a]; }
-    }
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      gjn[a] = 0.0;
-#pragma unroll
-      for (int b = 0; b < 3; ++b) Ajn[a][b] = 0.0;
-    }
-    if (i + 1 < L) {
-      const double* o = odo + 6 * i;
-      double r[3], Ji[3][3], Jj[3][3];
-      odo_factor(xi, x + 3 * (i + 1), o, r, Ji, Jj);
-      add_jtwj(A, Ji, o + 3, Ji);
-      add_jtwj(B, Ji, o + 3, Jj);
-      add_jtwr(g, Ji, o + 3, r);
-      add_jtwj(Ajn, Jj, o + 3, Jj);
-      add_jtwr(gjn, Jj, o + 3, r);
-    }
-    // Schur complement with the previous pose
-    double y[3] = {-g[0], -g[1], -g[2]};
     if (i > 0) {
-      const double* Dp = work + 21 * (i - 1);        // D_{i-1}^{-1}
-      const double* Cp = Dp + 9;                      // C_{i-1} = D_{i-1}^{-1} B_{i-1}
-      const double* yp = Dp + 18;
-      // A -= B_{i-1}^T C_{i-1};  y -= B_{i-1}^T (D_{i-1}^{-1} y_{i-1})
+      const double* Dp = sDi + 9 * (i - 1);
+      const double* Cp = sC + 9 * (i - 1);
+      const double* yp = sy + 3 * (i - 1);
+      const double* Bp = sB + 9 * (i - 1);
       double t[3];
 #pragma unroll
       for (int a = 0; a < 3; ++a) t[a] = Dp[3 * a] * yp[0] + Dp[3 * a + 1] * yp[1] + Dp[3 * a + 2] * yp[2];
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
 #pragma unroll
-        for (int b = 0; b < 3; ++b)
-          A[a][b] -= Bprev[0][a] * Cp[b] + Bprev[1][a] * Cp[3 + b] + Bprev[2][a] * Cp[6 + b];
-        y[a] -= Bprev[0][a] * t[0] + Bprev[1][a] * t[1] + Bprev[2][a] * t[2];
+        for (int b = 0; b < 3; ++b) D.a[a][b] -= Bp[a] * Cp[b] + Bp[3 + a] * Cp[3 + b] + Bp[6 + a] * Cp[6 + b];
+        y[a] -= Bp[a] * t[0] + Bp[3 + a] * t[1] + Bp[6 + a] * t[2];
       }
     }
-    M3 D;
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-      for (int b = 0; b < 3; ++b) D.a[a][b] = A[a][b];
     const M3 Di = inv3(D);
-    double* wk = work + 21 * i;
+    const double* B = sB + 9 * i;
 #pragma unroll
-    for (int a = 0; a < 3; ++a)
+    for (int a = 0; a < 3; ++a) {
+      sy[3 * i + a] = y[a];
 #pragma unroll
       for (int b = 0; b < 3; ++b) {
-        wk[3 * a + b] = Di.a[a][b];
-        wk[9 + 3 * a + b] = Di.a[a][0] * B[0][b] + Di.a[a][1] * B[1][b] + Di.a[a][2] * B[2][b];
+        sDi[9 * i + 3 * a + b] = Di.a[a][b];
+        sC[9 * i + 3 * a + b] = Di.a[a][0] * B[b] + Di.a[a][1] * B[3 + b] + Di.a[a][2] * B[6 + b];
       }
-    wk[18] = y[0]; wk[19] = y[1]; wk[20] = y[2];
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-      for (int b = 0; b < 3; ++b) Bprev[a][b] = B[a][b];
+    }
     if (i == L - 1) last = Di;
   }
 }
 
-// One thread per window: K steps (x <- x + delta, H delta = -g) then Sigma = D_{L-1}^{-1} at the result.
-// With lds_lag > 0 (L <= lds_lag) the thread keeps its poses and elimination workspace in LDS (the
-// sweeps read back what they just wrote), else in the global workspace.
-constexpr int kLagThreads = 32;
-constexpr int kLagLdsMax = 24;    // windows of at most 24 poses use LDS: 32 x 24 x 24 doubles = 144 KB
-
-__global__ __launch_bounds__(kLagThreads) void k_fixedlag(int n, int L, const double* __restrict__ x0,
+__global__ __launch_bounds__(kLagThreads) void k_fixedlag(int L, const double* __restrict__ x0,
                                                           const double* __restrict__ prior,
                                                           const double* __restrict__ odo,
                                                           const double* __restrict__ scan, int iters,
-                                                          double* __restrict__ xout, double* __restrict__ cov,
-                                                          double* __restrict__ work, int use_lds) {
+                                                          double* __restrict__ xout, double* __restrict__ cov) {
   extern __shared__ __align__(16) double s_lag[];
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= n) return;
-  double* x = use_lds ? s_lag + (int64_t)threadIdx.x * L * 24 : xout + (int64_t)r * L * 3;
-  double* wk = use_lds ? x + 3 * L : work + (int64_t)r * L * 21;
-  for (int e = 0; e < 3 * L; ++e) x[e] = x0[(int64_t)r * L * 3 + e];
+  double* sx = s_lag;
+  double* sA = sx + 3 * L;
+  double* sB = sA + 9 * L;
+  double* sg = sB + 9 * L;
+  double* sDi = sg + 3 * L;
+  double* sC = sDi + 9 * L;
+  double* sy = sC + 9 * L;
+  const int r = blockIdx.x;
+  const int lane = threadIdx.x;
+  for (int e = lane; e < 3 * L; e += kLagThreads) sx[e] = x0[(int64_t)r * L * 3 + e];
   const double* pr = prior + 6 * (int64_t)r;
   const double* od = odo + (int64_t)r * (L > 1 ? L - 1 : 0) * 6;
   const double* sc = scan + (int64_t)r * L * 6;
   M3 last;
-  for (int it = 0; it < iters; ++it) {
-    eliminate(x, L, pr, od, sc, wk, last);
-    // back substitution: delta_{L-1} = D^{-1} y;  delta_i = D_i^{-1} y_i - C_i delta_{i+1}
-    double dn[3] = {0, 0, 0};
-    for (int i = L - 1; i >= 0; --i) {
-      const double* w = wk + 21 * i;
-      double d[3];
+  for (int it = 0; it <= iters; ++it) {
+    __syncthreads();
+    for (int i = lane; i < L; i += kLagThreads) linearise_pose(sx, L, i, pr, od, sc, sA + 9 * i, sB + 9 * i, sg + 3 * i);
+    __syncthreads();
+    if (lane == 0) {
+      eliminate_sweep(L, sA, sB, sg, sDi, sC, sy, last);
+      if (it < iters) {
+        double dn[3] = {0, 0, 0};
+        for (int i = L - 1; i >= 0; --i) {
+          const double* Di = sDi + 9 * i;
+          const double* C = sC + 9 * i;
+          const double* y = sy + 3 * i;
+          double d[3];
 #pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        d[a] = w[3 * a] * w[18] + w[3 * a + 1] * w[19] + w[3 * a + 2] * w[20];
-        if (i < L - 1) d[a] -= w[9 + 3 * a] * dn[0] + w[9 + 3 * a + 1] * dn[1] + w[9 + 3 * a + 2] * dn[2];
+          for (int a = 0; a < 3; ++a) {
+            d[a] = Di[3 * a] * y[0] + Di[3 * a + 1] * y[1] + Di[3 * a + 2] * y[2];
+            if (i < L - 1) d[a] -= C[3 * a] * dn[0] + C[3 * a + 1] * dn[1] + C[3 * a + 2] * dn[2];
+          }
+#pragma unroll
+          for (int a = 0; a < 3; ++a) { sx[3 * i + a] += d[a]; dn[a] = d[a]; }
+        }
+      } else {
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+          for (int b = 0; b < 3; ++b) cov[9 * (int64_t)r + 3 * a + b] = last.a[a][b];
       }
-#pragma unroll
-      for (int a = 0; a < 3; ++a) { x[3 * i + a] += d[a]; dn[a] = d[a]; }
     }
   }
-  eliminate(x, L, pr, od, sc, wk, last);
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int b = 0; b < 3; ++b) cov[9 * (int64_t)r + 3 * a + b] = last.a[a][b];
-  if (use_lds)
-    for (int e = 0; e < 3 * L; ++e) xout[(int64_t)r * L * 3 + e] = x[e];
+  __syncthreads();
+  for (int e = lane; e < 3 * L; e += kLagThreads) xout[(int64_t)r * L * 3 + e] = sx[e];
 }
 
 // ------------------------------------------------------------------ heading table (per device)
@@ -902,18 +915,15 @@ int64_t aslam_fixedlag_work_doubles(int32_t n, int32_t L) {
 int aslam_fixedlag_solve(int32_t n, int32_t L, const double* x0_dev, const double* prior_dev, const double* odo_dev,
                          const double* scan_dev, int32_t iters, double* x_dev, double* cov_dev, double* work_dev,
                          aslam_stream_t stream) {
-  if (n < 0 || L < 1 || L > 64 || iters < 0 || iters > 100)
+  if (n < 0 || L < 1 || L > kLagMaxL || iters < 0 || iters > 100)
     return sfail(ASL_EINVAL, "need n >= 0, 1 <= L <= 64, 0 <= iters <= 100");
   if (n == 0) return ASL_OK;
-  if (!x0_dev || !prior_dev || (L > 1 && !odo_dev) || !scan_dev || !x_dev || !cov_dev || !work_dev)
+  if (!x0_dev || !prior_dev || (L > 1 && !odo_dev) || !scan_dev || !x_dev || !cov_dev)
     return sfail(ASL_EINVAL, "null argument to fixedlag_solve");
-  const int use_lds = L <= kLagLdsMax ? 1 : 0;
-  const int bytes = use_lds ? (int)(sizeof(double) * kLagThreads * L * 24) : 0;
-  if (use_lds)
-    SCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fixedlag), hipFuncAttributeMaxDynamicSharedMemorySize,
-                             bytes));
-  k_fixedlag<<<(n + kLagThreads - 1) / kLagThreads, kLagThreads, bytes, (hipStream_t)stream>>>(
-      n, L, x0_dev, prior_dev, odo_dev, scan_dev, iters, x_dev, cov_dev, work_dev, use_lds);
+  (void)work_dev;   // the windows are solved in LDS
+  const int bytes = (int)(sizeof(double) * 45 * L);
+  k_fixedlag<<<n, kLagThreads, bytes, (hipStream_t)stream>>>(L, x0_dev, prior_dev, odo_dev, scan_dev, iters, x_dev,
+                                                             cov_dev);
   SCHK(hipGetLastError());
   return ASL_OK;
 }

@@ -90,8 +90,6 @@ def fixedlag_solve(x0: torch.Tensor, prior: torch.Tensor, odo: torch.Tensor | No
         assert t.dtype == torch.float64
     x = torch.empty_like(x0) if x is None else x
     cov = torch.empty((n, 3, 3), dtype=torch.float64, device=x0.device) if cov is None else cov
-    if work is None:
-        work = torch.empty(int(lib().aslam_fixedlag_work_doubles(n, L)), dtype=torch.float64, device=x0.device)
     check(lib().aslam_fixedlag_solve(n, L, _p(x0), _p(prior), _p(odo), _p(scan), iters, _p(x), _p(cov), _p(work),
                                      _stream()))
     return x, cov

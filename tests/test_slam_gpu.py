@@ -133,7 +133,7 @@ def _windows(n, L, seed):
     return x0, prior, odo, scan
 
 
-@pytest.mark.parametrize("L,iters", [(1, 2), (2, 3), (8, 3), (16, 5), (30, 3)])
+@pytest.mark.parametrize("L,iters", [(1, 2), (2, 3), (8, 3), (16, 5), (30, 3), (64, 2), (10, 0)])
 def test_fixedlag_matches_oracle(L, iters):
     n = 48
     x0, prior, odo, scan = _windows(n, L, 100 + L)
