@@ -672,44 +672,60 @@ __device__ __forceinline__ void linearise_pose(const double* x, int L, int i, co
   }
 }
 
-// Lane 0: the elimination sweep over the linearised window; returns D_{L-1}^{-1} in *last.
+// Lane 0: the elimination sweep over the linearised window; returns D_{L-1}^{-1} in *last.  The previous
+// pose's D^{-1}, C, y and B stay in registers and the next pose's blocks are read one pose ahead, so
+// the recursion's chain holds no LDS round trip.
 __device__ __forceinline__ void eliminate_sweep(int L, const double* sA, const double* sB, const double* sg,
                                                 double* sDi, double* sC, double* sy, M3& last) {
+  double nA[9], nB[9], ng[3];
+#pragma unroll
+  for (int e = 0; e < 9; ++e) { nA[e] = sA[e]; nB[e] = sB[e]; }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) ng[a] = sg[a];
+  double pDi[9], pC[9], py[3], pB[9];
   for (int i = 0; i < L; ++i) {
     M3 D;
-    double y[3];
+    double y[3], B[9];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      y[a] = -sg[3 * i + a];
+      y[a] = -ng[a];
 #pragma unroll
-      for (int b = 0; b < 3; ++b) D.a[a][b] = sA[9 * i + 3 * a + b];
+      for (int b = 0; b < 3; ++b) D.a[a][b] = nA[3 * a + b];
+    }
+#pragma unroll
+    for (int e = 0; e < 9; ++e) B[e] = nB[e];
+    if (i + 1 < L) {
+#pragma unroll
+      for (int e = 0; e < 9; ++e) { nA[e] = sA[9 * (i + 1) + e]; nB[e] = sB[9 * (i + 1) + e]; }
+#pragma unroll
+      for (int a = 0; a < 3; ++a) ng[a] = sg[3 * (i + 1) + a];
     }
     if (i > 0) {
-      const double* Dp = sDi + 9 * (i - 1);
-      const double* Cp = sC + 9 * (i - 1);
-      const double* yp = sy + 3 * (i - 1);
-      const double* Bp = sB + 9 * (i - 1);
       double t[3];
 #pragma unroll
-      for (int a = 0; a < 3; ++a) t[a] = Dp[3 * a] * yp[0] + Dp[3 * a + 1] * yp[1] + Dp[3 * a + 2] * yp[2];
+      for (int a = 0; a < 3; ++a) t[a] = pDi[3 * a] * py[0] + pDi[3 * a + 1] * py[1] + pDi[3 * a + 2] * py[2];
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
 #pragma unroll
-        for (int b = 0; b < 3; ++b) D.a[a][b] -= Bp[a] * Cp[b] + Bp[3 + a] * Cp[3 + b] + Bp[6 + a] * Cp[6 + b];
-        y[a] -= Bp[a] * t[0] + Bp[3 + a] * t[1] + Bp[6 + a] * t[2];
+        for (int b = 0; b < 3; ++b) D.a[a][b] -= pB[a] * pC[b] + pB[3 + a] * pC[3 + b] + pB[6 + a] * pC[6 + b];
+        y[a] -= pB[a] * t[0] + pB[3 + a] * t[1] + pB[6 + a] * t[2];
       }
     }
     const M3 Di = inv3(D);
-    const double* B = sB + 9 * i;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
+      py[a] = y[a];
       sy[3 * i + a] = y[a];
 #pragma unroll
       for (int b = 0; b < 3; ++b) {
-        sDi[9 * i + 3 * a + b] = Di.a[a][b];
-        sC[9 * i + 3 * a + b] = Di.a[a][0] * B[b] + Di.a[a][1] * B[3 + b] + Di.a[a][2] * B[6 + b];
+        pDi[3 * a + b] = Di.a[a][b];
+        pC[3 * a + b] = Di.a[a][0] * B[b] + Di.a[a][1] * B[3 + b] + Di.a[a][2] * B[6 + b];
+        sDi[9 * i + 3 * a + b] = pDi[3 * a + b];
+        sC[9 * i + 3 * a + b] = pC[3 * a + b];
       }
     }
+#pragma unroll
+    for (int e = 0; e < 9; ++e) pB[e] = B[e];
     if (i == L - 1) last = Di;
   }
 }
@@ -741,16 +757,20 @@ __global__ __launch_bounds__(kLagThreads) void k_fixedlag(int L, const double* _
     if (lane == 0) {
       eliminate_sweep(L, sA, sB, sg, sDi, sC, sy, last);
       if (it < iters) {
+        // the terms D_i^{-1} y_i do not depend on the recursion: each pose's is formed first
         double dn[3] = {0, 0, 0};
         for (int i = L - 1; i >= 0; --i) {
           const double* Di = sDi + 9 * i;
           const double* C = sC + 9 * i;
           const double* y = sy + 3 * i;
-          double d[3];
+          double d[3], c[9];
 #pragma unroll
-          for (int a = 0; a < 3; ++a) {
-            d[a] = Di[3 * a] * y[0] + Di[3 * a + 1] * y[1] + Di[3 * a + 2] * y[2];
-            if (i < L - 1) d[a] -= C[3 * a] * dn[0] + C[3 * a + 1] * dn[1] + C[3 * a + 2] * dn[2];
+          for (int e = 0; e < 9; ++e) c[e] = C[e];
+#pragma unroll
+          for (int a = 0; a < 3; ++a) d[a] = Di[3 * a] * y[0] + Di[3 * a + 1] * y[1] + Di[3 * a + 2] * y[2];
+          if (i < L - 1) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) d[a] -= c[3 * a] * dn[0] + c[3 * a + 1] * dn[1] + c[3 * a + 2] * dn[2];
           }
 #pragma unroll
           for (int a = 0; a < 3; ++a) { sx[3 * i + a] += d[a]; dn[a] = d[a]; }
