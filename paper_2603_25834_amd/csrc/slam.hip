@@ -167,10 +167,10 @@ __global__ __launch_bounds__(kCsmLdsThreads) void k_csm_lds(const int16_t* __res
                                                             const int32_t* __restrict__ rho_q, int R,
                                                             const int32_t* __restrict__ a_off,
                                                             const int32_t* __restrict__ dirtab, int W, int V,
-                                                            int step_xy, int step_h, int lds_side,
+                                                            int step_xy, int step_h, int lds_side, int pad,
                                                             int32_t* __restrict__ out) {
   extern __shared__ __align__(16) unsigned char s_dyn[];
-  const int lds_cells = (lds_side * lds_side + 7) & ~7;
+  const int lds_cells = ((lds_side + pad) * lds_side + 7) & ~7;
   int16_t* s_grid = reinterpret_cast<int16_t*>(s_dyn);
   int2* s_off = reinterpret_cast<int2*>(s_dyn + 2 * (int64_t)lds_cells);
   int32_t* s_part = reinterpret_cast<int32_t*>(s_off);
@@ -198,15 +198,26 @@ __global__ __launch_bounds__(kCsmLdsThreads) void k_csm_lds(const int16_t* __res
   const int32_t sd = side[r];
   const int64_t base = cell_off[r];
   const bool staged = sd > 0 && sd <= lds_side;
+  // Staged rows are `pad` cells apart beyond the side: with pad = 2 the lanes that read the same ray's
+  // endpoint in neighbouring rows (neighbouring y candidates) hit neighbouring LDS banks, not one bank.
+  const int pitch = staged ? sd + pad : sd;
   if (staged) {
     const int64_t cells = (int64_t)sd * sd;
-    if ((reinterpret_cast<uintptr_t>(belief + base) & 15) == 0) {
+    if ((reinterpret_cast<uintptr_t>(belief + base) & 15) == 0 && (sd & 7) == 0 && (pad & 1) == 0) {
+      // 8 cells per access: one 16-byte read, four 4-byte writes (rows start on 4-byte boundaries)
       const uint4* src = reinterpret_cast<const uint4*>(belief + base);
-      uint4* dst = reinterpret_cast<uint4*>(s_grid);
-      for (int64_t v = threadIdx.x; v < cells / 8; v += kCsmLdsThreads) dst[v] = src[v];
-      for (int64_t e = (cells / 8) * 8 + threadIdx.x; e < cells; e += kCsmLdsThreads) s_grid[e] = belief[base + e];
+      const int per_row = sd >> 3;
+      for (int64_t v = threadIdx.x; v < cells / 8; v += kCsmLdsThreads) {
+        const uint4 t = src[v];
+        const int y = (int)(v / per_row), x = (int)(v - (int64_t)y * per_row) * 8;
+        uint32_t* d = reinterpret_cast<uint32_t*>(s_grid + (int64_t)y * pitch + x);
+        d[0] = t.x; d[1] = t.y; d[2] = t.z; d[3] = t.w;
+      }
     } else {
-      for (int64_t e = threadIdx.x; e < cells; e += kCsmLdsThreads) s_grid[e] = belief[base + e];
+      for (int64_t e = threadIdx.x; e < cells; e += kCsmLdsThreads) {
+        const int y = (int)(e / sd), x = (int)(e - (int64_t)y * sd);
+        s_grid[(int64_t)y * pitch + x] = belief[base + e];
+      }
     }
   }
   __syncthreads();
@@ -226,7 +237,7 @@ __global__ __launch_bounds__(kCsmLdsThreads) void k_csm_lds(const int16_t* __res
       const int2 v = o[q];
       const int64_t cy = (y + v.y) >> 16;
       if (cy < 0 || cy >= sd) continue;
-      const int16_t* grow = g + cy * sd;
+      const int16_t* grow = g + cy * pitch;
       const int64_t ex = x0 + v.x;
 #pragma unroll
       for (int i = 0; i < kCsmLdsMaxLine; ++i) {
@@ -853,15 +864,21 @@ int aslam_csm_match(const int16_t* belief_dev, const int64_t* cell_off_dev, cons
                                                                                        (2 * cfg->W + 1))))) {
     // the grids staged in LDS when the largest fits beside the ray offsets (a 256 x 256 grid does with
     // 11 headings x 360 rays), else read from global memory
-    int64_t grid_bytes = 2 * ((((int64_t)max_side * max_side) + 7) & ~(int64_t)7);
+    // rows padded by 2 cells when that still fits (fewer LDS bank conflicts), else unpadded
+    int pad = 2;
+    int64_t grid_bytes = 2 * ((((int64_t)max_side + pad) * max_side + 7) & ~(int64_t)7);
+    if (grid_bytes + off_bytes > kCsmLdsBudget) {
+      pad = 0;
+      grid_bytes = 2 * ((((int64_t)max_side * max_side) + 7) & ~(int64_t)7);
+    }
     int lds_side = max_side;
-    if (grid_bytes + off_bytes > kCsmLdsBudget) { grid_bytes = 0; lds_side = 0; }
+    if (grid_bytes + off_bytes > kCsmLdsBudget) { grid_bytes = 0; lds_side = 0; pad = 0; }
     const int bytes = (int)(grid_bytes + off_bytes);
     SCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_csm_lds), hipFuncAttributeMaxDynamicSharedMemorySize,
                              bytes));
     k_csm_lds<<<n, kCsmLdsThreads, bytes, (hipStream_t)stream>>>(belief_dev, cell_off_dev, side_dev, pose_q_dev,
                                                               rho_q_dev, R, a_off_dev, tab, cfg->W, cfg->V,
-                                                              cfg->step_xy_q, cfg->step_h, lds_side, out_dev);
+                                                              cfg->step_xy_q, cfg->step_h, lds_side, pad, out_dev);
   } else {
     k_csm<<<n, kCsmThreads, 0, (hipStream_t)stream>>>(belief_dev, cell_off_dev, side_dev, pose_q_dev, rho_q_dev, R,
                                                        a_off_dev, tab, cfg->W, cfg->V, cfg->step_xy_q, cfg->step_h,

@@ -72,10 +72,11 @@ def test_match_bit_exact(W, V, sxy, sh, R):
         assert tuple(int(v) for v in got[r]) == want, (r, got[r], want)
 
 
-@pytest.mark.parametrize("sides,max_side", [([300, 64, 128], None), ([256, 64, 200, 96], 96)],
-                         ids=["grid_too_big_for_lds", "mixed_staged_and_global"])
+@pytest.mark.parametrize("sides,max_side", [([300, 64, 128], None), ([256, 64, 200, 96], 96), ([100, 64, 37], None)],
+                         ids=["grid_too_big_for_lds", "mixed_staged_and_global", "sides_not_multiple_of_8"])
 def test_match_staged_and_global_grids(sides, max_side):
-    """Grids staged in LDS or read from global memory give the same (exact) answers."""
+    """Grids staged in LDS (rows padded, sides of any residue) or read from global memory give the same
+    (exact) answers."""
     W, V, sxy, sh, R = 4, 5, 65536, 64, 360
     grids, belief, cell_off, side, pose, rho, a_off = _batch(17 + len(sides), sides, R, W, V, sxy, sh)
     cfg = slam.csm_config(W, V, sxy, sh)
