@@ -221,14 +221,15 @@ __global__ __launch_bounds__(kCsmLdsThreads) void k_csm_lds(const int16_t* __res
     }
   }
   __syncthreads();
-  const int16_t* g = staged ? s_grid : belief + base;
   // lines x chunks of rays
   const int chunks = max(1, min(R, kCsmLdsThreads / nline));
   int32_t acc[kCsmLdsMaxLine];
 #pragma unroll
   for (int i = 0; i < kCsmLdsMaxLine; ++i) acc[i] = 0;
   const int line = threadIdx.x / chunks, ch = threadIdx.x - line * chunks;
-  if (line < nline) {
+  // One instance per grid location, so that the reads of a staged grid compile to LDS reads (a pointer
+  // that may point to either memory would make every read a flat access).
+  auto score = [&](const int16_t* g) {
     const int k = line / nw, j = line - k * nw;
     const int q0 = (int)((int64_t)ch * R / chunks), q1 = (int)((int64_t)(ch + 1) * R / chunks);
     const int64_t x0 = (int64_t)px - (int64_t)W * step_xy, y = (int64_t)py + (int64_t)(j - W) * step_xy;
@@ -247,6 +248,12 @@ __global__ __launch_bounds__(kCsmLdsThreads) void k_csm_lds(const int16_t* __res
         }
       }
     }
+  };
+  if (line < nline) {
+    if (staged)
+      score(s_grid);
+    else
+      score(belief + base);
   }
   __syncthreads();   // every line is done with the offsets: their space takes the partial sums
   if (line < nline) {
