@@ -234,7 +234,33 @@ __global__ __launch_bounds__(kCsmLdsThreads) void k_csm_lds(const int16_t* __res
     const int q0 = (int)((int64_t)ch * R / chunks), q1 = (int)((int64_t)(ch + 1) * R / chunks);
     const int64_t x0 = (int64_t)px - (int64_t)W * step_xy, y = (int64_t)py + (int64_t)(j - W) * step_xy;
     const int2* o = s_off + k * R;
-    for (int q = q0; q < q1; ++q) {
+    // four rays per step, every read issued before any is used: a cell off the grid reads cell 0 of
+    // the grid and adds nothing
+    constexpr int kRays = 4;
+    int q = q0;
+    for (; q + kRays <= q1; q += kRays) {
+      int32_t val[kRays][kCsmLdsMaxLine];
+#pragma unroll
+      for (int u = 0; u < kRays; ++u) {
+        const int2 v = o[q + u];
+        const int64_t cy = (y + v.y) >> 16;
+        const bool row_ok = cy >= 0 && cy < sd;
+        const int16_t* grow = g + (row_ok ? cy : 0) * pitch;
+        const int64_t ex = x0 + v.x;
+#pragma unroll
+        for (int i = 0; i < kCsmLdsMaxLine; ++i) {
+          const int64_t cx = (ex + (int64_t)i * step_xy) >> 16;
+          const bool ok = row_ok && i < nw && cx >= 0 && cx < sd;
+          const int32_t t = grow[ok ? cx : 0];
+          val[u][i] = ok ? t : 0;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kRays; ++u)
+#pragma unroll
+        for (int i = 0; i < kCsmLdsMaxLine; ++i) acc[i] += val[u][i];
+    }
+    for (; q < q1; ++q) {
       const int2 v = o[q];
       const int64_t cy = (y + v.y) >> 16;
       if (cy < 0 || cy >= sd) continue;
@@ -249,7 +275,7 @@ __global__ __launch_bounds__(kCsmLdsThreads) void k_csm_lds(const int16_t* __res
       }
     }
   };
-  if (line < nline) {
+  if (line < nline && sd > 0) {   // an empty grid scores 0 everywhere
     if (staged)
       score(s_grid);
     else
