@@ -1,6 +1,6 @@
 // slam.hip -- the fixed-lag SLAM backbone on gfx950 (arXiv 2603.25834, Sec. III-D).
 //
-// Three batched calls, one robot per workgroup or thread:
+// Four batched calls, one robot (or pose window) per workgroup or thread:
 //  * correlative scan matching: every candidate of a (dx, dy, dheading) lattice around the predicted
 //    pose scored against the robot's int16 log-odds grid -- exact integer arithmetic (Q16 positions,
 //    the Q14 heading table), so results equal the definition bit for bit;

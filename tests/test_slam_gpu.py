@@ -224,8 +224,9 @@ def test_integrate_bands_and_max_side():
 
 
 def test_integrate_full_batch_sampled_and_errors():
-    """750 robots of 256^2 grids and 360 rays from the scan matcher's own output on the GPU (inputs only:
-    each sampled robot is checked with the oracle on that match); then the argument checks."""
+    """750 robots of 256^2 grids and 360 rays integrated from the GPU matcher's own output; for 12 sampled
+    robots the oracle matches (which the GPU's must equal) drive the oracle's integration; then the
+    argument checks."""
     from paper_2603_25834_amd import _lib
     W, V, sxy, sh, R = 4, 5, 65536, 64, 360
     sides = [256] * 750
@@ -238,9 +239,13 @@ def test_integrate_full_batch_sampled_and_errors():
                                match=match, cfg=cfg, l_max=896.0)
     torch.cuda.synchronize()
     got, m, coded = bel.cpu().numpy(), match.cpu().numpy(), coded.cpu().numpy()
+    trig = S._trig()
     for r in np.random.default_rng(4).choice(750, 12, replace=False):
+        # the oracle integrates from its own match, which the GPU's must equal
+        mo = S.csm_match(grids[r], int(pose[r, 0]), int(pose[r, 1]), int(pose[r, 2]), rho[r], a_off, W, V, sxy, sh, trig)
+        assert tuple(int(v) for v in m[r]) == mo, r
         want, nc = S.integrate(grids[r], int(pose[r, 0]), int(pose[r, 1]), int(pose[r, 2]), rho[r], a_off,
-                               200 * 65536, 218, -102, 896, match=m[r], step_xy=sxy, step_h=sh, l_max=896.0)
+                               200 * 65536, 218, -102, 896, match=mo, step_xy=sxy, step_h=sh, l_max=896.0)
         o = int(cell_off[r])
         assert np.array_equal(got[o:o + 65536].reshape(256, 256), want) and int(coded[r]) == nc, r
     with pytest.raises(_lib.AslamError):   # l_clamp out of range
@@ -249,3 +254,82 @@ def test_integrate_full_batch_sampled_and_errors():
         _lib.check(_lib.lib().aslam_csm_integrate(slam._p(bel), slam._p(d(cell_off)), slam._p(d(side)), 750,
                                                   slam._p(d(pose)), slam._p(d(rho)), R, slam._p(d(a_off)), 256, 65536,
                                                   slam._p(match), None, 896.0, 218, -102, 896, None, slam._stream()))
+
+
+def test_backbone_on_env_state():
+    """The four calls in sequence on the state an env reached: 16 robots of 64^2 grids and 180 rays stepped
+    20 times on the GPU and by the oracle env (their states agree bit for bit); the GPU backbone runs on the
+    GPU env's state and the oracle backbone on the oracle env's -- scan matching of the last scan around the
+    estimated pose, the scan factor, the weighted integration from the match, and a 6-pose window whose
+    newest pose carries the scan factor."""
+    from envpair import Pair
+    from oracle import oracle as O
+    from paper_2603_25834_amd import _lib
+    pr = Pair("small_16x64", 7, steps=20, exec_kw=dict(form=1, threads=256, record_rays=1))
+    o = None
+    for _ in range(20):
+        o = pr.step()
+    g = pr.compare(o)
+    say("[slam] backbone on the env state of small_16x64 after 20 steps")
+    p, n, R = pr.p, pr.n, pr.R
+    sides = np.asarray(pr.b.sides, np.int64)
+    cell_off = np.concatenate([[0], np.cumsum(sides * sides)[:-1]]).astype(np.int64)
+    inv_c16 = np.float32(65536.0 / float(np.float32(p["cell_m"])))
+    rmax_q = int(round(float(np.float32(p["r_max_m"])) / float(np.float32(p["cell_m"])) * 65536.0))
+    a_off = (np.arange(R) * (S.NANG // R)).astype(np.int32)
+    W, V, sxy, sh, L = 3, 4, 65536, 64, 6
+    cm, lmax, sig_xy, sig_th = float(p["cell_m"]), 896.0, 0.05, 0.02
+
+    def inputs(est, rho, hitc):
+        pose = np.stack([np.rint(est[:, 0].astype(np.float32) * inv_c16), np.rint(est[:, 1].astype(np.float32) * inv_c16),
+                         [O.heading_index(float(t)) for t in est[:, 2]]], 1).astype(np.int32)
+        return pose, np.where(hitc >= 0, rho, -1).astype(np.int32)
+
+    def window(est, z, om):
+        x0 = np.repeat(est.astype(np.float64)[:, None, :], L, 1)
+        x0 += 0.01 * np.sin(np.arange(n * L * 3, dtype=np.float64)).reshape(n, L, 3)
+        prior = np.concatenate([x0[:, 0], np.full((n, 3), 400.0)], 1)
+        odo = np.concatenate([np.zeros((n, L - 1, 3)), np.full((n, L - 1, 3), 2500.0)], 2)
+        scan = np.zeros((n, L, 6))
+        scan[:, -1, :3], scan[:, -1, 3:] = z, om
+        return x0, prior, odo, scan
+
+    # oracle side: the oracle env's state
+    orc = pr.orc
+    pose_o, rho_o = inputs(orc.est, o.rho_q, o.hit_cell)
+    trig = S._trig()
+    match_o, z_o, om_o, grid_o, coded_o = [], [], [], [], []
+    for r in range(n):
+        m = S.csm_match(orc.belief_of(r), int(pose_o[r, 0]), int(pose_o[r, 1]), int(pose_o[r, 2]), rho_o[r], a_off,
+                        W, V, sxy, sh, trig)
+        z, om = S.scan_factor(*m, int(pose_o[r, 0]), int(pose_o[r, 1]), int(pose_o[r, 2]), sxy, sh, cm, lmax, sig_xy,
+                              sig_th)
+        gi, nc = S.integrate(orc.belief_of(r), int(pose_o[r, 0]), int(pose_o[r, 1]), int(pose_o[r, 2]), rho_o[r],
+                             a_off, rmax_q, 218, -102, 896, match=m, step_xy=sxy, step_h=sh, l_max=lmax)
+        match_o.append(m); z_o.append(z); om_o.append(om); grid_o.append(gi); coded_o.append(nc)
+    x0o, pro, odo_o, sco = window(orc.est, np.array(z_o), np.array(om_o))
+    lag_o = [S.fixedlag_solve(x0o[r], pro[r], odo_o[r], sco[r], 3) for r in range(n)]
+
+    # GPU side: the GPU env's state, through the C-ABI
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    pose_g, rho_g = inputs(g["est"], g["rho"], g["hitc"])
+    cfg = slam.csm_config(W, V, sxy, sh)
+    bel = pr.env.read(_lib.FIELD_BELIEF)
+    CO, SD, PO = d(cell_off), d(sides.astype(np.int32)), d(pose_g)
+    match = slam.csm_match(bel, CO, SD, PO, d(rho_g), d(a_off), cfg)
+    meas, info = slam.csm_factor(match, PO, cfg, cm, lmax, sig_xy, sig_th)
+    coded = slam.csm_integrate(bel, CO, SD, PO, d(rho_g), d(a_off), rmax_q, 218, -102, 896, match=match, cfg=cfg,
+                               l_max=lmax)
+    x0g, prg, odg, scg = window(g["est"], meas.cpu().numpy(), info.cpu().numpy())
+    xg, covg = slam.fixedlag_solve(d(x0g), d(prg), d(odg), d(scg), 3)
+    torch.cuda.synchronize()
+    match, meas, info = match.cpu().numpy(), meas.cpu().numpy(), info.cpu().numpy()
+    bel, coded, xg, covg = bel.cpu().numpy(), coded.cpu().numpy(), xg.cpu().numpy(), covg.cpu().numpy()
+    for r in range(n):
+        s_, off = int(sides[r]), int(cell_off[r])
+        assert tuple(int(v) for v in match[r]) == match_o[r], r
+        assert np.array_equal(meas[r], z_o[r]) and np.array_equal(info[r], om_o[r]), r
+        assert np.array_equal(bel[off:off + s_ * s_].reshape(s_, s_), grid_o[r]) and int(coded[r]) == coded_o[r], r
+        assert np.abs(xg[r] - lag_o[r][0]).max() < 1e-9, r
+        assert np.abs(covg[r] - lag_o[r][1]).max() <= 1e-8 * np.abs(lag_o[r][1]).max(), r
+    assert sum(coded_o) > 0 and any(w[0] > 0 for w in om_o)
