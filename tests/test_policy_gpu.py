@@ -248,7 +248,8 @@ def test_sample_and_gather():
     ls = torch.tensor(theta[-2:], dtype=torch.float64)
     want = torch.from_numpy(mu).double() + torch.exp(ls) * torch.from_numpy(eps).double()
     assert torch.allclose(act, want, rtol=1e-6, atol=1e-6)
-    assert torch.allclose(logp, PR.gaussian_logp(torch.from_numpy(mu).double(), ls, act), rtol=1e-5, atol=1e-5)
+    # the oracle's density at its own FP64 action (within 1e-6 of the GPU's)
+    assert torch.allclose(logp, PR.gaussian_logp(torch.from_numpy(mu).double(), ls, want), rtol=1e-5, atol=1e-5)
     crops = torch.from_numpy(rng.integers(-896, 897, size=(300, 64, 64)).astype(np.int16)).cuda()
     scans = torch.from_numpy(rng.normal(size=(300, 13)).astype(np.float32)).cuda()   # 52-byte rows
     idx = torch.from_numpy(rng.integers(0, 300, size=517).astype(np.int32)).cuda()

@@ -99,8 +99,12 @@ def test_factor_matches_oracle_exactly():
     meas, info = slam.csm_factor(torch.from_numpy(got).cuda(), torch.from_numpy(pose).cuda(), cfg, 0.05, 896.0,
                                  0.05, 0.02)
     torch.cuda.synchronize()
+    trig = S._trig()
     for r in range(len(sides)):
-        z, om = S.scan_factor(*[int(v) for v in got[r]], int(pose[r, 0]), int(pose[r, 1]), int(pose[r, 2]), sxy, sh,
+        # the oracle's factor from the oracle's own match, which the GPU's must equal
+        mo = S.csm_match(grids[r], int(pose[r, 0]), int(pose[r, 1]), int(pose[r, 2]), rho[r], a_off, W, V, sxy, sh, trig)
+        assert tuple(int(v) for v in got[r]) == mo, r
+        z, om = S.scan_factor(*mo, int(pose[r, 0]), int(pose[r, 1]), int(pose[r, 2]), sxy, sh,
                               0.05, 896.0, 0.05, 0.02)
         assert np.array_equal(meas[r].cpu().numpy(), z) and np.array_equal(info[r].cpu().numpy(), om), r
 
