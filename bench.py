@@ -213,15 +213,6 @@ def slam_time(wb, reps: int = 20, L: int = 10, iters: int = 3) -> dict:
     del bel_w
     m = match.cpu().numpy()
     ncand = 9 * 9 * 11
-    # a few robots' inputs on the host, for the oracle's timing in the CPU-baseline leg
-    k = min(8, n)
-    bel = belief.cpu().numpy()
-    offs = cell_off.cpu().numpy()
-    sd = wb.b.sides
-    wb.slam_sample = dict(grids=[bel[offs[r]:offs[r] + sd[r] * sd[r]].reshape(sd[r], sd[r]) for r in range(k)],
-                          pose=pose_q[:k].cpu().numpy(), rho=rho_q[:k].cpu().numpy(), a_off=a_off.cpu().numpy(),
-                          x0=x0[:64].cpu().numpy(), prior=prior[:64].cpu().numpy(), odo=odo[:64].cpu().numpy(),
-                          scan=scan[:64].cpu().numpy(), L=L, iters=iters, match=m[:k], rmax_q=rmax_q, lq=lq)
     used = float(m[:, 5].mean())
     return {"robots": n, "rays": R, "lattice": [9, 9, 11], "candidates": ncand,
             "csm_us": csm_ms * 1e3, "factor_us": fac_ms * 1e3, "integrate_us": int_ms * 1e3,
@@ -358,33 +349,55 @@ def cpu_full_loop(name: str, seed: int, robots: int, T: int, epochs: int) -> dic
                       f"of one {n * T}-sample minibatch, FP64 policy ({dt:.1f} s)"}
 
 
-def cpu_slam(sample: dict) -> dict:
-    """The SLAM oracle as it stands on a few robots' inputs: scan matching (numpy, integer) and the
-    fixed-lag solve (numpy FP64), per robot."""
+def cpu_slam(seed: int, robots: int = 8, windows: int = 64, R: int = 360, L: int = 10, iters: int = 3) -> dict:
+    """The SLAM oracle as it stands on a seeded synthetic sample of the benchmark's shapes (256^2 int16 grids
+    with walls, 360 rays of up to 10 m at 0.05 m cells, the 9 x 9 x 11 lattice, 10-pose windows): scan
+    matching, the oracle's own matches integrated into the grids, and the fixed-lag solve, per robot."""
     from oracle import slam_ref as S
+    rng = np.random.default_rng([seed, 11])
+    s, nang = 256, S.NANG
+    lq = [218, -102, 896]
+    rmax_q = 200 * 65536
+    a_off = (np.arange(R) * (nang // R)).astype(np.int32)
+    grids, poses, rhos = [], [], []
+    for _ in range(robots):
+        g = rng.integers(-300, 150, (s, s)).astype(np.int16)
+        for _ in range(24):   # walls of strong occupied evidence
+            y0, x0, ln = int(rng.integers(0, s)), int(rng.integers(0, s)), int(rng.integers(8, 64))
+            if rng.random() < 0.5:
+                g[y0, x0:x0 + ln] = 880
+            else:
+                g[y0:y0 + ln, x0] = 880
+        rho = (rng.uniform(0.5, 200.0, R) * 65536).astype(np.int32)
+        rho[rng.random(R) < 0.05] = -1
+        grids.append(g)
+        poses.append((int(rng.integers(64, 192)) * 65536 + 32768, int(rng.integers(64, 192)) * 65536 + 32768,
+                      int(rng.integers(0, nang))))
+        rhos.append(rho)
     trig = S._trig()
     t0 = time.time()
-    for r in range(len(sample["grids"])):
-        p = sample["pose"][r]
-        S.csm_match(sample["grids"][r], int(p[0]), int(p[1]), int(p[2]), sample["rho"][r], sample["a_off"], 4, 5,
-                    65536, 64, trig)
-    t_csm = (time.time() - t0) / len(sample["grids"])
+    matches = [S.csm_match(grids[r], *poses[r], rhos[r], a_off, 4, 5, 65536, 64, trig) for r in range(robots)]
+    t_csm = (time.time() - t0) / robots
     t0 = time.time()
-    for r in range(len(sample["grids"])):
-        p = sample["pose"][r]
-        S.integrate(sample["grids"][r], int(p[0]), int(p[1]), int(p[2]), sample["rho"][r], sample["a_off"],
-                    sample["rmax_q"], *sample["lq"], match=sample["match"][r], step_xy=65536, step_h=64,
-                    l_max=float(sample["lq"][2]))
-    t_int = (time.time() - t0) / len(sample["grids"])
+    for r in range(robots):
+        S.integrate(grids[r], *poses[r], rhos[r], a_off, rmax_q, *lq, match=matches[r], step_xy=65536, step_h=64,
+                    l_max=float(lq[2]))
+    t_int = (time.time() - t0) / robots
+    x0 = rng.uniform(-5.0, 5.0, (windows, 1, 3)) + 0.01 * rng.standard_normal((windows, L, 3))
+    prior = np.concatenate([x0[:, 0], np.full((windows, 3), 400.0)], 1)
+    odo = np.concatenate([np.zeros((windows, L - 1, 3)), np.full((windows, L - 1, 3), 2500.0)], 2)
+    scan = np.zeros((windows, L, 6))
+    scan[:, -1, :3] = x0[:, -1] + 0.02 * rng.standard_normal((windows, 3))
+    scan[:, -1, 3:] = 100.0
     t0 = time.time()
-    nw = sample["x0"].shape[0]
-    for w in range(nw):
-        S.fixedlag_solve(sample["x0"][w], sample["prior"][w], sample["odo"][w], sample["scan"][w], sample["iters"])
-    t_gn = (time.time() - t0) / nw
+    for w in range(windows):
+        S.fixedlag_solve(x0[w], prior[w], odo[w], scan[w], iters)
+    t_gn = (time.time() - t0) / windows
     return {"kind": "oracle", "cores": 1, "robots_per_s": 1.0 / (t_csm + t_int + t_gn),
             "csm_ms_per_robot": t_csm * 1e3, "integrate_ms_per_robot": t_int * 1e3,
             "fixedlag_ms_per_window": t_gn * 1e3,
-            "sample": f"{len(sample['grids'])} robots' scan matching, {nw} windows of {sample['L']} poses"}
+            "sample": f"seeded synthetic: {robots} robots' scan matching and integration (256^2, {R} rays), "
+                      f"{windows} windows of {L} poses"}
 
 
 def cpu_baseline(name: str, seed: int, robots: int, steps: int) -> dict:
@@ -635,7 +648,6 @@ def main():
         "device": {"lds_per_block": lds, "compute_units": cus},
         "autotune": tuned or None,
     }
-    slam_sample = wb.slam_sample
     del wb
     torch.cuda.empty_cache()
     if not args.no_ppo:
@@ -652,7 +664,7 @@ def main():
         out["cpu_baseline"] = cpu_full_loop(args.workload, args.seed, args.cpu_robots, args.horizon, args.epochs)
         out["cpu_baseline"]["env_step_only"] = cpu_baseline(args.workload, args.seed, args.cpu_env_robots,
                                                             args.cpu_env_steps)
-        out["cpu_baseline"]["slam"] = cpu_slam(slam_sample)
+        out["cpu_baseline"]["slam"] = cpu_slam(args.seed)
     print(json.dumps(out), flush=True)
 
 
