@@ -498,13 +498,27 @@ __global__ __launch_bounds__(kIntThreads) void k_csm_integrate(
     const int32_t rows = min(band, si - by0);
     for (int32_t w = threadIdx.x; w < 2 * band * nw; w += kIntThreads) bits[w] = 0u;
     __syncthreads();
-    for (int j = threadIdx.x; j < R; j += kIntThreads) {
-      const int k = sorted ? (int)s_perm[j] : j;
-      const int32_t rho = rho_q[(int64_t)r * R + k];
+    // Each lane's walk length and end cell are known before it starts: the walk stops at the first
+    // barred crossing in distance order -- x crossing #nx at axis distance ex0 + 65536 nx or y crossing
+    // #ny, whichever comes first (x on a tie) -- after every crossing that precedes it.  The loop then
+    // only selects the next crossing by the sign of D and marks the cell; trip counts are uniform over
+    // the wave (lanes past their own length mark nothing), and while the band holds the whole grid and
+    // every lane is within its length the marks need no test.
+    const int32_t rowbits = nw << 5;
+    const uint32_t band_bits = (uint32_t)(rows * rowbits);
+    const bool one_band = band >= si;
+    for (int j0 = 0; j0 < R; j0 += kIntThreads) {
+      const int j = j0 + (int)threadIdx.x;
+      const bool valid = j < R;
+      int32_t rho = -1, dv = 0;
+      if (valid) {
+        const int k = sorted ? (int)s_perm[j] : j;
+        rho = rho_q[(int64_t)r * R + k];
+        int64_t di = (ah + (int64_t)a_off[k]) % kNang;
+        if (di < 0) di += kNang;
+        dv = dirtab[di];
+      }
       const int64_t lim = rho >= 0 ? (int64_t)rho : (int64_t)rmax_q;
-      int64_t di = (ah + (int64_t)a_off[k]) % kNang;
-      if (di < 0) di += kNang;
-      const int32_t dv = dirtab[di];
       const int32_t a = (int16_t)(dv & 0xffff), b = dv >> 16;
       const int32_t aa = abs(a), bb = abs(b);
       const int32_t ex0 = a > 0 ? 65536 - fx : fx, ey0 = b > 0 ? 65536 - fy : fy;
@@ -514,30 +528,55 @@ __global__ __launch_bounds__(kIntThreads) void k_csm_integrate(
       const int32_t nxg = a > 0 ? si - 1 - cx0 : cx0, nyg = b > 0 ? si - 1 - cy0 : cy0;
       const int32_t nx = (int32_t)min((int64_t)nxg, nxl), ny = (int32_t)min((int64_t)nyg, nyl);
       const bool gx = nxg < nxl, gy = nyg < nyl;
-      const int32_t sx = a > 0 ? 1 : -1, sy = b > 0 ? 1 : -1;
-      const int32_t DX = bb << 16, DY = aa << 16;
-      // D <= 0 steps x; a direction along an axis never steps the other one
-      int32_t D = aa == 0 ? 1 : (bb == 0 ? -1 : ex0 * bb - ey0 * aa);
-      const int32_t dX = bb == 0 ? 0 : DX, dY = aa == 0 ? 0 : DY;
-      // branch-free steps (the crossing is selected, not branched on); a lane leaves when its next
-      // crossing is not allowed
-      int32_t cx = cx0, cy = cy0, kx = 0, ky = 0;
-      bool stepx;
-      for (;;) {
-        const int32_t row = cy - by0;
-        if ((uint32_t)row < (uint32_t)rows) atomicOr(&miss[row * nw + (cx >> 5)], 1u << (cx & 31));
-        stepx = D <= 0;
-        if (stepx ? kx == nx : ky == ny) break;
-        kx += stepx ? 1 : 0;
-        ky += stepx ? 0 : 1;
-        cx += stepx ? sx : 0;
-        cy += stepx ? 0 : sy;
-        D += stepx ? dX : -dY;
+      int32_t kx, ky;     // x and y steps of the walk
+      bool at_limit;      // the barred crossing is barred by the range (else by the grid's edge only)
+      if (aa == 0) {
+        kx = 0; ky = ny; at_limit = !gy;
+      } else if (bb == 0) {
+        kx = nx; ky = 0; at_limit = !gx;
+      } else {
+        const int64_t tx = ((int64_t)ex0 + ((int64_t)nx << 16)) * bb;   // barred x crossing (scaled)
+        const int64_t ty = ((int64_t)ey0 + ((int64_t)ny << 16)) * aa;   // barred y crossing (scaled)
+        if (tx <= ty) {   // stops at the x crossing: the y crossings strictly before it
+          const int64_t X = tx - (int64_t)ey0 * aa, den = (int64_t)aa << 16;
+          kx = nx;
+          ky = X <= 0 ? 0 : (int32_t)min<int64_t>(ny, (X + den - 1) / den);
+          at_limit = !gx;
+        } else {          // stops at the y crossing: the x crossings at or before it
+          const int64_t Y = ty - (int64_t)ex0 * bb, den = (int64_t)bb << 16;
+          ky = ny;
+          kx = Y < 0 ? 0 : (int32_t)min<int64_t>(nx, Y / den + 1);
+          at_limit = !gy;
+        }
       }
-      const bool at_limit = !(stepx ? gx : gy);
-      const int32_t row = cy - by0;
-      if (rho >= 0 && at_limit && (uint32_t)row < (uint32_t)rows)
-        atomicOr(&hitm[row * nw + (cx >> 5)], 1u << (cx & 31));
+      const int32_t n = valid ? kx + ky : 0;
+      const int32_t sxw = a > 0 ? 1 : -1, syw = b > 0 ? rowbits : -rowbits;
+      const int32_t w0 = (cy0 - by0) * rowbits + cx0;   // bit of the origin cell (may lie outside the band)
+      int32_t D = aa == 0 ? 1 : (bb == 0 ? -1 : ex0 * bb - ey0 * aa);
+      const int32_t dX = bb == 0 ? 0 : bb << 16, dY = aa == 0 ? 0 : aa << 16;
+      if (valid && (uint32_t)w0 < band_bits) atomicOr(&miss[w0 >> 5], 1u << (w0 & 31));
+      int32_t nmax = n, nmin = n;
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        nmax = max(nmax, __shfl_xor(nmax, o, 64));
+        nmin = min(nmin, __shfl_xor(nmin, o, 64));
+      }
+      if (!one_band) nmin = 0;
+      int32_t wi = w0, i = 0;
+      for (; i < nmin; ++i) {
+        const bool stepx = D <= 0;
+        wi += stepx ? sxw : syw;
+        D += stepx ? dX : -dY;
+        atomicOr(&miss[wi >> 5], 1u << (wi & 31));
+      }
+      for (; i < nmax; ++i) {
+        const bool stepx = D <= 0;
+        wi += stepx ? sxw : syw;
+        D += stepx ? dX : -dY;
+        if (i < n && (uint32_t)wi < band_bits) atomicOr(&miss[wi >> 5], 1u << (wi & 31));
+      }
+      const int32_t we = w0 + kx * sxw + ky * syw;   // the end cell
+      if (valid && rho >= 0 && at_limit && (uint32_t)we < band_bits) atomicOr(&hitm[we >> 5], 1u << (we & 31));
     }
     __syncthreads();
     // apply: octet o covers cells 8 (o mod 4nw) .. + 7 of band row o / 4nw
