@@ -227,6 +227,35 @@ def test_integrate_bands_and_max_side():
     _integrate_case(44, [300, 64, 200, 96], 90, 2, 2, 65536, 64, 120 * 65536, max_side=64)
 
 
+def test_integrate_many_rays_and_no_count():
+    """More rays than the length sort takes (2100 > 2048: rays in their own order), and the call without
+    the coded-cell output: same exact grids as the oracle."""
+    from paper_2603_25834_amd import _lib
+    sides = [64, 96, 48]
+    W, V, sxy, sh, R = 1, 0, 65536, 0, 2100
+    grids, belief, cell_off, side, pose, rho, a_off = _batch(51, sides, R, W, V, sxy, sh)
+    a_off = (np.arange(R) * 21).astype(np.int32)          # headings need not divide the table evenly
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    say(f"[slam] integrate with R={R} rays, with and without the coded-cell output")
+    bel = d(belief)
+    coded = slam.csm_integrate(bel, d(cell_off), d(side), d(pose), d(rho), d(a_off), 50 * 65536, 218, -102, 896)
+    bel2 = d(belief)
+    # device copies held by names for the raw call (a temporary could be freed and its memory reused by the
+    # next argument before the launch)
+    co2, sd2, po2, rh2, ao2 = d(cell_off), d(side), d(pose), d(rho), d(a_off)
+    _lib.check(_lib.lib().aslam_csm_integrate(slam._p(bel2), slam._p(co2), slam._p(sd2), len(sides), slam._p(po2),
+                                              slam._p(rh2), R, slam._p(ao2), 96, 50 * 65536, None, None, 1.0, 218,
+                                              -102, 896, None, slam._stream()))
+    torch.cuda.synchronize()
+    got, got2, coded = bel.cpu().numpy(), bel2.cpu().numpy(), coded.cpu().numpy()
+    for r, s_ in enumerate(sides):
+        want, nc = S.integrate(grids[r], int(pose[r, 0]), int(pose[r, 1]), int(pose[r, 2]), rho[r], a_off, 50 * 65536,
+                               218, -102, 896)
+        o = int(cell_off[r])
+        assert np.array_equal(got[o:o + s_ * s_].reshape(s_, s_), want) and int(coded[r]) == nc, r
+        assert np.array_equal(got2[o:o + s_ * s_].reshape(s_, s_), want), r
+
+
 def test_integrate_full_batch_sampled_and_errors():
     """750 robots of 256^2 grids and 360 rays integrated from the GPU matcher's own output; for 12 sampled
     robots the oracle matches (which the GPU's must equal) drive the oracle's integration; then the
@@ -254,10 +283,11 @@ def test_integrate_full_batch_sampled_and_errors():
         assert np.array_equal(got[o:o + 65536].reshape(256, 256), want) and int(coded[r]) == nc, r
     with pytest.raises(_lib.AslamError):   # l_clamp out of range
         slam.csm_integrate(bel, d(cell_off), d(side), d(pose), d(rho), d(a_off), 65536, 218, -102, 0)
+    co, sd, po, rh, ao = d(cell_off), d(side), d(pose), d(rho), d(a_off)
     with pytest.raises(_lib.AslamError):   # a match without a config
-        _lib.check(_lib.lib().aslam_csm_integrate(slam._p(bel), slam._p(d(cell_off)), slam._p(d(side)), 750,
-                                                  slam._p(d(pose)), slam._p(d(rho)), R, slam._p(d(a_off)), 256, 65536,
-                                                  slam._p(match), None, 896.0, 218, -102, 896, None, slam._stream()))
+        _lib.check(_lib.lib().aslam_csm_integrate(slam._p(bel), slam._p(co), slam._p(sd), 750, slam._p(po),
+                                                  slam._p(rh), R, slam._p(ao), 256, 65536, slam._p(match), None, 896.0,
+                                                  218, -102, 896, None, slam._stream()))
 
 
 def test_backbone_on_env_state():
