@@ -96,11 +96,30 @@ __global__ __launch_bounds__(kCsmThreads) void k_csm(const int16_t* __restrict__
     const int64_t x = (int64_t)px + (int64_t)(i - W) * step_xy, y = (int64_t)py + (int64_t)(j - W) * step_xy;
     const int2* o = s_off + k * R;
     int32_t sc = 0;
-    for (int q = 0; q < R; ++q) {
-      const int2 v = o[q];
-      if (v.x == INT32_MIN) continue;
-      const int64_t cx = (x + v.x) >> 16, cy = (y + v.y) >> 16;
-      if (cx >= 0 && cx < sd && cy >= 0 && cy < sd) sc += g[cy * sd + cx];
+    if (sd > 0) {
+      // eight rays per step with every read issued before any is used (reads from global memory);
+      // a ray without a return or a cell off the grid reads cell 0 and adds nothing
+      constexpr int kRays = 8;
+      int q = 0;
+      for (; q + kRays <= R; q += kRays) {
+        int32_t t[kRays];
+#pragma unroll
+        for (int u = 0; u < kRays; ++u) {
+          const int2 v = o[q + u];
+          const int64_t cx = (x + v.x) >> 16, cy = (y + v.y) >> 16;
+          const bool ok = v.x != INT32_MIN && cx >= 0 && cx < sd && cy >= 0 && cy < sd;
+          const int32_t val = g[ok ? cy * sd + cx : 0];
+          t[u] = ok ? val : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < kRays; ++u) sc += t[u];
+      }
+      for (; q < R; ++q) {
+        const int2 v = o[q];
+        if (v.x == INT32_MIN) continue;
+        const int64_t cx = (x + v.x) >> 16, cy = (y + v.y) >> 16;
+        if (cx >= 0 && cx < sd && cy >= 0 && cy < sd) sc += g[cy * sd + cx];
+      }
     }
     s_score[c] = sc;
   }
