@@ -56,6 +56,72 @@ void orc_entropy_table(int32_t lc, uint32_t* hq) {
   }
 }
 
+/* ---------------------------------------------------------- random numbers
+ * Philox4x64-10 as published (Salmon et al., SC'11): each round multiplies
+ * counter words 0 and 2 by the two round multipliers (128-bit products), and
+ * the new counter is (hi(M1 x2) ^ x1 ^ k0, lo(M1 x2), hi(M0 x0) ^ x3 ^ k1,
+ * lo(M0 x0)); the key grows by the two Weyl constants between rounds. */
+void orc_philox4x64(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]) {
+  const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+  const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+  uint64_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+  uint64_t k0 = key[0], k1 = key[1];
+  for (int round = 0; round < 10; ++round) {
+    if (round > 0) {
+      k0 += W0;
+      k1 += W1;
+    }
+    unsigned __int128 p0 = (unsigned __int128)M0 * x0;
+    unsigned __int128 p1 = (unsigned __int128)M1 * x2;
+    uint64_t hi0 = (uint64_t)(p0 >> 64), lo0 = (uint64_t)p0;
+    uint64_t hi1 = (uint64_t)(p1 >> 64), lo1 = (uint64_t)p1;
+    uint64_t y0 = hi1 ^ x1 ^ k0, y1 = lo1, y2 = hi0 ^ x3 ^ k1, y3 = lo0;
+    x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+  }
+  out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+/* Irwin-Hall(12) normal: the 256-bit block gives twelve 21-bit uniforms (bits
+ * 63..43, 42..22 and 21..1 of each word); their integer sum minus its mean
+ * 6 (2^21 - 1) is below 2^24 in magnitude, so the FP32 value is exact.  Mean
+ * 0, variance 1 - 2^-42, support [-6, 6]: a reproducible stand-in for the
+ * Gaussian draws of the workload. */
+float orc_normal(uint64_t seed, uint64_t domain, uint64_t c0, uint64_t c1, uint64_t c2) {
+  const uint64_t ctr[4] = {c0, c1, c2, 0}, key[2] = {seed, domain};
+  uint64_t w[4];
+  orc_philox4x64(ctr, key, w);
+  const uint64_t m21 = (1ull << 21) - 1;
+  int64_t sum = 0;
+  for (int i = 0; i < 4; ++i) sum += (int64_t)((w[i] >> 43) & m21) + (int64_t)((w[i] >> 22) & m21) + (int64_t)((w[i] >> 1) & m21);
+  return (float)(sum - 6 * (int64_t)m21) * (1.0f / 2097152.0f);
+}
+
+/* Feistel network of 8 rounds over b bits (halves of h = b/2 bits); four rounds left the
+ * images of tiny domains visibly non-uniform after cycle walking. */
+static uint64_t feistel(uint64_t v, int h, uint64_t seed, uint64_t counter) {
+  const uint64_t mask = (1ull << h) - 1;
+  uint64_t l = v >> h, r = v & mask;
+  for (uint64_t round = 0; round < 8; ++round) {
+    const uint64_t ctr[4] = {counter, r, round, 0}, key[2] = {seed, ORC_DOMAIN_PERM};
+    uint64_t w[4];
+    orc_philox4x64(ctr, key, w);
+    uint64_t nl = r, nr = l ^ (w[0] & mask);
+    l = nl;
+    r = nr;
+  }
+  return (l << h) | r;
+}
+
+void orc_permute(int32_t n, uint64_t seed, uint64_t counter, int32_t* out) {
+  int b = 2;
+  while ((1ll << b) < (int64_t)n) b += 2;
+  for (int32_t j = 0; j < n; ++j) {
+    uint64_t y = feistel((uint64_t)j, b / 2, seed, counter);
+    while (y >= (uint64_t)n) y = feistel(y, b / 2, seed, counter);  /* cycle walking */
+    out[j] = (int32_t)y;
+  }
+}
+
 /* idx(theta) = rint(theta * NANG/(2 pi)) mod NANG, in FP32. */
 int32_t orc_heading_index(float theta) {
   const float k_ang = (float)((double)ORC_NANG / (2.0 * M_PI));
@@ -587,12 +653,23 @@ void orc_step(const orc_config* cfg, orc_state* st, const float* actions, const 
   orc_entropy_table(T->lc, T->hq);
   int32_t smax = 0;
   for (int32_t r = 0; r < st->n; ++r) if (st->side[r] > smax) smax = st->side[r];
+  const int32_t G = orc_noise_width(cfg);
 #pragma omp parallel num_threads(n_threads > 0 ? n_threads : 1)
   {
     uint8_t* code = (uint8_t*)malloc((size_t)smax * (size_t)smax);
+    float* own = (float*)malloc(sizeof(float) * (size_t)G);
 #pragma omp for schedule(dynamic, 1)
-    for (int32_t r = 0; r < st->n; ++r)
-      step_robot(cfg, T, st, r, actions + 2 * (int64_t)r, noise + (int64_t)orc_noise_width(cfg) * r, out, code);
+    for (int32_t r = 0; r < st->n; ++r) {
+      const float* g = noise ? noise + (int64_t)G * r : own;
+      if (!noise) {
+        /* the step's own draws: normal k of robot r at its step count draws[r] */
+        for (int32_t k = 0; k < G; ++k)
+          own[k] = orc_normal(cfg->noise_seed, ORC_DOMAIN_ENV, st->draws[r], (uint64_t)r, (uint64_t)k);
+      }
+      step_robot(cfg, T, st, r, actions + 2 * (int64_t)r, g, out, code);
+      st->draws[r] += 1;
+    }
+    free(own);
     free(code);
   }
   free(T->hq);

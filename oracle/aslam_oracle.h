@@ -61,6 +61,7 @@ typedef struct {
   float d_crash_m;       /* proximity collision distance (0 = off) */
   float d_full_m;        /* clearance at which the wall-hugging factor reaches 1 */
   float lambda_explore, lambda_abs, lambda_delta, u_hi, kappa;
+  uint64_t noise_seed;   /* key of the step's own normal draws (used when the caller passes none) */
 } orc_config;
 
 /* Per-robot state, caller-owned arrays (robots are independent). */
@@ -84,6 +85,7 @@ typedef struct {
   int32_t* visit_last;       /* ragged last-visit step (-1 none; reward_mode 1) */
   int32_t* prev_vcell;       /* [n] visit cell of the previous step (-1 none; reward_mode 1) */
   double* u_prev;            /* [n] U_{t-1} = cbrt(det Sigma) of the previous step (reward_mode 1) */
+  uint64_t* draws;           /* [n] steps taken since the state was created (counter of the draws) */
 } orc_state;
 
 typedef struct {
@@ -114,12 +116,33 @@ int32_t orc_walk(int64_t ox, int64_t oy, int64_t a, int64_t b, int64_t scale, in
                  int32_t s, int32_t* cells_x, int32_t* cells_y, int64_t* e_out, int32_t* axis_out,
                  int32_t max_out, int32_t* end_reason);
 
+/* Counter-based random numbers (test twin of the library's generator).
+ * Philox4x64-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy
+ * as 1, 2, 3", SC'11): out = 10 rounds over the 4-word counter under the
+ * 2-word key. */
+void orc_philox4x64(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);
+/* One standard-normal draw: the Irwin-Hall sum of the twelve 21-bit fields of
+ * the block at counter (c0, c1, c2, 0) under key (seed, domain), centred and
+ * scaled exactly: (sum - 6 (2^21 - 1)) / 2^21. */
+float orc_normal(uint64_t seed, uint64_t domain, uint64_t c0, uint64_t c1, uint64_t c2);
+/* Keyed permutation of [0, n): an 8-round Feistel network on the smallest even
+ * number of bits b >= 2 with 2^b >= n, round function = low b/2 bits of word 0
+ * of Philox at counter (counter, half, round, 0) under key (seed, 3), with
+ * cycle walking back into [0, n).  out[j] = image of j. */
+void orc_permute(int32_t n, uint64_t seed, uint64_t counter, int32_t* out);
+#define ORC_DOMAIN_ENV 1        /* env step draws: counter (robot's step count, robot, draw index) */
+#define ORC_DOMAIN_ACTION 2     /* action sampling: counter (caller's counter, row, action dimension) */
+#define ORC_DOMAIN_PERM 3       /* minibatch permutations */
+
 void orc_reset(const orc_config* cfg, orc_state* st, const float* init_pose, const uint8_t* mask);
 /* Normal draws per robot and step in the noise input: 5, plus R with range noise. */
 int32_t orc_noise_width(const orc_config* cfg);
 /* The paper's reward, Eq. (7) with Eqs. (8)-(17), from its inputs (all FP64). */
 double orc_paper_reward(const orc_config* cfg, int collided, double delta_cells, double u_prev, double u,
                         double d_min);
+/* One step of every robot.  noise: caller's normals [n, orc_noise_width], or
+ * NULL to draw them: normal k of robot r is orc_normal(noise_seed, ORC_DOMAIN_ENV,
+ * draws[r], r, k).  Either way draws[r] grows by one. */
 void orc_step(const orc_config* cfg, orc_state* st, const float* actions, const float* noise,
               orc_out* out, int32_t n_threads);
 /* Observation.  With reward_mode 1 and u_new != NULL the uncertainty entry is

@@ -50,6 +50,7 @@ class OrcConfig(ctypes.Structure):
         ("d_crash_m", ctypes.c_float), ("d_full_m", ctypes.c_float),
         ("lambda_explore", ctypes.c_float), ("lambda_abs", ctypes.c_float), ("lambda_delta", ctypes.c_float),
         ("u_hi", ctypes.c_float), ("kappa", ctypes.c_float),
+        ("noise_seed", ctypes.c_uint64),
     ]
 
 
@@ -59,7 +60,8 @@ _P = ctypes.c_void_p
 class OrcState(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32)] + [(f, _P) for f in (
         "side", "world_off", "cell_off", "visit_off", "world", "belief", "pose", "est", "cov",
-        "h_q", "step", "last_lc", "visit_t", "visit_x", "visit_y", "visit_last", "prev_vcell", "u_prev")]
+        "h_q", "step", "last_lc", "visit_t", "visit_x", "visit_y", "visit_last", "prev_vcell", "u_prev",
+        "draws")]
 
 
 class OrcOut(ctypes.Structure):
@@ -95,6 +97,10 @@ def lib():
         L.orc_paper_reward.argtypes = [ctypes.POINTER(OrcConfig), ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                        ctypes.c_double, ctypes.c_double]
         L.orc_paper_reward.restype = ctypes.c_double
+        L.orc_philox4x64.argtypes = [_P, _P, _P]
+        L.orc_normal.argtypes = [ctypes.c_uint64] * 5
+        L.orc_normal.restype = ctypes.c_float
+        L.orc_permute.argtypes = [ctypes.c_int32, ctypes.c_uint64, ctypes.c_uint64, _P]
         _lib = L
     return _lib
 
@@ -140,8 +146,41 @@ def walk(ox, oy, a, b, scale, lim, s, max_out=1 << 16):
 def make_config(p: dict) -> OrcConfig:
     c = OrcConfig()
     for name, _ in OrcConfig._fields_:
-        setattr(c, name, p[name])
+        setattr(c, name, p.get(name, 0) if name == "noise_seed" else p[name])
     return c
+
+
+DOMAIN_ENV, DOMAIN_ACTION, DOMAIN_PERM = 1, 2, 3
+
+
+def philox4x64(ctr, key) -> np.ndarray:
+    """Philox4x64-10 block at a 4-word counter under a 2-word key (the oracle's own C implementation)."""
+    c = np.ascontiguousarray(ctr, np.uint64)
+    k = np.ascontiguousarray(key, np.uint64)
+    out = np.zeros(4, np.uint64)
+    lib().orc_philox4x64(_ptr(c), _ptr(k), _ptr(out))
+    return out
+
+
+def normal(seed: int, domain: int, c0: int, c1: int, c2: int) -> np.float32:
+    """Irwin-Hall(12) standard normal of the block at counter (c0, c1, c2, 0) under key (seed, domain)."""
+    return np.float32(lib().orc_normal(seed, domain, c0, c1, c2))
+
+
+def normals(seed: int, domain: int, c0: int, rows: int, cols: int) -> np.ndarray:
+    """[rows, cols] draws: entry (b, d) at counter (c0, b, d)."""
+    out = np.zeros((rows, cols), np.float32)
+    for b in range(rows):
+        for d in range(cols):
+            out[b, d] = lib().orc_normal(seed, domain, c0, b, d)
+    return out
+
+
+def permute(n: int, seed: int, counter: int) -> np.ndarray:
+    """Keyed permutation of [0, n) (Feistel network with cycle walking), out[j] = image of j."""
+    out = np.zeros(max(n, 1), np.int32)
+    lib().orc_permute(int(n), seed, counter, _ptr(out))
+    return out[:n]
 
 
 def bridge_alpha(t: int, t_bridge: int) -> float:
@@ -204,6 +243,7 @@ class OracleEnv:
         self.h_q = np.zeros(n, np.int64)
         self.step_ct = np.zeros(n, np.int32)
         self.last_lc = np.zeros(n, np.int32)
+        self.draws = np.zeros(n, np.uint64)
         self.R = int(self.p["n_rays"])
 
     def _state(self) -> OrcState:
@@ -214,7 +254,7 @@ class OracleEnv:
                      ("pose", self.pose), ("est", self.est), ("cov", self.cov), ("h_q", self.h_q),
                      ("step", self.step_ct), ("last_lc", self.last_lc), ("visit_t", self.visit_t),
                      ("visit_x", self.visit_x), ("visit_y", self.visit_y), ("visit_last", self.visit_last),
-                     ("prev_vcell", self.prev_vcell), ("u_prev", self.u_prev)):
+                     ("prev_vcell", self.prev_vcell), ("u_prev", self.u_prev), ("draws", self.draws)):
             setattr(st, f, _ptr(a))
         return st
 
@@ -224,10 +264,13 @@ class OracleEnv:
         st = self._state()
         lib().orc_reset(ctypes.byref(self.cfg), ctypes.byref(st), _ptr(ip), None if m is None else _ptr(m))
 
-    def step(self, actions: np.ndarray, noise: np.ndarray, threads: int = 0) -> StepOut:
+    def step(self, actions: np.ndarray, noise: np.ndarray | None, threads: int = 0) -> StepOut:
+        """One step; noise None draws the step's own normals (key noise_seed, counter draws[r])."""
         n, R = self.n, self.R
         a = np.ascontiguousarray(actions, np.float32).reshape(n, 2)
-        g = np.ascontiguousarray(noise, np.float32).reshape(n, int(lib().orc_noise_width(ctypes.byref(self.cfg))))
+        g = None
+        if noise is not None:
+            g = np.ascontiguousarray(noise, np.float32).reshape(n, int(lib().orc_noise_width(ctypes.byref(self.cfg))))
         o = StepOut(ranges=np.zeros((n, R), np.float32), rho_q=np.zeros((n, R), np.int32),
                     hit_cell=np.zeros((n, R), np.int32), reward=np.zeros(n, np.float64),
                     done=np.zeros(n, np.uint8), collided=np.zeros(n, np.uint8),
@@ -238,7 +281,8 @@ class OracleEnv:
             setattr(co, f[0], _ptr(getattr(o, f[0])))
         st = self._state()
         th = threads if threads > 0 else (os.cpu_count() or 1)
-        lib().orc_step(ctypes.byref(self.cfg), ctypes.byref(st), _ptr(a), _ptr(g), ctypes.byref(co), th)
+        lib().orc_step(ctypes.byref(self.cfg), ctypes.byref(st), _ptr(a), None if g is None else _ptr(g),
+                       ctypes.byref(co), th)
         return o
 
     def observe(self, ranges: np.ndarray, crop_side: int = 64, u_new: np.ndarray | None = None, t: int = 0,
