@@ -3,8 +3,9 @@
 One step = one environment step of every robot (motion and collision, EKF
 predict and loop closure, LiDAR march, log-odds map update, entropy and
 D-optimality reward) followed by the observation assembly for the policy.
-Inputs (worlds, start poses, actions, normal draws) are seeded, synthetic and
-resident in HBM before the timed region.  Prints one JSON line.
+Inputs (worlds, start poses, actions) are seeded, synthetic and resident in
+HBM before the timed region; the normal draws and permutations come from the
+library's counter-based generator inside the kernels.  Prints one JSON line.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 """
@@ -27,19 +28,25 @@ BF16_PEAK_TFLOPS = 2500.0
 METRIC = "env-steps/s and rays/s at 750 & 4096 robots; % HBM roofline; PPO fwd+bwd/s"
 
 
-def alg_bytes_per_robot_step(D: float, R: int, loop_closure: bool, noise_width: int = 5,
+def alg_bytes_per_robot_step(D: float, R: int, loop_closure: bool, host_draws: int = 0,
                              paper_reward: bool = False) -> float:
     """Algorithmic HBM bytes of one robot-step.
 
     Map: read + write each coded int16 cell (4 B); world bits of the cells the
     rays cross, taken equal to the coded cells (D/8 B); ranges out (4R B);
-    per-robot state and I/O: action 8, normal draws 4G (G = 5, or 5 + R with
-    range noise), true pose r/w 24, estimate r/w 24, covariance r/w 48, step
-    r/w 8, entropy r/w 16, reward 4, done 1 (133 B + 4G); loop-closure visit
-    record read 12 B; Eq. (7) reward state: U_{t-1} r/w 16, previous visit
-    cell r/w 8, last visit r/w 8 (32 B)."""
-    return (4.0 * D + D / 8.0 + 4.0 * R + 133.0 + 4.0 * noise_width + (12.0 if loop_closure else 0.0) +
+    per-robot state and I/O: action 8, true pose r/w 24, estimate r/w 24,
+    covariance r/w 48, step r/w 8, entropy r/w 16, draw counter r/w 16,
+    reward 4, done 1 (149 B), plus 4 B per normal draw read from the caller
+    (none when the step draws its own); loop-closure visit record read 12 B;
+    Eq. (7) reward state: U_{t-1} r/w 16, previous visit cell r/w 8, last
+    visit r/w 8 (32 B)."""
+    return (4.0 * D + D / 8.0 + 4.0 * R + 149.0 + 4.0 * host_draws + (12.0 if loop_closure else 0.0) +
             (32.0 if paper_reward else 0.0))
+
+
+def noise_seed(seed: int) -> int:
+    """Key of the env step's own normal draws for a benchmark seed."""
+    return 0x5EED0000 + int(seed)
 
 
 def kernel_source_digest() -> str:
@@ -81,11 +88,11 @@ class Workbench:
         self.name = name
         w = self.w = synth.WORKLOADS[name]
         self.p = w.params()
+        self.p["noise_seed"] = noise_seed(seed)
         t0 = time.time()
         self.b = synth.make_batch(name, seed)
         self.n, self.R = len(self.b.sides), w.n_rays
         A = synth.actions(name, seed, steps)
-        G = synth.noise(name, seed, steps)
         self.gen_s = time.time() - t0
         self.env = Env(self.p, self.b.sides)
         self.env.set_exec(**exec_kw)
@@ -94,7 +101,6 @@ class Workbench:
         self.world = torch.from_numpy(self.b.world.view(np.int32).copy()).to(dev)
         self.start = torch.from_numpy(self.b.start).to(dev)
         self.dA = torch.from_numpy(A).to(dev)
-        self.dG = torch.from_numpy(G).to(dev)
         self.ranges = torch.zeros((self.n, self.R), device=dev)
         self.reward = torch.zeros(self.n, device=dev)
         self.done = torch.zeros(self.n, dtype=torch.uint8, device=dev)
@@ -110,10 +116,9 @@ class Workbench:
         e = self.env
         n = self.n
         for t in range(warmup):
-            e.step(self.dA[t], self.dG[t], self.ranges, self.reward, self.done)
+            e.step(self.dA[t], None, self.ranges, self.reward, self.done)
         if graph:
-            e.graph_build(steps, self.dA[warmup:], 2 * n, self.dG[warmup:], e.G * n, self.ranges, 0, self.reward, 0,
-                          self.done, 0)
+            e.graph_build(steps, self.dA[warmup:], 2 * n, None, 0, self.ranges, 0, self.reward, 0, self.done, 0)
         torch.cuda.synchronize()
         c0 = e.read(_lib.FIELD_COUNTERS).sum(0).cpu().numpy()
         t_start = torch.cuda.Event(enable_timing=True)
@@ -124,7 +129,7 @@ class Workbench:
             e.graph_launch()
         else:
             for t in range(warmup, warmup + steps):
-                e.step(self.dA[t], self.dG[t], self.ranges, self.reward, self.done)
+                e.step(self.dA[t], None, self.ranges, self.reward, self.done)
         t_end.record()
         torch.cuda.synchronize()
         ms = t_start.elapsed_time(t_end)
@@ -132,7 +137,7 @@ class Workbench:
         D = float(c1[0] - c0[0]) / (n * steps)
         vm = float(c1[1] - c0[1]) / (n * steps)
         vu = float(c1[2] - c0[2]) / (n * steps)
-        bytes_step = n * alg_bytes_per_robot_step(D, self.R, bool(self.p["loop_closure"]), e.G,
+        bytes_step = n * alg_bytes_per_robot_step(D, self.R, bool(self.p["loop_closure"]), 0,
                                                   int(self.p.get("reward_mode", 0)) == 1)
         s = ms / 1e3
         return dict(ms=ms, ms_per_step=ms / steps, env_steps_per_s=n * steps / s, rays_per_s=n * steps * self.R / s,
@@ -300,14 +305,14 @@ def cpu_full_loop(name: str, seed: int, robots: int, T: int, epochs: int) -> dic
     idx = np.arange(min(robots, w.n_robots))
     n = len(idx)
     b = synth.make_batch(name, seed, idx)
-    G = synth.noise(name, seed, T, idx)
-    env = O.OracleEnv(w.params(), b.sides, b.world, b.world_off)
+    p = w.params()
+    p["noise_seed"] = noise_seed(seed)
+    env = O.OracleEnv(p, b.sides, b.world, b.world_off)
     env.reset(b.start)
     shape = PR.PolicyShape(w.n_rays)
     theta = torch.from_numpy(synth.init_policy_params(w.n_rays, seed)).double()
     m = torch.zeros_like(theta)
     v = torch.zeros_like(theta)
-    rng = np.random.default_rng([seed, 78])
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
     threads = min(threads, os.cpu_count() or threads)
     ranges = np.zeros((n, w.n_rays), np.float32)
@@ -324,10 +329,11 @@ def cpu_full_loop(name: str, seed: int, robots: int, T: int, epochs: int) -> dic
                 break
             for k, a in (("crop", crop), ("scan", scan), ("state", state)):
                 obs[k].append(a)
-            act = mu + torch.exp(ls) * torch.from_numpy(rng.standard_normal((n, 2)))
+            eps = O.normals(seed, O.DOMAIN_ACTION, t, n, 2)
+            act = mu + torch.exp(ls) * torch.from_numpy(eps.astype(np.float64))
             act_l.append(act.float())
             logp_l.append(PR.gaussian_logp(mu, ls, act).float())
-            o = env.step(act.float().numpy(), G[t], threads=threads)
+            o = env.step(act.float().numpy(), None, threads=threads)
             ranges = o.ranges
             rew_l.append(torch.from_numpy(o.reward))
             done_l.append(torch.from_numpy(o.done.astype(np.float64)))
@@ -408,15 +414,16 @@ def cpu_baseline(name: str, seed: int, robots: int, steps: int) -> dict:
     idx = np.arange(min(robots, w.n_robots))
     b = synth.make_batch(name, seed, idx)
     A = synth.actions(name, seed, steps, idx)
-    G = synth.noise(name, seed, steps, idx)
-    env = O.OracleEnv(w.params(), b.sides, b.world, b.world_off)
+    p = w.params()
+    p["noise_seed"] = noise_seed(seed)
+    env = O.OracleEnv(p, b.sides, b.world, b.world_off)
     env.reset(b.start)
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
     threads = min(threads, os.cpu_count() or threads)
     cnt = np.zeros(4, np.int64)
     t0 = time.time()
     for t in range(steps):
-        o = env.step(A[t], G[t], threads=threads)
+        o = env.step(A[t], None, threads=threads)
         cnt += o.counters.sum(0)
     dt = time.time() - t0
     rs = len(idx) * steps
@@ -438,16 +445,15 @@ def train_loop(wb, horizon: int, epochs: int, minibatch: int, warmup: int, iters
     init = synth.init_recurrent_params if recurrent else synth.init_policy_params
     params = torch.from_numpy(init(wb.R, seed)).cuda()
     tr = PPOTrainer(wb.env, wb.world, wb.start, params, T=horizon, epochs=epochs, minibatch=minibatch,
-                    recurrent=recurrent)
-    noise, eps, perm = tr.draws(warmup + iters, seed)
+                    recurrent=recurrent, seed=seed)
     for i in range(warmup):
-        tr.iteration(noise[i], eps[i], perm[i])
+        tr.iteration()
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record()
     for i in range(warmup, warmup + iters):
-        tr.iteration(noise[i], eps[i], perm[i])
+        tr.iteration()
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / iters
@@ -463,11 +469,11 @@ def autotune_forms(wb) -> tuple:
     """Autotune the fused and the plain form on the workbench's own batch, then reset it."""
     from paper_2603_25834_amd import _lib
     from paper_2603_25834_amd.autotune import THREADS, Candidate, default_candidates, tune
-    A, G = wb.dA[:8], wb.dG[:8]
+    A = wb.dA[:8]
     out = (wb.ranges, wb.reward, wb.done)
-    rf = tune(wb.env, A, G, *out, candidates=default_candidates(wb.env), force=True)
+    rf = tune(wb.env, A, None, *out, candidates=default_candidates(wb.env), force=True)
     fused = dict(rf["best"])
-    rp = tune(wb.env, A, G, *out, candidates=[Candidate(t, form=_lib.FORM_PLAIN) for t in THREADS], force=True)
+    rp = tune(wb.env, A, None, *out, candidates=[Candidate(t, form=_lib.FORM_PLAIN) for t in THREADS], force=True)
     plain = dict(rp["best"])
     wb.env.set_exec(**fused)
     wb.env.reset(wb.world, wb.start)
@@ -616,7 +622,8 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "int32+bf16",
-        "data": "synthetic (seeded worlds, start poses, odometry and action noise, minibatch permutations; "
+        "data": "synthetic (seeded worlds, start poses and env-timing actions; odometry, loop-closure and action "
+                "noise and minibatch permutations from the library's counter-based generator in the kernels; "
                 "random-init policy)",
         "config": {"workload": args.workload, "robots": wb.n, "grid_side": sorted(set(map(int, wb.b.sides))),
                    "rays": wb.R, "r_max_m": wb.p["r_max_m"], "cell_m": wb.p["cell_m"],

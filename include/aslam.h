@@ -80,11 +80,21 @@ typedef struct {
   float d_full_m;       /* Eq. 15: the positive reward terms reach full weight at this clearance (> d_crash) */
   float lambda_explore, lambda_abs, lambda_delta; /* Eqs. 8, 13, 14 */
   float u_hi, kappa;    /* Eq. 11 uncertainty gate, Eq. 12 saturation drop (both > 0 in mode 1) */
+  uint64_t noise_seed;  /* key of the step's own normal draws (env_step with noise_dev NULL) */
 } aslam_env_config;
 
 /* Standard-normal draws per robot in the step's noise row: 5 (odometry x,
  * y, theta, loop-closure x, y), plus n_rays range draws when range_sigma_m
- * > 0.  Returns -1 for a NULL handle. */
+ * > 0.  Returns -1 for a NULL handle.
+ *
+ * The library's own draws (env_step with noise_dev NULL): draw k of robot r
+ * at a step is the Irwin-Hall(12) normal of one Philox4x64-10 block (Salmon
+ * et al., SC'11) at counter (c_r, r, k, 0) under key (noise_seed, 1), where c_r
+ * counts the robot's env_step calls since create (resets keep it): the sum of
+ * the block's twelve 21-bit fields (bits 63..43, 42..22, 21..1 of each word)
+ * minus 6 (2^21 - 1), times 2^-21 (exact in FP32; mean 0, variance 1 - 2^-42).
+ * A stand-in for the Gaussian odometry and range noise (Sec. IV-A) that any
+ * implementation reproduces bit for bit. */
 int32_t aslam_env_noise_width(const aslam_env* env);
 
 /* Execution form of env_step.  PLAIN issues one launch per stage (motion and
@@ -133,7 +143,8 @@ int aslam_env_reset(aslam_env* env, const uint32_t* world_dev, const float* init
  *   actions_dev float [n,2] (v, w), clamped to the box; NaN -> 0.
  *   noise_dev   float [n,G] standard-normal draws, G = aslam_env_noise_width:
  *               odometry x, y, theta, the loop-closure measurement x, y, then
- *               (with range noise) one draw per ray.
+ *               (with range noise) one draw per ray; NULL = the library's own
+ *               draws (above).  Either way each robot's draw counter moves on.
  *   ranges_dev  float [n,R] out: range (m) to the entry face of the first
  *               occupied cell, r_max when none within range; with the sensor
  *               model, plus noise, rounded to the quantum and clamped to
@@ -180,13 +191,16 @@ int aslam_env_observe_bridge(aslam_env* env, const float* ranges_dev, int16_t* c
 #define ASLAM_FIELD_U_PREV 11    /* double [n] U of the last step (reward_mode 1), cbrt(det Sigma) */
 #define ASLAM_FIELD_VISIT_LAST 12 /* int32 [sum v_i^2] last step each visit cell held the robot, -1 never
                                      (v_i = ceil(s_i c / lc_cell_m); loop closure or reward_mode 1) */
+#define ASLAM_FIELD_DRAWS 13     /* uint64 [n] env_step calls since create (the draw counter) */
 int aslam_env_read(const aslam_env* env, int32_t field, void* dst_dev, aslam_stream_t stream);
 
 /* HIP graph of K consecutive env_step calls.  Step k reads
  * actions_dev + k*a_stride, noise_dev + k*g_stride and writes
  * ranges_dev + k*r_stride, reward_dev + k*w_stride, done_dev + k*d_stride
- * (strides in elements; 0 = same buffer every step).  The graph is
- * instantiated once and replayed with aslam_env_graph_launch. */
+ * (strides in elements; 0 = same buffer every step).  noise_dev NULL: every
+ * step takes the library's own draws, whose counters live on the device, so
+ * each replay draws new numbers.  The graph is instantiated once and replayed
+ * with aslam_env_graph_launch. */
 int aslam_env_graph_build(aslam_env* env, int32_t k_steps, const float* actions_dev, int64_t a_stride,
                           const float* noise_dev, int64_t g_stride, float* ranges_dev, int64_t r_stride,
                           float* reward_dev, int64_t w_stride, uint8_t* done_dev, int64_t d_stride);
@@ -244,7 +258,10 @@ int aslam_policy_prepare(aslam_policy* pol, const float* params_dev, aslam_strea
 
 /* Rollout step of the actor (Sec. III-F): the forward pass and the Gaussian
  * action sample in one call.  Inputs as aslam_policy_forward; eps_dev [B,2]
- * standard normals drawn by the caller.  Writes value_dev [B], act_dev [B,2],
+ * standard normals drawn by the caller, or NULL for the library's own: the
+ * normal of row b, dimension d is the Irwin-Hall(12) value of the Philox4x64-10
+ * block at counter (counter, b, d, 0) under key (seed, 2) (the generator
+ * described at aslam_env_noise_width).  Writes value_dev [B], act_dev [B,2],
  * logp_dev [B] and, if mu_dev is not NULL, mu_dev [B,2]; the results equal
  * aslam_policy_forward followed by aslam_policy_sample bit for bit.
  * prepared = 1 uses the weight copies of the last prepare, forward, act or
@@ -253,7 +270,8 @@ int aslam_policy_prepare(aslam_policy* pol, const float* params_dev, aslam_strea
  * them first. */
 int aslam_policy_act(aslam_policy* pol, const float* params_dev, int32_t prepared, const int16_t* crop_dev,
                      const float* scan_dev, const float* state_dev, int32_t batch, const float* eps_dev,
-                     float* mu_dev, float* value_dev, float* act_dev, float* logp_dev, aslam_stream_t stream);
+                     uint64_t seed, uint64_t counter, float* mu_dev, float* value_dev, float* act_dev,
+                     float* logp_dev, aslam_stream_t stream);
 
 /* PPO loss and its gradient over one minibatch, recomputing the forward
  * activations (only the inputs are stored across the rollout).
@@ -283,13 +301,14 @@ int aslam_policy_backward_rows(aslam_policy* pol, const float* params_dev, const
  * x = the FC1 output, h = h_in_dev [B,256] FP32 row b, or 0 where first_dev[b]
  * (uint8 [B], may be NULL) marks the first step of an episode.  Writes the new
  * state h_out_dev [B,256] (may alias h_in_dev) and, from the heads on h', as
- * aslam_policy_act: value_dev, act_dev, logp_dev and mu_dev if not NULL.
- * prepared as in aslam_policy_act.  BF16 products with FP32 accumulation;
+ * aslam_policy_act: value_dev, act_dev, logp_dev and mu_dev if not NULL
+ * (eps_dev, seed, counter as there).  prepared as in aslam_policy_act.  BF16 products with FP32 accumulation;
  * gate math and state in FP32. */
 int aslam_policy_act_rnn(aslam_policy* pol, const float* params_dev, int32_t prepared, const int16_t* crop_dev,
                          const float* scan_dev, const float* state_dev, int32_t batch, const float* h_in_dev,
-                         const uint8_t* first_dev, const float* eps_dev, float* mu_dev, float* value_dev,
-                         float* act_dev, float* logp_dev, float* h_out_dev, aslam_stream_t stream);
+                         const uint8_t* first_dev, const float* eps_dev, uint64_t seed, uint64_t counter,
+                         float* mu_dev, float* value_dev, float* act_dev, float* logp_dev, float* h_out_dev,
+                         aslam_stream_t stream);
 
 /* PPO loss and its gradient for the recurrent policy over whole sequences,
  * with backpropagation through time.  The rollout arrays are time-major:
@@ -319,10 +338,20 @@ int aslam_adam(float* params_dev, const float* grads_dev, float* m_dev, float* v
 
 /* Action sampling of the Gaussian policy (Sec. III-F): act = mu + exp(log_std) * eps and
  * logp = sum_d [-eps_d^2 / 2 - log_std_d - ln(2 pi) / 2], the log-density of act.  mu_dev and eps_dev
- * are [batch,2] float (eps: standard normals drawn by the caller), log_std is read from params_dev;
- * act_dev [batch,2] and logp_dev [batch] are written.  The env step clamps actions to its box. */
+ * are [batch,2] float (eps: standard normals drawn by the caller, or NULL for the library's own at
+ * (seed, counter) as in aslam_policy_act), log_std is read from params_dev; act_dev [batch,2] and
+ * logp_dev [batch] are written.  The env step clamps actions to its box. */
 int aslam_policy_sample(aslam_policy* pol, const float* params_dev, const float* mu_dev, const float* eps_dev,
-                        int32_t batch, float* act_dev, float* logp_dev, aslam_stream_t stream);
+                        uint64_t seed, uint64_t counter, int32_t batch, float* act_dev, float* logp_dev,
+                        aslam_stream_t stream);
+
+/* Keyed permutation of [0, n) for PPO's shuffled minibatches (Sec. III-F): out_dev int32 [n],
+ * out[j] = the image of j under an 8-round balanced Feistel network on the smallest even bit width
+ * b >= 2 with 2^b >= n (halves of b/2 bits; round i maps (l, r) to (r, l ^ f), f = the low b/2 bits of
+ * word 0 of the Philox4x64-10 block at counter (counter, r, i, 0) under key (seed, 3)), applied again
+ * while the image is >= n (cycle walking).  A bijection for every key.  ASL_EINVAL on n < 0 or a NULL
+ * out_dev with n > 0. */
+int aslam_permutation(int32_t n, uint64_t seed, uint64_t counter, int32_t* out_dev, aslam_stream_t stream);
 
 /* Row gather for minibatch assembly: dst row i = src row idx_dev[i], i < n, rows of row_bytes bytes
  * (a multiple of 4; src and dst 4-byte aligned).  Indices are not checked against the source size:

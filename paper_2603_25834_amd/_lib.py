@@ -18,7 +18,7 @@ FORM_PLAIN = 0
 FORM_FUSED = 1
 
 FIELD_BELIEF, FIELD_POSE, FIELD_EST, FIELD_COV, FIELD_RHO_Q, FIELD_HIT_CELL, FIELD_ENTROPY_Q, \
-    FIELD_STEP, FIELD_FLAGS, FIELD_TERMS, FIELD_COUNTERS, FIELD_U_PREV, FIELD_VISIT_LAST = range(13)
+    FIELD_STEP, FIELD_FLAGS, FIELD_TERMS, FIELD_COUNTERS, FIELD_U_PREV, FIELD_VISIT_LAST, FIELD_DRAWS = range(14)
 
 
 class AslamError(RuntimeError):
@@ -43,6 +43,7 @@ class EnvConfig(ctypes.Structure):
         ("d_crash_m", ctypes.c_float), ("d_full_m", ctypes.c_float),
         ("lambda_explore", ctypes.c_float), ("lambda_abs", ctypes.c_float), ("lambda_delta", ctypes.c_float),
         ("u_hi", ctypes.c_float), ("kappa", ctypes.c_float),
+        ("noise_seed", ctypes.c_uint64),
     ]
 
 
@@ -57,6 +58,7 @@ class ExecConfig(ctypes.Structure):
 _P = ctypes.c_void_p
 _I32 = ctypes.c_int32
 _I64 = ctypes.c_int64
+_U64 = ctypes.c_uint64
 
 # name -> (restype, argtypes); every function of include/aslam.h
 SIGNATURES = {
@@ -79,17 +81,19 @@ SIGNATURES = {
     "aslam_env_graph_launch": (ctypes.c_int, [_P, _P]),
     "aslam_policy_num_params": (_I64, [_I32]),
     "aslam_policy_param_count": (_I64, [_P]),
-    "aslam_policy_act_rnn": (ctypes.c_int, [_P, _P, _I32, _P, _P, _P, _I32, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "aslam_policy_act_rnn": (ctypes.c_int, [_P, _P, _I32, _P, _P, _P, _I32, _P, _P, _P, _U64, _U64, _P, _P, _P, _P, _P,
+                                            _P]),
     "aslam_policy_backward_seq": (ctypes.c_int, [_P, _P, _P, _P, _P, _I32, _I32, _P, _I32, _P, _P, _P, _P, _P, _P, _P,
                                                  _P, _P]),
     "aslam_policy_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_P)]),
     "aslam_policy_destroy": (ctypes.c_int, [_P]),
     "aslam_policy_forward": (ctypes.c_int, [_P, _P, _P, _P, _P, _I32, _P, _P, _P]),
     "aslam_policy_backward": (ctypes.c_int, [_P, _P, _P, _P, _P, _I32, _P, _P, _P, _P, _P, _P, _P]),
-    "aslam_policy_sample": (ctypes.c_int, [_P, _P, _P, _P, _I32, _P, _P, _P]),
+    "aslam_policy_sample": (ctypes.c_int, [_P, _P, _P, _P, _U64, _U64, _I32, _P, _P, _P]),
+    "aslam_permutation": (ctypes.c_int, [_I32, _U64, _U64, _P, _P]),
     "aslam_policy_prepare": (ctypes.c_int, [_P, _P, _P]),
     "aslam_policy_backward_rows": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _I32, _P, _P, _P, _P, _P, _P, _P]),
-    "aslam_policy_act": (ctypes.c_int, [_P, _P, _I32, _P, _P, _P, _I32, _P, _P, _P, _P, _P, _P]),
+    "aslam_policy_act": (ctypes.c_int, [_P, _P, _I32, _P, _P, _P, _I32, _P, _U64, _U64, _P, _P, _P, _P, _P]),
     "aslam_gather_rows": (ctypes.c_int, [_P, _I64, _P, _I32, _P, _P]),
     "aslam_gae": (ctypes.c_int, [_P, _P, _P, _P, _I32, _I32, ctypes.c_float, ctypes.c_float, _P, _P, _P]),
     "aslam_adam": (ctypes.c_int, [_P, _P, _P, _P, _I64, _I32, ctypes.c_float, ctypes.c_float, ctypes.c_float,

@@ -92,24 +92,24 @@ _MEMO: dict = {}
 def _time_candidate(env: Env, c: Candidate, actions, noise, ranges, reward, done, warmup: int, steps: int) -> float:
     env.set_exec(form=c.form, threads=c.threads, band_rows=c.band_rows, grid=c.grid)
     for t in range(warmup):
-        env.step(actions[t % len(actions)], noise[t % len(noise)], ranges, reward, done)
+        env.step(actions[t % len(actions)], None if noise is None else noise[t % len(noise)], ranges, reward, done)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record()
     for t in range(steps):
         k = (warmup + t) % len(actions)
-        env.step(actions[k], noise[k], ranges, reward, done)
+        env.step(actions[k], None if noise is None else noise[k], ranges, reward, done)
     e1.record()
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / steps
 
 
-def tune(env: Env, actions: torch.Tensor, noise: torch.Tensor, ranges: torch.Tensor, reward: torch.Tensor,
+def tune(env: Env, actions: torch.Tensor, noise: torch.Tensor | None, ranges: torch.Tensor, reward: torch.Tensor,
          done: torch.Tensor, candidates: list[Candidate] | None = None, warmup: int = 3, steps: int = 10,
          cache_path: str | None = None, force: bool = False) -> dict:
     """Pick the fastest launch shape for this env's batch and apply it with ``Env.set_exec``.
 
-    actions [T, n, 2] and noise [T, n, env.G] are device tensors of per-step inputs
+    actions [T, n, 2] and noise [T, n, env.G] (or None: the step draws its own) are device tensors of per-step inputs
     (cycled if T is short).  Returns {"signature", "best", "table"} with the
     per-candidate time in microseconds per step."""
     key = signature(env)

@@ -84,6 +84,7 @@ struct aslam_env {
   void* d_u_prev = nullptr;
   void* d_dcells = nullptr;
   void* d_dmin = nullptr;
+  void* d_draws = nullptr;
   // captured step sequence
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
@@ -96,7 +97,7 @@ void free_env(aslam_env* e) {
   void** ptrs[] = {&e->d_meta, &e->d_order, &e->d_world, &e->d_belief, &e->d_pose, &e->d_est, &e->d_cov,
                    &e->d_hq_total, &e->d_step, &e->d_last_lc, &e->d_visit_t, &e->d_visit_xy, &e->d_rho,
                    &e->d_hitc, &e->d_flags, &e->d_terms, &e->d_counters, &e->d_raylen, &e->d_dirtab, &e->d_hq_lut,
-                   &e->d_visit_last, &e->d_prev_vcell, &e->d_u_prev, &e->d_dcells, &e->d_dmin};
+                   &e->d_visit_last, &e->d_prev_vcell, &e->d_u_prev, &e->d_dcells, &e->d_dmin, &e->d_draws};
   for (void** p : ptrs) {
     if (*p) (void)hipFree(*p);
     *p = nullptr;
@@ -293,6 +294,7 @@ int aslam_env_create(const aslam_env_config* cfg, int32_t n_robots, const int32_
       {&e->d_u_prev, sizeof(double) * (size_t)n_robots},
       {&e->d_dcells, sizeof(double) * (size_t)n_robots},
       {&e->d_dmin, sizeof(int32_t) * (size_t)n_robots},
+      {&e->d_draws, sizeof(uint64_t) * (size_t)n_robots},
   };
   for (auto& a : allocs) {
     hipError_t he = hipMalloc(a.p, a.bytes);
@@ -312,6 +314,8 @@ int aslam_env_create(const aslam_env_config* cfg, int32_t n_robots, const int32_
   if (he == hipSuccess) he = hipMemcpy(e->d_order, order.data(), sizeof(int32_t) * n_robots, hipMemcpyHostToDevice);
   if (he == hipSuccess) he = hipMemcpy(e->d_dirtab, dirtab.data(), sizeof(int32_t) * kNang, hipMemcpyHostToDevice);
   if (he == hipSuccess) he = hipMemcpy(e->d_hq_lut, lut.data(), sizeof(uint32_t) * lut.size(), hipMemcpyHostToDevice);
+  if (he == hipSuccess) he = hipMemset(e->d_draws, 0, sizeof(uint64_t) * (size_t)n_robots);
+  if (he == hipSuccess) he = hipDeviceSynchronize();
   if (he == hipSuccess) he = hipStreamCreateWithFlags(&e->capture_stream, hipStreamNonBlocking);
   if (he != hipSuccess) {
     free_env(e);
@@ -398,6 +402,8 @@ int aslam_env_create(const aslam_env_config* cfg, int32_t n_robots, const int32_
   P.u_prev = (double*)e->d_u_prev;
   P.dcells = (double*)e->d_dcells;
   P.dmin_bits = (int32_t*)e->d_dmin;
+  P.seed = cfg->noise_seed;
+  P.draws = (uint64_t*)e->d_draws;
 
   he = set_kernel_lds_limits(e->lds_max);
   if (he != hipSuccess) {
@@ -479,7 +485,7 @@ static int do_step(aslam_env* env, const StepArgs& A, hipStream_t st) {
 
 int aslam_env_step(aslam_env* env, const float* actions_dev, const float* noise_dev, float* ranges_dev,
                    float* reward_dev, uint8_t* done_dev, aslam_stream_t stream) {
-  if (!env || !actions_dev || !noise_dev || !ranges_dev || !reward_dev || !done_dev)
+  if (!env || !actions_dev || !ranges_dev || !reward_dev || !done_dev)
     return fail(ASL_EINVAL, "null argument to env_step");
   if (!env->was_reset) return fail(ASL_ESTATE, "env_step called before env_reset");
   StepArgs A{actions_dev, noise_dev, ranges_dev, reward_dev, done_dev};
@@ -531,6 +537,7 @@ int aslam_env_read(const aslam_env* env, int32_t field, void* dst_dev, aslam_str
     case ASLAM_FIELD_COUNTERS: src = env->d_counters; bytes = 24 * n; break;
     case ASLAM_FIELD_U_PREV: src = env->d_u_prev; bytes = 8 * n; break;
     case ASLAM_FIELD_VISIT_LAST: src = env->d_visit_last; bytes = 4 * (size_t)env->visits; break;
+    case ASLAM_FIELD_DRAWS: src = env->d_draws; bytes = 8 * n; break;
     default: return fail(ASL_EINVAL, "unknown field");
   }
   HIP_TRY(hipMemcpyAsync(dst_dev, src, bytes, hipMemcpyDeviceToDevice, (hipStream_t)stream), "read");
@@ -540,7 +547,7 @@ int aslam_env_read(const aslam_env* env, int32_t field, void* dst_dev, aslam_str
 int aslam_env_graph_build(aslam_env* env, int32_t k_steps, const float* actions_dev, int64_t a_stride,
                           const float* noise_dev, int64_t g_stride, float* ranges_dev, int64_t r_stride,
                           float* reward_dev, int64_t w_stride, uint8_t* done_dev, int64_t d_stride) {
-  if (!env || k_steps < 1 || !actions_dev || !noise_dev || !ranges_dev || !reward_dev || !done_dev)
+  if (!env || k_steps < 1 || !actions_dev || !ranges_dev || !reward_dev || !done_dev)
     return fail(ASL_EINVAL, "bad graph arguments");
   if (a_stride < 0 || g_stride < 0 || r_stride < 0 || w_stride < 0 || d_stride < 0)
     return fail(ASL_EINVAL, "negative stride");
@@ -555,7 +562,7 @@ int aslam_env_graph_build(aslam_env* env, int32_t k_steps, const float* actions_
   hipStream_t cs = env->capture_stream;
   HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "begin capture");
   for (int32_t k = 0; k < k_steps; ++k) {
-    StepArgs A{actions_dev + k * a_stride, noise_dev + k * g_stride, ranges_dev + k * r_stride,
+    StepArgs A{actions_dev + k * a_stride, noise_dev ? noise_dev + k * g_stride : nullptr, ranges_dev + k * r_stride,
                reward_dev + k * w_stride, done_dev + k * d_stride};
     int rc = do_step(env, A, cs);
     if (rc) {

@@ -86,11 +86,13 @@ struct EnvParams {
   double* u_prev;        // [n] U_{t-1} = cbrt(det Sigma) of the previous step
   double* dcells;        // [n] novelty of this step's visit cell (motion -> reward)
   int32_t* dmin_bits;    // [n] FP32 bits of the smallest reported range (march -> reward)
+  uint64_t seed;         // key of the step's own normal draws
+  uint64_t* draws;       // [n] steps taken since create: counter of the robot's draws
 };
 
 struct StepArgs {
   const float* actions;  // [n,2]
-  const float* noise;    // [n,G]
+  const float* noise;    // [n,G], or NULL: the step draws its own normals
   float* ranges;         // [n,R]
   float* reward;         // [n]
   uint8_t* done;         // [n]

@@ -17,6 +17,7 @@
 // coalesced pass applies one saturating int16 add to each coded cell and
 // accumulates the exact entropy change in int64.
 #include "env_internal.h"
+#include "rng.h"
 
 namespace aslam {
 
@@ -169,6 +170,26 @@ __device__ __forceinline__ int32_t wave_sum_i32(int32_t v) {
   return v;
 }
 
+// The step's standard-normal draws of robot r: column k of the caller's noise row, or the
+// library's own draw k at the robot's draw counter (the counter moves on at the end of the step).
+struct StepNoise {
+  const float* row;
+  uint64_t seed, ctr;
+  int32_t r;
+  __device__ __forceinline__ float operator()(int32_t k) const {
+    return row ? row[k] : rng::normal(seed, rng::kDomainEnv, ctr, (uint64_t)r, (uint64_t)k);
+  }
+};
+
+__device__ __forceinline__ StepNoise step_noise(const EnvParams& P, const StepArgs& A, int32_t r) {
+  StepNoise g{nullptr, P.seed, 0ull, r};
+  if (A.noise)
+    g.row = A.noise + (int64_t)P.G * r;
+  else
+    g.ctr = P.draws[r];
+  return g;
+}
+
 struct MotionOut {
   int32_t tox, toy, ib_t;   // true origin (Q16) and heading index of ray 0
   int32_t eox, eoy, ib_e;   // estimated origin and heading index of ray 0
@@ -181,7 +202,7 @@ __device__ MotionOut robot_motion(const EnvParams& P, const StepArgs& A, int32_t
   const RobotMeta m = P.meta[r];
   const int32_t s = m.side;
   const float a0 = A.actions[2 * r], a1 = A.actions[2 * r + 1];
-  const float* g = A.noise + (int64_t)P.G * r;
+  const StepNoise g = step_noise(P, A, r);
   float v = fminf(fmaxf(a0, 0.0f), P.v_max);
   float w = fminf(fmaxf(a1, -P.w_max), P.w_max);
   if (v != v) v = 0.0f;
@@ -192,9 +213,9 @@ __device__ MotionOut robot_motion(const EnvParams& P, const StepArgs& A, int32_t
   float* p = P.pose + 3 * (int64_t)r;
   float px = p[0], py = p[1], pth = p[2];
   const int32_t dt_ = P.dirtab[heading_index(pth, P.k_ang)];
-  const float nx = (px + d * dir_cos(dt_)) + P.sigma_x * g[0];
-  const float ny = (py + d * dir_sin(dt_)) + P.sigma_y * g[1];
-  const float nth = wrap_pi((pth + phi) + P.sigma_th * g[2]);
+  const float nx = (px + d * dir_cos(dt_)) + P.sigma_x * g(0);
+  const float ny = (py + d * dir_sin(dt_)) + P.sigma_y * g(1);
+  const float nth = wrap_pi((pth + phi) + P.sigma_th * g(2));
   const uint32_t* W = P.world + m.world_off;
   const bool col = segment_blocked(W, s, to_q16(px, P.inv_c16), to_q16(py, P.inv_c16),
                                    to_q16(nx, P.inv_c16), to_q16(ny, P.inv_c16));
@@ -269,8 +290,8 @@ __device__ MotionOut robot_motion(const EnvParams& P, const StepArgs& A, int32_t
       const float dx = px - P.visit_xy[2 * vk];
       const float dy = py - P.visit_xy[2 * vk + 1];
       if (t - t0 >= P.lc_gap && t - P.last_lc[r] >= P.lc_gap && (dx * dx + dy * dy) <= P.lc_r2) {
-        const float zx = px + P.lc_sigma * g[3];
-        const float zy = py + P.lc_sigma * g[4];
+        const float zx = px + P.lc_sigma * g(3);
+        const float zy = py + P.lc_sigma * g(4);
         const float s00 = c0 + P.lc_var, s01 = c1, s11 = c3 + P.lc_var;
         const float det = s00 * s11 - s01 * s01;
         const float i00 = s11 / det, i01 = (-s01) / det, i11 = s00 / det;
@@ -540,10 +561,10 @@ constexpr int kLook = kMarchLook;
 // LiDAR march of every ray of the robot from the true pose (lanes = rays),
 // then the reported range of each ray (sensor model of Sec. IV-A: true range
 // plus noise, rounded to the quantum, clamped to [r_min, r_max]).  The map
-// update walks the reported range; gr holds the ray noise draws.
+// update walks the reported range; ray k takes draw 5 + k of gr.
 template <int NT>
 __device__ void march_rays(const EnvParams& P, const RobotMeta& m, const LdsView& V, const uint32_t* sw,
-                           int32_t wy0, float* ranges_out, const float* gr, bool record, int32_t r) {
+                           int32_t wy0, float* ranges_out, const StepNoise& gr, bool record, int32_t r) {
   RobotShared* sh = V.sh;
   int32_t* rho_lds = V.rho;
   const int32_t s = m.side;
@@ -644,7 +665,7 @@ __device__ void march_rays(const EnvParams& P, const RobotMeta& m, const LdsView
       float rep = (float)rq * P.c16;
       int32_t rho_u = rq;
       if (P.sensed) {
-        if (P.range_sigma > 0.0f) rep = rep + P.range_sigma * gr[k];
+        if (P.range_sigma > 0.0f) rep = rep + P.range_sigma * gr(5 + k);
         if (P.range_quant > 0.0f) rep = rintf(rep * P.inv_quant) * P.range_quant;
         rep = fminf(fmaxf(rep, P.r_min), P.r_max);
         rho_u = to_q16(rep, P.inv_c16);
@@ -880,6 +901,7 @@ __device__ void update_and_reward(const EnvParams& P, const StepArgs& A, const R
     A.done[r] = (uint8_t)(col || (P.episode_len > 0 && t >= P.episode_len));
     P.terms[2 * (int64_t)r] = (float)rH;
     P.terms[2 * (int64_t)r + 1] = (float)ld;
+    P.draws[r] += 1;   // every step, with or without the caller's draws
   }
 }
 
@@ -911,7 +933,7 @@ __global__ __launch_bounds__(NT) void k_march(EnvParams P, StepArgs A, LdsPlan L
   uint32_t* sw = V.uni + march_guard_words(m.side);
   stage_world<NT>(P, m, sh->toy >> 16, L.world_halo, sw, wy0);
   __syncthreads();
-  march_rays<NT>(P, m, V, sw, wy0, A.ranges, A.noise + (int64_t)P.G * r + 5, true, r);
+  march_rays<NT>(P, m, V, sw, wy0, A.ranges, step_noise(P, A, r), true, r);
   if (threadIdx.x == 0) {
     P.counters[3 * (int64_t)r + 1] += sh->cnt_march;
     P.dmin_bits[r] = sh->dmin_bits;
@@ -982,7 +1004,7 @@ __device__ __forceinline__ void fused_robot(const EnvParams& P, const StepArgs& 
     sh->collided = 1;
     P.flags[2 * (int64_t)r] = 1;
   }
-  march_rays<NT>(P, m, V, sw, wy0, A.ranges, A.noise + (int64_t)P.G * r + 5, L.record != 0, r);
+  march_rays<NT>(P, m, V, sw, wy0, A.ranges, step_noise(P, A, r), L.record != 0, r);
   endpoint_bbox<NT>(P, V.rho, sh->eox, sh->eoy, sh->ib_e, sh);
   __syncthreads();
   update_and_reward<NT>(P, A, m, V, L, r);

@@ -147,7 +147,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
 // units 4 l .. 4 l + 3); also copies the state to h_out (which may alias the step's entering state,
 // read completely by the step kernel before this one runs).
 __global__ __launch_bounds__(256) void k_gru_heads(const float* prm, Offsets o, const float* h, int rows,
-                                                   float* h_out, float* mu, float* value, const float* eps,
+                                                   float* h_out, float* mu, float* value, ActDraws eps,
                                                    float* act, float* logp) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t row = (int64_t)blockIdx.x * 4 + wave;
@@ -176,7 +176,7 @@ __global__ __launch_bounds__(256) void k_gru_heads(const float* prm, Offsets o, 
     }
     value[row] = sv + prm[o.vb];
     const float ls0 = prm[o.lstd], ls1 = prm[o.lstd + 1];
-    const float e0 = eps[2 * row], e1 = eps[2 * row + 1];
+    const float e0 = eps(row, 0), e1 = eps(row, 1);
     act[2 * row] = m0 + expf(ls0) * e0;
     act[2 * row + 1] = m1 + expf(ls1) * e1;
     logp[row] = -0.5f * (e0 * e0 + e1 * e1) - (ls0 + ls1) - 1.8378770664093453f;

@@ -190,8 +190,8 @@ int forward_core(aslam_policy* P, const float* prm, const int16_t* crop, const f
 
 // Forward-only pass: encoder, FC1, then the fused tail (FC2, heads and, with eps, the sample).
 int act_core(aslam_policy* P, const float* prm, bool prepared, const int16_t* crop, const float* scan,
-             const float* state, int B, const float* eps, float* mu, float* value, float* act, float* logp,
-             hipStream_t st) {
+             const float* state, int B, bool sample, ActDraws eps, float* mu, float* value, float* act,
+             float* logp, hipStream_t st) {
   if (!prepared) {
     int rc = convert_weights(P, prm, st, false);
     if (rc) return rc;
@@ -208,7 +208,7 @@ int act_core(aslam_policy* P, const float* prm, bool prepared, const int16_t* cr
     S = 0;
   }
   k_fwd_tail<<<(B + kTailRows - 1) / kTailRows, 256, 0, st>>>(prm, P->off, P->part, S, P->h1, P->w2b, B, mu, value,
-                                                              eps, act, logp);
+                                                              sample, eps, act, logp);
   PCHK(hipGetLastError());
   return ASL_OK;
 }
@@ -300,8 +300,8 @@ int aslam_policy_forward(aslam_policy* P, const float* params, const int16_t* cr
   if (!P || !params || !crop || !scan || !state || !mu || !value) return pfail(ASL_EINVAL, "null argument");
   if (batch < 1 || batch > P->max_b) return pfail(ASL_EINVAL, "batch must be in [1, max_batch]");
   if (P->rec) return pfail(ASL_EINVAL, "recurrent policy: use aslam_policy_act_rnn");
-  return act_core(P, params, false, crop, scan, state, batch, nullptr, mu, value, nullptr, nullptr,
-                  (hipStream_t)stream);
+  return act_core(P, params, false, crop, scan, state, batch, false, ActDraws{nullptr, 0, 0}, mu, value, nullptr,
+                  nullptr, (hipStream_t)stream);
 }
 
 int aslam_policy_prepare(aslam_policy* P, const float* params, aslam_stream_t stream) {
@@ -310,15 +310,15 @@ int aslam_policy_prepare(aslam_policy* P, const float* params, aslam_stream_t st
 }
 
 int aslam_policy_act(aslam_policy* P, const float* params, int32_t prepared, const int16_t* crop, const float* scan,
-                     const float* state, int32_t batch, const float* eps, float* mu, float* value, float* act,
-                     float* logp, aslam_stream_t stream) {
-  if (!P || !params || !crop || !scan || !state || !eps || !value || !act || !logp)
+                     const float* state, int32_t batch, const float* eps, uint64_t seed, uint64_t counter, float* mu,
+                     float* value, float* act, float* logp, aslam_stream_t stream) {
+  if (!P || !params || !crop || !scan || !state || !value || !act || !logp)
     return pfail(ASL_EINVAL, "null argument");
   if (batch < 1 || batch > P->max_b) return pfail(ASL_EINVAL, "batch must be in [1, max_batch]");
   if (P->rec) return pfail(ASL_EINVAL, "recurrent policy: use aslam_policy_act_rnn");
   if (prepared && !P->prepared) return pfail(ASL_ESTATE, "act with prepared = 1 before any prepare");
-  return act_core(P, params, prepared != 0, crop, scan, state, batch, eps, mu, value, act, logp,
-                  (hipStream_t)stream);
+  return act_core(P, params, prepared != 0, crop, scan, state, batch, true, ActDraws{eps, seed, counter}, mu, value,
+                  act, logp, (hipStream_t)stream);
 }
 
 int aslam_policy_backward(aslam_policy* P, const float* params, const int16_t* crop, const float* scan,
@@ -409,11 +409,21 @@ int backward_fc1_encoder(aslam_policy* P, const float* params, const int16_t* cr
 
 extern "C" {
 
-int aslam_policy_sample(aslam_policy* P, const float* params, const float* mu, const float* eps, int32_t batch,
-                        float* act, float* logp, aslam_stream_t stream) {
-  if (!P || !params || !mu || !eps || !act || !logp) return pfail(ASL_EINVAL, "null argument");
+int aslam_policy_sample(aslam_policy* P, const float* params, const float* mu, const float* eps, uint64_t seed,
+                        uint64_t counter, int32_t batch, float* act, float* logp, aslam_stream_t stream) {
+  if (!P || !params || !mu || !act || !logp) return pfail(ASL_EINVAL, "null argument");
   if (batch < 1) return pfail(ASL_EINVAL, "batch must be >= 1");
-  k_sample<<<(batch + 255) / 256, 256, 0, (hipStream_t)stream>>>(params, P->off, mu, eps, batch, act, logp);
+  k_sample<<<(batch + 255) / 256, 256, 0, (hipStream_t)stream>>>(params, P->off, mu, ActDraws{eps, seed, counter},
+                                                                  batch, act, logp);
+  PCHK(hipGetLastError());
+  return ASL_OK;
+}
+
+int aslam_permutation(int32_t n, uint64_t seed, uint64_t counter, int32_t* out, aslam_stream_t stream) {
+  if (n < 0) return pfail(ASL_EINVAL, "n must be >= 0");
+  if (n == 0) return ASL_OK;
+  if (!out) return pfail(ASL_EINVAL, "null argument");
+  k_permutation<<<(n + 255) / 256, 256, 0, (hipStream_t)stream>>>(n, rng::perm_half_bits(n), seed, counter, out);
   PCHK(hipGetLastError());
   return ASL_OK;
 }
@@ -457,9 +467,9 @@ int aslam_adam(float* params, const float* grads, float* m, float* v, int64_t n,
 
 int aslam_policy_act_rnn(aslam_policy* P, const float* params, int32_t prepared, const int16_t* crop,
                          const float* scan, const float* state, int32_t batch, const float* h_in, const uint8_t* first,
-                         const float* eps, float* mu, float* value, float* act, float* logp, float* h_out,
-                         aslam_stream_t stream) {
-  if (!P || !params || !crop || !scan || !state || !h_in || !eps || !value || !act || !logp || !h_out)
+                         const float* eps, uint64_t seed, uint64_t counter, float* mu, float* value, float* act,
+                         float* logp, float* h_out, aslam_stream_t stream) {
+  if (!P || !params || !crop || !scan || !state || !h_in || !value || !act || !logp || !h_out)
     return pfail(ASL_EINVAL, "null argument");
   if (!P->rec) return pfail(ASL_EINVAL, "feed-forward policy: use aslam_policy_act");
   if (batch < 1 || batch > P->max_b) return pfail(ASL_EINVAL, "batch must be in [1, max_batch]");
@@ -491,7 +501,8 @@ int aslam_policy_act_rnn(aslam_policy* P, const float* params, int32_t prepared,
   a.h_out = P->hst;
   k_gru_fwd<false><<<dim3((batch + kGruRows - 1) / kGruRows, kGruSlices), 256, 0, st>>>(a);
   PCHK(hipGetLastError());
-  k_gru_heads<<<(batch + 3) / 4, 256, 0, st>>>(params, P->off, P->hst, batch, h_out, mu, value, eps, act, logp);
+  k_gru_heads<<<(batch + 3) / 4, 256, 0, st>>>(params, P->off, P->hst, batch, h_out, mu, value,
+                                                ActDraws{eps, seed, counter}, act, logp);
   PCHK(hipGetLastError());
   return ASL_OK;
 }

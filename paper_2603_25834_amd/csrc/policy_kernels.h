@@ -25,6 +25,7 @@
 
 #include "aslam.h"
 #include "gemm_bf16.h"
+#include "rng.h"
 
 namespace aslam {
 namespace pol {
@@ -609,13 +610,24 @@ __global__ __launch_bounds__(256) void k_transpose_bf16(const float* src, int64_
 // chunks in the GEMM engine's order, + bias, then the heads and, when eps is given, the Gaussian
 // action sample.  Every value is formed by the same operations in the same order as the unfused
 // sequence (split-K reduce, FC2 GEMM, k_heads, k_sample), so the outputs are bit-identical to it.
+// Standard normals of the Gaussian action sample: the caller's eps [B,2], or the library's own draw
+// of row b, dimension d at counter (counter, b, d) under key (seed, action domain).
+struct ActDraws {
+  const float* eps;
+  uint64_t seed, counter;
+  __device__ __forceinline__ float operator()(int64_t b, int d) const {
+    return eps ? eps[2 * b + d] : rng::normal(seed, rng::kDomainAction, counter, (uint64_t)b, (uint64_t)d);
+  }
+};
+
 constexpr int kTailRows = 16;
 constexpr int kTailLdH = kHid + 8;   // BF16 h1 rows in LDS, padded
 constexpr int kTailLdZ = kHid + 4;   // FP32 z2 rows in LDS, padded
 
 __global__ __launch_bounds__(256) void k_fwd_tail(const float* prm, Offsets o, const float* part, int S,
                                                   const uint16_t* h1, const uint16_t* w2b, int B, float* mu_out,
-                                                  float* v_out, const float* eps, float* act, float* logp) {
+                                                  float* v_out, bool sample, ActDraws eps, float* act,
+                                                  float* logp) {
   __shared__ __align__(16) uint16_t s_h[kTailRows * kTailLdH];
   __shared__ __align__(16) float s_z[kTailRows * kTailLdZ];
   const int row0 = blockIdx.x * kTailRows;
@@ -702,9 +714,9 @@ __global__ __launch_bounds__(256) void k_fwd_tail(const float* prm, Offsets o, c
         mu_out[2 * row + 1] = m1;
       }
       v_out[row] = sv + bv;
-      if (eps) {
+      if (sample) {
         const float ls0 = prm[o.lstd], ls1 = prm[o.lstd + 1];
-        const float e0 = eps[2 * row], e1 = eps[2 * row + 1];
+        const float e0 = eps(row, 0), e1 = eps(row, 1);
         act[2 * row] = m0 + expf(ls0) * e0;
         act[2 * row + 1] = m1 + expf(ls1) * e1;
         logp[row] = -0.5f * (e0 * e0 + e1 * e1) - (ls0 + ls1) - 1.8378770664093453f;
@@ -714,15 +726,21 @@ __global__ __launch_bounds__(256) void k_fwd_tail(const float* prm, Offsets o, c
 }
 
 // Gaussian action sampling: act = mu + exp(log_std) eps, logp = log N(act; mu, exp(log_std)).
-__global__ void k_sample(const float* prm, Offsets o, const float* mu, const float* eps, int B, float* act,
+__global__ void k_sample(const float* prm, Offsets o, const float* mu, ActDraws eps, int B, float* act,
                          float* logp) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= B) return;
   const float ls0 = prm[o.lstd], ls1 = prm[o.lstd + 1];
-  const float e0 = eps[2 * (int64_t)b], e1 = eps[2 * (int64_t)b + 1];
+  const float e0 = eps(b, 0), e1 = eps(b, 1);
   act[2 * (int64_t)b] = mu[2 * (int64_t)b] + expf(ls0) * e0;
   act[2 * (int64_t)b + 1] = mu[2 * (int64_t)b + 1] + expf(ls1) * e1;
   logp[b] = -0.5f * (e0 * e0 + e1 * e1) - (ls0 + ls1) - 1.8378770664093453f;
+}
+
+// Keyed permutation of [0, n): out[j] = the image of j (rng::permute).
+__global__ void k_permutation(int32_t n, int h, uint64_t seed, uint64_t counter, int32_t* out) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < n) out[j] = rng::permute((int32_t)j, n, h, seed, counter);
 }
 
 // dst row i = src row idx[i]; rows of `words` 32-bit words, 16-byte vectors when `vec`.

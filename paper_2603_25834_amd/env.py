@@ -36,7 +36,7 @@ class Env:
         self.params = dict(params)
         cfg = EnvConfig()
         for f in _CFG_FIELDS:
-            setattr(cfg, f, params[f])
+            setattr(cfg, f, params.get(f, 0) if f == "noise_seed" else params[f])
         self.device = torch.device(device)
         self.sides = np.ascontiguousarray(np.asarray(sides, np.int32))
         self.n = len(self.sides)
@@ -83,10 +83,11 @@ class Env:
             assert mask.dtype == torch.uint8 and mask.numel() == self.n
         check(lib().aslam_env_reset(self.h, _ptr(world_words), _ptr(init_pose), _ptr(mask), _stream()))
 
-    def step(self, actions: torch.Tensor, noise: torch.Tensor, ranges: torch.Tensor, reward: torch.Tensor,
+    def step(self, actions: torch.Tensor, noise: torch.Tensor | None, ranges: torch.Tensor, reward: torch.Tensor,
              done: torch.Tensor):
+        """One step; noise None takes the library's own draws (key params['noise_seed'])."""
         assert actions.dtype == torch.float32 and actions.numel() == 2 * self.n
-        assert noise.dtype == torch.float32 and noise.numel() == self.G * self.n
+        assert noise is None or (noise.dtype == torch.float32 and noise.numel() == self.G * self.n)
         assert ranges.dtype == torch.float32 and ranges.numel() == self.R * self.n
         assert reward.dtype == torch.float32 and reward.numel() == self.n
         assert done.dtype == torch.uint8 and done.numel() == self.n
@@ -126,6 +127,7 @@ class Env:
         _lib.FIELD_COUNTERS: (torch.int64, lambda s: (s.n, 3)),
         _lib.FIELD_U_PREV: (torch.float64, lambda s: (s.n,)),
         _lib.FIELD_VISIT_LAST: (torch.int32, lambda s: (s.visit_cells,)),
+        _lib.FIELD_DRAWS: (torch.int64, lambda s: (s.n,)),
     }
 
     def read(self, field: int) -> torch.Tensor:
@@ -135,13 +137,13 @@ class Env:
             check(lib().aslam_env_read(self.h, field, _ptr(out), _stream()))
         return out
 
-    def graph_build(self, k_steps: int, actions: torch.Tensor, a_stride: int, noise: torch.Tensor, g_stride: int,
+    def graph_build(self, k_steps: int, actions: torch.Tensor, a_stride: int, noise: torch.Tensor | None, g_stride: int,
                     ranges: torch.Tensor, r_stride: int, reward: torch.Tensor, w_stride: int,
                     done: torch.Tensor, d_stride: int):
         # the buffers must hold k_steps strided slices
         for t, st, per in ((actions, a_stride, 2 * self.n), (noise, g_stride, self.G * self.n),
                            (ranges, r_stride, self.R * self.n), (reward, w_stride, self.n), (done, d_stride, self.n)):
-            assert t.is_contiguous() and t.numel() >= (k_steps - 1) * st + per
+            assert t is None or (t.is_contiguous() and t.numel() >= (k_steps - 1) * st + per)
         check(lib().aslam_env_graph_build(self.h, k_steps, _ptr(actions), a_stride, _ptr(noise), g_stride,
                                           _ptr(ranges), r_stride, _ptr(reward), w_stride, _ptr(done), d_stride))
 

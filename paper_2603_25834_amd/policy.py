@@ -70,26 +70,29 @@ class Policy:
         assert params.dtype == torch.float32 and params.numel() == self.n_params
         check(lib().aslam_policy_prepare(self.h, _p(params), _stream()))
 
-    def act(self, params, crop, scan, state, eps, value=None, act=None, logp=None, mu=None, prepared=False):
+    def act(self, params, crop, scan, state, eps, value=None, act=None, logp=None, mu=None, prepared=False,
+            seed=0, counter=0):
         """Forward + Gaussian sample in one call: value [B], act [B, 2], logp [B] (and mu [B, 2] if given).
+        eps [B, 2] standard normals, or None for the library's own draws at (seed, counter).
         prepared=True reuses the weight copies of the last prepare/forward/act/backward call; the caller
         guarantees that `params` has not changed since."""
         B = self._check_obs(params, crop, scan, state)
-        assert eps.dtype == torch.float32 and tuple(eps.shape) == (B, 2)
+        assert eps is None or (eps.dtype == torch.float32 and tuple(eps.shape) == (B, 2))
         value = torch.empty(B, device=crop.device) if value is None else value
         act = torch.empty((B, 2), device=crop.device) if act is None else act
         logp = torch.empty(B, device=crop.device) if logp is None else logp
         check(lib().aslam_policy_act(self.h, _p(params), int(bool(prepared)), _p(crop), _p(scan), _p(state), B,
-                                     _p(eps), _p(mu), _p(value), _p(act), _p(logp), _stream()))
+                                     _p(eps), int(seed), int(counter), _p(mu), _p(value), _p(act), _p(logp),
+                                     _stream()))
         return value, act, logp
 
     def act_rnn(self, params, crop, scan, state, h_in, first, eps, value=None, act=None, logp=None, h_out=None,
-                mu=None, prepared=False):
+                mu=None, prepared=False, seed=0, counter=0):
         """Recurrent rollout step: the GRU state h_in [B, 256] (zeroed where first [B] uint8 is set, may be
         None) advances to h_out (may be h_in itself); value, action and log-prob as act()."""
         B = self._check_obs(params, crop, scan, state)
         assert h_in.dtype == torch.float32 and tuple(h_in.shape) == (B, 256)
-        assert eps.dtype == torch.float32 and tuple(eps.shape) == (B, 2)
+        assert eps is None or (eps.dtype == torch.float32 and tuple(eps.shape) == (B, 2))
         if first is not None:
             assert first.dtype == torch.uint8 and first.numel() == B
         value = torch.empty(B, device=crop.device) if value is None else value
@@ -97,8 +100,8 @@ class Policy:
         logp = torch.empty(B, device=crop.device) if logp is None else logp
         h_out = torch.empty_like(h_in) if h_out is None else h_out
         check(lib().aslam_policy_act_rnn(self.h, _p(params), int(bool(prepared)), _p(crop), _p(scan), _p(state), B,
-                                         _p(h_in), _p(first), _p(eps), _p(mu), _p(value), _p(act), _p(logp),
-                                         _p(h_out), _stream()))
+                                         _p(h_in), _p(first), _p(eps), int(seed), int(counter), _p(mu), _p(value),
+                                         _p(act), _p(logp), _p(h_out), _stream()))
         return value, act, logp, h_out
 
     def backward_seq(self, params, crop, scan, state, h0, first, act, old_logp, adv, ret, robots, grads, loss=None):
@@ -137,13 +140,16 @@ class Policy:
         return loss
 
 
-    def sample(self, params, mu, eps, act=None, logp=None):
-        """act = mu + exp(log_std) eps and its log-density; eps are standard normals [B, 2]."""
+    def sample(self, params, mu, eps, act=None, logp=None, seed=0, counter=0):
+        """act = mu + exp(log_std) eps and its log-density; eps are standard normals [B, 2], or None for
+        the library's own draws at (seed, counter)."""
         B = mu.shape[0]
-        assert mu.dtype == torch.float32 and tuple(mu.shape) == (B, 2) and tuple(eps.shape) == (B, 2)
+        assert mu.dtype == torch.float32 and tuple(mu.shape) == (B, 2)
+        assert eps is None or tuple(eps.shape) == (B, 2)
         act = torch.empty_like(mu) if act is None else act
         logp = torch.empty(B, device=mu.device) if logp is None else logp
-        check(lib().aslam_policy_sample(self.h, _p(params), _p(mu), _p(eps), B, _p(act), _p(logp), _stream()))
+        check(lib().aslam_policy_sample(self.h, _p(params), _p(mu), _p(eps), int(seed), int(counter), B, _p(act),
+                                        _p(logp), _stream()))
         return act, logp
 
 
@@ -156,6 +162,14 @@ def gather_rows(src, idx, out=None):
         return out
     row_bytes = src[0].numel() * src.element_size()
     check(lib().aslam_gather_rows(_p(src), row_bytes, _p(idx), n, _p(out), _stream()))
+    return out
+
+
+def permutation(n: int, seed: int, counter: int, out=None, device="cuda"):
+    """Keyed permutation of [0, n) (int32 [n], out[j] = image of j) from the library's generator."""
+    out = torch.empty(n, dtype=torch.int32, device=device) if out is None else out
+    assert out.dtype == torch.int32 and out.numel() == n and (n == 0 or out.is_cuda)
+    check(lib().aslam_permutation(int(n), int(seed), int(counter), _p(out) if n else None, _stream()))
     return out
 
 

@@ -18,15 +18,16 @@ backpropagation through time, starting from the state each robot had entering th
 
 Every stage runs in the library's kernels; torch provides device memory, the stream, the
 gradient accumulator's `zero_()` fill and a few small device copies (recurrent bookkeeping).
-Random draws (odometry noise, action noise, minibatch permutations) are passed in, so an iteration
-is deterministic given its inputs.
+Random draws come from the library's counter-based generator inside the kernels that use them: the
+env step's odometry (and range) noise under the env's own key, the action samples under (seed,
+iteration * (T + 1) + t) and one minibatch permutation per epoch under (seed, iteration * epochs + e),
+so an iteration is deterministic given the trainer's seed and iteration count.
 """
 from __future__ import annotations
 
-import numpy as np
 import torch
 
-from .policy import Policy, adam, gae
+from .policy import Policy, adam, gae, permutation
 
 
 class PPOTrainer:
@@ -55,7 +56,11 @@ class PPOTrainer:
         self.m = torch.zeros_like(params)
         self.v = torch.zeros_like(params)
         self.step_count = 0
+        self.seed = int(seed)
+        self.iters = 0                                   # iterations run (counter of the draws)
         T, n, R = self.T, self.n, self.R
+        self.units = n if self.recurrent else self.S     # what a minibatch permutation shuffles
+        self.perm = torch.zeros(self.units, dtype=torch.int32, device=dev)
         # rollout storage (time-major)
         self.crop = torch.zeros((T + 1, n, crop, crop), dtype=torch.int16, device=dev)
         self.scan = torch.zeros((T + 1, n, R), device=dev)
@@ -75,34 +80,28 @@ class PPOTrainer:
             self.h_boot = torch.zeros((n, 256), device=dev)       # the bootstrap step's state (unused)
             self.first = torch.ones((T + 1, n), dtype=torch.uint8, device=dev)   # episode starts per step
 
-    def draws(self, iterations: int, seed: int):
-        """Seeded synthetic randomness for `iterations` iterations: step noise [I,T,n,G], action noise
-        [I,T,n,2] and one permutation per epoch [I,epochs,*] (int32) of the T*n samples, or with a
-        recurrent policy of the n robots."""
-        rng = np.random.default_rng([seed, 77])
-        I, T, n = iterations, self.T, self.n
-        dev = self.params.device
-        noise = torch.from_numpy(rng.standard_normal((I, T, n, self.env.G), dtype=np.float32)).to(dev)
-        eps = torch.from_numpy(rng.standard_normal((I, T, n, 2), dtype=np.float32)).to(dev)
-        units = n if self.recurrent else self.S
-        perm = np.stack([np.stack([rng.permutation(units) for _ in range(self.epochs)]) for _ in range(I)])
-        return noise, eps, torch.from_numpy(perm.astype(np.int32)).to(dev)
+    def _shuffle(self, it: int, e: int) -> torch.Tensor:
+        """The permutation of epoch e of iteration `it` (library generator, into self.perm)."""
+        return permutation(self.units, self.seed, it * self.epochs + e, out=self.perm)
 
-    def iteration(self, noise: torch.Tensor, eps: torch.Tensor, perm: torch.Tensor) -> None:
+    def iteration(self) -> None:
         """One rollout of T steps and `epochs` update passes (all launches on the current stream)."""
+        it = self.iters
+        self.iters += 1
         if self.recurrent:
-            return self._iteration_recurrent(noise, eps, perm)
-        env, pol, p = self.env, self.policy, self.params
+            return self._iteration_recurrent(it)
+        env, pol, p, sd = self.env, self.policy, self.params, self.seed
+        c0 = it * (self.T + 1)
         pol.prepare(p)   # the parameters are fixed during the rollout
         for t in range(self.T):
             env.observe(self.ranges, self.crop[t], self.scan[t], self.state[t])
-            pol.act(p, self.crop[t], self.scan[t], self.state[t], eps[t], self.value[t], self.act[t], self.logp[t],
-                    prepared=True)
-            env.step(self.act[t], noise[t], self.ranges, self.reward[t], self.done[t])
+            pol.act(p, self.crop[t], self.scan[t], self.state[t], None, self.value[t], self.act[t], self.logp[t],
+                    prepared=True, seed=sd, counter=c0 + t)
+            env.step(self.act[t], None, self.ranges, self.reward[t], self.done[t])
             env.reset(self.world, self.start, mask=self.done[t])
         env.observe(self.ranges, self.crop[self.T], self.scan[self.T], self.state[self.T])
-        pol.act(p, self.crop[self.T], self.scan[self.T], self.state[self.T], eps[self.T - 1], self.value[self.T],
-                self.act_boot, self.logp_boot, prepared=True)
+        pol.act(p, self.crop[self.T], self.scan[self.T], self.state[self.T], None, self.value[self.T],
+                self.act_boot, self.logp_boot, prepared=True, seed=sd, counter=c0 + self.T)
         adv, ret = gae(self.reward, self.value[:self.T].contiguous(), self.done, self.value[self.T],
                        self.gamma, self.lam)
         flat = {
@@ -115,9 +114,10 @@ class PPOTrainer:
             "ret": ret.reshape(self.S),
         }
         for e in range(self.epochs):
+            perm = self._shuffle(it, e)
             for k in range(self.n_mb):
                 lo = k * self.mb
-                idx = perm[e, lo:min(self.S, lo + self.mb)]
+                idx = perm[lo:min(self.S, lo + self.mb)]
                 self.grads.zero_()
                 # the minibatch is the rows idx of the rollout arrays: the kernels read them in place
                 pol.backward(p, flat["crop"], flat["scan"], flat["state"], flat["act"], flat["logp"], flat["adv"],
@@ -125,27 +125,29 @@ class PPOTrainer:
                 self.step_count += 1
                 adam(p, self.grads, self.m, self.v, self.step_count, lr=self.lr)
 
-    def _iteration_recurrent(self, noise: torch.Tensor, eps: torch.Tensor, perm: torch.Tensor) -> None:
-        env, pol, p, T = self.env, self.policy, self.params, self.T
+    def _iteration_recurrent(self, it: int) -> None:
+        env, pol, p, T, sd = self.env, self.policy, self.params, self.T, self.seed
+        c0 = it * (T + 1)
         pol.prepare(p)
         self.h0.copy_(self.h)
         self.first[0].copy_(self.first[T])     # episode starts carried over from the last rollout's end
         for t in range(T):
             env.observe(self.ranges, self.crop[t], self.scan[t], self.state[t])
-            pol.act_rnn(p, self.crop[t], self.scan[t], self.state[t], self.h, self.first[t], eps[t], self.value[t],
-                        self.act[t], self.logp[t], h_out=self.h, prepared=True)
-            env.step(self.act[t], noise[t], self.ranges, self.reward[t], self.done[t])
+            pol.act_rnn(p, self.crop[t], self.scan[t], self.state[t], self.h, self.first[t], None, self.value[t],
+                        self.act[t], self.logp[t], h_out=self.h, prepared=True, seed=sd, counter=c0 + t)
+            env.step(self.act[t], None, self.ranges, self.reward[t], self.done[t])
             env.reset(self.world, self.start, mask=self.done[t])
             self.first[t + 1].copy_(self.done[t])
         env.observe(self.ranges, self.crop[T], self.scan[T], self.state[T])
-        pol.act_rnn(p, self.crop[T], self.scan[T], self.state[T], self.h, self.first[T], eps[T - 1], self.value[T],
-                    self.act_boot, self.logp_boot, h_out=self.h_boot, prepared=True)
+        pol.act_rnn(p, self.crop[T], self.scan[T], self.state[T], self.h, self.first[T], None, self.value[T],
+                    self.act_boot, self.logp_boot, h_out=self.h_boot, prepared=True, seed=sd, counter=c0 + T)
         adv, ret = gae(self.reward, self.value[:T].contiguous(), self.done, self.value[T], self.gamma, self.lam)
         first = self.first[:T]
         for e in range(self.epochs):
+            perm = self._shuffle(it, e)
             for k in range(self.n_mb):
                 lo = k * self.mb
-                robots = perm[e, lo:min(self.n, lo + self.mb)]
+                robots = perm[lo:min(self.n, lo + self.mb)]
                 self.grads.zero_()
                 pol.backward_seq(p, self.crop[:T], self.scan[:T], self.state[:T], self.h0, first, self.act,
                                  self.logp, adv, ret, robots, self.grads, self.loss)

@@ -17,7 +17,9 @@ class Pair:
     """The same robots, stepped by the C-ABI library (GPU) and by the CPU oracle."""
 
     def __init__(self, name: str, seed: int, robots=None, exec_kw=None, params_over=None, steps: int = 100,
-                 oracle: bool = True):
+                 oracle: bool = True, own_draws: bool = False):
+        """own_draws: both sides take the step's normals from their own counter-based generators
+        (params['noise_seed']) instead of the host-drawn rows."""
         import torch
 
         from oracle import oracle as O
@@ -58,6 +60,7 @@ class Pair:
         self.ranges = torch.zeros((self.n, self.R), dtype=torch.float32, device=dev)
         self.reward = torch.zeros(self.n, dtype=torch.float32, device=dev)
         self.done = torch.zeros(self.n, dtype=torch.uint8, device=dev)
+        self.own = own_draws
         self.t = 0
         self.cum = np.zeros((self.n, 3), np.int64)   # oracle work counters since reset
 
@@ -74,10 +77,11 @@ class Pair:
             self.cum[m.astype(bool)] = 0
 
     def step(self):
-        o = self.orc.step(self.A[self.t], self.G[self.t]) if self.orc is not None else None
+        g = None if self.own else self.G[self.t]
+        o = self.orc.step(self.A[self.t], g) if self.orc is not None else None
         if o is not None:
             self.cum += o.counters[:, [2, 0, 1]]
-        self.env.step(self.dA[self.t], self.dG[self.t], self.ranges, self.reward, self.done)
+        self.env.step(self.dA[self.t], None if self.own else self.dG[self.t], self.ranges, self.reward, self.done)
         self.t += 1
         return o
 
