@@ -249,6 +249,22 @@ int aslam_policy_forward(aslam_policy* pol, const float* params_dev, const int16
                          const float* state_dev, int32_t batch, float* mu_dev, float* value_dev,
                          aslam_stream_t stream);
 
+/* Forward pass that allocates nothing, for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, hosts that forbid hipMalloc).  Same kernels and results as
+ * aslam_policy_forward (bit for bit) without a handle: params_dev is the feed-forward layout for
+ * n_scan, inputs and outputs as aslam_policy_forward.  What the forward stages between its kernels
+ * (weight copies, FC1 input rows, split-K partial sums) lives in one static device array of the
+ * library, sized for n_scan <= 720 and batch <= 256 (about 18 MB per GPU, held until the process ends;
+ * the first call on a device looks up its address, no allocation).  Every call on a GPU shares that
+ * array: calls that overlap on one GPU (other streams, other host threads) race and must be ordered by
+ * the caller.  ASL_EINVAL on NULL pointers, n_scan outside [1, 720] or batch outside [1, 256]. */
+int aslam_policy_forward_noalloc(const float* params_dev, int32_t n_scan, const int16_t* crop_dev,
+                                 const float* scan_dev, const float* state_dev, int32_t batch, float* mu_dev,
+                                 float* value_dev, aslam_stream_t stream);
+/* The limits of aslam_policy_forward_noalloc (largest n_scan and batch, written if not NULL); returns
+ * the size of its static device array in bytes. */
+int64_t aslam_policy_noalloc_limits(int32_t* max_scan, int32_t* max_batch);
+
 /* BF16 copies of the weights that the forward reads (FC1 and FC2), formed
  * from params_dev into the handle.  aslam_policy_forward, _act (prepared = 0)
  * and _backward form them themselves; a caller whose parameters do not change

@@ -6,7 +6,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
+#include <vector>
 
 #include "aslam.h"
 #include "policy_kernels.h"
@@ -301,6 +303,89 @@ int aslam_policy_forward(aslam_policy* P, const float* params, const int16_t* cr
   if (batch < 1 || batch > P->max_b) return pfail(ASL_EINVAL, "batch must be in [1, max_batch]");
   if (P->rec) return pfail(ASL_EINVAL, "recurrent policy: use aslam_policy_act_rnn");
   return act_core(P, params, false, crop, scan, state, batch, false, ActDraws{nullptr, 0, 0}, mu, value, nullptr,
+                  nullptr, (hipStream_t)stream);
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ forward without allocation
+//
+// aslam_policy_forward_noalloc keeps what the forward stages between its kernels (the BF16 weight
+// copies, the encoder's weight fragments, the FC1 input rows, FC1's split-K partial sums and the
+// hidden rows) in one file-scope device array instead of a handle's allocations.  Its layout is fixed
+// for the largest scan and batch it accepts.  Host code never passes the array's name to a kernel:
+// the device address is looked up once per device with hipGetSymbolAddress and kept.
+namespace {
+constexpr int64_t kNoAllocMaxScan = 720;
+constexpr int64_t kNoAllocMaxBatch = 256;
+constexpr int64_t kNoAllocK1p = (kFeat + kNoAllocMaxScan + 12 + 7) / 8 * 8;
+constexpr int64_t align256(int64_t v) { return (v + 255) / 256 * 256; }
+constexpr int64_t kNaW1b = 0;
+constexpr int64_t kNaW2b = kNaW1b + align256(2 * kHid * kNoAllocK1p);
+constexpr int64_t kNaFrag = kNaW2b + align256(2 * kHid * kHid);
+constexpr int64_t kNaX = kNaFrag + align256(16 * 64 * (kConvFrags + kConvPhaseFrags));
+constexpr int64_t kNaH1 = kNaX + align256(2 * kNoAllocMaxBatch * kNoAllocK1p);
+constexpr int64_t kNaPart = kNaH1 + align256(2 * kNoAllocMaxBatch * kHid);
+constexpr int64_t kNaBytes = kNaPart + align256(4 * 32 * kNoAllocMaxBatch * kHid);   // at most 32 K slices
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNaBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+std::vector<unsigned char*> g_scratch_ptr;   // per device: the array's device address, looked up once
+
+int scratch_for_current_device(unsigned char** out) {
+  int dev = 0;
+  PCHK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if ((int)g_scratch_ptr.size() <= dev) g_scratch_ptr.resize(dev + 1, nullptr);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    PCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return pfail(ASL_EHIP, "hipGetSymbolAddress returned no address for the forward's scratch");
+    g_scratch_ptr[dev] = static_cast<unsigned char*>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return ASL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t aslam_policy_noalloc_limits(int32_t* max_scan, int32_t* max_batch) {
+  if (max_scan) *max_scan = (int32_t)kNoAllocMaxScan;
+  if (max_batch) *max_batch = (int32_t)kNoAllocMaxBatch;
+  return kNaBytes;
+}
+
+int aslam_policy_forward_noalloc(const float* params, int32_t n_scan, const int16_t* crop, const float* scan,
+                                 const float* state, int32_t batch, float* mu, float* value, aslam_stream_t stream) {
+  if (!params || !crop || !scan || !state || !mu || !value) return pfail(ASL_EINVAL, "null argument");
+  if (n_scan < 1 || n_scan > kNoAllocMaxScan)
+    return pfail(ASL_EINVAL, "forward_noalloc: n_scan must be in [1, " + std::to_string(kNoAllocMaxScan) + "]");
+  if (batch < 1 || batch > kNoAllocMaxBatch)
+    return pfail(ASL_EINVAL, "forward_noalloc: batch must be in [1, " + std::to_string(kNoAllocMaxBatch) +
+                                 "] (the scratch array is sized for that)");
+  unsigned char* base = nullptr;
+  int rc = scratch_for_current_device(&base);
+  if (rc) return rc;
+  // a handle on the stack whose workspaces are views of the scratch array: the same kernels as
+  // aslam_policy_forward, in the same order, with the same split of FC1's K
+  aslam_policy P{};
+  P.cfg.n_scan = n_scan;
+  P.cfg.max_batch = batch;
+  P.off = offsets(n_scan);
+  P.max_b = batch;
+  P.k1p = (P.off.k1 + 7) / 8 * 8;
+  P.w1b = reinterpret_cast<uint16_t*>(base + kNaW1b);
+  P.w2b = reinterpret_cast<uint16_t*>(base + kNaW2b);
+  P.cfrag = reinterpret_cast<uint4*>(base + kNaFrag);
+  P.x = reinterpret_cast<uint16_t*>(base + kNaX);
+  P.h1 = reinterpret_cast<uint16_t*>(base + kNaH1);
+  P.part = reinterpret_cast<float*>(base + kNaPart);
+  return act_core(&P, params, false, crop, scan, state, batch, false, ActDraws{nullptr, 0, 0}, mu, value, nullptr,
                   nullptr, (hipStream_t)stream);
 }
 
