@@ -383,6 +383,15 @@ int aslam_gather_rows(const void* src_dev, int64_t row_bytes, const int32_t* idx
  * pose's covariance.  The paper gives the method but not its
  * constants or exact rules; the rules below are this library's reading of it. */
 
+/* The backbone's handle: the 46080-entry direction table (cos and sin of 2 pi k / 46080 rounded to
+ * Q14) on the device current at create (180 KB).  Created and destroyed outside any stream capture;
+ * the scan-matching and integration calls only read it, so they allocate nothing and never
+ * synchronise (they can be captured into a HIP graph).  Errors: ASL_EINVAL (NULL out), ASL_ENOMEM,
+ * ASL_EHIP.  A call with a handle of another device returns ASL_ESTATE. */
+typedef struct aslam_slam aslam_slam;
+int aslam_slam_create(aslam_slam** out);
+int aslam_slam_destroy(aslam_slam* slam);
+
 typedef struct {
   int32_t W;          /* translation half-width of the candidate lattice, in steps, 0..8 */
   int32_t V;          /* heading half-width, in steps, 0..8 */
@@ -409,8 +418,8 @@ typedef struct {
  * memory; results do not depend on it).
  * Device arrays are not checked: the caller guarantees grids inside belief_dev, 0 <= rho_q < 2^31.
  * ASL_EINVAL on NULL pointers, n < 0 or a config outside the ranges above, or (2V + 1) R > 8192. */
-int aslam_csm_match(const int16_t* belief_dev, const int64_t* cell_off_dev, const int32_t* side_dev,
-                    int32_t max_side, int32_t n, const int32_t* pose_q_dev, const int32_t* rho_q_dev, int32_t R,
+int aslam_csm_match(const aslam_slam* slam, const int16_t* belief_dev, const int64_t* cell_off_dev,
+                    const int32_t* side_dev, int32_t max_side, int32_t n, const int32_t* pose_q_dev, const int32_t* rho_q_dev, int32_t R,
                     const int32_t* a_off_dev, const aslam_csm_config* cfg, int32_t* out_dev, aslam_stream_t stream);
 
 /* The scan factor of a match (Sec. III-D: an absolute pose measurement whose information is scaled
@@ -435,22 +444,19 @@ int aslam_csm_factor(const int32_t* match_dev, const int32_t* pose_q_dev, int32_
  * Visited cells are MISS; the last cell of a ray with a return that stopped at its range is HIT (HIT
  * beats MISS).  Each coded cell gets one add, L <- clamp(L + floor((w_q l + 128) / 256), -l_clamp,
  * l_clamp), l = l_hit or l_miss (log-odds units of the grid).  An aligned position outside the grid
- * leaves it unchanged.  coded_dev int32 [n] (may be NULL): coded cells per robot (-1: side above 65536,
+ * leaves it unchanged.  coded_dev int32 [n] (may be NULL): coded cells per robot (-1: side above 32768,
  * grid left unchanged).  max_side: the largest side (a host value) sizes the LDS bitmaps so that such a
  * grid is one band of rows (at most 64 KB; larger grids take several bands; results do not depend on
  * it).  The result does not depend on ray order.  Device arrays are not checked (the caller guarantees
  * grids inside belief_dev).  ASL_EINVAL on NULL pointers, n < 0, max_side < 0, R outside [1, 65536],
  * rmax_q < 0, l_clamp outside [1, 32767], increments outside [-32767, 32767], or, with a
  * match, a NULL cfg, steps outside aslam_csm_config's ranges or l_max <= 0. */
-int aslam_csm_integrate(int16_t* belief_dev, const int64_t* cell_off_dev, const int32_t* side_dev, int32_t n,
+int aslam_csm_integrate(const aslam_slam* slam, int16_t* belief_dev, const int64_t* cell_off_dev,
+                        const int32_t* side_dev, int32_t n,
                         const int32_t* pose_q_dev, const int32_t* rho_q_dev, int32_t R, const int32_t* a_off_dev,
                         int32_t max_side, int32_t rmax_q, const int32_t* match_dev, const aslam_csm_config* cfg,
                         double l_max, int32_t l_hit, int32_t l_miss, int32_t l_clamp, int32_t* coded_dev,
                         aslam_stream_t stream);
-
-/* Doubles of workspace a caller may pass to aslam_fixedlag_solve for n windows of L poses (21 n L);
- * -1 on bad sizes.  The solver keeps its workspace in LDS and does not touch the buffer. */
-int64_t aslam_fixedlag_work_doubles(int32_t n, int32_t L);
 
 /* Fixed-lag pose graph (Sec. III-D; the minimisation of the weighted residuals and the covariance
  * of the newest pose as the last block of the inverse Gauss-Newton Hessian), n windows of L poses in
@@ -461,11 +467,11 @@ int64_t aslam_fixedlag_work_doubles(int32_t n, int32_t L);
  * be NULL when L = 1); scan factors scan_dev [n,L,6] (measurement; information diagonal, all zero = no
  * factor).  From x0_dev [n,L,3] it takes `iters` Gauss-Newton steps (analytic Jacobians, block
  * elimination of the block-tridiagonal normal equations) into x_dev [n,L,3], then writes the newest
- * pose's covariance, formed at the result, to cov_dev [n,3,3].  work_dev: unused, may be NULL.
- * ASL_EINVAL on NULL pointers (other than work_dev), n < 0, L outside [1, 64] or
+ * pose's covariance, formed at the result, to cov_dev [n,3,3].
+ * ASL_EINVAL on NULL pointers, n < 0, L outside [1, 64] or
  * iters outside [0, 100].  A singular window (no prior information) gives non-finite results. */
 int aslam_fixedlag_solve(int32_t n, int32_t L, const double* x0_dev, const double* prior_dev, const double* odo_dev,
-                         const double* scan_dev, int32_t iters, double* x_dev, double* cov_dev, double* work_dev,
+                         const double* scan_dev, int32_t iters, double* x_dev, double* cov_dev,
                          aslam_stream_t stream);
 
 /* ------------------------------------------------------------------ misc */

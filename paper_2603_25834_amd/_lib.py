@@ -100,13 +100,15 @@ SIGNATURES = {
     "aslam_gae": (ctypes.c_int, [_P, _P, _P, _P, _I32, _I32, ctypes.c_float, ctypes.c_float, _P, _P, _P]),
     "aslam_adam": (ctypes.c_int, [_P, _P, _P, _P, _I64, _I32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                   ctypes.c_float, _P]),
-    "aslam_csm_match": (ctypes.c_int, [_P, _P, _P, _I32, _I32, _P, _P, _I32, _P, ctypes.POINTER(CsmConfig), _P, _P]),
+    "aslam_slam_create": (ctypes.c_int, [ctypes.POINTER(_P)]),
+    "aslam_slam_destroy": (ctypes.c_int, [_P]),
+    "aslam_csm_match": (ctypes.c_int, [_P, _P, _P, _P, _I32, _I32, _P, _P, _I32, _P, ctypes.POINTER(CsmConfig), _P,
+                                       _P]),
     "aslam_csm_factor": (ctypes.c_int, [_P, _P, _I32, ctypes.POINTER(CsmConfig), ctypes.c_double, ctypes.c_double,
                                         ctypes.c_double, ctypes.c_double, _P, _P, _P]),
-    "aslam_fixedlag_work_doubles": (_I64, [_I32, _I32]),
-    "aslam_csm_integrate": (ctypes.c_int, [_P, _P, _P, _I32, _P, _P, _I32, _P, _I32, _I32, _P, ctypes.POINTER(CsmConfig),
+    "aslam_csm_integrate": (ctypes.c_int, [_P, _P, _P, _P, _I32, _P, _P, _I32, _P, _I32, _I32, _P, ctypes.POINTER(CsmConfig),
                                             ctypes.c_double, _I32, _I32, _I32, _P, _P]),
-    "aslam_fixedlag_solve": (ctypes.c_int, [_I32, _I32, _P, _P, _P, _P, _I32, _P, _P, _P, _P]),
+    "aslam_fixedlag_solve": (ctypes.c_int, [_I32, _I32, _P, _P, _P, _P, _I32, _P, _P, _P]),
 }
 
 _lib = None

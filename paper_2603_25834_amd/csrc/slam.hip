@@ -18,7 +18,6 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
-#include <mutex>
 #include <string>
 #include <vector>
 
@@ -400,7 +399,7 @@ __global__ void k_csm_factor(const int32_t* __restrict__ match, const int32_t* _
 constexpr int kIntThreads = 512;
 constexpr int kIntLdsMinWords = 4096;    // LDS bitmaps of at least 16 KB: a band holds a row of any side <= 65536
 constexpr int kIntLdsMaxWords = 16384;   // and at most 64 KB
-constexpr int kIntMaxSide = 65536;
+constexpr int kIntMaxSide = 32768;   // bit indices (row offset x row bits + column) stay below 2^31
 constexpr int kIntInFlight = 4;          // octets (8 cells, 16 bytes) each thread keeps in flight in the apply pass
 constexpr int kIntSortMax = 2048;        // rays are ordered by walk length when R <= this
 constexpr int kIntBins = 64;             // length classes of 8 steps
@@ -889,35 +888,17 @@ __global__ __launch_bounds__(kLagThreads) void k_fixedlag(int L, const double* _
   for (int e = lane; e < 3 * L; e += kLagThreads) xout[(int64_t)r * L * 3 + e] = sx[e];
 }
 
-// ------------------------------------------------------------------ heading table (per device)
+// ------------------------------------------------------------------ heading table
 
-std::mutex g_tab_mu;
-std::vector<int32_t*> g_tab;   // per device, built once
-
-int dirtab_for_current_device(const int32_t** out) {
-  int dev = 0;
-  SCHK(hipGetDevice(&dev));
-  std::lock_guard<std::mutex> lk(g_tab_mu);
-  if ((int)g_tab.size() <= dev) g_tab.resize(dev + 1, nullptr);
-  if (!g_tab[dev]) {
-    std::vector<int32_t> t(kNang);
-    for (int k = 0; k < kNang; ++k) {
-      const double ang = (2.0 * M_PI * (double)k) / (double)kNang;
-      const int32_t c = (int32_t)std::llround(std::cos(ang) * (double)kDirOne);
-      const int32_t s = (int32_t)std::llround(std::sin(ang) * (double)kDirOne);
-      t[k] = (int32_t)(((uint32_t)c & 0xffffu) | ((uint32_t)s << 16));
-    }
-    int32_t* d = nullptr;
-    SCHK(hipMalloc(&d, sizeof(int32_t) * kNang));
-    const hipError_t e = hipMemcpy(d, t.data(), sizeof(int32_t) * kNang, hipMemcpyHostToDevice);
-    if (e != hipSuccess) {
-      (void)hipFree(d);
-      return sfail(ASL_EHIP, hipGetErrorString(e));
-    }
-    g_tab[dev] = d;
+// Direction of heading step k, cos and sin of 2 pi k / 46080 rounded to Q14, packed (cos low, sin high).
+void build_dirtab(std::vector<int32_t>& t) {
+  t.resize(kNang);
+  for (int k = 0; k < kNang; ++k) {
+    const double ang = (2.0 * M_PI * (double)k) / (double)kNang;
+    const int32_t c = (int32_t)std::llround(std::cos(ang) * (double)kDirOne);
+    const int32_t sn = (int32_t)std::llround(std::sin(ang) * (double)kDirOne);
+    t[k] = (int32_t)(((uint32_t)c & 0xffffu) | ((uint32_t)sn << 16));
   }
-  *out = g_tab[dev];
-  return ASL_OK;
 }
 
 int check_csm_config(const aslam_csm_config* c, int32_t R) {
@@ -933,9 +914,55 @@ int check_csm_config(const aslam_csm_config* c, int32_t R) {
 
 }  // namespace
 
+// The backbone's handle: the direction table on the device it was created on.
+struct aslam_slam {
+  int device = -1;
+  int32_t* tab = nullptr;
+};
+
+namespace {
+
+// The handle's table, checked to belong to the current device (a host query: no allocation, no sync).
+int slam_table(const aslam_slam* h, const int32_t** tab) {
+  if (!h || !h->tab) return sfail(ASL_EINVAL, "slam handle is NULL");
+  int dev = 0;
+  SCHK(hipGetDevice(&dev));
+  if (dev != h->device) return sfail(ASL_ESTATE, "slam handle was created on another device");
+  *tab = h->tab;
+  return ASL_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
-int aslam_csm_match(const int16_t* belief_dev, const int64_t* cell_off_dev, const int32_t* side_dev,
+int aslam_slam_create(aslam_slam** out) {
+  if (!out) return sfail(ASL_EINVAL, "out is NULL");
+  *out = nullptr;
+  aslam_slam* h = new (std::nothrow) aslam_slam();
+  if (!h) return sfail(ASL_ENOMEM, "host allocation failed");
+  hipError_t e = hipGetDevice(&h->device);
+  std::vector<int32_t> t;
+  build_dirtab(t);
+  if (e == hipSuccess) e = hipMalloc(&h->tab, sizeof(int32_t) * kNang);
+  if (e == hipSuccess) e = hipMemcpy(h->tab, t.data(), sizeof(int32_t) * kNang, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    if (h->tab) (void)hipFree(h->tab);
+    delete h;
+    return sfail(e == hipErrorOutOfMemory ? ASL_ENOMEM : ASL_EHIP, hipGetErrorString(e));
+  }
+  *out = h;
+  return ASL_OK;
+}
+
+int aslam_slam_destroy(aslam_slam* h) {
+  if (!h) return sfail(ASL_EINVAL, "slam handle is NULL");
+  if (h->tab) (void)hipFree(h->tab);
+  delete h;
+  return ASL_OK;
+}
+
+int aslam_csm_match(const aslam_slam* slam, const int16_t* belief_dev, const int64_t* cell_off_dev, const int32_t* side_dev,
                     int32_t max_side, int32_t n, const int32_t* pose_q_dev, const int32_t* rho_q_dev, int32_t R,
                     const int32_t* a_off_dev, const aslam_csm_config* cfg, int32_t* out_dev, aslam_stream_t stream) {
   int rc = check_csm_config(cfg, R);
@@ -946,7 +973,7 @@ int aslam_csm_match(const int16_t* belief_dev, const int64_t* cell_off_dev, cons
   if (!belief_dev || !cell_off_dev || !side_dev || !pose_q_dev || !rho_q_dev || !a_off_dev || !out_dev)
     return sfail(ASL_EINVAL, "null argument to csm_match");
   const int32_t* tab = nullptr;
-  rc = dirtab_for_current_device(&tab);
+  rc = slam_table(slam, &tab);
   if (rc) return rc;
   const int ncand = (2 * cfg->V + 1) * (2 * cfg->W + 1) * (2 * cfg->W + 1);
   const int64_t off_bytes = (int64_t)(2 * cfg->V + 1) * R * (int64_t)sizeof(int2);
@@ -995,7 +1022,7 @@ int aslam_csm_factor(const int32_t* match_dev, const int32_t* pose_q_dev, int32_
   return ASL_OK;
 }
 
-int aslam_csm_integrate(int16_t* belief_dev, const int64_t* cell_off_dev, const int32_t* side_dev, int32_t n,
+int aslam_csm_integrate(const aslam_slam* slam, int16_t* belief_dev, const int64_t* cell_off_dev, const int32_t* side_dev, int32_t n,
                         const int32_t* pose_q_dev, const int32_t* rho_q_dev, int32_t R, const int32_t* a_off_dev,
                         int32_t max_side, int32_t rmax_q, const int32_t* match_dev, const aslam_csm_config* cfg,
                         double l_max, int32_t l_hit, int32_t l_miss, int32_t l_clamp, int32_t* coded_dev,
@@ -1019,7 +1046,7 @@ int aslam_csm_integrate(int16_t* belief_dev, const int64_t* cell_off_dev, const 
   if (!belief_dev || !cell_off_dev || !side_dev || !pose_q_dev || !rho_q_dev || !a_off_dev)
     return sfail(ASL_EINVAL, "null argument to csm_integrate");
   const int32_t* tab = nullptr;
-  const int rc = dirtab_for_current_device(&tab);
+  const int rc = slam_table(slam, &tab);
   if (rc) return rc;
   // bitmaps of one band holding the largest grid whole, within [16 KB, 64 KB]
   const int64_t nw_max = ((int64_t)std::min(max_side, kIntMaxSide) + 31) >> 5;
@@ -1035,20 +1062,14 @@ int aslam_csm_integrate(int16_t* belief_dev, const int64_t* cell_off_dev, const 
   return ASL_OK;
 }
 
-int64_t aslam_fixedlag_work_doubles(int32_t n, int32_t L) {
-  if (n < 0 || L < 1) return -1;
-  return (int64_t)n * L * 21;
-}
-
 int aslam_fixedlag_solve(int32_t n, int32_t L, const double* x0_dev, const double* prior_dev, const double* odo_dev,
-                         const double* scan_dev, int32_t iters, double* x_dev, double* cov_dev, double* work_dev,
+                         const double* scan_dev, int32_t iters, double* x_dev, double* cov_dev,
                          aslam_stream_t stream) {
   if (n < 0 || L < 1 || L > kLagMaxL || iters < 0 || iters > 100)
     return sfail(ASL_EINVAL, "need n >= 0, 1 <= L <= 64, 0 <= iters <= 100");
   if (n == 0) return ASL_OK;
   if (!x0_dev || !prior_dev || (L > 1 && !odo_dev) || !scan_dev || !x_dev || !cov_dev)
     return sfail(ASL_EINVAL, "null argument to fixedlag_solve");
-  (void)work_dev;   // the windows are solved in LDS
   const int bytes = (int)(sizeof(double) * 45 * L);
   k_fixedlag<<<n, kLagThreads, bytes, (hipStream_t)stream>>>(L, x0_dev, prior_dev, odo_dev, scan_dev, iters, x_dev,
                                                              cov_dev);

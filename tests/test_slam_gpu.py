@@ -243,9 +243,9 @@ def test_integrate_many_rays_and_no_count():
     # device copies held by names for the raw call (a temporary could be freed and its memory reused by the
     # next argument before the launch)
     co2, sd2, po2, rh2, ao2 = d(cell_off), d(side), d(pose), d(rho), d(a_off)
-    _lib.check(_lib.lib().aslam_csm_integrate(slam._p(bel2), slam._p(co2), slam._p(sd2), len(sides), slam._p(po2),
-                                              slam._p(rh2), R, slam._p(ao2), 96, 50 * 65536, None, None, 1.0, 218,
-                                              -102, 896, None, slam._stream()))
+    _lib.check(_lib.lib().aslam_csm_integrate(slam.handle().h, slam._p(bel2), slam._p(co2), slam._p(sd2), len(sides),
+                                              slam._p(po2), slam._p(rh2), R, slam._p(ao2), 96, 50 * 65536, None, None,
+                                              1.0, 218, -102, 896, None, slam._stream()))
     torch.cuda.synchronize()
     got, got2, coded = bel.cpu().numpy(), bel2.cpu().numpy(), coded.cpu().numpy()
     for r, s_ in enumerate(sides):
@@ -285,9 +285,13 @@ def test_integrate_full_batch_sampled_and_errors():
         slam.csm_integrate(bel, d(cell_off), d(side), d(pose), d(rho), d(a_off), 65536, 218, -102, 0)
     co, sd, po, rh, ao = d(cell_off), d(side), d(pose), d(rho), d(a_off)
     with pytest.raises(_lib.AslamError):   # a match without a config
-        _lib.check(_lib.lib().aslam_csm_integrate(slam._p(bel), slam._p(co), slam._p(sd), 750, slam._p(po),
-                                                  slam._p(rh), R, slam._p(ao), 256, 65536, slam._p(match), None, 896.0,
-                                                  218, -102, 896, None, slam._stream()))
+        _lib.check(_lib.lib().aslam_csm_integrate(slam.handle().h, slam._p(bel), slam._p(co), slam._p(sd), 750,
+                                                  slam._p(po), slam._p(rh), R, slam._p(ao), 256, 65536, slam._p(match),
+                                                  None, 896.0, 218, -102, 896, None, slam._stream()))
+    with pytest.raises(_lib.AslamError):   # no handle
+        _lib.check(_lib.lib().aslam_csm_integrate(None, slam._p(bel), slam._p(co), slam._p(sd), 750, slam._p(po),
+                                                  slam._p(rh), R, slam._p(ao), 256, 65536, None, None, 896.0, 218,
+                                                  -102, 896, None, slam._stream()))
 
 
 def test_backbone_on_env_state():
@@ -367,3 +371,60 @@ def test_backbone_on_env_state():
         assert np.abs(xg[r] - lag_o[r][0]).max() < 1e-9, r
         assert np.abs(covg[r] - lag_o[r][1]).max() <= 1e-8 * np.abs(lag_o[r][1]).max(), r
     assert sum(coded_o) > 0 and any(w[0] > 0 for w in om_o)
+
+
+def test_backbone_calls_captured_in_one_graph():
+    """Scan matching, the scan factor, the weighted integration and the fixed-lag solve captured in one
+    HIP graph (the calls allocate nothing and never synchronise once the handle exists) and replayed
+    three times, each replay matching on the grids the previous one integrated into: equal bit for bit
+    to the same three rounds launched eagerly."""
+    W, V, sxy, sh, R, L = 4, 5, 65536, 64, 360, 8
+    sides = [256] * 64
+    grids, belief, cell_off, side, pose, rho, a_off = _batch(31, sides, R, W, V, sxy, sh, invalid_p=0.05)
+    # grids biased towards occupied evidence, so the best scores are positive and the weights non-zero
+    belief = np.clip(belief.astype(np.int32) + 400, -896, 896).astype(np.int16)
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    n = len(sides)
+    cfg = slam.csm_config(W, V, sxy, sh)
+    slam.handle()   # created (allocates) before the capture
+    CO, SD, PO, RH, AO = d(cell_off), d(side), d(pose), d(rho), d(a_off)
+    rng = np.random.default_rng(5)
+    x0 = rng.uniform(1.0, 12.0, (n, 1, 3)) + 0.01 * rng.standard_normal((n, L, 3))
+    prior = d(np.concatenate([x0[:, 0], np.full((n, 3), 400.0)], 1))
+    odo = d(np.concatenate([np.zeros((n, L - 1, 3)), np.full((n, L - 1, 3), 2500.0)], 2))
+    X0 = d(x0)
+
+    def make_state():
+        return dict(bel=d(belief), match=torch.empty((n, 6), dtype=torch.int32, device="cuda"),
+                    meas=torch.empty((n, 3), dtype=torch.float64, device="cuda"),
+                    info=torch.empty((n, 3), dtype=torch.float64, device="cuda"),
+                    coded=torch.empty(n, dtype=torch.int32, device="cuda"),
+                    scan=torch.zeros((n, L, 6), dtype=torch.float64, device="cuda"),
+                    x=torch.empty((n, L, 3), dtype=torch.float64, device="cuda"),
+                    cov=torch.empty((n, 3, 3), dtype=torch.float64, device="cuda"))
+
+    def round_(st):
+        slam.csm_match(st["bel"], CO, SD, PO, RH, AO, cfg, out=st["match"], max_side=256)
+        slam.csm_factor(st["match"], PO, cfg, 0.05, 896.0, 0.05, 0.02, meas=st["meas"], info=st["info"])
+        slam.csm_integrate(st["bel"], CO, SD, PO, RH, AO, 200 * 65536, 218, -102, 896, match=st["match"], cfg=cfg,
+                           l_max=896.0, coded=st["coded"], max_side=256)
+        st["scan"][:, -1, :3].copy_(st["meas"])
+        st["scan"][:, -1, 3:].copy_(st["info"])
+        slam.fixedlag_solve(X0, prior, odo, st["scan"], 3, x=st["x"], cov=st["cov"])
+
+    eager, graphed = make_state(), make_state()
+    round_(graphed)        # warm-up round outside the capture, repeated by the eager side
+    round_(eager)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        round_(graphed)
+    for k in range(3):
+        g.replay()
+        round_(eager)
+        torch.cuda.synchronize()
+        for key in ("bel", "match", "coded", "meas", "info", "x", "cov"):
+            assert torch.equal(graphed[key], eager[key]), (k, key)
+    # the rounds changed the grids (the integration ran with non-zero weights on every replay)
+    assert (graphed["info"][:, 0] > 0).sum().item() > n // 2
+    assert not torch.equal(graphed["bel"], d(belief))
