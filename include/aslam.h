@@ -230,6 +230,14 @@ typedef struct {
   float c_entropy;    /* entropy-bonus weight */
   int32_t recurrent;  /* 1: the GRU of Sec. III-F ("Recurrent Layer", 256 units) in place of FC2, layout
                          below; such a handle takes aslam_policy_act_rnn / _backward_seq only */
+  int32_t precision;  /* 0: BF16 operands with FP32 accumulation throughout.  1 (feed-forward only):
+                         split forward -- every operand v of the four forward products (crop, weights,
+                         activations, scan and state) is the pair hi = bf16(v), lo = bf16(v - hi), and
+                         each product is hi*hi + hi*lo + lo*hi on MFMA with FP32 accumulation, so the
+                         ReLU pre-activations are FP32-accurate (the forward and its recomputation in
+                         the backward cost about three times the MFMA work); the backward's products
+                         stay BF16.  This is the mode whose gradients agree with the exact FP64
+                         network to 1e-2 per tensor on random minibatches. */
 } aslam_policy_config;
 
 /* Number of parameters for scan length n_scan (2,264,005 for R = 360), feed-forward layout. */

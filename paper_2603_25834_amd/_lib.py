@@ -137,4 +137,5 @@ def check(rc: int) -> None:
 
 class PolicyConfig(ctypes.Structure):
     _fields_ = [("n_scan", ctypes.c_int32), ("max_batch", ctypes.c_int32), ("clip_eps", ctypes.c_float),
-                ("c_value", ctypes.c_float), ("c_entropy", ctypes.c_float), ("recurrent", ctypes.c_int32)]
+                ("c_value", ctypes.c_float), ("c_entropy", ctypes.c_float), ("recurrent", ctypes.c_int32),
+                ("precision", ctypes.c_int32)]

@@ -22,6 +22,13 @@
 // a1 pixel, one 16-byte LDS read; the weights stay in registers for the
 // workgroup's lifetime.  Each lane then holds four consecutive positions of
 // one output channel, one 8-byte store into a2[b][co*256 + pos].
+//
+// Split precision (PREC): every operand v of both convolutions is carried as
+// two BF16 numbers, hi = bf16(v) and lo = bf16(v - hi) (16 significant bits;
+// the crop L/256 is exact), and each product is hi*hi + hi*lo + lo*hi on
+// MFMA (the lo*lo term is below FP32 resolution of the sum), so the ReLU
+// pre-activations are FP32-accurate and a ReLU sees the sign the exact
+// network gives; the outputs (a1 and the FC1 input) are stored as hi and lo.
 #pragma once
 
 #include "policy_kernels.h"
@@ -48,7 +55,15 @@ __device__ __forceinline__ uint32_t pack_bf16x2(float lo, float hi) {
   return (uint32_t)f2bf(lo) | ((uint32_t)f2bf(hi) << 16);
 }
 
+// hi = bf16(v), or with LO the remainder bf16(v - hi).
+template <bool LO>
+__device__ __forceinline__ uint16_t bf16_part(float v) {
+  const uint16_t h = f2bf(v);
+  return LO ? f2bf(v - bf2f(h)) : h;
+}
+
 // conv1 weights as the A operand: lane supplies W'[co = lane % 16][k = 8 (lane / 16) + j].
+template <bool LO = false>
 __device__ __forceinline__ bf16x8 conv1_weight_frag(const float* w1, int lr, int lg) {
   uint16_t v[8];
 #pragma unroll
@@ -56,7 +71,7 @@ __device__ __forceinline__ bf16x8 conv1_weight_frag(const float* w1, int lr, int
     const int k = 8 * lg + j;
     const int r = k >> 3, c = (k >> 2) & 1, dy = (k >> 1) & 1, dx = k & 1;
     const int ky = 2 * r + dy - 1, kx = 2 * c + dx - 1;
-    v[j] = (lg < 2 && ky >= 0 && kx >= 0) ? f2bf(w1[lr * 9 + ky * 3 + kx]) : (uint16_t)0;
+    v[j] = (lg < 2 && ky >= 0 && kx >= 0) ? bf16_part<LO>(w1[lr * 9 + ky * 3 + kx]) : (uint16_t)0;
   }
   uint4 u;
   u.x = v[0] | ((uint32_t)v[1] << 16);
@@ -67,12 +82,13 @@ __device__ __forceinline__ bf16x8 conv1_weight_frag(const float* w1, int lr, int
 }
 
 // conv2 weights as the B operand: lane supplies W2[k = 32 s + 8 (lane / 16) + j][co], k = tap*16 + ci.
+template <bool LO = false>
 __device__ __forceinline__ bf16x8 conv2_weight_frag(const float* w2, int co, int s, int lg) {
   uint16_t v[8];
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
     const int k = 32 * s + 8 * lg + j, tap = k >> 4, ci = k & 15;
-    v[j] = tap < 9 ? f2bf(w2[(co * kC1 + ci) * 9 + tap]) : (uint16_t)0;
+    v[j] = tap < 9 ? bf16_part<LO>(w2[(co * kC1 + ci) * 9 + tap]) : (uint16_t)0;
   }
   uint4 u;
   u.x = v[0] | ((uint32_t)v[1] << 16);
@@ -85,16 +101,18 @@ __device__ __forceinline__ bf16x8 conv2_weight_frag(const float* w2, int co, int
 // The forward's weight fragments, formed once per parameter update: fragment f < 11 of lane l at
 // frag[64 f + l]; f = 0 is conv1's A operand, f = 1 + 5 nt + s is conv2's B operand for output
 // channels 16 nt .. 16 nt + 15 and k slice s (the values conv1_weight_frag / conv2_weight_frag give).
+// With LO the same fragments of the weights' lo parts, written from frag[64 kConvLoFrag] on.
 constexpr int kConvFrags = 11;
 
+template <bool LO = false>
 __global__ __launch_bounds__(64 * kConvFrags) void k_conv_frags(const float* prm, Offsets o, uint4* frag) {
   const int f = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
   bf16x8 v;
   if (f == 0) {
-    v = conv1_weight_frag(prm + o.c1w, lr, lg);
+    v = conv1_weight_frag<LO>(prm + o.c1w, lr, lg);
   } else {
     const int nt = (f - 1) / 5, s = (f - 1) % 5;
-    v = conv2_weight_frag(prm + o.c2w, 16 * nt + lr, s, lg);
+    v = conv2_weight_frag<LO>(prm + o.c2w, 16 * nt + lr, s, lg);
   }
   frag[threadIdx.x] = __builtin_bit_cast(uint4, v);
 }
@@ -116,10 +134,10 @@ __device__ __forceinline__ void load_crop(const int16_t* src, CropRegs<NT>& r) {
   for (int i = 0; i < CropRegs<NT>::kPer; ++i) r.v[i] = s4[threadIdx.x + i * NT];
 }
 
-// Crop registers into LDS, space-to-depth, as BF16(L / 256).  Block (Y, X)
+// Crop registers into LDS, space-to-depth, as BF16(L / 256) (with LO its lo part).  Block (Y, X)
 // sits at ((Y + 1) * 33 + X + 1) * 4; the row and column of index 0 are the
 // zero padding and are never written here.
-template <int NT>
+template <int NT, bool LO = false>
 __device__ __forceinline__ void store_crop(const CropRegs<NT>& r, uint16_t* s_crop) {
 #pragma unroll
   for (int i = 0; i < CropRegs<NT>::kPer; ++i) {
@@ -132,36 +150,58 @@ __device__ __forceinline__ void store_crop(const CropRegs<NT>& r, uint16_t* s_cr
       const float lo = (float)(int16_t)(w[q] & 0xffff) * (1.0f / 256.0f);
       const float hi = (float)(int16_t)(w[q] >> 16) * (1.0f / 256.0f);
       const int X = (x0 >> 1) + q;
-      *reinterpret_cast<uint32_t*>(s_crop + ((Y + 1) * kBlk + X + 1) * 4 + 2 * dy) = pack_bf16x2(lo, hi);
+      *reinterpret_cast<uint32_t*>(s_crop + ((Y + 1) * kBlk + X + 1) * 4 + 2 * dy) =
+          (uint32_t)bf16_part<LO>(lo) | ((uint32_t)bf16_part<LO>(hi) << 16);
     }
   }
 }
 
+// conv1 window operand of pixel px (lanes with lg >= 2 supply zeros) from a space-to-depth crop.
+__device__ __forceinline__ uint4 conv1_window(const uint16_t* s_crop, int px, int lg) {
+  const int y = px >> 5, x = px & 31;
+  if (lg >= 2) return make_uint4(0u, 0u, 0u, 0u);
+  const uint16_t* q = s_crop + ((y + lg) * kBlk + x) * 4;
+  const uint2 a = *reinterpret_cast<const uint2*>(q);
+  const uint2 c = *reinterpret_cast<const uint2*>(q + 4);
+  return make_uint4(a.x, a.y, c.x, c.y);
+}
+
+// Four ReLU outputs packed as BF16 (hi parts, or with LO the lo parts).
+template <bool LO>
+__device__ __forceinline__ uint2 pack_relu4(const f32x4& acc, const float b[4]) {
+  uint16_t h[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) h[e] = bf16_part<LO>(fmaxf(acc[e] + b[e], 0.0f));
+  return make_uint2((uint32_t)h[0] | ((uint32_t)h[1] << 16), (uint32_t)h[2] | ((uint32_t)h[3] << 16));
+}
+
 // conv1 + ReLU of the staged crop into s_a1 (pixel (y, x) at a1_slot(y, x) * 16): 64 tiles of 16
 // pixels, 16 per wave, taken four at a time so that their operand reads are in flight together.
-__device__ __forceinline__ void conv1_lds(const uint16_t* s_crop, uint16_t* s_a1, const bf16x8& w1f,
-                                          const float b1[4], int wave, int lr, int lg) {
+// PREC: the crop's and the weights' lo parts enter the product too, and a1's lo part goes to s_a1l.
+template <bool PREC>
+__device__ __forceinline__ void conv1_lds(const uint16_t* s_crop, const uint16_t* s_cropl, uint16_t* s_a1,
+                                          uint16_t* s_a1l, const bf16x8& w1f, const bf16x8& w1fl, const float b1[4],
+                                          int wave, int lr, int lg) {
   for (int t0 = wave; t0 < kA1 * kA1 / 16; t0 += 16) {
-    uint4 u[4];
+    uint4 u[4], ul[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int px = (t0 + 4 * i) * 16 + lr, y = px >> 5, x = px & 31;
-      u[i] = make_uint4(0u, 0u, 0u, 0u);
-      if (lg < 2) {
-        const uint16_t* q = s_crop + ((y + lg) * kBlk + x) * 4;
-        const uint2 a = *reinterpret_cast<const uint2*>(q);
-        const uint2 c = *reinterpret_cast<const uint2*>(q + 4);
-        u[i] = make_uint4(a.x, a.y, c.x, c.y);
-      }
+      const int px = (t0 + 4 * i) * 16 + lr;
+      u[i] = conv1_window(s_crop, px, lg);
+      if (PREC) ul[i] = conv1_window(s_cropl, px, lg);
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int px = (t0 + 4 * i) * 16 + lr, y = px >> 5, x = px & 31;
-      const f32x4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1f, __builtin_bit_cast(bf16x8, u[i]),
-                                                               f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
-      const uint32_t lo = pack_bf16x2(fmaxf(acc[0] + b1[0], 0.0f), fmaxf(acc[1] + b1[1], 0.0f));
-      const uint32_t hi = pack_bf16x2(fmaxf(acc[2] + b1[2], 0.0f), fmaxf(acc[3] + b1[3], 0.0f));
-      *reinterpret_cast<uint2*>(s_a1 + a1_slot(y, x) * kC1 + 4 * lg) = make_uint2(lo, hi);
+      f32x4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1f, __builtin_bit_cast(bf16x8, u[i]),
+                                                         f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+      if (PREC) {
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1f, __builtin_bit_cast(bf16x8, ul[i]), acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1fl, __builtin_bit_cast(bf16x8, u[i]), acc, 0, 0, 0);
+      }
+      const int slot = a1_slot(y, x) * kC1 + 4 * lg;
+      *reinterpret_cast<uint2*>(s_a1 + slot) = pack_relu4<false>(acc, b1);
+      if (PREC) *reinterpret_cast<uint2*>(s_a1l + slot) = pack_relu4<true>(acc, b1);
     }
   }
 }
@@ -185,29 +225,43 @@ __device__ __forceinline__ bf16x8 conv2_col_frag(const uint16_t* s_a1, int oy, i
 // is waited on inside a sample (a longer tail, R > 500, reads its remainder directly).
 constexpr int kConvFwdTailPre = 2;   // tail elements per thread held in registers
 
+// The lo fragments of the split-precision path start at fragment kConvLoFrag (after the backward's).
+constexpr int kConvLoFrag = 20;
+
+// PREC: a2lo receives the lo parts of the same row (conv features and the scan / state tail), the
+// products are split as described at the top, and the workgroup holds the crop and a1 twice (87 KB of
+// LDS: one workgroup per CU).
+template <bool PREC>
 __global__ __launch_bounds__(256) void k_conv_fwd(const float* __restrict__ prm, Offsets o,
                                                   const uint4* __restrict__ frag, const int16_t* __restrict__ crop,
                                                   const float* __restrict__ scan, const float* __restrict__ state,
                                                   int R, const int32_t* __restrict__ rows, uint16_t* __restrict__ a2,
-                                                  int64_t lda2, int B) {
-  __shared__ __align__(16) uint16_t s_crop[kCropLds];
-  __shared__ __align__(16) uint16_t s_a1[kA1Lds];
+                                                  uint16_t* __restrict__ a2lo, int64_t lda2, int B) {
+  constexpr int kCopies = PREC ? 2 : 1;
+  __shared__ __align__(16) uint16_t s_crop[kCopies * kCropLds];
+  __shared__ __align__(16) uint16_t s_a1[kCopies * kA1Lds];
+  uint16_t* const s_cropl = s_crop + (PREC ? kCropLds : 0);
+  uint16_t* const s_a1l = s_a1 + (PREC ? kA1Lds : 0);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
   {
     uint4* z = reinterpret_cast<uint4*>(s_crop);
-    for (int i = threadIdx.x; i < kCropLds / 8; i += 256) z[i] = make_uint4(0u, 0u, 0u, 0u);
+    for (int i = threadIdx.x; i < kCopies * kCropLds / 8; i += 256) z[i] = make_uint4(0u, 0u, 0u, 0u);
     z = reinterpret_cast<uint4*>(s_a1);
-    for (int i = threadIdx.x; i < kA1Lds / 8; i += 256) z[i] = make_uint4(0u, 0u, 0u, 0u);
+    for (int i = threadIdx.x; i < kCopies * kA1Lds / 8; i += 256) z[i] = make_uint4(0u, 0u, 0u, 0u);
   }
   const bf16x8 w1f = __builtin_bit_cast(bf16x8, frag[lane]);
+  const bf16x8 w1fl = PREC ? __builtin_bit_cast(bf16x8, frag[64 * kConvLoFrag + lane]) : w1f;
   float b1[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) b1[i] = prm[o.c1b + 4 * lg + i];
-  bf16x8 w2f[2][5];
+  bf16x8 w2f[2][5], w2fl[2][5];
 #pragma unroll
   for (int nt = 0; nt < 2; ++nt)
 #pragma unroll
-    for (int s = 0; s < 5; ++s) w2f[nt][s] = __builtin_bit_cast(bf16x8, frag[64 * (1 + 5 * nt + s) + lane]);
+    for (int s = 0; s < 5; ++s) {
+      w2f[nt][s] = __builtin_bit_cast(bf16x8, frag[64 * (1 + 5 * nt + s) + lane]);
+      if (PREC) w2fl[nt][s] = __builtin_bit_cast(bf16x8, frag[64 * (kConvLoFrag + 1 + 5 * nt + s) + lane]);
+    }
   const float b2[2] = {prm[o.c2b + lr], prm[o.c2b + 16 + lr]};
   const int tail = (int)(lda2 - kFeat);
   auto src = [&](int b) -> int64_t { return rows ? (int64_t)rows[b] : (int64_t)b; };
@@ -229,18 +283,26 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const float* __restrict__ prm,
   __syncthreads();
   for (int b = blockIdx.x; b < B; b += gridDim.x) {
     store_crop<256>(cr, s_crop);
+    if (PREC) store_crop<256, true>(cr, s_cropl);
     uint16_t* row = a2 + (int64_t)b * lda2 + kFeat;
+    uint16_t* rowl = PREC ? a2lo + (int64_t)b * lda2 + kFeat : row;
 #pragma unroll
     for (int i = 0; i < kConvFwdTailPre; ++i) {
       const int j = threadIdx.x + 256 * i;
-      if (j < tail) row[j] = j < R + 12 ? f2bf(tv[i]) : (uint16_t)0;
+      if (j < tail) {
+        row[j] = j < R + 12 ? f2bf(tv[i]) : (uint16_t)0;
+        if (PREC) rowl[j] = j < R + 12 ? bf16_part<true>(tv[i]) : (uint16_t)0;
+      }
     }
-    for (int j = threadIdx.x + 256 * kConvFwdTailPre; j < tail; j += 256)
-      row[j] = j < R + 12 ? f2bf(tail_value(src(b), j)) : (uint16_t)0;
+    for (int j = threadIdx.x + 256 * kConvFwdTailPre; j < tail; j += 256) {
+      const float v = j < R + 12 ? tail_value(src(b), j) : 0.0f;
+      row[j] = f2bf(v);
+      if (PREC) rowl[j] = bf16_part<true>(v);
+    }
     __syncthreads();
     // the next sample's crop and tail are loaded while this one is processed
     if (b + (int)gridDim.x < B) load_sample(b + gridDim.x);
-    conv1_lds(s_crop, s_a1, w1f, b1, wave, lr, lg);
+    conv1_lds<PREC>(s_crop, s_cropl, s_a1, s_a1l, w1f, w1fl, b1, wave, lr, lg);
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < kA2 / 4; ++i) {
@@ -251,14 +313,22 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const float* __restrict__ prm,
         const bf16x8 af = conv2_col_frag(s_a1, oy, lr, s, lg);
         acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, w2f[0][s], acc0, 0, 0, 0);
         acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, w2f[1][s], acc1, 0, 0, 0);
+        if (PREC) {
+          const bf16x8 afl = conv2_col_frag(s_a1l, oy, lr, s, lg);
+          acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, w2fl[0][s], acc0, 0, 0, 0);
+          acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, w2fl[1][s], acc1, 0, 0, 0);
+          acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afl, w2f[0][s], acc0, 0, 0, 0);
+          acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afl, w2f[1][s], acc1, 0, 0, 0);
+        }
       }
-      uint16_t* dst = a2 + (int64_t)b * lda2 + oy * kA2 + 4 * lg;
-      *reinterpret_cast<uint2*>(dst + lr * 256) =
-          make_uint2(pack_bf16x2(fmaxf(acc0[0] + b2[0], 0.0f), fmaxf(acc0[1] + b2[0], 0.0f)),
-                     pack_bf16x2(fmaxf(acc0[2] + b2[0], 0.0f), fmaxf(acc0[3] + b2[0], 0.0f)));
-      *reinterpret_cast<uint2*>(dst + (16 + lr) * 256) =
-          make_uint2(pack_bf16x2(fmaxf(acc1[0] + b2[1], 0.0f), fmaxf(acc1[1] + b2[1], 0.0f)),
-                     pack_bf16x2(fmaxf(acc1[2] + b2[1], 0.0f), fmaxf(acc1[3] + b2[1], 0.0f)));
+      const int64_t off = (int64_t)b * lda2 + oy * kA2 + 4 * lg;
+      const float bb0[4] = {b2[0], b2[0], b2[0], b2[0]}, bb1[4] = {b2[1], b2[1], b2[1], b2[1]};
+      *reinterpret_cast<uint2*>(a2 + off + lr * 256) = pack_relu4<false>(acc0, bb0);
+      *reinterpret_cast<uint2*>(a2 + off + (16 + lr) * 256) = pack_relu4<false>(acc1, bb1);
+      if (PREC) {
+        *reinterpret_cast<uint2*>(a2lo + off + lr * 256) = pack_relu4<true>(acc0, bb0);
+        *reinterpret_cast<uint2*>(a2lo + off + (16 + lr) * 256) = pack_relu4<true>(acc1, bb1);
+      }
     }
     __syncthreads();
   }
@@ -363,6 +433,7 @@ __device__ __forceinline__ bf16x8 phase_weight_frag(const float* w2, int ky, int
 // kConvFrags: fragment kConvFrags + q of lane l at frag[64 (kConvFrags + q) + l], q enumerating the
 // (phase, tap) pairs in phase order (9 in all).
 constexpr int kConvPhaseFrags = 9;
+static_assert(kConvLoFrag == kConvFrags + kConvPhaseFrags, "lo fragments follow the backward's");
 
 __global__ __launch_bounds__(64 * kConvPhaseFrags) void k_conv_bwd_frags(const float* prm, Offsets o, uint4* frag) {
   const int f = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
@@ -382,13 +453,17 @@ __global__ __launch_bounds__(64 * kConvPhaseFrags) void k_conv_bwd_frags(const f
   }
 }
 
+// PREC: conv1 is recomputed with split operands (the crop's lo part staged beside it), so its ReLU
+// mask is the one the split forward applied; the products of the backward stay BF16.
+template <bool PREC>
 __global__ __launch_bounds__(kBwdThreads) void k_conv_bwd(const float* __restrict__ prm, Offsets o,
                                                           const uint4* __restrict__ frag,
                                                           const int16_t* __restrict__ crop,
                                                           const int32_t* __restrict__ rows,
                                                           const uint16_t* __restrict__ dz2c, int B,
                                                           float* __restrict__ part) {
-  __shared__ __align__(16) uint16_t s_crop[kCropLds];
+  __shared__ __align__(16) uint16_t s_crop[(PREC ? 2 : 1) * kCropLds];
+  uint16_t* const s_cropl = s_crop + (PREC ? kCropLds : 0);
   __shared__ __align__(16) uint16_t s_a1x[kA1xLds];
   __shared__ __align__(16) uint16_t s_dz[kDzLds];
   __shared__ __align__(16) uint16_t s_dzp[kDzPLds];
@@ -397,7 +472,7 @@ __global__ __launch_bounds__(kBwdThreads) void k_conv_bwd(const float* __restric
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
   {
     uint4* z = reinterpret_cast<uint4*>(s_crop);
-    for (int i = threadIdx.x; i < kCropLds / 8; i += kBwdThreads) z[i] = make_uint4(0u, 0u, 0u, 0u);
+    for (int i = threadIdx.x; i < (PREC ? 2 : 1) * kCropLds / 8; i += kBwdThreads) z[i] = make_uint4(0u, 0u, 0u, 0u);
     z = reinterpret_cast<uint4*>(s_a1x);
     for (int i = threadIdx.x; i < kA1xLds / 8; i += kBwdThreads) z[i] = make_uint4(0u, 0u, 0u, 0u);
     z = reinterpret_cast<uint4*>(s_dzp);
@@ -408,6 +483,7 @@ __global__ __launch_bounds__(kBwdThreads) void k_conv_bwd(const float* __restric
   // registers that live for the whole workgroup
   // conv1's weights as the B operand: the same values as the forward's A fragment (W'[k][co] at co = lane % 16)
   const bf16x8 w1f = __builtin_bit_cast(bf16x8, frag[lane]);
+  const bf16x8 w1fl = PREC ? __builtin_bit_cast(bf16x8, frag[64 * kConvLoFrag + lane]) : w1f;
   const float b1c = prm[o.c1b + lr];
   // phase weights: this wave's qy rows are {wave, wave + 8}; all four phases, 9 k-steps
   bf16x8 wph[kConvPhaseFrags];
@@ -437,6 +513,7 @@ __global__ __launch_bounds__(kBwdThreads) void k_conv_bwd(const float* __restric
   for (int b = blockIdx.x; b < B; b += gridDim.x) {
     // ---- stage the crop and dz2 ([co][pos]); db2 from the same values
     store_crop<kBwdThreads>(cr, s_crop);
+    if (PREC) store_crop<kBwdThreads, true>(cr, s_cropl);
     {
       // the thread's eight cells: row y = v / 8, columns 8 (v % 8) + j, i.e. X = 2 (v % 8) + (j >= 4)
       // and residue j % 4
@@ -472,24 +549,22 @@ __global__ __launch_bounds__(kBwdThreads) void k_conv_bwd(const float* __restric
     // eight tiles t = wave + 8 m are taken four at a time so that their operand reads overlap
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      uint4 u[4];
+      uint4 u[4], ul[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int t = wave + 8 * (4 * h + i);
-        const int pxa = t * 16 + lr, ya = pxa >> 5, xa = pxa & 31;
-        u[i] = make_uint4(0u, 0u, 0u, 0u);
-        if (lg < 2) {
-          const uint16_t* q = s_crop + ((ya + lg) * kBlk + xa) * 4;
-          const uint2 a = *reinterpret_cast<const uint2*>(q);
-          const uint2 c = *reinterpret_cast<const uint2*>(q + 4);
-          u[i] = make_uint4(a.x, a.y, c.x, c.y);
-        }
+        u[i] = conv1_window(s_crop, t * 16 + lr, lg);
+        if (PREC) ul[i] = conv1_window(s_cropl, t * 16 + lr, lg);
       }
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int t = wave + 8 * (4 * h + i);
-        const f32x4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, u[i]), w1f,
-                                                                 f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+        f32x4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, u[i]), w1f,
+                                                           f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+        if (PREC) {
+          acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, ul[i]), w1f, acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, u[i]), w1fl, acc, 0, 0, 0);
+        }
         const int px0 = t * 16 + 4 * lg, y = px0 >> 5, x0 = px0 & 31;   // x0 = 0 mod 4
         uint16_t hv[4];
 #pragma unroll

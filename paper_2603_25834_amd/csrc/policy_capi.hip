@@ -40,6 +40,10 @@ struct aslam_policy {
   uint16_t *w1b = nullptr, *w1t = nullptr, *w2b = nullptr, *w2t = nullptr;   // BF16 weight copies
   uint4* cfrag = nullptr;   // the encoder's weight fragments (k_conv_frags, k_conv_bwd_frags)
   int32_t k1p = 0;   // FC1 input width padded to a multiple of 8
+  // split-precision forward (config precision 1): the lo parts of the FC1 input rows, of h1 and of the
+  // FC weights (the encoder's lo fragments sit in cfrag from kConvLoFrag on)
+  bool prec = false;
+  uint16_t *x_lo = nullptr, *h1_lo = nullptr, *w1b_lo = nullptr, *w2b_lo = nullptr;
   int64_t part_floats = 0;
   bool prepared = false;   // w1b / w2b hold the weights of some params (the caller tracks which)
   // recurrent handle: the GRU's weight copies and the sequence minibatch's buffers
@@ -54,6 +58,8 @@ struct aslam_policy {
 namespace {
 
 constexpr int kConvGrid = 768;     // encoder forward: the resident workgroups (three per CU, LDS-bound), each looping over samples
+constexpr int kConvGridPrec = 256; // the split-precision encoder forward holds twice the LDS: one per CU
+constexpr int kConvFragsAll = kConvLoFrag + kConvFrags;   // forward, backward phase and lo fragments
 constexpr int kConvBwdGrid = 256;  // encoder backward: one 8-wave workgroup per CU (LDS-bound)
 constexpr int64_t kFc1Splits = 12, kFc2Splits = 64;
 constexpr int kFc1MinBlocks = 512;   // FC1 forward: resident workgroups (two per CU) that its K splits fill
@@ -91,6 +97,10 @@ int64_t part_need(const aslam_policy* p) {
   need = std::max<int64_t>(need, (int64_t)kConvBwdGrid * kConvPart);   // encoder backward partials
   need = std::max<int64_t>(need, (int64_t)kBiasBlocks * 256);
   need = std::max<int64_t>(need, (int64_t)kFc1MinBlocks * 64 * kHid);   // FC1 forward split-K: S * B <= 512 * 64
+  if (p->prec) {   // the three products of a split FC1 (S * B <= 512 * 64 each) and of FC2 (one slice each)
+    need = std::max<int64_t>(need, 3 * (int64_t)kFc1MinBlocks * 64 * kHid);
+    need = std::max<int64_t>(need, 3 * p->max_b * kHid);
+  }
   return need;
 }
 
@@ -105,7 +115,7 @@ int64_t part_need(const aslam_policy* p) {
 // the encoder backward's phase fragments).
 int convert_weights(aslam_policy* P, const float* prm, hipStream_t st, bool transposed) {
   const Offsets& o = P->off;
-  k_convert_bf16<<<1024, 256, 0, st>>>(prm + o.f1w, o.k1, kHid, o.k1, P->w1b, P->k1p);
+  k_convert_bf16<<<1024, 256, 0, st>>>(prm + o.f1w, o.k1, kHid, o.k1, P->w1b, P->k1p, P->prec ? P->w1b_lo : nullptr);
   PCHK(hipGetLastError());
   if (P->rec) {
     k_convert_bf16<<<768, 256, 0, st>>>(prm + o.gih, kHid, kGates, kHid, P->wihb, kHid);
@@ -127,10 +137,14 @@ int convert_weights(aslam_policy* P, const float* prm, hipStream_t st, bool tran
     P->prepared = true;
     return ASL_OK;
   }
-  k_convert_bf16<<<256, 256, 0, st>>>(prm + o.f2w, kHid, kHid, kHid, P->w2b, kHid);
+  k_convert_bf16<<<256, 256, 0, st>>>(prm + o.f2w, kHid, kHid, kHid, P->w2b, kHid, P->prec ? P->w2b_lo : nullptr);
   PCHK(hipGetLastError());
   k_conv_frags<<<1, 64 * kConvFrags, 0, st>>>(prm, o, P->cfrag);
   PCHK(hipGetLastError());
+  if (P->prec) {
+    k_conv_frags<true><<<1, 64 * kConvFrags, 0, st>>>(prm, o, P->cfrag + 64 * kConvLoFrag);
+    PCHK(hipGetLastError());
+  }
   if (transposed) {
     k_conv_bwd_frags<<<1, 64 * kConvPhaseFrags, 0, st>>>(prm, o, P->cfrag);
     PCHK(hipGetLastError());
@@ -149,8 +163,12 @@ int convert_weights(aslam_policy* P, const float* prm, hipStream_t st, bool tran
 int encode_fc1(aslam_policy* P, const float* prm, const int16_t* crop, const float* scan, const float* state,
                const int32_t* rows, int B, hipStream_t st, int* S_used) {
   const Offsets& o = P->off;
-  k_conv_fwd<<<std::min(B, kConvGrid), 256, 0, st>>>(prm, o, P->cfrag, crop, scan, state, P->cfg.n_scan, rows, P->x,
-                                                      P->k1p, B);
+  if (P->prec)
+    k_conv_fwd<true><<<std::min(B, kConvGridPrec), 256, 0, st>>>(prm, o, P->cfrag, crop, scan, state, P->cfg.n_scan,
+                                                                 rows, P->x, P->x_lo, P->k1p, B);
+  else
+    k_conv_fwd<false><<<std::min(B, kConvGrid), 256, 0, st>>>(prm, o, P->cfrag, crop, scan, state, P->cfg.n_scan,
+                                                              rows, P->x, nullptr, P->k1p, B);
   PCHK(hipGetLastError());
   // FC1: [B x k1p] x [k1p x 256] (both operands zero-padded from k1 to k1p)
   const int K1 = P->k1p;
@@ -159,7 +177,17 @@ int encode_fc1(aslam_policy* P, const float* prm, const int16_t* crop, const flo
   // as many K splits as keep the grid within one round of kFc1MinBlocks resident workgroups
   const int tiles = ((B + 127) / 128) * (kHid / 128);
   const int S = std::max(1, std::min(32, kFc1MinBlocks / tiles));
-  if (S == 1) {
+  if (P->prec) {
+    // x_hi W_hi, x_hi W_lo and x_lo W_hi, each split S ways, into consecutive groups of slices
+    const int nz = slices_used(K1, S, 64);
+    const int64_t slice = (int64_t)B * kHid;
+    PCHK((gemm::run<128, 128, 64, 2, 2>(xa, wa, EpiPartial{P->part, kHid, slice}, B, kHid, K1, S, st)));
+    PCHK((gemm::run<128, 128, 64, 2, 2>(xa, LdBF16K{P->w1b_lo, K1, kHid, K1}, EpiPartial{P->part + nz * slice, kHid, slice},
+                                         B, kHid, K1, S, st)));
+    PCHK((gemm::run<128, 128, 64, 2, 2>(LdBF16K{P->x_lo, K1, B, K1}, wa,
+                                         EpiPartial{P->part + 2 * nz * slice, kHid, slice}, B, kHid, K1, S, st)));
+    *S_used = 3 * nz;
+  } else if (S == 1) {
     PCHK((gemm::run<128, 128, 64, 2, 2>(xa, wa, EpiBiasReluBF16{P->h1, prm + o.f1b, kHid}, B, kHid, K1, 1, st)));
     *S_used = 0;
   } else {
@@ -182,11 +210,25 @@ int forward_core(aslam_policy* P, const float* prm, const int16_t* crop, const f
   if (S > 0) {
     const int64_t groups = (int64_t)B * (kHid / 8);
     k_reduce_bias_relu_bf16<<<(int)std::min<int64_t>(4096, (groups + 255) / 256), 256, 0, st>>>(
-        P->part, S, B, kHid, prm + o.f1b, P->h1, kHid);
+        P->part, S, B, kHid, prm + o.f1b, P->h1, kHid, P->prec ? P->h1_lo : nullptr);
     PCHK(hipGetLastError());
   }
-  PCHK((gemm::run<128, 128, 64, 2, 2>(LdBF16K{P->h1, kHid, B, kHid}, LdBF16K{P->w2b, kHid, kHid, kHid},
-                                     EpiBiasF32{P->z2, prm + o.f2b, kHid}, B, kHid, kHid, 1, st)));
+  const LdBF16K ha{P->h1, kHid, B, kHid}, wb{P->w2b, kHid, kHid, kHid};
+  if (P->prec) {
+    // z2 = h1_hi W2_hi + h1_hi W2_lo + h1_lo W2_hi (+ b2), one slice per product
+    const int64_t slice = (int64_t)B * kHid;
+    PCHK((gemm::run<128, 128, 64, 2, 2>(ha, wb, EpiPartial{P->part, kHid, slice}, B, kHid, kHid, 1, st)));
+    PCHK((gemm::run<128, 128, 64, 2, 2>(ha, LdBF16K{P->w2b_lo, kHid, kHid, kHid}, EpiPartial{P->part + slice, kHid, slice},
+                                       B, kHid, kHid, 1, st)));
+    PCHK((gemm::run<128, 128, 64, 2, 2>(LdBF16K{P->h1_lo, kHid, B, kHid}, wb,
+                                       EpiPartial{P->part + 2 * slice, kHid, slice}, B, kHid, kHid, 1, st)));
+    const int64_t groups = (int64_t)B * (kHid / 8);
+    k_reduce_bias_f32<<<(int)std::min<int64_t>(4096, (groups + 255) / 256), 256, 0, st>>>(P->part, 3, B, kHid,
+                                                                                          prm + o.f2b, P->z2, kHid);
+    PCHK(hipGetLastError());
+    return ASL_OK;
+  }
+  PCHK((gemm::run<128, 128, 64, 2, 2>(ha, wb, EpiBiasF32{P->z2, prm + o.f2b, kHid}, B, kHid, kHid, 1, st)));
   return ASL_OK;
 }
 
@@ -205,12 +247,17 @@ int act_core(aslam_policy* P, const float* prm, bool prepared, const int16_t* cr
     // many split-K slices: their sum is spread over the chip first (the tail kernel has B / 16 workgroups)
     const int64_t groups = (int64_t)B * (kHid / 8);
     k_reduce_bias_relu_bf16_q<<<(unsigned)((groups + 63) / 64), 256, 0, st>>>(P->part, S, B, kHid, prm + P->off.f1b,
-                                                                              P->h1, kHid);
+                                                                              P->h1, kHid, P->prec ? P->h1_lo : nullptr);
     PCHK(hipGetLastError());
     S = 0;
   }
-  k_fwd_tail<<<(B + kTailRows - 1) / kTailRows, 256, 0, st>>>(prm, P->off, P->part, S, P->h1, P->w2b, B, mu, value,
-                                                              sample, eps, act, logp);
+  const int tail_blocks = (B + kTailRows - 1) / kTailRows;
+  if (P->prec)
+    k_fwd_tail<true><<<tail_blocks, 256, 0, st>>>(prm, P->off, P->part, S, P->h1, P->h1_lo, P->w2b, P->w2b_lo, B, mu,
+                                                  value, sample, eps, act, logp);
+  else
+    k_fwd_tail<false><<<tail_blocks, 256, 0, st>>>(prm, P->off, P->part, S, P->h1, nullptr, P->w2b, nullptr, B, mu,
+                                                   value, sample, eps, act, logp);
   PCHK(hipGetLastError());
   return ASL_OK;
 }
@@ -233,10 +280,14 @@ int aslam_policy_create(const aslam_policy_config* cfg, aslam_policy** out) {
   if (cfg->n_scan < 1 || cfg->n_scan > 4096) return pfail(ASL_EINVAL, "n_scan must be in [1, 4096]");
   if (cfg->max_batch < 1 || cfg->max_batch > (1 << 20)) return pfail(ASL_EINVAL, "max_batch must be in [1, 2^20]");
   if (cfg->recurrent != 0 && cfg->recurrent != 1) return pfail(ASL_EINVAL, "recurrent must be 0 or 1");
+  if (cfg->precision != 0 && cfg->precision != 1) return pfail(ASL_EINVAL, "precision must be 0 or 1");
+  if (cfg->precision == 1 && cfg->recurrent == 1)
+    return pfail(ASL_ENOTIMPL, "the split-precision forward is built for the feed-forward policy only");
   aslam_policy* p = new (std::nothrow) aslam_policy();
   if (!p) return pfail(ASL_ENOMEM, "host allocation failed");
   p->cfg = *cfg;
   p->rec = cfg->recurrent == 1;
+  p->prec = cfg->precision == 1;
   p->off = offsets(cfg->n_scan, p->rec);
   p->max_b = cfg->max_batch;
   const int64_t Bm = p->max_b;
@@ -251,12 +302,24 @@ int aslam_policy_create(const aslam_policy_config* cfg, aslam_policy** out) {
       {(void**)&p->hsum, 4 * (size_t)kHeadPart},
       {(void**)&p->w1b, 2 * (size_t)kHid * ((p->off.k1 + 7) / 8 * 8)}, {(void**)&p->w1t, 2 * (size_t)kFeat * kHid},
       {(void**)&p->w2b, 2 * (size_t)kHid * kHid},                        {(void**)&p->w2t, 2 * (size_t)kHid * kHid},
-      {(void**)&p->cfrag, sizeof(uint4) * 64 * (kConvFrags + kConvPhaseFrags)},
+      {(void**)&p->cfrag, sizeof(uint4) * 64 * kConvFragsAll},
   };
   for (auto& a : al) {
     if (hipMalloc(a.ptr, a.bytes) != hipSuccess) {
       aslam_policy_destroy(p);
       return pfail(ASL_ENOMEM, "hipMalloc of policy workspace failed");
+    }
+  }
+  if (p->prec) {
+    struct A pl[] = {
+        {(void**)&p->x_lo, 2 * (size_t)Bm * p->k1p}, {(void**)&p->h1_lo, 2 * (size_t)Bm * kHid},
+        {(void**)&p->w1b_lo, 2 * (size_t)kHid * p->k1p}, {(void**)&p->w2b_lo, 2 * (size_t)kHid * kHid},
+    };
+    for (auto& a : pl) {
+      if (hipMalloc(a.ptr, a.bytes) != hipSuccess) {
+        aslam_policy_destroy(p);
+        return pfail(ASL_ENOMEM, "hipMalloc of policy workspace failed");
+      }
     }
   }
   if (p->rec) {
@@ -290,7 +353,8 @@ int aslam_policy_destroy(aslam_policy* p) {
   void* ptrs[] = {p->x, p->h1, p->dz2, p->dz1, p->dz2c, p->z2, p->part, p->hpart, p->hsum,
                   p->w1b, p->w1t, p->w2b, p->w2t, p->cfrag,
                   p->wihb, p->whhb, p->wiht, p->whht, p->hst, p->g_r, p->g_z, p->g_n, p->g_ghn, p->hp_used,
-                  p->dh_head, p->dh_buf, p->hp_bf, p->dgi, p->dgh, p->rows};
+                  p->dh_head, p->dh_buf, p->hp_bf, p->dgi, p->dgh, p->rows, p->x_lo, p->h1_lo, p->w1b_lo,
+                  p->w2b_lo};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   delete p;
@@ -480,7 +544,10 @@ int backward_fc1_encoder(aslam_policy* P, const float* params, const int16_t* cr
   // encoder: conv2 / conv1 weight and bias gradients in one pass over the minibatch
   {
     const int grid = std::min(B, kConvBwdGrid);
-    k_conv_bwd<<<grid, kBwdThreads, 0, st>>>(params, o, P->cfrag, crop, rows, P->dz2c, B, part);
+    if (P->prec)
+      k_conv_bwd<true><<<grid, kBwdThreads, 0, st>>>(params, o, P->cfrag, crop, rows, P->dz2c, B, part);
+    else
+      k_conv_bwd<false><<<grid, kBwdThreads, 0, st>>>(params, o, P->cfrag, crop, rows, P->dz2c, B, part);
     PCHK(hipGetLastError());
     PCHK(launch_reduce(part, grid, kConvPartW2, grads + o.c2w, 1, kConvPart, st));
     PCHK(launch_reduce(part + kConvPartW2, grid, kConvPartW1, grads + o.c1w, 2, kConvPart, st));

@@ -446,10 +446,26 @@ __device__ __forceinline__ void sum_slices8(const float* q, int S, int64_t strid
   }
 }
 
+// Eight ReLU outputs relu(a + bias) as BF16 into out (hi parts) and, when out_lo is given, their
+// lo parts into out_lo (the split operand of the next layer).
+__device__ __forceinline__ void store_relu8(const float a[8], const float* bias, int n0, uint16_t* out,
+                                            uint16_t* out_lo, int64_t o) {
+  uint16_t h[8], l[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const float v = fmaxf(a[j] + bias[n0 + j], 0.0f);
+    h[j] = f2bf(v);
+    l[j] = f2bf(v - bf2f(h[j]));
+  }
+  *reinterpret_cast<uint4*>(out + o) = pack8(h);
+  if (out_lo) *reinterpret_cast<uint4*>(out_lo + o) = pack8(l);
+}
+
 // Split-K finish of a GEMM with a bias + ReLU + BF16 epilogue: out[m][n] =
-// bf16(relu(bias[n] + sum_z part[z][m][n])), z in order; 8 columns per thread (N % 8 == 0).
+// bf16(relu(bias[n] + sum_z part[z][m][n])), z in order; 8 columns per thread (N % 8 == 0);
+// out_lo (may be NULL) receives the lo parts.
 __global__ void k_reduce_bias_relu_bf16(const float* part, int S, int M, int N, const float* bias, uint16_t* out,
-                                        int64_t ldo) {
+                                        int64_t ldo, uint16_t* out_lo = nullptr) {
   const int64_t groups = (int64_t)M * (N / 8);
   for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < groups;
        g += (int64_t)gridDim.x * blockDim.x) {
@@ -459,17 +475,34 @@ __global__ void k_reduce_bias_relu_bf16(const float* part, int S, int M, int N, 
 #pragma unroll
     for (int j = 0; j < 8; ++j) a[j] = 0.0f;
     sum_slices8(part + m * N + n0, S, (int64_t)M * N, a);
-    uint16_t h[8];
+    store_relu8(a, bias, n0, out, out_lo, m * ldo + n0);
+  }
+}
+
+// Split-K finish into FP32 with a bias: out[m][n] = bias[n] + sum_z part[z][m][n], z in order.
+__global__ void k_reduce_bias_f32(const float* part, int S, int M, int N, const float* bias, float* out, int64_t ldo) {
+  const int64_t groups = (int64_t)M * (N / 8);
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < groups;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t m = g / (N / 8);
+    const int n0 = (int)(g - m * (N / 8)) * 8;
+    float a[8];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) h[j] = f2bf(fmaxf(a[j] + bias[n0 + j], 0.0f));
-    *reinterpret_cast<uint4*>(out + m * ldo + n0) = pack8(h);
+    for (int j = 0; j < 8; ++j) a[j] = 0.0f;
+    sum_slices8(part + m * N + n0, S, (int64_t)M * N, a);
+    float* q = out + m * ldo + n0;
+    *reinterpret_cast<float4*>(q) = make_float4(a[0] + bias[n0], a[1] + bias[n0 + 1], a[2] + bias[n0 + 2],
+                                                a[3] + bias[n0 + 3]);
+    *reinterpret_cast<float4*>(q + 4) = make_float4(a[4] + bias[n0 + 4], a[5] + bias[n0 + 5], a[6] + bias[n0 + 6],
+                                                    a[7] + bias[n0 + 7]);
   }
 }
 
 // The same for many slices (a small batch split many ways): each wave sums a quarter of the slices
 // for 64 consecutive 8-column groups, and wave 0 adds the four quarters in order.
 __global__ __launch_bounds__(256) void k_reduce_bias_relu_bf16_q(const float* part, int S, int M, int N,
-                                                                 const float* bias, uint16_t* out, int64_t ldo) {
+                                                                 const float* bias, uint16_t* out, int64_t ldo,
+                                                                 uint16_t* out_lo = nullptr) {
   __shared__ float s_q[3][64][9];
   const int64_t groups = (int64_t)M * (N / 8);
   const int64_t g = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
@@ -491,10 +524,7 @@ __global__ __launch_bounds__(256) void k_reduce_bias_relu_bf16_q(const float* pa
     for (int r = 0; r < 3; ++r)
 #pragma unroll
       for (int j = 0; j < 8; ++j) a[j] += s_q[r][threadIdx.x][j];
-    uint16_t h[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) h[j] = f2bf(fmaxf(a[j] + bias[n0 + j], 0.0f));
-    *reinterpret_cast<uint4*>(out + m * ldo + n0) = pack8(h);
+    store_relu8(a, bias, n0, out, out_lo, m * ldo + n0);
   }
 }
 
@@ -577,14 +607,18 @@ __global__ __launch_bounds__(256) void k_bias_rows(const uint16_t* src, int64_t 
 }
 
 // BF16 copies of FP32 weight matrices for the GEMMs (rounded to nearest even).
-// k_convert_bf16: dst[r][c] = bf16(src[r][c]) for c < cols, 0 for cols <= c < ld_dst.
+// k_convert_bf16: dst[r][c] = bf16(src[r][c]) for c < cols, 0 for cols <= c < ld_dst; with dst_lo
+// also the remainder dst_lo[r][c] = bf16(src[r][c] - bf16(src[r][c])) (the split operand's lo part).
 __global__ void k_convert_bf16(const float* src, int64_t ld_src, int rows, int cols, uint16_t* dst,
-                               int64_t ld_dst) {
+                               int64_t ld_dst, uint16_t* dst_lo = nullptr) {
   const int64_t total = (int64_t)rows * ld_dst;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
        i += (int64_t)gridDim.x * blockDim.x) {
     const int64_t r = i / ld_dst, c = i - r * ld_dst;
-    dst[i] = c < cols ? f2bf(src[r * ld_src + c]) : (uint16_t)0;
+    const float v = c < cols ? src[r * ld_src + c] : 0.0f;
+    const uint16_t h = f2bf(v);
+    dst[i] = h;
+    if (dst_lo) dst_lo[i] = f2bf(v - bf2f(h));
   }
 }
 
@@ -624,34 +658,46 @@ constexpr int kTailRows = 16;
 constexpr int kTailLdH = kHid + 8;   // BF16 h1 rows in LDS, padded
 constexpr int kTailLdZ = kHid + 4;   // FP32 z2 rows in LDS, padded
 
+//
+// PREC (split operands): h1's lo parts ride along (h1lo rows, or formed from the slice sums) and FC2 is
+// h1_hi W2_hi + h1_hi W2_lo + h1_lo W2_hi (w2lo the lo parts of the weights), k step by k step.
+template <bool PREC>
 __global__ __launch_bounds__(256) void k_fwd_tail(const float* prm, Offsets o, const float* part, int S,
-                                                  const uint16_t* h1, const uint16_t* w2b, int B, float* mu_out,
-                                                  float* v_out, bool sample, ActDraws eps, float* act,
-                                                  float* logp) {
-  __shared__ __align__(16) uint16_t s_h[kTailRows * kTailLdH];
+                                                  const uint16_t* h1, const uint16_t* h1lo, const uint16_t* w2b,
+                                                  const uint16_t* w2lo, int B, float* mu_out, float* v_out,
+                                                  bool sample, ActDraws eps, float* act, float* logp) {
+  __shared__ __align__(16) uint16_t s_h[(PREC ? 2 : 1) * kTailRows * kTailLdH];
   __shared__ __align__(16) float s_z[kTailRows * kTailLdZ];
+  uint16_t* const s_hl = s_h + (PREC ? kTailRows * kTailLdH : 0);
   const int row0 = blockIdx.x * kTailRows;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
   const float* b1 = prm + o.f1b;
   for (int g = threadIdx.x; g < kTailRows * (kHid / 8); g += 256) {
     const int r = g / (kHid / 8), n0 = (g % (kHid / 8)) * 8;
     const int64_t m = row0 + r;
-    uint4 v = make_uint4(0u, 0u, 0u, 0u);
+    uint4 v = make_uint4(0u, 0u, 0u, 0u), vl = v;
     if (m < B) {
       if (S > 0) {
         float a[8];
 #pragma unroll
         for (int j = 0; j < 8; ++j) a[j] = 0.0f;
         sum_slices8(part + m * kHid + n0, S, (int64_t)B * kHid, a);
-        uint16_t h[8];
+        uint16_t h[8], l[8];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) h[j] = f2bf(fmaxf(a[j] + b1[n0 + j], 0.0f));
+        for (int j = 0; j < 8; ++j) {
+          const float y = fmaxf(a[j] + b1[n0 + j], 0.0f);
+          h[j] = f2bf(y);
+          l[j] = f2bf(y - bf2f(h[j]));
+        }
         v = pack8(h);
+        vl = pack8(l);
       } else {
         v = *reinterpret_cast<const uint4*>(h1 + m * kHid + n0);
+        if (PREC) vl = *reinterpret_cast<const uint4*>(h1lo + m * kHid + n0);
       }
     }
     *reinterpret_cast<uint4*>(s_h + r * kTailLdH + n0) = v;
+    if (PREC) *reinterpret_cast<uint4*>(s_hl + r * kTailLdH + n0) = vl;
   }
   __syncthreads();
   // FC2: wave w owns columns 64 w .. 64 w + 63 (four 16-column fragments)
@@ -662,12 +708,21 @@ __global__ __launch_bounds__(256) void k_fwd_tail(const float* prm, Offsets o, c
   for (int k0 = 0; k0 < kHid; k0 += 32) {
     const gemm::bf16x8 af =
         __builtin_bit_cast(gemm::bf16x8, *reinterpret_cast<const uint4*>(s_h + lr * kTailLdH + k0 + 8 * lg));
+    gemm::bf16x8 afl = af;
+    if (PREC)
+      afl = __builtin_bit_cast(gemm::bf16x8, *reinterpret_cast<const uint4*>(s_hl + lr * kTailLdH + k0 + 8 * lg));
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int n = 64 * wave + 16 * j + lr;
       const gemm::bf16x8 bf =
           __builtin_bit_cast(gemm::bf16x8, *reinterpret_cast<const uint4*>(w2b + (int64_t)n * kHid + k0 + 8 * lg));
       acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bf, acc[j], 0, 0, 0);
+      if (PREC) {
+        const gemm::bf16x8 bfl =
+            __builtin_bit_cast(gemm::bf16x8, *reinterpret_cast<const uint4*>(w2lo + (int64_t)n * kHid + k0 + 8 * lg));
+        acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bfl, acc[j], 0, 0, 0);
+        acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afl, bf, acc[j], 0, 0, 0);
+      }
     }
   }
   const float* b2 = prm + o.f2b;

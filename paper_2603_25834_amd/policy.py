@@ -30,9 +30,12 @@ def num_params(n_scan: int) -> int:
 
 class Policy:
     def __init__(self, n_scan: int = 360, max_batch: int = 16384, clip_eps: float = 0.2, c_value: float = 0.5,
-                 c_entropy: float = 0.005, recurrent: bool = False):
+                 c_entropy: float = 0.005, recurrent: bool = False, precision: int = 0):
+        """precision 0: BF16 operands; 1: split (hi + lo BF16) forward operands, FP32-accurate ReLU
+        pre-activations (feed-forward policy only)."""
         self.n_scan, self.max_batch, self.recurrent = n_scan, max_batch, bool(recurrent)
-        self.cfg = PolicyConfig(n_scan, max_batch, clip_eps, c_value, c_entropy, int(self.recurrent))
+        self.precision = int(precision)
+        self.cfg = PolicyConfig(n_scan, max_batch, clip_eps, c_value, c_entropy, int(self.recurrent), self.precision)
         h = ctypes.c_void_p()
         check(lib().aslam_policy_create(ctypes.byref(self.cfg), ctypes.byref(h)))
         self.h = h

@@ -22,7 +22,7 @@ def _p(t):
 
 def _handle_forward(R, d, params, B):
     L = _lib.lib()
-    cfg = _lib.PolicyConfig(R, B, 0.2, 0.5, 0.005, 0)
+    cfg = _lib.PolicyConfig(R, B, 0.2, 0.5, 0.005, 0, 0)
     h = ctypes.c_void_p()
     _lib.check(L.aslam_policy_create(ctypes.byref(cfg), ctypes.byref(h)))
     mu = torch.empty((B, 2), device="cuda")
