@@ -247,13 +247,14 @@ def policy_flops(n_scan: int) -> tuple:
     return float(fwd), float(bwd)
 
 
-def ppo_time(n_scan: int, batch: int, seed: int, reps: int = 10) -> dict:
-    """Policy forward and fused loss+backward on one synthetic minibatch resident in HBM."""
+def ppo_time(n_scan: int, batch: int, seed: int, reps: int = 10, precision: int = 0) -> dict:
+    """Policy forward and fused loss+backward on one synthetic minibatch resident in HBM (precision 0:
+    BF16 operands; 1: split hi + lo forward operands)."""
     import torch
 
     from paper_2603_25834_amd import synth
     from paper_2603_25834_amd.policy import Policy
-    pol = Policy(n_scan, max_batch=batch)
+    pol = Policy(n_scan, max_batch=batch, precision=precision)
     d = {k: torch.from_numpy(v).cuda() for k, v in synth.policy_batch(batch, n_scan, seed).items()}
     params = torch.from_numpy(synth.init_policy_params(n_scan, seed)).cuda()
     grads = torch.zeros_like(params)
@@ -285,7 +286,8 @@ def ppo_time(n_scan: int, batch: int, seed: int, reps: int = 10) -> dict:
     tf_f = f_fwd * batch / (out["forward"] / 1e3) / 1e12
     tf_b = f_bwd * batch / (out["backward"] / 1e3) / 1e12
     pol.close()
-    return {"minibatch": batch, "forward_ms": out["forward"], "backward_ms": out["backward"],
+    return {"minibatch": batch, "precision": "split" if precision else "bf16",
+            "forward_ms": out["forward"], "backward_ms": out["backward"],
             "forward_samples_per_s": batch / (out["forward"] / 1e3),
             "fwd_bwd_samples_per_s": batch / ((out["forward"] + out["backward"]) / 1e3),
             "forward_tflops": tf_f, "backward_tflops": tf_b,
@@ -434,7 +436,7 @@ def cpu_baseline(name: str, seed: int, robots: int, steps: int) -> dict:
 
 
 def train_loop(wb, horizon: int, epochs: int, minibatch: int, warmup: int, iters: int, seed: int,
-               recurrent: bool = False) -> dict:
+               recurrent: bool = False, precision: int = 0) -> dict:
     """Time `iters` PPO training iterations on the workbench's env after `warmup` untimed ones (with
     `recurrent`, the GRU policy and sequence minibatches)."""
     import torch
@@ -445,7 +447,7 @@ def train_loop(wb, horizon: int, epochs: int, minibatch: int, warmup: int, iters
     init = synth.init_recurrent_params if recurrent else synth.init_policy_params
     params = torch.from_numpy(init(wb.R, seed)).cuda()
     tr = PPOTrainer(wb.env, wb.world, wb.start, params, T=horizon, epochs=epochs, minibatch=minibatch,
-                    recurrent=recurrent, seed=seed)
+                    recurrent=recurrent, seed=seed, precision=precision)
     for i in range(warmup):
         tr.iteration()
     torch.cuda.synchronize()
@@ -459,7 +461,8 @@ def train_loop(wb, horizon: int, epochs: int, minibatch: int, warmup: int, iters
     ms = e0.elapsed_time(e1) / iters
     out = {"ms_per_iteration": ms, "env_steps_per_s": wb.n * horizon / (ms / 1e3),
            "samples_per_iteration": tr.S, "minibatch": tr.mb, "minibatches_per_epoch": tr.n_mb,
-           "iterations": iters, "final_loss_terms": [float(x) for x in tr.loss.cpu()]}
+           "iterations": iters, "final_loss_terms": [float(x) for x in tr.loss.cpu()],
+           "policy_precision": "bf16" if recurrent or not precision else "split"}
     del tr
     torch.cuda.empty_cache()
     return out
@@ -548,6 +551,9 @@ def main():
     ap.add_argument("--only-env", action="store_true", help="time the env step alone (profiling)")
     ap.add_argument("--only-slam", action="store_true", help="time the SLAM backbone alone (profiling)")
     ap.add_argument("--ppo-batch", type=int, default=16384)
+    ap.add_argument("--precision", type=int, default=1,
+                    help="policy forward operands: 1 split hi + lo BF16 (gradients within 1e-2 of exact FP64), "
+                         "0 BF16")
     ap.add_argument("--cpu-robots", type=int, default=640, help="oracle training-loop sample: robots")
     ap.add_argument("--cpu-env-robots", type=int, default=750, help="oracle env-step sample: robots")
     ap.add_argument("--cpu-env-steps", type=int, default=400, help="oracle env-step sample: steps")
@@ -566,7 +572,7 @@ def main():
     lds, cus = device_info()
 
     if args.only_ppo:   # profiling aid: the PPO minibatch timing alone
-        print(json.dumps({"ppo": ppo_time(360, args.ppo_batch, args.seed)}), flush=True)
+        print(json.dumps({"ppo": ppo_time(360, args.ppo_batch, args.seed, precision=args.precision)}), flush=True)
         return
     fused = dict(form=_lib.FORM_FUSED, threads=args.threads or 256, band_rows=args.band, grid=args.grid)
     plain = dict(form=_lib.FORM_PLAIN, threads=args.threads or 256, band_rows=args.band)
@@ -605,10 +611,15 @@ def main():
         return
     # ---- the bench step: one PPO training iteration (rollout of `horizon` steps + update)
     wb.env.set_exec(**fused)
-    loop = train_loop(wb, args.horizon, args.epochs, args.minibatch, args.warmup, args.steps, args.seed)
+    loop = train_loop(wb, args.horizon, args.epochs, args.minibatch, args.warmup, args.steps, args.seed,
+                      precision=args.precision)
     print(f"[bench] training iteration: {loop['ms_per_iteration']:.2f} ms "
           f"({loop['env_steps_per_s']:.4g} env-steps/s)", file=sys.stderr, flush=True)
     value = loop["env_steps_per_s"]
+    loop_other = train_loop(wb, args.horizon, args.epochs, args.minibatch, 1, max(2, args.steps // 2), args.seed,
+                            precision=1 - args.precision)
+    print(f"[bench] training iteration, {loop_other['policy_precision']} policy: "
+          f"{loop_other['ms_per_iteration']:.2f} ms", file=sys.stderr, flush=True)
 
     out = {
         "metric": METRIC,
@@ -621,7 +632,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "int32+bf16",
+        "dtype": "int32+bf16" if args.precision == 0 else "int32+bf16x3",
         "data": "synthetic (seeded worlds, start poses and env-timing actions; odometry, loop-closure and action "
                 "noise and minibatch permutations from the library's counter-based generator in the kernels; "
                 "random-init policy)",
@@ -631,6 +642,7 @@ def main():
                    "step": f"one PPO iteration: {args.horizon} env steps (fused persistent form) with observe, "
                            f"policy forward and action sampling per step, GAE, {args.epochs} epochs of "
                            f"minibatches <= {args.minibatch} (gather, loss+gradient with recompute, Adam)",
+                   "policy_precision": loop["policy_precision"],
                    "horizon": args.horizon, "epochs": args.epochs, "minibatch": loop["minibatch"],
                    "minibatches_per_epoch": loop["minibatches_per_epoch"],
                    "threads": fused["threads"], "band_rows": fused.get("band_rows", 0),
@@ -639,6 +651,7 @@ def main():
         "rays_per_s": value * wb.R,
         "slam": slam_res,
         "training_loop": loop,
+        "training_loop_other_precision": loop_other,
         "env_step_only": {"env_steps_per_s": wb.n / ((res["ms_per_step"] + obs_ms) / 1e3),
                           "rays_per_s": wb.n * wb.R / ((res["ms_per_step"] + obs_ms) / 1e3),
                           "step_ms": res["ms_per_step"], "observe_ms": obs_ms, "steps": args.env_steps,
@@ -659,9 +672,12 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_ppo:
         print(f"[bench] PPO minibatch {args.ppo_batch}", file=sys.stderr, flush=True)
-        out["ppo"] = ppo_time(out["config"]["rays"], args.ppo_batch, args.seed)
-        print(f"[bench] PPO fwd {out['ppo']['forward_ms']:.3f} ms, fwd+bwd(recompute) {out['ppo']['backward_ms']:.3f} ms",
-              file=sys.stderr, flush=True)
+        out["ppo"] = ppo_time(out["config"]["rays"], args.ppo_batch, args.seed, precision=args.precision)
+        out["ppo_other_precision"] = ppo_time(out["config"]["rays"], args.ppo_batch, args.seed,
+                                              precision=1 - args.precision)
+        for k in ("ppo", "ppo_other_precision"):
+            print(f"[bench] PPO ({out[k]['precision']}) fwd {out[k]['forward_ms']:.3f} ms, "
+                  f"fwd+bwd(recompute) {out[k]['backward_ms']:.3f} ms", file=sys.stderr, flush=True)
         torch.cuda.empty_cache()
     for key, name in (("secondary", args.secondary), ("paper_mode", args.paper_mode)):
         if name:

@@ -176,23 +176,24 @@ __device__ __forceinline__ uint2 pack_relu4(const f32x4& acc, const float b[4]) 
 }
 
 // conv1 + ReLU of the staged crop into s_a1 (pixel (y, x) at a1_slot(y, x) * 16): 64 tiles of 16
-// pixels, 16 per wave, taken four at a time so that their operand reads are in flight together.
-// PREC: the crop's and the weights' lo parts enter the product too, and a1's lo part goes to s_a1l.
-template <bool PREC>
+// pixels over the NW waves, each taking four at a time so that their operand reads are in flight
+// together.  PREC: the crop's and the weights' lo parts enter the product too, and a1's lo part goes
+// to s_a1l.
+template <bool PREC, int NW>
 __device__ __forceinline__ void conv1_lds(const uint16_t* s_crop, const uint16_t* s_cropl, uint16_t* s_a1,
                                           uint16_t* s_a1l, const bf16x8& w1f, const bf16x8& w1fl, const float b1[4],
                                           int wave, int lr, int lg) {
-  for (int t0 = wave; t0 < kA1 * kA1 / 16; t0 += 16) {
+  for (int t0 = wave; t0 < kA1 * kA1 / 16; t0 += 4 * NW) {
     uint4 u[4], ul[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int px = (t0 + 4 * i) * 16 + lr;
+      const int px = (t0 + NW * i) * 16 + lr;
       u[i] = conv1_window(s_crop, px, lg);
       if (PREC) ul[i] = conv1_window(s_cropl, px, lg);
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int px = (t0 + 4 * i) * 16 + lr, y = px >> 5, x = px & 31;
+      const int px = (t0 + NW * i) * 16 + lr, y = px >> 5, x = px & 31;
       f32x4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1f, __builtin_bit_cast(bf16x8, u[i]),
                                                          f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
       if (PREC) {
@@ -230,9 +231,9 @@ constexpr int kConvLoFrag = 20;
 
 // PREC: a2lo receives the lo parts of the same row (conv features and the scan / state tail), the
 // products are split as described at the top, and the workgroup holds the crop and a1 twice (87 KB of
-// LDS: one workgroup per CU).
-template <bool PREC>
-__global__ __launch_bounds__(256) void k_conv_fwd(const float* __restrict__ prm, Offsets o,
+// LDS: one workgroup per CU, of NT = 512 threads so that eight waves share the CU).
+template <bool PREC, int NT = 256>
+__global__ __launch_bounds__(NT) void k_conv_fwd(const float* __restrict__ prm, Offsets o,
                                                   const uint4* __restrict__ frag, const int16_t* __restrict__ crop,
                                                   const float* __restrict__ scan, const float* __restrict__ state,
                                                   int R, const int32_t* __restrict__ rows, uint16_t* __restrict__ a2,
@@ -242,12 +243,14 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const float* __restrict__ prm,
   __shared__ __align__(16) uint16_t s_a1[kCopies * kA1Lds];
   uint16_t* const s_cropl = s_crop + (PREC ? kCropLds : 0);
   uint16_t* const s_a1l = s_a1 + (PREC ? kA1Lds : 0);
+  constexpr int NW = NT / 64;
+  static_assert(NW == 4 || NW == 8, "four or eight waves");
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
   {
     uint4* z = reinterpret_cast<uint4*>(s_crop);
-    for (int i = threadIdx.x; i < kCopies * kCropLds / 8; i += 256) z[i] = make_uint4(0u, 0u, 0u, 0u);
+    for (int i = threadIdx.x; i < kCopies * kCropLds / 8; i += NT) z[i] = make_uint4(0u, 0u, 0u, 0u);
     z = reinterpret_cast<uint4*>(s_a1);
-    for (int i = threadIdx.x; i < kCopies * kA1Lds / 8; i += 256) z[i] = make_uint4(0u, 0u, 0u, 0u);
+    for (int i = threadIdx.x; i < kCopies * kA1Lds / 8; i += NT) z[i] = make_uint4(0u, 0u, 0u, 0u);
   }
   const bf16x8 w1f = __builtin_bit_cast(bf16x8, frag[lane]);
   const bf16x8 w1fl = PREC ? __builtin_bit_cast(bf16x8, frag[64 * kConvLoFrag + lane]) : w1f;
@@ -268,33 +271,33 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const float* __restrict__ prm,
   auto tail_value = [&](int64_t sb, int j) -> float {
     return j < R ? scan[sb * R + j] : (j < R + 12 ? state[sb * 12 + (j - R)] : 0.0f);
   };
-  CropRegs<256> cr;
+  CropRegs<NT> cr;
   float tv[kConvFwdTailPre];
   auto load_sample = [&](int b) {
     const int64_t sb = src(b);
-    load_crop<256>(crop + sb * kCrop * kCrop, cr);
+    load_crop<NT>(crop + sb * kCrop * kCrop, cr);
 #pragma unroll
     for (int i = 0; i < kConvFwdTailPre; ++i) {
-      const int j = threadIdx.x + 256 * i;
+      const int j = threadIdx.x + NT * i;
       tv[i] = j < tail ? tail_value(sb, j) : 0.0f;
     }
   };
   if (blockIdx.x < B) load_sample(blockIdx.x);
   __syncthreads();
   for (int b = blockIdx.x; b < B; b += gridDim.x) {
-    store_crop<256>(cr, s_crop);
-    if (PREC) store_crop<256, true>(cr, s_cropl);
+    store_crop<NT>(cr, s_crop);
+    if (PREC) store_crop<NT, true>(cr, s_cropl);
     uint16_t* row = a2 + (int64_t)b * lda2 + kFeat;
     uint16_t* rowl = PREC ? a2lo + (int64_t)b * lda2 + kFeat : row;
 #pragma unroll
     for (int i = 0; i < kConvFwdTailPre; ++i) {
-      const int j = threadIdx.x + 256 * i;
+      const int j = threadIdx.x + NT * i;
       if (j < tail) {
         row[j] = j < R + 12 ? f2bf(tv[i]) : (uint16_t)0;
         if (PREC) rowl[j] = j < R + 12 ? bf16_part<true>(tv[i]) : (uint16_t)0;
       }
     }
-    for (int j = threadIdx.x + 256 * kConvFwdTailPre; j < tail; j += 256) {
+    for (int j = threadIdx.x + NT * kConvFwdTailPre; j < tail; j += NT) {
       const float v = j < R + 12 ? tail_value(src(b), j) : 0.0f;
       row[j] = f2bf(v);
       if (PREC) rowl[j] = bf16_part<true>(v);
@@ -302,11 +305,11 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const float* __restrict__ prm,
     __syncthreads();
     // the next sample's crop and tail are loaded while this one is processed
     if (b + (int)gridDim.x < B) load_sample(b + gridDim.x);
-    conv1_lds<PREC>(s_crop, s_cropl, s_a1, s_a1l, w1f, w1fl, b1, wave, lr, lg);
+    conv1_lds<PREC, NW>(s_crop, s_cropl, s_a1, s_a1l, w1f, w1fl, b1, wave, lr, lg);
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < kA2 / 4; ++i) {
-      const int oy = wave + 4 * i;
+    for (int i = 0; i < kA2 / NW; ++i) {
+      const int oy = wave + NW * i;
       f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int s = 0; s < 5; ++s) {

@@ -164,8 +164,8 @@ int encode_fc1(aslam_policy* P, const float* prm, const int16_t* crop, const flo
                const int32_t* rows, int B, hipStream_t st, int* S_used) {
   const Offsets& o = P->off;
   if (P->prec)
-    k_conv_fwd<true><<<std::min(B, kConvGridPrec), 256, 0, st>>>(prm, o, P->cfrag, crop, scan, state, P->cfg.n_scan,
-                                                                 rows, P->x, P->x_lo, P->k1p, B);
+    k_conv_fwd<true, 512><<<std::min(B, kConvGridPrec), 512, 0, st>>>(prm, o, P->cfrag, crop, scan, state,
+                                                                      P->cfg.n_scan, rows, P->x, P->x_lo, P->k1p, B);
   else
     k_conv_fwd<false><<<std::min(B, kConvGrid), 256, 0, st>>>(prm, o, P->cfrag, crop, scan, state, P->cfg.n_scan,
                                                               rows, P->x, nullptr, P->k1p, B);

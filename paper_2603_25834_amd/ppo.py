@@ -33,7 +33,9 @@ from .policy import Policy, adam, gae, permutation
 class PPOTrainer:
     def __init__(self, env, world: torch.Tensor, start: torch.Tensor, params: torch.Tensor, T: int = 24,
                  epochs: int = 4, minibatch: int = 16384, lr: float = 3e-4, gamma: float = 0.99, lam: float = 0.95,
-                 seed: int = 0, crop: int = 64, recurrent: bool = False):
+                 seed: int = 0, crop: int = 64, recurrent: bool = False, precision: int = 0):
+        """precision: the feed-forward policy's forward operands, 0 BF16, 1 split hi + lo BF16 (the
+        gradients then follow the exact network to 1e-2)."""
         self.env, self.world, self.start = env, world, start
         self.n, self.R = env.n, env.R
         self.T, self.epochs = T, epochs
@@ -50,7 +52,8 @@ class PPOTrainer:
             max_b = max(self.mb, self.n)
         self.lr, self.gamma, self.lam = lr, gamma, lam
         dev = params.device
-        self.policy = Policy(self.R, max_batch=max_b, recurrent=self.recurrent)
+        self.policy = Policy(self.R, max_batch=max_b, recurrent=self.recurrent,
+                             precision=0 if self.recurrent else precision)
         self.params = params
         self.grads = torch.zeros_like(params)
         self.m = torch.zeros_like(params)
