@@ -26,6 +26,18 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 BF16_PEAK_TFLOPS = 2500.0
 METRIC = "env-steps/s and rays/s at 750 & 4096 robots; % HBM roofline; PPO fwd+bwd/s"
+# The paper's own training-time figures (Sec. IV-A hardware, Sec. IV-B results), quoted as context only:
+# a different pipeline (Isaac Sim physics, the fixed-lag SLAM, the GRU policy) on other hardware.
+PAPER_CONTEXT = {
+    "training_time": "about 4 h to train the evaluated policy with 750 parallel agents (Env 1, episodes of at "
+                     "most 2048 steps, PPO with a GRU(256) policy)",
+    "hardware": "laptop: Intel Core i7 13th gen, NVIDIA RTX 4060 Laptop GPU 8 GB, 32 GB RAM; Ubuntu 22.04, "
+                "Isaac Sim 4.5, Isaac Lab 2.3.2",
+    "training_volume": "tens of millions of timesteps in a few hours",
+    "derived_rate": "about 0.7k-7k env-steps/s end to end (10-99 M steps over about 4 h; derived here, not stated "
+                    "in the paper)",
+    "prior_work": "over 50 h for Gazebo-based single-robot training",
+}
 
 
 def alg_bytes_per_robot_step(D: float, R: int, loop_closure: bool, host_draws: int = 0,
@@ -408,8 +420,8 @@ def cpu_slam(seed: int, robots: int = 8, windows: int = 64, R: int = 360, L: int
                       f"{windows} windows of {L} poses"}
 
 
-def cpu_baseline(name: str, seed: int, robots: int, steps: int) -> dict:
-    """The oracle as it stands, all host threads, on a bounded sample of the workload."""
+def cpu_baseline(name: str, seed: int, robots: int, steps: int, threads: int = 0) -> dict:
+    """The oracle as it stands, all host threads (or `threads`), on a bounded sample of the workload."""
     from oracle import oracle as O
     from paper_2603_25834_amd import synth
     w = synth.WORKLOADS[name]
@@ -420,8 +432,9 @@ def cpu_baseline(name: str, seed: int, robots: int, steps: int) -> dict:
     p["noise_seed"] = noise_seed(seed)
     env = O.OracleEnv(p, b.sides, b.world, b.world_off)
     env.reset(b.start)
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
-    threads = min(threads, os.cpu_count() or threads)
+    if threads <= 0:
+        threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
+        threads = min(threads, os.cpu_count() or threads)
     cnt = np.zeros(4, np.int64)
     t0 = time.time()
     for t in range(steps):
@@ -453,16 +466,24 @@ def train_loop(wb, horizon: int, epochs: int, minibatch: int, warmup: int, iters
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
+    phases = [] if not recurrent else None
     e0.record()
     for i in range(warmup, warmup + iters):
+        if phases is not None:
+            tr.phase_events = tuple(torch.cuda.Event(enable_timing=True) for _ in range(3))
+            phases.append(tr.phase_events)
         tr.iteration()
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / iters
+    split = {}
+    if phases:
+        split = {"rollout_ms": float(np.mean([a.elapsed_time(b) for a, b, _ in phases])),
+                 "update_ms": float(np.mean([b.elapsed_time(c) for _, b, c in phases]))}
     out = {"ms_per_iteration": ms, "env_steps_per_s": wb.n * horizon / (ms / 1e3),
            "samples_per_iteration": tr.S, "minibatch": tr.mb, "minibatches_per_epoch": tr.n_mb,
            "iterations": iters, "final_loss_terms": [float(x) for x in tr.loss.cpu()],
-           "policy_precision": "bf16" if recurrent or not precision else "split"}
+           "policy_precision": "bf16" if recurrent or not precision else "split", **split}
     del tr
     torch.cuda.empty_cache()
     return out
@@ -524,6 +545,44 @@ def side_workload(name: str, args, fused: dict, plain: dict, recurrent: bool = F
     return res
 
 
+def full_loop(name: str, args, fused: dict, plain: dict) -> dict:
+    """The full training loop on the largest workload: env-step timings (fused and plain, each autotuned on
+    this batch) and PPO training iterations (rollout with the policy forward per step, then the update
+    epochs with recomputation) with the env in the fused and in the plain form."""
+    import torch
+    print(f"[bench] {name}: setting up", file=sys.stderr, flush=True)
+    wb = Workbench(name, args.seed, args.env_warmup + args.secondary_steps, fused)
+    f2, p2, t2 = autotune_forms(wb) if not args.threads else (fused, plain, {})
+    r_f = wb.run(args.env_warmup, args.secondary_steps)
+    wb.env.set_exec(**p2)
+    wb.env.reset(wb.world, wb.start)
+    r_p = wb.run(args.env_warmup, args.secondary_steps)
+    res = {"workload": name, "robots": wb.n, "rays": wb.R, "grid_side": sorted(set(map(int, wb.b.sides))),
+           "r_max_m": wb.p["r_max_m"], "env_steps": args.secondary_steps,
+           "fused_us_per_step": r_f["ms_per_step"] * 1e3, "plain_us_per_step": r_p["ms_per_step"] * 1e3,
+           "fused_env_steps_per_s": r_f["env_steps_per_s"], "plain_env_steps_per_s": r_p["env_steps_per_s"],
+           "fused_speedup": r_f["env_steps_per_s"] / r_p["env_steps_per_s"],
+           "fused_hbm_frac": r_f["achieved_gbs"] / HBM_PEAK_GBS,
+           "coded_cells_per_robot_step": r_f["coded_cells_per_robot_step"],
+           "fused_exec": f2, "plain_exec": p2}
+    print(f"[bench] {name}: fused {r_f['ms_per_step']*1e3:.1f} us/step, plain {r_p['ms_per_step']*1e3:.1f} us/step",
+          file=sys.stderr, flush=True)
+    for form, ex in (("fused", f2), ("plain", p2)):
+        wb.env.set_exec(**ex)
+        lp = train_loop(wb, args.horizon, args.epochs, args.minibatch, 1, args.full_iters, args.seed,
+                        precision=args.precision)
+        res[f"training_loop_{form}"] = lp
+        print(f"[bench] {name}: training iteration ({form} env) {lp['ms_per_iteration']:.1f} ms "
+              f"(rollout {lp.get('rollout_ms', 0):.1f}, update {lp.get('update_ms', 0):.1f})",
+              file=sys.stderr, flush=True)
+    res["end_to_end_env_steps_per_s"] = res["training_loop_fused"]["env_steps_per_s"]
+    res["end_to_end_fused_speedup"] = (res["training_loop_plain"]["ms_per_iteration"] /
+                                       res["training_loop_fused"]["ms_per_iteration"])
+    del wb
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -545,6 +604,9 @@ def main():
     ap.add_argument("--secondary-iters", type=int, default=2, help="timed training iterations of the secondary")
     ap.add_argument("--paper-mode", default="paper_sensor_750x256",
                     help="workload of the paper's sensor / Eq. (7) reward mode, timed like the secondary ('' to skip)")
+    ap.add_argument("--full-loop", default="full_8192x512",
+                    help="workload of the full-loop timing (env fused vs plain, training iterations; '' to skip)")
+    ap.add_argument("--full-iters", type=int, default=2, help="timed training iterations of the full loop")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-ppo", action="store_true")
     ap.add_argument("--only-ppo", action="store_true", help="time the PPO minibatch alone (profiling)")
@@ -682,12 +744,16 @@ def main():
     for key, name in (("secondary", args.secondary), ("paper_mode", args.paper_mode)):
         if name:
             out[key] = side_workload(name, args, fused, plain, recurrent=key == "paper_mode")
+    if args.full_loop:
+        out["full_loop"] = full_loop(args.full_loop, args, fused, plain)
     if not args.no_cpu:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_full_loop(args.workload, args.seed, args.cpu_robots, args.horizon, args.epochs)
         out["cpu_baseline"]["env_step_only"] = cpu_baseline(args.workload, args.seed, args.cpu_env_robots,
                                                             args.cpu_env_steps)
         out["cpu_baseline"]["slam"] = cpu_slam(args.seed)
+        out["cpu_baseline"]["env_step_single_thread"] = cpu_baseline(args.workload, args.seed, 64, 100, threads=1)
+    out["context"] = PAPER_CONTEXT
     print(json.dumps(out), flush=True)
 
 

@@ -63,6 +63,7 @@ class PPOTrainer:
         self.iters = 0                                   # iterations run (counter of the draws)
         T, n, R = self.T, self.n, self.R
         self.units = n if self.recurrent else self.S     # what a minibatch permutation shuffles
+        self.phase_events = None   # set to (start, rollout done, end) torch.cuda.Events to time the phases
         self.perm = torch.zeros(self.units, dtype=torch.int32, device=dev)
         # rollout storage (time-major)
         self.crop = torch.zeros((T + 1, n, crop, crop), dtype=torch.int16, device=dev)
@@ -95,6 +96,9 @@ class PPOTrainer:
             return self._iteration_recurrent(it)
         env, pol, p, sd = self.env, self.policy, self.params, self.seed
         c0 = it * (self.T + 1)
+        ev = self.phase_events
+        if ev:
+            ev[0].record()
         pol.prepare(p)   # the parameters are fixed during the rollout
         for t in range(self.T):
             env.observe(self.ranges, self.crop[t], self.scan[t], self.state[t])
@@ -107,6 +111,8 @@ class PPOTrainer:
                 self.act_boot, self.logp_boot, prepared=True, seed=sd, counter=c0 + self.T)
         adv, ret = gae(self.reward, self.value[:self.T].contiguous(), self.done, self.value[self.T],
                        self.gamma, self.lam)
+        if ev:
+            ev[1].record()
         flat = {
             "crop": self.crop[:self.T].reshape(self.S, *self.crop.shape[2:]),
             "scan": self.scan[:self.T].reshape(self.S, self.R),
@@ -127,6 +133,8 @@ class PPOTrainer:
                              flat["ret"], self.grads, self.loss, rows=idx)
                 self.step_count += 1
                 adam(p, self.grads, self.m, self.v, self.step_count, lr=self.lr)
+        if ev:
+            ev[2].record()
 
     def _iteration_recurrent(self, it: int) -> None:
         env, pol, p, T, sd = self.env, self.policy, self.params, self.T, self.seed

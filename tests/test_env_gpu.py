@@ -176,13 +176,15 @@ def test_graph_replay_matches_eager(form):
         del junk
 
 
-@pytest.mark.parametrize("name,steps,threads", [("paper_750x256", 60, 512), ("ragged_4096", 20, 512)],
-                         ids=["paper_750x256", "ragged_4096"])
+@pytest.mark.parametrize("name,steps,threads", [("paper_750x256", 1000, 512), ("ragged_4096", 1000, 512),
+                                                ("full_8192x512", 30, 512)],
+                         ids=["paper_750x256_T1000", "ragged_4096_T1000", "full_8192x512"])
 def test_full_batch_sampled(name, steps, threads):
     """The whole batch stepped in the fused launch the benchmark times (512 threads per robot, steps
-    captured in a HIP graph); 16 sampled robots re-run alone by the oracle (robots are independent, so
-    a sample sees the same inputs) and compared bit for bit: ranges, rewards, poses, covariances,
-    beliefs and entropies."""
+    captured in one HIP graph): the 750-robot and the ragged 4096-robot scenes for their full 1000
+    steps, and 30 steps of the 8192-robot, 512^2, 720-ray, 15 m scene.  16 sampled robots re-run alone
+    by the oracle (robots are independent, so a sample sees the same inputs) and compared bit for bit
+    at every step (ranges, rewards, done) and at the end (poses, covariances, beliefs, entropies)."""
     import torch
     from oracle import oracle as O
     from paper_2603_25834_amd import _lib
@@ -201,12 +203,14 @@ def test_full_batch_sampled(name, steps, threads):
     full.env.graph_launch()
     torch.cuda.synchronize()
     say(f"[full] {name}: {steps} graph steps of {n} robots, sample {len(pick)}")
-    gr, gw, gd = rng_.cpu().numpy(), rew.cpu().numpy(), dn.cpu().numpy()
+    ip = torch.from_numpy(pick).cuda()
+    gr, gw, gd = rng_[:, ip].cpu().numpy(), rew[:, ip].cpu().numpy(), dn[:, ip].cpu().numpy()
+    del rng_
     for t in range(steps):
         o = orc.step(A[t], G[t])
-        assert np.array_equal(gr[t][pick], o.ranges), t
-        assert np.all(np.abs(gw[t][pick] - o.reward) <= 1e-4 * np.maximum(1.0, np.abs(o.reward))), t
-        assert np.array_equal(gd[t][pick], o.done), t
+        assert np.array_equal(gr[t], o.ranges), t
+        assert np.all(np.abs(gw[t] - o.reward) <= 1e-4 * np.maximum(1.0, np.abs(o.reward))), t
+        assert np.array_equal(gd[t], o.done), t
     e = full.env
     assert np.array_equal(e.read(_lib.FIELD_POSE).cpu().numpy()[pick].view(np.int32), orc.pose.view(np.int32))
     assert np.array_equal(e.read(_lib.FIELD_COV).cpu().numpy()[pick].view(np.int32), orc.cov.view(np.int32))
