@@ -148,6 +148,8 @@ static int64_t to_q16(float v, float inv_c16) {
   return (int64_t)rintf(t);
 }
 
+int64_t orc_to_q16(float v, float cell_m) { return to_q16(v, (float)(65536.0 / (double)cell_m)); }
+
 static int64_t floor_div_q16(int64_t v) {
   /* floor(v / 65536) for any sign */
   int64_t q = v / ORC_Q16;
@@ -294,6 +296,8 @@ static double uncertainty(const float* c) {
   double d = cov_det(c);
   return d > 0.0 ? cbrt(d) : 0.0;
 }
+
+double orc_uncertainty(const float* c6) { return uncertainty(c6); }
 
 static double clip01(double v) { return v < 0.0 ? 0.0 : (v > 1.0 ? 1.0 : v); }
 
@@ -582,6 +586,26 @@ static void step_robot(const orc_config* cfg, const orc_tables* T, orc_state* st
     }
   }
   memset(code, 0, (size_t)s * (size_t)s);
+
+  if (out->odo) {
+    out->odo[2 * (int64_t)r] = d;
+    out->odo[2 * (int64_t)r + 1] = phi;
+  }
+  if (out->d_min) out->d_min[r] = d_min;
+  if (out->dcells) out->dcells[r] = dcells;
+  if (cfg->slam_backend == 1) {
+    /* the fixed-lag backbone finishes the step (scan matching, the window, the weighted map
+     * integration and the reward); here: motion, the predicted estimate, the visits and the scan */
+    out->collided[r] = (uint8_t)collided;
+    out->closed[r] = 0;
+    out->done[r] = (uint8_t)(collided || (cfg->episode_len > 0 && t + 1 >= cfg->episode_len));
+    st->step[r] = t + 1;
+    if (out->counters) {
+      int64_t* q = out->counters + 4 * (int64_t)r;
+      q[0] = cnt_march; q[1] = 0; q[2] = 0; q[3] = cnt_dw;
+    }
+    return;
+  }
 
   /* --- map update from the estimated pose: one code per cell and scan
    * (HIT beats MISS), then one saturating add per coded cell. */

@@ -62,6 +62,8 @@ typedef struct {
   float d_full_m;        /* clearance at which the wall-hugging factor reaches 1 */
   float lambda_explore, lambda_abs, lambda_delta, u_hi, kappa;
   uint64_t noise_seed;   /* key of the step's own normal draws (used when the caller passes none) */
+  int32_t slam_backend;  /* 0: the EKF of the step; 1: the fixed-lag graph of Sec. III-D (orc_step then
+                            stops after the LiDAR march; oracle/fixedlag_env.py finishes the step) */
 } orc_config;
 
 /* Per-robot state, caller-owned arrays (robots are independent). */
@@ -99,6 +101,9 @@ typedef struct {
   double* r_entropy;   /* [n] entropy decrease (nats) */
   double* logdet;      /* [n] ln det Sigma */
   int64_t* counters;   /* [n,4]: march visits, update visits, distinct updated cells, distinct world cells read */
+  float* odo;          /* [n,2] commanded motion (d, phi) of the step, 0 when blocked (may be NULL) */
+  double* d_min;       /* [n] smallest reported range (may be NULL) */
+  double* dcells;      /* [n] novelty of the step's visit cell, Eq. (9) (may be NULL) */
 } orc_out;
 
 /* Tables built by the oracle's own code. */
@@ -140,6 +145,10 @@ int32_t orc_noise_width(const orc_config* cfg);
 /* The paper's reward, Eq. (7) with Eqs. (8)-(17), from its inputs (all FP64). */
 double orc_paper_reward(const orc_config* cfg, int collided, double delta_cells, double u_prev, double u,
                         double d_min);
+/* Q16 cells of a coordinate: rint(v * (float)(65536 / c)) in FP32, clamped to +-1e9 (as the step). */
+int64_t orc_to_q16(float v, float cell_m);
+/* U_t = cbrt(det Sigma) of the 6 unique FP32 entries (0 if det <= 0), as the reward uses it. */
+double orc_uncertainty(const float* c6);
 /* One step of every robot.  noise: caller's normals [n, orc_noise_width], or
  * NULL to draw them: normal k of robot r is orc_normal(noise_seed, ORC_DOMAIN_ENV,
  * draws[r], r, k).  Either way draws[r] grows by one. */

@@ -51,6 +51,7 @@ class OrcConfig(ctypes.Structure):
         ("lambda_explore", ctypes.c_float), ("lambda_abs", ctypes.c_float), ("lambda_delta", ctypes.c_float),
         ("u_hi", ctypes.c_float), ("kappa", ctypes.c_float),
         ("noise_seed", ctypes.c_uint64),
+        ("slam_backend", ctypes.c_int32),
     ]
 
 
@@ -67,7 +68,7 @@ class OrcState(ctypes.Structure):
 class OrcOut(ctypes.Structure):
     _fields_ = [(f, _P) for f in (
         "ranges", "rho_q", "hit_cell", "reward", "done", "collided", "closed", "r_entropy",
-        "logdet", "counters")]
+        "logdet", "counters", "odo", "d_min", "dcells")]
 
 
 _lib = None
@@ -101,6 +102,10 @@ def lib():
         L.orc_normal.argtypes = [ctypes.c_uint64] * 5
         L.orc_normal.restype = ctypes.c_float
         L.orc_permute.argtypes = [ctypes.c_int32, ctypes.c_uint64, ctypes.c_uint64, _P]
+        L.orc_to_q16.argtypes = [ctypes.c_float, ctypes.c_float]
+        L.orc_to_q16.restype = ctypes.c_int64
+        L.orc_uncertainty.argtypes = [_P]
+        L.orc_uncertainty.restype = ctypes.c_double
         _lib = L
     return _lib
 
@@ -146,7 +151,7 @@ def walk(ox, oy, a, b, scale, lim, s, max_out=1 << 16):
 def make_config(p: dict) -> OrcConfig:
     c = OrcConfig()
     for name, _ in OrcConfig._fields_:
-        setattr(c, name, p.get(name, 0) if name == "noise_seed" else p[name])
+        setattr(c, name, p.get(name, 0) if name in ("noise_seed", "slam_backend") else p[name])
     return c
 
 
@@ -194,6 +199,17 @@ def noise_width(p: dict) -> int:
     return int(lib().orc_noise_width(ctypes.byref(c)))
 
 
+def to_q16(v: float, cell_m: float) -> int:
+    """Q16 cells of a coordinate, as the step forms them (FP32 product, rint, clamp)."""
+    return int(lib().orc_to_q16(float(v), float(cell_m)))
+
+
+def uncertainty(c6: np.ndarray) -> float:
+    """U = cbrt(det Sigma) of the 6 unique FP32 covariance entries, as the reward uses it."""
+    c = np.ascontiguousarray(c6, np.float32)
+    return float(lib().orc_uncertainty(_ptr(c)))
+
+
 def paper_reward(p: dict, collided: bool, dcells: float, u_prev: float, u: float, d_min: float) -> float:
     """The paper's Eq. (7) reward from its inputs (the oracle's own function)."""
     c = make_config(p)
@@ -212,6 +228,9 @@ class StepOut:
     r_entropy: np.ndarray
     logdet: np.ndarray
     counters: np.ndarray
+    odo: np.ndarray
+    d_min: np.ndarray
+    dcells: np.ndarray
 
 
 class OracleEnv:
@@ -275,7 +294,8 @@ class OracleEnv:
                     hit_cell=np.zeros((n, R), np.int32), reward=np.zeros(n, np.float64),
                     done=np.zeros(n, np.uint8), collided=np.zeros(n, np.uint8),
                     closed=np.zeros(n, np.uint8), r_entropy=np.zeros(n, np.float64),
-                    logdet=np.zeros(n, np.float64), counters=np.zeros((n, 4), np.int64))
+                    logdet=np.zeros(n, np.float64), counters=np.zeros((n, 4), np.int64),
+                    odo=np.zeros((n, 2), np.float32), d_min=np.zeros(n, np.float64), dcells=np.zeros(n, np.float64))
         co = OrcOut()
         for f in OrcOut._fields_:
             setattr(co, f[0], _ptr(getattr(o, f[0])))

@@ -125,15 +125,16 @@ def weighted_increment(w_q: int, l: int) -> int:
 
 def integrate(grid: np.ndarray, px: int, py: int, ph: int, rho_q: np.ndarray, a_off: np.ndarray, rmax_q: int,
               l_hit: int, l_miss: int, l_clamp: int, match=None, step_xy: int = 0, step_h: int = 0,
-              l_max: float = 1.0):
+              l_max: float = 1.0, w_q: int | None = None):
     """The grid after integrating the scan from the aligned pose (S8), and the number of coded cells.
-    `match` = (best_i, best_j, best_k, best, second, n_used) of csm_match, or None for the unweighted
-    update from (px, py, ph) itself."""
+    `match` = (best_i, best_j, best_k, best, second, n_used) of csm_match, or None for the update from
+    (px, py, ph) itself at weight w_q (256, the unweighted update, when not given)."""
     from oracle import oracle as O
     cq, sq = _trig()
     s = grid.shape[0]
     if match is None:
-        ax, ay, ah, w_q = px, py, ph, 256
+        ax, ay, ah = px, py, ph
+        w_q = 256 if w_q is None else int(w_q)
     else:
         bi, bj, bk, best, second, n_used = (int(v) for v in match)
         ax, ay, ah = px + bi * step_xy, py + bj * step_xy, (ph + bk * step_h) % NANG

@@ -30,6 +30,10 @@ ENV_DEFAULTS = dict(
     # sensor model and the paper's reward (zeros: full-circle fan, exact ranges, workload reward)
     fov_steps=0, reward_mode=0, r_min_m=0.0, range_sigma_m=0.0, range_quant_m=0.0,
     d_crash_m=0.0, d_full_m=0.0, lambda_explore=0.0, lambda_abs=0.0, lambda_delta=0.0, u_hi=0.0, kappa=0.0,
+    # SLAM backend: 0 the EKF; 1 the fixed-lag graph of Sec. III-D (window, Gauss-Newton steps, scan-match
+    # lattice of 9 x 9 x 11 candidates one cell and 0.5 degree apart, scan-factor sigmas, integration floor)
+    slam_backend=0, lag_len=10, gn_iters=3, csm_W=4, csm_V=5, csm_step_xy_q=65536, csm_step_h=64,
+    scan_sigma_xy_m=0.05, scan_sigma_th=0.02, int_weight_floor=0.5,
 )
 
 # The paper's sensor, collision rule and reward (Sec. IV-A, Sec. III-E): 128 rays over the 180-degree
@@ -83,6 +87,10 @@ WORKLOADS = {
     "paper_sensor_750x256": Workload("paper_sensor_750x256", 750, (256,), 0.05, 128, 10.0, 1000, 0,
                                      rects=(20, 40), rect_side=(4, 24), thin_walls=(4, 8), thin_len=(16, 64),
                                      extra=dict(PAPER_MODE)),
+    # The paper's mode with the fixed-lag SLAM backbone in the loop instead of the EKF.
+    "paper_fixedlag_750x256": Workload("paper_fixedlag_750x256", 750, (256,), 0.05, 128, 10.0, 1000, 0,
+                                       rects=(20, 40), rect_side=(4, 24), thin_walls=(4, 8), thin_len=(16, 64),
+                                       extra=dict(PAPER_MODE, slam_backend=1)),
     # 8192 robots in 512x512 worlds, 720 rays, 15 m.
     "full_8192x512": Workload("full_8192x512", 8192, (512,), 0.05, 720, 15.0, 1000, 1,
                               rects=(80, 160), rect_side=(4, 24), thin_walls=(16, 32), thin_len=(16, 64),
