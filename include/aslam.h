@@ -81,6 +81,34 @@ typedef struct {
   float lambda_explore, lambda_abs, lambda_delta; /* Eqs. 8, 13, 14 */
   float u_hi, kappa;    /* Eq. 11 uncertainty gate, Eq. 12 saturation drop (both > 0 in mode 1) */
   uint64_t noise_seed;  /* key of the step's own normal draws (env_step with noise_dev NULL) */
+  /* SLAM backend (Sec. III-D).  0: the EKF above.  1: the fixed-lag graph in the loop (needs
+   * reward_mode 1 and loop_closure 0), per robot and step:
+   *   - the predicted pose (the previous estimate moved by the commanded motion, as the EKF mean) is
+   *     the centre of a correlative search (aslam_csm_match's rules) of the scan -- the reported
+   *     ranges of the rays whose true march hit, Q16 -- over the robot's log-odds grid;
+   *   - alignment: with match weight w = q m > 0 (aslam_csm_factor's rule, l_max = l_clamp in 1/256)
+   *     the aligned pose is the best candidate, else the prediction; the estimate becomes the aligned
+   *     pose, x = ax c / 65536, y likewise, theta = wrap(2 pi h / 46080) in FP64, stored in FP32;
+   *   - the window of the last lag_len poses (FP64): a prior on the oldest, odometry factors (the
+   *     commanded (d, 0, phi) in the earlier pose's frame, 0 when blocked, information 1/sigma^2 of the
+   *     odometry noise), a scan factor on each added pose (the aligned pose, information
+   *     w (1/s_xy^2, 1/s_xy^2, 1/s_th^2)); a full window drops its oldest pose and the next one takes
+   *     as prior its estimate with the inverse covariance diagonal it had as the newest; after a reset
+   *     the window is the initial pose with the prior (pose, 1/var0);
+   *   - gn_iters Gauss-Newton steps (aslam_fixedlag_solve's rules) from the last estimates and the
+   *     aligned pose; the newest pose's covariance becomes the state's Sigma (FP32), U_t = cbrt(det);
+   *   - the scan is integrated from the aligned pose (aslam_csm_integrate's rules) with weight
+   *     w_q = rint(256 (f + (1 - f) w)), f = int_weight_floor;
+   *   - reward Eq. (7) with U_{t-1}, U_t; the map entropy is not tracked.
+   * The step is a sequence of launches in every exec form (threads per robot from the exec config). */
+  int32_t slam_backend;
+  int32_t lag_len;        /* poses in the window, 2..64 */
+  int32_t gn_iters;       /* Gauss-Newton steps per env step, 0..100 */
+  int32_t csm_W, csm_V;   /* lattice half-widths (translation, heading), 0..8, (2 csm_V + 1) n_rays <= 8192 */
+  int32_t csm_step_xy_q;  /* lattice translation step, Q16 cells, 1..2^20 */
+  int32_t csm_step_h;     /* lattice heading step, table steps, 0..46080 */
+  float scan_sigma_xy_m, scan_sigma_th; /* scan-factor standard deviations (> 0) */
+  float int_weight_floor; /* integration weight floor f in [0, 1] */
 } aslam_env_config;
 
 /* Standard-normal draws per robot in the step's noise row: 5 (odometry x,
@@ -192,6 +220,7 @@ int aslam_env_observe_bridge(aslam_env* env, const float* ranges_dev, int16_t* c
 #define ASLAM_FIELD_VISIT_LAST 12 /* int32 [sum v_i^2] last step each visit cell held the robot, -1 never
                                      (v_i = ceil(s_i c / lc_cell_m); loop closure or reward_mode 1) */
 #define ASLAM_FIELD_DRAWS 13     /* uint64 [n] env_step calls since create (the draw counter) */
+#define ASLAM_FIELD_MATCH 14     /* int32 [n,6] the last step's scan match (slam_backend 1), as aslam_csm_match */
 int aslam_env_read(const aslam_env* env, int32_t field, void* dst_dev, aslam_stream_t stream);
 
 /* HIP graph of K consecutive env_step calls.  Step k reads

@@ -39,6 +39,8 @@ how they are wired together; the readings taken here (the library follows the sa
 """
 from __future__ import annotations
 
+import math
+
 import numpy as np
 
 from oracle import oracle as O
@@ -69,7 +71,7 @@ class FixedLagOracleEnv:
         self.l_hit = O.logodds_q(p["l_hit"])
         self.l_miss = O.logodds_q(p["l_miss"])
         self.l_clamp = O.logodds_q(p["l_clamp"])
-        self.rmax_q = int(round(f32("r_max_m") / self.cell * 65536.0))
+        self.rmax_q = int(math.floor(f32("r_max_m") / self.cell * 65536.0 + 0.5))   # llround of the step
         fov = int(p.get("fov_steps", 0))
         fan = fov if 0 < fov < NANG else NANG
         step_ang = fan // self.R

@@ -143,7 +143,8 @@ def integrate(grid: np.ndarray, px: int, py: int, ph: int, rho_q: np.ndarray, a_
     for k in range(len(rho_q)):
         d = (ah + int(a_off[k])) % NANG
         ret = int(rho_q[k]) >= 0
-        cells, _, _, end = O.walk(ax, ay, int(cq[d]), int(sq[d]), 16384, int(rho_q[k]) if ret else rmax_q, s)
+        cells, _, _, end = O.walk(ax, ay, int(cq[d]), int(sq[d]), 16384, int(rho_q[k]) if ret else rmax_q, s,
+                                  max_out=2 * s + 2)   # a walk inside an s x s grid visits at most 2 s + 1 cells
         if len(cells) == 0:
             continue
         code[cells[:, 1], cells[:, 0]] = np.maximum(code[cells[:, 1], cells[:, 0]], 1)

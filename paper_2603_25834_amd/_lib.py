@@ -18,7 +18,8 @@ FORM_PLAIN = 0
 FORM_FUSED = 1
 
 FIELD_BELIEF, FIELD_POSE, FIELD_EST, FIELD_COV, FIELD_RHO_Q, FIELD_HIT_CELL, FIELD_ENTROPY_Q, \
-    FIELD_STEP, FIELD_FLAGS, FIELD_TERMS, FIELD_COUNTERS, FIELD_U_PREV, FIELD_VISIT_LAST, FIELD_DRAWS = range(14)
+    FIELD_STEP, FIELD_FLAGS, FIELD_TERMS, FIELD_COUNTERS, FIELD_U_PREV, FIELD_VISIT_LAST, FIELD_DRAWS, \
+    FIELD_MATCH = range(15)
 
 
 class AslamError(RuntimeError):
@@ -44,6 +45,10 @@ class EnvConfig(ctypes.Structure):
         ("lambda_explore", ctypes.c_float), ("lambda_abs", ctypes.c_float), ("lambda_delta", ctypes.c_float),
         ("u_hi", ctypes.c_float), ("kappa", ctypes.c_float),
         ("noise_seed", ctypes.c_uint64),
+        ("slam_backend", ctypes.c_int32), ("lag_len", ctypes.c_int32), ("gn_iters", ctypes.c_int32),
+        ("csm_W", ctypes.c_int32), ("csm_V", ctypes.c_int32), ("csm_step_xy_q", ctypes.c_int32),
+        ("csm_step_h", ctypes.c_int32), ("scan_sigma_xy_m", ctypes.c_float), ("scan_sigma_th", ctypes.c_float),
+        ("int_weight_floor", ctypes.c_float),
     ]
 
 

@@ -16,6 +16,7 @@
 
 #include "aslam.h"
 #include "env_internal.h"
+#include "slam_internal.h"
 
 using namespace aslam;
 
@@ -85,6 +86,10 @@ struct aslam_env {
   void* d_dcells = nullptr;
   void* d_dmin = nullptr;
   void* d_draws = nullptr;
+  void* d_odo_u = nullptr;
+  // fixed-lag backend
+  FixedLag F{};
+  std::vector<void*> fl_bufs;
   // captured step sequence
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
@@ -102,6 +107,11 @@ void free_env(aslam_env* e) {
     if (*p) (void)hipFree(*p);
     *p = nullptr;
   }
+  for (void* q : e->fl_bufs)
+    if (q) (void)hipFree(q);
+  e->fl_bufs.clear();
+  if (e->d_odo_u) (void)hipFree(e->d_odo_u);
+  e->d_odo_u = nullptr;
   if (e->graph_exec) (void)hipGraphExecDestroy(e->graph_exec);
   if (e->graph) (void)hipGraphDestroy(e->graph);
   if (e->capture_stream) (void)hipStreamDestroy(e->capture_stream);
@@ -159,6 +169,22 @@ int validate_config(const aslam_env_config* c) {
     return fail(ASL_EINVAL, "sensor model needs 0 <= r_min <= r_max, sigma >= 0, quantum >= 0");
   if (!(c->d_crash_m >= 0.0f) || (double)c->d_crash_m / (double)c->cell_m > 32.0)
     return fail(ASL_EINVAL, "d_crash_m must be in [0, 32 cells]");
+  if (c->slam_backend != 0 && c->slam_backend != 1) return fail(ASL_EINVAL, "slam_backend must be 0 or 1");
+  if (c->slam_backend == 1) {
+    if (c->reward_mode != 1 || c->loop_closure)
+      return fail(ASL_EINVAL, "the fixed-lag backend needs reward_mode 1 and loop_closure 0");
+    if (c->lag_len < 2 || c->lag_len > slam::kMaxWindow || c->gn_iters < 0 || c->gn_iters > 100)
+      return fail(ASL_EINVAL, "the fixed-lag backend needs lag_len in [2, 64] and gn_iters in [0, 100]");
+    if (c->csm_W < 0 || c->csm_W > slam::kMaxHalf || c->csm_V < 0 || c->csm_V > slam::kMaxHalf ||
+        (int64_t)(2 * c->csm_V + 1) * c->n_rays > slam::kMaxRayHeadings)
+      return fail(ASL_EINVAL, "csm_W and csm_V must be in [0, 8] with (2 csm_V + 1) n_rays <= 8192");
+    if (c->csm_step_xy_q < 1 || c->csm_step_xy_q > (1 << 20) || c->csm_step_h < 0 || c->csm_step_h > kNang)
+      return fail(ASL_EINVAL, "csm steps out of range (step_xy_q in [1, 2^20], step_h in [0, 46080])");
+    if (!(c->scan_sigma_xy_m > 0.0f) || !(c->scan_sigma_th > 0.0f) || !(c->int_weight_floor >= 0.0f) ||
+        !(c->int_weight_floor <= 1.0f) || !(c->sigma_x > 0.0f) || !(c->sigma_y > 0.0f) || !(c->sigma_th > 0.0f) ||
+        !(c->var0_xy > 0.0f) || !(c->var0_th > 0.0f))
+      return fail(ASL_EINVAL, "the fixed-lag backend needs positive sigmas and var0, and a floor in [0, 1]");
+  }
   if (c->reward_mode == 1) {
     if (!(c->lc_cell_m > 0.0f)) return fail(ASL_EINVAL, "reward_mode 1 needs lc_cell_m > 0 (novelty cells)");
     if (!(c->u_hi > 0.0f) || !(c->kappa > 0.0f) || !(c->d_full_m > c->d_crash_m))
@@ -201,6 +227,67 @@ int plan_lds(aslam_env* e, const aslam_exec_config& ex, LdsPlan& L) {
   L.union_bytes = (int32_t)std::max<int64_t>(world_max, 8 * band * nw_max + 16);
   L.total = L.off_union + L.union_bytes;
   L.record = ex.record_rays;
+  return ASL_OK;
+}
+
+// Device buffers of the fixed-lag backend and its constants (FP64 of the FP32 configuration values).
+int setup_fixedlag(aslam_env* e, const std::vector<int32_t>& order) {
+  (void)order;
+  const aslam_env_config* c = &e->cfg;
+  const int64_t n = e->n, L = c->lag_len, R = c->n_rays;
+  FixedLag& F = e->F;
+  F.L = (int32_t)L;
+  F.iters = c->gn_iters;
+  F.W = c->csm_W;
+  F.V = c->csm_V;
+  F.step_xy = c->csm_step_xy_q;
+  F.step_h = c->csm_step_h;
+  F.max_side = e->max_side;
+  F.cell = (double)c->cell_m;
+  F.l_max = (double)e->P.lclamp;
+  F.floor = (double)c->int_weight_floor;
+  const double sx = c->sigma_x, sy = c->sigma_y, st = c->sigma_th;
+  F.odo_info[0] = 1.0 / (sx * sx);
+  F.odo_info[1] = 1.0 / (sy * sy);
+  F.odo_info[2] = 1.0 / (st * st);
+  const double ss = c->scan_sigma_xy_m, sh = c->scan_sigma_th;
+  F.scan_info[0] = 1.0 / (ss * ss);
+  F.scan_info[1] = 1.0 / (ss * ss);
+  F.scan_info[2] = 1.0 / (sh * sh);
+  F.var0[0] = (double)c->var0_xy;
+  F.var0[1] = (double)c->var0_xy;
+  F.var0[2] = (double)c->var0_th;
+  struct B { void** p; size_t bytes; } bufs[] = {
+      {(void**)&F.x, sizeof(double) * n * L * 3},      {(void**)&F.prior, sizeof(double) * n * 6},
+      {(void**)&F.odo, sizeof(double) * n * (L - 1) * 6}, {(void**)&F.scan, sizeof(double) * n * L * 6},
+      {(void**)&F.sig, sizeof(double) * n * L * 3},    {(void**)&F.count, sizeof(int32_t) * n},
+      {(void**)&F.xout, sizeof(double) * n * L * 3},   {(void**)&F.covw, sizeof(double) * n * 9},
+      {(void**)&F.pose_q, sizeof(int32_t) * n * 3},    {(void**)&F.rho_q, sizeof(int32_t) * n * R},
+      {(void**)&F.match, sizeof(int32_t) * n * 6},     {(void**)&F.pose_al, sizeof(int32_t) * n * 3},
+      {(void**)&F.wq, sizeof(int32_t) * n},            {(void**)&F.coded, sizeof(int32_t) * n},
+      {(void**)&F.a_off, sizeof(int32_t) * R},         {(void**)&F.cell_off, sizeof(int64_t) * n},
+      {(void**)&F.side, sizeof(int32_t) * n},          {&e->d_odo_u, sizeof(float) * n * 2},
+  };
+  for (auto& b : bufs) {
+    hipError_t he = hipMalloc(b.p, b.bytes);
+    if (he != hipSuccess) return fail(ASL_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(he));
+    if (b.p != &e->d_odo_u) e->fl_bufs.push_back(*b.p);
+  }
+  std::vector<int32_t> a_off(R), side(n);
+  std::vector<int64_t> cell_off(n);
+  for (int64_t k = 0; k < R; ++k) a_off[k] = (int32_t)((e->P.ray0 + k * e->P.step_ang) % kNang);
+  for (int64_t i = 0; i < n; ++i) {
+    side[i] = e->meta_h[i].side;
+    cell_off[i] = e->meta_h[i].cell_off;
+  }
+  hipError_t he = hipMemcpy((void*)F.a_off, a_off.data(), sizeof(int32_t) * R, hipMemcpyHostToDevice);
+  if (he == hipSuccess) he = hipMemcpy((void*)F.side, side.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice);
+  if (he == hipSuccess) he = hipMemcpy((void*)F.cell_off, cell_off.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice);
+  if (he == hipSuccess) he = hipMemset(F.count, 0, sizeof(int32_t) * n);
+  if (he == hipSuccess) he = hipMemset(F.match, 0, sizeof(int32_t) * n * 6);
+  if (he == hipSuccess) he = hipDeviceSynchronize();
+  if (he != hipSuccess) return hip_fail(he, "fixed-lag setup");
+  e->P.odo_u = (float*)e->d_odo_u;
   return ASL_OK;
 }
 
@@ -404,6 +491,16 @@ int aslam_env_create(const aslam_env_config* cfg, int32_t n_robots, const int32_
   P.dmin_bits = (int32_t*)e->d_dmin;
   P.seed = cfg->noise_seed;
   P.draws = (uint64_t*)e->d_draws;
+  P.odo_u = nullptr;
+  if (cfg->slam_backend == 1) {
+    rc = setup_fixedlag(e, order);
+    if (rc) {
+      std::string msg = g_err;
+      free_env(e);
+      delete e;
+      return fail(rc, msg);
+    }
+  }
 
   he = set_kernel_lds_limits(e->lds_max);
   if (he != hipSuccess) {
@@ -467,13 +564,17 @@ int aslam_env_reset(aslam_env* env, const uint32_t* world_dev, const float* init
                     aslam_stream_t stream) {
   if (!env || !world_dev || !init_pose_dev) return fail(ASL_EINVAL, "env, world or init_pose is NULL");
   HIP_TRY(launch_reset(env->P, world_dev, init_pose_dev, mask_dev, env->max_side, (hipStream_t)stream), "reset");
+  if (env->cfg.slam_backend == 1)
+    HIP_TRY(launch_reset_fixedlag(env->P, env->F, init_pose_dev, mask_dev, (hipStream_t)stream), "reset");
   env->was_reset = true;
   return ASL_OK;
 }
 
 static int do_step(aslam_env* env, const StepArgs& A, hipStream_t st) {
   hipError_t he;
-  if (env->ex.form == ASLAM_FORM_PLAIN) {
+  if (env->cfg.slam_backend == 1) {
+    he = launch_step_fixedlag(env->P, A, env->L, env->F, env->ex.threads, st);
+  } else if (env->ex.form == ASLAM_FORM_PLAIN) {
     he = launch_step_plain(env->P, A, env->L, env->ex.threads, st);
   } else {
     const int grid = env->ex.grid > 0 ? std::min(env->ex.grid, env->n) : env->n;
@@ -538,6 +639,11 @@ int aslam_env_read(const aslam_env* env, int32_t field, void* dst_dev, aslam_str
     case ASLAM_FIELD_U_PREV: src = env->d_u_prev; bytes = 8 * n; break;
     case ASLAM_FIELD_VISIT_LAST: src = env->d_visit_last; bytes = 4 * (size_t)env->visits; break;
     case ASLAM_FIELD_DRAWS: src = env->d_draws; bytes = 8 * n; break;
+    case ASLAM_FIELD_MATCH:
+      if (env->cfg.slam_backend != 1) return fail(ASL_EINVAL, "no scan match without the fixed-lag backend");
+      src = env->F.match;
+      bytes = 24 * n;
+      break;
     default: return fail(ASL_EINVAL, "unknown field");
   }
   HIP_TRY(hipMemcpyAsync(dst_dev, src, bytes, hipMemcpyDeviceToDevice, (hipStream_t)stream), "read");

@@ -88,6 +88,33 @@ struct EnvParams {
   int32_t* dmin_bits;    // [n] FP32 bits of the smallest reported range (march -> reward)
   uint64_t seed;         // key of the step's own normal draws
   uint64_t* draws;       // [n] steps taken since create: counter of the robot's draws
+  float* odo_u;          // [n,2] commanded motion (d, phi) of the step, 0 when blocked (fixed-lag backend)
+};
+
+// The fixed-lag SLAM backend (Sec. III-D in the loop): per-robot windows of up to L poses (FP64,
+// [n][L][3] poses, [n][6] prior, [n][L-1][6] odometry factors, [n][L][6] scan factors, [n][L][3] the
+// covariance diagonal each pose had when it was the newest) and the step's scan-matching buffers.
+struct FixedLag {
+  int32_t L, iters, W, V, step_xy, step_h, max_side;
+  double cell, l_max, floor;
+  double odo_info[3], scan_info[3], var0[3];
+  double* x;
+  double* prior;
+  double* odo;
+  double* scan;
+  double* sig;
+  int32_t* count;
+  double* xout;
+  double* covw;          // [n][3][3] newest pose's covariance
+  int32_t* pose_q;       // [n,3] predicted pose: Q16 x, y, heading index
+  int32_t* rho_q;        // [n,R] reported ranges of the rays that hit (Q16), -1 otherwise
+  int32_t* match;        // [n,6]
+  int32_t* pose_al;      // [n,3] aligned pose (Q16, heading index)
+  int32_t* wq;           // [n] integration weight, 1/256
+  int32_t* coded;        // [n] coded cells of the integration
+  const int32_t* a_off;  // [R] ray heading offsets
+  const int64_t* cell_off;
+  const int32_t* side;
 };
 
 struct StepArgs {
@@ -117,6 +144,10 @@ hipError_t launch_step_plain(const EnvParams& P, const StepArgs& A, const LdsPla
                              hipStream_t stream);
 hipError_t launch_step_fused(const EnvParams& P, const StepArgs& A, const LdsPlan& L, int threads,
                              int grid, hipStream_t stream);
+hipError_t launch_step_fixedlag(const EnvParams& P, const StepArgs& A, const LdsPlan& L, const FixedLag& F,
+                                int threads, hipStream_t stream);
+hipError_t launch_reset_fixedlag(const EnvParams& P, const FixedLag& F, const float* init_pose, const uint8_t* mask,
+                                 hipStream_t stream);
 hipError_t launch_observe(const EnvParams& P, const float* ranges, int16_t* crop, int32_t cs,
                           float* scan, float* state, const float* u_new, double alpha, hipStream_t stream);
 hipError_t set_kernel_lds_limits(int bytes);

@@ -16,8 +16,11 @@
 // OR-ing bits makes the result independent of ray and lane order), then a
 // coalesced pass applies one saturating int16 add to each coded cell and
 // accumulates the exact entropy change in int64.
+#include <algorithm>
+
 #include "env_internal.h"
 #include "rng.h"
+#include "slam_internal.h"
 
 namespace aslam {
 
@@ -225,6 +228,10 @@ __device__ MotionOut robot_motion(const EnvParams& P, const StepArgs& A, int32_t
   } else {
     px = nx; py = ny; pth = nth;
     p[0] = px; p[1] = py; p[2] = pth;
+  }
+  if (P.odo_u) {
+    P.odo_u[2 * (int64_t)r] = d;
+    P.odo_u[2 * (int64_t)r + 1] = phi;
   }
   // the paper's collision: closer than d_crash to an obstacle (the move stands)
   int32_t collided = col;
@@ -1153,6 +1160,170 @@ __global__ void k_observe(EnvParams P, const float* ranges, int16_t* crop, int32
   }
 }
 
+// ---------------------------------------------------------------- fixed-lag backend
+//
+// The step with the fixed-lag SLAM backbone of Sec. III-D in place of the EKF: motion, prediction and
+// visits (k_motion), the LiDAR march (k_march), the scan-matching inputs (k_fl_prep), the correlative
+// search, the alignment and the window's new pose and factors (k_fl_window), Gauss-Newton over the
+// window, the estimates and covariance back into the state (k_fl_post), the weighted integration of the
+// aligned scan, and the reward of Eq. (7) (k_fl_reward).  The estimate is the aligned pose (integer
+// work), the window only yields the covariance; see the C-ABI header for the rules.
+
+// Predicted pose (Q16 x, y, heading index) and the scan: reported ranges of the rays that hit.
+__global__ void k_fl_prep(EnvParams P, FixedLag F) {
+  const int64_t total = (int64_t)P.n * P.R;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = i / P.R;
+    F.rho_q[i] = P.hitc[i] >= 0 ? P.rho[i] : -1;
+    if (i - r * P.R == 0) {
+      const float* e = P.est + 3 * r;
+      F.pose_q[3 * r] = to_q16(e[0], P.inv_c16);
+      F.pose_q[3 * r + 1] = to_q16(e[1], P.inv_c16);
+      F.pose_q[3 * r + 2] = heading_index(e[2], P.k_ang);
+    }
+  }
+}
+
+// One thread per robot: the alignment, the estimate, and the window's new pose with its odometry and
+// scan factors (the oldest pose leaves a full window, the next one taking the prior).
+__global__ void k_fl_window(EnvParams P, FixedLag F) {
+  const int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= P.n) return;
+  const int32_t* m = F.match + 6 * (int64_t)r;
+  const double w = slam::match_weight(m, F.l_max);
+  const int64_t px = F.pose_q[3 * r], py = F.pose_q[3 * r + 1], ph = F.pose_q[3 * r + 2];
+  int64_t ax = px, ay = py, ah = ph;
+  if (w > 0.0) {
+    ax = px + (int64_t)m[0] * F.step_xy;
+    ay = py + (int64_t)m[1] * F.step_xy;
+    ah = (ph + (int64_t)m[2] * F.step_h) % kNang;
+    if (ah < 0) ah += kNang;
+  }
+  F.pose_al[3 * r] = (int32_t)ax;
+  F.pose_al[3 * r + 1] = (int32_t)ay;
+  F.pose_al[3 * r + 2] = (int32_t)ah;
+  const double two_pi = 2.0 * M_PI;
+  double th = (two_pi * (double)ah) / (double)kNang;
+  th = th - two_pi * rint(th / two_pi);
+  const double z[3] = {(double)ax / 65536.0 * F.cell, (double)ay / 65536.0 * F.cell, th};
+  float* e = P.est + 3 * (int64_t)r;
+  e[0] = (float)z[0];
+  e[1] = (float)z[1];
+  e[2] = (float)z[2];
+  const int L = F.L;
+  double* x = F.x + (int64_t)r * L * 3;
+  double* od = F.odo + (int64_t)r * (L - 1) * 6;
+  double* sc = F.scan + (int64_t)r * L * 6;
+  double* sg = F.sig + (int64_t)r * L * 3;
+  int c = F.count[r];
+  if (c == L) {
+    for (int i = 0; i + 1 < L; ++i) {
+      for (int a = 0; a < 3; ++a) {
+        x[3 * i + a] = x[3 * (i + 1) + a];
+        sg[3 * i + a] = sg[3 * (i + 1) + a];
+      }
+      for (int a = 0; a < 6; ++a) sc[6 * i + a] = sc[6 * (i + 1) + a];
+      if (i + 2 < L)
+        for (int a = 0; a < 6; ++a) od[6 * i + a] = od[6 * (i + 1) + a];
+    }
+    double* pr = F.prior + 6 * (int64_t)r;
+    for (int a = 0; a < 3; ++a) {
+      pr[a] = x[a];
+      pr[3 + a] = 1.0 / sg[a];
+    }
+    c = L - 1;
+  }
+  const double d = (double)P.odo_u[2 * (int64_t)r], phi = (double)P.odo_u[2 * (int64_t)r + 1];
+  double* o = od + 6 * (c - 1);
+  o[0] = d; o[1] = 0.0; o[2] = phi;
+  o[3] = F.odo_info[0]; o[4] = F.odo_info[1]; o[5] = F.odo_info[2];
+  for (int a = 0; a < 3; ++a) {
+    sc[6 * c + a] = z[a];
+    sc[6 * c + 3 + a] = w * F.scan_info[a];
+    x[3 * c + a] = z[a];
+  }
+  F.count[r] = c + 1;
+  F.wq[r] = (int32_t)rint(256.0 * (F.floor + (1.0 - F.floor) * w));
+}
+
+// The window's solution back into the state: poses, the FP32 covariance entries of the newest pose and
+// its covariance diagonal (the prior the pose will carry as the oldest).
+__global__ void k_fl_post(EnvParams P, FixedLag F) {
+  const int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= P.n) return;
+  const int L = F.L, c = F.count[r];
+  const double* xo = F.xout + (int64_t)r * L * 3;
+  double* x = F.x + (int64_t)r * L * 3;
+  for (int e = 0; e < 3 * c; ++e) x[e] = xo[e];
+  const double* S = F.covw + 9 * (int64_t)r;
+  float* cv = P.cov + 6 * (int64_t)r;
+  cv[0] = (float)S[0]; cv[1] = (float)S[1]; cv[2] = (float)S[2];
+  cv[3] = (float)S[4]; cv[4] = (float)S[5]; cv[5] = (float)S[8];
+  double* sg = F.sig + ((int64_t)r * L + (c - 1)) * 3;
+  sg[0] = S[0]; sg[1] = S[4]; sg[2] = S[8];
+}
+
+// Eq. (7) with U_t of the window's covariance; done, terms, work counters and the draw counter.
+__global__ void k_fl_reward(EnvParams P, StepArgs A, FixedLag F) {
+  const int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= P.n) return;
+  if (F.coded[r] > 0) P.counters[3 * (int64_t)r] += F.coded[r];
+  const float* c = P.cov + 6 * (int64_t)r;
+  const double det = cov_det(c);
+  const double ld = det > 0.0 ? log(det) : log(1.17549435e-38);
+  const double u = det > 0.0 ? cbrt(det) : 0.0;
+  const int32_t col = P.flags[2 * (int64_t)r];
+  const double rew = paper_reward(P, col, P.dcells[r], P.u_prev[r], u, (double)__int_as_float(P.dmin_bits[r]));
+  P.u_prev[r] = u;
+  A.reward[r] = (float)rew;
+  const int32_t t = P.step[r];
+  A.done[r] = (uint8_t)(col || (P.episode_len > 0 && t >= P.episode_len));
+  P.terms[2 * (int64_t)r] = 0.0f;
+  P.terms[2 * (int64_t)r + 1] = (float)ld;
+  P.draws[r] += 1;
+}
+
+// Masked reset of the windows: the initial pose with the prior (pose, 1 / var0), no scan factor.
+__global__ void k_fl_reset(int32_t n, FixedLag F, const float* init_pose, const uint8_t* mask) {
+  const int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n || (mask && !mask[r])) return;
+  const int L = F.L;
+  double* x = F.x + (int64_t)r * L * 3;
+  double* pr = F.prior + 6 * (int64_t)r;
+  double* sc = F.scan + (int64_t)r * L * 6;
+  double* sg = F.sig + (int64_t)r * L * 3;
+  for (int a = 0; a < 3; ++a) {
+    x[a] = (double)init_pose[3 * (int64_t)r + a];
+    pr[a] = x[a];
+    pr[3 + a] = 1.0 / F.var0[a];
+    sg[a] = F.var0[a];
+  }
+  for (int a = 0; a < 6; ++a) sc[a] = 0.0;
+  F.count[r] = 1;
+}
+
+template <int NT>
+hipError_t fixedlag_nt(const EnvParams& P, const StepArgs& A, const LdsPlan& L, const FixedLag& F, hipStream_t st) {
+  const int blocks = (P.n + 255) / 256;
+  k_motion<<<blocks, 256, 0, st>>>(P, A);
+  k_march<NT><<<P.n, NT, L.total, st>>>(P, A, L);
+  const int64_t items = (int64_t)P.n * P.R;
+  k_fl_prep<<<(unsigned)std::min<int64_t>(4096, (items + 255) / 256), 256, 0, st>>>(P, F);
+  hipError_t e = slam::launch_csm_match(P.dirtab, P.belief, F.cell_off, F.side, F.max_side, P.n, F.pose_q, F.rho_q,
+                                        P.R, F.a_off, F.W, F.V, F.step_xy, F.step_h, F.match, st);
+  if (e != hipSuccess) return e;
+  k_fl_window<<<blocks, 256, 0, st>>>(P, F);
+  e = slam::launch_fixedlag(P.n, F.L, F.count, F.x, F.prior, F.odo, F.scan, F.iters, F.xout, F.covw, st);
+  if (e != hipSuccess) return e;
+  k_fl_post<<<blocks, 256, 0, st>>>(P, F);
+  e = slam::launch_csm_integrate(P.dirtab, P.belief, F.cell_off, F.side, P.n, F.pose_al, F.rho_q, P.R, F.a_off,
+                                 F.max_side, P.rhat_q, nullptr, 0, 0, 1.0, P.lhit, P.lmiss, P.lclamp, F.coded, F.wq,
+                                 st);
+  if (e != hipSuccess) return e;
+  k_fl_reward<<<blocks, 256, 0, st>>>(P, A, F);
+  return hipGetLastError();
+}
+
 template <int NT>
 hipError_t plain_nt(const EnvParams& P, const StepArgs& A, const LdsPlan& L, hipStream_t st) {
   k_motion<<<(P.n + 255) / 256, 256, 0, st>>>(P, A);
@@ -1218,6 +1389,24 @@ hipError_t launch_step_fused(const EnvParams& P, const StepArgs& A, const LdsPla
     case 512: return fused_nt<512>(P, A, L, grid, stream);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_step_fixedlag(const EnvParams& P, const StepArgs& A, const LdsPlan& L, const FixedLag& F,
+                                int threads, hipStream_t stream) {
+  switch (threads) {
+    case 128: return fixedlag_nt<128>(P, A, L, F, stream);
+    case 192: return fixedlag_nt<192>(P, A, L, F, stream);
+    case 256: return fixedlag_nt<256>(P, A, L, F, stream);
+    case 384: return fixedlag_nt<384>(P, A, L, F, stream);
+    case 512: return fixedlag_nt<512>(P, A, L, F, stream);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_reset_fixedlag(const EnvParams& P, const FixedLag& F, const float* init_pose, const uint8_t* mask,
+                                 hipStream_t stream) {
+  k_fl_reset<<<(P.n + 255) / 256, 256, 0, stream>>>(P.n, F, init_pose, mask);
+  return hipGetLastError();
 }
 
 hipError_t launch_observe(const EnvParams& P, const float* ranges, int16_t* crop, int32_t cs, float* scan,

@@ -23,6 +23,7 @@
 
 #include "aslam.h"
 #include "env_internal.h"
+#include "slam_internal.h"
 
 namespace aslam {
 void set_last_error(const std::string& msg);
@@ -368,12 +369,7 @@ __device__ __forceinline__ double wrap_pi(double a) {
 }
 
 // Weight of a match: the normalised score times the margin to the second peak, both clamped to [0, 1].
-__device__ __forceinline__ double match_weight(const int32_t* m, double l_max) {
-  const double best = (double)m[3], second = (double)m[4];
-  const double q = m[5] <= 0 ? 0.0 : fmin(fmax(best / ((double)m[5] * l_max), 0.0), 1.0);
-  const double mg = fmin(fmax((best - second) / fmax(best, 1.0), 0.0), 1.0);
-  return q * mg;
-}
+using aslam::slam::match_weight;
 
 __global__ void k_csm_factor(const int32_t* __restrict__ match, const int32_t* __restrict__ pose_q, int n,
                              int step_xy, int step_h, double cell_m, double l_max, double sig_xy, double sig_th,
@@ -439,7 +435,8 @@ __global__ __launch_bounds__(kIntThreads) void k_csm_integrate(
     int16_t* __restrict__ belief, const int64_t* __restrict__ cell_off, const int32_t* __restrict__ side,
     const int32_t* __restrict__ pose_q, const int32_t* __restrict__ rho_q, int R, const int32_t* __restrict__ a_off,
     const int32_t* __restrict__ dirtab, int32_t rmax_q, const int32_t* __restrict__ match, int step_xy, int step_h,
-    double l_max, int l_hit, int l_miss, int l_clamp, int32_t* __restrict__ coded, int lds_words) {
+    double l_max, int l_hit, int l_miss, int l_clamp, int32_t* __restrict__ coded, int lds_words,
+    const int32_t* __restrict__ wq_in) {
   extern __shared__ __align__(16) uint32_t bits[];
   __shared__ int32_t s_cnt[kIntThreads / 64];
   __shared__ uint16_t s_perm[kIntSortMax];
@@ -449,7 +446,9 @@ __global__ __launch_bounds__(kIntThreads) void k_csm_integrate(
   const int64_t base = cell_off[r];
   int64_t ax = pose_q[3 * (int64_t)r], ay = pose_q[3 * (int64_t)r + 1], ah = pose_q[3 * (int64_t)r + 2];
   int32_t wq = 256;
-  if (match) {
+  if (wq_in) {
+    wq = wq_in[r];
+  } else if (match) {
     const int32_t* m = match + 6 * (int64_t)r;
     ax += (int64_t)m[0] * step_xy;
     ay += (int64_t)m[1] * step_xy;
@@ -831,25 +830,28 @@ __device__ __forceinline__ void eliminate_sweep(int L, const double* sA, const d
   }
 }
 
-__global__ __launch_bounds__(kLagThreads) void k_fixedlag(int L, const double* __restrict__ x0,
+// counts (may be NULL): the poses of window r (<= Ls); the arrays are strided for Ls poses.
+__global__ __launch_bounds__(kLagThreads) void k_fixedlag(int Ls, const int32_t* __restrict__ counts,
+                                                          const double* __restrict__ x0,
                                                           const double* __restrict__ prior,
                                                           const double* __restrict__ odo,
                                                           const double* __restrict__ scan, int iters,
                                                           double* __restrict__ xout, double* __restrict__ cov) {
   extern __shared__ __align__(16) double s_lag[];
   double* sx = s_lag;
-  double* sA = sx + 3 * L;
-  double* sB = sA + 9 * L;
-  double* sg = sB + 9 * L;
-  double* sDi = sg + 3 * L;
-  double* sC = sDi + 9 * L;
-  double* sy = sC + 9 * L;
+  double* sA = sx + 3 * Ls;
+  double* sB = sA + 9 * Ls;
+  double* sg = sB + 9 * Ls;
+  double* sDi = sg + 3 * Ls;
+  double* sC = sDi + 9 * Ls;
+  double* sy = sC + 9 * Ls;
   const int r = blockIdx.x;
   const int lane = threadIdx.x;
-  for (int e = lane; e < 3 * L; e += kLagThreads) sx[e] = x0[(int64_t)r * L * 3 + e];
+  const int L = counts ? min(max(counts[r], 1), Ls) : Ls;   // uniform over the wavefront
+  for (int e = lane; e < 3 * L; e += kLagThreads) sx[e] = x0[(int64_t)r * Ls * 3 + e];
   const double* pr = prior + 6 * (int64_t)r;
-  const double* od = odo + (int64_t)r * (L > 1 ? L - 1 : 0) * 6;
-  const double* sc = scan + (int64_t)r * L * 6;
+  const double* od = odo + (int64_t)r * (Ls > 1 ? Ls - 1 : 0) * 6;
+  const double* sc = scan + (int64_t)r * Ls * 6;
   M3 last;
   for (int it = 0; it <= iters; ++it) {
     __syncthreads();
@@ -885,7 +887,7 @@ __global__ __launch_bounds__(kLagThreads) void k_fixedlag(int L, const double* _
     }
   }
   __syncthreads();
-  for (int e = lane; e < 3 * L; e += kLagThreads) xout[(int64_t)r * L * 3 + e] = sx[e];
+  for (int e = lane; e < 3 * L; e += kLagThreads) xout[(int64_t)r * Ls * 3 + e] = sx[e];
 }
 
 // ------------------------------------------------------------------ heading table
@@ -934,6 +936,76 @@ int slam_table(const aslam_slam* h, const int32_t** tab) {
 
 }  // namespace
 
+namespace aslam {
+namespace slam {
+
+hipError_t launch_csm_match(const int32_t* tab, const int16_t* belief_dev, const int64_t* cell_off_dev,
+                            const int32_t* side_dev, int32_t max_side, int32_t n, const int32_t* pose_q_dev,
+                            const int32_t* rho_q_dev, int32_t R, const int32_t* a_off_dev, int W, int V,
+                            int step_xy_q, int step_h, int32_t* out_dev, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  const int ncand = (2 * V + 1) * (2 * W + 1) * (2 * W + 1);
+  const int64_t off_bytes = (int64_t)(2 * V + 1) * R * (int64_t)sizeof(int2);
+  if (ncand <= kCsmLdsMaxCand && 2 * W + 1 <= kCsmLdsMaxLine &&
+      off_bytes >= (int64_t)sizeof(int32_t) * ncand * std::max(1, std::min((int)R, kCsmLdsThreads / ((2 * V + 1) *
+                                                                                       (2 * W + 1))))) {
+    // the grids staged in LDS when the largest fits beside the ray offsets (a 256 x 256 grid does with
+    // 11 headings x 360 rays), else read from global memory
+    // rows padded by 2 cells when that still fits (fewer LDS bank conflicts), else unpadded
+    int pad = 2;
+    int64_t grid_bytes = 2 * ((((int64_t)max_side + pad) * max_side + 7) & ~(int64_t)7);
+    if (grid_bytes + off_bytes > kCsmLdsBudget) {
+      pad = 0;
+      grid_bytes = 2 * ((((int64_t)max_side * max_side) + 7) & ~(int64_t)7);
+    }
+    int lds_side = max_side;
+    if (grid_bytes + off_bytes > kCsmLdsBudget) { grid_bytes = 0; lds_side = 0; pad = 0; }
+    const int bytes = (int)(grid_bytes + off_bytes);
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_csm_lds),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e != hipSuccess) return e;
+    k_csm_lds<<<n, kCsmLdsThreads, bytes, stream>>>(belief_dev, cell_off_dev, side_dev, pose_q_dev, rho_q_dev, R,
+                                                    a_off_dev, tab, W, V, step_xy_q, step_h, lds_side, pad, out_dev);
+  } else {
+    k_csm<<<n, kCsmThreads, 0, stream>>>(belief_dev, cell_off_dev, side_dev, pose_q_dev, rho_q_dev, R, a_off_dev, tab,
+                                         W, V, step_xy_q, step_h, out_dev);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_csm_integrate(const int32_t* tab, int16_t* belief_dev, const int64_t* cell_off_dev,
+                                const int32_t* side_dev, int32_t n, const int32_t* pose_q_dev,
+                                const int32_t* rho_q_dev, int32_t R, const int32_t* a_off_dev, int32_t max_side,
+                                int32_t rmax_q, const int32_t* match_dev, int step_xy, int step_h, double l_max,
+                                int32_t l_hit, int32_t l_miss, int32_t l_clamp, int32_t* coded_dev,
+                                const int32_t* wq_dev, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  // bitmaps of one band holding the largest grid whole, within [16 KB, 64 KB]
+  const int64_t nw_max = ((int64_t)std::min(max_side, kIntMaxSide) + 31) >> 5;
+  const int words = (int)std::min<int64_t>(kIntLdsMaxWords, std::max<int64_t>(kIntLdsMinWords, 2 * nw_max * max_side));
+  const int bytes = (int)sizeof(uint32_t) * words;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_csm_integrate),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e != hipSuccess) return e;
+  k_csm_integrate<<<n, kIntThreads, bytes, stream>>>(belief_dev, cell_off_dev, side_dev, pose_q_dev, rho_q_dev, R,
+                                                     a_off_dev, tab, rmax_q, match_dev, step_xy, step_h,
+                                                     match_dev ? l_max : 1.0, l_hit, l_miss, l_clamp, coded_dev,
+                                                     words, wq_dev);
+  return hipGetLastError();
+}
+
+hipError_t launch_fixedlag(int32_t n, int32_t L, const int32_t* counts, const double* x0, const double* prior,
+                           const double* odo, const double* scan, int32_t iters, double* x, double* cov,
+                           hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  const int bytes = (int)(sizeof(double) * 45 * L);
+  k_fixedlag<<<n, kLagThreads, bytes, stream>>>(L, counts, x0, prior, odo, scan, iters, x, cov);
+  return hipGetLastError();
+}
+
+}  // namespace slam
+}  // namespace aslam
+
 extern "C" {
 
 int aslam_slam_create(aslam_slam** out) {
@@ -962,8 +1034,8 @@ int aslam_slam_destroy(aslam_slam* h) {
   return ASL_OK;
 }
 
-int aslam_csm_match(const aslam_slam* slam, const int16_t* belief_dev, const int64_t* cell_off_dev, const int32_t* side_dev,
-                    int32_t max_side, int32_t n, const int32_t* pose_q_dev, const int32_t* rho_q_dev, int32_t R,
+int aslam_csm_match(const aslam_slam* slam, const int16_t* belief_dev, const int64_t* cell_off_dev,
+                    const int32_t* side_dev, int32_t max_side, int32_t n, const int32_t* pose_q_dev, const int32_t* rho_q_dev, int32_t R,
                     const int32_t* a_off_dev, const aslam_csm_config* cfg, int32_t* out_dev, aslam_stream_t stream) {
   int rc = check_csm_config(cfg, R);
   if (rc) return rc;
@@ -975,34 +1047,9 @@ int aslam_csm_match(const aslam_slam* slam, const int16_t* belief_dev, const int
   const int32_t* tab = nullptr;
   rc = slam_table(slam, &tab);
   if (rc) return rc;
-  const int ncand = (2 * cfg->V + 1) * (2 * cfg->W + 1) * (2 * cfg->W + 1);
-  const int64_t off_bytes = (int64_t)(2 * cfg->V + 1) * R * (int64_t)sizeof(int2);
-  if (ncand <= kCsmLdsMaxCand && 2 * cfg->W + 1 <= kCsmLdsMaxLine &&
-      off_bytes >= (int64_t)sizeof(int32_t) * ncand * std::max(1, std::min((int)R, kCsmLdsThreads / ((2 * cfg->V + 1) *
-                                                                                       (2 * cfg->W + 1))))) {
-    // the grids staged in LDS when the largest fits beside the ray offsets (a 256 x 256 grid does with
-    // 11 headings x 360 rays), else read from global memory
-    // rows padded by 2 cells when that still fits (fewer LDS bank conflicts), else unpadded
-    int pad = 2;
-    int64_t grid_bytes = 2 * ((((int64_t)max_side + pad) * max_side + 7) & ~(int64_t)7);
-    if (grid_bytes + off_bytes > kCsmLdsBudget) {
-      pad = 0;
-      grid_bytes = 2 * ((((int64_t)max_side * max_side) + 7) & ~(int64_t)7);
-    }
-    int lds_side = max_side;
-    if (grid_bytes + off_bytes > kCsmLdsBudget) { grid_bytes = 0; lds_side = 0; pad = 0; }
-    const int bytes = (int)(grid_bytes + off_bytes);
-    SCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_csm_lds), hipFuncAttributeMaxDynamicSharedMemorySize,
-                             bytes));
-    k_csm_lds<<<n, kCsmLdsThreads, bytes, (hipStream_t)stream>>>(belief_dev, cell_off_dev, side_dev, pose_q_dev,
-                                                              rho_q_dev, R, a_off_dev, tab, cfg->W, cfg->V,
-                                                              cfg->step_xy_q, cfg->step_h, lds_side, pad, out_dev);
-  } else {
-    k_csm<<<n, kCsmThreads, 0, (hipStream_t)stream>>>(belief_dev, cell_off_dev, side_dev, pose_q_dev, rho_q_dev, R,
-                                                       a_off_dev, tab, cfg->W, cfg->V, cfg->step_xy_q, cfg->step_h,
-                                                       out_dev);
-  }
-  SCHK(hipGetLastError());
+  SCHK(aslam::slam::launch_csm_match(tab, belief_dev, cell_off_dev, side_dev, max_side, n, pose_q_dev, rho_q_dev, R,
+                                     a_off_dev, cfg->W, cfg->V, cfg->step_xy_q, cfg->step_h, out_dev,
+                                     (hipStream_t)stream));
   return ASL_OK;
 }
 
@@ -1022,7 +1069,8 @@ int aslam_csm_factor(const int32_t* match_dev, const int32_t* pose_q_dev, int32_
   return ASL_OK;
 }
 
-int aslam_csm_integrate(const aslam_slam* slam, int16_t* belief_dev, const int64_t* cell_off_dev, const int32_t* side_dev, int32_t n,
+int aslam_csm_integrate(const aslam_slam* slam, int16_t* belief_dev, const int64_t* cell_off_dev,
+                        const int32_t* side_dev, int32_t n,
                         const int32_t* pose_q_dev, const int32_t* rho_q_dev, int32_t R, const int32_t* a_off_dev,
                         int32_t max_side, int32_t rmax_q, const int32_t* match_dev, const aslam_csm_config* cfg,
                         double l_max, int32_t l_hit, int32_t l_miss, int32_t l_clamp, int32_t* coded_dev,
@@ -1048,17 +1096,9 @@ int aslam_csm_integrate(const aslam_slam* slam, int16_t* belief_dev, const int64
   const int32_t* tab = nullptr;
   const int rc = slam_table(slam, &tab);
   if (rc) return rc;
-  // bitmaps of one band holding the largest grid whole, within [16 KB, 64 KB]
-  const int64_t nw_max = ((int64_t)std::min(max_side, kIntMaxSide) + 31) >> 5;
-  const int words = (int)std::min<int64_t>(kIntLdsMaxWords, std::max<int64_t>(kIntLdsMinWords, 2 * nw_max * max_side));
-  const int bytes = (int)sizeof(uint32_t) * words;
-  SCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_csm_integrate),
-                           hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
-  k_csm_integrate<<<n, kIntThreads, bytes, (hipStream_t)stream>>>(belief_dev, cell_off_dev, side_dev, pose_q_dev,
-                                                                  rho_q_dev, R, a_off_dev, tab, rmax_q, match_dev,
-                                                                  step_xy, step_h, match_dev ? l_max : 1.0, l_hit,
-                                                                  l_miss, l_clamp, coded_dev, words);
-  SCHK(hipGetLastError());
+  SCHK(aslam::slam::launch_csm_integrate(tab, belief_dev, cell_off_dev, side_dev, n, pose_q_dev, rho_q_dev, R,
+                                         a_off_dev, max_side, rmax_q, match_dev, step_xy, step_h, l_max, l_hit, l_miss,
+                                         l_clamp, coded_dev, nullptr, (hipStream_t)stream));
   return ASL_OK;
 }
 
@@ -1070,10 +1110,8 @@ int aslam_fixedlag_solve(int32_t n, int32_t L, const double* x0_dev, const doubl
   if (n == 0) return ASL_OK;
   if (!x0_dev || !prior_dev || (L > 1 && !odo_dev) || !scan_dev || !x_dev || !cov_dev)
     return sfail(ASL_EINVAL, "null argument to fixedlag_solve");
-  const int bytes = (int)(sizeof(double) * 45 * L);
-  k_fixedlag<<<n, kLagThreads, bytes, (hipStream_t)stream>>>(L, x0_dev, prior_dev, odo_dev, scan_dev, iters, x_dev,
-                                                             cov_dev);
-  SCHK(hipGetLastError());
+  SCHK(aslam::slam::launch_fixedlag(n, L, nullptr, x0_dev, prior_dev, odo_dev, scan_dev, iters, x_dev, cov_dev,
+                                    (hipStream_t)stream));
   return ASL_OK;
 }
 

@@ -128,6 +128,7 @@ class Env:
         _lib.FIELD_U_PREV: (torch.float64, lambda s: (s.n,)),
         _lib.FIELD_VISIT_LAST: (torch.int32, lambda s: (s.visit_cells,)),
         _lib.FIELD_DRAWS: (torch.int64, lambda s: (s.n,)),
+        _lib.FIELD_MATCH: (torch.int32, lambda s: (s.n, 6)),
     }
 
     def read(self, field: int) -> torch.Tensor:
