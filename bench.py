@@ -531,7 +531,8 @@ def side_workload(name: str, args, fused: dict, plain: dict, recurrent: bool = F
           f"{r2p['ms_per_step']*1e3:.1f} us/step", file=sys.stderr, flush=True)
     if args.secondary_iters > 0:
         wb2.env.set_exec(**f2)
-        l2 = train_loop(wb2, args.horizon, args.epochs, args.minibatch, 1, args.secondary_iters, args.seed)
+        l2 = train_loop(wb2, args.horizon, args.epochs, args.minibatch, 1, args.secondary_iters, args.seed,
+                        precision=args.precision)
         res["training_loop"] = l2
         print(f"[bench] {name}: training iteration {l2['ms_per_iteration']:.2f} ms", file=sys.stderr, flush=True)
         if recurrent:
@@ -541,6 +542,32 @@ def side_workload(name: str, args, fused: dict, plain: dict, recurrent: bool = F
             print(f"[bench] {name}: training iteration with the GRU policy {l3['ms_per_iteration']:.2f} ms",
                   file=sys.stderr, flush=True)
     del wb2
+    torch.cuda.empty_cache()
+    return res
+
+
+def fixedlag_workload(name: str, args, ex: dict) -> dict:
+    """The paper's mode with the fixed-lag SLAM backbone in the loop: env steps (a sequence of launches:
+    motion, march, scan matching, window, Gauss-Newton, weighted integration, reward) in one HIP graph,
+    and training iterations with the split-precision MLP policy."""
+    import torch
+    from paper_2603_25834_amd import _lib
+    print(f"[bench] {name}: setting up", file=sys.stderr, flush=True)
+    ex = dict(ex, form=_lib.FORM_FUSED)
+    wb = Workbench(name, args.seed, args.env_warmup + args.secondary_steps, ex)
+    r = wb.run(args.env_warmup, args.secondary_steps)
+    res = {"workload": name, "robots": wb.n, "rays": wb.R, "steps": args.secondary_steps,
+           "lag_len": int(wb.p["lag_len"]), "gn_iters": int(wb.p["gn_iters"]),
+           "lattice": [2 * int(wb.p["csm_W"]) + 1, 2 * int(wb.p["csm_W"]) + 1, 2 * int(wb.p["csm_V"]) + 1],
+           "us_per_step": r["ms_per_step"] * 1e3, "env_steps_per_s": r["env_steps_per_s"],
+           "rays_per_s": r["rays_per_s"], "coded_cells_per_robot_step": r["coded_cells_per_robot_step"]}
+    print(f"[bench] {name}: {r['ms_per_step']*1e3:.1f} us/step", file=sys.stderr, flush=True)
+    if args.secondary_iters > 0:
+        lp = train_loop(wb, args.horizon, args.epochs, args.minibatch, 1, args.secondary_iters, args.seed,
+                        precision=args.precision)
+        res["training_loop"] = lp
+        print(f"[bench] {name}: training iteration {lp['ms_per_iteration']:.2f} ms", file=sys.stderr, flush=True)
+    del wb
     torch.cuda.empty_cache()
     return res
 
@@ -604,6 +631,8 @@ def main():
     ap.add_argument("--secondary-iters", type=int, default=2, help="timed training iterations of the secondary")
     ap.add_argument("--paper-mode", default="paper_sensor_750x256",
                     help="workload of the paper's sensor / Eq. (7) reward mode, timed like the secondary ('' to skip)")
+    ap.add_argument("--fixedlag", default="paper_fixedlag_750x256",
+                    help="workload of the paper's mode with the fixed-lag SLAM backbone in the loop ('' to skip)")
     ap.add_argument("--full-loop", default="full_8192x512",
                     help="workload of the full-loop timing (env fused vs plain, training iterations; '' to skip)")
     ap.add_argument("--full-iters", type=int, default=2, help="timed training iterations of the full loop")
@@ -744,6 +773,9 @@ def main():
     for key, name in (("secondary", args.secondary), ("paper_mode", args.paper_mode)):
         if name:
             out[key] = side_workload(name, args, fused, plain, recurrent=key == "paper_mode")
+    if args.fixedlag:
+        ex = out.get("paper_mode", {}).get("fused_exec") or fused
+        out["paper_mode_fixedlag"] = fixedlag_workload(args.fixedlag, args, ex)
     if args.full_loop:
         out["full_loop"] = full_loop(args.full_loop, args, fused, plain)
     if not args.no_cpu:
