@@ -775,7 +775,7 @@ def main():
             out[key] = side_workload(name, args, fused, plain, recurrent=key == "paper_mode")
     if args.fixedlag:
         ex = out.get("paper_mode", {}).get("fused_exec") or fused
-        out["paper_mode_fixedlag"] = fixedlag_workload(args.fixedlag, args, ex)
+        out.setdefault("paper_mode", {})["fixedlag"] = fixedlag_workload(args.fixedlag, args, ex)
     if args.full_loop:
         out["full_loop"] = full_loop(args.full_loop, args, fused, plain)
     if not args.no_cpu:

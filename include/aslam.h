@@ -404,7 +404,16 @@ int aslam_policy_sample(aslam_policy* pol, const float* params_dev, const float*
  * word 0 of the Philox4x64-10 block at counter (counter, r, i, 0) under key (seed, 3)), applied again
  * while the image is >= n (cycle walking).  A bijection for every key.  ASL_EINVAL on n < 0 or a NULL
  * out_dev with n > 0. */
-int aslam_permutation(int32_t n, uint64_t seed, uint64_t counter, int32_t* out_dev, aslam_stream_t stream);
+int aslam_permutation(int32_t n, uint64_t seed, uint64_t counter, int32_t* out_dev, void* work_dev,
+                      int64_t work_bytes, aslam_stream_t stream);
+
+/* Bytes of the optional device workspace of aslam_permutation: 4 * 2^b (at most 16 n for n >= 1), 0
+ * for n <= 0.  With a workspace (4-byte aligned, at least this size, caller-owned, overwritten) the
+ * call tabulates the Feistel image of the whole 2^b domain in one pass and walks the cycles through
+ * that table -- the same permutation, without each lane evaluating its whole walk; with
+ * work_dev = NULL each element walks its cycle by itself.  ASL_EINVAL on a short or misaligned
+ * workspace. */
+int64_t aslam_permutation_work_bytes(int32_t n);
 
 /* Row gather for minibatch assembly: dst row i = src row idx_dev[i], i < n, rows of row_bytes bytes
  * (a multiple of 4; src and dst 4-byte aligned).  Indices are not checked against the source size:

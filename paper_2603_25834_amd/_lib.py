@@ -95,7 +95,8 @@ SIGNATURES = {
     "aslam_policy_forward": (ctypes.c_int, [_P, _P, _P, _P, _P, _I32, _P, _P, _P]),
     "aslam_policy_backward": (ctypes.c_int, [_P, _P, _P, _P, _P, _I32, _P, _P, _P, _P, _P, _P, _P]),
     "aslam_policy_sample": (ctypes.c_int, [_P, _P, _P, _P, _U64, _U64, _I32, _P, _P, _P]),
-    "aslam_permutation": (ctypes.c_int, [_I32, _U64, _U64, _P, _P]),
+    "aslam_permutation": (ctypes.c_int, [_I32, _U64, _U64, _P, _P, _I64, _P]),
+    "aslam_permutation_work_bytes": (_I64, [_I32]),
     "aslam_policy_prepare": (ctypes.c_int, [_P, _P, _P]),
     "aslam_policy_forward_noalloc": (ctypes.c_int, [_P, _I32, _P, _P, _P, _I32, _P, _P, _P]),
     "aslam_policy_noalloc_limits": (_I64, [_P, _P]),

@@ -571,11 +571,29 @@ int aslam_policy_sample(aslam_policy* P, const float* params, const float* mu, c
   return ASL_OK;
 }
 
-int aslam_permutation(int32_t n, uint64_t seed, uint64_t counter, int32_t* out, aslam_stream_t stream) {
+int64_t aslam_permutation_work_bytes(int32_t n) {
+  if (n <= 0) return 0;
+  return (int64_t)4 << (2 * rng::perm_half_bits(n));
+}
+
+int aslam_permutation(int32_t n, uint64_t seed, uint64_t counter, int32_t* out, void* work, int64_t work_bytes,
+                      aslam_stream_t stream) {
   if (n < 0) return pfail(ASL_EINVAL, "n must be >= 0");
   if (n == 0) return ASL_OK;
   if (!out) return pfail(ASL_EINVAL, "null argument");
-  k_permutation<<<(n + 255) / 256, 256, 0, (hipStream_t)stream>>>(n, rng::perm_half_bits(n), seed, counter, out);
+  const int h = rng::perm_half_bits(n);
+  hipStream_t st = (hipStream_t)stream;
+  if (!work) {
+    k_permutation<<<(n + 255) / 256, 256, 0, st>>>(n, h, seed, counter, out);
+  } else {
+    const int64_t dom = (int64_t)1 << (2 * h);
+    if (work_bytes < 4 * dom) return pfail(ASL_EINVAL, "work_bytes below aslam_permutation_work_bytes(n)");
+    if ((uintptr_t)work & 3) return pfail(ASL_EINVAL, "work must be 4-byte aligned");
+    uint32_t* tab = static_cast<uint32_t*>(work);
+    k_feistel_table<<<(unsigned)((dom + 255) / 256), 256, 0, st>>>(h, seed, counter, tab);
+    PCHK(hipGetLastError());
+    k_permutation_walk<<<(n + 255) / 256, 256, 0, st>>>(n, tab, out);
+  }
   PCHK(hipGetLastError());
   return ASL_OK;
 }

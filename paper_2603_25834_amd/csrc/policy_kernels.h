@@ -792,10 +792,27 @@ __global__ void k_sample(const float* prm, Offsets o, const float* mu, ActDraws 
   logp[b] = -0.5f * (e0 * e0 + e1 * e1) - (ls0 + ls1) - 1.8378770664093453f;
 }
 
-// Keyed permutation of [0, n): out[j] = the image of j (rng::permute).
+// Keyed permutation of [0, n): out[j] = the image of j (rng::permute), each lane walking its own
+// cycle through Feistel evaluations.
 __global__ void k_permutation(int32_t n, int h, uint64_t seed, uint64_t counter, int32_t* out) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j < n) out[j] = rng::permute((int32_t)j, n, h, seed, counter);
+}
+
+// The same permutation in two passes: the Feistel image of every point of the 2^(2h) domain (one
+// evaluation per lane, all lanes busy), then each j < n follows its cycle through that table, so the
+// walk past images >= n costs a load per hop instead of eight Philox blocks.
+__global__ void k_feistel_table(int h, uint64_t seed, uint64_t counter, uint32_t* tab) {
+  const uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < (1ull << (2 * h))) tab[v] = (uint32_t)rng::feistel(v, h, seed, counter);
+}
+
+__global__ void k_permutation_walk(int32_t n, const uint32_t* __restrict__ tab, int32_t* out) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  uint32_t y = tab[j];
+  while (y >= (uint32_t)n) y = tab[y];   // ends: j's cycle returns to j < n
+  out[j] = (int32_t)y;
 }
 
 // dst row i = src row idx[i]; rows of `words` 32-bit words, 16-byte vectors when `vec`.

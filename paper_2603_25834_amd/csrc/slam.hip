@@ -173,7 +173,7 @@ __global__ __launch_bounds__(kCsmThreads) void k_csm(const int16_t* __restrict__
 // whole line (the line's cells are read side by side); the chunks' partial sums are then added in
 // chunk order.  A robot whose side exceeds the staged size reads its grid from global memory instead.
 // Dynamic LDS: the grid (lds_cells int16, a multiple of 8), then the (2V + 1) R ray offsets, whose
-// space takes the partial sums once every line is done.
+// space (sized for whichever is larger) takes the partial sums once every line is done.
 constexpr int kCsmLdsThreads = 512;
 constexpr int kCsmLdsMaxCand = 1024;
 constexpr int kCsmLdsMaxLine = 9;                  // 2W + 1 <= 9
@@ -945,13 +945,14 @@ hipError_t launch_csm_match(const int32_t* tab, const int16_t* belief_dev, const
                             int step_xy_q, int step_h, int32_t* out_dev, hipStream_t stream) {
   if (n <= 0) return hipSuccess;
   const int ncand = (2 * V + 1) * (2 * W + 1) * (2 * W + 1);
-  const int64_t off_bytes = (int64_t)(2 * V + 1) * R * (int64_t)sizeof(int2);
-  if (ncand <= kCsmLdsMaxCand && 2 * W + 1 <= kCsmLdsMaxLine &&
-      off_bytes >= (int64_t)sizeof(int32_t) * ncand * std::max(1, std::min((int)R, kCsmLdsThreads / ((2 * V + 1) *
-                                                                                       (2 * W + 1))))) {
-    // the grids staged in LDS when the largest fits beside the ray offsets (a 256 x 256 grid does with
-    // 11 headings x 360 rays), else read from global memory
-    // rows padded by 2 cells when that still fits (fewer LDS bank conflicts), else unpadded
+  if (ncand <= kCsmLdsMaxCand && 2 * W + 1 <= kCsmLdsMaxLine) {
+    // the grids staged in LDS when the largest fits beside the ray offsets and the chunks' partial
+    // sums, which reuse the offsets' space (a 256 x 256 grid does with 11 headings x 360 rays), else
+    // read from global memory; rows padded by 2 cells when that still fits (fewer LDS bank
+    // conflicts), else unpadded
+    const int chunks = std::max(1, std::min((int)R, kCsmLdsThreads / ((2 * V + 1) * (2 * W + 1))));
+    const int64_t off_bytes = std::max<int64_t>((int64_t)(2 * V + 1) * R * (int64_t)sizeof(int2),
+                                                (int64_t)sizeof(int32_t) * ncand * chunks);
     int pad = 2;
     int64_t grid_bytes = 2 * ((((int64_t)max_side + pad) * max_side + 7) & ~(int64_t)7);
     if (grid_bytes + off_bytes > kCsmLdsBudget) {

@@ -168,11 +168,21 @@ def gather_rows(src, idx, out=None):
     return out
 
 
-def permutation(n: int, seed: int, counter: int, out=None, device="cuda"):
-    """Keyed permutation of [0, n) (int32 [n], out[j] = image of j) from the library's generator."""
+def permutation_work_bytes(n: int) -> int:
+    return int(lib().aslam_permutation_work_bytes(int(n)))
+
+
+def permutation(n: int, seed: int, counter: int, out=None, device="cuda", work=None):
+    """Keyed permutation of [0, n) (int32 [n], out[j] = image of j) from the library's generator.
+    work: an optional device workspace of permutation_work_bytes(n) bytes (the tabulated form)."""
     out = torch.empty(n, dtype=torch.int32, device=device) if out is None else out
     assert out.dtype == torch.int32 and out.numel() == n and (n == 0 or out.is_cuda)
-    check(lib().aslam_permutation(int(n), int(seed), int(counter), _p(out) if n else None, _stream()))
+    wb = 0
+    if work is not None:
+        assert work.is_cuda and work.is_contiguous()
+        wb = work.numel() * work.element_size()
+    check(lib().aslam_permutation(int(n), int(seed), int(counter), _p(out) if n else None,
+                                  _p(work) if work is not None else None, wb, _stream()))
     return out
 
 

@@ -27,7 +27,7 @@ from __future__ import annotations
 
 import torch
 
-from .policy import Policy, adam, gae, permutation
+from .policy import Policy, adam, gae, permutation, permutation_work_bytes
 
 
 class PPOTrainer:
@@ -65,6 +65,7 @@ class PPOTrainer:
         self.units = n if self.recurrent else self.S     # what a minibatch permutation shuffles
         self.phase_events = None   # set to (start, rollout done, end) torch.cuda.Events to time the phases
         self.perm = torch.zeros(self.units, dtype=torch.int32, device=dev)
+        self.perm_work = torch.zeros(max(1, permutation_work_bytes(self.units) // 4), dtype=torch.int32, device=dev)
         # rollout storage (time-major)
         self.crop = torch.zeros((T + 1, n, crop, crop), dtype=torch.int16, device=dev)
         self.scan = torch.zeros((T + 1, n, R), device=dev)
@@ -86,7 +87,7 @@ class PPOTrainer:
 
     def _shuffle(self, it: int, e: int) -> torch.Tensor:
         """The permutation of epoch e of iteration `it` (library generator, into self.perm)."""
-        return permutation(self.units, self.seed, it * self.epochs + e, out=self.perm)
+        return permutation(self.units, self.seed, it * self.epochs + e, out=self.perm, work=self.perm_work)
 
     def iteration(self) -> None:
         """One rollout of T steps and `epochs` update passes (all launches on the current stream)."""

@@ -128,8 +128,20 @@ def test_rollout_call_own_draws_equal_fed_draws(oracle_mod):
 
 @pytest.mark.parametrize("n", [1, 2, 3, 5, 17, 1000, 18000, 98304, 131073])
 def test_permutation_equals_oracle(oracle_mod, n):
-    from paper_2603_25834_amd.policy import permutation
+    from paper_2603_25834_amd.policy import permutation, permutation_work_bytes
     p = permutation(n, SEED, 3).cpu().numpy()
     want = oracle_mod.permute(n, SEED, 3)
     assert np.array_equal(p, want)
     assert np.array_equal(np.sort(p), np.arange(n))
+    # the tabulated form (workspace of the whole Feistel domain) is the same permutation
+    wb = permutation_work_bytes(n)
+    b = 2
+    while (1 << b) < n:
+        b += 2
+    assert wb == 4 << b
+    work = torch.full((wb // 4 + 3,), -1, dtype=torch.int32, device="cuda")
+    q = permutation(n, SEED, 3, work=work[:wb // 4]).cpu().numpy()
+    assert np.array_equal(q, want)
+    assert int(work[wb // 4:].min()) == -1 and int(work[wb // 4:].max()) == -1   # nothing past the workspace
+    with pytest.raises(Exception, match="work_bytes"):
+        permutation(n, SEED, 3, work=work[:wb // 4 - 1])
