@@ -199,13 +199,33 @@ struct MotionOut {
   int32_t collided, closed;
 };
 
-// Motion, collision, EKF predict and loop closure of robot r (one thread).  The proximity part of the
-// collision test is done here when `proximity` is set; the fused step does it with the whole workgroup.
-__device__ MotionOut robot_motion(const EnvParams& P, const StepArgs& A, int32_t r, bool proximity) {
+// The step's five motion normals of robot r (odometry x, y, theta; loop-closure x, y), drawn by five
+// lanes of a wave at once and gathered in every lane of the group of eight that holds `lane0`
+// (a library draw is a long dependent chain; one lane drawing all five would wait for five).
+struct MotionDraws {
+  float g[5];
+  __device__ __forceinline__ float operator()(int k) const { return g[k]; }
+};
+
+__device__ __forceinline__ MotionDraws motion_draws(const EnvParams& P, const StepArgs& A, int32_t r, bool valid,
+                                                    int lane0) {
+  const int sub = (int)(threadIdx.x & 63) - lane0;
+  float gk = 0.0f;
+  if (valid && sub >= 0 && sub < 5) gk = step_noise(P, A, r)(sub);
+  MotionDraws d;
+#pragma unroll
+  for (int k = 0; k < 5; ++k) d.g[k] = __shfl(gk, lane0 + k, 64);
+  return d;
+}
+
+// Motion, collision, EKF predict and loop closure of robot r (one thread, with the robot's draws).  The
+// proximity part of the collision test is done here when `proximity` is set; the fused step does it
+// with the whole workgroup.
+__device__ MotionOut robot_motion(const EnvParams& P, const StepArgs& A, int32_t r, bool proximity,
+                                  const MotionDraws& g) {
   const RobotMeta m = P.meta[r];
   const int32_t s = m.side;
   const float a0 = A.actions[2 * r], a1 = A.actions[2 * r + 1];
-  const StepNoise g = step_noise(P, A, r);
   float v = fminf(fmaxf(a0, 0.0f), P.v_max);
   float w = fminf(fmaxf(a1, -P.w_max), P.w_max);
   if (v != v) v = 0.0f;
@@ -914,10 +934,15 @@ __device__ void update_and_reward(const EnvParams& P, const StepArgs& A, const R
 
 // ---------------------------------------------------------------- kernels
 
+// Eight lanes per robot: five draw its normals, the first one moves it.
+constexpr int kMotionLanes = 8;
+
 __global__ void k_motion(EnvParams P, StepArgs A) {
-  const int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= P.n) return;
-  robot_motion(P, A, r, true);
+  const int32_t r = (int32_t)((blockIdx.x * blockDim.x + threadIdx.x) / kMotionLanes);
+  const int lane0 = (int)(threadIdx.x & 63) & ~(kMotionLanes - 1);
+  const MotionDraws g = motion_draws(P, A, r, r < P.n, lane0);
+  if (r >= P.n || (threadIdx.x & (kMotionLanes - 1)) != 0) return;
+  robot_motion(P, A, r, true, g);
 }
 
 template <int NT>
@@ -988,16 +1013,19 @@ __device__ __forceinline__ void fused_robot(const EnvParams& P, const StepArgs& 
                                             const LdsView& V, int32_t r) {
   RobotShared* sh = V.sh;
   const RobotMeta m = P.meta[r];
-  if (threadIdx.x == 0) {
-    const MotionOut o = robot_motion(P, A, r, false);
-    sh->tox = o.tox; sh->toy = o.toy; sh->ib_t = o.ib_t;
-    sh->eox = o.eox; sh->eoy = o.eoy; sh->ib_e = o.ib_e;
-    sh->collided = o.collided;
-    sh->cnt_march = 0;
-    sh->cnt_upd = 0;
-    sh->dmin_bits = 0x7f800000;
-    sh->near = 0;
-    init_bbox(sh);
+  if (threadIdx.x < 64) {   // wave 0: lanes 0..4 draw the normals, lane 0 moves the robot
+    const MotionDraws g = motion_draws(P, A, r, true, 0);
+    if (threadIdx.x == 0) {
+      const MotionOut o = robot_motion(P, A, r, false, g);
+      sh->tox = o.tox; sh->toy = o.toy; sh->ib_t = o.ib_t;
+      sh->eox = o.eox; sh->eoy = o.eoy; sh->ib_e = o.ib_e;
+      sh->collided = o.collided;
+      sh->cnt_march = 0;
+      sh->cnt_upd = 0;
+      sh->dmin_bits = 0x7f800000;
+      sh->near = 0;
+      init_bbox(sh);
+    }
   }
   __syncthreads();
   // the paper's proximity collision (the move stands), one cell per thread
@@ -1305,7 +1333,7 @@ __global__ void k_fl_reset(int32_t n, FixedLag F, const float* init_pose, const 
 template <int NT>
 hipError_t fixedlag_nt(const EnvParams& P, const StepArgs& A, const LdsPlan& L, const FixedLag& F, hipStream_t st) {
   const int blocks = (P.n + 255) / 256;
-  k_motion<<<blocks, 256, 0, st>>>(P, A);
+  k_motion<<<(unsigned)(((int64_t)P.n * kMotionLanes + 255) / 256), 256, 0, st>>>(P, A);
   k_march<NT><<<P.n, NT, L.total, st>>>(P, A, L);
   const int64_t items = (int64_t)P.n * P.R;
   k_fl_prep<<<(unsigned)std::min<int64_t>(4096, (items + 255) / 256), 256, 0, st>>>(P, F);
@@ -1326,7 +1354,7 @@ hipError_t fixedlag_nt(const EnvParams& P, const StepArgs& A, const LdsPlan& L, 
 
 template <int NT>
 hipError_t plain_nt(const EnvParams& P, const StepArgs& A, const LdsPlan& L, hipStream_t st) {
-  k_motion<<<(P.n + 255) / 256, 256, 0, st>>>(P, A);
+  k_motion<<<(unsigned)(((int64_t)P.n * kMotionLanes + 255) / 256), 256, 0, st>>>(P, A);
   k_march<NT><<<P.n, NT, L.total, st>>>(P, A, L);
   k_update<NT><<<P.n, NT, L.total, st>>>(P, A, L);
   return hipGetLastError();

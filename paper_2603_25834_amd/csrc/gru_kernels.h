@@ -168,6 +168,9 @@ __global__ __launch_bounds__(256) void k_gru_heads(const float* prm, Offsets o, 
     s1 += __shfl_xor(s1, off, 64);
     sv += __shfl_xor(sv, off, 64);
   }
+  // the row's two normals on lanes 0 and 1 at once (a library draw is a long dependent chain)
+  const float ed = lane < 2 ? eps(row, lane) : 0.0f;
+  const float e1 = __shfl(ed, 1, 64);
   if (lane == 0) {
     const float m0 = s0 + prm[o.mub], m1 = s1 + prm[o.mub + 1];
     if (mu) {
@@ -176,7 +179,7 @@ __global__ __launch_bounds__(256) void k_gru_heads(const float* prm, Offsets o, 
     }
     value[row] = sv + prm[o.vb];
     const float ls0 = prm[o.lstd], ls1 = prm[o.lstd + 1];
-    const float e0 = eps(row, 0), e1 = eps(row, 1);
+    const float e0 = ed;
     act[2 * row] = m0 + expf(ls0) * e0;
     act[2 * row + 1] = m1 + expf(ls1) * e1;
     logp[row] = -0.5f * (e0 * e0 + e1 * e1) - (ls0 + ls1) - 1.8378770664093453f;

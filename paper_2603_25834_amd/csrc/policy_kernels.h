@@ -672,6 +672,10 @@ __global__ __launch_bounds__(256) void k_fwd_tail(const float* prm, Offsets o, c
   const int row0 = blockIdx.x * kTailRows;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
   const float* b1 = prm + o.f1b;
+  // the sample's normals of the wave's rows (4 w .. 4 w + 3, two each), one per lane 0..7, drawn up
+  // front: a library draw is a long dependent chain that the loads and MFMAs below can hide
+  float my_eps = 0.0f;
+  if (sample && lane < 8 && row0 + 4 * wave + (lane >> 1) < B) my_eps = eps(row0 + 4 * wave + (lane >> 1), lane & 1);
   for (int g = threadIdx.x; g < kTailRows * (kHid / 8); g += 256) {
     const int r = g / (kHid / 8), n0 = (g % (kHid / 8)) * 8;
     const int64_t m = row0 + r;
@@ -762,6 +766,7 @@ __global__ __launch_bounds__(256) void k_fwd_tail(const float* prm, Offsets o, c
       s1 += __shfl_xor(s1, off, 64);
       sv += __shfl_xor(sv, off, 64);
     }
+    const float e0 = __shfl(my_eps, 2 * rr, 64), e1 = __shfl(my_eps, 2 * rr + 1, 64);
     if (lane == 0) {
       const float m0 = s0 + bmu0, m1 = s1 + bmu1;
       if (mu_out) {
@@ -771,7 +776,6 @@ __global__ __launch_bounds__(256) void k_fwd_tail(const float* prm, Offsets o, c
       v_out[row] = sv + bv;
       if (sample) {
         const float ls0 = prm[o.lstd], ls1 = prm[o.lstd + 1];
-        const float e0 = eps(row, 0), e1 = eps(row, 1);
         act[2 * row] = m0 + expf(ls0) * e0;
         act[2 * row + 1] = m1 + expf(ls1) * e1;
         logp[row] = -0.5f * (e0 * e0 + e1 * e1) - (ls0 + ls1) - 1.8378770664093453f;
