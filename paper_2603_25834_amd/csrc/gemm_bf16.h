@@ -59,6 +59,32 @@ __device__ __forceinline__ uint16_t lane16(const uint4& v, int j) {
 // engine issues those reads at kernel start, so their latency hides behind the
 // main loop (others declare kPrefetch = false).
 
+// Several products in one launch (the split-precision forward: hi x hi, hi x lo, lo x hi into
+// consecutive groups of K slices): an operand given as HiLo reads its `lo` matrix in product p when
+// bit p of lo_mask is set, else its `hi` matrix; the workgroup's z index runs over the products'
+// slice groups (product = z / slices per product).  A plain loader is the same in every product.
+template <class L>
+struct HiLo {
+  L hi, lo;
+  unsigned lo_mask;
+};
+
+template <class L>
+__device__ __forceinline__ L bind_product(const L& l, int) { return l; }
+template <class L>
+__device__ __forceinline__ L bind_product(const HiLo<L>& l, int p) { return ((l.lo_mask >> p) & 1u) ? l.lo : l.hi; }
+
+template <class L>
+struct BoundT {
+  using type = L;
+};
+template <class L>
+struct BoundT<HiLo<L>> {
+  using type = L;
+};
+template <class L>
+using Bound = typename BoundT<L>::type;
+
 // LDS elements of one stage of an operand with ROWS rows ([row][k], rows padded by 8).
 template <bool KMAJOR, int ROWS, int BK>
 struct Stage {
@@ -265,8 +291,11 @@ __device__ __forceinline__ TileId xcd_tile() {
   return t;
 }
 
-template <int BM, int BN, int BK, int WM, int WN, class LA, class LB, class EPI>
-__global__ __launch_bounds__(256) void k_gemm(LA la, LB lb, EPI epi, int M, int N, int K, int k_split) {
+template <int BM, int BN, int BK, int WM, int WN, class LA0, class LB0, class EPI>
+__global__ __launch_bounds__(256) void k_gemm(LA0 la0, LB0 lb0, EPI epi, int M, int N, int K, int k_split,
+                                              int zper) {
+  using LA = Bound<LA0>;
+  using LB = Bound<LB0>;
   using C = Cfg<BM, BN, BK, WM, WN>;
   using SA = Stage<LA::kMajor, BM, BK>;
   using SB = Stage<LB::kMajor, BN, BK>;
@@ -278,8 +307,11 @@ __global__ __launch_bounds__(256) void k_gemm(LA la, LB lb, EPI epi, int M, int 
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int wm = wave / WN, wn = wave % WN;
   const TileId tile = xcd_tile();
+  const int prod = zper > 0 ? tile.tz / zper : 0;
+  const LA la = bind_product(la0, prod);
+  const LB lb = bind_product(lb0, prod);
   const int m_blk = tile.tm * BM, n_blk = tile.tn * BN;   // M tiles on x (up to 2^31 - 1)
-  const int kb = tile.tz * k_split;
+  const int kb = (tile.tz - prod * zper) * k_split;
   const int ke = min(K, kb + k_split);
   f32x4 acc[C::FM][C::FN];
 #pragma unroll
@@ -400,16 +432,21 @@ __global__ __launch_bounds__(256) void k_gemm(LA la, LB lb, EPI epi, int M, int 
   }
 }
 
+// `products` products (HiLo operands) of `splits` K slices each, slice z of product p at z index
+// p * nz + z (nz = the slices K actually splits into).
 template <int BM, int BN, int BK, int WM, int WN, class LA, class LB, class EPI>
-hipError_t run(const LA& la, const LB& lb, const EPI& epi, int M, int N, int K, int splits, hipStream_t st) {
+hipError_t run(const LA& la, const LB& lb, const EPI& epi, int M, int N, int K, int splits, hipStream_t st,
+               int products = 1) {
   if (M <= 0 || N <= 0) return hipSuccess;
   if (splits < 1) splits = 1;
+  if (products < 1) products = 1;
   int k_split = (K + splits - 1) / splits;
   k_split = (k_split + BK - 1) / BK * BK;
   const int nz = K > 0 ? (K + k_split - 1) / k_split : 1;
-  if ((N + BN - 1) / BN > 65535 || nz > 65535) return hipErrorInvalidValue;
-  dim3 grid((M + BM - 1) / BM, (N + BN - 1) / BN, nz);
-  k_gemm<BM, BN, BK, WM, WN, LA, LB, EPI><<<grid, 256, 0, st>>>(la, lb, epi, M, N, K, k_split);
+  if ((N + BN - 1) / BN > 65535 || (int64_t)nz * products > 65535) return hipErrorInvalidValue;
+  dim3 grid((M + BM - 1) / BM, (N + BN - 1) / BN, nz * products);
+  k_gemm<BM, BN, BK, WM, WN, LA, LB, EPI><<<grid, 256, 0, st>>>(la, lb, epi, M, N, K, k_split,
+                                                                 products > 1 ? nz : 0);
   return hipGetLastError();
 }
 

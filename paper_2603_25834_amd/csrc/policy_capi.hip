@@ -178,14 +178,13 @@ int encode_fc1(aslam_policy* P, const float* prm, const int16_t* crop, const flo
   const int tiles = ((B + 127) / 128) * (kHid / 128);
   const int S = std::max(1, std::min(32, kFc1MinBlocks / tiles));
   if (P->prec) {
-    // x_hi W_hi, x_hi W_lo and x_lo W_hi, each split S ways, into consecutive groups of slices
+    // x_hi W_hi, x_hi W_lo and x_lo W_hi, each split S ways, into consecutive groups of slices (one
+    // launch: product 1 reads W's lo part, product 2 x's)
     const int nz = slices_used(K1, S, 64);
     const int64_t slice = (int64_t)B * kHid;
-    PCHK((gemm::run<128, 128, 64, 2, 2>(xa, wa, EpiPartial{P->part, kHid, slice}, B, kHid, K1, S, st)));
-    PCHK((gemm::run<128, 128, 64, 2, 2>(xa, LdBF16K{P->w1b_lo, K1, kHid, K1}, EpiPartial{P->part + nz * slice, kHid, slice},
-                                         B, kHid, K1, S, st)));
-    PCHK((gemm::run<128, 128, 64, 2, 2>(LdBF16K{P->x_lo, K1, B, K1}, wa,
-                                         EpiPartial{P->part + 2 * nz * slice, kHid, slice}, B, kHid, K1, S, st)));
+    PCHK((gemm::run<128, 128, 64, 2, 2>(gemm::HiLo<LdBF16K>{xa, LdBF16K{P->x_lo, K1, B, K1}, 4u},
+                                         gemm::HiLo<LdBF16K>{wa, LdBF16K{P->w1b_lo, K1, kHid, K1}, 2u},
+                                         EpiPartial{P->part, kHid, slice}, B, kHid, K1, S, st, 3)));
     *S_used = 3 * nz;
   } else if (S == 1) {
     PCHK((gemm::run<128, 128, 64, 2, 2>(xa, wa, EpiBiasReluBF16{P->h1, prm + o.f1b, kHid}, B, kHid, K1, 1, st)));
@@ -215,13 +214,11 @@ int forward_core(aslam_policy* P, const float* prm, const int16_t* crop, const f
   }
   const LdBF16K ha{P->h1, kHid, B, kHid}, wb{P->w2b, kHid, kHid, kHid};
   if (P->prec) {
-    // z2 = h1_hi W2_hi + h1_hi W2_lo + h1_lo W2_hi (+ b2), one slice per product
+    // z2 = h1_hi W2_hi + h1_hi W2_lo + h1_lo W2_hi (+ b2), one slice per product, one launch
     const int64_t slice = (int64_t)B * kHid;
-    PCHK((gemm::run<128, 128, 64, 2, 2>(ha, wb, EpiPartial{P->part, kHid, slice}, B, kHid, kHid, 1, st)));
-    PCHK((gemm::run<128, 128, 64, 2, 2>(ha, LdBF16K{P->w2b_lo, kHid, kHid, kHid}, EpiPartial{P->part + slice, kHid, slice},
-                                       B, kHid, kHid, 1, st)));
-    PCHK((gemm::run<128, 128, 64, 2, 2>(LdBF16K{P->h1_lo, kHid, B, kHid}, wb,
-                                       EpiPartial{P->part + 2 * slice, kHid, slice}, B, kHid, kHid, 1, st)));
+    PCHK((gemm::run<128, 128, 64, 2, 2>(gemm::HiLo<LdBF16K>{ha, LdBF16K{P->h1_lo, kHid, B, kHid}, 4u},
+                                       gemm::HiLo<LdBF16K>{wb, LdBF16K{P->w2b_lo, kHid, kHid, kHid}, 2u},
+                                       EpiPartial{P->part, kHid, slice}, B, kHid, kHid, 1, st, 3)));
     const int64_t groups = (int64_t)B * (kHid / 8);
     k_reduce_bias_f32<<<(int)std::min<int64_t>(4096, (groups + 255) / 256), 256, 0, st>>>(P->part, 3, B, kHid,
                                                                                           prm + o.f2b, P->z2, kHid);
