@@ -497,14 +497,17 @@ def autotune_forms(wb) -> tuple:
     out = (wb.ranges, wb.reward, wb.done)
     rf = tune(wb.env, A, None, *out, candidates=default_candidates(wb.env), force=True)
     fused = dict(rf["best"])
-    rp = tune(wb.env, A, None, *out, candidates=[Candidate(t, form=_lib.FORM_PLAIN) for t in THREADS], force=True)
+    rp = tune(wb.env, A, None, *out, candidates=[Candidate(t, form=_lib.FORM_PLAIN, mark_seg=g) for t in THREADS
+                                                  for g in (0, 32)], force=True)
     plain = dict(rp["best"])
     wb.env.set_exec(**fused)
     wb.env.reset(wb.world, wb.start)
-    summary = {"fused_us": {f"{r['candidate']['threads']}/{r['candidate']['band_rows']}/{r['candidate']['grid']}":
-                            round(r["us_per_step"], 1) for r in rf["table"] if r["us_per_step"] is not None},
-               "plain_us": {str(r["candidate"]["threads"]): round(r["us_per_step"], 1)
-                            for r in rp["table"] if r["us_per_step"] is not None}}
+    # keys threads/band/grid/mark_seg
+    key = lambda c: f"{c['threads']}/{c['band_rows']}/{c['grid']}/{c['mark_seg']}"
+    summary = {"fused_us": {key(r["candidate"]): round(r["us_per_step"], 1) for r in rf["table"]
+                            if r["us_per_step"] is not None},
+               "plain_us": {key(r["candidate"]): round(r["us_per_step"], 1) for r in rp["table"]
+                            if r["us_per_step"] is not None}}
     return fused, plain, summary
 
 

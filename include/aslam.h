@@ -139,6 +139,8 @@ typedef struct {
   int32_t grid;          /* FUSED: workgroups launched; 0 = one per robot */
   int32_t record_rays;   /* FUSED: also write per-ray rho_q / hit_cell to the state (PLAIN always does) */
   int32_t lds_bytes;     /* LDS budget per workgroup; 0 = device maximum */
+  int32_t mark_seg;      /* map update's walk: 0 = one lane per ray; k in [8, 1024] = the rays cut into
+                            segments of k steps shared out over the lanes (results are identical) */
 } aslam_exec_config;
 
 /* Create n_robots environments.  sides_host[n_robots]: grid side of each

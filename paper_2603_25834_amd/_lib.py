@@ -57,7 +57,8 @@ class CsmConfig(ctypes.Structure):
 
 
 class ExecConfig(ctypes.Structure):
-    _fields_ = [(n, ctypes.c_int32) for n in ("form", "threads", "band_rows", "grid", "record_rays", "lds_bytes")]
+    _fields_ = [(n, ctypes.c_int32) for n in ("form", "threads", "band_rows", "grid", "record_rays", "lds_bytes",
+                                              "mark_seg")]
 
 
 _P = ctypes.c_void_p

@@ -2,7 +2,9 @@
 
 The step's cost depends on how a robot's ray fan is spread over a workgroup
 (threads per robot, i.e. rays per lane and waves per robot), on the band of
-code-window rows staged in LDS at once, and on the persistent grid size.  The
+code-window rows staged in LDS at once, on the persistent grid size, and on
+whether the map update walks one ray per lane or shares segments of all rays
+out over the lanes (shorter walks per lane, a setup per segment).  The
 best choice moves with the grid sides, the ray count and the range, so it is
 measured: every candidate runs a few steps of the caller's own batch, timed
 with HIP events on the stream the steps are launched on, and the fastest one
@@ -36,6 +38,7 @@ class Candidate:
     band_rows: int = 0      # 0: the largest band the LDS budget allows
     grid: int = 0           # 0: one workgroup per robot
     form: int = _lib.FORM_FUSED
+    mark_seg: int = 0       # map update's walk: 0 one lane per ray, else segments of this many steps
 
 
 def signature(env: Env) -> str:
@@ -51,18 +54,21 @@ def signature(env: Env) -> str:
     return "/".join(parts)
 
 
+MARK_SEGS = (32, 64)
+
+
 def default_candidates(env: Env) -> list[Candidate]:
-    """Threads per robot over the supported set; for grids whose code window
-    needs several bands, also half-height bands; a persistent grid of a few
-    workgroups per CU besides one workgroup per robot."""
+    """Threads per robot over the supported set, each with one lane per ray and with segmented walks in
+    the map update; for grids whose code window needs several bands, also half-height bands; a
+    persistent grid of a few workgroups per CU besides one workgroup per robot."""
     _, cus = device_info()
-    cands = [Candidate(t) for t in THREADS]
+    cands = [Candidate(t) for t in THREADS] + [Candidate(t, mark_seg=g) for t in THREADS for g in MARK_SEGS]
     if env.n > 4 * cus:
-        cands += [Candidate(t, grid=k * cus) for t in (256, 512) for k in (2, 4)]
+        cands += [Candidate(t, grid=k * cus, mark_seg=g) for t in (256, 512) for k in (2, 4) for g in (0, 32)]
     env.set_exec(form=_lib.FORM_FUSED, threads=256)
     band = env.get_exec()["band_rows"]
     if band < int(env.sides.max()) and band >= 16:
-        cands += [Candidate(t, band_rows=band // 2) for t in (256, 512)]
+        cands += [Candidate(t, band_rows=band // 2, mark_seg=g) for t in (256, 512) for g in (0, 32)]
     return cands
 
 
@@ -90,7 +96,7 @@ _MEMO: dict = {}
 
 
 def _time_candidate(env: Env, c: Candidate, actions, noise, ranges, reward, done, warmup: int, steps: int) -> float:
-    env.set_exec(form=c.form, threads=c.threads, band_rows=c.band_rows, grid=c.grid)
+    env.set_exec(form=c.form, threads=c.threads, band_rows=c.band_rows, grid=c.grid, mark_seg=c.mark_seg)
     for t in range(warmup):
         env.step(actions[t % len(actions)], None if noise is None else noise[t % len(noise)], ranges, reward, done)
     e0 = torch.cuda.Event(enable_timing=True)
@@ -117,7 +123,8 @@ def tune(env: Env, actions: torch.Tensor, noise: torch.Tensor | None, ranges: to
     hit = None if force else (_MEMO.get(key) or cache.get(key))
     if hit is not None:
         best = Candidate(**hit["best"])
-        env.set_exec(form=best.form, threads=best.threads, band_rows=best.band_rows, grid=best.grid)
+        env.set_exec(form=best.form, threads=best.threads, band_rows=best.band_rows, grid=best.grid,
+                     mark_seg=best.mark_seg)
         return dict(hit, cached=True)
     cands = candidates if candidates is not None else default_candidates(env)
     table = []
@@ -133,7 +140,8 @@ def tune(env: Env, actions: torch.Tensor, noise: torch.Tensor | None, ranges: to
         raise RuntimeError("autotune: no candidate ran")
     best_row = min(timed, key=lambda r: r["us_per_step"])
     best = Candidate(**best_row["candidate"])
-    env.set_exec(form=best.form, threads=best.threads, band_rows=best.band_rows, grid=best.grid)
+    env.set_exec(form=best.form, threads=best.threads, band_rows=best.band_rows, grid=best.grid,
+                     mark_seg=best.mark_seg)
     out = {"signature": key, "best": asdict(best), "us_per_step": best_row["us_per_step"], "table": table}
     _MEMO[key] = out
     cache.put(key, out)

@@ -193,14 +193,15 @@ int validate_config(const aslam_env_config* c) {
   return ASL_OK;
 }
 
-// LDS plan: lut | rho | shared | union(world rows, code bitmaps of one band).
+// LDS plan: lut | rho | perm | seg | shared | union(world rows, code bitmaps of one band).
 int plan_lds(aslam_env* e, const aslam_exec_config& ex, LdsPlan& L) {
   const int32_t lc = e->P.lclamp;
   const int32_t rhat_cells = e->P.rhat_cells;
   L.off_lut = 0;
   L.off_rho = (int32_t)align_up((2 * lc + 1) * 4, 16);
   L.off_perm = L.off_rho + (int32_t)align_up(e->cfg.n_rays * 4, 16);
-  L.off_hist = L.off_perm + (int32_t)align_up(e->cfg.n_rays * 4, 16);
+  L.off_seg = L.off_perm + (int32_t)align_up(e->cfg.n_rays * 4, 16);
+  L.off_hist = L.off_seg + (int32_t)align_up(e->cfg.n_rays * 4, 16);
   L.off_misc = L.off_hist + 256;
   L.off_union = L.off_misc + 256;
   L.world_halo = rhat_cells + 3;
@@ -227,6 +228,7 @@ int plan_lds(aslam_env* e, const aslam_exec_config& ex, LdsPlan& L) {
   L.union_bytes = (int32_t)std::max<int64_t>(world_max, 8 * band * nw_max + 16);
   L.total = L.off_union + L.union_bytes;
   L.record = ex.record_rays;
+  L.mark_seg = ex.mark_seg;
   return ASL_OK;
 }
 
@@ -514,6 +516,7 @@ int aslam_env_create(const aslam_env_config* cfg, int32_t n_robots, const int32_
   ex.band_rows = 0;
   ex.grid = 0;
   ex.record_rays = 0;
+  ex.mark_seg = 0;
   ex.lds_bytes = 0;
   rc = aslam_env_set_exec(e, &ex);
   if (rc) {
@@ -544,6 +547,8 @@ int aslam_env_set_exec(aslam_env* env, const aslam_exec_config* ex) {
   if (ex->threads != 128 && ex->threads != 192 && ex->threads != 256 && ex->threads != 384 && ex->threads != 512)
     return fail(ASL_EINVAL, "threads must be 128, 192, 256, 384 or 512");
   if (ex->grid < 0 || ex->band_rows < 0 || ex->lds_bytes < 0) return fail(ASL_EINVAL, "negative exec field");
+  if (ex->mark_seg != 0 && (ex->mark_seg < 8 || ex->mark_seg > 1024))
+    return fail(ASL_EINVAL, "mark_seg must be 0 or in [8, 1024]");
   LdsPlan L{};
   int rc = plan_lds(env, *ex, L);
   if (rc) return rc;

@@ -127,12 +127,13 @@ struct StepArgs {
 
 // LDS plan of the per-robot kernels (byte offsets into dynamic LDS).
 struct LdsPlan {
-  int32_t off_lut, off_rho, off_perm, off_hist, off_misc, off_union;
+  int32_t off_lut, off_rho, off_perm, off_seg, off_hist, off_misc, off_union;
   int32_t total;
   int32_t union_bytes;
   int32_t band_rows;      // code-window rows per pass
   int32_t world_halo;     // rows staged around the robot: rhat_cells + 3
   int32_t record;         // fused: write rho / hitc to the state
+  int32_t mark_seg;       // map update's walk: 0 one lane per ray, else segments of this many steps
 };
 
 struct ExecState;

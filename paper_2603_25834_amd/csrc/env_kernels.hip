@@ -377,7 +377,8 @@ struct RobotShared {
 struct LdsView {
   uint32_t* lut;     // binary entropy table
   int32_t* rho;      // [R] range (Q16) | bit 31 = hit
-  int32_t* perm;     // [R] ray of each lane slot, longest walk first
+  int32_t* perm;     // [R] ray of each lane slot, longest walk first (march); steps of each ray (mark)
+  int32_t* seg;      // [R] first walk segment of each ray (mark)
   int32_t* hist;     // [64] sort buckets
   RobotShared* sh;
   uint32_t* uni;     // world rows, then the code bitmaps
@@ -388,6 +389,7 @@ __device__ __forceinline__ LdsView lds_view(unsigned char* smem, const LdsPlan& 
   v.lut = reinterpret_cast<uint32_t*>(smem + L.off_lut);
   v.rho = reinterpret_cast<int32_t*>(smem + L.off_rho);
   v.perm = reinterpret_cast<int32_t*>(smem + L.off_perm);
+  v.seg = reinterpret_cast<int32_t*>(smem + L.off_seg);
   v.hist = reinterpret_cast<int32_t*>(smem + L.off_hist);
   v.sh = reinterpret_cast<RobotShared*>(smem + L.off_misc);
   v.uni = reinterpret_cast<uint32_t*>(smem + L.off_union);
@@ -790,9 +792,205 @@ __device__ __forceinline__ void apply_band(const EnvParams& P, const uint32_t* m
 
 constexpr int kApplyInFlight = 4;
 
+// The map update's mark pass over one band: the MISS bit of every cell the walks of all rays visit
+// inside the band and the HIT bit of each hit's last cell, for rays from the Q16 origin (eox, eoy)
+// with heading index ib of ray 0 and the ranges of rho_lds; bit index (cy - by0) * rowbits + (cx - x0w).
+// Two forms with identical results.  One lane per ray (mark_rays): lane slots ordered by the walk
+// length, so a wave's trip count stays close to its lanes' own; the pass lasts as long as the longest
+// walk.  Segments (mark_segments): a ray of n steps is cut into ceil(n / seg) segments and the lanes
+// take the segments of all rays in turn, so the pass lasts about (total steps / lanes) steps plus a
+// setup per segment; a segment starts from the DDA state after i0 steps in closed form: with the
+// decision variable after i >= 1 steps in (-DY, DX] and equal to D0 + kx DX - (i - kx) DY, kx (the
+// x steps among them) is floor((i DY - D0 + DX) / (DX + DY)).  Which is faster depends on how many
+// robots share a CU (measured by the autotuner).
+// Lane slots ordered by the walk length estimated from the range (once for all bands of mark_rays).
+template <int NT>
+__device__ void sort_mark_rays(const EnvParams& P, const int32_t* rho_lds, int32_t* perm, int32_t* hist, int32_t ib) {
+  sort_rays<NT>(P.R, perm, hist, [&](int32_t k) {
+    const int32_t dv = ray_dir(P, ib, k);
+    const int32_t ab = abs((int32_t)(int16_t)(dv & 0xffff)) + abs(dv >> 16);
+    return (int32_t)((((int64_t)(rho_lds[k] & 0x7fffffff) >> 16) * ab) >> 16);
+  });
+}
+
+// perm: the lane slots of sort_mark_rays.
+template <int NT>
+__device__ void mark_rays(const EnvParams& P, const int32_t* rho_lds, const int32_t* perm, int32_t s, int32_t eox,
+                          int32_t eoy, int32_t ib, int32_t by0, int32_t x0w, int32_t rowbits, uint32_t band_bits,
+                          bool one_band, bool count_visits, uint32_t* miss, uint32_t* hitm, int32_t& uvisits) {
+  const int32_t ecx = eox >> 16, ecy = eoy >> 16;
+  for (int32_t k0 = 0; k0 < P.R; k0 += NT) {
+    const int32_t j = k0 + (int32_t)threadIdx.x;
+    const bool valid = j < P.R;
+    const int32_t k = valid ? perm[j] : 0;
+    RaySetup q{};
+    int32_t wi = 0, sx = 0, sy = 0, D = 0, n = -1;
+    bool hit = false;
+    if (valid) {
+      const int32_t pk = rho_lds[k];
+      hit = pk < 0;
+      const int32_t dv = ray_dir(P, ib, k);
+      const int32_t a = (int16_t)(dv & 0xffff), b = dv >> 16;
+      q = ray_setup(eox, eoy, a, b, pk & 0x7fffffff, s);
+      wi = (ecy - by0) * rowbits + (ecx - x0w);
+      sx = a > 0 ? 1 : -1;
+      sy = b > 0 ? rowbits : -rowbits;
+      D = q.D;
+      n = q.n;
+      if ((uint32_t)wi < band_bits) atomicOr(&miss[wi >> 5], 1u << (wi & 31));
+    }
+    const int32_t w0 = wi;
+    // Uniform trip counts over the wave.  While every lane is within its
+    // own count and the band holds the whole window, every step lands in
+    // the bitmap (the window holds every visited cell), so the first
+    // loop marks without tests; the word index is clamped only to keep
+    // the store inside the bitmap.  The second loop finishes the longer
+    // walks, testing each step.
+    const int32_t nmax = wave_max_i32(n);
+    const int32_t nmin = one_band ? wave_min_i32(valid ? n : 0) : 0;
+    const uint32_t last_word = (band_bits >> 5) - 1u;
+    int32_t i = 0;
+    for (; i < nmin; ++i) {
+      const bool stepx = D <= 0;
+      wi += stepx ? sx : sy;
+      D += stepx ? q.DX : -q.DY;
+      atomicOr(&miss[min((uint32_t)wi >> 5, last_word)], 1u << (wi & 31));
+    }
+    for (; i < nmax; ++i) {
+      const bool stepx = D <= 0;
+      wi += stepx ? sx : sy;
+      D += stepx ? q.DX : -q.DY;
+      if (i < n && (uint32_t)wi < band_bits) atomicOr(&miss[wi >> 5], 1u << (wi & 31));
+    }
+    if (valid) {
+      if (count_visits) uvisits += n + 1;
+      const int32_t we = w0 + q.kx * sx + q.ky * sy;   // last visited cell
+      if (hit && !q.gend && (uint32_t)we < band_bits) atomicOr(&hitm[we >> 5], 1u << (we & 31));
+    }
+  }
+}
+
+// nray and segoff: [R] LDS scratch.
+template <int NT>
+__device__ void mark_segments(const EnvParams& P, const int32_t* rho_lds, int32_t* nray, int32_t* segoff,
+                              int32_t* hist, int32_t s, int32_t eox, int32_t eoy, int32_t ib, int32_t by0, int32_t x0w,
+                              int32_t rowbits, uint32_t band_bits, bool one_band, bool count_visits, int32_t seg,
+                              uint32_t* miss, uint32_t* hitm, int32_t& uvisits) {
+  constexpr int NWAVE = NT / 64;
+  const int32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int32_t R = P.R;
+  const int32_t w0 = ((eoy >> 16) - by0) * rowbits + ((eox >> 16) - x0w);   // the origin cell
+  // per ray: its step count, the HIT bit of its last cell, its visits
+  for (int32_t k = tid; k < R; k += NT) {
+    const int32_t pk = rho_lds[k];
+    const int32_t dv = ray_dir(P, ib, k);
+    const int32_t a = (int16_t)(dv & 0xffff), b = dv >> 16;
+    const RaySetup q = ray_setup(eox, eoy, a, b, pk & 0x7fffffff, s);
+    nray[k] = q.n;
+    const int32_t we = w0 + q.kx * (a > 0 ? 1 : -1) + q.ky * (b > 0 ? rowbits : -rowbits);   // last visited cell
+    if (pk < 0 && !q.gend && (uint32_t)we < band_bits) atomicOr(&hitm[we >> 5], 1u << (we & 31));
+    if (count_visits) uvisits += q.n + 1;
+  }
+  if (tid == 0 && (uint32_t)w0 < band_bits) atomicOr(&miss[w0 >> 5], 1u << (w0 & 31));   // every walk's first cell
+  __syncthreads();
+  // segment offsets: exclusive prefix sum of ceil(n / seg) over the rays (each thread a run of rays)
+  const int32_t per = (R + NT - 1) / NT;
+  const int32_t k0 = min(R, tid * per), k1 = min(R, k0 + per);
+  int32_t loc = 0;
+  for (int32_t k = k0; k < k1; ++k) loc += (nray[k] + seg - 1) / seg;
+  int32_t inc = loc;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int32_t y = __shfl_up(inc, o, 64);
+    if (lane >= o) inc += y;
+  }
+  if (lane == 63) hist[wave] = inc;
+  __syncthreads();
+  int32_t run = inc - loc, nseg = 0;
+#pragma unroll
+  for (int w = 0; w < NWAVE; ++w) {
+    const int32_t t = hist[w];
+    run += w < wave ? t : 0;
+    nseg += t;
+  }
+  for (int32_t k = k0; k < k1; ++k) {
+    segoff[k] = run;
+    run += (nray[k] + seg - 1) / seg;
+  }
+  __syncthreads();
+  const uint32_t last_word = (band_bits >> 5) - 1u;
+  for (int32_t j0 = 0; j0 < nseg; j0 += NT) {
+    const int32_t j = j0 + tid;
+    const bool valid = j < nseg;
+    int32_t wi = 0, D = 0, DX = 0, DY = 0, sx = 0, sy = 0, len = 0;
+    if (valid) {
+      // the ray of segment j: the last ray whose first segment is <= j
+      int32_t lo = 0, hi = R - 1;
+      while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (segoff[mid] <= j) lo = mid;
+        else hi = mid - 1;
+      }
+      const int32_t k = lo;
+      const int32_t i0 = (j - segoff[k]) * seg;
+      len = min(seg, nray[k] - i0);
+      const int32_t dv = ray_dir(P, ib, k);
+      const int32_t a = (int16_t)(dv & 0xffff), b = dv >> 16;
+      const int32_t aa = abs(a), bb = abs(b);
+      int32_t D0;
+      if (aa == 0) { D0 = 1; }
+      else if (bb == 0) { D0 = -1; }
+      else {
+        const int32_t fx = eox & 0xffff, fy = eoy & 0xffff;
+        const int32_t ex0 = a > 0 ? kQ16 - fx : fx, ey0 = b > 0 ? kQ16 - fy : fy;
+        D0 = ex0 * bb - ey0 * aa;
+        DX = bb << 16;
+        DY = aa << 16;
+      }
+      sx = a > 0 ? 1 : -1;
+      sy = b > 0 ? rowbits : -rowbits;
+      int32_t kx = 0;
+      if (i0 > 0) {
+        if (DX + DY == 0) {
+          kx = D0 <= 0 ? i0 : 0;   // axis rays: x steps only (D = -1) or y steps only (D = 1)
+        } else {
+          // floor((i0 DY - D0 + DX) / (DX + DY)) in 32 bits: with D0 = 65536 q + rr (0 <= rr < 65536) and
+          // M = i0 aa + bb - q >= 0 it is floor(M / (aa + bb)) when rr = 0, else floor((M - 1) / (aa + bb))
+          const int32_t aa = DY >> 16, bb = DX >> 16;
+          const int32_t q = D0 >> 16, rr = D0 & 0xffff;
+          const int32_t M = i0 * aa + bb - q - (rr != 0 ? 1 : 0);
+          kx = (int32_t)((uint32_t)M / (uint32_t)(aa + bb));
+        }
+      }
+      const int32_t ky = i0 - kx;
+      wi = w0 + kx * sx + ky * sy;
+      D = D0 + (int32_t)((uint32_t)(kx * (DX >> 16) - ky * (DY >> 16)) << 16);
+    }
+    // Uniform trip counts over the wave.  While every lane is within its own segment and the band
+    // holds the whole window, every step lands in the bitmap (the window holds every visited cell),
+    // so the first loop marks without tests; the word index is clamped only to keep the store inside
+    // the bitmap.  The second loop finishes the longer segments, testing each step.
+    const int32_t nmax = wave_max_i32(len);
+    const int32_t nmin = one_band ? wave_min_i32(len) : 0;
+    int32_t i = 0;
+    for (; i < nmin; ++i) {
+      const bool stepx = D <= 0;
+      wi += stepx ? sx : sy;
+      D += stepx ? DX : -DY;
+      atomicOr(&miss[min((uint32_t)wi >> 5, last_word)], 1u << (wi & 31));
+    }
+    for (; i < nmax; ++i) {
+      const bool stepx = D <= 0;
+      wi += stepx ? sx : sy;
+      D += stepx ? DX : -DY;
+      if (i < len && (uint32_t)wi < band_bits) atomicOr(&miss[wi >> 5], 1u << (wi & 31));
+    }
+  }
+}
+
 // Map update from the estimated pose with the measured ranges, then the
 // reward.  rho_lds[k]: range (Q16) with bit 31 set when ray k hit.
-template <int NT>
+template <int NT, bool SEG>
 __device__ void update_and_reward(const EnvParams& P, const StepArgs& A, const RobotMeta& m, const LdsView& V,
                                   const LdsPlan& L, int32_t r) {
   constexpr int NWAVE = NT / 64;
@@ -816,12 +1014,7 @@ __device__ void update_and_reward(const EnvParams& P, const StepArgs& A, const R
     uint32_t* miss = uni;
     uint32_t* hitm = uni + band * nw;
     const int64_t base = m.cell_off;
-    // lane slots ordered by the walk length estimated from the range
-    sort_rays<NT>(P.R, V.perm, V.hist, [&](int32_t k) {
-      const int32_t dv = ray_dir(P, ib, k);
-      const int32_t ab = abs((int32_t)(int16_t)(dv & 0xffff)) + abs(dv >> 16);
-      return (int32_t)((((int64_t)(rho_lds[k] & 0x7fffffff) >> 16) * ab) >> 16);
-    });
+    if (!SEG) sort_mark_rays<NT>(P, rho_lds, V.perm, V.hist, ib);
     for (int32_t by0 = y0; by0 <= y1; by0 += band) {
       const int32_t rows = min(band, y1 - by0 + 1);
       const uint32_t band_bits = (uint32_t)(rows * rowbits);
@@ -832,56 +1025,12 @@ __device__ void update_and_reward(const EnvParams& P, const StepArgs& A, const R
         for (int32_t k = threadIdx.x; k < nclr; k += NT) u4[k] = make_uint4(0u, 0u, 0u, 0u);
       }
       __syncthreads();
-      // mark: one lane per ray
-      for (int32_t k0 = 0; k0 < P.R; k0 += NT) {
-        const int32_t j = k0 + (int32_t)threadIdx.x;
-        const bool valid = j < P.R;
-        const int32_t k = valid ? V.perm[j] : 0;
-        RaySetup q{};
-        int32_t wi = 0, sx = 0, sy = 0, D = 0, n = -1;
-        bool hit = false;
-        if (valid) {
-          const int32_t pk = rho_lds[k];
-          hit = pk < 0;
-          const int32_t dv = ray_dir(P, ib, k);
-          const int32_t a = (int16_t)(dv & 0xffff), b = dv >> 16;
-          q = ray_setup(eox, eoy, a, b, pk & 0x7fffffff, s);
-          wi = (ecy - by0) * rowbits + (ecx - x0w);
-          sx = a > 0 ? 1 : -1;
-          sy = b > 0 ? rowbits : -rowbits;
-          D = q.D;
-          n = q.n;
-          if ((uint32_t)wi < band_bits) atomicOr(&miss[wi >> 5], 1u << (wi & 31));
-        }
-        const int32_t w0 = wi;
-        // Uniform trip counts over the wave.  While every lane is within its
-        // own count and the band holds the whole window, every step lands in
-        // the bitmap (the window holds every visited cell), so the first
-        // loop marks without tests; the word index is clamped only to keep
-        // the store inside the bitmap.  The second loop finishes the longer
-        // walks, testing each step.
-        const int32_t nmax = wave_max_i32(n);
-        const int32_t nmin = one_band ? wave_min_i32(valid ? n : 0) : 0;
-        const uint32_t last_word = (band_bits >> 5) - 1u;
-        int32_t i = 0;
-        for (; i < nmin; ++i) {
-          const bool stepx = D <= 0;
-          wi += stepx ? sx : sy;
-          D += stepx ? q.DX : -q.DY;
-          atomicOr(&miss[min((uint32_t)wi >> 5, last_word)], 1u << (wi & 31));
-        }
-        for (; i < nmax; ++i) {
-          const bool stepx = D <= 0;
-          wi += stepx ? sx : sy;
-          D += stepx ? q.DX : -q.DY;
-          if (i < n && (uint32_t)wi < band_bits) atomicOr(&miss[wi >> 5], 1u << (wi & 31));
-        }
-        if (valid) {
-          if (by0 == y0) uvisits += n + 1;
-          const int32_t we = w0 + q.kx * sx + q.ky * sy;   // last visited cell
-          if (hit && !q.gend && (uint32_t)we < band_bits) atomicOr(&hitm[we >> 5], 1u << (we & 31));
-        }
-      }
+      if (SEG)
+        mark_segments<NT>(P, rho_lds, V.perm, V.seg, V.hist, s, eox, eoy, ib, by0, x0w, rowbits, band_bits, one_band,
+                          by0 == y0, L.mark_seg, miss, hitm, uvisits);
+      else
+        mark_rays<NT>(P, rho_lds, V.perm, s, eox, eoy, ib, by0, x0w, rowbits, band_bits, one_band, by0 == y0, miss,
+                      hitm, uvisits);
       __syncthreads();
       // apply: each coded cell once (8 cells = one 16-byte access per octet)
       apply_band<NT, kApplyInFlight>(P, miss, hitm, rows, nw, P.belief + base + (int64_t)by0 * s + x0w, s, V.lut, dh,
@@ -977,7 +1126,8 @@ __device__ __forceinline__ void init_bbox(RobotShared* sh) {
   sh->by0 = 0x7fffffff; sh->by1 = -0x7fffffff;
 }
 
-template <int NT>
+// SEG: the map update's walk in segments (its own instance: the two forms differ in register use).
+template <int NT, bool SEG>
 __global__ __launch_bounds__(NT) void k_update(EnvParams P, StepArgs A, LdsPlan L) {
   extern __shared__ __align__(16) unsigned char smem[];
   const LdsView V = lds_view(smem, L);
@@ -1004,11 +1154,11 @@ __global__ __launch_bounds__(NT) void k_update(EnvParams P, StepArgs A, LdsPlan 
   __syncthreads();
   endpoint_bbox<NT>(P, V.rho, sh->eox, sh->eoy, sh->ib_e, sh);
   __syncthreads();
-  update_and_reward<NT>(P, A, m, V, L, r);
+  update_and_reward<NT, SEG>(P, A, m, V, L, r);
 }
 
 // One robot of the fused step (motion, march, update, reward) by the whole workgroup.
-template <int NT>
+template <int NT, bool SEG>
 __device__ __forceinline__ void fused_robot(const EnvParams& P, const StepArgs& A, const LdsPlan& L,
                                             const LdsView& V, int32_t r) {
   RobotShared* sh = V.sh;
@@ -1042,29 +1192,29 @@ __device__ __forceinline__ void fused_robot(const EnvParams& P, const StepArgs& 
   march_rays<NT>(P, m, V, sw, wy0, A.ranges, step_noise(P, A, r), L.record != 0, r);
   endpoint_bbox<NT>(P, V.rho, sh->eox, sh->eoy, sh->ib_e, sh);
   __syncthreads();
-  update_and_reward<NT>(P, A, m, V, L, r);
+  update_and_reward<NT, SEG>(P, A, m, V, L, r);
 }
 
 // Fused step, one workgroup per robot: workgroup b takes the b-th robot of the
 // largest-grid-first order, so the dispatcher hands out the big grids first.
-template <int NT>
+template <int NT, bool SEG>
 __global__ __launch_bounds__(NT) void k_fused(EnvParams P, StepArgs A, LdsPlan L) {
   extern __shared__ __align__(16) unsigned char smem[];
   const LdsView V = lds_view(smem, L);
   for (int32_t i = threadIdx.x; i < 2 * P.lclamp + 1; i += NT) V.lut[i] = P.hq_lut[i];
-  fused_robot<NT>(P, A, L, V, P.order[blockIdx.x]);
+  fused_robot<NT, SEG>(P, A, L, V, P.order[blockIdx.x]);
 }
 
 // Fused persistent step on a smaller grid: workgroups pull robots in largest-grid-first
 // order.  The register budget is capped at four waves per SIMD (128 VGPRs); the
 // loop-carried state would otherwise double it.
-template <int NT>
+template <int NT, bool SEG>
 __global__ __launch_bounds__(NT, 4) void k_fused_persist(EnvParams P, StepArgs A, LdsPlan L) {
   extern __shared__ __align__(16) unsigned char smem[];
   const LdsView V = lds_view(smem, L);
   for (int32_t i = threadIdx.x; i < 2 * P.lclamp + 1; i += NT) V.lut[i] = P.hq_lut[i];
   for (int32_t w = blockIdx.x; w < P.n; w += gridDim.x) {
-    fused_robot<NT>(P, A, L, V, P.order[w]);
+    fused_robot<NT, SEG>(P, A, L, V, P.order[w]);
     __syncthreads();
   }
 }
@@ -1356,16 +1506,20 @@ template <int NT>
 hipError_t plain_nt(const EnvParams& P, const StepArgs& A, const LdsPlan& L, hipStream_t st) {
   k_motion<<<(unsigned)(((int64_t)P.n * kMotionLanes + 255) / 256), 256, 0, st>>>(P, A);
   k_march<NT><<<P.n, NT, L.total, st>>>(P, A, L);
-  k_update<NT><<<P.n, NT, L.total, st>>>(P, A, L);
+  if (L.mark_seg > 0) k_update<NT, true><<<P.n, NT, L.total, st>>>(P, A, L);
+  else k_update<NT, false><<<P.n, NT, L.total, st>>>(P, A, L);
   return hipGetLastError();
 }
 
 template <int NT>
 hipError_t fused_nt(const EnvParams& P, const StepArgs& A, const LdsPlan& L, int grid, hipStream_t st) {
+  const bool seg = L.mark_seg > 0;
   if (grid >= P.n) {
-    k_fused<NT><<<P.n, NT, L.total, st>>>(P, A, L);
+    if (seg) k_fused<NT, true><<<P.n, NT, L.total, st>>>(P, A, L);
+    else k_fused<NT, false><<<P.n, NT, L.total, st>>>(P, A, L);
   } else {
-    k_fused_persist<NT><<<grid, NT, L.total, st>>>(P, A, L);
+    if (seg) k_fused_persist<NT, true><<<grid, NT, L.total, st>>>(P, A, L);
+    else k_fused_persist<NT, false><<<grid, NT, L.total, st>>>(P, A, L);
   }
   return hipGetLastError();
 }
@@ -1375,12 +1529,15 @@ hipError_t set_lds_nt(int bytes) {
   hipError_t e;
   if ((e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_march<NT>),
                                hipFuncAttributeMaxDynamicSharedMemorySize, bytes)) != hipSuccess) return e;
-  if ((e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_update<NT>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes)) != hipSuccess) return e;
-  if ((e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fused<NT>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes)) != hipSuccess) return e;
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fused_persist<NT>),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  const void* fns[] = {reinterpret_cast<const void*>(&k_update<NT, false>),
+                       reinterpret_cast<const void*>(&k_update<NT, true>),
+                       reinterpret_cast<const void*>(&k_fused<NT, false>),
+                       reinterpret_cast<const void*>(&k_fused<NT, true>),
+                       reinterpret_cast<const void*>(&k_fused_persist<NT, false>),
+                       reinterpret_cast<const void*>(&k_fused_persist<NT, true>)};
+  for (const void* f : fns)
+    if ((e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes)) != hipSuccess) return e;
+  return hipSuccess;
 }
 
 }  // namespace

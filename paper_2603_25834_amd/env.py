@@ -66,8 +66,8 @@ class Env:
 
     # ------------------------------------------------------------ exec form
     def set_exec(self, form: int = _lib.FORM_FUSED, threads: int = 256, band_rows: int = 0, grid: int = 0,
-                 record_rays: int = 0, lds_bytes: int = 0):
-        ex = ExecConfig(form, threads, band_rows, grid, record_rays, lds_bytes)
+                 record_rays: int = 0, lds_bytes: int = 0, mark_seg: int = 0):
+        ex = ExecConfig(form, threads, band_rows, grid, record_rays, lds_bytes, mark_seg)
         check(lib().aslam_env_set_exec(self.h, ctypes.byref(ex)))
 
     def get_exec(self) -> dict:

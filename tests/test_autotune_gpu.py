@@ -44,7 +44,8 @@ def _run(env, world, start, A, G, out, k):
 def test_tune_applies_best_and_caches(tmp_path):
     env, world, start, A, G, out = _setup()
     env.reset(world, start)
-    cands = [Candidate(128), Candidate(256), Candidate(512), Candidate(256, grid=7), Candidate(256, band_rows=8)]
+    cands = [Candidate(128), Candidate(256), Candidate(512), Candidate(256, grid=7), Candidate(256, band_rows=8),
+             Candidate(512, mark_seg=32)]
     cache = str(tmp_path / "tune.json")
     res = tune(env, A, G, *out, candidates=cands, warmup=1, steps=3, cache_path=cache)
     say(f"[autotune] {res['signature']}: best {res['best']} "
@@ -65,8 +66,10 @@ def test_every_launch_shape_gives_identical_state():
     env, world, start, A, G, out = _setup()
     ref = None
     for c in (Candidate(128), Candidate(384), Candidate(512, grid=5), Candidate(256, band_rows=8),
-              Candidate(256, form=_lib.FORM_PLAIN)):
-        env.set_exec(form=c.form, threads=c.threads, band_rows=c.band_rows, grid=c.grid)
+              Candidate(256, form=_lib.FORM_PLAIN), Candidate(512, mark_seg=32), Candidate(128, mark_seg=8),
+              Candidate(256, band_rows=8, mark_seg=16), Candidate(512, grid=5, mark_seg=64),
+              Candidate(192, form=_lib.FORM_PLAIN, mark_seg=1024)):
+        env.set_exec(form=c.form, threads=c.threads, band_rows=c.band_rows, grid=c.grid, mark_seg=c.mark_seg)
         got = _run(env, world, start, A, G, out, 10)
         if ref is None:
             ref = got

@@ -27,7 +27,7 @@ def test_small_16x64_every_step(exec_kw):
         pr.compare(o)
 
 
-@pytest.mark.parametrize("exec_kw", [PLAIN, FUSED], ids=["plain", "fused"])
+@pytest.mark.parametrize("exec_kw", [PLAIN, FUSED, dict(FUSED, mark_seg=32)], ids=["plain", "fused", "fused_seg32"])
 def test_paper_750x256_subset_loop_closure(exec_kw):
     """24 robots of the 750-robot 256x256 scene, 360 rays, 10 m, loop closure, 240 steps."""
     pr = Pair("paper_750x256", 1, robots=np.arange(0, 750, 31)[:24], exec_kw=exec_kw, steps=240)
@@ -51,10 +51,14 @@ def _ragged_robots():
 @pytest.mark.parametrize("exec_kw", [
     dict(form=0, threads=128), dict(form=1, threads=512, record_rays=1),
     dict(form=1, threads=256, record_rays=1, band_rows=8),
-    dict(form=1, threads=256, record_rays=1, grid=7)],
-    ids=["plain128", "fused512", "fused_band8", "fused_grid7"])
+    dict(form=1, threads=256, record_rays=1, grid=7),
+    dict(form=1, threads=256, record_rays=1, mark_seg=32), dict(form=1, threads=512, record_rays=1, mark_seg=8),
+    dict(form=1, threads=256, record_rays=1, band_rows=8, mark_seg=16), dict(form=0, threads=192, mark_seg=64)],
+    ids=["plain128", "fused512", "fused_band8", "fused_grid7", "fused_seg32", "fused512_seg8", "fused_band8_seg16",
+         "plain192_seg64"])
 def test_ragged_sides(exec_kw):
-    """Robots of every side in {128,...,512}; tiny bands force the multi-pass code window."""
+    """Robots of every side in {128,...,512}; tiny bands force the multi-pass code window; the map update's
+    walk one lane per ray or in segments of 8 to 64 steps."""
     pr = Pair("ragged_4096", 0, robots=_ragged_robots(), exec_kw=exec_kw, steps=40)
     for t in range(40):
         o = pr.step()
@@ -176,19 +180,24 @@ def test_graph_replay_matches_eager(form):
         del junk
 
 
-@pytest.mark.parametrize("name,steps,threads", [("paper_750x256", 1000, 512), ("ragged_4096", 1000, 512),
-                                                ("full_8192x512", 30, 512)],
-                         ids=["paper_750x256_T1000", "ragged_4096_T1000", "full_8192x512"])
-def test_full_batch_sampled(name, steps, threads):
-    """The whole batch stepped in the fused launch the benchmark times (512 threads per robot, steps
-    captured in one HIP graph): the 750-robot and the ragged 4096-robot scenes for their full 1000
-    steps, and 30 steps of the 8192-robot, 512^2, 720-ray, 15 m scene.  16 sampled robots re-run alone
-    by the oracle (robots are independent, so a sample sees the same inputs) and compared bit for bit
-    at every step (ranges, rewards, done) and at the end (poses, covariances, beliefs, entropies)."""
+@pytest.mark.parametrize("name,steps,exec_kw", [
+    ("paper_750x256", 1000, dict(form=1, threads=512)),
+    ("ragged_4096", 1000, dict(form=1, threads=512)),
+    ("ragged_4096", 1000, dict(form=1, threads=256, band_rows=203, mark_seg=32)),
+    ("full_8192x512", 30, dict(form=1, threads=512))],
+    ids=["paper_750x256_T1000", "ragged_4096_T1000", "ragged_4096_T1000_t256_band203_seg32", "full_8192x512"])
+def test_full_batch_sampled(name, steps, exec_kw):
+    """The whole batch stepped in the fused launches the benchmark times (the shapes its autotuner picks:
+    512 threads per robot at 750 robots; 256 threads, 203-row bands and 32-step walk segments for the
+    ragged batch; also 512 threads there), steps captured in one HIP graph: the 750-robot and the ragged
+    4096-robot scenes for their full 1000 steps, and 30 steps of the 8192-robot, 512^2, 720-ray, 15 m
+    scene.  16 sampled robots re-run alone by the oracle (robots are independent, so a sample sees the
+    same inputs) and compared bit for bit at every step (ranges, rewards, done) and at the end (poses,
+    covariances, beliefs, entropies)."""
     import torch
     from oracle import oracle as O
     from paper_2603_25834_amd import _lib
-    full = Pair(name, 8, exec_kw=dict(form=1, threads=threads), steps=steps, oracle=False)
+    full = Pair(name, 8, exec_kw=exec_kw, steps=steps, oracle=False)
     n = full.n
     pick = np.unique(np.linspace(3, n - 1, 16).astype(np.int64))
     b = synth.make_batch(name, 8, pick)
