@@ -64,6 +64,9 @@ class PPOTrainer:
         T, n, R = self.T, self.n, self.R
         self.units = n if self.recurrent else self.S     # what a minibatch permutation shuffles
         self.phase_events = None   # set to (start, rollout done, end) torch.cuda.Events to time the phases
+        # set to a callable hook(epoch, k, rows, flat, grads, params) to see each minibatch's gradient
+        # before its Adam step (feed-forward policy; flat holds the rollout arrays, adv and ret)
+        self.minibatch_hook = None
         self.perm = torch.zeros(self.units, dtype=torch.int32, device=dev)
         self.perm_work = torch.zeros(max(1, permutation_work_bytes(self.units) // 4), dtype=torch.int32, device=dev)
         # rollout storage (time-major)
@@ -132,6 +135,8 @@ class PPOTrainer:
                 # the minibatch is the rows idx of the rollout arrays: the kernels read them in place
                 pol.backward(p, flat["crop"], flat["scan"], flat["state"], flat["act"], flat["logp"], flat["adv"],
                              flat["ret"], self.grads, self.loss, rows=idx)
+                if self.minibatch_hook is not None:
+                    self.minibatch_hook(e, k, idx, flat, self.grads, p)
                 self.step_count += 1
                 adam(p, self.grads, self.m, self.v, self.step_count, lr=self.lr)
         if ev:

@@ -3,7 +3,12 @@
 The stages are checked one by one elsewhere (env step, forward, loss gradient, sampling, gather,
 GAE, Adam); here: the iteration runs on the small workload, the losses stay finite, the parameters
 move, and two runs from the same state with the same seed end bit-identical (every draw comes from
-the library's counter-based generator), while another seed ends elsewhere."""
+the library's counter-based generator), while another seed ends elsewhere.  And one whole iteration
+is checked against the oracle, stage by stage on the iteration's own data: the rollout's values,
+actions and log-probs against the FP64 network at the rollout's parameters with the oracle's own
+action draws; GAE on the rollout's rewards; each minibatch's rows against the oracle's permutation;
+each minibatch's gradient against the exact FP64 loss gradient at the parameters it was taken at;
+each Adam step against the oracle's update (Sec. III-F, Eqs. (18)-(20))."""
 import numpy as np
 import pytest
 import torch
@@ -16,7 +21,7 @@ from paper_2603_25834_amd.ppo import PPOTrainer
 pytestmark = pytest.mark.gpu
 
 
-def _trainer(seed, recurrent=False, name="small_16x64", draw_seed=5):
+def _trainer(seed, recurrent=False, name="small_16x64", draw_seed=5, precision=0, minibatch=40):
     w = synth.WORKLOADS[name]
     b = synth.make_batch(name, seed, np.arange(16) if w.n_robots > 16 else None)
     p = w.params()
@@ -28,8 +33,8 @@ def _trainer(seed, recurrent=False, name="small_16x64", draw_seed=5):
     env.reset(world, start)
     init = synth.init_recurrent_params if recurrent else synth.init_policy_params
     params = torch.from_numpy(init(w.n_rays, seed)).cuda()
-    tr = PPOTrainer(env, world, start, params, T=6, epochs=2, minibatch=40, lr=1e-3, recurrent=recurrent,
-                    seed=draw_seed)
+    tr = PPOTrainer(env, world, start, params, T=6, epochs=2, minibatch=minibatch, lr=1e-3, recurrent=recurrent,
+                    seed=draw_seed, precision=precision)
     return tr, params.clone()
 
 
@@ -52,3 +57,77 @@ def test_iteration_runs_and_is_deterministic(recurrent, name):
         finals.append(tr.params.cpu().numpy().copy())
     assert np.array_equal(finals[0], finals[1])
     assert not np.array_equal(finals[0], finals[2])
+
+
+def test_iteration_matches_oracle():
+    """Split-precision policy on the small workload (16 robots, 180 rays, T = 6, 2 epochs of 2 minibatches
+    of 48 samples)."""
+    from oracle import oracle as O
+    from oracle import policy_ref as PR
+    tr, p0 = _trainer(4, False, "small_16x64", 9, precision=1, minibatch=48)
+    shape = PR.PolicyShape(n_scan=tr.R)
+    recs = []
+
+    def hook(e, k, rows, flat, grads, params):
+        recs.append(dict(e=e, k=k, rows=rows.cpu().numpy().copy(), grads=grads.cpu().numpy().astype(np.float64),
+                         params=params.cpu().numpy().copy(),
+                         adv=flat["adv"].cpu().numpy().copy(), ret=flat["ret"].cpu().numpy().copy()))
+
+    tr.minibatch_hook = hook
+    tr.iteration()
+    torch.cuda.synchronize()
+    T, n, S = tr.T, tr.n, tr.S
+    assert tr.n_mb == 2 and len(recs) == 2 * tr.epochs
+    crop, scan, state = tr.crop.cpu(), tr.scan.cpu(), tr.state.cpu()
+    # rollout: values, actions and log-probs at the rollout's parameters
+    th0 = torch.from_numpy(p0.cpu().numpy()).double()
+    with torch.no_grad():
+        mu, ls, val = PR.forward(th0, crop.reshape(-1, *crop.shape[2:]), scan.reshape(-1, tr.R),
+                                 state.reshape(-1, 12), shape)
+    mu = mu.reshape(T + 1, n, 2).numpy()
+    val = val.reshape(T + 1, n).numpy()
+    ls = ls.numpy()
+    got_v = tr.value.cpu().numpy()
+    scale = np.abs(val) + np.mean(np.abs(val))
+    assert np.max(np.abs(got_v - val) / scale) < 1e-4
+    act, logp = tr.act.cpu().numpy(), tr.logp.cpu().numpy()
+    for t in range(T):
+        eps = O.normals(tr.seed, O.DOMAIN_ACTION, t, n, 2).astype(np.float64)   # iteration 0: counter t
+        want_act = mu[t] + np.exp(ls) * eps
+        assert np.allclose(act[t], want_act, rtol=0, atol=1e-4), t
+        want_logp = -0.5 * (eps ** 2).sum(1) - ls.sum() - 0.5 * np.log(2 * np.pi) * 2
+        assert np.allclose(logp[t], want_logp, rtol=0, atol=1e-5), t
+    # GAE on the rollout's rewards, values and episode ends
+    adv, ret = PR.gae(tr.reward.cpu(), tr.value[:T].cpu(), tr.done.cpu(), tr.value[T].cpu())
+    assert np.allclose(recs[0]["adv"], adv.reshape(S).numpy(), rtol=1e-5, atol=1e-5)
+    assert np.allclose(recs[0]["ret"], ret.reshape(S).numpy(), rtol=1e-5, atol=1e-5)
+    flat = dict(crop=crop[:T].reshape(S, *crop.shape[2:]), scan=scan[:T].reshape(S, tr.R),
+                state=state[:T].reshape(S, 12), act=torch.from_numpy(act.reshape(S, 2)),
+                logp=torch.from_numpy(logp.reshape(S)), adv=adv.reshape(S), ret=ret.reshape(S))
+    m = torch.zeros(len(p0), dtype=torch.float64)
+    v = torch.zeros(len(p0), dtype=torch.float64)
+    for j, rec in enumerate(recs):
+        e, k = rec["e"], rec["k"]
+        perm = O.permute(S, tr.seed, e)                        # iteration 0, epoch e
+        assert np.array_equal(rec["rows"], perm[k * tr.mb:min(S, (k + 1) * tr.mb)]), (e, k)
+        idx = torch.from_numpy(rec["rows"].astype(np.int64))
+        th = torch.from_numpy(rec["params"]).double().requires_grad_(True)
+        loss, _ = PR.ppo_loss(th, flat["crop"][idx], flat["scan"][idx], flat["state"][idx], flat["act"][idx],
+                              flat["logp"][idx], flat["adv"][idx], flat["ret"][idx], shape)
+        (g_ref,) = torch.autograd.grad(loss, th)
+        g_ref = g_ref.numpy()
+        o = 0
+        errs = {}
+        for name, shp in shape.param_layout():
+            c = int(np.prod(shp))
+            a, b = rec["grads"][o:o + c], g_ref[o:o + c]
+            errs[name] = float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
+            o += c
+        say(f"[ppo] epoch {e} minibatch {k}: " + " ".join(f"{q}={w:.1e}" for q, w in errs.items()))
+        for name, err in errs.items():
+            assert err < 1e-2, (e, k, name, err)
+        # Adam: the next minibatch's parameters (or the final ones) from this gradient
+        nxt = recs[j + 1]["params"] if j + 1 < len(recs) else tr.params.cpu().numpy()
+        want, m, v = PR.adam_step(torch.from_numpy(rec["params"]), torch.from_numpy(rec["grads"]), m, v, j + 1,
+                                  lr=tr.lr)
+        assert np.allclose(nxt, want.numpy(), rtol=1e-5, atol=1e-7), (e, k)
