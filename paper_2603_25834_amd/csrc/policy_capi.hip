@@ -174,9 +174,13 @@ int encode_fc1(aslam_policy* P, const float* prm, const int16_t* crop, const flo
   const int K1 = P->k1p;
   const LdBF16K xa{P->x, K1, B, K1};
   const LdBF16K wa{P->w1b, K1, kHid, K1};
-  // as many K splits as keep the grid within one round of kFc1MinBlocks resident workgroups
+  // as many K splits as keep the grid within one round of kFc1MinBlocks resident workgroups; with the
+  // three split-precision products and few row tiles (a rollout step) a third of that: the products
+  // fill the round themselves, and more slices would only add partial-sum traffic (at 750 rows, 32
+  // splits of 3 products wrote and re-read 74 MB of partial sums per call)
   const int tiles = ((B + 127) / 128) * (kHid / 128);
-  const int S = std::max(1, std::min(32, kFc1MinBlocks / tiles));
+  int S = std::max(1, std::min(32, kFc1MinBlocks / tiles));
+  if (P->prec && tiles < 32) S = std::max(1, std::min(32, kFc1MinBlocks / (3 * tiles)));
   if (P->prec) {
     // x_hi W_hi, x_hi W_lo and x_lo W_hi, each split S ways, into consecutive groups of slices (one
     // launch: product 1 reads W's lo part, product 2 x's)
