@@ -1196,9 +1196,12 @@ __device__ __forceinline__ void fused_robot(const EnvParams& P, const StepArgs& 
 }
 
 // Fused step, one workgroup per robot: workgroup b takes the b-th robot of the
-// largest-grid-first order, so the dispatcher hands out the big grids first.
+// largest-grid-first order, so the dispatcher hands out the big grids first.  The segmented instance
+// is held to 80 VGPRs (six waves per SIMD: three 512-thread workgroups per CU, every robot of a
+// 750-robot batch resident at once); unbounded it takes 89 and fits two, which costs more than the
+// few spilled values do.
 template <int NT, bool SEG>
-__global__ __launch_bounds__(NT) void k_fused(EnvParams P, StepArgs A, LdsPlan L) {
+__global__ __launch_bounds__(NT, SEG ? 6 : 1) void k_fused(EnvParams P, StepArgs A, LdsPlan L) {
   extern __shared__ __align__(16) unsigned char smem[];
   const LdsView V = lds_view(smem, L);
   for (int32_t i = threadIdx.x; i < 2 * P.lclamp + 1; i += NT) V.lut[i] = P.hq_lut[i];
@@ -1294,25 +1297,41 @@ __global__ void k_observe(EnvParams P, const float* ranges, int16_t* crop, int32
   const int32_t ecy = to_q16(e[1], P.inv_c16) >> 16;
   const int16_t* bel = P.belief + m.cell_off;
   int16_t* out = crop + (int64_t)r * cs * cs;
-  // eight crop cells per item: the loads of an item are independent and its store is one 16-byte
-  // store when the crop side is a multiple of 8
+  // eight crop cells per item: cells i0 .. i0 + 7 of row j lie in the grid row's octets floor(i0 / 8)
+  // and the next (rows start on 64-byte boundaries, s being a multiple of 32), so an item is two
+  // aligned 16-byte loads (an octet outside the row reads as zeros, which are the cells off the grid)
+  // funnel-shifted into place, and one 16-byte store when the crop side is a multiple of 8
   const int32_t chunks = (cs + 7) >> 3;
+  const int32_t octs = s >> 3;
   for (int32_t q = threadIdx.x; q < cs * chunks; q += blockDim.x) {
     const int32_t jj = q / chunks, i8 = (q - jj * chunks) * 8;
     const int32_t j = ecy - cs / 2 + jj, i0 = ecx - cs / 2 + i8;
-    const bool row_in = j >= 0 && j < s;
-    uint16_t v[8];
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int32_t i = i0 + e;
-      v[e] = (row_in && i >= 0 && i < s) ? (uint16_t)bel[(int64_t)j * s + i] : (uint16_t)0;
+    uint64_t w[4] = {0ull, 0ull, 0ull, 0ull};
+    if (j >= 0 && j < s) {
+      const int32_t k0 = i0 >> 3;   // floor
+      const uint4* row = reinterpret_cast<const uint4*>(bel + (int64_t)j * s);
+      if (k0 >= 0 && k0 < octs) {
+        const uint4 a = row[k0];
+        w[0] = a.x | ((uint64_t)a.y << 32);
+        w[1] = a.z | ((uint64_t)a.w << 32);
+      }
+      if (k0 + 1 >= 0 && k0 + 1 < octs) {
+        const uint4 b = row[k0 + 1];
+        w[2] = b.x | ((uint64_t)b.y << 32);
+        w[3] = b.z | ((uint64_t)b.w << 32);
+      }
     }
+    // the eight cells start at bit 16 (i0 & 7) of the 256-bit concatenation w[0] .. w[3]
+    const int32_t bit = 16 * (i0 & 7);
+    const int32_t wi = bit >> 6, bs = bit & 63;
+    const uint64_t x0 = wi ? w[1] : w[0], x1 = wi ? w[2] : w[1], x2 = wi ? w[3] : w[2];
+    const uint64_t lo = bs ? (x0 >> bs) | (x1 << (64 - bs)) : x0;
+    const uint64_t hi = bs ? (x1 >> bs) | (x2 << (64 - bs)) : x1;
     int16_t* dst = out + (int64_t)jj * cs + i8;
     if ((cs & 7) == 0 && (reinterpret_cast<uintptr_t>(dst) & 15) == 0) {
-      *reinterpret_cast<uint4*>(dst) = make_uint4(v[0] | ((uint32_t)v[1] << 16), v[2] | ((uint32_t)v[3] << 16),
-                                                  v[4] | ((uint32_t)v[5] << 16), v[6] | ((uint32_t)v[7] << 16));
+      *reinterpret_cast<uint4*>(dst) = make_uint4((uint32_t)lo, (uint32_t)(lo >> 32), (uint32_t)hi, (uint32_t)(hi >> 32));
     } else {
-      for (int e = 0; e < 8 && i8 + e < cs; ++e) dst[e] = (int16_t)v[e];
+      for (int e = 0; e < 8 && i8 + e < cs; ++e) dst[e] = (int16_t)((e < 4 ? lo >> (16 * e) : hi >> (16 * (e - 4))) & 0xffffu);
     }
   }
   for (int32_t k = threadIdx.x; k < P.R; k += blockDim.x)
