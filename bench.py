@@ -69,10 +69,15 @@ def kernel_source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def read_traffic(kernel: str, workload: str, threads: int):
-    """HBM traffic per launch from the committed rocprofv3 counter summary for this kernel, workload and
-    workgroup size, if it was taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_t{threads}_{workload}.txt")
+def traffic_file(kernel: str, workload: str, threads: int, mark_seg: int = 0) -> str:
+    seg = f"_s{mark_seg}" if mark_seg else ""
+    return os.path.join(ROOT, "profiles", f"traffic_{kernel}_t{threads}{seg}_{workload}.txt")
+
+
+def read_traffic(kernel: str, workload: str, threads: int, mark_seg: int = 0):
+    """HBM traffic per launch from the committed rocprofv3 counter summary for this kernel, workload,
+    workgroup size and walk form, if it was taken on the current kernel source; else None."""
+    path = traffic_file(kernel, workload, threads, mark_seg)
     if not os.path.exists(path):
         return None
     kv = {}
@@ -628,6 +633,7 @@ def main():
     ap.add_argument("--threads", type=int, default=0, help="threads per robot; 0: autotune the launch shape")
     ap.add_argument("--band", type=int, default=0)
     ap.add_argument("--grid", type=int, default=0)
+    ap.add_argument("--mark-seg", type=int, default=0, help="with --threads: the map update's walk segments (0: one lane per ray)")
     ap.add_argument("--eager", action="store_true", help="eager launches instead of one HIP graph")
     ap.add_argument("--secondary", default="ragged_4096", help="second workload ('' to skip)")
     ap.add_argument("--secondary-steps", type=int, default=200)
@@ -668,8 +674,9 @@ def main():
     if args.only_ppo:   # profiling aid: the PPO minibatch timing alone
         print(json.dumps({"ppo": ppo_time(360, args.ppo_batch, args.seed, precision=args.precision)}), flush=True)
         return
-    fused = dict(form=_lib.FORM_FUSED, threads=args.threads or 256, band_rows=args.band, grid=args.grid)
-    plain = dict(form=_lib.FORM_PLAIN, threads=args.threads or 256, band_rows=args.band)
+    fused = dict(form=_lib.FORM_FUSED, threads=args.threads or 256, band_rows=args.band, grid=args.grid,
+                 mark_seg=args.mark_seg)
+    plain = dict(form=_lib.FORM_PLAIN, threads=args.threads or 256, band_rows=args.band, mark_seg=args.mark_seg)
     print(f"[bench] {args.workload}: setting up", file=sys.stderr, flush=True)
     wb = Workbench(args.workload, args.seed, args.env_warmup + args.env_steps, fused)
     tuned = {}
@@ -691,7 +698,7 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    traffic = read_traffic("k_fused", args.workload, fused["threads"])
+    traffic = read_traffic("k_fused", args.workload, fused["threads"], fused.get("mark_seg", 0))
     if args.only_env:   # profiling aid: the env-step timings alone
         print(json.dumps({"env_step_ms": res["ms_per_step"], "plain_step_ms": res_plain["ms_per_step"],
                           "observe_ms": obs_ms, "alg_bytes_per_launch": res["alg_bytes_per_step"],
@@ -740,7 +747,8 @@ def main():
                    "horizon": args.horizon, "epochs": args.epochs, "minibatch": loop["minibatch"],
                    "minibatches_per_epoch": loop["minibatches_per_epoch"],
                    "threads": fused["threads"], "band_rows": fused.get("band_rows", 0),
-                   "grid": fused.get("grid", 0), "plain_threads": plain["threads"],
+                   "grid": fused.get("grid", 0), "mark_seg": fused.get("mark_seg", 0),
+                   "plain_threads": plain["threads"],
                    "lds_bytes": wb.env.get_exec()["lds_bytes"]},
         "rays_per_s": value * wb.R,
         "slam": slam_res,
@@ -754,7 +762,8 @@ def main():
                        "fused_speedup": res["env_steps_per_s"] / res_plain["env_steps_per_s"]},
         "roofline": {"bound": "hbm", "achieved": res["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": res["achieved_gbs"] / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": f"k_fused<{fused['threads']}>", "alg_bytes_per_launch": res["alg_bytes_per_step"],
+                     "kernel": f"k_fused<{fused['threads']}, {'true' if fused.get('mark_seg', 0) else 'false'}>",
+                     "mark_seg": fused.get("mark_seg", 0), "alg_bytes_per_launch": res["alg_bytes_per_step"],
                      "avg_launch_ms": res["ms_per_step"],
                      "coded_cells_per_robot_step": res["coded_cells_per_robot_step"],
                      "cell_visits_per_robot_step": res["march_visits_per_robot_step"] +
