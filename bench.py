@@ -74,10 +74,9 @@ def traffic_file(kernel: str, workload: str, threads: int, mark_seg: int = 0) ->
     return os.path.join(ROOT, "profiles", f"traffic_{kernel}_t{threads}{seg}_{workload}.txt")
 
 
-def read_traffic(kernel: str, workload: str, threads: int, mark_seg: int = 0):
-    """HBM traffic per launch from the committed rocprofv3 counter summary for this kernel, workload,
-    workgroup size and walk form, if it was taken on the current kernel source; else None."""
-    path = traffic_file(kernel, workload, threads, mark_seg)
+def read_summary(path: str) -> dict | None:
+    """key: value lines of a committed rocprofv3 counter summary, if it was taken on the current kernel
+    source; else None."""
     if not os.path.exists(path):
         return None
     kv = {}
@@ -85,12 +84,59 @@ def read_traffic(kernel: str, workload: str, threads: int, mark_seg: int = 0):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
-    if kv.get("source_digest") != kernel_source_digest():
-        return None
+    return kv if kv.get("source_digest") == kernel_source_digest() else None
+
+
+def read_traffic(kernel: str, workload: str, threads: int, mark_seg: int = 0):
+    """HBM traffic per launch from the committed rocprofv3 counter summary for this kernel, workload,
+    workgroup size and walk form, if it was taken on the current kernel source; else None."""
+    kv = read_summary(traffic_file(kernel, workload, threads, mark_seg))
     try:
-        return float(kv["hbm_bytes_per_launch"])
+        return float(kv["hbm_bytes_per_launch"]) if kv else None
     except (KeyError, ValueError):
         return None
+
+
+# VALU issue peak of the chip: 256 CUs x 4 SIMDs x 16 lanes per cycle x 2.4 GHz (a wave64 instruction
+# occupies a SIMD for 4 cycles), in lane-instructions per second.
+VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
+
+
+def valu_roofline(kernel: str, workload: str, threads: int, mark_seg: int, avg_launch_ms: float):
+    """VALU issue of the kernel: SQ_INSTS_VALU per launch (committed counter summary of the same shape,
+    current source) x 64 lanes over the live average launch time, against the issue peak."""
+    seg = f"_s{mark_seg}" if mark_seg else ""
+    path = os.path.join(ROOT, "profiles", f"sq_counters_{kernel}_t{threads}{seg}_{workload}.txt")
+    kv = read_summary(path)
+    if not kv or "SQ_INSTS_VALU" not in kv:
+        return None
+    lane_ops = float(kv["SQ_INSTS_VALU"]) * 64
+    achieved = lane_ops / (avg_launch_ms * 1e-3)
+    return {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_LANE_OPS / 1e12,
+            "unit": "T lane-instructions/s", "frac": achieved / VALU_PEAK_LANE_OPS,
+            "valu_instructions_per_launch": float(kv["SQ_INSTS_VALU"]),
+            "wait_share": float(kv["SQ_WAIT_ANY"]) / float(kv["SQ_WAVE_CYCLES"]),
+            "source": os.path.basename(path)}
+
+
+def copy_bandwidth(gib: float = 1.0, reps: int = 10) -> float:
+    """Measured device-to-device copy rate (read + write bytes / time) of a gib-GiB buffer, GB/s."""
+    import torch
+    n = int(gib * (1 << 30)) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2.0 * n * 4 * reps / (e0.elapsed_time(e1) / 1e3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return gbs
 
 
 class Workbench:
@@ -722,6 +768,7 @@ def main():
     print(f"[bench] training iteration, {loop_other['policy_precision']} policy: "
           f"{loop_other['ms_per_iteration']:.2f} ms", file=sys.stderr, flush=True)
 
+    copy_gbs = copy_bandwidth()   # after the profiling exits above, so counter passes see only their own copy
     out = {
         "metric": METRIC,
         "value": value,
@@ -760,6 +807,9 @@ def main():
                           "form": "fused persistent, HIP graph"},
         "plain_form": {"env_steps_per_s": res_plain["env_steps_per_s"], "ms_per_step": res_plain["ms_per_step"],
                        "fused_speedup": res["env_steps_per_s"] / res_plain["env_steps_per_s"]},
+        "roofline_valu": valu_roofline("k_fused", args.workload, fused["threads"], fused.get("mark_seg", 0),
+                                       res["ms_per_step"]),
+        "hbm_copy_gbs": copy_gbs,
         "roofline": {"bound": "hbm", "achieved": res["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": res["achieved_gbs"] / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": f"k_fused<{fused['threads']}, {'true' if fused.get('mark_seg', 0) else 'false'}>",
