@@ -91,31 +91,15 @@ __device__ bool segment_blocked(const uint32_t* w, int32_t s, int32_t ox, int32_
 
 // Proximity collision (Sec. IV-A): an occupied or off-grid cell lies closer
 // than rc (1/65536 cell) to the Q16 point, by the exact integer distance from
-// the point to the cell's square.
-__device__ bool near_obstacle(const uint32_t* w, int32_t s, int32_t px, int32_t py, int32_t rc) {
-  const int32_t cx = px >> 16, cy = py >> 16;
-  const int32_t m = rc / kQ16 + 1;
-  const int64_t rc2 = (int64_t)rc * rc;
-  for (int32_t j = cy - m; j <= cy + m; ++j) {
-    for (int32_t i = cx - m; i <= cx + m; ++i) {
-      const bool occ = (i < 0 || j < 0 || i >= s || j >= s) || world_bit(w, s, i, j);
-      if (!occ) continue;
-      const int64_t dx = max(max((int64_t)i * kQ16 - px, (int64_t)px - (int64_t)(i + 1) * kQ16), (int64_t)0);
-      const int64_t dy = max(max((int64_t)j * kQ16 - py, (int64_t)py - (int64_t)(j + 1) * kQ16), (int64_t)0);
-      if (dx * dx + dy * dy < rc2) return true;
-    }
-  }
-  return false;
-}
-
-// The same test by a whole workgroup, one cell per thread; sets *flag (LDS) when some cell is near.
-template <int NT>
-__device__ void near_obstacle_wg(const uint32_t* w, int32_t s, int32_t px, int32_t py, int32_t rc, int32_t* flag) {
+// the point to the cell's square.  The (2m+1)^2 cells around the point's cell
+// (m = rc / 65536 + 1) are shared out: this lane tests cells k0, k0 + stride, ...
+__device__ bool near_obstacle_part(const uint32_t* w, int32_t s, int32_t px, int32_t py, int32_t rc, int32_t k0,
+                                   int32_t stride) {
   const int32_t cx = px >> 16, cy = py >> 16;
   const int32_t m = rc / kQ16 + 1, side = 2 * m + 1;
   const int64_t rc2 = (int64_t)rc * rc;
   bool near = false;
-  for (int32_t k = threadIdx.x; k < side * side; k += NT) {
+  for (int32_t k = k0; k < side * side; k += stride) {
     const int32_t j = cy - m + k / side, i = cx - m + k % side;
     const bool occ = (i < 0 || j < 0 || i >= s || j >= s) || world_bit(w, s, i, j);
     if (occ) {
@@ -124,6 +108,13 @@ __device__ void near_obstacle_wg(const uint32_t* w, int32_t s, int32_t px, int32
       near = near || dx * dx + dy * dy < rc2;
     }
   }
+  return near;
+}
+
+// The test by a whole workgroup, one cell per thread; sets *flag (LDS) when some cell is near.
+template <int NT>
+__device__ void near_obstacle_wg(const uint32_t* w, int32_t s, int32_t px, int32_t py, int32_t rc, int32_t* flag) {
+  const bool near = near_obstacle_part(w, s, px, py, rc, (int32_t)threadIdx.x, NT);
   if (__builtin_amdgcn_ballot_w64(near) != 0 && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
 }
 
@@ -219,10 +210,9 @@ __device__ __forceinline__ MotionDraws motion_draws(const EnvParams& P, const St
 }
 
 // Motion, collision, EKF predict and loop closure of robot r (one thread, with the robot's draws).  The
-// proximity part of the collision test is done here when `proximity` is set; the fused step does it
-// with the whole workgroup.
-__device__ MotionOut robot_motion(const EnvParams& P, const StepArgs& A, int32_t r, bool proximity,
-                                  const MotionDraws& g) {
+// proximity part of the collision test (which leaves the move standing) is left to the caller's lanes:
+// the fused step runs it on the whole workgroup, k_motion on the robot's eight lanes.
+__device__ MotionOut robot_motion(const EnvParams& P, const StepArgs& A, int32_t r, const MotionDraws& g) {
   const RobotMeta m = P.meta[r];
   const int32_t s = m.side;
   const float a0 = A.actions[2 * r], a1 = A.actions[2 * r + 1];
@@ -253,11 +243,7 @@ __device__ MotionOut robot_motion(const EnvParams& P, const StepArgs& A, int32_t
     P.odo_u[2 * (int64_t)r] = d;
     P.odo_u[2 * (int64_t)r + 1] = phi;
   }
-  // the paper's collision: closer than d_crash to an obstacle (the move stands)
-  int32_t collided = col;
-  if (proximity && P.crash_q > 0 && !col &&
-      near_obstacle(W, s, to_q16(px, P.inv_c16), to_q16(py, P.inv_c16), P.crash_q))
-    collided = 1;
+  const int32_t collided = col;
 
   // EKF predict; F uses the estimated heading before the step.
   float* e = P.est + 3 * (int64_t)r;
@@ -1083,15 +1069,27 @@ __device__ void update_and_reward(const EnvParams& P, const StepArgs& A, const R
 
 // ---------------------------------------------------------------- kernels
 
-// Eight lanes per robot: five draw its normals, the first one moves it.
+// Eight lanes per robot: five draw its normals, the first one moves it, all eight test the paper's
+// proximity collision around the new position (the move stands).
 constexpr int kMotionLanes = 8;
 
 __global__ void k_motion(EnvParams P, StepArgs A) {
   const int32_t r = (int32_t)((blockIdx.x * blockDim.x + threadIdx.x) / kMotionLanes);
   const int lane0 = (int)(threadIdx.x & 63) & ~(kMotionLanes - 1);
-  const MotionDraws g = motion_draws(P, A, r, r < P.n, lane0);
-  if (r >= P.n || (threadIdx.x & (kMotionLanes - 1)) != 0) return;
-  robot_motion(P, A, r, true, g);
+  const int sub = (int)(threadIdx.x & 63) - lane0;
+  const bool valid = r < P.n;
+  const MotionDraws g = motion_draws(P, A, r, valid, lane0);
+  MotionOut o{};
+  if (valid && sub == 0) o = robot_motion(P, A, r, g);
+  const int32_t tox = __shfl(o.tox, lane0, 64), toy = __shfl(o.toy, lane0, 64);
+  const int32_t col = __shfl(o.collided, lane0, 64);
+  bool near = false;
+  if (valid && P.crash_q > 0 && !col) {
+    const RobotMeta m = P.meta[r];
+    near = near_obstacle_part(P.world + m.world_off, m.side, tox, toy, P.crash_q, sub, kMotionLanes);
+  }
+  const uint64_t b = __builtin_amdgcn_ballot_w64(near);
+  if (valid && sub == 0 && ((b >> lane0) & 0xffull) != 0) P.flags[2 * (int64_t)r] = 1;
 }
 
 template <int NT>
@@ -1166,7 +1164,7 @@ __device__ __forceinline__ void fused_robot(const EnvParams& P, const StepArgs& 
   if (threadIdx.x < 64) {   // wave 0: lanes 0..4 draw the normals, lane 0 moves the robot
     const MotionDraws g = motion_draws(P, A, r, true, 0);
     if (threadIdx.x == 0) {
-      const MotionOut o = robot_motion(P, A, r, false, g);
+      const MotionOut o = robot_motion(P, A, r, g);
       sh->tox = o.tox; sh->toy = o.toy; sh->ib_t = o.ib_t;
       sh->eox = o.eox; sh->eoy = o.eoy; sh->ib_e = o.ib_e;
       sh->collided = o.collided;
@@ -1381,11 +1379,57 @@ __global__ void k_fl_prep(EnvParams P, FixedLag F) {
   }
 }
 
-// One thread per robot: the alignment, the estimate, and the window's new pose with its odometry and
-// scan factors (the oldest pose leaves a full window, the next one taking the prior).
+// One wave per robot: the alignment, the estimate, and the window's new pose with its odometry and
+// scan factors (the oldest pose leaves a full window, the next one taking the prior).  The slide of a
+// full window moves up to 18 L doubles; the wave's lanes move them together, every value loaded before
+// any is stored (the stores land below the loads, so none overwrites an element still to be read).
+constexpr int kFlLanes = 64;
+constexpr int kFlPer = (6 * slam::kMaxWindow + kFlLanes - 1) / kFlLanes;   // elements per lane and array
+
+__device__ __forceinline__ void fl_shift_load(const double* a, int n, int off, int lane, double (&v)[kFlPer]) {
+#pragma unroll
+  for (int q = 0; q < kFlPer; ++q) {
+    const int e = lane + kFlLanes * q;
+    v[q] = e < n ? a[e + off] : 0.0;
+  }
+}
+
+__device__ __forceinline__ void fl_shift_store(double* a, int n, int lane, const double (&v)[kFlPer]) {
+#pragma unroll
+  for (int q = 0; q < kFlPer; ++q) {
+    const int e = lane + kFlLanes * q;
+    if (e < n) a[e] = v[q];
+  }
+}
+
 __global__ void k_fl_window(EnvParams P, FixedLag F) {
-  const int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= P.n) return;
+  const int32_t r = (int32_t)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kFlLanes);
+  const int lane = (int)(threadIdx.x & (kFlLanes - 1));
+  if (r >= P.n) return;   // uniform over the wave
+  const int L = F.L;
+  double* x = F.x + (int64_t)r * L * 3;
+  double* od = F.odo + (int64_t)r * (L - 1) * 6;
+  double* sc = F.scan + (int64_t)r * L * 6;
+  double* sg = F.sig + (int64_t)r * L * 3;
+  int c = F.count[r];
+  if (c == L) {
+    double vx[kFlPer], vs[kFlPer], vc[kFlPer], vo[kFlPer];
+    fl_shift_load(x, 3 * (L - 1), 3, lane, vx);
+    fl_shift_load(sg, 3 * (L - 1), 3, lane, vs);
+    fl_shift_load(sc, 6 * (L - 1), 6, lane, vc);
+    fl_shift_load(od, 6 * (L - 2), 6, lane, vo);
+    fl_shift_store(x, 3 * (L - 1), lane, vx);
+    fl_shift_store(sg, 3 * (L - 1), lane, vs);
+    fl_shift_store(sc, 6 * (L - 1), lane, vc);
+    fl_shift_store(od, 6 * (L - 2), lane, vo);
+    if (lane < 3) {   // the new oldest pose's prior: its estimate, the inverse of its covariance diagonal
+      double* pr = F.prior + 6 * (int64_t)r;
+      pr[lane] = vx[0];
+      pr[3 + lane] = 1.0 / vs[0];
+    }
+    c = L - 1;
+  }
+  if (lane != 0) return;
   const int32_t* m = F.match + 6 * (int64_t)r;
   const double w = slam::match_weight(m, F.l_max);
   const int64_t px = F.pose_q[3 * r], py = F.pose_q[3 * r + 1], ph = F.pose_q[3 * r + 2];
@@ -1407,29 +1451,6 @@ __global__ void k_fl_window(EnvParams P, FixedLag F) {
   e[0] = (float)z[0];
   e[1] = (float)z[1];
   e[2] = (float)z[2];
-  const int L = F.L;
-  double* x = F.x + (int64_t)r * L * 3;
-  double* od = F.odo + (int64_t)r * (L - 1) * 6;
-  double* sc = F.scan + (int64_t)r * L * 6;
-  double* sg = F.sig + (int64_t)r * L * 3;
-  int c = F.count[r];
-  if (c == L) {
-    for (int i = 0; i + 1 < L; ++i) {
-      for (int a = 0; a < 3; ++a) {
-        x[3 * i + a] = x[3 * (i + 1) + a];
-        sg[3 * i + a] = sg[3 * (i + 1) + a];
-      }
-      for (int a = 0; a < 6; ++a) sc[6 * i + a] = sc[6 * (i + 1) + a];
-      if (i + 2 < L)
-        for (int a = 0; a < 6; ++a) od[6 * i + a] = od[6 * (i + 1) + a];
-    }
-    double* pr = F.prior + 6 * (int64_t)r;
-    for (int a = 0; a < 3; ++a) {
-      pr[a] = x[a];
-      pr[3 + a] = 1.0 / sg[a];
-    }
-    c = L - 1;
-  }
   const double d = (double)P.odo_u[2 * (int64_t)r], phi = (double)P.odo_u[2 * (int64_t)r + 1];
   double* o = od + 6 * (c - 1);
   o[0] = d; o[1] = 0.0; o[2] = phi;
@@ -1443,15 +1464,18 @@ __global__ void k_fl_window(EnvParams P, FixedLag F) {
   F.wq[r] = (int32_t)rint(256.0 * (F.floor + (1.0 - F.floor) * w));
 }
 
-// The window's solution back into the state: poses, the FP32 covariance entries of the newest pose and
-// its covariance diagonal (the prior the pose will carry as the oldest).
+// One wave per robot: the window's solution back into the state (poses by all lanes), the FP32
+// covariance entries of the newest pose and its covariance diagonal (the prior the pose will carry as
+// the oldest).
 __global__ void k_fl_post(EnvParams P, FixedLag F) {
-  const int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+  const int32_t r = (int32_t)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kFlLanes);
+  const int lane = (int)(threadIdx.x & (kFlLanes - 1));
   if (r >= P.n) return;
   const int L = F.L, c = F.count[r];
   const double* xo = F.xout + (int64_t)r * L * 3;
   double* x = F.x + (int64_t)r * L * 3;
-  for (int e = 0; e < 3 * c; ++e) x[e] = xo[e];
+  for (int e = lane; e < 3 * c; e += kFlLanes) x[e] = xo[e];
+  if (lane != 0) return;
   const double* S = F.covw + 9 * (int64_t)r;
   float* cv = P.cov + 6 * (int64_t)r;
   cv[0] = (float)S[0]; cv[1] = (float)S[1]; cv[2] = (float)S[2];
@@ -1509,10 +1533,11 @@ hipError_t fixedlag_nt(const EnvParams& P, const StepArgs& A, const LdsPlan& L, 
   hipError_t e = slam::launch_csm_match(P.dirtab, P.belief, F.cell_off, F.side, F.max_side, P.n, F.pose_q, F.rho_q,
                                         P.R, F.a_off, F.W, F.V, F.step_xy, F.step_h, F.match, st);
   if (e != hipSuccess) return e;
-  k_fl_window<<<blocks, 256, 0, st>>>(P, F);
+  const unsigned wave_blocks = (unsigned)(((int64_t)P.n * kFlLanes + 255) / 256);
+  k_fl_window<<<wave_blocks, 256, 0, st>>>(P, F);
   e = slam::launch_fixedlag(P.n, F.L, F.count, F.x, F.prior, F.odo, F.scan, F.iters, F.xout, F.covw, st);
   if (e != hipSuccess) return e;
-  k_fl_post<<<blocks, 256, 0, st>>>(P, F);
+  k_fl_post<<<wave_blocks, 256, 0, st>>>(P, F);
   e = slam::launch_csm_integrate(P.dirtab, P.belief, F.cell_off, F.side, P.n, F.pose_al, F.rho_q, P.R, F.a_off,
                                  F.max_side, P.rhat_q, nullptr, 0, 0, 1.0, P.lhit, P.lmiss, P.lclamp, F.coded, F.wq,
                                  st);
