@@ -59,10 +59,12 @@ __device__ __forceinline__ uint16_t lane16(const uint4& v, int j) {
 // engine issues those reads at kernel start, so their latency hides behind the
 // main loop (others declare kPrefetch = false).
 
-// Several products in one launch (the split-precision forward: hi x hi, hi x lo, lo x hi into
-// consecutive groups of K slices): an operand given as HiLo reads its `lo` matrix in product p when
-// bit p of lo_mask is set, else its `hi` matrix; the workgroup's z index runs over the products'
-// slice groups (product = z / slices per product).  A plain loader is the same in every product.
+// Several products in one launch (the split-precision forward: hi x hi, hi x lo, lo x hi): an operand
+// given as HiLo reads its `lo` matrix in product p when bit p of lo_mask is set, else its `hi` matrix
+// (a plain loader is the same in every product).  Two ways to lay them out: over the z index, each
+// product into its own group of K slices (more workgroups in flight: the wide FC1), or inside the
+// workgroup, its K loop run once per product with the accumulator carried across (no extra partial
+// sums, so a bias epilogue can finish the sum directly: the short-K FC2).
 template <class L>
 struct HiLo {
   L hi, lo;
@@ -293,7 +295,7 @@ __device__ __forceinline__ TileId xcd_tile() {
 
 template <int BM, int BN, int BK, int WM, int WN, class LA0, class LB0, class EPI>
 __global__ __launch_bounds__(256) void k_gemm(LA0 la0, LB0 lb0, EPI epi, int M, int N, int K, int k_split,
-                                              int zper) {
+                                              int zper, int kprod) {
   using LA = Bound<LA0>;
   using LB = Bound<LB0>;
   using C = Cfg<BM, BN, BK, WM, WN>;
@@ -307,11 +309,9 @@ __global__ __launch_bounds__(256) void k_gemm(LA0 la0, LB0 lb0, EPI epi, int M, 
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int wm = wave / WN, wn = wave % WN;
   const TileId tile = xcd_tile();
-  const int prod = zper > 0 ? tile.tz / zper : 0;
-  const LA la = bind_product(la0, prod);
-  const LB lb = bind_product(lb0, prod);
   const int m_blk = tile.tm * BM, n_blk = tile.tn * BN;   // M tiles on x (up to 2^31 - 1)
-  const int kb = (tile.tz - prod * zper) * k_split;
+  const int zg = zper > 0 ? tile.tz / zper : 0;   // product group of the z index
+  const int kb = (tile.tz - zg * zper) * k_split;
   const int ke = min(K, kb + k_split);
   f32x4 acc[C::FM][C::FN];
 #pragma unroll
@@ -332,11 +332,14 @@ __global__ __launch_bounds__(256) void k_gemm(LA0 la0, LB0 lb0, EPI epi, int M, 
                                                            : make_uint4(0u, 0u, 0u, 0u);
     }
   }
-  const TileOff oa = tile_offsets<LA, BM, BK>(la), ob = tile_offsets<LB, BN, BK>(lb);
   const int nsteps = (ke - kb + BK - 1) / BK;
   const int ra0 = wm * C::TM + (lane & 15), rb0 = wn * C::TN + (lane & 15), kl = 8 * (lane >> 4);
   uint16_t* const sA1 = sA + SA::kElems;
   uint16_t* const sB1 = sB + SB::kElems;
+  for (int ip = 0; ip < kprod; ++ip) {   // every path below ends at a barrier: the stages are free again
+  const LA la = bind_product(la0, zg * kprod + ip);
+  const LB lb = bind_product(lb0, zg * kprod + ip);
+  const TileOff oa = tile_offsets<LA, BM, BK>(la), ob = tile_offsets<LB, BN, BK>(lb);
   // Steps whose tiles are interior in both operands (rows inside, K step whole) run a loop with two
   // stages of loads in registers: step t's MFMAs overlap the loads of step t + 2, and the stores of
   // step t + 1 wait only for loads issued a whole step earlier.  Every step issues the same loads
@@ -403,6 +406,7 @@ __global__ __launch_bounds__(256) void k_gemm(LA0 la0, LB0 lb0, EPI epi, int M, 
       __syncthreads();
     }
   }
+  }   // products
   // stage the FP32 tile through LDS, then hand rows of eight columns to the epilogue
   float* sc = reinterpret_cast<float*>(smem);
   constexpr int LDC = BN + 4;
@@ -432,21 +436,23 @@ __global__ __launch_bounds__(256) void k_gemm(LA0 la0, LB0 lb0, EPI epi, int M, 
   }
 }
 
-// `products` products (HiLo operands) of `splits` K slices each, slice z of product p at z index
-// p * nz + z (nz = the slices K actually splits into).
+// `products` products (HiLo operands), K split `splits` ways (nz = the slices K actually splits into):
+// over z, product p's slice z at z index p * nz + z (in_kernel = false); or summed in each workgroup,
+// slice z at z index z (in_kernel = true).
 template <int BM, int BN, int BK, int WM, int WN, class LA, class LB, class EPI>
 hipError_t run(const LA& la, const LB& lb, const EPI& epi, int M, int N, int K, int splits, hipStream_t st,
-               int products = 1) {
+               int products = 1, bool in_kernel = false) {
   if (M <= 0 || N <= 0) return hipSuccess;
   if (splits < 1) splits = 1;
   if (products < 1) products = 1;
   int k_split = (K + splits - 1) / splits;
   k_split = (k_split + BK - 1) / BK * BK;
   const int nz = K > 0 ? (K + k_split - 1) / k_split : 1;
-  if ((N + BN - 1) / BN > 65535 || (int64_t)nz * products > 65535) return hipErrorInvalidValue;
-  dim3 grid((M + BM - 1) / BM, (N + BN - 1) / BN, nz * products);
+  const int zprod = in_kernel ? 1 : products;
+  if ((N + BN - 1) / BN > 65535 || (int64_t)nz * zprod > 65535) return hipErrorInvalidValue;
+  dim3 grid((M + BM - 1) / BM, (N + BN - 1) / BN, nz * zprod);
   k_gemm<BM, BN, BK, WM, WN, LA, LB, EPI><<<grid, 256, 0, st>>>(la, lb, epi, M, N, K, k_split,
-                                                                 products > 1 ? nz : 0);
+                                                                 zprod > 1 ? nz : 0, in_kernel ? products : 1);
   return hipGetLastError();
 }
 

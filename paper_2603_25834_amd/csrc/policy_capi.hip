@@ -97,10 +97,8 @@ int64_t part_need(const aslam_policy* p) {
   need = std::max<int64_t>(need, (int64_t)kConvBwdGrid * kConvPart);   // encoder backward partials
   need = std::max<int64_t>(need, (int64_t)kBiasBlocks * 256);
   need = std::max<int64_t>(need, (int64_t)kFc1MinBlocks * 64 * kHid);   // FC1 forward split-K: S * B <= 512 * 64
-  if (p->prec) {   // the three products of a split FC1 (S * B <= 512 * 64 each) and of FC2 (one slice each)
+  if (p->prec)   // the three products of a split FC1, over z (S * B <= 512 * 64 each)
     need = std::max<int64_t>(need, 3 * (int64_t)kFc1MinBlocks * 64 * kHid);
-    need = std::max<int64_t>(need, 3 * p->max_b * kHid);
-  }
   return need;
 }
 
@@ -183,7 +181,7 @@ int encode_fc1(aslam_policy* P, const float* prm, const int16_t* crop, const flo
   if (P->prec && tiles < 32) S = std::max(1, std::min(32, kFc1MinBlocks / (3 * tiles)));
   if (P->prec) {
     // x_hi W_hi, x_hi W_lo and x_lo W_hi, each split S ways, into consecutive groups of slices (one
-    // launch: product 1 reads W's lo part, product 2 x's)
+    // launch, the products over z: product 1 reads W's lo part, product 2 x's)
     const int nz = slices_used(K1, S, 64);
     const int64_t slice = (int64_t)B * kHid;
     PCHK((gemm::run<128, 128, 64, 2, 2>(gemm::HiLo<LdBF16K>{xa, LdBF16K{P->x_lo, K1, B, K1}, 4u},
@@ -218,15 +216,10 @@ int forward_core(aslam_policy* P, const float* prm, const int16_t* crop, const f
   }
   const LdBF16K ha{P->h1, kHid, B, kHid}, wb{P->w2b, kHid, kHid, kHid};
   if (P->prec) {
-    // z2 = h1_hi W2_hi + h1_hi W2_lo + h1_lo W2_hi (+ b2), one slice per product, one launch
-    const int64_t slice = (int64_t)B * kHid;
+    // z2 = h1_hi W2_hi + h1_hi W2_lo + h1_lo W2_hi + b2, the three products in one accumulator
     PCHK((gemm::run<128, 128, 64, 2, 2>(gemm::HiLo<LdBF16K>{ha, LdBF16K{P->h1_lo, kHid, B, kHid}, 4u},
                                        gemm::HiLo<LdBF16K>{wb, LdBF16K{P->w2b_lo, kHid, kHid, kHid}, 2u},
-                                       EpiPartial{P->part, kHid, slice}, B, kHid, kHid, 1, st, 3)));
-    const int64_t groups = (int64_t)B * (kHid / 8);
-    k_reduce_bias_f32<<<(int)std::min<int64_t>(4096, (groups + 255) / 256), 256, 0, st>>>(P->part, 3, B, kHid,
-                                                                                          prm + o.f2b, P->z2, kHid);
-    PCHK(hipGetLastError());
+                                       EpiBiasF32{P->z2, prm + o.f2b, kHid}, B, kHid, kHid, 1, st, 3, true)));
     return ASL_OK;
   }
   PCHK((gemm::run<128, 128, 64, 2, 2>(ha, wb, EpiBiasF32{P->z2, prm + o.f2b, kHid}, B, kHid, kHid, 1, st)));

@@ -479,25 +479,6 @@ __global__ void k_reduce_bias_relu_bf16(const float* part, int S, int M, int N, 
   }
 }
 
-// Split-K finish into FP32 with a bias: out[m][n] = bias[n] + sum_z part[z][m][n], z in order.
-__global__ void k_reduce_bias_f32(const float* part, int S, int M, int N, const float* bias, float* out, int64_t ldo) {
-  const int64_t groups = (int64_t)M * (N / 8);
-  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < groups;
-       g += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t m = g / (N / 8);
-    const int n0 = (int)(g - m * (N / 8)) * 8;
-    float a[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) a[j] = 0.0f;
-    sum_slices8(part + m * N + n0, S, (int64_t)M * N, a);
-    float* q = out + m * ldo + n0;
-    *reinterpret_cast<float4*>(q) = make_float4(a[0] + bias[n0], a[1] + bias[n0 + 1], a[2] + bias[n0 + 2],
-                                                a[3] + bias[n0 + 3]);
-    *reinterpret_cast<float4*>(q + 4) = make_float4(a[4] + bias[n0 + 4], a[5] + bias[n0 + 5], a[6] + bias[n0 + 6],
-                                                    a[7] + bias[n0 + 7]);
-  }
-}
-
 // The same for many slices (a small batch split many ways): each wave sums a quarter of the slices
 // for 64 consecutive 8-column groups, and wave 0 adds the four quarters in order.
 __global__ __launch_bounds__(256) void k_reduce_bias_relu_bf16_q(const float* part, int S, int M, int N,
