@@ -62,6 +62,7 @@ struct aslam_env {
   // device allocations
   void* d_meta = nullptr;
   void* d_order = nullptr;
+  void* d_cost = nullptr;
   void* d_world = nullptr;
   void* d_belief = nullptr;
   void* d_pose = nullptr;
@@ -99,7 +100,7 @@ struct aslam_env {
 namespace {
 
 void free_env(aslam_env* e) {
-  void** ptrs[] = {&e->d_meta, &e->d_order, &e->d_world, &e->d_belief, &e->d_pose, &e->d_est, &e->d_cov,
+  void** ptrs[] = {&e->d_meta, &e->d_order, &e->d_cost, &e->d_world, &e->d_belief, &e->d_pose, &e->d_est, &e->d_cov,
                    &e->d_hq_total, &e->d_step, &e->d_last_lc, &e->d_visit_t, &e->d_visit_xy, &e->d_rho,
                    &e->d_hitc, &e->d_flags, &e->d_terms, &e->d_counters, &e->d_raylen, &e->d_dirtab, &e->d_hq_lut,
                    &e->d_visit_last, &e->d_prev_vcell, &e->d_u_prev, &e->d_dcells, &e->d_dmin, &e->d_draws};
@@ -360,6 +361,7 @@ int aslam_env_create(const aslam_env_config* cfg, int32_t n_robots, const int32_
   struct Alloc { void** p; size_t bytes; } allocs[] = {
       {&e->d_meta, sizeof(RobotMeta) * (size_t)n_robots},
       {&e->d_order, sizeof(int32_t) * (size_t)n_robots},
+      {&e->d_cost, sizeof(int32_t) * (size_t)n_robots},
       {&e->d_world, sizeof(uint32_t) * (size_t)e->world_words},
       {&e->d_belief, sizeof(int16_t) * (size_t)e->cells},
       {&e->d_pose, sizeof(float) * 3 * (size_t)n_robots},
@@ -401,6 +403,10 @@ int aslam_env_create(const aslam_env_config* cfg, int32_t n_robots, const int32_
   hipError_t he = hipSuccess;
   if (he == hipSuccess) he = hipMemcpy(e->d_meta, e->meta_h.data(), sizeof(RobotMeta) * n_robots, hipMemcpyHostToDevice);
   if (he == hipSuccess) he = hipMemcpy(e->d_order, order.data(), sizeof(int32_t) * n_robots, hipMemcpyHostToDevice);
+  // until a robot has stepped, its grid area stands in for its work
+  std::vector<int32_t> cost0(n_robots);
+  for (int32_t r = 0; r < n_robots; ++r) cost0[r] = (int32_t)std::min<int64_t>((int64_t)e->sides[r] * e->sides[r] / 4, 1 << 30);
+  if (he == hipSuccess) he = hipMemcpy(e->d_cost, cost0.data(), sizeof(int32_t) * n_robots, hipMemcpyHostToDevice);
   if (he == hipSuccess) he = hipMemcpy(e->d_dirtab, dirtab.data(), sizeof(int32_t) * kNang, hipMemcpyHostToDevice);
   if (he == hipSuccess) he = hipMemcpy(e->d_hq_lut, lut.data(), sizeof(uint32_t) * lut.size(), hipMemcpyHostToDevice);
   if (he == hipSuccess) he = hipMemset(e->d_draws, 0, sizeof(uint64_t) * (size_t)n_robots);
@@ -467,7 +473,8 @@ int aslam_env_create(const aslam_env_config* cfg, int32_t n_robots, const int32_
   P.u_hi = cfg->u_hi;
   P.kappa = cfg->kappa;
   P.meta = (const RobotMeta*)e->d_meta;
-  P.order = (const int32_t*)e->d_order;
+  P.order = (int32_t*)e->d_order;
+  P.cost = (int32_t*)e->d_cost;
   P.world = (const uint32_t*)e->d_world;
   P.belief = (int16_t*)e->d_belief;
   P.pose = (float*)e->d_pose;

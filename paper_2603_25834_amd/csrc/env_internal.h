@@ -62,7 +62,8 @@ struct EnvParams {
   float r_max, r_min, range_sigma, range_quant, inv_quant;
   float d_crash, d_full, lambda_explore, lambda_abs, lambda_delta, u_hi, kappa;
   const RobotMeta* meta;
-  const int32_t* order;  // robots, largest grid first
+  int32_t* order;        // [n] the fused step's robot of each workgroup: the most work first
+  int32_t* cost;         // [n] DDA cell visits of the robot's last step (its next step's work, nearly)
   const uint32_t* world;
   int16_t* belief;
   float* pose;

@@ -1044,6 +1044,7 @@ __device__ void update_and_reward(const EnvParams& P, const StepArgs& A, const R
     cnt[0] += dsum;
     cnt[1] += sh->cnt_march;
     cnt[2] += sh->cnt_upd;
+    P.cost[r] = sh->cnt_march + sh->cnt_upd;
     P.hq_total[r] += tot;
     const double rH = (double)(-tot) * (1.0 / 4294967296.0);
     const float* c = P.cov + 6 * (int64_t)r;
@@ -1193,8 +1194,51 @@ __device__ __forceinline__ void fused_robot(const EnvParams& P, const StepArgs& 
   update_and_reward<NT, SEG>(P, A, m, V, L, r);
 }
 
-// Fused step, one workgroup per robot: workgroup b takes the b-th robot of the
-// largest-grid-first order, so the dispatcher hands out the big grids first.  The segmented instance
+// The fused step's order of robots, the most work first (largest-processing-time order): a counting
+// sort of the robots' last-step DDA visits into 1024 buckets, one workgroup.  A CU takes its workgroups
+// in launch order and its SIMDs issue the oldest waves first, so the robot a CU got last runs on what
+// the others leave; with the heaviest robots first and the lightest last, the CUs' robots end together
+// instead of the last-placed heavy ones setting the launch's length.  Robots are independent: the order
+// changes no result.
+constexpr int kOrderThreads = 1024;
+constexpr int kOrderBuckets = 1024;
+
+__global__ __launch_bounds__(kOrderThreads) void k_order(int32_t n, const int32_t* __restrict__ cost,
+                                                         int32_t* __restrict__ order) {
+  __shared__ int32_t s_hist[kOrderBuckets];
+  __shared__ int32_t s_max[kOrderThreads / 64];
+  const int32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  int32_t mx = 0;
+  for (int32_t r = tid; r < n; r += kOrderThreads) mx = max(mx, cost[r]);
+  mx = wave_max_i32(mx);
+  if (lane == 0) s_max[wave] = mx;
+  for (int32_t b = tid; b < kOrderBuckets; b += kOrderThreads) s_hist[b] = 0;
+  __syncthreads();
+  mx = 0;
+  for (int w = 0; w < kOrderThreads / 64; ++w) mx = max(mx, s_max[w]);
+  const int32_t q = mx / kOrderBuckets + 1;
+  for (int32_t r = tid; r < n; r += kOrderThreads) atomicAdd(&s_hist[kOrderBuckets - 1 - min(cost[r] / q, kOrderBuckets - 1)], 1);
+  __syncthreads();
+  // exclusive prefix sum of the buckets (the heaviest bucket first), one bucket per thread
+  const int32_t v = tid < kOrderBuckets ? s_hist[tid] : 0;
+  int32_t x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int32_t y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  __syncthreads();
+  if (lane == 63) s_max[wave] = x;
+  __syncthreads();
+  int32_t base = 0;
+  for (int w = 0; w < wave; ++w) base += s_max[w];
+  if (tid < kOrderBuckets) s_hist[tid] = base + x - v;
+  __syncthreads();
+  for (int32_t r = tid; r < n; r += kOrderThreads)
+    order[atomicAdd(&s_hist[kOrderBuckets - 1 - min(cost[r] / q, kOrderBuckets - 1)], 1)] = r;
+}
+
+// Fused step, one workgroup per robot: workgroup b takes the b-th robot of the most-work-first order.  The segmented instance
 // is held to 80 VGPRs (six waves per SIMD: three 512-thread workgroups per CU, every robot of a
 // 750-robot batch resident at once); unbounded it takes 89 and fits two, which costs more than the
 // few spilled values do.
@@ -1558,6 +1602,7 @@ hipError_t plain_nt(const EnvParams& P, const StepArgs& A, const LdsPlan& L, hip
 template <int NT>
 hipError_t fused_nt(const EnvParams& P, const StepArgs& A, const LdsPlan& L, int grid, hipStream_t st) {
   const bool seg = L.mark_seg > 0;
+  if (P.n > 1) k_order<<<1, kOrderThreads, 0, st>>>(P.n, P.cost, P.order);
   if (grid >= P.n) {
     if (seg) k_fused<NT, true><<<P.n, NT, L.total, st>>>(P, A, L);
     else k_fused<NT, false><<<P.n, NT, L.total, st>>>(P, A, L);
