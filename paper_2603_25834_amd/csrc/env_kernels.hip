@@ -630,9 +630,9 @@ __device__ void march_rays(const EnvParams& P, const RobotMeta& m, const LdsView
         uint32_t wd[kLook];
 #pragma unroll
         for (int u = 0; u < kLook; ++u) wd[u] = sw[l[u] >> 5];   // inside the guard words
-        uint32_t bits = 0u;
+        uint32_t bits = 0u;   // v_bfe_u32 takes the bit offset mod 32 itself
 #pragma unroll
-        for (int u = 0; u < kLook; ++u) bits |= ((wd[u] >> (l[u] & 31)) & 1u) << u;
+        for (int u = 0; u < kLook; ++u) bits |= __builtin_amdgcn_ubfe(wd[u], (uint32_t)l[u], 1u) << u;
         const int32_t rem = q.n - i;   // >= 1 while the lane walks
         bits &= rem >= kLook ? (1u << kLook) - 1u : ((1u << rem) - 1u);
         if (bits) {
