@@ -199,6 +199,9 @@ __global__ __launch_bounds__(kCsmLdsThreads) void k_csm_lds(const int16_t* __res
   const int32_t px = pose_q[3 * r], py = pose_q[3 * r + 1], ph = pose_q[3 * r + 2];
   const int32_t* rho = rho_q + (int64_t)r * R;
   int used = 0;
+  bool far_off = false;   // a ray offset beyond 2^29 (Q16) in either axis; the workgroup's OR in s_red[0][0]
+  if (threadIdx.x == 0) s_red[0][0] = 0;
+  __syncthreads();
   for (int e = threadIdx.x; e < nk * R; e += kCsmLdsThreads) {
     const int k = e / R, q = e - k * R;
     const int32_t rq = rho[q];
@@ -210,10 +213,12 @@ __global__ __launch_bounds__(kCsmLdsThreads) void k_csm_lds(const int16_t* __res
       const int32_t c = (int32_t)(int16_t)(d & 0xffff), s = d >> 16;
       o.x = (int32_t)(((int64_t)rq * c) >> 14);
       o.y = (int32_t)(((int64_t)rq * s) >> 14);
+      far_off |= abs(o.x) > (1 << 29) || abs(o.y) > (1 << 29);
       if (k == 0) ++used;
     }
     s_off[e] = o;
   }
+  if (__builtin_amdgcn_ballot_w64(far_off) != 0 && (threadIdx.x & 63) == 0) atomicOr(&s_red[0][0], 1);
   const int32_t sd = side[r];
   const int64_t base = cell_off[r];
   const bool staged = sd > 0 && sd <= lds_side;
@@ -223,14 +228,28 @@ __global__ __launch_bounds__(kCsmLdsThreads) void k_csm_lds(const int16_t* __res
   if (staged) {
     const int64_t cells = (int64_t)sd * sd;
     if ((reinterpret_cast<uintptr_t>(belief + base) & 15) == 0 && (sd & 7) == 0 && (pad & 1) == 0) {
-      // 8 cells per access: one 16-byte read, four 4-byte writes (rows start on 4-byte boundaries)
+      // 8 cells per access: one 16-byte read, four 4-byte writes (rows start on 4-byte boundaries);
+      // each thread has kStage reads in flight before it writes any (a staged side is small, so the
+      // indices fit 32 bits)
+      constexpr int kStage = 8;
       const uint4* src = reinterpret_cast<const uint4*>(belief + base);
-      const int per_row = sd >> 3;
-      for (int64_t v = threadIdx.x; v < cells / 8; v += kCsmLdsThreads) {
-        const uint4 t = src[v];
-        const int y = (int)(v / per_row), x = (int)(v - (int64_t)y * per_row) * 8;
-        uint32_t* d = reinterpret_cast<uint32_t*>(s_grid + (int64_t)y * pitch + x);
-        d[0] = t.x; d[1] = t.y; d[2] = t.z; d[3] = t.w;
+      const uint32_t per_row = (uint32_t)sd >> 3, total = (uint32_t)(cells >> 3);
+      for (uint32_t v0 = threadIdx.x; v0 < total; v0 += kStage * kCsmLdsThreads) {
+        uint4 t[kStage];
+#pragma unroll
+        for (int u = 0; u < kStage; ++u) {
+          const uint32_t v = v0 + u * kCsmLdsThreads;
+          if (v < total) t[u] = src[v];
+        }
+#pragma unroll
+        for (int u = 0; u < kStage; ++u) {
+          const uint32_t v = v0 + u * kCsmLdsThreads;
+          if (v < total) {
+            const uint32_t y = v / per_row, x = (v - y * per_row) * 8;
+            uint32_t* d = reinterpret_cast<uint32_t*>(s_grid + y * (uint32_t)pitch + x);
+            d[0] = t[u].x; d[1] = t[u].y; d[2] = t[u].z; d[3] = t[u].w;
+          }
+        }
       }
     } else {
       for (int64_t e = threadIdx.x; e < cells; e += kCsmLdsThreads) {
@@ -240,6 +259,7 @@ __global__ __launch_bounds__(kCsmLdsThreads) void k_csm_lds(const int16_t* __res
     }
   }
   __syncthreads();
+  far_off = s_red[0][0] != 0;
   // lines x chunks of rays
   const int chunks = max(1, min(R, kCsmLdsThreads / nline));
   int32_t acc[kCsmLdsMaxLine];
@@ -247,11 +267,14 @@ __global__ __launch_bounds__(kCsmLdsThreads) void k_csm_lds(const int16_t* __res
   for (int i = 0; i < kCsmLdsMaxLine; ++i) acc[i] = 0;
   const int line = threadIdx.x / chunks, ch = threadIdx.x - line * chunks;
   // One instance per grid location, so that the reads of a staged grid compile to LDS reads (a pointer
-  // that may point to either memory would make every read a flat access).
-  auto score = [&](const int16_t* g) {
+  // that may point to either memory would make every read a flat access).  The cell arithmetic runs in
+  // I: 32 bits for a staged grid whose search centre is within 2^28 and whose ray offsets are within
+  // 2^29 (every candidate's Q16 coordinate then stays within 2^30), else 64.
+  auto score = [&](const int16_t* g, auto tag) {
+    using I = decltype(tag);
     const int k = line / nw, j = line - k * nw;
     const int q0 = (int)((int64_t)ch * R / chunks), q1 = (int)((int64_t)(ch + 1) * R / chunks);
-    const int64_t x0 = (int64_t)px - (int64_t)W * step_xy, y = (int64_t)py + (int64_t)(j - W) * step_xy;
+    const I x0 = (I)px - (I)W * step_xy, y = (I)py + (I)(j - W) * step_xy;
     const int2* o = s_off + k * R;
     // four rays per step, every read issued before any is used: a cell off the grid reads cell 0 of
     // the grid and adds nothing
@@ -262,13 +285,13 @@ __global__ __launch_bounds__(kCsmLdsThreads) void k_csm_lds(const int16_t* __res
 #pragma unroll
       for (int u = 0; u < kRays; ++u) {
         const int2 v = o[q + u];
-        const int64_t cy = (y + v.y) >> 16;
+        const I cy = (y + v.y) >> 16;
         const bool row_ok = cy >= 0 && cy < sd;
         const int16_t* grow = g + (row_ok ? cy : 0) * pitch;
-        const int64_t ex = x0 + v.x;
+        const I ex = x0 + v.x;
 #pragma unroll
         for (int i = 0; i < kCsmLdsMaxLine; ++i) {
-          const int64_t cx = (ex + (int64_t)i * step_xy) >> 16;
+          const I cx = (ex + (I)i * step_xy) >> 16;
           const bool ok = row_ok && i < nw && cx >= 0 && cx < sd;
           const int32_t t = grow[ok ? cx : 0];
           val[u][i] = ok ? t : 0;
@@ -281,24 +304,27 @@ __global__ __launch_bounds__(kCsmLdsThreads) void k_csm_lds(const int16_t* __res
     }
     for (; q < q1; ++q) {
       const int2 v = o[q];
-      const int64_t cy = (y + v.y) >> 16;
+      const I cy = (y + v.y) >> 16;
       if (cy < 0 || cy >= sd) continue;
       const int16_t* grow = g + cy * pitch;
-      const int64_t ex = x0 + v.x;
+      const I ex = x0 + v.x;
 #pragma unroll
       for (int i = 0; i < kCsmLdsMaxLine; ++i) {
         if (i < nw) {
-          const int64_t cx = (ex + (int64_t)i * step_xy) >> 16;
+          const I cx = (ex + (I)i * step_xy) >> 16;
           if (cx >= 0 && cx < sd) acc[i] += grow[cx];
         }
       }
     }
   };
+  const bool near = !far_off && px > -(1 << 28) && px < (1 << 28) && py > -(1 << 28) && py < (1 << 28);
   if (line < nline && sd > 0) {   // an empty grid scores 0 everywhere
-    if (staged)
-      score(s_grid);
+    if (staged && near)
+      score(s_grid, int32_t{});
+    else if (staged)
+      score(s_grid, int64_t{});
     else
-      score(belief + base);
+      score(belief + base, int64_t{});
   }
   __syncthreads();   // every line is done with the offsets: their space takes the partial sums
   if (line < nline) {

@@ -91,6 +91,28 @@ def test_match_staged_and_global_grids(sides, max_side):
         assert tuple(int(v) for v in got[r]) == want, (r, got[r], want)
 
 
+def test_match_far_centres_and_offsets():
+    """Staged grids are scored in 32-bit cell arithmetic only when the search centre lies within 2^28
+    and every ray offset within 2^29 (Q16); a robot beyond either bound is scored in 64 bits in the same
+    launch: a centre far off the grid, ranges near the int32 limit on half the rays, a centre just inside
+    the bound, and ordinary robots beside them, all against the oracle."""
+    W, V, sxy, sh, R = 4, 5, 65536, 64, 128
+    sides = [64, 96, 128, 64, 128]
+    grids, belief, cell_off, side, pose, rho, a_off = _batch(91, sides, R, W, V, sxy, sh, invalid_p=0.05)
+    pose[0, 0] = (1 << 28) + 5 * 65536                  # centre beyond the bound: 64-bit arithmetic
+    pose[1, 1] = -(1 << 29)
+    rho[3, ::2] = (1 << 31) - 1 - np.arange(0, R, 2)     # offsets near the int32 limit on half the rays
+    pose[4, 0] = (1 << 28) - 65536 - 1                  # centre just inside the bound, far off its grid
+    say(f"[slam] csm far centres and offsets R={R} robots={len(sides)}")
+    got, _ = _gpu_match(belief, cell_off, side, pose, rho, a_off, W, V, sxy, sh)
+    trig = S._trig()
+    for r in range(len(sides)):
+        want = S.csm_match(grids[r], int(pose[r, 0]), int(pose[r, 1]), int(pose[r, 2]), rho[r], a_off, W, V, sxy, sh,
+                           trig)
+        assert tuple(int(v) for v in got[r]) == want, (r, got[r], want)
+    assert got[3][5] == int(np.sum(rho[3] >= 0))        # the far rays count as used rays
+
+
 def test_factor_matches_oracle_exactly():
     W, V, sxy, sh, R = 4, 5, 32768, 48, 90
     sides = [64, 96, 128, 256, 32, 64]
