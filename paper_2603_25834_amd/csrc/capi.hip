@@ -63,6 +63,7 @@ struct aslam_env {
   void* d_meta = nullptr;
   void* d_order = nullptr;
   void* d_cost = nullptr;
+  int64_t fused_steps = 0;   // fused steps launched: the robot order is refreshed on every kOrderEvery-th
   void* d_world = nullptr;
   void* d_belief = nullptr;
   void* d_pose = nullptr;
@@ -590,7 +591,7 @@ static int do_step(aslam_env* env, const StepArgs& A, hipStream_t st) {
     he = launch_step_plain(env->P, A, env->L, env->ex.threads, st);
   } else {
     const int grid = env->ex.grid > 0 ? std::min(env->ex.grid, env->n) : env->n;
-    he = launch_step_fused(env->P, A, env->L, env->ex.threads, grid, st);
+    he = launch_step_fused(env->P, A, env->L, env->ex.threads, grid, env->fused_steps++ % kOrderEvery == 0, st);
   }
   if (he != hipSuccess) return hip_fail(he, "env_step launch");
   return ASL_OK;

@@ -144,8 +144,12 @@ hipError_t launch_reset(const EnvParams& P, const uint32_t* world_src, const flo
                         const uint8_t* mask, int32_t max_side, hipStream_t stream);
 hipError_t launch_step_plain(const EnvParams& P, const StepArgs& A, const LdsPlan& L, int threads,
                              hipStream_t stream);
+// The fused step's robot order (most work first) is refreshed by a sort of the robots' last-step work
+// before every kOrderEvery-th fused step: the work a robot does changes slowly from step to step, and
+// the order never changes a result.
+constexpr int kOrderEvery = 4;
 hipError_t launch_step_fused(const EnvParams& P, const StepArgs& A, const LdsPlan& L, int threads,
-                             int grid, hipStream_t stream);
+                             int grid, bool order, hipStream_t stream);
 hipError_t launch_step_fixedlag(const EnvParams& P, const StepArgs& A, const LdsPlan& L, const FixedLag& F,
                                 int threads, hipStream_t stream);
 hipError_t launch_reset_fixedlag(const EnvParams& P, const FixedLag& F, const float* init_pose, const uint8_t* mask,

@@ -1600,9 +1600,9 @@ hipError_t plain_nt(const EnvParams& P, const StepArgs& A, const LdsPlan& L, hip
 }
 
 template <int NT>
-hipError_t fused_nt(const EnvParams& P, const StepArgs& A, const LdsPlan& L, int grid, hipStream_t st) {
+hipError_t fused_nt(const EnvParams& P, const StepArgs& A, const LdsPlan& L, int grid, bool order, hipStream_t st) {
   const bool seg = L.mark_seg > 0;
-  if (P.n > 1) k_order<<<1, kOrderThreads, 0, st>>>(P.n, P.cost, P.order);
+  if (order && P.n > 1) k_order<<<1, kOrderThreads, 0, st>>>(P.n, P.cost, P.order);
   if (grid >= P.n) {
     if (seg) k_fused<NT, true><<<P.n, NT, L.total, st>>>(P, A, L);
     else k_fused<NT, false><<<P.n, NT, L.total, st>>>(P, A, L);
@@ -1654,13 +1654,13 @@ hipError_t launch_step_plain(const EnvParams& P, const StepArgs& A, const LdsPla
 }
 
 hipError_t launch_step_fused(const EnvParams& P, const StepArgs& A, const LdsPlan& L, int threads, int grid,
-                             hipStream_t stream) {
+                             bool order, hipStream_t stream) {
   switch (threads) {
-    case 128: return fused_nt<128>(P, A, L, grid, stream);
-    case 192: return fused_nt<192>(P, A, L, grid, stream);
-    case 256: return fused_nt<256>(P, A, L, grid, stream);
-    case 384: return fused_nt<384>(P, A, L, grid, stream);
-    case 512: return fused_nt<512>(P, A, L, grid, stream);
+    case 128: return fused_nt<128>(P, A, L, grid, order, stream);
+    case 192: return fused_nt<192>(P, A, L, grid, order, stream);
+    case 256: return fused_nt<256>(P, A, L, grid, order, stream);
+    case 384: return fused_nt<384>(P, A, L, grid, order, stream);
+    case 512: return fused_nt<512>(P, A, L, grid, order, stream);
     default: return hipErrorInvalidValue;
   }
 }
