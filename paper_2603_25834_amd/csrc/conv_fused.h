@@ -105,8 +105,8 @@ __device__ __forceinline__ bf16x8 conv2_weight_frag(const float* w2, int co, int
 constexpr int kConvFrags = 11;
 
 template <bool LO = false>
-__global__ __launch_bounds__(64 * kConvFrags) void k_conv_frags(const float* prm, Offsets o, uint4* frag) {
-  const int f = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
+__device__ __forceinline__ void conv_frag_elem(const float* prm, const Offsets& o, uint4* frag, int idx) {
+  const int f = idx >> 6, lane = idx & 63, lr = lane & 15, lg = lane >> 4;
   bf16x8 v;
   if (f == 0) {
     v = conv1_weight_frag<LO>(prm + o.c1w, lr, lg);
@@ -114,7 +114,12 @@ __global__ __launch_bounds__(64 * kConvFrags) void k_conv_frags(const float* prm
     const int nt = (f - 1) / 5, s = (f - 1) % 5;
     v = conv2_weight_frag<LO>(prm + o.c2w, 16 * nt + lr, s, lg);
   }
-  frag[threadIdx.x] = __builtin_bit_cast(uint4, v);
+  frag[idx] = __builtin_bit_cast(uint4, v);
+}
+
+template <bool LO = false>
+__global__ __launch_bounds__(64 * kConvFrags) void k_conv_frags(const float* prm, Offsets o, uint4* frag) {
+  conv_frag_elem<LO>(prm, o, frag, threadIdx.x);
 }
 
 // A 64x64 int16 crop is 512 vectors of eight cells (row y = v / 8, columns
@@ -438,8 +443,8 @@ __device__ __forceinline__ bf16x8 phase_weight_frag(const float* w2, int ky, int
 constexpr int kConvPhaseFrags = 9;
 static_assert(kConvLoFrag == kConvFrags + kConvPhaseFrags, "lo fragments follow the backward's");
 
-__global__ __launch_bounds__(64 * kConvPhaseFrags) void k_conv_bwd_frags(const float* prm, Offsets o, uint4* frag) {
-  const int f = threadIdx.x >> 6, lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
+__device__ __forceinline__ void conv_bwd_frag_elem(const float* prm, const Offsets& o, uint4* frag, int idx) {
+  const int f = idx >> 6, lane = idx & 63, lr = lane & 15, lg = lane >> 4;
   int q = 0;
 #pragma unroll
   for (int ph = 0; ph < 4; ++ph) {
@@ -454,6 +459,10 @@ __global__ __launch_bounds__(64 * kConvPhaseFrags) void k_conv_bwd_frags(const f
       }
     }
   }
+}
+
+__global__ __launch_bounds__(64 * kConvPhaseFrags) void k_conv_bwd_frags(const float* prm, Offsets o, uint4* frag) {
+  conv_bwd_frag_elem(prm, o, frag, threadIdx.x);
 }
 
 // PREC: conv1 is recomputed with split operands (the crop's lo part staged beside it), so its ReLU

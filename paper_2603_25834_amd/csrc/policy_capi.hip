@@ -36,7 +36,7 @@ struct aslam_policy {
   int64_t max_b = 0;
   uint16_t *x = nullptr;   // FC1 input [B][k1p]: conv features (8192) | scan | state | zero pad, BF16
   uint16_t *h1 = nullptr, *dz2 = nullptr, *dz1 = nullptr, *dz2c = nullptr;
-  float *z2 = nullptr, *part = nullptr, *hpart = nullptr, *hsum = nullptr;
+  float *z2 = nullptr, *part = nullptr, *hpart = nullptr;
   uint16_t *w1b = nullptr, *w1t = nullptr, *w2b = nullptr, *w2t = nullptr;   // BF16 weight copies
   uint4* cfrag = nullptr;   // the encoder's weight fragments (k_conv_frags, k_conv_bwd_frags)
   int32_t k1p = 0;   // FC1 input width padded to a multiple of 8
@@ -108,14 +108,56 @@ int64_t part_need(const aslam_policy* p) {
     if (e_ != hipSuccess) return pfail(ASL_EHIP, hipGetErrorString(e_)); \
   } while (0)
 
+// The MLP policy's weight preparation in one launch, the jobs taken by workgroup ranges in this order:
+// kPrepW1 workgroups convert W1 (and its lo part), kPrepW2 convert W2, then with `transposed` the
+// 32 x 32 tiles of W1's conv-feature columns and of W2 transposed, and the last workgroup forms the
+// encoder's fragments (the forward's, with PREC their lo parts, with `transposed` the backward's phase
+// fragments).  Each job does what its own kernel (k_convert_bf16, k_transpose_bf16, k_conv_frags,
+// k_conv_bwd_frags) does, value for value; one launch instead of up to seven per parameter update.
+constexpr int kPrepW1 = 1024, kPrepW2 = 256;
+constexpr int kPrepT1 = (kFeat / 32) * (kHid / 32), kPrepT2 = (kHid / 32) * (kHid / 32);
+
+__global__ __launch_bounds__(256) void k_prep_mlp(const float* __restrict__ prm, Offsets o, int k1p,
+                                                  uint16_t* w1b, uint16_t* w1b_lo, uint16_t* w2b, uint16_t* w2b_lo,
+                                                  uint16_t* w1t, uint16_t* w2t, uint4* cfrag, int transposed) {
+  __shared__ float tile[32][33];
+  int b = blockIdx.x;
+  if (b < kPrepW1) {
+    convert_bf16_part(prm + o.f1w, o.k1, kHid, o.k1, w1b, k1p, w1b_lo, b, kPrepW1);
+    return;
+  }
+  b -= kPrepW1;
+  if (b < kPrepW2) {
+    convert_bf16_part(prm + o.f2w, kHid, kHid, kHid, w2b, kHid, w2b_lo, b, kPrepW2);
+    return;
+  }
+  b -= kPrepW2;
+  if (transposed) {
+    if (b < kPrepT1) {
+      transpose_bf16_tile(prm + o.f1w, o.k1, kHid, kFeat, w1t, kHid, tile, b % (kFeat / 32), b / (kFeat / 32));
+      return;
+    }
+    b -= kPrepT1;
+    if (b < kPrepT2) {
+      transpose_bf16_tile(prm + o.f2w, kHid, kHid, kHid, w2t, kHid, tile, b % (kHid / 32), b / (kHid / 32));
+      return;
+    }
+  }
+  for (int t = threadIdx.x; t < 64 * kConvFrags; t += 256) conv_frag_elem<false>(prm, o, cfrag, t);
+  if (w1b_lo)
+    for (int t = threadIdx.x; t < 64 * kConvFrags; t += 256) conv_frag_elem<true>(prm, o, cfrag + 64 * kConvLoFrag, t);
+  if (transposed)
+    for (int t = threadIdx.x; t < 64 * kConvPhaseFrags; t += 256) conv_bwd_frag_elem(prm, o, cfrag, t);
+}
+
 // BF16 copies of W1 (rows padded to k1p) and W2 and the encoder's weight fragments that the forward
 // reads; with `transposed` also what only the backward reads (the transposes for the input gradients,
 // the encoder backward's phase fragments).
 int convert_weights(aslam_policy* P, const float* prm, hipStream_t st, bool transposed) {
   const Offsets& o = P->off;
-  k_convert_bf16<<<1024, 256, 0, st>>>(prm + o.f1w, o.k1, kHid, o.k1, P->w1b, P->k1p, P->prec ? P->w1b_lo : nullptr);
-  PCHK(hipGetLastError());
   if (P->rec) {
+    k_convert_bf16<<<1024, 256, 0, st>>>(prm + o.f1w, o.k1, kHid, o.k1, P->w1b, P->k1p, P->prec ? P->w1b_lo : nullptr);
+    PCHK(hipGetLastError());
     k_convert_bf16<<<768, 256, 0, st>>>(prm + o.gih, kHid, kGates, kHid, P->wihb, kHid);
     PCHK(hipGetLastError());
     k_convert_bf16<<<768, 256, 0, st>>>(prm + o.ghh, kHid, kGates, kHid, P->whhb, kHid);
@@ -135,22 +177,10 @@ int convert_weights(aslam_policy* P, const float* prm, hipStream_t st, bool tran
     P->prepared = true;
     return ASL_OK;
   }
-  k_convert_bf16<<<256, 256, 0, st>>>(prm + o.f2w, kHid, kHid, kHid, P->w2b, kHid, P->prec ? P->w2b_lo : nullptr);
+  const int blocks = kPrepW1 + kPrepW2 + (transposed ? kPrepT1 + kPrepT2 : 0) + 1;
+  k_prep_mlp<<<blocks, 256, 0, st>>>(prm, o, P->k1p, P->w1b, P->prec ? P->w1b_lo : nullptr, P->w2b,
+                                     P->prec ? P->w2b_lo : nullptr, P->w1t, P->w2t, P->cfrag, transposed ? 1 : 0);
   PCHK(hipGetLastError());
-  k_conv_frags<<<1, 64 * kConvFrags, 0, st>>>(prm, o, P->cfrag);
-  PCHK(hipGetLastError());
-  if (P->prec) {
-    k_conv_frags<true><<<1, 64 * kConvFrags, 0, st>>>(prm, o, P->cfrag + 64 * kConvLoFrag);
-    PCHK(hipGetLastError());
-  }
-  if (transposed) {
-    k_conv_bwd_frags<<<1, 64 * kConvPhaseFrags, 0, st>>>(prm, o, P->cfrag);
-    PCHK(hipGetLastError());
-    k_transpose_bf16<<<dim3(kFeat / 32, kHid / 32), 256, 0, st>>>(prm + o.f1w, o.k1, kHid, kFeat, P->w1t, kHid);
-    PCHK(hipGetLastError());
-    k_transpose_bf16<<<dim3(kHid / 32, kHid / 32), 256, 0, st>>>(prm + o.f2w, kHid, kHid, kHid, P->w2t, kHid);
-    PCHK(hipGetLastError());
-  }
   P->prepared = true;
   return ASL_OK;
 }
@@ -293,7 +323,6 @@ int aslam_policy_create(const aslam_policy_config* cfg, aslam_policy** out) {
       {(void**)&p->dz2c, 2 * (size_t)Bm * kFeat}, {(void**)&p->z2, 4 * (size_t)Bm * kHid},
       {(void**)&p->part, 4 * (size_t)p->part_floats},
       {(void**)&p->hpart, 4 * (size_t)((Bm + kHeadRows - 1) / kHeadRows) * kHeadPart},
-      {(void**)&p->hsum, 4 * (size_t)kHeadPart},
       {(void**)&p->w1b, 2 * (size_t)kHid * ((p->off.k1 + 7) / 8 * 8)}, {(void**)&p->w1t, 2 * (size_t)kFeat * kHid},
       {(void**)&p->w2b, 2 * (size_t)kHid * kHid},                        {(void**)&p->w2t, 2 * (size_t)kHid * kHid},
       {(void**)&p->cfrag, sizeof(uint4) * 64 * kConvFragsAll},
@@ -344,7 +373,7 @@ int64_t aslam_policy_param_count(const aslam_policy_config* cfg) {
 
 int aslam_policy_destroy(aslam_policy* p) {
   if (!p) return pfail(ASL_EINVAL, "policy is NULL");
-  void* ptrs[] = {p->x, p->h1, p->dz2, p->dz1, p->dz2c, p->z2, p->part, p->hpart, p->hsum,
+  void* ptrs[] = {p->x, p->h1, p->dz2, p->dz1, p->dz2c, p->z2, p->part, p->hpart,
                   p->w1b, p->w1t, p->w2b, p->w2t, p->cfrag,
                   p->wihb, p->whhb, p->wiht, p->whht, p->hst, p->g_r, p->g_z, p->g_n, p->g_ghn, p->hp_used,
                   p->dh_head, p->dh_buf, p->hp_bf, p->dgi, p->dgh, p->rows, p->x_lo, p->h1_lo, p->w1b_lo,
@@ -490,11 +519,7 @@ int aslam_policy_backward_rows(aslam_policy* P, const float* params, const int16
   k_heads<true><<<nb, 256, 0, st>>>(params, o, P->z2, B, nullptr, nullptr, act, old_logp, adv, ret, rows, lc, P->dz2,
                                     P->hpart);
   PCHK(hipGetLastError());
-  PCHK(launch_reduce(P->hpart, nb, kHeadPart, P->hsum, 3, kHeadPart, st));
-  k_scatter_heads<<<1, 256, 0, st>>>(P->hsum, grads, o, loss, P->cfg.c_entropy);
-  PCHK(hipGetLastError());
-  k_loss_total<<<1, 1, 0, st>>>(params, o, loss, P->cfg.c_value, P->cfg.c_entropy);
-  PCHK(hipGetLastError());
+  PCHK(launch_reduce_heads(P->hpart, nb, params, o, grads, loss, P->cfg.c_value, P->cfg.c_entropy, st));
   float* part = P->part;
   // FC2 weight: dW2[out][in] = sum_b dz2[b][out] h1[b][in]
   {
@@ -543,10 +568,9 @@ int backward_fc1_encoder(aslam_policy* P, const float* params, const int16_t* cr
     else
       k_conv_bwd<false><<<grid, kBwdThreads, 0, st>>>(params, o, P->cfrag, crop, rows, P->dz2c, B, part);
     PCHK(hipGetLastError());
-    PCHK(launch_reduce(part, grid, kConvPartW2, grads + o.c2w, 1, kConvPart, st));
-    PCHK(launch_reduce(part + kConvPartW2, grid, kConvPartW1, grads + o.c1w, 2, kConvPart, st));
-    PCHK(launch_reduce(part + kConvPartW2 + kConvPartW1, grid, kC1, grads + o.c1b, 0, kConvPart, st));
-    PCHK(launch_reduce(part + kConvPartW2 + kConvPartW1 + kC1, grid, kC2, grads + o.c2b, 0, kConvPart, st));
+    // the four gradient blocks of the encoder's partials in one reduction
+    const ReduceSegs sg{{kConvPartW2, kConvPartW1, kC1, kC2}, {1, 2, 0, 0}, {o.c2w, o.c1w, o.c1b, o.c2b}};
+    PCHK(launch_reduce_segs(part, grid, grads, sg, kConvPart, st));
   }
   return ASL_OK;
 }
@@ -718,11 +742,7 @@ int aslam_policy_backward_seq(aslam_policy* P, const float* params, const int16_
   k_heads<true, true><<<nh, 256, 0, st>>>(params, o, P->hst, B, nullptr, nullptr, act, old_logp, adv, ret, P->rows,
                                           lc, nullptr, P->hpart, P->dh_head);
   PCHK(hipGetLastError());
-  PCHK(launch_reduce(P->hpart, nh, kHeadPart, P->hsum, 3, kHeadPart, st));
-  k_scatter_heads<<<1, 256, 0, st>>>(P->hsum, grads, o, loss, P->cfg.c_entropy);
-  PCHK(hipGetLastError());
-  k_loss_total<<<1, 1, 0, st>>>(params, o, loss, P->cfg.c_value, P->cfg.c_entropy);
-  PCHK(hipGetLastError());
+  PCHK(launch_reduce_heads(P->hpart, nh, params, o, grads, loss, P->cfg.c_value, P->cfg.c_entropy, st));
   // backpropagation through time
   for (int t = T - 1; t >= 0; --t) {
     GruBwdArgs b{};

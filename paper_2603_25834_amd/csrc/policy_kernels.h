@@ -364,12 +364,13 @@ __device__ __forceinline__ int64_t reduce_dst(int map, int64_t i, bool& skip) {
   return i;
 }
 
-__global__ __launch_bounds__(kReduceThreads) void k_reduce(const float* part, int S, int64_t count, float* dst,
-                                                           int map, int64_t slice, int cx_log2) {
-  __shared__ float4 red[kReduceThreads];
+// The sum over the S slices of the four outputs i0 .. i0 + 3 of this thread's group, in a fixed order:
+// true (and the sums in tv) for the thread that holds the group's result.
+__device__ __forceinline__ bool reduce_group(const float* part, int S, int64_t count, int64_t slice, int cx_log2,
+                                             float4* red, float (&tv)[4], int64_t& i0) {
   const int CX = 1 << cx_log2, LY = kReduceThreads >> cx_log2;
   const int cx = threadIdx.x & (CX - 1), ly = threadIdx.x >> cx_log2;
-  const int64_t i0 = ((int64_t)blockIdx.x * CX + cx) * 4;
+  i0 = ((int64_t)blockIdx.x * CX + cx) * 4;
   float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
   if (i0 < count) {
     if (i0 + 3 < count && (slice & 3) == 0) {
@@ -400,23 +401,58 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce(const float* part, in
   }
   red[threadIdx.x] = acc;
   __syncthreads();
-  if (ly == 0 && i0 < count) {
-    float4 t = red[cx];
-    for (int y = 1; y < LY; ++y) {
-      const float4 v = red[y * CX + cx];
-      t.x += v.x; t.y += v.y; t.z += v.z; t.w += v.w;
-    }
-    const float tv[4] = {t.x, t.y, t.z, t.w};
+  if (ly != 0 || i0 >= count) return false;
+  float4 t = red[cx];
+  for (int y = 1; y < LY; ++y) {
+    const float4 v = red[y * CX + cx];
+    t.x += v.x; t.y += v.y; t.z += v.z; t.w += v.w;
+  }
+  tv[0] = t.x; tv[1] = t.y; tv[2] = t.z; tv[3] = t.w;
+  return true;
+}
+
+__global__ __launch_bounds__(kReduceThreads) void k_reduce(const float* part, int S, int64_t count, float* dst,
+                                                           int map, int64_t slice, int cx_log2) {
+  __shared__ float4 red[kReduceThreads];
+  float tv[4];
+  int64_t i0;
+  if (!reduce_group(part, S, count, slice, cx_log2, red, tv, i0)) return;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int64_t i = i0 + e;
-      if (i >= count) break;
-      bool skip;
-      const int64_t d = reduce_dst(map, i, skip);
-      if (skip) continue;
-      if (map == 3) dst[d] = tv[e];
-      else dst[d] += tv[e];
-    }
+  for (int e = 0; e < 4; ++e) {
+    const int64_t i = i0 + e;
+    if (i >= count) break;
+    bool skip;
+    const int64_t d = reduce_dst(map, i, skip);
+    if (skip) continue;
+    if (map == 3) dst[d] = tv[e];
+    else dst[d] += tv[e];
+  }
+}
+
+// Up to four consecutive output segments of one partial layout in one launch: segment k holds n[k]
+// outputs (multiples of four) added into grads + off[k] through map[k] (0, 1 or 2 of reduce_dst).
+struct ReduceSegs {
+  int32_t n[4];
+  int32_t map[4];
+  int64_t off[4];
+};
+
+__global__ __launch_bounds__(kReduceThreads) void k_reduce_segs(const float* part, int S, int64_t count,
+                                                                float* grads, ReduceSegs sg, int64_t slice,
+                                                                int cx_log2) {
+  __shared__ float4 red[kReduceThreads];
+  float tv[4];
+  int64_t i0;
+  if (!reduce_group(part, S, count, slice, cx_log2, red, tv, i0)) return;
+  int k = 0;
+  int64_t j0 = i0;
+  while (k < 3 && j0 >= sg.n[k]) j0 -= sg.n[k++];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    if (i0 + e >= count) break;
+    bool skip;
+    const int64_t d = reduce_dst(sg.map[k], j0 + e, skip);
+    if (!skip) grads[sg.off[k] + d] += tv[e];
   }
 }
 
@@ -513,35 +549,81 @@ __global__ __launch_bounds__(256) void k_reduce_bias_relu_bf16_q(const float* pa
 // (at least 2048 workgroups with every lane on its own group) give each lane a group and all the
 // slices, so a wave reads 1 KB contiguous per slice; otherwise 16 groups x 16 lanes, fewer groups
 // for tiny outputs.
+inline int64_t reduce_shape(int64_t count, int& cx_log2) {
+  const int64_t groups = (count + 3) / 4;
+  cx_log2 = groups >= 2048LL * kReduceThreads ? 8 : 4;
+  while (cx_log2 > 0 && (1LL << (cx_log2 - 1)) >= groups) --cx_log2;
+  return (groups + (1LL << cx_log2) - 1) >> cx_log2;
+}
+
 inline hipError_t launch_reduce(const float* part, int S, int64_t count, float* dst, int map, int64_t slice,
                                 hipStream_t st) {
-  const int64_t groups = (count + 3) / 4;
-  int cx_log2 = groups >= 2048LL * kReduceThreads ? 8 : 4;
-  while (cx_log2 > 0 && (1LL << (cx_log2 - 1)) >= groups) --cx_log2;
-  const int64_t blocks = (groups + (1LL << cx_log2) - 1) >> cx_log2;
+  int cx_log2;
+  const int64_t blocks = reduce_shape(count, cx_log2);
   k_reduce<<<(unsigned)blocks, kReduceThreads, 0, st>>>(part, S, count, dst, map, slice, cx_log2);
   return hipGetLastError();
 }
 
-// Head sums [kHeadPart] -> gradient vector and loss terms.
-__global__ void k_scatter_heads(const float* hs, float* grad, Offsets o, float* loss, float c_e) {
-  for (int i = threadIdx.x; i < kHeadPart; i += blockDim.x) {
-    const float s = hs[i];
-    if (i < 512) grad[o.muw + i] += s;
-    else if (i < 514) grad[o.mub + (i - 512)] += s;
-    else if (i < 770) grad[o.vw + (i - 514)] += s;
-    else if (i == 770) grad[o.vb] += s;
-    else if (i < 773) grad[o.lstd + (i - 771)] += s - c_e;  // entropy term: -c_e dH/dlog_std
-    else if (i < 1029) { if (o.f2b >= 0) grad[o.f2b + (i - 773)] += s; }
-    else if (i == 1029) loss[1] = s;
-    else if (i == 1030) loss[2] = s;
-  }
+inline hipError_t launch_reduce_segs(const float* part, int S, float* grads, const ReduceSegs& sg, int64_t slice,
+                                     hipStream_t st) {
+  const int64_t count = (int64_t)sg.n[0] + sg.n[1] + sg.n[2] + sg.n[3];
+  int cx_log2;
+  const int64_t blocks = reduce_shape(count, cx_log2);
+  k_reduce_segs<<<(unsigned)blocks, kReduceThreads, 0, st>>>(part, S, count, grads, sg, slice, cx_log2);
+  return hipGetLastError();
 }
 
-__global__ void k_loss_total(const float* prm, Offsets o, float* loss, float c_v, float c_e) {
+// Head sum i (of kHeadPart) -> its gradient entry or loss term.
+__device__ __forceinline__ void scatter_head(int i, float s, float* grad, const Offsets& o, float* loss, float c_e) {
+  if (i < 512) grad[o.muw + i] += s;
+  else if (i < 514) grad[o.mub + (i - 512)] += s;
+  else if (i < 770) grad[o.vw + (i - 514)] += s;
+  else if (i == 770) grad[o.vb] += s;
+  else if (i < 773) grad[o.lstd + (i - 771)] += s - c_e;  // entropy term: -c_e dH/dlog_std
+  else if (i < 1029) { if (o.f2b >= 0) grad[o.f2b + (i - 773)] += s; }
+  else if (i == 1029) loss[1] = s;
+  else if (i == 1030) loss[2] = s;
+}
+
+// Head sums [kHeadPart] -> gradient vector and loss terms.
+__global__ void k_scatter_heads(const float* hs, float* grad, Offsets o, float* loss, float c_e) {
+  for (int i = threadIdx.x; i < kHeadPart; i += blockDim.x) scatter_head(i, hs[i], grad, o, loss, c_e);
+}
+
+__device__ __forceinline__ void loss_total(const float* prm, const Offsets& o, float* loss, float c_v, float c_e) {
   const float h = (prm[o.lstd] + prm[o.lstd + 1]) + 2.0f * 1.4189385332046727f;  // 0.5*log(2*pi*e) per dim
   loss[3] = h;
   loss[0] = loss[1] + c_v * loss[2] - c_e * h;
+}
+
+__global__ void k_loss_total(const float* prm, Offsets o, float* loss, float c_v, float c_e) {
+  loss_total(prm, o, loss, c_v, c_e);
+}
+
+// The head partials' reduction, their scatter into the gradient and the loss total in one launch
+// (the sums as the reduction forms them; the thread holding sums 1028 .. 1031 writes both loss terms
+// and then the total).
+static_assert(kHeadPart > 1030 && 1028 % 4 == 0, "the loss terms share one group of four sums");
+
+__global__ __launch_bounds__(kReduceThreads) void k_reduce_heads(const float* part, int S, const float* prm,
+                                                                 Offsets o, float* grad, float* loss, float c_v,
+                                                                 float c_e, int cx_log2) {
+  __shared__ float4 red[kReduceThreads];
+  float tv[4];
+  int64_t i0;
+  if (!reduce_group(part, S, kHeadPart, kHeadPart, cx_log2, red, tv, i0)) return;
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+    if (i0 + e < kHeadPart) scatter_head((int)i0 + e, tv[e], grad, o, loss, c_e);
+  if (i0 == 1028) loss_total(prm, o, loss, c_v, c_e);
+}
+
+inline hipError_t launch_reduce_heads(const float* part, int S, const float* prm, const Offsets& o, float* grad,
+                                      float* loss, float c_v, float c_e, hipStream_t st) {
+  int cx_log2;
+  const int64_t blocks = reduce_shape(kHeadPart, cx_log2);
+  k_reduce_heads<<<(unsigned)blocks, kReduceThreads, 0, st>>>(part, S, prm, o, grad, loss, c_v, c_e, cx_log2);
+  return hipGetLastError();
 }
 
 // Bias gradients: column sums of a BF16 [rows][ch] tensor (ch divides 2048,
@@ -590,11 +672,11 @@ __global__ __launch_bounds__(256) void k_bias_rows(const uint16_t* src, int64_t 
 // BF16 copies of FP32 weight matrices for the GEMMs (rounded to nearest even).
 // k_convert_bf16: dst[r][c] = bf16(src[r][c]) for c < cols, 0 for cols <= c < ld_dst; with dst_lo
 // also the remainder dst_lo[r][c] = bf16(src[r][c] - bf16(src[r][c])) (the split operand's lo part).
-__global__ void k_convert_bf16(const float* src, int64_t ld_src, int rows, int cols, uint16_t* dst,
-                               int64_t ld_dst, uint16_t* dst_lo = nullptr) {
+// (one workgroup's share: workgroup blk of nblk, blockDim threads)
+__device__ __forceinline__ void convert_bf16_part(const float* src, int64_t ld_src, int rows, int cols, uint16_t* dst,
+                                                  int64_t ld_dst, uint16_t* dst_lo, int blk, int nblk) {
   const int64_t total = (int64_t)rows * ld_dst;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
-       i += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t i = (int64_t)blk * blockDim.x + threadIdx.x; i < total; i += (int64_t)nblk * blockDim.x) {
     const int64_t r = i / ld_dst, c = i - r * ld_dst;
     const float v = c < cols ? src[r * ld_src + c] : 0.0f;
     const uint16_t h = f2bf(v);
@@ -603,11 +685,16 @@ __global__ void k_convert_bf16(const float* src, int64_t ld_src, int rows, int c
   }
 }
 
+__global__ void k_convert_bf16(const float* src, int64_t ld_src, int rows, int cols, uint16_t* dst,
+                               int64_t ld_dst, uint16_t* dst_lo = nullptr) {
+  convert_bf16_part(src, ld_src, rows, cols, dst, ld_dst, dst_lo, blockIdx.x, gridDim.x);
+}
+
 // k_transpose_bf16: dst[c][r] = bf16(src[r][c]) through 32 x 32 LDS tiles (256 threads).
-__global__ __launch_bounds__(256) void k_transpose_bf16(const float* src, int64_t ld_src, int rows, int cols,
-                                                        uint16_t* dst, int64_t ld_dst) {
-  __shared__ float tile[32][33];
-  const int c0 = blockIdx.x * 32, r0 = blockIdx.y * 32;
+// (tile (bx, by) with 256 threads and a [32][33] LDS tile)
+__device__ __forceinline__ void transpose_bf16_tile(const float* src, int64_t ld_src, int rows, int cols,
+                                                    uint16_t* dst, int64_t ld_dst, float (*tile)[33], int bx, int by) {
+  const int c0 = bx * 32, r0 = by * 32;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
   for (int k = ty; k < 32; k += 8) {
     const int r = r0 + k, c = c0 + tx;
@@ -618,6 +705,12 @@ __global__ __launch_bounds__(256) void k_transpose_bf16(const float* src, int64_
     const int c = c0 + k, r = r0 + tx;
     if (c < cols && r < rows) dst[(int64_t)c * ld_dst + r] = f2bf(tile[tx][k]);
   }
+}
+
+__global__ __launch_bounds__(256) void k_transpose_bf16(const float* src, int64_t ld_src, int rows, int cols,
+                                                        uint16_t* dst, int64_t ld_dst) {
+  __shared__ float tile[32][33];
+  transpose_bf16_tile(src, ld_src, rows, cols, dst, ld_dst, tile, blockIdx.x, blockIdx.y);
 }
 
 // Forward tail of a tile of kTailRows rows, for the forward-only calls: the FC1 split-K sum (slices in
