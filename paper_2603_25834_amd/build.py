@@ -2,7 +2,8 @@
 
 Every HIP source is compiled for gfx950 with FP contraction off (the pose and
 covariance arithmetic is specified operation by operation), correctly rounded
-FP32 division, and packed-FP32 instructions disabled.
+FP32 division, and packed-FP32 instructions disabled; each to an object of its
+own (the sources in parallel), then linked into one shared library.
 """
 from __future__ import annotations
 
@@ -15,10 +16,10 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libaslam.so")
 
-SOURCES = ["capi.hip", "env_kernels.hip", "policy_capi.hip", "slam.hip"]
+SOURCES = ["capi.hip", "env_kernels.hip", "policy_capi.hip", "slam.hip", "fixedlag.hip"]
 
 HIPCC_FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     "-ffp-contract=off", "-fhip-fp32-correctly-rounded-divide-sqrt",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
@@ -37,11 +38,26 @@ def sources() -> list[str]:
 
 
 def build_library(verbose: bool = False) -> str:
-    tmp = LIB + ".tmp"
-    cmd = [hipcc()] + HIPCC_FLAGS + ["-I", os.path.join(ROOT, "include"), "-I", CSRC, "-o", tmp] + sources()
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.check_call(cmd)
+    """Each source compiled to an object (in parallel), then linked."""
+    import tempfile
+    from concurrent.futures import ThreadPoolExecutor
+    inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
+    with tempfile.TemporaryDirectory(prefix="aslam_build_") as work:
+        jobs = []
+        for src in sources():
+            obj = os.path.join(work, os.path.basename(src) + ".o")
+            jobs.append(([hipcc()] + HIPCC_FLAGS + inc + ["-c", src, "-o", obj], obj))
+        if verbose:
+            for cmd, _ in jobs:
+                print(" ".join(cmd), flush=True)
+        with ThreadPoolExecutor(max_workers=min(len(jobs), max(1, os.cpu_count() or 1))) as ex:
+            for f in [ex.submit(subprocess.check_call, cmd) for cmd, _ in jobs]:
+                f.result()
+        tmp = LIB + ".tmp"
+        link = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + [o for _, o in jobs]
+        if verbose:
+            print(" ".join(link), flush=True)
+        subprocess.check_call(link)
     os.replace(tmp, LIB)
     return LIB
 

@@ -682,254 +682,6 @@ __global__ __launch_bounds__(kIntThreads) void k_csm_integrate(
   }
 }
 
-// ------------------------------------------------------------------ fixed-lag Gauss-Newton
-//
-// FP64 throughout, with multiply-adds fused (the solve is checked against the oracle to 1e-9, not bit
-// for bit): one lane runs the elimination chain of a window, so its instruction count and dependency
-// depth are the kernel's time.
-#pragma clang fp contract(fast)
-
-struct M3 {
-  double a[3][3];
-};
-
-// Inverse of a symmetric 3 x 3 matrix from its upper triangle (the result is symmetric): six cofactors,
-// and the determinant's reciprocal by the hardware estimate refined with two Newton steps (about one
-// ulp, against the dozen dependent operations of an IEEE division).
-__device__ __forceinline__ M3 sym_inv3(const M3& m) {
-  const double (*a)[3] = m.a;
-  const double c00 = a[1][1] * a[2][2] - a[1][2] * a[1][2];
-  const double c01 = a[0][2] * a[1][2] - a[0][1] * a[2][2];
-  const double c02 = a[0][1] * a[1][2] - a[0][2] * a[1][1];
-  const double c11 = a[0][0] * a[2][2] - a[0][2] * a[0][2];
-  const double c12 = a[0][2] * a[0][1] - a[0][0] * a[1][2];
-  const double c22 = a[0][0] * a[1][1] - a[0][1] * a[0][1];
-  const double det = a[0][0] * c00 + a[0][1] * c01 + a[0][2] * c02;
-  double id = __builtin_amdgcn_rcp(det);
-  id = id + id * (1.0 - det * id);
-  id = id + id * (1.0 - det * id);
-  M3 r;
-  r.a[0][0] = c00 * id;
-  r.a[0][1] = r.a[1][0] = c01 * id;
-  r.a[0][2] = r.a[2][0] = c02 * id;
-  r.a[1][1] = c11 * id;
-  r.a[1][2] = r.a[2][1] = c12 * id;
-  r.a[2][2] = c22 * id;
-  return r;
-}
-
-// Odometry factor between poses xi and xj: residual, and its Jacobians Ji (wrt xi) and Jj (wrt xj).
-__device__ __forceinline__ void odo_factor(const double* xi, const double* xj, const double* u, double r[3],
-                                           double Ji[3][3], double Jj[3][3]) {
-  double s, c;
-  sincos(xi[2], &s, &c);
-  const double dx = xj[0] - xi[0], dy = xj[1] - xi[1];
-  r[0] = (c * dx + s * dy) - u[0];
-  r[1] = (-s * dx + c * dy) - u[1];
-  r[2] = wrap_pi(xj[2] - xi[2] - u[2]);
-  Ji[0][0] = -c; Ji[0][1] = -s; Ji[0][2] = -s * dx + c * dy;
-  Ji[1][0] = s;  Ji[1][1] = -c; Ji[1][2] = -c * dx - s * dy;
-  Ji[2][0] = 0;  Ji[2][1] = 0;  Ji[2][2] = -1.0;
-  Jj[0][0] = c;  Jj[0][1] = s;  Jj[0][2] = 0;
-  Jj[1][0] = -s; Jj[1][1] = c;  Jj[1][2] = 0;
-  Jj[2][0] = 0;  Jj[2][1] = 0;  Jj[2][2] = 1.0;
-}
-
-// acc += P^T diag(w) Q (3 x 3)
-__device__ __forceinline__ void add_jtwj(double acc[3][3], const double P[3][3], const double* w, const double Q[3][3]) {
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int b = 0; b < 3; ++b) {
-      double t = 0.0;
-#pragma unroll
-      for (int k = 0; k < 3; ++k) t += P[k][a] * w[k] * Q[k][b];
-      acc[a][b] += t;
-    }
-}
-
-__device__ __forceinline__ void add_jtwr(double* acc, const double P[3][3], const double* w, const double* rr) {
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    double t = 0.0;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) t += P[k][a] * w[k] * rr[k];
-    acc[a] += t;
-  }
-}
-
-// One wavefront per window.  Each Gauss-Newton step linearises every pose in parallel, lane i < L
-// forming the diagonal block A_i, the coupling B_i = H[i][i+1] and the gradient g_i from the factors
-// that touch pose i (the prior on pose 0, its scan factor, the odometry factors to i-1 and to i+1,
-// each with analytic Jacobians).  Lane 0 then eliminates the block-tridiagonal system pose by pose,
-// D_i = A_i - B_{i-1}^T D_{i-1}^{-1} B_{i-1}, y_i = -g_i - B_{i-1}^T D_{i-1}^{-1} y_{i-1}, keeping
-// D_i^{-1}, C_i = D_i^{-1} B_i and y_i, and back-substitutes delta_{L-1} = D_{L-1}^{-1} y_{L-1},
-// delta_i = D_i^{-1} y_i - C_i delta_{i+1}.  After K steps one more linearisation and elimination at
-// the result gives Sigma = D_{L-1}^{-1}, the last diagonal block of the inverse Hessian.  Everything
-// lives in LDS: 45 L doubles per window.
-constexpr int kLagThreads = 64;
-constexpr int kLagMaxL = 64;
-
-__device__ __forceinline__ void linearise_pose(const double* x, int L, int i, const double* prior, const double* odo,
-                                               const double* scan, double* A_out, double* B_out, double* g_out) {
-  double A[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, B[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-  double g[3] = {0, 0, 0};
-  const double* xi = x + 3 * i;
-  if (i == 0) {
-    const double r[3] = {xi[0] - prior[0], xi[1] - prior[1], wrap_pi(xi[2] - prior[2])};
-#pragma unroll
-    for (int a = 0; a < 3; ++a) { A[a][a] += prior[3 + a]; g[a] += prior[3 + a] * r[a]; }
-  }
-  const double* sc = scan + 6 * i;
-  if (sc[3] != 0.0 || sc[4] != 0.0 || sc[5] != 0.0) {
-    const double r[3] = {xi[0] - sc[0], xi[1] - sc[1], wrap_pi(xi[2] - sc[2])};
-#pragma unroll
-    for (int a = 0; a < 3; ++a) { A[a][a] += sc[3 + a]; g[a] += sc[3 + a] * r[a]; }
-  }
-  if (i > 0) {   // odometry factor (i-1, i): pose i's share
-    const double* o = odo + 6 * (i - 1);
-    double r[3], Ji[3][3], Jj[3][3];
-    odo_factor(x + 3 * (i - 1), xi, o, r, Ji, Jj);
-    add_jtwj(A, Jj, o + 3, Jj);
-    add_jtwr(g, Jj, o + 3, r);
-  }
-  if (i + 1 < L) {   // odometry factor (i, i+1): pose i's share and the coupling
-    const double* o = odo + 6 * i;
-    double r[3], Ji[3][3], Jj[3][3];
-    odo_factor(xi, x + 3 * (i + 1), o, r, Ji, Jj);
-    add_jtwj(A, Ji, o + 3, Ji);
-    add_jtwj(B, Ji, o + 3, Jj);
-    add_jtwr(g, Ji, o + 3, r);
-  }
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    g_out[a] = g[a];
-#pragma unroll
-    for (int b = 0; b < 3; ++b) { A_out[3 * a + b] = A[a][b]; B_out[3 * a + b] = B[a][b]; }
-  }
-}
-
-// Lane 0: the elimination sweep over the linearised window; returns D_{L-1}^{-1} in *last.  The previous
-// pose's D^{-1}, C, y and B stay in registers and the next pose's blocks are read one pose ahead, so
-// the recursion's chain holds no LDS round trip.
-__device__ __forceinline__ void eliminate_sweep(int L, const double* sA, const double* sB, const double* sg,
-                                                double* sDi, double* sC, double* sy, M3& last) {
-  double nA[9], nB[9], ng[3];
-#pragma unroll
-  for (int e = 0; e < 9; ++e) { nA[e] = sA[e]; nB[e] = sB[e]; }
-#pragma unroll
-  for (int a = 0; a < 3; ++a) ng[a] = sg[a];
-  double pDi[9], pC[9], py[3], pB[9];
-  for (int i = 0; i < L; ++i) {
-    M3 D;
-    double y[3], B[9];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      y[a] = -ng[a];
-#pragma unroll
-      for (int b = 0; b < 3; ++b) D.a[a][b] = nA[3 * a + b];
-    }
-#pragma unroll
-    for (int e = 0; e < 9; ++e) B[e] = nB[e];
-    if (i + 1 < L) {
-#pragma unroll
-      for (int e = 0; e < 9; ++e) { nA[e] = sA[9 * (i + 1) + e]; nB[e] = sB[9 * (i + 1) + e]; }
-#pragma unroll
-      for (int a = 0; a < 3; ++a) ng[a] = sg[3 * (i + 1) + a];
-    }
-    if (i > 0) {
-      double t[3];
-#pragma unroll
-      for (int a = 0; a < 3; ++a) t[a] = pDi[3 * a] * py[0] + pDi[3 * a + 1] * py[1] + pDi[3 * a + 2] * py[2];
-      // B^T D^{-1} B is symmetric: its upper triangle, mirrored
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-#pragma unroll
-        for (int b = a; b < 3; ++b) D.a[a][b] -= pB[a] * pC[b] + pB[3 + a] * pC[3 + b] + pB[6 + a] * pC[6 + b];
-        y[a] -= pB[a] * t[0] + pB[3 + a] * t[1] + pB[6 + a] * t[2];
-      }
-    }
-    const M3 Di = sym_inv3(D);   // D is symmetric (its lower triangle is not read)
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      py[a] = y[a];
-      sy[3 * i + a] = y[a];
-#pragma unroll
-      for (int b = 0; b < 3; ++b) {
-        pDi[3 * a + b] = Di.a[a][b];
-        pC[3 * a + b] = Di.a[a][0] * B[b] + Di.a[a][1] * B[3 + b] + Di.a[a][2] * B[6 + b];
-        sDi[9 * i + 3 * a + b] = pDi[3 * a + b];
-        sC[9 * i + 3 * a + b] = pC[3 * a + b];
-      }
-    }
-#pragma unroll
-    for (int e = 0; e < 9; ++e) pB[e] = B[e];
-    if (i == L - 1) last = Di;
-  }
-}
-
-// counts (may be NULL): the poses of window r (<= Ls); the arrays are strided for Ls poses.
-__global__ __launch_bounds__(kLagThreads) void k_fixedlag(int Ls, const int32_t* __restrict__ counts,
-                                                          const double* __restrict__ x0,
-                                                          const double* __restrict__ prior,
-                                                          const double* __restrict__ odo,
-                                                          const double* __restrict__ scan, int iters,
-                                                          double* __restrict__ xout, double* __restrict__ cov) {
-  extern __shared__ __align__(16) double s_lag[];
-  double* sx = s_lag;
-  double* sA = sx + 3 * Ls;
-  double* sB = sA + 9 * Ls;
-  double* sg = sB + 9 * Ls;
-  double* sDi = sg + 3 * Ls;
-  double* sC = sDi + 9 * Ls;
-  double* sy = sC + 9 * Ls;
-  const int r = blockIdx.x;
-  const int lane = threadIdx.x;
-  const int L = counts ? min(max(counts[r], 1), Ls) : Ls;   // uniform over the wavefront
-  for (int e = lane; e < 3 * L; e += kLagThreads) sx[e] = x0[(int64_t)r * Ls * 3 + e];
-  const double* pr = prior + 6 * (int64_t)r;
-  const double* od = odo + (int64_t)r * (Ls > 1 ? Ls - 1 : 0) * 6;
-  const double* sc = scan + (int64_t)r * Ls * 6;
-  M3 last;
-  for (int it = 0; it <= iters; ++it) {
-    __syncthreads();
-    for (int i = lane; i < L; i += kLagThreads) linearise_pose(sx, L, i, pr, od, sc, sA + 9 * i, sB + 9 * i, sg + 3 * i);
-    __syncthreads();
-    if (lane == 0) {
-      eliminate_sweep(L, sA, sB, sg, sDi, sC, sy, last);
-      if (it < iters) {
-        // the terms D_i^{-1} y_i do not depend on the recursion: each pose's is formed first
-        double dn[3] = {0, 0, 0};
-        for (int i = L - 1; i >= 0; --i) {
-          const double* Di = sDi + 9 * i;
-          const double* C = sC + 9 * i;
-          const double* y = sy + 3 * i;
-          double d[3], c[9];
-#pragma unroll
-          for (int e = 0; e < 9; ++e) c[e] = C[e];
-#pragma unroll
-          for (int a = 0; a < 3; ++a) d[a] = Di[3 * a] * y[0] + Di[3 * a + 1] * y[1] + Di[3 * a + 2] * y[2];
-          if (i < L - 1) {
-#pragma unroll
-            for (int a = 0; a < 3; ++a) d[a] -= c[3 * a] * dn[0] + c[3 * a + 1] * dn[1] + c[3 * a + 2] * dn[2];
-          }
-#pragma unroll
-          for (int a = 0; a < 3; ++a) { sx[3 * i + a] += d[a]; dn[a] = d[a]; }
-        }
-      } else {
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-          for (int b = 0; b < 3; ++b) cov[9 * (int64_t)r + 3 * a + b] = last.a[a][b];
-      }
-    }
-  }
-  __syncthreads();
-  for (int e = lane; e < 3 * L; e += kLagThreads) xout[(int64_t)r * Ls * 3 + e] = sx[e];
-}
-
-#pragma clang fp contract(off)
-
 // ------------------------------------------------------------------ heading table
 
 // Direction of heading step k, cos and sin of 2 pi k / 46080 rounded to Q14, packed (cos low, sin high).
@@ -1035,15 +787,6 @@ hipError_t launch_csm_integrate(const int32_t* tab, int16_t* belief_dev, const i
   return hipGetLastError();
 }
 
-hipError_t launch_fixedlag(int32_t n, int32_t L, const int32_t* counts, const double* x0, const double* prior,
-                           const double* odo, const double* scan, int32_t iters, double* x, double* cov,
-                           hipStream_t stream) {
-  if (n <= 0) return hipSuccess;
-  const int bytes = (int)(sizeof(double) * 45 * L);
-  k_fixedlag<<<n, kLagThreads, bytes, stream>>>(L, counts, x0, prior, odo, scan, iters, x, cov);
-  return hipGetLastError();
-}
-
 }  // namespace slam
 }  // namespace aslam
 
@@ -1146,7 +889,7 @@ int aslam_csm_integrate(const aslam_slam* slam, int16_t* belief_dev, const int64
 int aslam_fixedlag_solve(int32_t n, int32_t L, const double* x0_dev, const double* prior_dev, const double* odo_dev,
                          const double* scan_dev, int32_t iters, double* x_dev, double* cov_dev,
                          aslam_stream_t stream) {
-  if (n < 0 || L < 1 || L > kLagMaxL || iters < 0 || iters > 100)
+  if (n < 0 || L < 1 || L > aslam::slam::kMaxWindow || iters < 0 || iters > 100)
     return sfail(ASL_EINVAL, "need n >= 0, 1 <= L <= 64, 0 <= iters <= 100");
   if (n == 0) return ASL_OK;
   if (!x0_dev || !prior_dev || (L > 1 && !odo_dev) || !scan_dev || !x_dev || !cov_dev)
