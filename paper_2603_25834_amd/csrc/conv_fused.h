@@ -180,47 +180,44 @@ __device__ __forceinline__ uint2 pack_relu4(const f32x4& acc, const float b[4]) 
   return make_uint2((uint32_t)h[0] | ((uint32_t)h[1] << 16), (uint32_t)h[2] | ((uint32_t)h[3] << 16));
 }
 
-// conv1 + ReLU of the staged crop into s_a1 (pixel (y, x) at a1_slot(y, x) * 16): 64 tiles of 16
-// pixels over the NW waves, each taking four at a time so that their operand reads are in flight
-// together.  PREC: the crop's and the weights' lo parts enter the product too, and a1's lo part goes
-// to s_a1l.
+// conv1 + ReLU of the staged crop into s_a1 (pixel (y, x) at a1_slot(y, x) * 16): 64 tiles of 16 pixels
+// over the NW waves, four at a time so that their operand reads are in flight together; PREC: the
+// crop's and the weights' lo parts enter the product too, and a1's lo part goes to s_a1l.  The wave's
+// tiles' LDS offsets are formed once for all samples: tile j of the wave is wave + NW j, win[j] the
+// element offset of its window operand in the crop (-1: the lanes with lg >= 2, which supply zeros)
+// and slot[j] that of its output in a1.
 template <bool PREC, int NW>
-__device__ __forceinline__ void conv1_lds(const uint16_t* s_crop, const uint16_t* s_cropl, uint16_t* s_a1,
-                                          uint16_t* s_a1l, const bf16x8& w1f, const bf16x8& w1fl, const float b1[4],
-                                          int wave, int lr, int lg) {
-  for (int t0 = wave; t0 < kA1 * kA1 / 16; t0 += 4 * NW) {
+__device__ __forceinline__ void conv1_lds_at(const uint16_t* s_crop, const uint16_t* s_cropl, uint16_t* s_a1,
+                                             uint16_t* s_a1l, const bf16x8& w1f, const bf16x8& w1fl, const float b1[4],
+                                             const int (&win)[kA1 * kA1 / 16 / NW],
+                                             const int (&slot)[kA1 * kA1 / 16 / NW]) {
+  constexpr int kT = kA1 * kA1 / 16 / NW;
+  auto window = [&](const uint16_t* c, int off) -> uint4 {
+    if (off < 0) return make_uint4(0u, 0u, 0u, 0u);
+    const uint2 a = *reinterpret_cast<const uint2*>(c + off);
+    const uint2 d = *reinterpret_cast<const uint2*>(c + off + 4);
+    return make_uint4(a.x, a.y, d.x, d.y);
+  };
+#pragma unroll
+  for (int j0 = 0; j0 < kT; j0 += 4) {
     uint4 u[4], ul[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int px = (t0 + NW * i) * 16 + lr;
-      u[i] = conv1_window(s_crop, px, lg);
-      if (PREC) ul[i] = conv1_window(s_cropl, px, lg);
+      u[i] = window(s_crop, win[j0 + i]);
+      if (PREC) ul[i] = window(s_cropl, win[j0 + i]);
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int px = (t0 + NW * i) * 16 + lr, y = px >> 5, x = px & 31;
       f32x4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1f, __builtin_bit_cast(bf16x8, u[i]),
                                                          f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
       if (PREC) {
         acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1f, __builtin_bit_cast(bf16x8, ul[i]), acc, 0, 0, 0);
         acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1fl, __builtin_bit_cast(bf16x8, u[i]), acc, 0, 0, 0);
       }
-      const int slot = a1_slot(y, x) * kC1 + 4 * lg;
-      *reinterpret_cast<uint2*>(s_a1 + slot) = pack_relu4<false>(acc, b1);
-      if (PREC) *reinterpret_cast<uint2*>(s_a1l + slot) = pack_relu4<true>(acc, b1);
+      *reinterpret_cast<uint2*>(s_a1 + slot[j0 + i]) = pack_relu4<false>(acc, b1);
+      if (PREC) *reinterpret_cast<uint2*>(s_a1l + slot[j0 + i]) = pack_relu4<true>(acc, b1);
     }
   }
-}
-
-// conv2 A fragment: eight channels of the a1 pixel under tap (32 s + 8 lg) / 16 of position (oy, ox).
-__device__ __forceinline__ bf16x8 conv2_col_frag(const uint16_t* s_a1, int oy, int ox, int s, int lg) {
-  const int k0 = 32 * s + 8 * lg, tap = k0 >> 4, ci0 = k0 & 15;
-  uint4 u = make_uint4(0u, 0u, 0u, 0u);
-  if (tap < 9) {
-    const int yy = 2 * oy + tap / 3 - 1, xx = 2 * ox + tap % 3 - 1;
-    u = *reinterpret_cast<const uint4*>(s_a1 + a1_slot(yy, xx) * kC1 + ci0);
-  }
-  return __builtin_bit_cast(bf16x8, u);
 }
 
 // Encoder forward: a2[b * lda2 + co*256 + oy*16 + ox] = bf16(relu(conv2(relu(conv1(crop_b))))), and
@@ -287,6 +284,25 @@ __global__ __launch_bounds__(NT) void k_conv_fwd(const float* __restrict__ prm, 
       tv[i] = j < tail ? tail_value(sb, j) : 0.0f;
     }
   };
+  // the LDS offsets of the wave's conv1 tiles and conv2 operands are the same for every sample
+  constexpr int kT1 = kA1 * kA1 / 16 / NW, kR2 = kA2 / NW;
+  int c1_win[kT1], c1_slot[kT1], c2_off[kR2][5];
+#pragma unroll
+  for (int j = 0; j < kT1; ++j) {
+    const int px = (wave + NW * j) * 16 + lr, y = px >> 5, x = px & 31;
+    c1_win[j] = lg < 2 ? ((y + lg) * kBlk + x) * 4 : -1;
+    c1_slot[j] = a1_slot(y, x) * kC1 + 4 * lg;
+  }
+#pragma unroll
+  for (int i = 0; i < kR2; ++i)
+#pragma unroll
+    for (int s = 0; s < 5; ++s) {
+      const int oy = wave + NW * i, k0 = 32 * s + 8 * lg, tap = k0 >> 4, ci0 = k0 & 15;
+      c2_off[i][s] = tap < 9 ? a1_slot(2 * oy + tap / 3 - 1, 2 * lr + tap % 3 - 1) * kC1 + ci0 : -1;
+    }
+  auto col_frag = [&](const uint16_t* a, int off) -> bf16x8 {
+    return __builtin_bit_cast(bf16x8, off < 0 ? make_uint4(0u, 0u, 0u, 0u) : *reinterpret_cast<const uint4*>(a + off));
+  };
   if (blockIdx.x < B) load_sample(blockIdx.x);
   __syncthreads();
   for (int b = blockIdx.x; b < B; b += gridDim.x) {
@@ -310,19 +326,19 @@ __global__ __launch_bounds__(NT) void k_conv_fwd(const float* __restrict__ prm, 
     __syncthreads();
     // the next sample's crop and tail are loaded while this one is processed
     if (b + (int)gridDim.x < B) load_sample(b + gridDim.x);
-    conv1_lds<PREC, NW>(s_crop, s_cropl, s_a1, s_a1l, w1f, w1fl, b1, wave, lr, lg);
+    conv1_lds_at<PREC, NW>(s_crop, s_cropl, s_a1, s_a1l, w1f, w1fl, b1, c1_win, c1_slot);
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < kA2 / NW; ++i) {
+    for (int i = 0; i < kR2; ++i) {
       const int oy = wave + NW * i;
       f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int s = 0; s < 5; ++s) {
-        const bf16x8 af = conv2_col_frag(s_a1, oy, lr, s, lg);
+        const bf16x8 af = col_frag(s_a1, c2_off[i][s]);
         acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, w2f[0][s], acc0, 0, 0, 0);
         acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, w2f[1][s], acc1, 0, 0, 0);
         if (PREC) {
-          const bf16x8 afl = conv2_col_frag(s_a1l, oy, lr, s, lg);
+          const bf16x8 afl = col_frag(s_a1l, c2_off[i][s]);
           acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, w2fl[0][s], acc0, 0, 0, 0);
           acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, w2fl[1][s], acc1, 0, 0, 0);
           acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afl, w2f[0][s], acc0, 0, 0, 0);
