@@ -341,11 +341,11 @@ __global__ __launch_bounds__(256) void k_heads(const float* prm, Offsets o, cons
     part[(int64_t)blockIdx.x * kHeadPart + i] = acc[0][i] + acc[1][i] + acc[2][i] + acc[3][i];
 }
 
-// Sum of split-K partials part[z * slice + i], z < S, in a fixed order, into
-// dst[map(i)].  A workgroup covers 4*CX consecutive outputs (CX groups of four)
+// Sum of split-K partials part[z * slice + i], z < S, in a fixed order, added
+// into dst[map(i)].  A workgroup covers 4*CX consecutive outputs (CX groups of four)
 // and splits S over 256/CX lanes; each lane sums its share with four loads in
 // flight, then one lane per group adds the lanes' sums in lane order.
-// map: 0 identity (added), 3 identity (assigned), 1 conv2 weight
+// map: 0 identity, 1 conv2 weight
 // (k' = tap*16 + ci -> ci*9 + tap within each co row of 144), 2 conv1 weight
 // (partial [16][16] tap-padded -> [16][9]).
 constexpr int kReduceThreads = 256;
@@ -424,8 +424,7 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce(const float* part, in
     bool skip;
     const int64_t d = reduce_dst(map, i, skip);
     if (skip) continue;
-    if (map == 3) dst[d] = tv[e];
-    else dst[d] += tv[e];
+    dst[d] += tv[e];
   }
 }
 
@@ -585,19 +584,11 @@ __device__ __forceinline__ void scatter_head(int i, float s, float* grad, const 
   else if (i == 1030) loss[2] = s;
 }
 
-// Head sums [kHeadPart] -> gradient vector and loss terms.
-__global__ void k_scatter_heads(const float* hs, float* grad, Offsets o, float* loss, float c_e) {
-  for (int i = threadIdx.x; i < kHeadPart; i += blockDim.x) scatter_head(i, hs[i], grad, o, loss, c_e);
-}
 
 __device__ __forceinline__ void loss_total(const float* prm, const Offsets& o, float* loss, float c_v, float c_e) {
   const float h = (prm[o.lstd] + prm[o.lstd + 1]) + 2.0f * 1.4189385332046727f;  // 0.5*log(2*pi*e) per dim
   loss[3] = h;
   loss[0] = loss[1] + c_v * loss[2] - c_e * h;
-}
-
-__global__ void k_loss_total(const float* prm, Offsets o, float* loss, float c_v, float c_e) {
-  loss_total(prm, o, loss, c_v, c_e);
 }
 
 // The head partials' reduction, their scatter into the gradient and the loss total in one launch
