@@ -211,7 +211,7 @@ __device__ __forceinline__ MotionDraws motion_draws(const EnvParams& P, const St
 
 // Motion, collision, EKF predict and loop closure of robot r (one thread, with the robot's draws).  The
 // proximity part of the collision test (which leaves the move standing) is left to the caller's lanes:
-// the fused step runs it on the whole workgroup, k_motion on the robot's eight lanes.
+// the fused step runs it on the whole workgroup, k_motion on the robot's sixteen lanes.
 __device__ MotionOut robot_motion(const EnvParams& P, const StepArgs& A, int32_t r, const MotionDraws& g) {
   const RobotMeta m = P.meta[r];
   const int32_t s = m.side;
@@ -1070,9 +1070,9 @@ __device__ void update_and_reward(const EnvParams& P, const StepArgs& A, const R
 
 // ---------------------------------------------------------------- kernels
 
-// Eight lanes per robot: five draw its normals, the first one moves it, all eight test the paper's
+// Sixteen lanes per robot: five draw its normals, the first one moves it, all sixteen test the paper's
 // proximity collision around the new position (the move stands).
-constexpr int kMotionLanes = 8;
+constexpr int kMotionLanes = 16;
 
 __global__ void k_motion(EnvParams P, StepArgs A) {
   const int32_t r = (int32_t)((blockIdx.x * blockDim.x + threadIdx.x) / kMotionLanes);
@@ -1090,7 +1090,7 @@ __global__ void k_motion(EnvParams P, StepArgs A) {
     near = near_obstacle_part(P.world + m.world_off, m.side, tox, toy, P.crash_q, sub, kMotionLanes);
   }
   const uint64_t b = __builtin_amdgcn_ballot_w64(near);
-  if (valid && sub == 0 && ((b >> lane0) & 0xffull) != 0) P.flags[2 * (int64_t)r] = 1;
+  if (valid && sub == 0 && ((b >> lane0) & ((1ull << kMotionLanes) - 1ull)) != 0) P.flags[2 * (int64_t)r] = 1;
 }
 
 template <int NT>
