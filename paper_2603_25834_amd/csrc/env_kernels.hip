@@ -1404,9 +1404,9 @@ __global__ void k_observe(EnvParams P, const float* ranges, int16_t* crop, int32
 // The step with the fixed-lag SLAM backbone of Sec. III-D in place of the EKF: motion, prediction and
 // visits (k_motion), the LiDAR march (k_march), the scan-matching inputs (k_fl_prep), the correlative
 // search, the alignment and the window's new pose and factors (k_fl_window), Gauss-Newton over the
-// window, the estimates and covariance back into the state (k_fl_post), the weighted integration of the
-// aligned scan, and the reward of Eq. (7) (k_fl_reward).  The estimate is the aligned pose (integer
-// work), the window only yields the covariance; see the C-ABI header for the rules.
+// window, the weighted integration of the aligned scan, then the estimates and covariance back into the
+// state and the reward of Eq. (7) (k_fl_post_reward).  The estimate is the aligned pose (integer work),
+// the window only yields the covariance; see the C-ABI header for the rules.
 
 // Predicted pose (Q16 x, y, heading index) and the scan: reported ranges of the rays that hit.
 __global__ void k_fl_prep(EnvParams P, FixedLag F) {
@@ -1508,33 +1508,27 @@ __global__ void k_fl_window(EnvParams P, FixedLag F) {
   F.wq[r] = (int32_t)rint(256.0 * (F.floor + (1.0 - F.floor) * w));
 }
 
-// One wave per robot: the window's solution back into the state (poses by all lanes), the FP32
-// covariance entries of the newest pose and its covariance diagonal (the prior the pose will carry as
-// the oldest).
-__global__ void k_fl_post(EnvParams P, FixedLag F) {
+// One wave per robot, after the weighted integration: the window's solution back into the state (poses
+// by all lanes); then lane 0 writes the FP32 covariance entries of the newest pose and its covariance
+// diagonal (the prior the pose will carry as the oldest), and forms Eq. (7) with U_t of that covariance,
+// done, terms, work counters and the draw counter.
+__global__ void k_fl_post_reward(EnvParams P, StepArgs A, FixedLag F) {
   const int32_t r = (int32_t)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kFlLanes);
   const int lane = (int)(threadIdx.x & (kFlLanes - 1));
   if (r >= P.n) return;
-  const int L = F.L, c = F.count[r];
+  const int L = F.L, cnt = F.count[r];
   const double* xo = F.xout + (int64_t)r * L * 3;
   double* x = F.x + (int64_t)r * L * 3;
-  for (int e = lane; e < 3 * c; e += kFlLanes) x[e] = xo[e];
+  for (int e = lane; e < 3 * cnt; e += kFlLanes) x[e] = xo[e];
   if (lane != 0) return;
   const double* S = F.covw + 9 * (int64_t)r;
   float* cv = P.cov + 6 * (int64_t)r;
   cv[0] = (float)S[0]; cv[1] = (float)S[1]; cv[2] = (float)S[2];
   cv[3] = (float)S[4]; cv[4] = (float)S[5]; cv[5] = (float)S[8];
-  double* sg = F.sig + ((int64_t)r * L + (c - 1)) * 3;
+  double* sg = F.sig + ((int64_t)r * L + (cnt - 1)) * 3;
   sg[0] = S[0]; sg[1] = S[4]; sg[2] = S[8];
-}
-
-// Eq. (7) with U_t of the window's covariance; done, terms, work counters and the draw counter.
-__global__ void k_fl_reward(EnvParams P, StepArgs A, FixedLag F) {
-  const int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= P.n) return;
   if (F.coded[r] > 0) P.counters[3 * (int64_t)r] += F.coded[r];
-  const float* c = P.cov + 6 * (int64_t)r;
-  const double det = cov_det(c);
+  const double det = cov_det(cv);
   const double ld = det > 0.0 ? log(det) : log(1.17549435e-38);
   const double u = det > 0.0 ? cbrt(det) : 0.0;
   const int32_t col = P.flags[2 * (int64_t)r];
@@ -1569,7 +1563,6 @@ __global__ void k_fl_reset(int32_t n, FixedLag F, const float* init_pose, const 
 
 template <int NT>
 hipError_t fixedlag_nt(const EnvParams& P, const StepArgs& A, const LdsPlan& L, const FixedLag& F, hipStream_t st) {
-  const int blocks = (P.n + 255) / 256;
   k_motion<<<(unsigned)(((int64_t)P.n * kMotionLanes + 255) / 256), 256, 0, st>>>(P, A);
   k_march<NT><<<P.n, NT, L.total, st>>>(P, A, L);
   const int64_t items = (int64_t)P.n * P.R;
@@ -1581,12 +1574,11 @@ hipError_t fixedlag_nt(const EnvParams& P, const StepArgs& A, const LdsPlan& L, 
   k_fl_window<<<wave_blocks, 256, 0, st>>>(P, F);
   e = slam::launch_fixedlag(P.n, F.L, F.count, F.x, F.prior, F.odo, F.scan, F.iters, F.xout, F.covw, st);
   if (e != hipSuccess) return e;
-  k_fl_post<<<wave_blocks, 256, 0, st>>>(P, F);
   e = slam::launch_csm_integrate(P.dirtab, P.belief, F.cell_off, F.side, P.n, F.pose_al, F.rho_q, P.R, F.a_off,
                                  F.max_side, P.rhat_q, nullptr, 0, 0, 1.0, P.lhit, P.lmiss, P.lclamp, F.coded, F.wq,
                                  st);
   if (e != hipSuccess) return e;
-  k_fl_reward<<<blocks, 256, 0, st>>>(P, A, F);
+  k_fl_post_reward<<<wave_blocks, 256, 0, st>>>(P, A, F);
   return hipGetLastError();
 }
 
