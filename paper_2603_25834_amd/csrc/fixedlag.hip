@@ -23,8 +23,8 @@ __device__ __forceinline__ double wrap_pi(double a) {
 // ------------------------------------------------------------------ fixed-lag Gauss-Newton
 //
 // FP64 throughout, with multiply-adds fused (the solve is checked against the oracle to 1e-9, not bit
-// for bit): one lane runs the elimination chain of a window, so its instruction count and dependency
-// depth are the kernel's time.
+// for bit): the elimination chain of a window is serial over its poses, so its dependency depth per
+// pose is the kernel's time; nine lanes share each pose's block arithmetic.
 #pragma clang fp contract(fast)
 
 struct M3 {
@@ -146,80 +146,52 @@ __device__ __forceinline__ void linearise_pose(const double* x, int L, int i, co
   }
 }
 
-// Lane 0: the elimination sweep over the linearised window; returns D_{L-1}^{-1} in *last.  The previous
-// pose's D^{-1}, C, y and B stay in registers and the next pose's blocks are read one pose ahead, so
-// the recursion's chain holds no LDS round trip.
-__device__ __forceinline__ void eliminate_sweep(int L, const double* sA, const double* sB, const double* sg,
-                                                double* sDi, double* sC, double* sy, M3& last) {
-  double nA[9], nB[9], ng[3];
-#pragma unroll
-  for (int e = 0; e < 9; ++e) { nA[e] = sA[e]; nB[e] = sB[e]; }
-#pragma unroll
-  for (int a = 0; a < 3; ++a) ng[a] = sg[a];
-  double pC[9], py[3], pB[9];
+// The elimination sweep spread over nine lanes, lane (a, b) owning entry (a, b) of the 3x3 blocks (every
+// lane of the wave runs it; lane l works on entry l mod 9 and only lanes < 9 store): each lane forms its
+// entry of the Schur complement D_i, the six upper entries are gathered to every lane by shuffles, every
+// lane inverts D_i (so D_i^{-1} needs no exchange), forms its entry of C_i = D_i^{-1} B_i, and C_i and
+// y_i are gathered for the next pose.  A lane's dependent chain per pose is a few operations and two
+// shuffle rounds instead of the whole block arithmetic of one lane (about 4x shorter).
+__device__ __forceinline__ double pick3(double x0, double x1, double x2, int k) {
+  return k == 0 ? x0 : (k == 1 ? x1 : x2);
+}
+
+__device__ __forceinline__ void eliminate_sweep9(int L, int lane, const double* sA, const double* sB,
+                                                 const double* sg, double* sDi, double* sC, double* sy, M3& last) {
+  // a lane's operands are read from LDS at its own addresses (the previous pose's B, C and y there are
+  // the ones the lanes stored one pose earlier: a wave's LDS accesses complete in order), so no register
+  // array is indexed by the lane
+  const int l = lane % 9, a = l / 3, b = l - 3 * a;
   for (int i = 0; i < L; ++i) {
-    M3 D;
-    double y[3], B[9];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      y[a] = -ng[a];
-#pragma unroll
-      for (int b = 0; b < 3; ++b) D.a[a][b] = nA[3 * a + b];
-    }
-#pragma unroll
-    for (int e = 0; e < 9; ++e) B[e] = nB[e];
-    if (i + 1 < L) {
-#pragma unroll
-      for (int e = 0; e < 9; ++e) { nA[e] = sA[9 * (i + 1) + e]; nB[e] = sB[9 * (i + 1) + e]; }
-#pragma unroll
-      for (int a = 0; a < 3; ++a) ng[a] = sg[3 * (i + 1) + a];
-    }
+    const double* Bi = sB + 9 * i;
+    const double bb0 = Bi[b], bb1 = Bi[3 + b], bb2 = Bi[6 + b];   // column b of B_i
+    double d = sA[9 * i + l];
+    double ya = -sg[3 * i + a];
     if (i > 0) {
-      // D -= B^T D^{-1} B (symmetric: its upper triangle) and y -= B^T D^{-1} y = C^T y with
-      // C = D^{-1} B; the sums run term by term over all entries, so the entries' chains interleave
-      // (one wave per window: the dependent FP64 latency, not the issue rate, bounds the sweep)
-      constexpr int ua[6] = {0, 0, 0, 1, 1, 2}, ub[6] = {0, 1, 2, 1, 2, 2};
-      double acc[6], ty[3];
-#pragma unroll
-      for (int u = 0; u < 6; ++u) acc[u] = pB[ua[u]] * pC[ub[u]];
-#pragma unroll
-      for (int a = 0; a < 3; ++a) ty[a] = pC[a] * py[0];
-#pragma unroll
-      for (int k = 1; k < 3; ++k) {
-#pragma unroll
-        for (int u = 0; u < 6; ++u) acc[u] += pB[3 * k + ua[u]] * pC[3 * k + ub[u]];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) ty[a] += pC[3 * k + a] * py[k];
-      }
-#pragma unroll
-      for (int u = 0; u < 6; ++u) D.a[ua[u]][ub[u]] -= acc[u];
-#pragma unroll
-      for (int a = 0; a < 3; ++a) y[a] -= ty[a];
+      const double* pB = sB + 9 * (i - 1);
+      const double* pC = sC + 9 * (i - 1);
+      const double* py = sy + 3 * (i - 1);
+      d -= pB[a] * pC[b] + pB[3 + a] * pC[3 + b] + pB[6 + a] * pC[6 + b];
+      ya -= pC[a] * py[0] + pC[3 + a] * py[1] + pC[6 + a] * py[2];
     }
-    const M3 Di = sym_inv3(D);   // D is symmetric (its lower triangle is not read)
-    // C = D^{-1} B, term by term
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-      for (int b = 0; b < 3; ++b) pC[3 * a + b] = Di.a[a][0] * B[b];
-#pragma unroll
-    for (int k = 1; k < 3; ++k)
-#pragma unroll
-      for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int b = 0; b < 3; ++b) pC[3 * a + b] += Di.a[a][k] * B[3 * k + b];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      py[a] = y[a];
-      sy[3 * i + a] = y[a];
-#pragma unroll
-      for (int b = 0; b < 3; ++b) {
-        sDi[9 * i + 3 * a + b] = Di.a[a][b];
-        sC[9 * i + 3 * a + b] = pC[3 * a + b];
-      }
+    M3 D;   // the upper triangle is read by sym_inv3
+    D.a[0][0] = __shfl(d, 0, 64);
+    D.a[0][1] = __shfl(d, 1, 64);
+    D.a[0][2] = __shfl(d, 2, 64);
+    D.a[1][1] = __shfl(d, 4, 64);
+    D.a[1][2] = __shfl(d, 5, 64);
+    D.a[2][2] = __shfl(d, 8, 64);
+    const M3 Di = sym_inv3(D);
+    // row a of the (symmetric) inverse
+    const double r0 = pick3(Di.a[0][0], Di.a[0][1], Di.a[0][2], a);
+    const double r1 = pick3(Di.a[1][0], Di.a[1][1], Di.a[1][2], a);
+    const double r2 = pick3(Di.a[2][0], Di.a[2][1], Di.a[2][2], a);
+    const double c = r0 * bb0 + r1 * bb1 + r2 * bb2;
+    if (lane < 9) {
+      sDi[9 * i + l] = pick3(r0, r1, r2, b);
+      sC[9 * i + l] = c;
+      if (b == 0) sy[3 * i + a] = ya;
     }
-#pragma unroll
-    for (int e = 0; e < 9; ++e) pB[e] = B[e];
     if (i == L - 1) last = Di;
   }
 }
@@ -251,33 +223,29 @@ __global__ __launch_bounds__(kLagThreads) void k_fixedlag(int Ls, const int32_t*
     __syncthreads();
     for (int i = lane; i < L; i += kLagThreads) linearise_pose(sx, L, i, pr, od, sc, sA + 9 * i, sB + 9 * i, sg + 3 * i);
     __syncthreads();
-    if (lane == 0) {
-      eliminate_sweep(L, sA, sB, sg, sDi, sC, sy, last);
-      if (it < iters) {
-        // the terms D_i^{-1} y_i do not depend on the recursion: each pose's is formed first
-        double dn[3] = {0, 0, 0};
-        for (int i = L - 1; i >= 0; --i) {
-          const double* Di = sDi + 9 * i;
-          const double* C = sC + 9 * i;
-          const double* y = sy + 3 * i;
-          double d[3], c[9];
-#pragma unroll
-          for (int e = 0; e < 9; ++e) c[e] = C[e];
-#pragma unroll
-          for (int a = 0; a < 3; ++a) d[a] = Di[3 * a] * y[0] + Di[3 * a + 1] * y[1] + Di[3 * a + 2] * y[2];
-          if (i < L - 1) {
-#pragma unroll
-            for (int a = 0; a < 3; ++a) d[a] -= c[3 * a] * dn[0] + c[3 * a + 1] * dn[1] + c[3 * a + 2] * dn[2];
-          }
-#pragma unroll
-          for (int a = 0; a < 3; ++a) { sx[3 * i + a] += d[a]; dn[a] = d[a]; }
-        }
-      } else {
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-          for (int b = 0; b < 3; ++b) cov[9 * (int64_t)r + 3 * a + b] = last.a[a][b];
+    eliminate_sweep9(L, lane, sA, sB, sg, sDi, sC, sy, last);
+    __syncthreads();
+    if (it < iters) {
+      // back-substitution over three lanes (lane a of 3 the component a of each pose's step); the
+      // steps reach every lane by shuffles
+      const int a = lane % 3;
+      double dn0 = 0.0, dn1 = 0.0, dn2 = 0.0;
+      for (int i = L - 1; i >= 0; --i) {
+        const double* Di = sDi + 9 * i + 3 * a;
+        const double* C = sC + 9 * i + 3 * a;
+        const double* y = sy + 3 * i;
+        double d = Di[0] * y[0] + Di[1] * y[1] + Di[2] * y[2];
+        if (i < L - 1) d -= C[0] * dn0 + C[1] * dn1 + C[2] * dn2;
+        if (lane < 3) sx[3 * i + a] += d;
+        dn0 = __shfl(d, 0, 64);
+        dn1 = __shfl(d, 1, 64);
+        dn2 = __shfl(d, 2, 64);
       }
+    } else if (lane == 0) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) cov[9 * (int64_t)r + 3 * a + b] = last.a[a][b];
     }
   }
   __syncthreads();
