@@ -461,9 +461,11 @@ typedef struct {
  * log-odds of its rays' endpoint cells inside the grid.  out_dev int32 [n,6]: best i, j, k (highest
  * score, lowest index ((k+V)(2W+1) + j+W)(2W+1) + i+W on ties), best score, second score (highest at
  * lattice Chebyshev distance >= 2 from the best; INT32_MIN if none), rays with a return.
- * max_side: the largest side (a host value): lattices of at most 1024 candidates stage each grid of at
- * most this side in LDS when it fits beside the ray offsets (a robot with a larger side reads global
- * memory; results do not depend on it).
+ * max_side: the largest side (a host value): lattices of at most 1024 candidates stage in LDS the part
+ * of each grid that the candidates' endpoints can reach, with room sized for a whole grid of this side
+ * when that fits beside the ray offsets; a larger part is staged in bands of rows, and a robot whose
+ * part has rows wider than that room, or whose centre or ray offsets lie beyond 2^28 / 2^29 (Q16),
+ * reads global memory (results do not depend on it).
  * Device arrays are not checked: the caller guarantees grids inside belief_dev, 0 <= rho_q < 2^31.
  * ASL_EINVAL on NULL pointers, n < 0 or a config outside the ranges above, or (2V + 1) R > 8192. */
 int aslam_csm_match(const aslam_slam* slam, const int16_t* belief_dev, const int64_t* cell_off_dev,

@@ -167,17 +167,22 @@ __global__ __launch_bounds__(kCsmThreads) void k_csm(const int16_t* __restrict__
   }
 }
 
-// The same with the robot's whole grid staged in LDS (when it fits beside the ray offsets), for
-// lattices of at most 9 translations per axis and 1024 candidates.  Thread (row, chunk) takes one
-// (heading k, row j) line of nine x candidates over a chunk of the rays, so one offset read serves the
-// whole line (the line's cells are read side by side); the chunks' partial sums are then added in
-// chunk order.  A robot whose side exceeds the staged size reads its grid from global memory instead.
-// Dynamic LDS: the grid (lds_cells int16, a multiple of 8), then the (2V + 1) R ray offsets, whose
-// space (sized for whichever is larger) takes the partial sums once every line is done.
+// The same with the robot's grid staged in LDS, for lattices of at most 9 translations per axis and
+// 1024 candidates.  Only the part of the grid that some candidate's ray endpoint can reach is staged:
+// the box of the rays' endpoint offsets over every heading candidate, widened by the translation
+// lattice and clipped to the grid (its columns widened to multiples of 8 for 16-byte reads).  A box
+// with more rows than the LDS holds is staged in bands of rows, each band scored in turn (an endpoint
+// outside the band adds nothing in that pass), so any side can be staged.  A box row wider than the LDS
+// is read from global memory instead.
+// Thread (row, chunk) takes one (heading k, row j) line of nine x candidates over a chunk of the rays,
+// so one offset read serves the whole line (the line's cells are read side by side); the chunks'
+// partial sums are then added in chunk order.  Dynamic LDS: cap_cells int16 grid cells (a multiple of
+// 8; the partial sums take this space after the last band), then the (2V + 1) R ray offsets.
 constexpr int kCsmLdsThreads = 512;
 constexpr int kCsmLdsMaxCand = 1024;
 constexpr int kCsmLdsMaxLine = 9;                  // 2W + 1 <= 9
-constexpr int32_t kNoReturn = -(1 << 30);         // offset of a ray without a return: off every grid
+constexpr int kCsmLdsPad = 2;                      // cells between a staged row's end and the next row
+constexpr int32_t kNoReturnY = -(1 << 30);        // y offset of a ray without a return: above every row
 
 __global__ __launch_bounds__(kCsmLdsThreads) void k_csm_lds(const int16_t* __restrict__ belief,
                                                             const int64_t* __restrict__ cell_off,
@@ -186,26 +191,29 @@ __global__ __launch_bounds__(kCsmLdsThreads) void k_csm_lds(const int16_t* __res
                                                             const int32_t* __restrict__ rho_q, int R,
                                                             const int32_t* __restrict__ a_off,
                                                             const int32_t* __restrict__ dirtab, int W, int V,
-                                                            int step_xy, int step_h, int lds_side, int pad,
+                                                            int step_xy, int step_h, int cap_cells,
                                                             int32_t* __restrict__ out) {
   extern __shared__ __align__(16) unsigned char s_dyn[];
-  const int lds_cells = ((lds_side + pad) * lds_side + 7) & ~7;
   int16_t* s_grid = reinterpret_cast<int16_t*>(s_dyn);
-  int2* s_off = reinterpret_cast<int2*>(s_dyn + 2 * (int64_t)lds_cells);
-  int32_t* s_part = reinterpret_cast<int32_t*>(s_off);
+  int32_t* s_part = reinterpret_cast<int32_t*>(s_dyn);
+  int2* s_off = reinterpret_cast<int2*>(s_dyn + 2 * (int64_t)cap_cells);
+  // s_red holds, until the scoring starts, the offsets' box: min x, max x, min y, max y
   __shared__ int32_t s_red[kCsmLdsThreads / 64][2];
   const int r = blockIdx.x;
   const int nw = 2 * W + 1, nk = 2 * V + 1, ncand = nk * nw * nw, nline = nk * nw;
   const int32_t px = pose_q[3 * r], py = pose_q[3 * r + 1], ph = pose_q[3 * r + 2];
   const int32_t* rho = rho_q + (int64_t)r * R;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   int used = 0;
-  bool far_off = false;   // a ray offset beyond 2^29 (Q16) in either axis; the workgroup's OR in s_red[0][0]
-  if (threadIdx.x == 0) s_red[0][0] = 0;
+  if (threadIdx.x == 0) {
+    s_red[0][0] = INT32_MAX; s_red[0][1] = INT32_MIN; s_red[1][0] = INT32_MAX; s_red[1][1] = INT32_MIN;
+  }
   __syncthreads();
+  int32_t mnx = INT32_MAX, mxx = INT32_MIN, mny = INT32_MAX, mxy = INT32_MIN;
   for (int e = threadIdx.x; e < nk * R; e += kCsmLdsThreads) {
     const int k = e / R, q = e - k * R;
     const int32_t rq = rho[q];
-    int2 o = make_int2(kNoReturn, kNoReturn);
+    int2 o = make_int2(0, kNoReturnY);
     if (rq >= 0) {
       int64_t h = ((int64_t)ph + (int64_t)(k - V) * step_h + a_off[q]) % kNang;
       if (h < 0) h += kNang;
@@ -213,68 +221,67 @@ __global__ __launch_bounds__(kCsmLdsThreads) void k_csm_lds(const int16_t* __res
       const int32_t c = (int32_t)(int16_t)(d & 0xffff), s = d >> 16;
       o.x = (int32_t)(((int64_t)rq * c) >> 14);
       o.y = (int32_t)(((int64_t)rq * s) >> 14);
-      far_off |= abs(o.x) > (1 << 29) || abs(o.y) > (1 << 29);
+      mnx = min(mnx, o.x); mxx = max(mxx, o.x); mny = min(mny, o.y); mxy = max(mxy, o.y);
       if (k == 0) ++used;
     }
     s_off[e] = o;
   }
-  if (__builtin_amdgcn_ballot_w64(far_off) != 0 && (threadIdx.x & 63) == 0) atomicOr(&s_red[0][0], 1);
-  const int32_t sd = side[r];
-  const int64_t base = cell_off[r];
-  const bool staged = sd > 0 && sd <= lds_side;
-  // Staged rows are `pad` cells apart beyond the side: with pad = 2 the lanes that read the same ray's
-  // endpoint in neighbouring rows (neighbouring y candidates) hit neighbouring LDS banks, not one bank.
-  const int pitch = staged ? sd + pad : sd;
-  if (staged) {
-    const int64_t cells = (int64_t)sd * sd;
-    if ((reinterpret_cast<uintptr_t>(belief + base) & 15) == 0 && (sd & 7) == 0 && (pad & 1) == 0) {
-      // 8 cells per access: one 16-byte read, four 4-byte writes (rows start on 4-byte boundaries);
-      // each thread has kStage reads in flight before it writes any (a staged side is small, so the
-      // indices fit 32 bits)
-      constexpr int kStage = 8;
-      const uint4* src = reinterpret_cast<const uint4*>(belief + base);
-      const uint32_t per_row = (uint32_t)sd >> 3, total = (uint32_t)(cells >> 3);
-      for (uint32_t v0 = threadIdx.x; v0 < total; v0 += kStage * kCsmLdsThreads) {
-        uint4 t[kStage];
 #pragma unroll
-        for (int u = 0; u < kStage; ++u) {
-          const uint32_t v = v0 + u * kCsmLdsThreads;
-          if (v < total) t[u] = src[v];
-        }
-#pragma unroll
-        for (int u = 0; u < kStage; ++u) {
-          const uint32_t v = v0 + u * kCsmLdsThreads;
-          if (v < total) {
-            const uint32_t y = v / per_row, x = (v - y * per_row) * 8;
-            uint32_t* d = reinterpret_cast<uint32_t*>(s_grid + y * (uint32_t)pitch + x);
-            d[0] = t[u].x; d[1] = t[u].y; d[2] = t[u].z; d[3] = t[u].w;
-          }
-        }
-      }
-    } else {
-      for (int64_t e = threadIdx.x; e < cells; e += kCsmLdsThreads) {
-        const int y = (int)(e / sd), x = (int)(e - (int64_t)y * sd);
-        s_grid[(int64_t)y * pitch + x] = belief[base + e];
-      }
-    }
+  for (int off = 32; off > 0; off >>= 1) {
+    mnx = min(mnx, __shfl_xor(mnx, off, 64)); mxx = max(mxx, __shfl_xor(mxx, off, 64));
+    mny = min(mny, __shfl_xor(mny, off, 64)); mxy = max(mxy, __shfl_xor(mxy, off, 64));
+  }
+  if (lane == 0) {
+    atomicMin(&s_red[0][0], mnx); atomicMax(&s_red[0][1], mxx);
+    atomicMin(&s_red[1][0], mny); atomicMax(&s_red[1][1], mxy);
   }
   __syncthreads();
-  far_off = s_red[0][0] != 0;
+  mnx = s_red[0][0]; mxx = s_red[0][1]; mny = s_red[1][0]; mxy = s_red[1][1];
+  const int32_t sd = side[r];
+  const int64_t base = cell_off[r];
+  // the cells any candidate's endpoint can reach, clipped to the grid (empty: every score is 0)
+  const int64_t span = (int64_t)W * step_xy;
+  int64_t bx0 = 0, bx1 = -1, by0 = 0, by1 = -1;
+  if (mnx <= mxx && sd > 0) {
+    bx0 = max<int64_t>(0, ((int64_t)px - span + mnx) >> 16);
+    bx1 = min<int64_t>(sd - 1, ((int64_t)px + span + mxx) >> 16);
+    by0 = max<int64_t>(0, ((int64_t)py - span + mny) >> 16);
+    by1 = min<int64_t>(sd - 1, ((int64_t)py + span + mxy) >> 16);
+  }
+  const bool empty = bx0 > bx1 || by0 > by1;
+  const bool vec = (reinterpret_cast<uintptr_t>(belief + base) & 15) == 0 && (sd & 7) == 0;
+  const int64_t x0a = vec ? (bx0 & ~(int64_t)7) : bx0;
+  const int64_t x1a = vec ? min<int64_t>(sd, (bx1 + 8) & ~(int64_t)7) : bx1 + 1;
+  const int64_t pitch = x1a - x0a + kCsmLdsPad;
+  // Staged grids are scored in 32-bit cell arithmetic, which needs the search centre within 2^28 and
+  // the ray offsets within 2^29 (Q16): every coordinate relative to a band's origin then stays within
+  // 2^31.  A robot beyond either bound (or with a box row wider than the LDS) is scored from global
+  // memory in 64 bits.
+  const bool near = mnx >= -(1 << 29) && mxx <= (1 << 29) && mny >= -(1 << 29) && mxy <= (1 << 29) &&
+                    px > -(1 << 28) && px < (1 << 28) && py > -(1 << 28) && py < (1 << 28);
+  const bool staged = near && pitch <= cap_cells;
   // lines x chunks of rays
   const int chunks = max(1, min(R, kCsmLdsThreads / nline));
   int32_t acc[kCsmLdsMaxLine];
 #pragma unroll
   for (int i = 0; i < kCsmLdsMaxLine; ++i) acc[i] = 0;
   const int line = threadIdx.x / chunks, ch = threadIdx.x - line * chunks;
-  // One instance per grid location, so that the reads of a staged grid compile to LDS reads (a pointer
-  // that may point to either memory would make every read a flat access).  The cell arithmetic runs in
-  // I: 32 bits for a staged grid whose search centre is within 2^28 and whose ray offsets are within
-  // 2^29 (every candidate's Q16 coordinate then stays within 2^30), else 64.
-  auto score = [&](const int16_t* g, auto tag) {
+  // One instance per memory, so that the reads of a staged grid compile to LDS reads (a pointer that
+  // may point to either would make every read a flat access).  g holds rows [row0, row0 + nrows) and
+  // columns [col0, col0 + ncols) of the grid, row y at (y - row0) * gp; coordinates are taken relative
+  // to (col0, row0) in Q16 so that the bounds are two unsigned compares.  In 64-bit arithmetic a ray
+  // without a return is skipped by its range; in 32 bits its y offset puts it above every row.
+  auto score = [&](const int16_t* g, int64_t gp, int64_t row0, int64_t nrows, int64_t col0, int64_t ncols,
+                   auto tag) {
     using I = decltype(tag);
+    using U = std::make_unsigned_t<I>;
+    constexpr bool kWide = sizeof(I) == 8;
     const int k = line / nw, j = line - k * nw;
     const int q0 = (int)((int64_t)ch * R / chunks), q1 = (int)((int64_t)(ch + 1) * R / chunks);
-    const I x0 = (I)px - (I)W * step_xy, y = (I)py + (I)(j - W) * step_xy;
+    const I x0 = (I)((int64_t)px - span - (col0 << 16));
+    const I y = (I)((int64_t)py + (int64_t)(j - W) * step_xy - (row0 << 16));
+    const U nr = (U)nrows, nc = (U)ncols;
+    const I pit = (I)gp;
     const int2* o = s_off + k * R;
     // four rays per step, every read issued before any is used: a cell off the grid reads cell 0 of
     // the grid and adds nothing
@@ -286,13 +293,14 @@ __global__ __launch_bounds__(kCsmLdsThreads) void k_csm_lds(const int16_t* __res
       for (int u = 0; u < kRays; ++u) {
         const int2 v = o[q + u];
         const I cy = (y + v.y) >> 16;
-        const bool row_ok = cy >= 0 && cy < sd;
-        const int16_t* grow = g + (row_ok ? cy : 0) * pitch;
+        bool row_ok = (U)cy < nr;
+        if constexpr (kWide) row_ok = row_ok && rho[q + u] >= 0;
+        const int16_t* grow = g + (row_ok ? cy : 0) * pit;
         const I ex = x0 + v.x;
 #pragma unroll
         for (int i = 0; i < kCsmLdsMaxLine; ++i) {
           const I cx = (ex + (I)i * step_xy) >> 16;
-          const bool ok = row_ok && i < nw && cx >= 0 && cx < sd;
+          const bool ok = row_ok && i < nw && (U)cx < nc;
           const int32_t t = grow[ok ? cx : 0];
           val[u][i] = ok ? t : 0;
         }
@@ -305,28 +313,70 @@ __global__ __launch_bounds__(kCsmLdsThreads) void k_csm_lds(const int16_t* __res
     for (; q < q1; ++q) {
       const int2 v = o[q];
       const I cy = (y + v.y) >> 16;
-      if (cy < 0 || cy >= sd) continue;
-      const int16_t* grow = g + cy * pitch;
+      if ((U)cy >= nr) continue;
+      if constexpr (kWide) {
+        if (rho[q] < 0) continue;
+      }
+      const int16_t* grow = g + cy * pit;
       const I ex = x0 + v.x;
 #pragma unroll
       for (int i = 0; i < kCsmLdsMaxLine; ++i) {
         if (i < nw) {
           const I cx = (ex + (I)i * step_xy) >> 16;
-          if (cx >= 0 && cx < sd) acc[i] += grow[cx];
+          if ((U)cx < nc) acc[i] += grow[cx];
         }
       }
     }
   };
-  const bool near = !far_off && px > -(1 << 28) && px < (1 << 28) && py > -(1 << 28) && py < (1 << 28);
-  if (line < nline && sd > 0) {   // an empty grid scores 0 everywhere
-    if (staged && near)
-      score(s_grid, int32_t{});
-    else if (staged)
-      score(s_grid, int64_t{});
-    else
-      score(belief + base, int64_t{});
+  if (!empty && staged) {
+    const int64_t band = cap_cells / pitch, ncols = x1a - x0a;
+    for (int64_t r0 = by0; r0 <= by1; r0 += band) {
+      const int64_t nrows = min<int64_t>(band, by1 + 1 - r0);
+      if (vec) {
+        // 8 cells per access: one 16-byte read, four 4-byte writes (pitch is even, so rows start on
+        // 4-byte boundaries).  Thread t takes piece t mod p of rows t / p, t / p + rs, ... (p pieces a
+        // row, rs = 512 / p rows a pass; a row of more than 512 pieces: pieces t, t + 512, ... of every
+        // row), with kStage reads in flight before it writes any
+        constexpr int kStage = 8;
+        const uint4* src = reinterpret_cast<const uint4*>(belief + base + r0 * sd + x0a);
+        const int per_row = (int)(ncols >> 3);
+        const int64_t src_pitch = sd >> 3;
+        const int rs = max(1, kCsmLdsThreads / per_row);
+        const int first = per_row >= kCsmLdsThreads ? 0 : (int)threadIdx.x / per_row;
+        const int piece0 = per_row >= kCsmLdsThreads ? (int)threadIdx.x : (int)threadIdx.x - first * per_row;
+        if (first < rs) {
+          for (int xp = piece0; xp < per_row; xp += kCsmLdsThreads) {
+            for (int64_t y0 = first; y0 < nrows; y0 += (int64_t)kStage * rs) {
+              const uint4* s0 = src + y0 * src_pitch + xp;
+              uint32_t* d0 = reinterpret_cast<uint32_t*>(s_grid + y0 * pitch + 8 * xp);
+              uint4 t[kStage];
+#pragma unroll
+              for (int u = 0; u < kStage; ++u)
+                if (y0 + u * rs < nrows) t[u] = s0[(int64_t)u * rs * src_pitch];
+#pragma unroll
+              for (int u = 0; u < kStage; ++u) {
+                if (y0 + u * rs < nrows) {
+                  uint32_t* d = d0 + (u * rs * pitch) / 2;
+                  d[0] = t[u].x; d[1] = t[u].y; d[2] = t[u].z; d[3] = t[u].w;
+                }
+              }
+            }
+          }
+        }
+      } else {
+        const int64_t cells = nrows * ncols;
+        for (int64_t e = threadIdx.x; e < cells; e += kCsmLdsThreads) {
+          const int64_t yy = e / ncols, xx = e - yy * ncols;
+          s_grid[yy * pitch + xx] = belief[base + (r0 + yy) * sd + x0a + xx];
+        }
+      }
+      __syncthreads();
+      if (line < nline) score(s_grid, pitch, r0, nrows, x0a, ncols, int32_t{});
+      __syncthreads();   // the band is read before the next one (or the partial sums) takes its space
+    }
+  } else if (!empty && line < nline) {
+    score(belief + base, sd, 0, sd, 0, sd, int64_t{});
   }
-  __syncthreads();   // every line is done with the offsets: their space takes the partial sums
   if (line < nline) {
 #pragma unroll
     for (int i = 0; i < kCsmLdsMaxLine; ++i)
@@ -344,7 +394,6 @@ __global__ __launch_bounds__(kCsmLdsThreads) void k_csm_lds(const int16_t* __res
       sc[m] = t;
     }
   }
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   int32_t bs = INT32_MIN, bi = INT32_MAX;
 #pragma unroll
   for (int m = 0; m < 2; ++m) {
@@ -738,27 +787,23 @@ hipError_t launch_csm_match(const int32_t* tab, const int16_t* belief_dev, const
   if (n <= 0) return hipSuccess;
   const int ncand = (2 * V + 1) * (2 * W + 1) * (2 * W + 1);
   if (ncand <= kCsmLdsMaxCand && 2 * W + 1 <= kCsmLdsMaxLine) {
-    // the grids staged in LDS when the largest fits beside the ray offsets and the chunks' partial
-    // sums, which reuse the offsets' space (a 256 x 256 grid does with 11 headings x 360 rays), else
-    // read from global memory; rows padded by 2 cells when that still fits (fewer LDS bank
-    // conflicts), else unpadded
+    // LDS: the ray offsets and room for a whole grid of the largest side (rows padded) within the
+    // CU's 160 KB, so one robot per CU; a box that does not fit is staged in bands.  (Smaller shares,
+    // two or three robots per CU, were slower: at 360 rays the extra bands repeat the scoring, which
+    // dominates.)  The grid space holds at least the chunks' partial sums.
     const int chunks = std::max(1, std::min((int)R, kCsmLdsThreads / ((2 * V + 1) * (2 * W + 1))));
-    const int64_t off_bytes = std::max<int64_t>((int64_t)(2 * V + 1) * R * (int64_t)sizeof(int2),
-                                                (int64_t)sizeof(int32_t) * ncand * chunks);
-    int pad = 2;
-    int64_t grid_bytes = 2 * ((((int64_t)max_side + pad) * max_side + 7) & ~(int64_t)7);
-    if (grid_bytes + off_bytes > kCsmLdsBudget) {
-      pad = 0;
-      grid_bytes = 2 * ((((int64_t)max_side * max_side) + 7) & ~(int64_t)7);
-    }
-    int lds_side = max_side;
-    if (grid_bytes + off_bytes > kCsmLdsBudget) { grid_bytes = 0; lds_side = 0; pad = 0; }
-    const int bytes = (int)(grid_bytes + off_bytes);
+    const int64_t off_bytes = (int64_t)(2 * V + 1) * R * (int64_t)sizeof(int2);
+    const int64_t part_cells = (2 * (int64_t)ncand * chunks + 7) & ~(int64_t)7;
+    const int64_t whole = (((int64_t)max_side + kCsmLdsPad) * max_side + 7) & ~(int64_t)7;
+    const int64_t room = ((kCsmLdsBudget - off_bytes) / 2) & ~(int64_t)7;
+    const int64_t cap_cells = std::max(part_cells, std::min(whole, room));
+    const int bytes = (int)(2 * cap_cells + off_bytes);
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_csm_lds),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     if (e != hipSuccess) return e;
     k_csm_lds<<<n, kCsmLdsThreads, bytes, stream>>>(belief_dev, cell_off_dev, side_dev, pose_q_dev, rho_q_dev, R,
-                                                    a_off_dev, tab, W, V, step_xy_q, step_h, lds_side, pad, out_dev);
+                                                    a_off_dev, tab, W, V, step_xy_q, step_h, (int)cap_cells,
+                                                    out_dev);
   } else {
     k_csm<<<n, kCsmThreads, 0, stream>>>(belief_dev, cell_off_dev, side_dev, pose_q_dev, rho_q_dev, R, a_off_dev, tab,
                                          W, V, step_xy_q, step_h, out_dev);

@@ -72,12 +72,17 @@ def test_match_bit_exact(W, V, sxy, sh, R):
         assert tuple(int(v) for v in got[r]) == want, (r, got[r], want)
 
 
-@pytest.mark.parametrize("sides,max_side", [([300, 64, 128], None), ([256, 64, 200, 96], 96), ([100, 64, 37], None)],
-                         ids=["grid_too_big_for_lds", "mixed_staged_and_global", "sides_not_multiple_of_8"])
-def test_match_staged_and_global_grids(sides, max_side):
-    """Grids staged in LDS (rows padded, sides of any residue) or read from global memory give the same
-    (exact) answers."""
-    W, V, sxy, sh, R = 4, 5, 65536, 64, 360
+@pytest.mark.parametrize("sides,max_side,W,V,R", [([300, 64, 128], None, 4, 5, 360), ([256, 64, 200, 96], 96, 4, 5, 360),
+                                                  ([100, 64, 37], None, 4, 5, 360), ([256, 64, 200, 96], 16, 4, 5, 360),
+                                                  ([300, 64, 37, 256], 1, 0, 0, 64)],
+                         ids=["grid_too_big_for_lds", "bands_below_max_side", "sides_not_multiple_of_8",
+                              "many_bands", "one_row_bands_and_global_rows"])
+def test_match_staged_and_global_grids(sides, max_side, W, V, R):
+    """Grids staged in LDS (the reachable box, in bands of rows when it exceeds the LDS the launch sized
+    from max_side; rows padded, sides of any residue) or read from global memory (a box row wider than
+    that LDS: with a one-candidate lattice and max_side 1 it holds 128 cells) give the same (exact)
+    answers."""
+    sxy, sh = 65536, 64
     grids, belief, cell_off, side, pose, rho, a_off = _batch(17 + len(sides), sides, R, W, V, sxy, sh)
     cfg = slam.csm_config(W, V, sxy, sh)
     d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
@@ -97,12 +102,16 @@ def test_match_far_centres_and_offsets():
     launch: a centre far off the grid, ranges near the int32 limit on half the rays, a centre just inside
     the bound, and ordinary robots beside them, all against the oracle."""
     W, V, sxy, sh, R = 4, 5, 65536, 64, 128
-    sides = [64, 96, 128, 64, 128]
+    sides = [64, 96, 128, 64, 128, 128, 64]
     grids, belief, cell_off, side, pose, rho, a_off = _batch(91, sides, R, W, V, sxy, sh, invalid_p=0.05)
     pose[0, 0] = (1 << 28) + 5 * 65536                  # centre beyond the bound: 64-bit arithmetic
     pose[1, 1] = -(1 << 29)
     rho[3, ::2] = (1 << 31) - 1 - np.arange(0, R, 2)     # offsets near the int32 limit on half the rays
     pose[4, 0] = (1 << 28) - 65536 - 1                  # centre just inside the bound, far off its grid
+    # rays without a return near centres 2^30 (Q16) off the grid in y, and in both axes: such a ray must
+    # add nothing even where its placeholder offset would land on the grid
+    pose[5] = (10 * 65536, (1 << 30) + 10 * 65536, 100)
+    pose[6] = ((1 << 30) + 12 * 65536, (1 << 30) + 9 * 65536, 7000)
     say(f"[slam] csm far centres and offsets R={R} robots={len(sides)}")
     got, _ = _gpu_match(belief, cell_off, side, pose, rho, a_off, W, V, sxy, sh)
     trig = S._trig()
