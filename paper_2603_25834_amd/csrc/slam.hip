@@ -283,15 +283,28 @@ __global__ __launch_bounds__(kCsmLdsThreads) void k_csm_lds(const int16_t* __res
     const U nr = (U)nrows, nc = (U)ncols;
     const I pit = (I)gp;
     const int2* o = s_off + k * R;
-    // four rays per step, every read issued before any is used: a cell off the grid reads cell 0 of
+    // four rays per step, every read issued before any is used (the next step's offsets are read
+    // before this step's cells, so one LDS round trip per step): a cell off the grid reads cell 0 of
     // the grid and adds nothing
     constexpr int kRays = 4;
     int q = q0;
+    int2 nv[kRays];
+    if (q + kRays <= q1) {
+#pragma unroll
+      for (int u = 0; u < kRays; ++u) nv[u] = o[q + u];
+    }
     for (; q + kRays <= q1; q += kRays) {
+      int2 cv[kRays];
+#pragma unroll
+      for (int u = 0; u < kRays; ++u) cv[u] = nv[u];
+      if (q + 2 * kRays <= q1) {
+#pragma unroll
+        for (int u = 0; u < kRays; ++u) nv[u] = o[q + kRays + u];
+      }
       int32_t val[kRays][kCsmLdsMaxLine];
 #pragma unroll
       for (int u = 0; u < kRays; ++u) {
-        const int2 v = o[q + u];
+        const int2 v = cv[u];
         const I cy = (y + v.y) >> 16;
         bool row_ok = (U)cy < nr;
         if constexpr (kWide) row_ok = row_ok && rho[q + u] >= 0;
