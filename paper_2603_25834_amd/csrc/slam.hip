@@ -182,7 +182,7 @@ constexpr int kCsmLdsThreads = 512;
 constexpr int kCsmLdsMaxCand = 1024;
 constexpr int kCsmLdsMaxLine = 9;                  // 2W + 1 <= 9
 constexpr int kCsmLdsPad = 2;                      // cells between a staged row's end and the next row
-constexpr int32_t kNoReturnY = -(1 << 30);        // y offset of a ray without a return: above every row
+constexpr int32_t kNoReturnY = -(1 << 30);        // y offset of a ray without a return: a negative row in every band
 
 __global__ __launch_bounds__(kCsmLdsThreads) void k_csm_lds(const int16_t* __restrict__ belief,
                                                             const int64_t* __restrict__ cell_off,
