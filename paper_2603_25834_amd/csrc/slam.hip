@@ -265,7 +265,11 @@ __global__ __launch_bounds__(kCsmLdsThreads) void k_csm_lds(const int16_t* __res
   int32_t acc[kCsmLdsMaxLine];
 #pragma unroll
   for (int i = 0; i < kCsmLdsMaxLine; ++i) acc[i] = 0;
-  const int line = threadIdx.x / chunks, ch = threadIdx.x - line * chunks;
+  // consecutive threads take consecutive lines of one chunk, so a wave's lanes read the same ray at
+  // the same time: neighbouring y candidates' endpoints are neighbouring rows, neighbouring headings'
+  // the same or adjacent cells (fewer LDS bank conflicts than lanes on different rays)
+  const int ch = threadIdx.x / nline, line = threadIdx.x - ch * nline;
+  const bool active = ch < chunks;
   // One instance per memory, so that the reads of a staged grid compile to LDS reads (a pointer that
   // may point to either would make every read a flat access).  g holds rows [row0, row0 + nrows) and
   // columns [col0, col0 + ncols) of the grid, row y at (y - row0) * gp; coordinates are taken relative
@@ -384,13 +388,13 @@ __global__ __launch_bounds__(kCsmLdsThreads) void k_csm_lds(const int16_t* __res
         }
       }
       __syncthreads();
-      if (line < nline) score(s_grid, pitch, r0, nrows, x0a, ncols, int32_t{});
+      if (active) score(s_grid, pitch, r0, nrows, x0a, ncols, int32_t{});
       __syncthreads();   // the band is read before the next one (or the partial sums) takes its space
     }
-  } else if (!empty && line < nline) {
+  } else if (!empty && active) {
     score(belief + base, sd, 0, sd, 0, sd, int64_t{});
   }
-  if (line < nline) {
+  if (active) {
 #pragma unroll
     for (int i = 0; i < kCsmLdsMaxLine; ++i)
       if (i < nw) s_part[ch * ncand + line * nw + i] = acc[i];
